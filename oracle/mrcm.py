@@ -1,0 +1,146 @@
+"""O-3: the plain non-recursive MRCM (oracle).
+
+Section 2.2 (the interface system A X = b): substitute the local solutions,
+written as basis combinations plus the particular solution (eq. uhatphat,
+eq. final), into the coarse continuity conditions eq. 13.2 and 14.2 tested
+with every interface basis function.  The unknowns are
+``X = (U_1 .. U_nseg, P_1 .. P_nseg)``: one flux and one pressure value per
+segment (piecewise-constant MuMM spaces, Section 4).  Rows follow the
+paper's order: first eq. 14.2 tested with phi^r (r <= n_U), then eq. 13.2
+tested with psi^r.
+
+For segment e between subdomains lo (sign +1) and hi (sign -1):
+* eq. 13.2:  F^lo_e + F^hi_e = 0
+* eq. 14.2:  beta_e (s_lo F^lo_e + s_hi F^hi_e - 2 |e| U_e) = 0
+with ``F^i_e = tbar^i_e + sum_b T^i[e, b] g^i_b`` and the Robin datum
+``g^i_b = P_b - beta_b s_{i,b} U_b``.  The U-type basis of eq. 11Hhatbasisa
+is the unit-datum basis times ``-beta s`` and the P-type basis of
+eq. 11Hhatbasisb is the unit-datum basis itself, so these rows are exactly
+the entries a_rj and b_r of eq. brhs.
+
+The sparse system is solved by SuperLU with one refinement step and the
+final solution assembled by eq. final.  With no Dirichlet face anywhere the
+cell pressure is defined up to a constant; the gauge is a zero mean of the
+cell pressures, imposed through a bordered system.
+
+Pinned by: equality with O-1 when every segment is one fine face (for any
+alpha), exact linear pressure on vertical strips, O-4 brute force, the
+Table 3 local-solve counts and the magnitude of the Table 6/8 errors.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+from .decomp import Decomposition
+from .local import local_solve, local_fluxes
+from .tpfa import solve_refined
+
+
+@dataclass
+class MRCMResult:
+    p: np.ndarray        # (ny, nx)
+    F: np.ndarray        # (4, ny, nx) one-sided outward fluxes
+    U: np.ndarray        # (nseg,)
+    P: np.ndarray        # (nseg,)
+    dec: Decomposition
+    locals: dict
+
+
+def all_local_solves(prob, dec):
+    return {(I, J): local_solve(prob, dec, I, J)
+            for J in range(dec.my) for I in range(dec.mx)}
+
+
+def assemble_interface_system(dec, loc):
+    """Sparse A (2 nseg x 2 nseg) and b of eq. linsys."""
+    ns = dec.nseg
+    rows, cols, vals = [], [], []
+    b = np.zeros(2 * ns)
+    beta = dec.seg_beta
+    for (I, J), r in loc.items():
+        act = [(a, e, sg) for a, (e, sg, _sd, _s) in enumerate(r.slots) if e >= 0]
+        for (a, e, sa) in act:
+            # F^i_e = tbar[a] + sum_b T[a, b] (P_eb - beta_eb s_b U_eb)
+            for (bb, eb, sb) in act:
+                t = r.T[a, bb]
+                if t == 0.0:
+                    continue
+                # eq. 14.2 row (index e): beta_e * s_a * F
+                rows += [e, e]
+                cols += [ns + eb, eb]
+                vals += [beta[e] * sa * t, -beta[e] * sa * t * beta[eb] * sb]
+                # eq. 13.2 row (index ns + e): F
+                rows += [ns + e, ns + e]
+                cols += [ns + eb, eb]
+                vals += [t, -t * beta[eb] * sb]
+            b[e] -= beta[e] * sa * r.tbar[a]
+            b[ns + e] -= r.tbar[a]
+    for e in range(ns):
+        rows.append(e)
+        cols.append(e)
+        vals.append(-2.0 * beta[e] * dec.seg_length[e])
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(2 * ns, 2 * ns)).tocsr()
+    return A, b
+
+
+def robin_data(r, U, P, beta):
+    g = np.zeros(len(r.slots))
+    for a, (e, sgn, _sd, _s) in enumerate(r.slots):
+        if e >= 0:
+            g[a] = P[e] - beta[e] * sgn * U[e]
+    return g
+
+
+def _gauge_row(prob, dec, loc):
+    """Linear functional X -> sum of all cell pressures (and its constant)."""
+    ns = dec.nseg
+    w = np.zeros(2 * ns)
+    c0 = 0.0
+    for (I, J), r in loc.items():
+        c0 += r.pbar.sum()
+        colsum = r.Psi.sum(axis=0)
+        for a, (e, sgn, _sd, _s) in enumerate(r.slots):
+            if e >= 0:
+                w[ns + e] += colsum[a]
+                w[e] -= colsum[a] * dec.seg_beta[e] * sgn
+    return w, c0
+
+
+def mrcm_solve(prob, loc=None) -> MRCMResult:
+    dec = Decomposition(prob)
+    if loc is None:
+        loc = all_local_solves(prob, dec)
+    ns = dec.nseg
+    if ns == 0:
+        U = P = np.zeros(0)
+    else:
+        A, b = assemble_interface_system(dec, loc)
+        if np.any(prob.bc_type == 1):
+            X = solve_refined(A, b)
+        else:
+            # All outer faces Neumann: shifting every P_e by a constant
+            # shifts every cell pressure by it (partition of unity) and
+            # leaves all fluxes unchanged, so n = (0, 1) spans the null
+            # space; the sum of the eq. 13.2 rows, y = (0, 1), spans the
+            # left null space.  Since y.n != 0 the bordered system
+            # [[A, n], [w^T, 0]] with the zero-mean gauge row w is regular.
+            w, c0 = _gauge_row(prob, dec, loc)
+            nullv = np.concatenate([np.zeros(ns), np.ones(ns)])
+            Ab = sp.bmat([[A, sp.csr_matrix(nullv[:, None])],
+                          [sp.csr_matrix(w[None, :]), None]]).tocsr()
+            sol = solve_refined(Ab, np.concatenate([b, [-c0]]))
+            X = sol[:2 * ns]
+        U, P = X[:ns], X[ns:]
+    p = np.zeros((prob.ny, prob.nx))
+    F = np.zeros((4, prob.ny, prob.nx))
+    for (I, J), r in loc.items():
+        g = robin_data(r, U, P, dec.seg_beta)
+        pl = (r.pbar + r.Psi @ g).reshape(dec.by, dec.bx)
+        cs = dec.subdomain_cells(I, J)
+        p[cs] = pl
+        F[(slice(None),) + cs] = local_fluxes(r, pl, g, prob, dec)
+    return MRCMResult(p, F, U, P, dec, loc)
