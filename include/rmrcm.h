@@ -1,0 +1,165 @@
+/*
+ * rmrcm.h - C ABI of the MI355X implementation of the recursive multiscale
+ * Robin coupled method (MRCM) for 2D Darcy flow.
+ *
+ * Method: Abreu, Ferraz, Espirito Santo, Pereira, Santos, Sousa,
+ * "Recursive formulation and parallel implementation of multiscale mixed
+ * methods".  The problem is the mixed Darcy system of Section 2 (model
+ * equations: div u = f, u = -K grad p, p = g_D on the Dirichlet part,
+ * u.n = g_N on the Neumann part) on [0,lx] x [0,ly], discretised on a
+ * uniform nx x ny grid by lowest-order Raviart-Thomas elements with a
+ * lumped velocity mass (the cell-centred two-point scheme that Section 2.1
+ * calls equivalent).  The domain is split into sub_nx x sub_ny-cell
+ * subdomains (Section 3.1 hierarchy, a power of two per direction as in
+ * Section 4) whose interfaces carry piecewise-constant flux and pressure
+ * unknowns on segments of `seg` fine faces (the intermediate scale Hbar of
+ * Section 4).  Subdomains are coupled by Robin conditions with
+ * beta = alpha * Hbar / Keff (Section 5.1, Robin-beta equation).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays are row-major: cell (i, j), i along x, j along y, at index
+ *    j * nx + i.  Permeability, source and pressure are nx*ny doubles.
+ *  - Boundary faces: 2*ny + 2*nx entries ordered W (ny faces, bottom to
+ *    top), E (ny), S (nx faces, left to right), N (nx).  Type 1 =
+ *    Dirichlet (value = pressure), 0 = Neumann (value = OUTWARD INTEGRATED
+ *    flux through the face).
+ *  - The source is cell-integrated (q_c = integral of f over cell c).
+ *  - Flux output: 4*nx*ny doubles, structure of arrays
+ *    [W | E | S | N][ny][nx]: the outward integrated flux of each cell
+ *    through each of its faces.  On the interfaces between subdomains the
+ *    method's fluxes are one-sided (no downscaling, Section 4), so the two
+ *    cells of such a face each report their own value.
+ *  - Interface segments are numbered: vertical segments first, by
+ *    interface line x = I*sub_nx*hx (I = 1..mx-1), bottom to top; then
+ *    horizontal segments by line y = J*sub_ny*hy (J = 1..my-1), left to
+ *    right.  The global normal of a segment points to +x or +y.
+ *  - Every pointer argument may be host or device memory; the library
+ *    tells them apart with hipPointerGetAttributes.  The caller owns every
+ *    buffer it passes; the library copies what it must keep.
+ *  - All functions return RMRCM_OK (0) or a negative RMRCM_E* code and
+ *    never throw.  Invalid arguments are rejected before any device work.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef RMRCM_H
+#define RMRCM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmrcm_ctx rmrcm_ctx;
+
+enum {
+    RMRCM_OK = 0,
+    RMRCM_EINVAL = -1,     /* invalid argument or geometry */
+    RMRCM_ENOMEM = -2,     /* device or host allocation failed */
+    RMRCM_EDEVICE = -3,    /* a HIP call failed */
+    RMRCM_ESINGULAR = -4,  /* a local or interface system is singular */
+    RMRCM_ENOTCONV = -5,   /* iterative refinement did not converge */
+    RMRCM_ESTATE = -6,     /* call out of order (e.g. solve before setup) */
+    RMRCM_ENOTSUP = -7     /* configuration not supported by this build */
+};
+
+/* Precision modes of the local solves.  Interface merges always run in
+ * FP64. */
+enum { RMRCM_FP64 = 0, RMRCM_MIXED = 1, RMRCM_MIXED_LEARNED = 2 };
+
+enum { RMRCM_BC_NEUMANN = 0, RMRCM_BC_DIRICHLET = 1 };
+
+typedef struct {
+    int32_t nx, ny;          /* fine cells; > 0 */
+    double lx, ly;           /* domain extents; > 0 */
+    int32_t sub_nx, sub_ny;  /* subdomain size in cells: divides nx, ny;
+                                nx/sub_nx and ny/sub_ny powers of two;
+                                sub_nx in {4, 8, 16, 32}, sub_ny <= 64 */
+    int32_t seg;             /* segment length in cells; divides sub_nx and sub_ny */
+    double alpha;            /* Robin alpha > 0 */
+    int32_t precision;       /* RMRCM_FP64 | RMRCM_MIXED | RMRCM_MIXED_LEARNED */
+    double ir_tol;           /* mixed: refinement stop (relative residual), default 1e-14 */
+    int32_t ir_max_iter;     /* mixed: refinement sweeps before FP64 fallback, default 8 */
+    double gate_tol;         /* learned: residual gate tau */
+    const char* cnn_weights; /* learned: weight file or NULL */
+    int32_t device;          /* HIP device ordinal */
+} rmrcm_params;
+
+/* Fill *p with defaults (alpha 1, FP64, unit square, device 0); the
+ * geometry fields are zeroed and must be set by the caller. */
+void rmrcm_default_params(rmrcm_params* p);
+
+/* Build a context: every step that depends on the permeability and on the
+ * boundary-condition TYPES only (they enter the local operators):
+ * Robin parameters, the factorisation of every subdomain's local system,
+ * the multiscale basis (one local solve per interface segment side,
+ * Section 2.1 basis problems; one pair of bases per segment collapses to
+ * one in the MuMM setting of Section 4), and the upward sweep of interface
+ * merges of Algorithm 1 for the basis columns (LU factors and coefficient
+ * matrices of every pair, Section 3.2 and its Remark).
+ *   perm:    nx*ny permeabilities, finite and > 0 (host or device).
+ *   bc_type: 2*nx + 2*ny boundary-face types (host or device).
+ *   out:     receives the new context (owned by the library; release with
+ *            rmrcm_destroy).
+ * Errors: EINVAL (geometry, K <= 0 or not finite), ENOTSUP (sub_nx not
+ * supported), ENOMEM, EDEVICE, ESINGULAR. */
+int rmrcm_setup(const rmrcm_params* prm, const double* perm,
+                const int8_t* bc_type, rmrcm_ctx** out);
+
+/* Recompute every permeability-dependent quantity of an existing context
+ * for a new permeability field of the same geometry (the work of
+ * rmrcm_setup without its allocations and table building): Robin
+ * parameters, local factorisations, basis and the upward merges.
+ *   perm: nx*ny permeabilities, finite and > 0 (host or device).
+ * Errors: EINVAL (perm NULL, or a value <= 0 / not finite, detected on the
+ * device; the context then holds no valid factorisation until the next
+ * successful refactor), EDEVICE, ESINGULAR. */
+int rmrcm_refactor(rmrcm_ctx* ctx, const double* perm);
+
+/* Solve for one right-hand side: the particular local solutions (source
+ * and outer boundary data, additive split of Section 2.1), their columns
+ * through the merges, the top interface solve, the downward propagation of
+ * interface values and the final reconstruction of cell pressures and face
+ * fluxes (eq. final).
+ *   source:   nx*ny cell-integrated sources, or NULL for zero.
+ *   bc_value: 2*nx + 2*ny values matching the setup's bc_type.
+ *   pressure: out, nx*ny.     flux: out, 4*nx*ny (layout above).
+ * With no Dirichlet face the pressure is fixed by a zero-mean gauge
+ * (requires sum(source) + sum(Neumann values) = 0 within round-off,
+ * otherwise EINVAL).  On a caller stream (rmrcm_set_stream) device outputs
+ * are complete when that stream completes; host outputs on return. */
+int rmrcm_solve(rmrcm_ctx* ctx, const double* source, const double* bc_value,
+                double* pressure, double* flux);
+
+/* Interface values of the last solve: U (normal flux density along the
+ * global normal) and P (pressure) per segment, nseg doubles each, in the
+ * documented segment order.  Host or device pointers. */
+int rmrcm_get_interface(rmrcm_ctx* ctx, double* U, double* P);
+
+/* Number of interface segments and of finest-level local solves
+ * (basis + particular, the Table 3 count). */
+int rmrcm_counts(const rmrcm_ctx* ctx, int64_t* nseg, int64_t* nlocal);
+
+/* Run all further work of this context on the caller's hipStream_t
+ * (e.g. torch.cuda.current_stream().cuda_stream).  NULL restores the
+ * library's own stream. */
+int rmrcm_set_stream(rmrcm_ctx* ctx, void* hip_stream);
+
+/* JSON object with per-phase device times of the last setup and solve
+ * (milliseconds, from HIP events recorded on the context's stream; waits
+ * for those events), workspace bytes and counters.  Writes at most cap
+ * bytes including the terminating NUL; returns the length it needs, or a
+ * negative error. */
+int rmrcm_get_stats(const rmrcm_ctx* ctx, char* json, size_t cap);
+
+/* Release the context and all device memory it owns.  NULL is ignored. */
+void rmrcm_destroy(rmrcm_ctx* ctx);
+
+/* Static message for a status code. */
+const char* rmrcm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMRCM_H */

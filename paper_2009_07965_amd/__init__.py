@@ -1,0 +1,27 @@
+"""MI355X-native recursive multiscale Robin coupled method (MRCM).
+
+The product is the C-ABI shared library ``librmrcm.so`` built from
+``csrc/`` (HIP kernels for gfx950 plus the host runtime); ``rmrcm`` is its
+Python binding.  There is no CPU fallback: without the built library the
+binding raises on first use.
+"""
+
+from .rmrcm import (  # noqa: F401
+    Solver,
+    RMRCMError,
+    load_library,
+    rmrcm_default_params,
+    rmrcm_setup,
+    rmrcm_refactor,
+    rmrcm_solve,
+    rmrcm_get_interface,
+    rmrcm_counts,
+    rmrcm_set_stream,
+    rmrcm_get_stats,
+    rmrcm_destroy,
+    rmrcm_strerror,
+    RMRCM_FP64,
+    RMRCM_MIXED,
+    RMRCM_MIXED_LEARNED,
+    EXPORTS,
+)

@@ -1,0 +1,518 @@
+// Host runtime behind the C ABI of include/rmrcm.h: validation, the level
+// tables of the nested binary hierarchy (Section 3.1), the device memory
+// plan and the order of kernel launches for setup and solve.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "rmrcm_internal.h"
+
+using rmrcm::Geo;
+using rmrcm::Level;
+
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int v) {
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) {                       \
+            if (e_ == hipErrorOutOfMemory) return RMRCM_ENOMEM; \
+            return RMRCM_EDEVICE;                     \
+        }                                             \
+    } while (0)
+
+template <typename T>
+int dalloc(rmrcm_ctx* c, T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    const size_t bytes = count * sizeof(T);
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return e == hipErrorOutOfMemory ? RMRCM_ENOMEM : RMRCM_EDEVICE;
+    }
+    c->device_bytes += bytes;
+    if (hipMemsetAsync(*p, 0, bytes, c->stream) != hipSuccess) return RMRCM_EDEVICE;
+    return RMRCM_OK;
+}
+
+#define TRY(expr)                \
+    do {                         \
+        int r_ = (expr);         \
+        if (r_ != RMRCM_OK) return r_; \
+    } while (0)
+
+int validate(const rmrcm_params* p) {
+    if (!p) return RMRCM_EINVAL;
+    if (p->nx <= 0 || p->ny <= 0 || p->sub_nx <= 0 || p->sub_ny <= 0 || p->seg <= 0)
+        return RMRCM_EINVAL;
+    if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly))
+        return RMRCM_EINVAL;
+    if (!(p->alpha > 0) || !std::isfinite(p->alpha)) return RMRCM_EINVAL;
+    if (p->nx % p->sub_nx || p->ny % p->sub_ny) return RMRCM_EINVAL;
+    if (p->sub_nx % p->seg || p->sub_ny % p->seg) return RMRCM_EINVAL;
+    if (!is_pow2(p->nx / p->sub_nx) || !is_pow2(p->ny / p->sub_ny)) return RMRCM_EINVAL;
+    if (p->precision < RMRCM_FP64 || p->precision > RMRCM_MIXED_LEARNED) return RMRCM_EINVAL;
+    if (p->sub_nx != 4 && p->sub_nx != 8 && p->sub_nx != 16 && p->sub_nx != 32) return RMRCM_ENOTSUP;
+    if (p->sub_ny > 64) return RMRCM_ENOTSUP;
+    if (p->precision != RMRCM_FP64) return RMRCM_ENOTSUP;
+    // the basis block of one subdomain row must fit the local kernel's LDS
+    const int R = 2 * (p->sub_nx + p->sub_ny) / p->seg;
+    const size_t lds = sizeof(double) * (size_t)(3 * p->sub_nx * p->sub_nx + 2 * p->sub_nx * R + 4 * p->sub_nx);
+    if (lds > 160 * 1024) return RMRCM_ENOTSUP;
+    return RMRCM_OK;
+}
+
+void build_geo(rmrcm_ctx* c) {
+    const rmrcm_params& p = c->prm;
+    Geo& g = c->geo;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.bx = p.sub_nx;
+    g.by = p.sub_ny;
+    g.sg = p.seg;
+    g.mx = p.nx / p.sub_nx;
+    g.my = p.ny / p.sub_ny;
+    g.nsx = g.bx / g.sg;
+    g.nsy = g.by / g.sg;
+    g.lines_v = g.ny / g.sg;
+    g.lines_h = g.nx / g.sg;
+    g.nv = (g.mx - 1) * g.lines_v;
+    g.nseg = g.nv + (g.my - 1) * g.lines_h;
+    g.hx = p.lx / p.nx;
+    g.hy = p.ly / p.ny;
+    g.alpha = p.alpha;
+}
+
+// Host tables of every level: node grid, slots, slot codes, merge maps.
+void build_levels(rmrcm_ctx* c) {
+    const Geo& g = c->geo;
+    c->D = ilog2(g.mx) + ilog2(g.my);
+    c->levels.assign(c->D + 1, Level());
+    int nxn = 1, nyn = 1, sx = g.mx, sy = g.my;
+    for (int d = 0; d <= c->D; ++d) {
+        Level& L = c->levels[d];
+        L.depth = d;
+        L.nodes_x = nxn;
+        L.nodes_y = nyn;
+        L.nnodes = nxn * nyn;
+        L.sx = sx;
+        L.sy = sy;
+        const int hw = sy * g.nsy, hs = sx * g.nsx;
+        L.nslot = 2 * (hw + hs);
+        L.ld = L.nslot + 1;
+        L.h_slotseg.assign((size_t)L.nnodes * L.nslot, -1);
+        for (int iy = 0; iy < nyn; ++iy)
+            for (int ix = 0; ix < nxn; ++ix) {
+                int* s = &L.h_slotseg[(size_t)(iy * nxn + ix) * L.nslot];
+                const int I0 = ix * sx, J0 = iy * sy;
+                for (int t = 0; t < hw; ++t) {
+                    if (I0 > 0) s[t] = rmrcm::slot_code((I0 - 1) * g.lines_v + J0 * g.nsy + t, 0);
+                    if (I0 + sx < g.mx)
+                        s[hw + t] = rmrcm::slot_code((I0 + sx - 1) * g.lines_v + J0 * g.nsy + t, 1);
+                }
+                for (int t = 0; t < hs; ++t) {
+                    if (J0 > 0)
+                        s[2 * hw + t] = rmrcm::slot_code(g.nv + (J0 - 1) * g.lines_h + I0 * g.nsx + t, 0);
+                    if (J0 + sy < g.my)
+                        s[2 * hw + hs + t] =
+                            rmrcm::slot_code(g.nv + (J0 + sy - 1) * g.lines_h + I0 * g.nsx + t, 1);
+                }
+            }
+        if (d == c->D) break;
+        // merge of this level from its children: split the side with more
+        // subdomains, x on ties
+        L.cut = sx >= sy ? 0 : 1;
+        L.h_pmap.assign(L.nslot, 0);
+        if (L.cut == 0) {
+            const int chw = hw, chs = hs / 2;
+            L.g = chw;
+            for (int t = 0; t < hw; ++t) {
+                L.h_pmap[t] = (0 << 24) | t;
+                L.h_pmap[hw + t] = (1 << 24) | (chw + t);
+            }
+            for (int t = 0; t < hs; ++t) {
+                L.h_pmap[2 * hw + t] = t < chs ? ((0 << 24) | (2 * chw + t)) : ((1 << 24) | (2 * chw + t - chs));
+                L.h_pmap[2 * hw + hs + t] =
+                    t < chs ? ((0 << 24) | (2 * chw + chs + t)) : ((1 << 24) | (2 * chw + t));
+            }
+            L.h_gmap.resize(2 * L.g);
+            for (int t = 0; t < L.g; ++t) {
+                L.h_gmap[t] = chw + t;   // child 1, E side
+                L.h_gmap[L.g + t] = t;   // child 2, W side
+            }
+            nxn *= 2;
+            sx /= 2;
+        } else {
+            const int chw = hw / 2, chs = hs;
+            L.g = chs;
+            for (int t = 0; t < hw; ++t) {
+                L.h_pmap[t] = t < chw ? ((0 << 24) | t) : ((1 << 24) | (t - chw));
+                L.h_pmap[hw + t] = t < chw ? ((0 << 24) | (chw + t)) : ((1 << 24) | t);
+            }
+            for (int t = 0; t < hs; ++t) {
+                L.h_pmap[2 * hw + t] = (0 << 24) | (2 * chw + t);
+                L.h_pmap[2 * hw + hs + t] = (1 << 24) | (2 * chw + chs + t);
+            }
+            L.h_gmap.resize(2 * L.g);
+            for (int t = 0; t < L.g; ++t) {
+                L.h_gmap[t] = 2 * chw + chs + t;   // child 1, N side
+                L.h_gmap[L.g + t] = 2 * chw + t;   // child 2, S side
+            }
+            nyn *= 2;
+            sy /= 2;
+        }
+        L.xi = 2 * L.g;
+    }
+}
+
+int alloc_levels(rmrcm_ctx* c) {
+    for (int d = 0; d <= c->D; ++d) {
+        Level& L = c->levels[d];
+        TRY(dalloc(c, &L.slotseg, L.h_slotseg.size()));
+        HIP_TRY(hipMemcpyAsync(L.slotseg, L.h_slotseg.data(), L.h_slotseg.size() * sizeof(int),
+                               hipMemcpyHostToDevice, c->stream));
+        if (d >= 1) TRY(dalloc(c, &L.T, (size_t)L.nnodes * L.nslot * L.ld));
+        if (d < c->D) {
+            TRY(dalloc(c, &L.pmap, L.h_pmap.size()));
+            TRY(dalloc(c, &L.gmap, L.h_gmap.size()));
+            HIP_TRY(hipMemcpyAsync(L.pmap, L.h_pmap.data(), L.h_pmap.size() * sizeof(int),
+                                   hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(L.gmap, L.h_gmap.data(), L.h_gmap.size() * sizeof(int),
+                                   hipMemcpyHostToDevice, c->stream));
+            TRY(dalloc(c, &L.M, (size_t)L.nnodes * L.xi * L.xi));
+            TRY(dalloc(c, &L.piv, (size_t)L.nnodes * L.xi));
+            TRY(dalloc(c, &L.X, (size_t)L.nnodes * L.xi * L.ld));
+        }
+    }
+    // the root level keeps a trace buffer only when it is also the leaf level
+    if (c->D == 0) TRY(dalloc(c, &c->levels[0].T, (size_t)c->levels[0].nslot * c->levels[0].ld));
+    return RMRCM_OK;
+}
+
+void free_all(rmrcm_ctx* c) {
+    auto f = [](void* p) {
+        if (p) (void)hipFree(p);
+    };
+    for (Level& L : c->levels) {
+        f(L.T);
+        f(L.slotseg);
+        f(L.pmap);
+        f(L.gmap);
+        f(L.M);
+        f(L.piv);
+        f(L.X);
+    }
+    f(c->K);
+    f(c->bct);
+    f(c->beta);
+    f(c->seglen);
+    f(c->Pstore);
+    f(c->Psi);
+    f(c->pbar);
+    f(c->glo);
+    f(c->ghi);
+    f(c->q);
+    f(c->bcv);
+    f(c->pout);
+    f(c->fout);
+    f(c->Uout);
+    f(c->Pout);
+    f(c->flags);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+}
+
+int check_flags(rmrcm_ctx* c) {
+    int h[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (h[rmrcm::FLAG_BAD_PERM]) return RMRCM_EINVAL;
+    if (h[rmrcm::FLAG_LOCAL_SINGULAR] || h[rmrcm::FLAG_MERGE_SINGULAR]) return RMRCM_ESINGULAR;
+    return RMRCM_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1.f;
+    }
+    return ms;
+}
+
+int run_setup(rmrcm_ctx* c) {
+    HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+    HIP_TRY(hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
+    HIP_TRY(rmrcm::launch_check_perm(c));
+    HIP_TRY(rmrcm::launch_beta(c));
+    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    HIP_TRY(rmrcm::launch_local_setup(c));
+    HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+    for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d));
+    HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+    c->setup_recorded = true;
+    TRY(check_flags(c));
+    return RMRCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rmrcm_default_params(rmrcm_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->lx = 1.0;
+    p->ly = 1.0;
+    p->alpha = 1.0;
+    p->precision = RMRCM_FP64;
+    p->ir_tol = 1e-14;
+    p->ir_max_iter = 8;
+    p->gate_tol = 1e-6;
+    p->cnn_weights = nullptr;
+    p->device = 0;
+}
+
+const char* rmrcm_strerror(int s) {
+    switch (s) {
+        case RMRCM_OK: return "ok";
+        case RMRCM_EINVAL: return "invalid argument";
+        case RMRCM_ENOMEM: return "out of memory";
+        case RMRCM_EDEVICE: return "HIP device error";
+        case RMRCM_ESINGULAR: return "singular local or interface system";
+        case RMRCM_ENOTCONV: return "iterative refinement did not converge";
+        case RMRCM_ESTATE: return "call out of order";
+        case RMRCM_ENOTSUP: return "configuration not supported";
+    }
+    return "unknown status";
+}
+
+int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_type,
+                rmrcm_ctx** out) {
+    if (!out) return RMRCM_EINVAL;
+    *out = nullptr;
+    int v = validate(prm);
+    if (v != RMRCM_OK) return v;
+    if (!perm || !bc_type) return RMRCM_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return RMRCM_EDEVICE;
+    }
+    if (prm->device < 0 || prm->device >= ndev) return RMRCM_EINVAL;
+    if (hipSetDevice(prm->device) != hipSuccess) return RMRCM_EDEVICE;
+
+    const size_t ncell = (size_t)prm->nx * prm->ny;
+    const size_t nbf = 2 * (size_t)prm->nx + 2 * (size_t)prm->ny;
+    const bool kdev = is_device_ptr(perm), tdev = is_device_ptr(bc_type);
+    // Validate the host-side copies before any device work.
+    std::vector<int8_t> ht(nbf);
+    if (tdev) {
+        if (hipMemcpy(ht.data(), bc_type, nbf, hipMemcpyDeviceToHost) != hipSuccess) return RMRCM_EDEVICE;
+    } else {
+        std::memcpy(ht.data(), bc_type, nbf);
+    }
+    bool any_dir = false;
+    for (int8_t t : ht) {
+        if (t != RMRCM_BC_NEUMANN && t != RMRCM_BC_DIRICHLET) return RMRCM_EINVAL;
+        any_dir |= t == RMRCM_BC_DIRICHLET;
+    }
+    std::vector<double> hk;
+    if (kdev) {
+        hk.resize(ncell);
+        if (hipMemcpy(hk.data(), perm, ncell * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+            return RMRCM_EDEVICE;
+    }
+    const double* kp = kdev ? hk.data() : perm;
+    for (size_t i = 0; i < ncell; ++i)
+        if (!(kp[i] > 0) || !std::isfinite(kp[i])) return RMRCM_EINVAL;
+
+    rmrcm_ctx* c = new (std::nothrow) rmrcm_ctx();
+    if (!c) return RMRCM_ENOMEM;
+    c->prm = *prm;
+    c->device = prm->device;
+    c->any_dirichlet = any_dir;
+    build_geo(c);
+    build_levels(c);
+    if (!any_dir) {
+        delete c;
+        return RMRCM_ENOTSUP;   // zero-mean gauge of all-Neumann problems: not in this build
+    }
+    auto fail = [&](int r) {
+        free_all(c);
+        delete c;
+        return r;
+    };
+    if (hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(RMRCM_EDEVICE);
+    c->stream = c->own_stream;
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return fail(RMRCM_EDEVICE);
+    const Geo& g = c->geo;
+    const size_t nsub = (size_t)g.mx * g.my;
+    const size_t n = (size_t)g.bx * g.by;
+    const int R = c->levels[c->D].nslot;
+    int r = RMRCM_OK;
+    if ((r = dalloc(c, &c->K, ncell)) || (r = dalloc(c, &c->bct, nbf)) ||
+        (r = dalloc(c, &c->beta, g.nseg)) || (r = dalloc(c, &c->seglen, g.nseg)) ||
+        (r = dalloc(c, &c->Pstore, nsub * g.by * g.bx * g.bx)) ||
+        (r = dalloc(c, &c->Psi, nsub * R * n)) || (r = dalloc(c, &c->pbar, nsub * n)) ||
+        (r = dalloc(c, &c->glo, g.nseg)) || (r = dalloc(c, &c->ghi, g.nseg)) ||
+        (r = dalloc(c, &c->q, ncell)) || (r = dalloc(c, &c->bcv, nbf)) ||
+        (r = dalloc(c, &c->pout, ncell)) || (r = dalloc(c, &c->fout, 4 * ncell)) ||
+        (r = dalloc(c, &c->Uout, g.nseg)) || (r = dalloc(c, &c->Pout, g.nseg)) ||
+        (r = dalloc(c, &c->flags, 4)))
+        return fail(r);
+    if ((r = alloc_levels(c)) != RMRCM_OK) return fail(r);
+    if (hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return fail(RMRCM_EDEVICE);
+    c->n_local_solves = 2 * (int64_t)g.nseg + (int64_t)nsub;
+    if ((r = run_setup(c)) != RMRCM_OK) return fail(r);
+    *out = c;
+    return RMRCM_OK;
+}
+
+int rmrcm_refactor(rmrcm_ctx* c, const double* perm) {
+    if (!c || !perm) return RMRCM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+    c->solved = false;
+    HIP_TRY(hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    return run_setup(c);
+}
+
+int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, double* pressure,
+                double* flux) {
+    if (!c || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    const Geo& g = c->geo;
+    const size_t ncell = (size_t)g.nx * g.ny;
+    const size_t nbf = 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+    HIP_TRY(hipEventRecord(c->ev[4], c->stream));
+    if (source) {
+        HIP_TRY(hipMemcpyAsync(c->q, source, ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    } else {
+        HIP_TRY(hipMemsetAsync(c->q, 0, ncell * sizeof(double), c->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(c->bcv, bc_value, nbf * sizeof(double), hipMemcpyDefault, c->stream));
+    HIP_TRY(hipEventRecord(c->ev[5], c->stream));
+    HIP_TRY(rmrcm::launch_local_particular(c));
+    HIP_TRY(hipEventRecord(c->ev[6], c->stream));
+    for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
+    HIP_TRY(hipEventRecord(c->ev[7], c->stream));
+    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    HIP_TRY(hipEventRecord(c->ev[8], c->stream));
+    HIP_TRY(rmrcm::launch_reconstruct(c));
+    HIP_TRY(hipEventRecord(c->ev[9], c->stream));
+    HIP_TRY(hipMemcpyAsync(pressure, c->pout, ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    HIP_TRY(hipMemcpyAsync(flux, c->fout, 4 * ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    HIP_TRY(hipEventRecord(c->ev[10], c->stream));
+    c->solve_recorded = true;
+    const bool host_out = !is_device_ptr(pressure) || !is_device_ptr(flux);
+    if (host_out || c->stream == c->own_stream) HIP_TRY(hipStreamSynchronize(c->stream));
+    c->solved = true;
+    return RMRCM_OK;
+}
+
+int rmrcm_get_interface(rmrcm_ctx* c, double* U, double* P) {
+    if (!c || !U || !P) return RMRCM_EINVAL;
+    if (!c->solved) return RMRCM_ESTATE;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    if (c->geo.nseg == 0) return RMRCM_OK;
+    HIP_TRY(rmrcm::launch_interface_values(c));
+    const size_t b = (size_t)c->geo.nseg * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(U, c->Uout, b, hipMemcpyDefault, c->stream));
+    HIP_TRY(hipMemcpyAsync(P, c->Pout, b, hipMemcpyDefault, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return RMRCM_OK;
+}
+
+int rmrcm_counts(const rmrcm_ctx* c, int64_t* nseg, int64_t* nlocal) {
+    if (!c) return RMRCM_EINVAL;
+    if (nseg) *nseg = c->geo.nseg;
+    if (nlocal) *nlocal = c->n_local_solves;
+    return RMRCM_OK;
+}
+
+int rmrcm_set_stream(rmrcm_ctx* c, void* s) {
+    if (!c) return RMRCM_EINVAL;
+    c->stream = s ? (hipStream_t)s : c->own_stream;
+    return RMRCM_OK;
+}
+
+int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
+    if (!cc) return RMRCM_EINVAL;
+    rmrcm_ctx* c = const_cast<rmrcm_ctx*>(cc);
+    // phase times of the last setup and solve, read from their events
+    if (c->setup_recorded && hipEventSynchronize(c->ev[3]) == hipSuccess) {
+        c->t_setup_ms[0] = elapsed(c->ev[0], c->ev[1]);
+        c->t_setup_ms[1] = elapsed(c->ev[1], c->ev[2]);
+        c->t_setup_ms[2] = elapsed(c->ev[2], c->ev[3]);
+        c->t_setup_ms[3] = elapsed(c->ev[0], c->ev[3]);
+    }
+    if (c->solve_recorded && hipEventSynchronize(c->ev[10]) == hipSuccess) {
+        c->t_solve_ms[0] = elapsed(c->ev[4], c->ev[5]);
+        c->t_solve_ms[1] = elapsed(c->ev[5], c->ev[6]);
+        c->t_solve_ms[2] = elapsed(c->ev[6], c->ev[7]);
+        c->t_solve_ms[3] = elapsed(c->ev[7], c->ev[8]);
+        c->t_solve_ms[4] = elapsed(c->ev[8], c->ev[9]);
+        c->t_solve_ms[5] = elapsed(c->ev[9], c->ev[10]);
+        c->t_solve_ms[6] = elapsed(c->ev[4], c->ev[10]);
+    }
+    char buf[2048];
+    const int n = std::snprintf(
+        buf, sizeof(buf),
+        "{\"setup_ms\": {\"beta\": %.6f, \"local\": %.6f, \"merge\": %.6f, \"total\": %.6f}, "
+        "\"solve_ms\": {\"upload\": %.6f, \"local\": %.6f, \"merge\": %.6f, \"down\": %.6f, "
+        "\"reconstruct\": %.6f, \"download\": %.6f, \"total\": %.6f}, "
+        "\"levels\": %d, \"nseg\": %d, \"subdomains\": %d, \"local_solves\": %lld, "
+        "\"device_bytes\": %zu}",
+        c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
+        c->t_solve_ms[1], c->t_solve_ms[2], c->t_solve_ms[3], c->t_solve_ms[4], c->t_solve_ms[5],
+        c->t_solve_ms[6], c->D, c->geo.nseg, c->geo.mx * c->geo.my, (long long)c->n_local_solves,
+        c->device_bytes);
+    if (json && cap > 0) {
+        std::strncpy(json, buf, cap - 1);
+        json[cap - 1] = '\0';
+    }
+    return n + 1;
+}
+
+void rmrcm_destroy(rmrcm_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+}  // extern "C"

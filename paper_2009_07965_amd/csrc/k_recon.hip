@@ -1,0 +1,133 @@
+// Final reconstruction (eq. final, Section 2.2) and flux assembly.
+//
+// Each finest subdomain gathers the Robin datum of each of its boundary
+// slots (the one-sided datum g = P - beta (n_i.n) U of its own side), then
+//     p = pbar + sum_a Psi_a g_a
+// over its cells, and the four outward integrated fluxes of every cell:
+// interior faces by the two-point law, Robin faces by
+// |f| (p_c - g) / (rho_c + beta), outer faces by the boundary data.
+
+#include "rmrcm_internal.h"
+
+namespace rmrcm {
+
+__device__ inline double kc(const double* __restrict__ K, const Geo& g, int gi, int gj) {
+    return K[(size_t)gj * g.nx + gi];
+}
+
+template <int BX>
+__global__ __launch_bounds__(256) void k_reconstruct(Geo g, const double* __restrict__ K,
+                                                     const int8_t* __restrict__ bct,
+                                                     const double* __restrict__ bcv,
+                                                     const double* __restrict__ beta,
+                                                     const int* __restrict__ slotseg, int R,
+                                                     const double* __restrict__ Psi,
+                                                     const double* __restrict__ pbar,
+                                                     const double* __restrict__ glo,
+                                                     const double* __restrict__ ghi,
+                                                     double* __restrict__ p_out,
+                                                     double* __restrict__ f_out) {
+    extern __shared__ double sm[];
+    double* gs = sm;            // R
+    double* ps = gs + R;        // BX * BY
+    const int sub = blockIdx.x;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int BY = g.by, n = BX * BY;
+    const int* ss = slotseg + (size_t)sub * R;
+    for (int a = threadIdx.x; a < R; a += blockDim.x) {
+        const int code = ss[a];
+        gs[a] = code < 0 ? 0.0 : ((code & 1) ? glo[code >> 1] : ghi[code >> 1]);
+    }
+    __syncthreads();
+    const double* Ps = Psi + (size_t)sub * R * n;
+    const double* pb = pbar + (size_t)sub * n;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        double s = pb[c];
+        for (int a = 0; a < R; ++a) s += Ps[(size_t)a * n + c] * gs[a];
+        ps[c] = s;
+        const int i = c % BX, j = c / BX;
+        p_out[(size_t)(J * BY + j) * g.nx + I * BX + i] = s;
+    }
+    __syncthreads();
+    const size_t plane = (size_t)g.nx * g.ny;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        const int i = c % BX, j = c / BX;
+        const int gi = I * BX + i, gj = J * BY + j;
+        const double k0 = kc(K, g, gi, gj);
+        const double p = ps[c];
+        double F[4];
+        for (int side = 0; side < 4; ++side) {
+            const bool inside = side == 0 ? i > 0 : side == 1 ? i < BX - 1 : side == 2 ? j > 0 : j < BY - 1;
+            const double area = side < 2 ? g.hy : g.hx;
+            const double h = side < 2 ? g.hx : g.hy;
+            const double rc = h / (2.0 * k0);
+            if (inside) {
+                const int ni = i + (side == 0 ? -1 : side == 1 ? 1 : 0);
+                const int nj = j + (side == 2 ? -1 : side == 3 ? 1 : 0);
+                const double rn = h / (2.0 * kc(K, g, I * BX + ni, J * BY + nj));
+                F[side] = area / (rc + rn) * (p - ps[nj * BX + ni]);
+                continue;
+            }
+            const int t = (side < 2 ? j : i) / g.sg;
+            const int a = side == 0 ? t : side == 1 ? g.nsy + t : side == 2 ? 2 * g.nsy + t
+                                                                               : 2 * g.nsy + g.nsx + t;
+            const int code = ss[a];
+            if (code >= 0) {
+                F[side] = area / (rc + beta[code >> 1]) * (p - gs[a]);
+            } else {
+                const int f = side == 0 ? gj : side == 1 ? g.ny + gj : side == 2 ? 2 * g.ny + gi
+                                                                                   : 2 * g.ny + g.nx + gi;
+                F[side] = bct[f] == RMRCM_BC_DIRICHLET ? area / rc * (p - bcv[f]) : bcv[f];
+            }
+        }
+        const size_t o = (size_t)gj * g.nx + gi;
+        f_out[o] = F[0];
+        f_out[plane + o] = F[1];
+        f_out[2 * plane + o] = F[2];
+        f_out[3 * plane + o] = F[3];
+    }
+}
+
+// Interface values per segment from the two one-sided Robin data:
+// P = (g_lo + g_hi) / 2, U = (g_hi - g_lo) / (2 beta).
+__global__ void k_interface_values(int nseg, const double* __restrict__ glo,
+                                   const double* __restrict__ ghi, const double* __restrict__ beta,
+                                   double* __restrict__ U, double* __restrict__ P) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nseg) return;
+    P[e] = 0.5 * (glo[e] + ghi[e]);
+    U[e] = (ghi[e] - glo[e]) / (2.0 * beta[e]);
+}
+
+template <int BX>
+static hipError_t recon_bx(rmrcm_ctx* c) {
+    const Level& L = c->levels[c->D];
+    const int nsub = c->geo.mx * c->geo.my;
+    const size_t lds = sizeof(double) * (size_t)(L.nslot + BX * c->geo.by);
+    hipError_t e = hipFuncSetAttribute((const void*)k_reconstruct<BX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reconstruct<BX>, dim3(nsub), dim3(256), lds, c->stream, c->geo, c->K,
+                       c->bct, c->bcv, c->beta, L.slotseg, L.nslot, c->Psi, c->pbar, c->glo,
+                       c->ghi, c->pout, c->fout);
+    return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(rmrcm_ctx* c) {
+    switch (c->geo.bx) {
+        case 4: return recon_bx<4>(c);
+        case 8: return recon_bx<8>(c);
+        case 16: return recon_bx<16>(c);
+        case 32: return recon_bx<32>(c);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_interface_values(rmrcm_ctx* c) {
+    if (c->geo.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_interface_values, dim3((c->geo.nseg + 255) / 256), dim3(256), 0, c->stream,
+                       c->geo.nseg, c->glo, c->ghi, c->beta, c->Uout, c->Pout);
+    return hipGetLastError();
+}
+
+}  // namespace rmrcm

@@ -1,0 +1,114 @@
+// Internal declarations shared by the host runtime (api.cpp) and the HIP
+// kernel files.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rmrcm.h"
+
+namespace rmrcm {
+
+// Geometry of the finest decomposition, passed by value to kernels.
+struct Geo {
+    int nx, ny;        // fine cells
+    int bx, by;        // subdomain size (cells)
+    int sg;            // segment length (cells)
+    int mx, my;        // subdomains per direction
+    int nsx, nsy;      // segments per S/N side and per W/E side of a subdomain
+    int lines_v;       // segments along one vertical interface line (= ny / sg)
+    int lines_h;       // segments along one horizontal interface line (= nx / sg)
+    int nv;            // number of vertical segments
+    int nseg;          // total segments
+    double hx, hy;
+    double alpha;
+};
+
+// Slot -> segment code: (segment id << 1) | low_side, or -1 if the slot lies
+// on the outer boundary.  low_side = 1 when the node is on the low (left or
+// bottom) side of the segment, i.e. the slot is on its E or N side.
+__host__ __device__ inline int slot_code(int seg, int low) { return (seg << 1) | low; }
+
+// One level of the nested binary hierarchy (depth 0 = whole domain,
+// depth D = finest subdomains).  Nodes at one depth all have the same
+// shape; their slots (boundary segments, listed W, E, S, N) are padded to
+// the full perimeter, inactive slots carry zero trace rows and columns.
+struct Level {
+    int depth = 0;
+    int nodes_x = 0, nodes_y = 0, nnodes = 0;
+    int sx = 0, sy = 0;        // node size in subdomains
+    int nslot = 0;             // slots per node
+    int ld = 0;                // nslot + 1 (trace columns: slots + particular)
+    double* T = nullptr;       // [nnodes][nslot][ld] traces (depth >= 1)
+    int* slotseg = nullptr;    // [nnodes][nslot] slot codes
+    // merge of this level's nodes from their two children (depth < D)
+    int cut = 0;               // 0: cut in x (children side by side), 1: cut in y
+    int g = 0;                 // segments on gamma
+    int xi = 0;                // 2 g interface unknowns (one Robin datum per side)
+    int* pmap = nullptr;       // [nslot] (child << 24) | child slot
+    int* gmap = nullptr;       // [2][g] gamma -> child-1 slot, child-2 slot
+    double* M = nullptr;       // [nnodes][xi][xi] LU factors (in place)
+    int* piv = nullptr;        // [nnodes][xi]
+    double* X = nullptr;       // [nnodes][xi][ld] coefficients of every column
+    std::vector<int> h_pmap, h_gmap, h_slotseg;
+};
+
+}  // namespace rmrcm
+
+struct rmrcm_ctx {
+    rmrcm_params prm{};
+    rmrcm::Geo geo{};
+    int D = 0;                               // finest depth
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t stream = nullptr;
+    bool any_dirichlet = false;
+    bool solved = false;
+    bool setup_recorded = false;
+    bool solve_recorded = false;
+    // device arrays
+    double* K = nullptr;                     // [ny][nx]
+    int8_t* bct = nullptr;                   // [2ny + 2nx]
+    double* beta = nullptr;                  // [nseg]
+    double* seglen = nullptr;                // [nseg]
+    double* Pstore = nullptr;                // [nsub][by][bx][bx]  S_j^{-1} of every block row
+    double* Psi = nullptr;                   // [nsub][nslot][bx*by] basis pressures
+    double* pbar = nullptr;                  // [nsub][bx*by] particular pressures
+    double* glo = nullptr;                   // [nseg] Robin datum on the low side
+    double* ghi = nullptr;                   // [nseg] Robin datum on the high side
+    double* q = nullptr;                     // staging for host inputs / outputs
+    double* bcv = nullptr;
+    double* pout = nullptr;
+    double* fout = nullptr;
+    double* Uout = nullptr;
+    double* Pout = nullptr;
+    int* flags = nullptr;                    // [4] device error flags
+    std::vector<rmrcm::Level> levels;        // index = depth
+    size_t device_bytes = 0;
+    // timing
+    hipEvent_t ev[16] = {};
+    double t_setup_ms[8] = {};
+    double t_solve_ms[8] = {};
+    int64_t n_local_solves = 0;
+};
+
+namespace rmrcm {
+
+// Kernel launchers (return hipError_t of the launch).
+hipError_t launch_beta(rmrcm_ctx* c);
+hipError_t launch_check_perm(rmrcm_ctx* c);
+hipError_t launch_local_setup(rmrcm_ctx* c);
+hipError_t launch_local_particular(rmrcm_ctx* c);
+hipError_t launch_merge_setup(rmrcm_ctx* c, int depth);
+hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
+hipError_t launch_down(rmrcm_ctx* c, int depth);
+hipError_t launch_reconstruct(rmrcm_ctx* c);
+hipError_t launch_interface_values(rmrcm_ctx* c);
+
+// Device error flag slots.
+enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2 };
+
+}  // namespace rmrcm

@@ -1,0 +1,231 @@
+"""Python binding of the C ABI in include/rmrcm.h.
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Functions keep the C names; ``Solver`` is a small convenience
+class over them.  Arrays may be NumPy arrays (host) or torch tensors on the
+GPU (device pointers are passed straight through, so inputs already in HBM
+are not copied through the host).
+
+If the shared library is missing the import fails loudly: there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librmrcm.so")
+
+RMRCM_OK = 0
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR",
+          -5: "ENOTCONV", -6: "ESTATE", -7: "ENOTSUP"}
+RMRCM_FP64, RMRCM_MIXED, RMRCM_MIXED_LEARNED = 0, 1, 2
+RMRCM_BC_NEUMANN, RMRCM_BC_DIRICHLET = 0, 1
+
+
+class rmrcm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double),
+        ("sub_nx", ctypes.c_int32), ("sub_ny", ctypes.c_int32),
+        ("seg", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("ir_tol", ctypes.c_double),
+        ("ir_max_iter", ctypes.c_int32),
+        ("gate_tol", ctypes.c_double),
+        ("cnn_weights", ctypes.c_char_p),
+        ("device", ctypes.c_int32),
+    ]
+
+
+EXPORTS = [
+    "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_solve", "rmrcm_get_interface",
+    "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
+    "rmrcm_strerror",
+]
+
+
+class RMRCMError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (where, STATUS.get(status, "?"), status))
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("librmrcm.so not built (run paper_2009_07965_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, dp, i8p = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p
+    lib.rmrcm_default_params.argtypes = [ctypes.POINTER(rmrcm_params)]
+    lib.rmrcm_default_params.restype = None
+    lib.rmrcm_setup.argtypes = [ctypes.POINTER(rmrcm_params), dp, i8p, ctypes.POINTER(vp)]
+    lib.rmrcm_setup.restype = ctypes.c_int
+    lib.rmrcm_refactor.argtypes = [vp, dp]
+    lib.rmrcm_refactor.restype = ctypes.c_int
+    lib.rmrcm_solve.argtypes = [vp, dp, dp, dp, dp]
+    lib.rmrcm_solve.restype = ctypes.c_int
+    lib.rmrcm_get_interface.argtypes = [vp, dp, dp]
+    lib.rmrcm_get_interface.restype = ctypes.c_int
+    lib.rmrcm_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.rmrcm_counts.restype = ctypes.c_int
+    lib.rmrcm_set_stream.argtypes = [vp, vp]
+    lib.rmrcm_set_stream.restype = ctypes.c_int
+    lib.rmrcm_get_stats.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.rmrcm_get_stats.restype = ctypes.c_int
+    lib.rmrcm_destroy.argtypes = [vp]
+    lib.rmrcm_destroy.restype = None
+    lib.rmrcm_strerror.argtypes = [ctypes.c_int]
+    lib.rmrcm_strerror.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        _lib = load_library()
+    return _lib
+
+
+def _ptr(a, dtype):
+    """Raw pointer of a NumPy array (host) or torch tensor (any device)."""
+    if a is None:
+        return None, None
+    if hasattr(a, "data_ptr"):                      # torch tensor
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return ctypes.c_void_p(arr.ctypes.data), arr
+
+
+def _check(st, where):
+    if st != RMRCM_OK:
+        raise RMRCMError(st, where)
+
+
+def rmrcm_default_params() -> rmrcm_params:
+    p = rmrcm_params()
+    lib().rmrcm_default_params(ctypes.byref(p))
+    return p
+
+
+def rmrcm_setup(params: rmrcm_params, perm, bc_type):
+    kp, _k = _ptr(perm, np.float64)
+    tp, _t = _ptr(bc_type, np.int8)
+    ctx = ctypes.c_void_p()
+    st = lib().rmrcm_setup(ctypes.byref(params), kp, tp, ctypes.byref(ctx))
+    _check(st, "rmrcm_setup")
+    return ctx
+
+
+def rmrcm_refactor(ctx, perm):
+    kp, _k = _ptr(perm, np.float64)
+    _check(lib().rmrcm_refactor(ctx, kp), "rmrcm_refactor")
+
+
+def rmrcm_solve(ctx, source, bc_value, pressure, flux):
+    sp, _s = _ptr(source, np.float64)
+    bp, _b = _ptr(bc_value, np.float64)
+    pp, _p = _ptr(pressure, np.float64)
+    fp, _f = _ptr(flux, np.float64)
+    _check(lib().rmrcm_solve(ctx, sp, bp, pp, fp), "rmrcm_solve")
+
+
+def rmrcm_get_interface(ctx, U, P):
+    up, _u = _ptr(U, np.float64)
+    pp, _p = _ptr(P, np.float64)
+    _check(lib().rmrcm_get_interface(ctx, up, pp), "rmrcm_get_interface")
+
+
+def rmrcm_counts(ctx):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rmrcm_counts(ctx, ctypes.byref(a), ctypes.byref(b)), "rmrcm_counts")
+    return a.value, b.value
+
+
+def rmrcm_set_stream(ctx, stream_handle):
+    _check(lib().rmrcm_set_stream(ctx, ctypes.c_void_p(stream_handle)), "rmrcm_set_stream")
+
+
+def rmrcm_get_stats(ctx) -> dict:
+    need = lib().rmrcm_get_stats(ctx, None, 0)
+    if need < 0:
+        raise RMRCMError(need, "rmrcm_get_stats")
+    buf = ctypes.create_string_buffer(need)
+    lib().rmrcm_get_stats(ctx, buf, need)
+    return json.loads(buf.value.decode())
+
+
+def rmrcm_destroy(ctx):
+    lib().rmrcm_destroy(ctx)
+
+
+def rmrcm_strerror(status: int) -> str:
+    return lib().rmrcm_strerror(status).decode()
+
+
+class Solver:
+    """One setup (permeability + boundary-condition types), many solves."""
+
+    def __init__(self, nx, ny, K, bc_type, sub_nx, sub_ny, seg, alpha=1.0,
+                 lx=1.0, ly=1.0, precision=RMRCM_FP64, device=0, **extra):
+        p = rmrcm_default_params()
+        p.nx, p.ny, p.lx, p.ly = nx, ny, lx, ly
+        p.sub_nx, p.sub_ny, p.seg, p.alpha = sub_nx, sub_ny, seg, alpha
+        p.precision, p.device = precision, device
+        for k, v in extra.items():
+            setattr(p, k, v)
+        self.params = p
+        self.nx, self.ny = nx, ny
+        self.ctx = rmrcm_setup(p, K, bc_type)
+        self.nseg, self.nlocal = rmrcm_counts(self.ctx)
+
+    @classmethod
+    def from_problem(cls, prob, **kw):
+        return cls(prob.nx, prob.ny, prob.K, prob.bc_type, prob.sub_nx, prob.sub_ny,
+                   prob.seg, alpha=prob.alpha, lx=prob.lx, ly=prob.ly, **kw)
+
+    def refactor(self, K):
+        rmrcm_refactor(self.ctx, K)
+
+    def solve(self, q, bc_value, pressure=None, flux=None):
+        """Returns (pressure (ny, nx), flux (4, ny, nx)); NumPy unless
+        output tensors are given."""
+        if pressure is None:
+            pressure = np.zeros((self.ny, self.nx))
+        if flux is None:
+            flux = np.zeros((4, self.ny, self.nx))
+        rmrcm_solve(self.ctx, q, bc_value, pressure, flux)
+        return pressure, flux
+
+    def interface(self):
+        U = np.zeros(self.nseg)
+        P = np.zeros(self.nseg)
+        rmrcm_get_interface(self.ctx, U, P)
+        return U, P
+
+    def set_stream(self, handle):
+        rmrcm_set_stream(self.ctx, handle)
+
+    def stats(self):
+        return rmrcm_get_stats(self.ctx)
+
+    def close(self):
+        if self.ctx is not None:
+            rmrcm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

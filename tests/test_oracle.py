@@ -16,7 +16,7 @@ from helpers import make_problem
 from oracle.decomp import Decomposition
 from oracle.fine import fine_solve
 from oracle.local import local_solve
-from oracle.metrics import rel_l2, cell_balance, interface_residual
+from oracle.metrics import rel_l2, cell_balance, cell_backward_error, interface_residual
 from oracle.monolithic import monolithic_solve
 from oracle.mrcm import mrcm_solve
 from oracle.recursive import recursive_solve
@@ -245,6 +245,18 @@ def test_mrcm_conservation_and_interface_equations():
     assert cell_balance(r.F, P.q) < 1e-12
     r13, r14 = interface_residual(r.dec, r.F, r.U)
     assert r13 < 1e-12 and r14 < 1e-12
+
+
+def test_conservation_backward_error_high_contrast():
+    """At high contrast the balance residual relative to max|F| grows with
+    the contrast, but the per-cell backward error stays at round-off; a
+    wrong face law (here: one flux perturbed by 1e-9 of its size) is seen."""
+    P = make_problem(64, b=16, seg=4, log_var=9.0, lam=0.05)
+    r = mrcm_solve(P)
+    assert cell_backward_error(P, r.p, r.F) < 1e-13
+    F2 = r.F.copy()
+    F2[1, 10, 10] *= 1 + 1e-6
+    assert cell_backward_error(P, r.p, F2) > 1e-12
 
 
 def test_mrcm_superposition():
