@@ -245,6 +245,7 @@ void free_all(rmrcm_ctx* c) {
     f(c->Uout);
     f(c->Pout);
     f(c->flags);
+    f(c->gauge);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -362,9 +363,9 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
     c->any_dirichlet = any_dir;
     build_geo(c);
     build_levels(c);
-    if (!any_dir) {
+    if (!any_dir && c->D == 0) {
         delete c;
-        return RMRCM_ENOTSUP;   // zero-mean gauge of all-Neumann problems: not in this build
+        return RMRCM_ENOTSUP;   // one subdomain with no Dirichlet face: singular local system
     }
     auto fail = [&](int r) {
         free_all(c);
@@ -389,7 +390,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
         (r = dalloc(c, &c->q, ncell)) || (r = dalloc(c, &c->bcv, nbf)) ||
         (r = dalloc(c, &c->pout, ncell)) || (r = dalloc(c, &c->fout, 4 * ncell)) ||
         (r = dalloc(c, &c->Uout, g.nseg)) || (r = dalloc(c, &c->Pout, g.nseg)) ||
-        (r = dalloc(c, &c->flags, 4)))
+        (r = dalloc(c, &c->flags, 4)) || (r = dalloc(c, &c->gauge, 256)))
         return fail(r);
     if ((r = alloc_levels(c)) != RMRCM_OK) return fail(r);
     if (hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
@@ -417,6 +418,22 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
     const Geo& g = c->geo;
     const size_t ncell = (size_t)g.nx * g.ny;
     const size_t nbf = 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+    if (!c->any_dirichlet) {
+        // all faces Neumann: the data must be compatible (net source equals
+        // the prescribed net outflow)
+        std::vector<double> hq, hb(nbf);
+        if (source) {
+            hq.resize(ncell);
+            if (hipMemcpy(hq.data(), source, ncell * sizeof(double), hipMemcpyDefault) != hipSuccess)
+                return RMRCM_EDEVICE;
+        }
+        if (hipMemcpy(hb.data(), bc_value, nbf * sizeof(double), hipMemcpyDefault) != hipSuccess)
+            return RMRCM_EDEVICE;
+        double s = 0.0, sa = 0.0;
+        for (double v : hq) s += v, sa += std::fabs(v);
+        for (double v : hb) s -= v, sa += std::fabs(v);
+        if (!(std::fabs(s) <= 1e-12 * sa + 1e-300)) return RMRCM_EINVAL;
+    }
     HIP_TRY(hipEventRecord(c->ev[4], c->stream));
     if (source) {
         HIP_TRY(hipMemcpyAsync(c->q, source, ncell * sizeof(double), hipMemcpyDefault, c->stream));
@@ -432,6 +449,7 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
     for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
     HIP_TRY(hipEventRecord(c->ev[8], c->stream));
     HIP_TRY(rmrcm::launch_reconstruct(c));
+    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
     HIP_TRY(hipEventRecord(c->ev[9], c->stream));
     HIP_TRY(hipMemcpyAsync(pressure, c->pout, ncell * sizeof(double), hipMemcpyDefault, c->stream));
     HIP_TRY(hipMemcpyAsync(flux, c->fout, 4 * ncell * sizeof(double), hipMemcpyDefault, c->stream));

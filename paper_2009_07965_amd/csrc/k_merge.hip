@@ -41,6 +41,7 @@ struct MergeArgs {
     const double* beta;
     const double* seglen;
     int* flags;
+    int pin;                    // 1 at the root of an all-Neumann problem
 };
 
 // Element-wise copy t -> st(t, ld(t)) for t < n over the workgroup, in
@@ -102,6 +103,7 @@ __global__ __launch_bounds__(256) void k_merge_assemble(MergeArgs a) {
         if (r < g && c < g) v = T1[(size_t)g1[r] * a.cld + g1[c]] + wdiag;
         else if (r >= g && c >= g) v = T2[(size_t)g2[rr] * a.cld + g2[cc]] + wdiag;
         else v = -wdiag;
+        if (a.pin && r == a.xi - 1) v = c == a.xi - 1 ? 1.0 : 0.0;
         M[t] = v;
     }
 }
@@ -196,6 +198,7 @@ __global__ __launch_bounds__(256) void k_merge_rhs(MergeArgs a, int col0, int nc
             if (k == 0) v = r < g ? T1[(size_t)g1[rr] * a.cld + o] : 0.0;
             else v = r >= g ? T2[(size_t)g2[rr] * a.cld + o] : 0.0;
         }
+        if (a.pin && r == a.xi - 1) v = 0.0;
         X[(size_t)r * a.ld + col] = -v;
     }
 }
@@ -334,6 +337,11 @@ __global__ __launch_bounds__(256) void k_merge_small(MergeArgs a, int mode) {
                        M[r * L + c] = v + ((r % g) == (c % g) ? (((r < g) == (c < g)) ? f[r % g] : -f[r % g]) : 0.0);
                    });
         __syncthreads();
+        // All-Neumann problem: the top system is singular (adding a constant
+        // to every Robin datum changes no flux); fix the last unknown to 0.
+        if (a.pin)
+            for (int c = tid; c < n; c += nt) M[(n - 1) * L + c] = c == n - 1 ? 1.0 : 0.0;
+        __syncthreads();
         for (int k = 0; k < n; ++k) {
             if (wave == 0) {
                 const int r = k + lane;
@@ -407,6 +415,7 @@ __global__ __launch_bounds__(256) void k_merge_small(MergeArgs a, int mode) {
                        const int r = t / kSCW, cc = t % kSCW, col = c0 + cc;
                        const int rr = r % g;
                        if (cc >= nc) return 0.0;
+                       if (a.pin && r == n - 1) return 0.0;
                        if (col == a.nslot)
                            return r < g ? T1[(size_t)g1[rr] * a.cld + a.cld - 1]
                                         : T2[(size_t)g2[rr] * a.cld + a.cld - 1];
@@ -914,6 +923,7 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     a.beta = c->beta;
     a.seglen = c->seglen;
     a.flags = c->flags;
+    a.pin = (d == 0 && !c->any_dirichlet) ? 1 : 0;
     return a;
 }
 

@@ -99,6 +99,56 @@ __global__ void k_interface_values(int nseg, const double* __restrict__ glo,
     U[e] = (ghi[e] - glo[e]) / (2.0 * beta[e]);
 }
 
+// Zero-mean gauge of all-Neumann problems: per-block partial sums of the
+// pressure, then every block re-adds the partials in the same order (the
+// result does not depend on scheduling) and subtracts the mean.
+constexpr int kGB = 256;      // blocks of the gauge reduction
+
+__global__ __launch_bounds__(256) void k_pressure_partial(const double* __restrict__ p, size_t n,
+                                                          double* __restrict__ part) {
+    __shared__ double s[256];
+    double acc = 0.0;
+    const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const size_t b0 = blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+    for (size_t t = b0 + threadIdx.x; t < b1; t += blockDim.x) acc += p[t];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_pressure_shift(double* __restrict__ p, size_t n,
+                                                        const double* __restrict__ part, int nb,
+                                                        double* __restrict__ glo,
+                                                        double* __restrict__ ghi, int nseg) {
+    __shared__ double mean;
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[b];
+        mean = s / (double)n;
+    }
+    __syncthreads();
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t t = t0; t < n; t += stride) p[t] -= mean;
+    // the same constant shifts every Robin datum (fluxes are unchanged)
+    for (size_t t = t0; t < (size_t)nseg; t += stride) {
+        glo[t] -= mean;
+        ghi[t] -= mean;
+    }
+}
+
+hipError_t launch_gauge(rmrcm_ctx* c) {
+    const size_t n = (size_t)c->geo.nx * c->geo.ny;
+    hipLaunchKernelGGL(k_pressure_partial, dim3(kGB), dim3(256), 0, c->stream, c->pout, n, c->gauge);
+    hipLaunchKernelGGL(k_pressure_shift, dim3(1024), dim3(256), 0, c->stream, c->pout, n, c->gauge, kGB,
+                       c->glo, c->ghi, c->geo.nseg);
+    return hipGetLastError();
+}
+
 template <int BX>
 static hipError_t recon_bx(rmrcm_ctx* c) {
     const Level& L = c->levels[c->D];

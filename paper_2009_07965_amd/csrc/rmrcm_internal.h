@@ -86,6 +86,7 @@ struct rmrcm_ctx {
     double* Uout = nullptr;
     double* Pout = nullptr;
     int* flags = nullptr;                    // [4] device error flags
+    double* gauge = nullptr;                 // partial sums of the zero-mean gauge
     std::vector<rmrcm::Level> levels;        // index = depth
     size_t device_bytes = 0;
     // timing
@@ -107,6 +108,7 @@ hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
 hipError_t launch_interface_values(rmrcm_ctx* c);
+hipError_t launch_gauge(rmrcm_ctx* c);
 
 // Device error flag slots.
 enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2 };

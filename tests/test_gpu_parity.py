@@ -74,6 +74,10 @@ CASES = {
     "two_subdomains": lambda: make_problem(64, ny=32, b=32, seg=8),
     "two_subdomains_y": lambda: make_problem(32, ny=64, b=32, seg=16, source=True),
     "single_subdomain": lambda: make_problem(32, b=32, seg=8, source=True),
+    "all_neumann_fivespot_b8": lambda: make_problem(64, b=8, seg=2, bc="fivespot", log_var=2.0),
+    "all_neumann_fivespot_b32": lambda: make_problem(256, b=32, seg=8, bc="fivespot", log_var=3.0),
+    "all_neumann_fivespot_big_root": lambda: make_problem(256, b=8, seg=2, bc="fivespot",
+                                                          log_var=1.0, lam=0.1),
 }
 
 
