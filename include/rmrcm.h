@@ -64,7 +64,10 @@ enum {
 };
 
 /* Precision modes of the local solves.  Interface merges always run in
- * FP64. */
+ * FP64.  RMRCM_MIXED: local factorisations and sweeps in FP32, accuracy
+ * recovered by iterative refinement with FP64 residuals (the basis and the
+ * particular solutions are stored in FP64); subdomains whose refinement
+ * does not reach ir_tol are factored again in FP64. */
 enum { RMRCM_FP64 = 0, RMRCM_MIXED = 1, RMRCM_MIXED_LEARNED = 2 };
 
 enum { RMRCM_BC_NEUMANN = 0, RMRCM_BC_DIRICHLET = 1 };
@@ -78,8 +81,11 @@ typedef struct {
     int32_t seg;             /* segment length in cells; divides sub_nx and sub_ny */
     double alpha;            /* Robin alpha > 0 */
     int32_t precision;       /* RMRCM_FP64 | RMRCM_MIXED | RMRCM_MIXED_LEARNED */
-    double ir_tol;           /* mixed: refinement stop (relative residual), default 1e-14 */
-    int32_t ir_max_iter;     /* mixed: refinement sweeps before FP64 fallback, default 8 */
+    double ir_tol;           /* mixed: refinement stops when max over subdomains and
+                                columns of |b - A x|_inf / |b|_inf <= ir_tol; default 1e-11 */
+    int32_t ir_max_iter;     /* mixed: refinement passes before the subdomains still above
+                                ir_tol are redone in FP64 (setup) or ENOTCONV (solve);
+                                default 6 */
     double gate_tol;         /* learned: residual gate tau */
     const char* cnn_weights; /* learned: weight file or NULL */
     int32_t device;          /* HIP device ordinal */

@@ -81,7 +81,8 @@ int validate(const rmrcm_params* p) {
     if (p->precision < RMRCM_FP64 || p->precision > RMRCM_MIXED_LEARNED) return RMRCM_EINVAL;
     if (p->sub_nx != 4 && p->sub_nx != 8 && p->sub_nx != 16 && p->sub_nx != 32) return RMRCM_ENOTSUP;
     if (p->sub_ny > 64) return RMRCM_ENOTSUP;
-    if (p->precision != RMRCM_FP64) return RMRCM_ENOTSUP;
+    if (p->precision == RMRCM_MIXED_LEARNED) return RMRCM_ENOTSUP;
+    if (p->precision == RMRCM_MIXED && (!(p->ir_tol > 0) || p->ir_max_iter < 1)) return RMRCM_EINVAL;
     // the basis block of one subdomain row must fit the local kernel's LDS
     const int R = 2 * (p->sub_nx + p->sub_ny) / p->seg;
     const size_t lds = sizeof(double) * (size_t)(3 * p->sub_nx * p->sub_nx + 2 * p->sub_nx * R + 4 * p->sub_nx);
@@ -246,6 +247,11 @@ void free_all(rmrcm_ctx* c) {
     f(c->Pout);
     f(c->flags);
     f(c->gauge);
+    f(c->dscal);
+    f(c->P32);
+    f(c->Wsc);
+    f(c->resid);
+    f(c->fb);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -269,13 +275,66 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+bool mixed(const rmrcm_ctx* c) { return c->prm.precision != RMRCM_FP64; }
+
+// Refinement passes until the largest relative residual measured before a
+// correction is below ir_tol (then the corrected iterate is better still).
+// Returns the number of passes and the last measured residual.
+int refine_loop(rmrcm_ctx* c, int part, int* iters, double* last) {
+    *iters = 0;
+    *last = 0.0;
+    for (int it = 0; it < c->prm.ir_max_iter; ++it) {
+        HIP_TRY(rmrcm::launch_local_refine(c, part, 1));
+        HIP_TRY(rmrcm::launch_max_resid(c, c->dscal));
+        double m = 0.0;
+        HIP_TRY(hipMemcpyAsync(&m, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        *iters = it + 1;
+        *last = m;
+        if (m <= c->prm.ir_tol) return RMRCM_OK;
+    }
+    return RMRCM_ENOTCONV;
+}
+
+// Local phase of the mixed-precision mode: FP32 factorisation and basis,
+// FP64-residual refinement, FP64 redo of the subdomains that do not reach
+// the tolerance, traces.
+int mixed_local_setup(rmrcm_ctx* c) {
+    const int nsub = c->geo.mx * c->geo.my;
+    HIP_TRY(hipMemsetAsync(c->fb, 0, nsub * sizeof(int), c->stream));
+    HIP_TRY(rmrcm::launch_local_setup(c, true, nullptr, 0, 0));
+    int it = 0;
+    double last = 0.0;
+    const int st = refine_loop(c, 0, &it, &last);
+    c->ir_iters_setup = it;
+    c->ir_resid_setup = last;
+    c->n_fallback = 0;
+    if (st == RMRCM_ENOTCONV) {
+        HIP_TRY(rmrcm::launch_local_refine(c, 0, 0));   // measure only
+        HIP_TRY(rmrcm::launch_mark_fallback(c, c->prm.ir_tol));
+        int h[4];
+        HIP_TRY(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        c->n_fallback = h[rmrcm::FLAG_FALLBACK];
+        if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_setup(c, false, c->fb, 1, 1));
+    } else if (st != RMRCM_OK) {
+        return st;
+    }
+    HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 0));
+    return RMRCM_OK;
+}
+
 int run_setup(rmrcm_ctx* c) {
     HIP_TRY(hipEventRecord(c->ev[0], c->stream));
     HIP_TRY(hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
     HIP_TRY(rmrcm::launch_check_perm(c));
     HIP_TRY(rmrcm::launch_beta(c));
     HIP_TRY(hipEventRecord(c->ev[1], c->stream));
-    HIP_TRY(rmrcm::launch_local_setup(c));
+    if (mixed(c)) {
+        TRY(mixed_local_setup(c));
+    } else {
+        HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
+    }
     HIP_TRY(hipEventRecord(c->ev[2], c->stream));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d));
     HIP_TRY(hipEventRecord(c->ev[3], c->stream));
@@ -295,8 +354,8 @@ void rmrcm_default_params(rmrcm_params* p) {
     p->ly = 1.0;
     p->alpha = 1.0;
     p->precision = RMRCM_FP64;
-    p->ir_tol = 1e-14;
-    p->ir_max_iter = 8;
+    p->ir_tol = 1e-11;
+    p->ir_max_iter = 6;
     p->gate_tol = 1e-6;
     p->cnn_weights = nullptr;
     p->device = 0;
@@ -390,8 +449,15 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
         (r = dalloc(c, &c->q, ncell)) || (r = dalloc(c, &c->bcv, nbf)) ||
         (r = dalloc(c, &c->pout, ncell)) || (r = dalloc(c, &c->fout, 4 * ncell)) ||
         (r = dalloc(c, &c->Uout, g.nseg)) || (r = dalloc(c, &c->Pout, g.nseg)) ||
-        (r = dalloc(c, &c->flags, 4)) || (r = dalloc(c, &c->gauge, 256)))
+        (r = dalloc(c, &c->flags, 4)) || (r = dalloc(c, &c->gauge, 256)) ||
+        (r = dalloc(c, &c->dscal, 1)))
         return fail(r);
+    if (prm->precision != RMRCM_FP64) {
+        if ((r = dalloc(c, &c->P32, nsub * g.by * g.bx * g.bx)) ||
+            (r = dalloc(c, &c->Wsc, nsub * R * n)) || (r = dalloc(c, &c->resid, nsub)) ||
+            (r = dalloc(c, &c->fb, nsub)))
+            return fail(r);
+    }
     if ((r = alloc_levels(c)) != RMRCM_OK) return fail(r);
     if (hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream) != hipSuccess)
@@ -442,7 +508,19 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
     }
     HIP_TRY(hipMemcpyAsync(c->bcv, bc_value, nbf * sizeof(double), hipMemcpyDefault, c->stream));
     HIP_TRY(hipEventRecord(c->ev[5], c->stream));
-    HIP_TRY(rmrcm::launch_local_particular(c));
+    if (mixed(c)) {
+        HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 0, 0));
+        if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));
+        int it = 0;
+        double last = 0.0;
+        const int st = refine_loop(c, 1, &it, &last);
+        c->ir_iters_solve = it;
+        c->ir_resid_solve = last;
+        if (st != RMRCM_OK) return st;
+        HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
+    } else {
+        HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
+    }
     HIP_TRY(hipEventRecord(c->ev[6], c->stream));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
     HIP_TRY(hipEventRecord(c->ev[7], c->stream));
@@ -513,11 +591,14 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         "\"solve_ms\": {\"upload\": %.6f, \"local\": %.6f, \"merge\": %.6f, \"down\": %.6f, "
         "\"reconstruct\": %.6f, \"download\": %.6f, \"total\": %.6f}, "
         "\"levels\": %d, \"nseg\": %d, \"subdomains\": %d, \"local_solves\": %lld, "
-        "\"device_bytes\": %zu}",
+        "\"device_bytes\": %zu, \"precision\": %d, \"ir_iters_setup\": %d, "
+        "\"ir_iters_solve\": %d, \"ir_resid_setup\": %.3e, \"ir_resid_solve\": %.3e, "
+        "\"fp64_fallback_subdomains\": %d}",
         c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
         c->t_solve_ms[1], c->t_solve_ms[2], c->t_solve_ms[3], c->t_solve_ms[4], c->t_solve_ms[5],
         c->t_solve_ms[6], c->D, c->geo.nseg, c->geo.mx * c->geo.my, (long long)c->n_local_solves,
-        c->device_bytes);
+        c->device_bytes, c->prm.precision, c->ir_iters_setup, c->ir_iters_solve, c->ir_resid_setup,
+        c->ir_resid_solve, c->n_fallback);
     if (json && cap > 0) {
         std::strncpy(json, buf, cap - 1);
         json[cap - 1] = '\0';

@@ -202,35 +202,35 @@ __device__ inline void stencil_coeffs(const Geo& g, const double kv[5], const do
     *tyu = tu;
 }
 
-// Adds the basis right-hand side of block row j (unit Robin datum on one
-// slot per column) to F (BX x R).
-template <int BX>
-__device__ inline void add_basis_rhs(const Geo& g, const double* cf, const int* rs, int j, int R,
-                                     double* F) {
-    const int lane = threadIdx.x, BY = g.by;
-    if (lane == 0 && rs[j] >= 0) F[rs[j]] += cf[j];
-    if (lane == 1 && rs[BY + j] >= 0) F[(BX - 1) * R + rs[BY + j]] += cf[BY + j];
-    __syncthreads();
-    if ((j == 0 || j == BY - 1) && lane < BX) {
-        const int f = (j == 0 ? 2 * BY : 2 * BY + BX) + lane;
-        if (rs[f] >= 0) F[lane * R + rs[f]] += cf[f];   // one (row, column) per lane
-    }
-    __syncthreads();
-}
-
-// Value of a double held by lane l (l uniform, a compile-time constant at
-// every call) as a wave-uniform scalar.
-__device__ inline double readlane_d(double v, int l) {
+// Value of a register of lane l (l uniform, a compile-time constant at every
+// call) as a wave-uniform scalar.
+__device__ inline double readlane_s(double v, int l) {
     const unsigned long long u = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), l);
     const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
     return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
+__device__ inline float readlane_s(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ inline double inv_sqrt(double d) { return 1.0 / sqrt(d); }
+__device__ inline float inv_sqrt(float d) { return 1.0f / sqrtf(d); }
 
 constexpr int kWPre = 16;   // basis columns prefetched per lane in the backward sweep
 
+// LDS carve-up helper: returns p and advances it, 16-byte aligned.
+template <typename T>
+__device__ inline T* carve(char*& p, size_t count) {
+    T* r = (T*)p;
+    p += (count * sizeof(T) + 15) & ~(size_t)15;
+    return r;
+}
+__host__ inline size_t carve_bytes(size_t count, size_t elem) { return (count * elem + 15) & ~(size_t)15; }
+
 // ---------------------------------------------------------------- K1
-// Factorisation and basis solves: one wavefront per subdomain.
+// Factorisation and basis solves: one wavefront per subdomain, in the
+// compute type S (double: the FP64 path; float: the factorisation of the
+// mixed-precision path, refined afterwards in FP64).
 //
 // Lane l < 2 BX owns column l of the augmented block [S_j | I] of the
 // current block row in registers.  Cholesky step k: the pivot comes from
@@ -240,32 +240,37 @@ constexpr int kWPre = 16;   // basis columns prefetched per lane in the backward
 // L_j^{-1}; P_j = L_j^{-T} L_j^{-1} is formed column by column (lane c
 // computes column c, which is also row c), stored, and used for the sweep
 // w_j = P_j z_j and the trailing update S_{j+1} = A_{j+1} - D_j P_j D_j.
-// Global loads are issued one row ahead of their use.
-template <int BX>
+// Global loads are issued one row ahead of their use.  With a mask, only
+// subdomains whose mask entry equals `want` are processed.
+template <int BX, typename S>
 __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restrict__ K,
                                                     const int8_t* __restrict__ bct,
                                                     const double* __restrict__ beta,
                                                     const int* __restrict__ slotseg, int R,
-                                                    double* __restrict__ Pstore,
+                                                    S* __restrict__ Pstore,
                                                     double* __restrict__ Psi,
                                                     double* __restrict__ T, int ld,
-                                                    int* __restrict__ flags) {
-    extern __shared__ double sm[];
+                                                    int* __restrict__ flags,
+                                                    const int* __restrict__ mask, int want,
+                                                    int do_traces) {
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != want) return;
+    extern __shared__ __align__(16) char smem[];
     constexpr int LT = BX + 1;             // padded row of L^{-T}
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
-    double* LTs = sm;                       // BX x LT: row c = column c of L^{-1}
-    double* Z = LTs + BX * LT;              // BX x R: z_j, later D_j x_{j+1}
-    double* Wl = Z + BX * R;                // BX x R: w_j, later x_j
-    double* tys = Wl + BX * R;              // BY x BX: couplings D_j
-    double* cf = tys + BY * BX;             // NF face conductances
-    int* rs = (int*)(cf + NF);              // NF Robin slots
-    int* of = rs + NF;                      // NF outer faces
+    char* cur = smem;
+    S* LTs = carve<S>(cur, BX * LT);        // row c = column c of L^{-1}
+    S* Z = carve<S>(cur, BX * R);           // z_j, later D_j x_{j+1}
+    S* Wl = carve<S>(cur, BX * R);          // w_j, later x_j
+    S* tys = carve<S>(cur, BY * BX);        // couplings D_j
+    double* cf = carve<double>(cur, NF);    // face conductances
+    int* rs = carve<int>(cur, NF);          // Robin slots
+    int* of = carve<int>(cur, NF);          // outer faces
 
     const int lane = threadIdx.x;
-    const int sub = blockIdx.x;
     const int I = sub % g.mx, J = sub / g.mx;
     const int* ss = slotseg + (size_t)sub * R;
-    double* Ps = Pstore + (size_t)sub * BY * BX * BX;
+    S* Ps = Pstore + (size_t)sub * BY * BX * BX;
     double* Psub = Psi + (size_t)sub * R * n;
 
     const bool scol = lane < BX;                    // column of S
@@ -275,11 +280,11 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
     face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
     double kv[5], kn[5];
     load_kstencil<BX>(g, K, I, J, c, 0, kv);
-    for (int t = lane; t < BX * R; t += 64) Z[t] = 0.0;
+    for (int t = lane; t < BX * R; t += 64) Z[t] = S(0);
     __syncthreads();
 
-    double a[BX];
-    double p[BX];
+    S a[BX];
+    S p[BX];
     int sing = 0;
     double dg, txr, tyu;
     stencil_coeffs<BX>(g, kv, cf, c, 0, &dg, &txr, &tyu);
@@ -289,24 +294,30 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
         double v = 0.0;
         if (scol) v = (i == c) ? dg : (i == c + 1) ? -txr : (i + 1 == c) ? -txl : 0.0;
         else if (icol) v = (i == c) ? 1.0 : 0.0;
-        a[i] = v;
+        a[i] = S(v);
     }
-    add_basis_rhs<BX>(g, cf, rs, 0, R, Z);
+    if (lane == 0 && rs[0] >= 0) Z[rs[0]] += S(cf[0]);
+    if (lane == 1 && rs[BY] >= 0) Z[(BX - 1) * R + rs[BY]] += S(cf[BY]);
+    __syncthreads();
+    if (lane < BX && rs[2 * BY + lane] >= 0) Z[lane * R + rs[2 * BY + lane]] += S(cf[2 * BY + lane]);
+    if (BY == 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+        Z[lane * R + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
+    __syncthreads();
 
     for (int j = 0; j < BY; ++j) {
         if (j + 1 < BY) load_kstencil<BX>(g, K, I, J, c, j + 1, kn);
         // ---- Cholesky of S_j fused with the inversion of its factor
 #pragma unroll
         for (int k = 0; k < BX; ++k) {
-            double d = readlane_d(a[k], k);
-            if (!(d > 0.0)) {
+            S d = readlane_s(a[k], k);
+            if (!(d > S(0))) {
                 sing = 1;
-                d = 1.0;
+                d = S(1);
             }
-            const double r = 1.0 / sqrt(d);
+            const S r = inv_sqrt(d);
             a[k] *= r;
 #pragma unroll
-            for (int i = k + 1; i < BX; ++i) a[i] = fma(-readlane_d(a[k], i), a[k], a[i]);
+            for (int i = k + 1; i < BX; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
         }
         // ---- P_j = L^{-T} L^{-1}
         if (icol) {
@@ -316,10 +327,10 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
         __syncthreads();
         if (scol) {
 #pragma unroll
-            for (int r = 0; r < BX; ++r) p[r] = 0.0;
+            for (int r = 0; r < BX; ++r) p[r] = S(0);
 #pragma unroll
             for (int i = 0; i < BX; ++i) {
-                const double lci = LTs[c * LT + i];
+                const S lci = LTs[c * LT + i];
 #pragma unroll
                 for (int r = 0; r <= i; ++r) p[r] = fma(LTs[r * LT + i], lci, p[r]);
             }
@@ -327,42 +338,48 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
             for (int r = 0; r < BX; ++r) Ps[(size_t)j * BX * BX + r * BX + c] = p[r];
             // w_j = P_j z_j: lane c computes row c (P symmetric)
             for (int q = 0; q < R; ++q) {
-                double s = 0.0;
+                S s = S(0);
 #pragma unroll
                 for (int k = 0; k < BX; ++k) s = fma(p[k], Z[k * R + q], s);
                 Wl[c * R + q] = s;
-                Psub[(size_t)q * n + j * BX + c] = s;
+                Psub[(size_t)q * n + j * BX + c] = (double)s;
             }
-            tys[j * BX + c] = tyu;    // D_j
+            tys[j * BX + c] = S(tyu);    // D_j
         }
         __syncthreads();
         if (j + 1 < BY) {
-            const double dc = tyu;
+            const S dc = S(tyu);
             stencil_coeffs<BX>(g, kn, cf, c, j + 1, &dg, &txr, &tyu);
             txl = __shfl(txr, lane > 0 ? lane - 1 : 0, 64);
 #pragma unroll
             for (int i = 0; i < BX; ++i) {
-                double v = 0.0;
+                S v = S(0);
                 if (scol) {
                     v = -p[i] * (tys[j * BX + i] * dc);
-                    if (i == c) v += dg;
-                    else if (i == c + 1) v -= txr;
-                    else if (i + 1 == c) v -= txl;
+                    if (i == c) v += S(dg);
+                    else if (i == c + 1) v -= S(txr);
+                    else if (i + 1 == c) v -= S(txl);
                 } else if (icol) {
-                    v = (i == c) ? 1.0 : 0.0;
+                    v = (i == c) ? S(1) : S(0);
                 }
                 a[i] = v;
             }
             // z_{j+1} = F_{j+1} + D_j w_j
             for (int t = lane; t < BX * R; t += 64) Z[t] = tys[j * BX + t / R] * Wl[t];
             __syncthreads();
-            add_basis_rhs<BX>(g, cf, rs, j + 1, R, Z);
+            const int jn = j + 1;
+            if (lane == 0 && rs[jn] >= 0) Z[rs[jn]] += S(cf[jn]);
+            if (lane == 1 && rs[BY + jn] >= 0) Z[(BX - 1) * R + rs[BY + jn]] += S(cf[BY + jn]);
+            __syncthreads();
+            if (jn == BY - 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+                Z[lane * R + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
+            __syncthreads();
         }
     }
     // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j D_j x_{j+1}
     // Wl holds x_{j+1}; lane c loads row c of P_j (= column c) and its own
     // row of w_j one step ahead.
-    double pn[BX];
+    S pn[BX];
     double wn[kWPre];
     if (scol && BY > 1) {
 #pragma unroll
@@ -390,30 +407,87 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
 #pragma unroll
             for (int q = 0; q < kWPre; ++q) {
                 if (q < R) {
-                    double s = wc[q];
+                    S s = S(wc[q]);
 #pragma unroll
                     for (int k = 0; k < BX; ++k) s = fma(p[k], Z[k * R + q], s);
                     Wl[c * R + q] = s;
-                    Psub[(size_t)q * n + j * BX + c] = s;
+                    Psub[(size_t)q * n + j * BX + c] = (double)s;
                 }
             }
             for (int q = kWPre; q < R; ++q) {
-                double s = Psub[(size_t)q * n + j * BX + c];
+                S s = S(Psub[(size_t)q * n + j * BX + c]);
 #pragma unroll
                 for (int k = 0; k < BX; ++k) s = fma(p[k], Z[k * R + q], s);
                 Wl[c * R + q] = s;
-                Psub[(size_t)q * n + j * BX + c] = s;
+                Psub[(size_t)q * n + j * BX + c] = (double)s;
             }
         }
         __syncthreads();
     }
-    // ---- traces T[a][b] = sum_{f in slot a} c_f (x_b(cell f) - delta_ab)
+    if (do_traces) {
+        // traces T[a][b] = sum_{f in slot a} c_f (x_b(cell f) - delta_ab)
+        double* Tsub = T + (size_t)sub * R * ld;
+        for (int t = lane; t < R * R; t += 64) {
+            const int ar = t / R, b = t % R;
+            double s = 0.0;
+            if (ss[ar] >= 0 && ss[b] >= 0) {
+                const double* col = Psub + (size_t)b * n;
+                for (int u = 0; u < g.sg; ++u) {
+                    const int f = face_of_slot(g, BX, ar, u);
+                    int side, i, jj;
+                    face_cell(g, BX, f, &side, &i, &jj);
+                    s += cf[f] * (col[jj * BX + i] - (ar == b ? 1.0 : 0.0));
+                }
+            }
+            Tsub[(size_t)ar * ld + b] = s;
+        }
+    }
+    if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+}
+
+// Traces of the basis (columns 0..R-1) or of the particular solution
+// (column R) of the subdomains whose mask entry equals `want`, from the
+// stored cell values.
+template <int BX>
+__global__ __launch_bounds__(64) void k_local_traces(Geo g, const double* __restrict__ K,
+                                                     const int8_t* __restrict__ bct,
+                                                     const double* __restrict__ beta,
+                                                     const int* __restrict__ slotseg, int R,
+                                                     const double* __restrict__ X, int part,
+                                                     double* __restrict__ T, int ld,
+                                                     const int* __restrict__ mask, int want) {
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != want) return;
+    __shared__ double cf[2 * (32 + 64)];
+    __shared__ int rs[2 * (32 + 64)], of[2 * (32 + 64)];
+    const int lane = threadIdx.x;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int n = BX * g.by;
+    const int* ss = slotseg + (size_t)sub * R;
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    __syncthreads();
     double* Tsub = T + (size_t)sub * R * ld;
+    if (part) {
+        const double* col = X + (size_t)sub * n;
+        for (int ar = lane; ar < R; ar += 64) {
+            double s = 0.0;
+            if (ss[ar] >= 0)
+                for (int u = 0; u < g.sg; ++u) {
+                    const int f = face_of_slot(g, BX, ar, u);
+                    int side, i, jj;
+                    face_cell(g, BX, f, &side, &i, &jj);
+                    s += cf[f] * col[jj * BX + i];
+                }
+            Tsub[(size_t)ar * ld + ld - 1] = s;
+        }
+        return;
+    }
+    const double* Xs = X + (size_t)sub * R * n;
     for (int t = lane; t < R * R; t += 64) {
         const int ar = t / R, b = t % R;
         double s = 0.0;
         if (ss[ar] >= 0 && ss[b] >= 0) {
-            const double* col = Psub + (size_t)b * n;
+            const double* col = Xs + (size_t)b * n;
             for (int u = 0; u < g.sg; ++u) {
                 const int f = face_of_slot(g, BX, ar, u);
                 int side, i, jj;
@@ -423,14 +497,10 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
         }
         Tsub[(size_t)ar * ld + b] = s;
     }
-    if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
 }
 
-// ---------------------------------------------------------------- K1p
-// Particular solution (source and outer boundary data, zero Robin data)
-// with the stored P_j: one wavefront per subdomain, lane c holding row c of
-// P_j; writes pbar and the particular trace column.  A subdomain whose
-// right-hand side vanishes has pbar = 0 and is finished at once.
+// Right-hand side of the particular problem at cell (i, j): the source plus
+// the outer boundary data (Dirichlet |f|/rho g_D, Neumann -g_N).
 template <int BX>
 __device__ inline double part_rhs(const Geo& g, const double* cf, const int* of,
                                   const int8_t* __restrict__ bct, const double* __restrict__ bcv,
@@ -449,25 +519,224 @@ __device__ inline double part_rhs(const Geo& g, const double* cf, const int* of,
     return f;
 }
 
+// ---------------------------------------------------------------- refinement
+// One step of iterative refinement of the mixed-precision local solves:
+//     r = b - A x   (FP64, the five-point operator applied on the fly)
+//     x += A_32^{-1} r   (the two sweeps with the stored FP32 factor)
+// for the basis columns (part = 0, X = Psi) or the particular solution
+// (part = 1, X = pbar).  resid[sub] receives max_q |r_q|_inf / |b_q|_inf of
+// the residual before the correction.  apply = 0 only measures.
 template <int BX>
+__global__ __launch_bounds__(64) void k_local_refine(Geo g, const double* __restrict__ K,
+                                                     const int8_t* __restrict__ bct,
+                                                     const double* __restrict__ beta,
+                                                     const int* __restrict__ slotseg, int R,
+                                                     const float* __restrict__ P32,
+                                                     double* __restrict__ X, int part,
+                                                     const double* __restrict__ q,
+                                                     const double* __restrict__ bcv,
+                                                     float* __restrict__ Wsc,
+                                                     double* __restrict__ resid,
+                                                     const int* __restrict__ mask, int apply) {
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != 0) return;
+    extern __shared__ __align__(16) char smem[];
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
+    const int ncol = part ? 1 : R;
+    char* cur = smem;
+    double* x3 = carve<double>(cur, 3 * BX * ncol);   // rows j-1, j, j+1 of x (ring)
+    float* zf = carve<float>(cur, BX * ncol);         // z_j, later D_j dx_{j+1}
+    float* wf = carve<float>(cur, BX * ncol);         // w_j, later dx_j
+    float* tys = carve<float>(cur, BY * BX);          // D_j
+    double* bn = carve<double>(cur, ncol);            // |b_q|_inf
+    double* rn = carve<double>(cur, ncol);            // |r_q|_inf
+    double* cf = carve<double>(cur, NF);
+    int* rs = carve<int>(cur, NF);
+    int* of = carve<int>(cur, NF);
+    const int lane = threadIdx.x;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    const float* Ps = P32 + (size_t)sub * BY * BX * BX;
+    double* Xs = X + (size_t)sub * ncol * n;
+    float* Ws = Wsc + (size_t)sub * ncol * n;
+    const bool act = lane < BX;
+    const int c = act ? lane : 0;
+
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    for (int t = lane; t < ncol; t += 64) bn[t] = 0.0, rn[t] = 0.0;
+    // rows 0 and 1 of x into the ring
+    for (int t = lane; t < BX * ncol; t += 64) {
+        const int i = t % BX, qq = t / BX;
+        x3[(1 * BX + i) * ncol + qq] = Xs[(size_t)qq * n + i];
+        x3[(2 * BX + i) * ncol + qq] = BY > 1 ? Xs[(size_t)qq * n + BX + i] : 0.0;
+    }
+    __syncthreads();
+    float pr[BX], pnx[BX];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < BX; ++k) pnx[k] = Ps[(size_t)k * BX + c];
+    }
+    double kv[5];
+    for (int j = 0; j < BY; ++j) {
+#pragma unroll
+        for (int k = 0; k < BX; ++k) pr[k] = pnx[k];
+        if (act && j + 1 < BY) {
+#pragma unroll
+            for (int k = 0; k < BX; ++k) pnx[k] = Ps[(size_t)(j + 1) * BX * BX + k * BX + c];
+        }
+        load_kstencil<BX>(g, K, I, J, c, j, kv);
+        double dg, txr, tyu;
+        stencil_coeffs<BX>(g, kv, cf, c, j, &dg, &txr, &tyu);
+        const double txl = __shfl(txr, lane > 0 ? lane - 1 : 0, 64);
+        const double tyd = j > 0 ? tpy(g, kv[3], kv[0]) : 0.0;
+        const int rc = (j + 1) % 3, rp = (j + 2) % 3;  // ring slots of rows j and j+1 (j-1: j % 3)
+        if (act) tys[j * BX + c] = (float)tyu;
+        for (int qq = 0; qq < ncol; ++qq) {
+            double b = 0.0, r = 0.0;
+            if (act) {
+                // right-hand side of cell (c, j), column qq
+                if (part) {
+                    const double qv = q ? q[(size_t)(J * BY + j) * g.nx + I * BX + c] : 0.0;
+                    b = part_rhs<BX>(g, cf, of, bct, bcv, qv, c, j);
+                } else {
+                    if (c == 0 && rs[j] == qq) b += cf[j];
+                    if (c == BX - 1 && rs[BY + j] == qq) b += cf[BY + j];
+                    if (j == 0 && rs[2 * BY + c] == qq) b += cf[2 * BY + c];
+                    if (j == BY - 1 && rs[2 * BY + BX + c] == qq) b += cf[2 * BY + BX + c];
+                }
+                const double xc = x3[(rc * BX + c) * ncol + qq];
+                double ax = dg * xc;
+                if (c > 0) ax -= txl * x3[(rc * BX + c - 1) * ncol + qq];
+                if (c < BX - 1) ax -= txr * x3[(rc * BX + c + 1) * ncol + qq];
+                if (j > 0) ax -= tyd * x3[((j % 3) * BX + c) * ncol + qq];
+                if (j < BY - 1) ax -= tyu * x3[(rp * BX + c) * ncol + qq];
+                r = b - ax;
+                zf[c * ncol + qq] = (float)r + (j > 0 ? tys[(j - 1) * BX + c] * wf[c * ncol + qq] : 0.0f);
+            }
+            double ab = fabs(b), ar = fabs(r);
+            for (int off = 32; off > 0; off >>= 1) {
+                ab = fmax(ab, __shfl_xor(ab, off));
+                ar = fmax(ar, __shfl_xor(ar, off));
+            }
+            if (lane == 0) {
+                bn[qq] = fmax(bn[qq], ab);
+                rn[qq] = fmax(rn[qq], ar);
+            }
+        }
+        __syncthreads();
+        // w_j = P_j z_j
+        if (act)
+            for (int qq = 0; qq < ncol; ++qq) {
+                float s = 0.0f;
+#pragma unroll
+                for (int k = 0; k < BX; ++k) s = fmaf(pr[k], zf[k * ncol + qq], s);
+                Ws[(size_t)qq * n + j * BX + c] = s;
+                wf[c * ncol + qq] = s;
+            }
+        // shift the ring: load row j+2 of x into the slot of row j-1
+        if (j + 2 < BY)
+            for (int t = lane; t < BX * ncol; t += 64) {
+                const int i = t % BX, qq = t / BX;
+                x3[((j % 3) * BX + i) * ncol + qq] = Xs[(size_t)qq * n + (j + 2) * BX + i];
+            }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        double m = 0.0;
+        for (int qq = 0; qq < ncol; ++qq)
+            if (bn[qq] > 0.0) m = fmax(m, rn[qq] / bn[qq]);
+            else if (rn[qq] > 0.0) m = fmax(m, 1.0);
+        resid[sub] = m;
+    }
+    if (!apply) return;
+    // backward: dx_{BY-1} = w_{BY-1}; dx_j = w_j + P_j D_j dx_{j+1}; x_j += dx_j
+    if (act) {
+        for (int qq = 0; qq < ncol; ++qq)
+            Xs[(size_t)qq * n + (BY - 1) * BX + c] += (double)wf[c * ncol + qq];
+    }
+    if (act && BY > 1) {
+#pragma unroll
+        for (int k = 0; k < BX; ++k) pnx[k] = Ps[(size_t)(BY - 2) * BX * BX + k * BX + c];
+    }
+    for (int j = BY - 2; j >= 0; --j) {
+#pragma unroll
+        for (int k = 0; k < BX; ++k) pr[k] = pnx[k];
+        if (act && j > 0) {
+#pragma unroll
+            for (int k = 0; k < BX; ++k) pnx[k] = Ps[(size_t)(j - 1) * BX * BX + k * BX + c];
+        }
+        if (act)
+            for (int qq = 0; qq < ncol; ++qq) zf[c * ncol + qq] = tys[j * BX + c] * wf[c * ncol + qq];
+        __syncthreads();
+        if (act)
+            for (int qq = 0; qq < ncol; ++qq) {
+                float s = Ws[(size_t)qq * n + j * BX + c];
+#pragma unroll
+                for (int k = 0; k < BX; ++k) s = fmaf(pr[k], zf[k * ncol + qq], s);
+                wf[c * ncol + qq] = s;
+                Xs[(size_t)qq * n + j * BX + c] += (double)s;
+            }
+        __syncthreads();
+    }
+}
+
+// Subdomains whose refinement did not reach the tolerance are redone in
+// FP64: mask = 1 marks them; their number is added to flags[3].
+__global__ void k_mark_fallback(int nsub, const double* __restrict__ resid, double tol,
+                                int* __restrict__ fb, int* __restrict__ flags) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsub) return;
+    const int f = !(resid[s] <= tol);
+    fb[s] = f;
+    if (f) atomicAdd(&flags[FLAG_FALLBACK], 1);
+}
+
+// Largest residual over all subdomains that are not marked (in flags[..]
+// order: one block, fixed summation order).
+__global__ __launch_bounds__(256) void k_max_resid(int nsub, const double* __restrict__ resid,
+                                                   const int* __restrict__ mask,
+                                                   double* __restrict__ out) {
+    __shared__ double s[256];
+    double m = 0.0;
+    for (int t = threadIdx.x; t < nsub; t += 256)
+        if (!mask || mask[t] == 0) m = fmax(m, resid[t]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+// ---------------------------------------------------------------- K1p
+// Particular solution (source and outer boundary data, zero Robin data)
+// with the stored P_j: one wavefront per subdomain, lane c holding row c of
+// P_j; writes pbar and (do_traces) the particular trace column.  A
+// subdomain whose right-hand side vanishes has pbar = 0 and is finished at
+// once.
+template <int BX, typename S>
 __global__ __launch_bounds__(64) void k_local_particular(
     Geo g, const double* __restrict__ K, const int8_t* __restrict__ bct,
     const double* __restrict__ beta, const int* __restrict__ slotseg, int R,
     const double* __restrict__ q, const double* __restrict__ bcv,
-    const double* __restrict__ Pstore, double* __restrict__ pbar, double* __restrict__ T, int ld) {
-    extern __shared__ double sm[];
+    const S* __restrict__ Pstore, double* __restrict__ pbar, double* __restrict__ T, int ld,
+    const int* __restrict__ mask, int want, int do_traces) {
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != want) return;
+    extern __shared__ __align__(16) char smem[];
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
-    double* fs = sm;                  // n right-hand side
-    double* z = fs + n;               // BX
-    double* cf = z + BX;              // NF
-    int* rs = (int*)(cf + NF);
-    int* of = rs + NF;
+    char* cur = smem;
+    double* fs = carve<double>(cur, n);     // right-hand side, then w, then x
+    S* z = carve<S>(cur, BX);
+    double* cf = carve<double>(cur, NF);
+    int* rs = carve<int>(cur, NF);
+    int* of = carve<int>(cur, NF);
     __shared__ int nonzero;
     const int lane = threadIdx.x;
-    const int sub = blockIdx.x;
     const int I = sub % g.mx, J = sub / g.mx;
     const int* ss = slotseg + (size_t)sub * R;
-    const double* Ps = Pstore + (size_t)sub * BY * BX * BX;
+    const S* Ps = Pstore + (size_t)sub * BY * BX * BX;
     double* pb = pbar + (size_t)sub * n;
     double* Tsub = T + (size_t)sub * R * ld;
     const bool act = lane < BX;
@@ -488,15 +757,16 @@ __global__ __launch_bounds__(64) void k_local_particular(
     __syncthreads();
     if (!nonzero) {
         for (int t = lane; t < n; t += 64) pb[t] = 0.0;
-        for (int a = lane; a < R; a += 64) Tsub[(size_t)a * ld + ld - 1] = 0.0;
+        if (do_traces)
+            for (int a = lane; a < R; a += 64) Tsub[(size_t)a * ld + ld - 1] = 0.0;
         return;
     }
-    double p[BX], pn[BX];
+    S p[BX], pn[BX];
     if (act) {
 #pragma unroll
         for (int k = 0; k < BX; ++k) pn[k] = Ps[(size_t)k * BX + c];
     }
-    double w = 0.0, dprev = 0.0;
+    S w = S(0), dprev = S(0);
     double kv[5];
     for (int j = 0; j < BY; ++j) {
 #pragma unroll
@@ -506,16 +776,16 @@ __global__ __launch_bounds__(64) void k_local_particular(
             for (int k = 0; k < BX; ++k) pn[k] = Ps[(size_t)(j + 1) * BX * BX + k * BX + c];
         }
         load_kstencil<BX>(g, K, I, J, c, j, kv);
-        if (act) z[c] = fs[j * BX + c] + dprev * w;
+        if (act) z[c] = S(fs[j * BX + c]) + dprev * w;
         __syncthreads();
         if (act) {
-            double s = 0.0;
+            S s = S(0);
 #pragma unroll
             for (int k = 0; k < BX; ++k) s = fma(p[k], z[k], s);
             w = s;
-            fs[j * BX + c] = s;
-            dprev = j + 1 < BY ? tpy(g, kv[0], kv[4]) : 0.0;
-            pb[j * BX + c] = dprev;   // D_j staged in the output; overwritten at the end
+            fs[j * BX + c] = (double)s;
+            dprev = j + 1 < BY ? S(tpy(g, kv[0], kv[4])) : S(0);
+            pb[j * BX + c] = (double)dprev;   // D_j staged in the output; overwritten at the end
         }
         __syncthreads();
     }
@@ -531,60 +801,91 @@ __global__ __launch_bounds__(64) void k_local_particular(
 #pragma unroll
             for (int k = 0; k < BX; ++k) pn[k] = Ps[(size_t)(j - 1) * BX * BX + k * BX + c];
         }
-        if (act) z[c] = pb[j * BX + c] * w;
+        if (act) z[c] = S(pb[j * BX + c]) * w;
         __syncthreads();
         if (act) {
-            double s = fs[j * BX + c];
+            S s = S(fs[j * BX + c]);
 #pragma unroll
             for (int k = 0; k < BX; ++k) s = fma(p[k], z[k], s);
             w = s;
-            fs[j * BX + c] = s;
+            fs[j * BX + c] = (double)s;
         }
         __syncthreads();
     }
     for (int t = lane; t < n; t += 64) pb[t] = fs[t];
     __syncthreads();
-    for (int a = lane; a < R; a += 64) {
-        double s = 0.0;
-        if (ss[a] >= 0)
-            for (int u = 0; u < g.sg; ++u) {
-                const int f = face_of_slot(g, BX, a, u);
-                int side, i, jj;
-                face_cell(g, BX, f, &side, &i, &jj);
-                s += cf[f] * fs[jj * BX + i];
-            }
-        Tsub[(size_t)a * ld + ld - 1] = s;
-    }
+    if (do_traces)
+        for (int a = lane; a < R; a += 64) {
+            double s = 0.0;
+            if (ss[a] >= 0)
+                for (int u = 0; u < g.sg; ++u) {
+                    const int f = face_of_slot(g, BX, a, u);
+                    int side, i, jj;
+                    face_cell(g, BX, f, &side, &i, &jj);
+                    s += cf[f] * fs[jj * BX + i];
+                }
+            Tsub[(size_t)a * ld + ld - 1] = s;
+        }
 }
 
 // ---------------------------------------------------------------- launchers
-template <int BX>
-static hipError_t setup_bx(rmrcm_ctx* c) {
+template <int BX, typename S>
+static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do_traces) {
     const Level& L = c->levels[c->D];
     const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY);
-    const size_t lds = sizeof(double) * (size_t)(BX * (BX + 1) + 2 * BX * R + BY * BX + NF) +
-                       sizeof(int) * (size_t)(2 * NF);
-    hipError_t e = hipFuncSetAttribute((const void*)k_local_setup<BX>,
+    const size_t lds = carve_bytes(BX * (BX + 1), sizeof(S)) + 2 * carve_bytes(BX * R, sizeof(S)) +
+                       carve_bytes(BY * BX, sizeof(S)) + carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4);
+    hipError_t e = hipFuncSetAttribute((const void*)k_local_setup<BX, S>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int nsub = c->geo.mx * c->geo.my;
-    hipLaunchKernelGGL(k_local_setup<BX>, dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
-                       c->bct, c->beta, L.slotseg, R, c->Pstore, c->Psi, L.T, L.ld, c->flags);
+    hipLaunchKernelGGL((k_local_setup<BX, S>), dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
+                       c->bct, c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask, want,
+                       do_traces);
+    return hipGetLastError();
+}
+
+template <int BX, typename S>
+static hipError_t part_bx(rmrcm_ctx* c, const S* P, const int* mask, int want, int do_traces) {
+    const Level& L = c->levels[c->D];
+    const int BY = c->geo.by, NF = 2 * (BX + BY);
+    const size_t lds = carve_bytes(BX * BY, 8) + carve_bytes(BX, sizeof(S)) + carve_bytes(NF, 8) +
+                       2 * carve_bytes(NF, 4);
+    hipError_t e = hipFuncSetAttribute((const void*)k_local_particular<BX, S>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int nsub = c->geo.mx * c->geo.my;
+    hipLaunchKernelGGL((k_local_particular<BX, S>), dim3(nsub), dim3(64), lds, c->stream, c->geo,
+                       c->K, c->bct, c->beta, L.slotseg, L.nslot, c->q, c->bcv, P, c->pbar, L.T,
+                       L.ld, mask, want, do_traces);
     return hipGetLastError();
 }
 
 template <int BX>
-static hipError_t part_bx(rmrcm_ctx* c) {
+static hipError_t refine_bx(rmrcm_ctx* c, int part, int apply) {
     const Level& L = c->levels[c->D];
-    const int BY = c->geo.by, NF = 2 * (BX + BY);
-    const size_t lds = sizeof(double) * (size_t)(BX * BY + BX + NF) + sizeof(int) * (size_t)(2 * NF);
-    hipError_t e = hipFuncSetAttribute((const void*)k_local_particular<BX>,
+    const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY);
+    const int ncol = part ? 1 : R;
+    const size_t lds = carve_bytes(3 * BX * ncol, 8) + 2 * carve_bytes(BX * ncol, 4) +
+                       carve_bytes(BY * BX, 4) + 2 * carve_bytes(ncol, 8) + carve_bytes(NF, 8) +
+                       2 * carve_bytes(NF, 4);
+    hipError_t e = hipFuncSetAttribute((const void*)k_local_refine<BX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const int nsub = c->geo.mx * c->geo.my;
-    hipLaunchKernelGGL(k_local_particular<BX>, dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
-                       c->bct, c->beta, L.slotseg, L.nslot, c->q, c->bcv, c->Pstore, c->pbar,
-                       L.T, L.ld);
+    hipLaunchKernelGGL(k_local_refine<BX>, dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
+                       c->bct, c->beta, L.slotseg, R, c->P32, part ? c->pbar : c->Psi, part, c->q,
+                       c->bcv, c->Wsc, c->resid, c->fb, apply);
+    return hipGetLastError();
+}
+
+template <int BX>
+static hipError_t traces_bx(rmrcm_ctx* c, int part, const int* mask, int want) {
+    const Level& L = c->levels[c->D];
+    const int nsub = c->geo.mx * c->geo.my;
+    hipLaunchKernelGGL(k_local_traces<BX>, dim3(nsub), dim3(64), 0, c->stream, c->geo, c->K, c->bct,
+                       c->beta, L.slotseg, L.nslot, part ? c->pbar : c->Psi, part, L.T, L.ld, mask,
+                       want);
     return hipGetLastError();
 }
 
@@ -601,24 +902,63 @@ hipError_t launch_check_perm(rmrcm_ctx* c) {
     return hipGetLastError();
 }
 
-hipError_t launch_local_setup(rmrcm_ctx* c) {
-    switch (c->geo.bx) {
-        case 4: return setup_bx<4>(c);
-        case 8: return setup_bx<8>(c);
-        case 16: return setup_bx<16>(c);
-        case 32: return setup_bx<32>(c);
-    }
+#define RMRCM_BX_SWITCH(call4, call8, call16, call32) \
+    switch (c->geo.bx) {                              \
+        case 4: return call4;                         \
+        case 8: return call8;                         \
+        case 16: return call16;                       \
+        case 32: return call32;                       \
+    }                                                 \
     return hipErrorInvalidValue;
+
+hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces) {
+    if (fp32) {
+        RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces)),
+                        (setup_bx<8, float>(c, c->P32, mask, want, do_traces)),
+                        (setup_bx<16, float>(c, c->P32, mask, want, do_traces)),
+                        (setup_bx<32, float>(c, c->P32, mask, want, do_traces)))
+    }
+    RMRCM_BX_SWITCH((setup_bx<4, double>(c, c->Pstore, mask, want, do_traces)),
+                    (setup_bx<8, double>(c, c->Pstore, mask, want, do_traces)),
+                    (setup_bx<16, double>(c, c->Pstore, mask, want, do_traces)),
+                    (setup_bx<32, double>(c, c->Pstore, mask, want, do_traces)))
 }
 
-hipError_t launch_local_particular(rmrcm_ctx* c) {
-    switch (c->geo.bx) {
-        case 4: return part_bx<4>(c);
-        case 8: return part_bx<8>(c);
-        case 16: return part_bx<16>(c);
-        case 32: return part_bx<32>(c);
+hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,
+                                   int do_traces) {
+    if (fp32) {
+        RMRCM_BX_SWITCH((part_bx<4, float>(c, c->P32, mask, want, do_traces)),
+                        (part_bx<8, float>(c, c->P32, mask, want, do_traces)),
+                        (part_bx<16, float>(c, c->P32, mask, want, do_traces)),
+                        (part_bx<32, float>(c, c->P32, mask, want, do_traces)))
     }
-    return hipErrorInvalidValue;
+    RMRCM_BX_SWITCH((part_bx<4, double>(c, c->Pstore, mask, want, do_traces)),
+                    (part_bx<8, double>(c, c->Pstore, mask, want, do_traces)),
+                    (part_bx<16, double>(c, c->Pstore, mask, want, do_traces)),
+                    (part_bx<32, double>(c, c->Pstore, mask, want, do_traces)))
+}
+
+hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply) {
+    RMRCM_BX_SWITCH((refine_bx<4>(c, part, apply)), (refine_bx<8>(c, part, apply)),
+                    (refine_bx<16>(c, part, apply)), (refine_bx<32>(c, part, apply)))
+}
+
+hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want) {
+    RMRCM_BX_SWITCH((traces_bx<4>(c, part, mask, want)), (traces_bx<8>(c, part, mask, want)),
+                    (traces_bx<16>(c, part, mask, want)), (traces_bx<32>(c, part, mask, want)))
+}
+
+hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol) {
+    const int nsub = c->geo.mx * c->geo.my;
+    hipLaunchKernelGGL(k_mark_fallback, dim3((nsub + 255) / 256), dim3(256), 0, c->stream, nsub,
+                       c->resid, tol, c->fb, c->flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_resid(rmrcm_ctx* c, double* out) {
+    const int nsub = c->geo.mx * c->geo.my;
+    hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(256), 0, c->stream, nsub, c->resid, c->fb, out);
+    return hipGetLastError();
 }
 
 }  // namespace rmrcm

@@ -75,6 +75,11 @@ struct rmrcm_ctx {
     double* beta = nullptr;                  // [nseg]
     double* seglen = nullptr;                // [nseg]
     double* Pstore = nullptr;                // [nsub][by][bx][bx]  S_j^{-1} of every block row
+    float* P32 = nullptr;                    // mixed mode: the same in FP32
+    float* Wsc = nullptr;                    // mixed mode: sweep scratch [nsub][nslot][bx*by]
+    double* resid = nullptr;                 // mixed mode: relative residual per subdomain
+    int* fb = nullptr;                       // mixed mode: 1 = subdomain redone in FP64
+    double* dscal = nullptr;                 // device scalar (max residual)
     double* Psi = nullptr;                   // [nsub][nslot][bx*by] basis pressures
     double* pbar = nullptr;                  // [nsub][bx*by] particular pressures
     double* glo = nullptr;                   // [nseg] Robin datum on the low side
@@ -94,6 +99,8 @@ struct rmrcm_ctx {
     double t_setup_ms[8] = {};
     double t_solve_ms[8] = {};
     int64_t n_local_solves = 0;
+    int ir_iters_setup = 0, ir_iters_solve = 0, n_fallback = 0;
+    double ir_resid_setup = 0.0, ir_resid_solve = 0.0;
 };
 
 namespace rmrcm {
@@ -101,8 +108,13 @@ namespace rmrcm {
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_beta(rmrcm_ctx* c);
 hipError_t launch_check_perm(rmrcm_ctx* c);
-hipError_t launch_local_setup(rmrcm_ctx* c);
-hipError_t launch_local_particular(rmrcm_ctx* c);
+hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces);
+hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,
+                                   int do_traces);
+hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply);
+hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want);
+hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol);
+hipError_t launch_max_resid(rmrcm_ctx* c, double* out);
 hipError_t launch_merge_setup(rmrcm_ctx* c, int depth);
 hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
@@ -111,6 +123,6 @@ hipError_t launch_interface_values(rmrcm_ctx* c);
 hipError_t launch_gauge(rmrcm_ctx* c);
 
 // Device error flag slots.
-enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2 };
+enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2, FLAG_FALLBACK = 3 };
 
 }  // namespace rmrcm
