@@ -18,9 +18,10 @@
 // solution as combinations of the children's (eq. new_bfs, eq. particular),
 // and the parent trace follows:
 //     T_p[o, s] = T_k[o, s] (if s belongs to child k) + T_k[o, gamma] y_k[:, s].
-// M is factored once (LU with partial pivoting) and kept with X for the
-// downward pass (the Remark of Section 3.2: coefficients are tracked back to
-// the finest level instead of storing coarse basis functions).
+// M is factored once and kept with X for the downward pass (the Remark of
+// Section 3.2: coefficients are tracked back to the finest level instead of
+// storing coarse basis functions).  Merges with g <= 128 use the pivot-free
+// quasi-definite form below; longer interfaces an LU with partial pivoting.
 
 #include "rmrcm_internal.h"
 
@@ -285,564 +286,398 @@ __global__ __launch_bounds__(256) void k_merge_trace(MergeArgs a, int col0, int 
 }
 
 // ---------------------------------------------------------------------------
-// Small merges (xi <= 64): one workgroup per merge does everything in LDS.
-// Setup mode: assemble M, invert it by Gauss-Jordan elimination with
-// partial pivoting (row interchanges, undone as column interchanges at the
-// end), store M^{-1}; then for chunks of parent columns: right-hand sides,
-// X = -M^{-1} R as a product, coefficients out, parent trace columns.
-// Particular mode: reload M^{-1} and process the particular column only.
-constexpr int kSX = 64;
-constexpr int kSCW = 64;
-constexpr int kTR = 64;   // parent trace rows per block
+// Merges with g <= 128: pivot-free elimination in sum/difference variables.
+//
+// With s = (y1 + y2) / 2 and d = (y2 - y1) / 2 (the interface pressure and
+// beta times the interface flux density of each gamma segment), the system
+//     (T1gg + W) y1 - W y2 = r1,   -W y1 + (T2gg + W) y2 = r2
+// becomes
+//     [ N  B ] [s]   [r1 + r2]      N = T1gg + T2gg
+//     [ B  D ] [d] = [r2 - r1],     B = T2gg - T1gg,   D = T1gg + T2gg + 4W.
+// Every trace matrix is the Robin-to-flux map of a passive TPFA network with
+// a series resistance beta on its Robin faces, so -diag(|f|/(rho+beta))
+// summed per segment <= T <= 0, hence T + 2W > 0 on gamma: D is symmetric
+// positive definite and S = N - B D^{-1} B negative definite (singular only
+// at the top of an all-Neumann problem, whose null vector is a constant s).
+// Such a quasi-definite system needs no pivoting.  Stored per merge, four
+// g x g blocks: D^{-1}, E = D^{-1} B, S^{-1}, B; then
+//     t = D^{-1}(r2 - r1),  s = S^{-1}(r1 + r2 - B t),  d = t - E s,
+//     y1 = s - d,  y2 = s + d.
+// The all-Neumann top pins s of the last gamma segment to zero.
+//
+// Factor: one workgroup per merge; each g x g matrix is held in registers as
+// a cyclic (GT/TL)^2 thread grid of TL x TL tiles (row i = ti + TG a, column
+// j = tj + TG b), inverted by Gauss-Jordan elimination with one barrier per
+// step, and multiplied by panels of PW columns staged in LDS.
 
-__global__ __launch_bounds__(256) void k_merge_small(MergeArgs a, int mode) {
-    __shared__ double M[kSX * (kSX + 1)];
-    __shared__ double Rc[kSX * kSCW];
-    __shared__ double Tg[kTR * kSX];
-    __shared__ double Dt[kTR * kSCW];
-    __shared__ int qk[kTR];
-    __shared__ double f[kSX];
-    __shared__ int piv[kSX];
-    __shared__ int sing;
-    const int n = a.xi, g = a.g, L = n + 1;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
-    const int node = blockIdx.x;
+template <int GT, int TL>
+struct QdGrid {
+    static constexpr int TG = GT / TL;
+    static constexpr int NT = TG * TG;
+    static constexpr int PW = 8;
+};
+
+// In-place Gauss-Jordan inversion without pivoting of the register-resident
+// g x g matrix v (zero outside g x g).  rowb/colb: [2][GT] LDS buffers.
+template <int GT, int TL>
+__device__ void gj_invert(int g, double (&v)[TL][TL], double* rowb, double* colb, int* bad) {
+    constexpr int TG = QdGrid<GT, TL>::TG;
+    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
+    for (int k = 0; k < g; ++k) {
+        double* rb = rowb + (k & 1) * GT;
+        double* cb = colb + (k & 1) * GT;
+        const int kt = k % TG, kl = k / TG;
+        if (ti == kt)
+#pragma unroll
+            for (int b = 0; b < TL; ++b) rb[tj + TG * b] = v[kl][b];
+        if (tj == kt)
+#pragma unroll
+            for (int a = 0; a < TL; ++a) cb[ti + TG * a] = v[a][kl];
+        __syncthreads();
+        const double piv = cb[k];
+        if (threadIdx.x == 0 && !(piv != 0.0 && isfinite(piv))) *bad = 1;
+        const double p = 1.0 / piv;
+        double r[TL], c[TL];
+#pragma unroll
+        for (int b = 0; b < TL; ++b) {
+            const int j = tj + TG * b;
+            r[b] = j == k ? 1.0 : rb[j];
+        }
+#pragma unroll
+        for (int a = 0; a < TL; ++a) {
+            const int i = ti + TG * a;
+            c[a] = i == k ? -p : cb[i] * p;
+        }
+#pragma unroll
+        for (int a = 0; a < TL; ++a)
+#pragma unroll
+            for (int b = 0; b < TL; ++b) {
+                const int i = ti + TG * a, j = tj + TG * b;
+                const double base = (i == k || j == k) ? 0.0 : v[a][b];
+                v[a][b] = base - c[a] * r[b];
+            }
+    }
+    __syncthreads();
+}
+
+// acc += A B over k < g, with PW-wide panels of A (columns) and B (rows)
+// published into LDS by pubA(k0, bufA[GT][PW]) and pubB(k0, bufB[PW][GT]).
+template <int GT, int TL, class PubA, class PubB>
+__device__ void summa(int g, double (&acc)[TL][TL], double* bufA, double* bufB, PubA pubA,
+                      PubB pubB) {
+    constexpr int TG = QdGrid<GT, TL>::TG, PW = QdGrid<GT, TL>::PW;
+    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
+    int pp = 0;
+    for (int k0 = 0; k0 < g; k0 += PW, pp ^= 1) {
+        double* A = bufA + pp * GT * PW;
+        double* B = bufB + pp * PW * GT;
+        pubA(k0, A);
+        pubB(k0, B);
+        __syncthreads();
+        const int kw = min(PW, g - k0);
+        for (int kk = 0; kk < kw; ++kk) {
+            double av[TL], bv[TL];
+#pragma unroll
+            for (int a = 0; a < TL; ++a) av[a] = A[(ti + TG * a) * PW + kk];
+#pragma unroll
+            for (int b = 0; b < TL; ++b) bv[b] = B[kk * GT + tj + TG * b];
+#pragma unroll
+            for (int a = 0; a < TL; ++a)
+#pragma unroll
+                for (int b = 0; b < TL; ++b) acc[a][b] += av[a] * bv[b];
+        }
+    }
+    __syncthreads();
+}
+
+template <int GT, int TL>
+__global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a) {
+    constexpr int TG = QdGrid<GT, TL>::TG, NT = QdGrid<GT, TL>::NT, PW = QdGrid<GT, TL>::PW;
+    __shared__ double rowb[2 * GT], colb[2 * GT];
+    __shared__ double bufA[2 * GT * PW], bufB[2 * PW * GT];
+    __shared__ double wv[GT];
+    __shared__ int gi1[GT], gi2[GT];
+    __shared__ int bad;
+    const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
+    const int node = blockIdx.x, g = a.g;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    const int* ss1 = a.css + (size_t)c1 * a.cnslot;
+    if (tid == 0) bad = 0;
+    for (int t = tid; t < g; t += NT) {
+        gi1[t] = a.gmap[t];
+        gi2[t] = a.gmap[g + t];
+        const int e = ss1[gi1[t]] >> 1;
+        wv[t] = a.seglen[e] / (2.0 * a.beta[e]);
+    }
+    __syncthreads();
+    const size_t gg = (size_t)g * g;
+    double* Dg = a.M + (size_t)node * 4 * gg;
+    double* Eg = Dg + gg;
+    double* Sg = Eg + gg;
+    double* Bg = Sg + gg;
+    double v[TL][TL];
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int i = ti + TG * p, j = tj + TG * q;
+            v[p][q] = 0.0;
+            if (i < g && j < g) {
+                const double t1 = T1[(size_t)gi1[i] * a.cld + gi1[j]];
+                const double t2 = T2[(size_t)gi2[i] * a.cld + gi2[j]];
+                v[p][q] = t1 + t2 + (i == j ? 4.0 * wv[i] : 0.0);
+                Bg[(size_t)i * g + j] = t2 - t1;
+            }
+        }
+    gj_invert<GT, TL>(g, v, rowb, colb, &bad);     // v = D^{-1}
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int i = ti + TG * p, j = tj + TG * q;
+            if (i < g && j < g) Dg[(size_t)i * g + j] = v[p][q];
+        }
+    // E = D^{-1} B: A panels (columns of D^{-1}) from registers, B panels
+    // (rows of B) gathered from the children's traces
+    double acc[TL][TL];
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) acc[p][q] = 0.0;
+    summa<GT, TL>(
+        g, acc, bufA, bufB,
+        [&](int k0, double* A) {
+#pragma unroll
+            for (int q = 0; q < TL; ++q) {
+                const int j = tj + TG * q;
+                if (j >= k0 && j < k0 + PW)
+#pragma unroll
+                    for (int p = 0; p < TL; ++p) A[(ti + TG * p) * PW + (j - k0)] = v[p][q];
+            }
+        },
+        [&](int k0, double* B) {
+            for (int t = tid; t < PW * GT; t += NT) {
+                const int kk = t / GT, j = t % GT, i = k0 + kk;
+                B[t] = (j < g && i < g) ? T2[(size_t)gi2[i] * a.cld + gi2[j]] -
+                                              T1[(size_t)gi1[i] * a.cld + gi1[j]]
+                                        : 0.0;
+            }
+        });
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int i = ti + TG * p, j = tj + TG * q;
+            if (i < g && j < g) Eg[(size_t)i * g + j] = acc[p][q];
+        }
+    // S = N - B E: A panels (columns of -B) gathered, B panels (rows of E)
+    // from registers
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int i = ti + TG * p, j = tj + TG * q;
+            v[p][q] = (i < g && j < g) ? T1[(size_t)gi1[i] * a.cld + gi1[j]] +
+                                             T2[(size_t)gi2[i] * a.cld + gi2[j]]
+                                       : 0.0;
+        }
+    summa<GT, TL>(
+        g, v, bufA, bufB,
+        [&](int k0, double* A) {
+            for (int t = tid; t < GT * PW; t += NT) {
+                const int i = t / PW, kk = t % PW, j = k0 + kk;
+                A[t] = (i < g && j < g) ? T1[(size_t)gi1[i] * a.cld + gi1[j]] -
+                                              T2[(size_t)gi2[i] * a.cld + gi2[j]]
+                                        : 0.0;
+            }
+        },
+        [&](int k0, double* B) {
+#pragma unroll
+            for (int p = 0; p < TL; ++p) {
+                const int i = ti + TG * p;
+                if (i >= k0 && i < k0 + PW)
+#pragma unroll
+                    for (int q = 0; q < TL; ++q) B[(i - k0) * GT + tj + TG * q] = acc[p][q];
+            }
+        });
+    if (a.pin) {
+#pragma unroll
+        for (int p = 0; p < TL; ++p)
+#pragma unroll
+            for (int q = 0; q < TL; ++q) {
+                const int i = ti + TG * p, j = tj + TG * q;
+                if (i == g - 1 || j == g - 1) v[p][q] = (i == j) ? 1.0 : 0.0;
+            }
+    }
+    gj_invert<GT, TL>(g, v, rowb, colb, &bad);     // v = S^{-1}
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int i = ti + TG * p, j = tj + TG * q;
+            if (i < g && j < g) Sg[(size_t)i * g + j] = (a.pin && i == g - 1 && j == g - 1) ? 0.0 : v[p][q];
+        }
+    if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
+}
+
+// Gamma coefficients of columns [col0, col0 + ncol): X = -M^{-1} R through
+// the stored blocks, kCT columns per workgroup.
+constexpr int kCT = 16;
+constexpr int kKP = 16;       // k-panel width of the block products
+
+// out[i][c] (= or -=) sum_k A[i][k] in[k][c] for i < g, c < kCT; A g x g
+// row-major in global memory, staged in kKP-wide panels; in/out in LDS.
+template <int GT, bool SUB>
+__device__ void qd_prod(int g, const double* __restrict__ A, const double* in, double* out,
+                        double* pan) {
+    constexpr int RPT = (GT + 15) / 16;      // rows per thread
+    const int tid = threadIdx.x, c = tid % kCT, r0 = tid / kCT;
+    double acc[RPT];
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) acc[u] = 0.0;
+    for (int k0 = 0; k0 < g; k0 += kKP) {
+        const int kw = min(kKP, g - k0);
+        for (int t = tid; t < g * kKP; t += 256) {
+            const int i = t / kKP, kk = t % kKP;
+            pan[t] = kk < kw ? A[(size_t)i * g + k0 + kk] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kw; ++kk) {
+            const double x = in[(k0 + kk) * kCT + c];
+#pragma unroll
+            for (int u = 0; u < RPT; ++u) {
+                const int i = r0 + 16 * u;
+                if (i < g) acc[u] += pan[i * kKP + kk] * x;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < RPT; ++u) {
+        const int i = r0 + 16 * u;
+        if (i < g) out[i * kCT + c] = SUB ? out[i * kCT + c] - acc[u] : acc[u];
+    }
+    __syncthreads();
+}
+
+template <int GT>
+__global__ __launch_bounds__(256) void k_qd_apply(MergeArgs a, int col0, int ncol) {
+    __shared__ double rs[GT * kCT], rd[GT * kCT], tt[GT * kCT];
+    __shared__ double pan[GT * kKP];
+    const int node = blockIdx.x, g = a.g;
+    const int cb = col0 + blockIdx.y * kCT;
+    const int nc = min(kCT, col0 + ncol - cb);
     int c1, c2;
     children(a, node, &c1, &c2);
     const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
     const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
     const int* g1 = a.gmap;
     const int* g2 = a.gmap + g;
-    double* Mg = a.M + (size_t)node * n * n;
-    double* Xg = a.X + (size_t)node * n * a.ld;
-    double* Tp = a.Tp ? a.Tp + (size_t)node * a.nslot * a.ld : nullptr;
-    if (tid == 0) sing = 0;
-
-    if (mode == 0) {
-        const int* ss1 = a.css + (size_t)c1 * a.cnslot;
-        for (int t = tid; t < g; t += nt) {
-            const int e = ss1[g1[t]] >> 1;
-            f[t] = a.seglen[e] / (2.0 * a.beta[e]);     // W, staged in f
-        }
-        __syncthreads();
-        batched<8>(n * n,
-                   [&](int t) {
-                       const int r = t / n, c = t % n;
-                       if (r < g && c < g) return T1[(size_t)g1[r] * a.cld + g1[c]];
-                       if (r >= g && c >= g) return T2[(size_t)g2[r - g] * a.cld + g2[c - g]];
-                       return 0.0;
-                   },
-                   [&](int t, double v) {
-                       const int r = t / n, c = t % n;
-                       M[r * L + c] = v + ((r % g) == (c % g) ? (((r < g) == (c < g)) ? f[r % g] : -f[r % g]) : 0.0);
-                   });
-        __syncthreads();
-        // All-Neumann problem: the top system is singular (adding a constant
-        // to every Robin datum changes no flux); fix the last unknown to 0.
-        if (a.pin)
-            for (int c = tid; c < n; c += nt) M[(n - 1) * L + c] = c == n - 1 ? 1.0 : 0.0;
-        __syncthreads();
-        for (int k = 0; k < n; ++k) {
-            if (wave == 0) {
-                const int r = k + lane;
-                double v = r < n ? fabs(M[r * L + k]) : -1.0;
-                int idx = r;
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ov = __shfl_xor(v, off);
-                    const int oi = __shfl_xor(idx, off);
-                    if (ov > v || (ov == v && oi < idx)) {
-                        v = ov;
-                        idx = oi;
-                    }
-                }
-                if (lane == 0) {
-                    piv[k] = idx;
-                    if (!(v > 0.0)) sing = 1;
-                }
-            }
-            __syncthreads();
-            const int p = piv[k];
-            const double pv = M[p * L + k];
-            const double inv = pv != 0.0 ? 1.0 / pv : 0.0;
-            __syncthreads();
-            // swap rows k, p and scale the pivot row (its diagonal becomes 1/pv)
-            for (int c = tid; c < n; c += nt) {
-                const double rk = M[k * L + c], rp = M[p * L + c];
-                M[p * L + c] = rk;
-                M[k * L + c] = (c == k ? 1.0 : rp) * inv;
-            }
-            __syncthreads();
-            for (int i = tid; i < n; i += nt) f[i] = i == k ? 0.0 : M[i * L + k];
-            __syncthreads();
-            // rank-one update, thread (ty, tx): rows ty + 4 u, column tx
-            if (lane < n) {
-                const double mk = M[k * L + lane];
-                for (int i = wave; i < n; i += 4) {
-                    if (i == k) continue;
-                    const double base = lane == k ? 0.0 : M[i * L + lane];
-                    M[i * L + lane] = base - f[i] * mk;
-                }
-            }
-            __syncthreads();
-        }
-        // undo the row interchanges as column interchanges, in reverse order
-        for (int k = n - 1; k >= 0; --k) {
-            const int p = piv[k];
-            if (p != k)
-                for (int i = tid; i < n; i += nt) {
-                    const double t0 = M[i * L + k];
-                    M[i * L + k] = M[i * L + p];
-                    M[i * L + p] = t0;
-                }
-            __syncthreads();
-        }
-        for (int t = tid; t < n * n; t += nt) Mg[t] = M[(t / n) * L + t % n];
-        if (tid == 0 && sing) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
-        if (!Tp) return;   // the root: no boundary columns
-    } else {
-        batched<16>(n * n, [&](int t) { return Mg[t]; },
-                    [&](int t, double v) { M[(t / n) * L + t % n] = v; });
-        __syncthreads();
-    }
-
-    const int col_begin = mode == 0 ? 0 : a.nslot;
-    const int col_end = mode == 0 ? a.nslot : a.nslot + 1;
-    for (int c0 = col_begin; c0 < col_end; c0 += kSCW) {
-        const int nc = min(kSCW, col_end - c0);
-        // right-hand sides R (not negated)
-        batched<8>(n * kSCW,
-                   [&](int t) {
-                       const int r = t / kSCW, cc = t % kSCW, col = c0 + cc;
-                       const int rr = r % g;
-                       if (cc >= nc) return 0.0;
-                       if (a.pin && r == n - 1) return 0.0;
-                       if (col == a.nslot)
-                           return r < g ? T1[(size_t)g1[rr] * a.cld + a.cld - 1]
-                                        : T2[(size_t)g2[rr] * a.cld + a.cld - 1];
-                       const int pm = a.pmap[col];
-                       const int k = pm >> 24, o = pm & 0xffffff;
-                       if (k == 0) return r < g ? T1[(size_t)g1[rr] * a.cld + o] : 0.0;
-                       return r >= g ? T2[(size_t)g2[rr] * a.cld + o] : 0.0;
-                   },
-                   [&](int t, double v) { Rc[t] = v; });
-        __syncthreads();
-        // X = -M^{-1} R, kept in registers until every thread has read Rc
-        constexpr int kIt = kSX * kSCW / 256;
-        double xv[kIt];
-        // thread (wave, lane): rows wave + 4 u, column lane
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int r = wave + 4 * it;
-            double s = 0.0;
-            if (r < n && lane < nc)
-                for (int k = 0; k < n; ++k) s += M[r * L + k] * Rc[k * kSCW + lane];
-            xv[it] = -s;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int r = wave + 4 * it;
-            if (r < n && lane < nc) {
-                Rc[r * kSCW + lane] = xv[it];
-                Xg[(size_t)r * a.ld + c0 + lane] = xv[it];
-            }
-        }
-        __syncthreads();
-        if (Tp) {
-            // parent trace rows in blocks of kTR: gamma columns of the owning
-            // child's trace row staged in LDS, then a product with X
-            for (int o0 = 0; o0 < a.nslot; o0 += kTR) {
-                const int nr = min(kTR, a.nslot - o0);
-                batched<8>(nr * g,
-                           [&](int t) {
-                               const int q = t / g, i = t % g;
-                               const int pm = a.pmap[o0 + q];
-                               const int k = pm >> 24, oc = pm & 0xffffff;
-                               const double* Tk = (k == 0 ? T1 : T2) + (size_t)oc * a.cld;
-                               return Tk[(k == 0 ? g1 : g2)[i]];
-                           },
-                           [&](int t, double v) { Tg[(t / g) * kSX + t % g] = v; });
-                __syncthreads();
-                // direct terms: the owning child's own entry, staged in Dt
-                batched<8>(nr * kSCW,
-                           [&](int t) {
-                               const int q = t >> 6, cc = t & (kSCW - 1), col = c0 + cc;
-                               if (cc >= nc) return 0.0;
-                               const int pm = a.pmap[o0 + q];
-                               const int k = pm >> 24, oc = pm & 0xffffff;
-                               const double* Tk = (k == 0 ? T1 : T2) + (size_t)oc * a.cld;
-                               if (col == a.nslot) return Tk[a.cld - 1];
-                               const int pc = a.pmap[col];
-                               return (pc >> 24) == k ? Tk[pc & 0xffffff] : 0.0;
-                           },
-                           [&](int t, double v) { Dt[t] = v; });
-                for (int q = wave; q < nr; q += 4) qk[q] = a.pmap[o0 + q] >> 24;
-                __syncthreads();
-                for (int q = wave; q < nr; q += 4) {
-                    const int cc = lane, o = o0 + q, col = c0 + cc;
-                    if (cc >= nc) continue;
-                    const int k = qk[q];
-                    double v = Dt[q * kSCW + cc];
-                    const double* xk = Rc + (k * g) * kSCW + cc;
-                    const double* tg = Tg + q * kSX;
-                    for (int i = 0; i < g; ++i) v += tg[i] * xk[i * kSCW];
-                    Tp[(size_t)o * a.ld + col] = v;
-                }
-                __syncthreads();
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Large merges (64 < xi <= 256): blocked right-looking LU with partial
-// pivoting, one workgroup of 512 threads per merge, the matrix in global
-// memory (L2-resident).  Per 32-column panel: the panel is factored in LDS,
-// its row interchanges are applied to the other columns as one composed
-// permutation, the block row of U comes from a triangular solve in
-// registers and the trailing matrix is updated by a register-tiled product.
-constexpr int kNB = 32;
-constexpr int kBX = 256;   // largest xi of this path
-
-constexpr int kLUT = 512;   // threads of the blocked LU
-
-__global__ __launch_bounds__(kLUT) void k_merge_lu_blocked(MergeArgs a) {
-    extern __shared__ double sm[];
-    const int n = a.xi;
-    constexpr int PL = kNB + 1;
-    double* Pn = sm;                    // n x PL panel
-    double* Us = Pn + (size_t)n * PL;   // kNB x (n - kNB) block row of U
-    __shared__ double rv[16];
-    __shared__ int ri[16];
-    __shared__ int pl[kNB];
-    __shared__ int perm[kBX];
-    __shared__ int ptmp[kBX];
-    __shared__ int rowsrc[kBX];
-    __shared__ int moved[2 * kNB];
-    __shared__ int wcnt[kLUT / 64];
-    __shared__ int nmoved;
-    __shared__ int sing;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
-    const int node = blockIdx.x;
-    double* M = a.M + (size_t)node * n * n;
-    int* piv = a.piv + (size_t)node * n;
-    if (tid == 0) sing = 0;
-    for (int i = tid; i < n; i += nt) rowsrc[i] = i;
-    for (int kb0 = 0; kb0 < n; kb0 += kNB) {
-        const int nb = min(kNB, n - kb0), r = n - kb0;
-        __syncthreads();
-        batched<16>(r * kNB,
-                    [&](int t) {
-                        const int i = t >> 5, j = t & (kNB - 1);
-                        return j < nb ? M[(size_t)(kb0 + i) * n + kb0 + j] : 0.0;
-                    },
-                    [&](int t, double v) { Pn[(t >> 5) * PL + (t & (kNB - 1))] = v; });
-        __syncthreads();
-        for (int j = 0; j < nb; ++j) {
-            const int cand = r - j;
-            if (tid < ((cand + 63) & ~63)) {
-                double v = tid < cand ? fabs(Pn[(j + tid) * PL + j]) : -1.0;
-                int idx = j + tid;
-                for (int off = 32; off > 0; off >>= 1) {
-                    const double ov = __shfl_xor(v, off);
-                    const int oi = __shfl_xor(idx, off);
-                    if (ov > v || (ov == v && oi < idx)) {
-                        v = ov;
-                        idx = oi;
-                    }
-                }
-                if (lane == 0) {
-                    rv[wave] = v;
-                    ri[wave] = idx;
-                }
-            }
-            __syncthreads();
-            if (tid == 0) {
-                const int nw = (cand + 63) / 64;
-                double bv = rv[0];
-                int bi = ri[0];
-                for (int w = 1; w < nw; ++w)
-                    if (rv[w] > bv || (rv[w] == bv && ri[w] < bi)) {
-                        bv = rv[w];
-                        bi = ri[w];
-                    }
-                pl[j] = bi;
-                if (!(bv > 0.0)) sing = 1;
-            }
-            __syncthreads();
-            const int p = pl[j];
-            if (p != j && tid < nb) {
-                const double t0 = Pn[j * PL + tid];
-                Pn[j * PL + tid] = Pn[p * PL + tid];
-                Pn[p * PL + tid] = t0;
-            }
-            __syncthreads();
-            const double d = Pn[j * PL + j];
-            const double inv = d != 0.0 ? 1.0 / d : 0.0;
-            for (int i = j + 1 + tid; i < r; i += nt) Pn[i * PL + j] *= inv;
-            __syncthreads();
-            {
-                const int c = tid & (kNB - 1);
-                if (c > j && c < nb) {
-                    const double pjc = Pn[j * PL + c];
-                    for (int i = j + 1 + (tid >> 5); i < r; i += kLUT / kNB)
-                        Pn[i * PL + c] -= Pn[i * PL + j] * pjc;
-                }
-            }
-            __syncthreads();
-        }
-        for (int t = tid; t < r * nb; t += nt) {
-            const int i = t / nb, j = t % nb;
-            M[(size_t)(kb0 + i) * n + kb0 + j] = Pn[i * PL + j];
-        }
-        // The panel's interchanges compose to one permutation of rows
-        // kb0..n-1 that moves at most 2 nb rows; apply it to the columns
-        // outside the panel with independent loads, then stores.
-        for (int i = tid; i < r; i += nt) perm[i] = i;
-        if (tid == 0) nmoved = 0;
-        __syncthreads();
-        if (tid == 0)
-            for (int j = 0; j < nb; ++j) {
-                const int p = pl[j];
-                const int t0 = perm[j];
-                perm[j] = perm[p];
-                perm[p] = t0;
-            }
-        __syncthreads();
-        // moved rows, listed in increasing order (ballot per wave)
-        for (int i0 = 0; i0 < r; i0 += nt) {
-            const int i = i0 + tid;
-            const bool mv = i < r && perm[i] != i;
-            const unsigned long long bal = __ballot(mv);
-            const int before = __popcll(bal & ((1ull << lane) - 1ull));
-            if (lane == 0) wcnt[wave] = __popcll(bal);
-            __syncthreads();
-            int off = nmoved;
-            for (int w = 0; w < wave; ++w) off += wcnt[w];
-            if (mv) moved[off + before] = i;
-            __syncthreads();
-            if (tid == 0) {
-                int s = 0;
-                for (int w = 0; w < nt / 64; ++w) s += wcnt[w];
-                nmoved += s;
-            }
-            __syncthreads();
-        }
-        // row of the original matrix now held by each row
-        for (int i = tid; i < r; i += nt) ptmp[i] = rowsrc[kb0 + perm[i]];
-        __syncthreads();
-        for (int i = tid; i < r; i += nt) rowsrc[kb0 + i] = ptmp[i];
-        __syncthreads();
-        {
-            // at most 2 kNB moved rows x (kBX - kNB) columns
-            constexpr int kIt = 2 * kNB * (kBX - kNB) / kLUT;
-            const int nm = nmoved, ncol = n - nb;
-            double vals[kIt];
-#pragma unroll
-            for (int it = 0; it < kIt; ++it) {
-                const int t = tid + it * kLUT;
-                vals[it] = 0.0;
-                if (t < nm * ncol) {
-                    const int q = t / ncol, cc = t % ncol;
-                    const int c = cc < kb0 ? cc : cc + nb;
-                    vals[it] = M[(size_t)(kb0 + perm[moved[q]]) * n + c];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int it = 0; it < kIt; ++it) {
-                const int t = tid + it * kLUT;
-                if (t < nm * ncol) {
-                    const int q = t / ncol, cc = t % ncol;
-                    const int c = cc < kb0 ? cc : cc + nb;
-                    M[(size_t)(kb0 + moved[q]) * n + c] = vals[it];
-                }
-            }
-        }
-        __syncthreads();
-        const int C = n - kb0 - nb;
-        if (C <= 0) continue;
-        // block row of U: unit-lower solve with the panel's L11, in LDS
-        batched<16>(nb * C, [&](int t) { return M[(size_t)(kb0 + t / C) * n + kb0 + nb + t % C]; },
-                    [&](int t, double v) { Us[t] = v; });
-        __syncthreads();
-        // one column of U12 per thread (columns are independent: no barrier)
-        for (int cc = tid; cc < C; cc += nt)
-            for (int jj = 0; jj < nb - 1; ++jj) {
-                const double xj = Us[jj * C + cc];
-                for (int i = jj + 1; i < nb; ++i) Us[i * C + cc] -= Pn[i * PL + jj] * xj;
-            }
-        __syncthreads();
-        for (int jj = 0; jj < nb; ++jj)
-            for (int cc = tid; cc < C; cc += nt) M[(size_t)(kb0 + jj) * n + kb0 + nb + cc] = Us[jj * C + cc];
-        __syncthreads();
-        // trailing update: M[kb0+nb+i][kb0+nb+cc] -= L21 * U12, 8x4 tiles per thread
-        const int R = r - nb;
-        const int ty = tid >> 5, tx = tid & 31;   // 16 x 32 threads
-        for (int ib = 0; ib < R; ib += 128)
-            for (int jb = 0; jb < C; jb += 128) {
-                double acc[8][4];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-                for (int j = 0; j < nb; ++j) {
-                    double av[8], bv[4];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int row = ib + ty + 16 * u;
-                        av[u] = row < R ? Pn[(nb + row) * PL + j] : 0.0;
-                    }
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int col = jb + tx + 32 * v;
-                        bv[v] = col < C ? Us[j * C + col] : 0.0;
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] += av[u] * bv[v];
-                }
-                double old[8][4];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = ib + ty + 16 * u, col = jb + tx + 32 * v;
-                        old[u][v] = (row < R && col < C)
-                                        ? M[(size_t)(kb0 + nb + row) * n + kb0 + nb + col] : 0.0;
-                    }
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = ib + ty + 16 * u, col = jb + tx + 32 * v;
-                        if (row < R && col < C)
-                            M[(size_t)(kb0 + nb + row) * n + kb0 + nb + col] = old[u][v] - acc[u][v];
-                    }
-            }
-    }
-    __syncthreads();
-    // piv holds the full row permutation: row i of L U is row piv[i] of M
-    for (int i = tid; i < n; i += nt) piv[i] = rowsrc[i];
-    if (tid == 0 && sing) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
-}
-
-// Column solves with the blocked LU factors: X[:, cols] <- M^{-1} X[:, cols].
-// One workgroup per (merge, chunk of kTCW columns); 32-row blocks of L and U
-// staged in LDS; diagonal blocks solved in registers by one thread per
-// column, the rest as a block product.
-constexpr int kTCW = 16;
-
-constexpr int kTT = 1024;   // threads of the blocked column solve
-
-__global__ __launch_bounds__(kTT) void k_merge_trsm(MergeArgs a, int col0, int ncol) {
-    extern __shared__ double sm[];
-    const int n = a.xi;
-    double* xs = sm;                       // n x kTCW
-    double* Bk = xs + (size_t)n * kTCW;    // n x kNB block column of L or U
-    const int node = blockIdx.x;
-    const int cbase = col0 + blockIdx.y * kTCW;
-    const int nc = min(kTCW, col0 + ncol - cbase);
-    if (nc <= 0) return;
-    const double* M = a.M + (size_t)node * n * n;
-    double* X = a.X + (size_t)node * n * a.ld;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int* pv = a.piv + (size_t)node * n;   // full row permutation
-    batched<4>(n * kTCW,
+    batched<4>(g * kCT,
                [&](int t) {
-                   const int r = t / kTCW, c = t % kTCW;
-                   return c < nc ? X[(size_t)pv[r] * a.ld + cbase + c] : 0.0;
+                   const int i = t / kCT, cc = t % kCT, col = cb + cc;
+                   if (cc >= nc) return 0.0;
+                   if (col == a.nslot) return T1[(size_t)g1[i] * a.cld + a.cld - 1];
+                   const int pm = a.pmap[col];
+                   return (pm >> 24) == 0 ? T1[(size_t)g1[i] * a.cld + (pm & 0xffffff)] : 0.0;
                },
-               [&](int t, double v) { xs[t] = v; });
-    // forward, unit lower
-    for (int kb0 = 0; kb0 < n; kb0 += kNB) {
-        const int nb = min(kNB, n - kb0), rows = n - kb0;
-        __syncthreads();
-        {
-            // rows x nb <= kBX x kNB = 8 x kTT entries, all loads issued first
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = tid + u * kTT;
-                v[u] = t < rows * nb ? M[(size_t)(kb0 + t / nb) * n + kb0 + t % nb] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = tid + u * kTT;
-                if (t < rows * nb) Bk[(t / nb) * kNB + t % nb] = v[u];
-            }
-        }
-        __syncthreads();
-        if (tid < kTCW) {
-            double x[kNB];
-#pragma unroll
-            for (int j = 0; j < kNB; ++j) x[j] = j < nb ? xs[(kb0 + j) * kTCW + tid] : 0.0;
-#pragma unroll
-            for (int j = 0; j < kNB; ++j)
-#pragma unroll
-                for (int i = j + 1; i < kNB; ++i)
-                    if (i < nb) x[i] -= Bk[i * kNB + j] * x[j];
-#pragma unroll
-            for (int j = 0; j < kNB; ++j)
-                if (j < nb) xs[(kb0 + j) * kTCW + tid] = x[j];
-        }
-        __syncthreads();
-        for (int t = tid; t < (rows - nb) * kTCW; t += nt) {
-            const int i = nb + t / kTCW, c = t % kTCW;
-            double s = 0.0;
-            for (int j = 0; j < nb; ++j) s += Bk[i * kNB + j] * xs[(kb0 + j) * kTCW + c];
-            xs[(kb0 + i) * kTCW + c] -= s;
-        }
-    }
-    // backward, upper
-    const int last = ((n - 1) / kNB) * kNB;
-    for (int kb0 = last; kb0 >= 0; kb0 -= kNB) {
-        const int nb = min(kNB, n - kb0), rows = kb0 + nb;
-        __syncthreads();
-        {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = tid + u * kTT;
-                v[u] = t < rows * nb ? M[(size_t)(t / nb) * n + kb0 + t % nb] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = tid + u * kTT;
-                if (t < rows * nb) Bk[(t / nb) * kNB + t % nb] = v[u];
-            }
-        }
-        __syncthreads();
-        if (tid < kTCW) {
-            double x[kNB];
-#pragma unroll
-            for (int j = 0; j < kNB; ++j) x[j] = j < nb ? xs[(kb0 + j) * kTCW + tid] : 0.0;
-#pragma unroll
-            for (int j = kNB - 1; j >= 0; --j) {
-                if (j < nb) {
-                    x[j] /= Bk[(kb0 + j) * kNB + j];
-#pragma unroll
-                    for (int i = 0; i < j; ++i) x[i] -= Bk[(kb0 + i) * kNB + j] * x[j];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kNB; ++j)
-                if (j < nb) xs[(kb0 + j) * kTCW + tid] = x[j];
-        }
-        __syncthreads();
-        for (int t = tid; t < kb0 * kTCW; t += nt) {
-            const int i = t / kTCW, c = t % kTCW;
-            double s = 0.0;
-            for (int j = 0; j < nb; ++j) s += Bk[i * kNB + j] * xs[(kb0 + j) * kTCW + c];
-            xs[i * kTCW + c] -= s;
-        }
+               [&](int t, double v) { rs[t] = v; });
+    batched<4>(g * kCT,
+               [&](int t) {
+                   const int i = t / kCT, cc = t % kCT, col = cb + cc;
+                   if (cc >= nc) return 0.0;
+                   if (col == a.nslot) return T2[(size_t)g2[i] * a.cld + a.cld - 1];
+                   const int pm = a.pmap[col];
+                   return (pm >> 24) == 1 ? T2[(size_t)g2[i] * a.cld + (pm & 0xffffff)] : 0.0;
+               },
+               [&](int t, double v) { rd[t] = v; });
+    __syncthreads();
+    for (int t = threadIdx.x; t < g * kCT; t += 256) {
+        const double r1 = rs[t], r2 = rd[t];
+        rs[t] = r1 + r2;
+        rd[t] = r2 - r1;
     }
     __syncthreads();
-    for (int t = tid; t < n * kTCW; t += nt) {
-        const int r = t / kTCW, c = t % kTCW;
-        if (c < nc) X[(size_t)r * a.ld + cbase + c] = xs[t];
+    const size_t gg = (size_t)g * g;
+    const double* Dg = a.M + (size_t)node * 4 * gg;
+    const double* Eg = Dg + gg;
+    const double* Sg = Eg + gg;
+    const double* Bg = Sg + gg;
+    qd_prod<GT, false>(g, Dg, rd, tt, pan);     // t = D^{-1} (r2 - r1)
+    qd_prod<GT, true>(g, Bg, tt, rs, pan);      // u = r1 + r2 - B t
+    qd_prod<GT, false>(g, Sg, rs, rd, pan);     // s = S^{-1} u
+    qd_prod<GT, true>(g, Eg, rd, tt, pan);      // d = t - E s
+    double* X = a.X + (size_t)node * a.xi * a.ld;
+    for (int t = threadIdx.x; t < g * kCT; t += 256) {
+        const int i = t / kCT, cc = t % kCT;
+        if (cc >= nc) continue;
+        const double s = rd[t], d = tt[t];
+        X[(size_t)i * a.ld + cb + cc] = -(s - d);
+        X[(size_t)(g + i) * a.ld + cb + cc] = -(s + d);
+    }
+}
+
+// Parent traces T_p[o][col] = direct + T_k[o, gamma_k] X_k[:, col] for a
+// tile of kTRR rows and kTRC columns; the gamma rows of the owning children
+// and both children's coefficient blocks staged in LDS.
+constexpr int kTRR = 32, kTRC = 32;
+
+template <int GT>
+__global__ __launch_bounds__(256) void k_qd_trace(MergeArgs a, int col0, int ncol) {
+    __shared__ double Tg[kTRR * GT];
+    __shared__ double Xs[2 * GT * kTRC];
+    __shared__ int qk[kTRR];
+    const int node = blockIdx.x, g = a.g;
+    const int o0 = blockIdx.y * kTRR, cb = col0 + blockIdx.z * kTRC;
+    const int nr = min(kTRR, a.nslot - o0), nc = min(kTRC, col0 + ncol - cb);
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    const double* X = a.X + (size_t)node * a.xi * a.ld;
+    for (int q = threadIdx.x; q < nr; q += 256) qk[q] = a.pmap[o0 + q] >> 24;
+    batched<4>(nr * g,
+               [&](int t) {
+                   const int q = t / g, i = t % g;
+                   const int pm = a.pmap[o0 + q];
+                   const int k = pm >> 24, oc = pm & 0xffffff;
+                   return (k == 0 ? T1 : T2)[(size_t)oc * a.cld + a.gmap[k * g + i]];
+               },
+               [&](int t, double v) { Tg[(t / g) * GT + t % g] = v; });
+    batched<8>(2 * g * kTRC,
+               [&](int t) {
+                   const int r = t / kTRC, cc = t % kTRC;
+                   return cc < nc ? X[(size_t)r * a.ld + cb + cc] : 0.0;
+               },
+               [&](int t, double v) { Xs[t] = v; });
+    __syncthreads();
+    const int cc = threadIdx.x % kTRC;
+    if (cc >= nc) return;
+    const int col = cb + cc;
+    for (int q = threadIdx.x / kTRC; q < nr; q += 256 / kTRC) {
+        const int o = o0 + q, k = qk[q];
+        const int pm = a.pmap[o];
+        const double* Tk = (k == 0 ? T1 : T2) + (size_t)(pm & 0xffffff) * a.cld;
+        double v;
+        if (col == a.nslot) {
+            v = Tk[a.cld - 1];
+        } else {
+            const int pc = a.pmap[col];
+            v = (pc >> 24) == k ? Tk[pc & 0xffffff] : 0.0;
+        }
+        const double* tg = Tg + q * GT;
+        const double* xk = Xs + (size_t)k * g * kTRC + cc;
+        double s0 = 0.0, s1 = 0.0;
+        int i = 0;
+        for (; i + 1 < g; i += 2) {
+            s0 += tg[i] * xk[i * kTRC];
+            s1 += tg[i + 1] * xk[(i + 1) * kTRC];
+        }
+        if (i < g) s0 += tg[i] * xk[i * kTRC];
+        a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = v + (s0 + s1);
     }
 }
 
@@ -941,46 +776,63 @@ static hipError_t solve_cols_generic(rmrcm_ctx* c, const MergeArgs& a, int col0,
     return hipGetLastError();
 }
 
-static hipError_t solve_cols_blocked(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
-    const int nchunk = (ncol + kTCW - 1) / kTCW;
-    const size_t lds = sizeof(double) * (size_t)a.xi * (kTCW + kNB);
-    hipError_t e = hipFuncSetAttribute((const void*)k_merge_trsm,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_trsm, dim3(a.nnodes, nchunk), dim3(kTT), lds, c->stream, a, col0,
-                       ncol);
+// Size class of the pivot-free path (0: gamma too long, generic LU path).
+static int qd_tier(int g) { return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : 0; }
+
+template <int GT, int TL>
+static hipError_t qd_factor(rmrcm_ctx* c, const MergeArgs& a) {
+    hipLaunchKernelGGL((k_qd_factor<GT, TL>), dim3(a.nnodes), dim3(QdGrid<GT, TL>::NT), 0, c->stream,
+                       a);
     return hipGetLastError();
 }
 
-static hipError_t lu_blocked(rmrcm_ctx* c, const MergeArgs& a) {
-    const size_t lds = sizeof(double) * ((size_t)a.xi * (kNB + 1) + (size_t)kNB * (a.xi - kNB));
-    hipError_t e = hipFuncSetAttribute((const void*)k_merge_lu_blocked,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_lu_blocked, dim3(a.nnodes), dim3(kLUT), lds, c->stream, a);
+template <int GT>
+static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace) {
+    hipLaunchKernelGGL(k_qd_apply<GT>, dim3(a.nnodes, (ncol + kCT - 1) / kCT), dim3(256), 0, c->stream,
+                       a, col0, ncol);
+    if (trace)
+        hipLaunchKernelGGL(k_qd_trace<GT>,
+                           dim3(a.nnodes, (a.nslot + kTRR - 1) / kTRR, (ncol + kTRC - 1) / kTRC),
+                           dim3(256), 0, c->stream, a, col0, ncol);
     return hipGetLastError();
+}
+
+static hipError_t qd_factor_any(rmrcm_ctx* c, const MergeArgs& a) {
+    switch (qd_tier(a.g)) {
+        case 16: return qd_factor<16, 2>(c, a);
+        case 32: return qd_factor<32, 4>(c, a);
+        case 64: return qd_factor<64, 4>(c, a);
+        case 128: return qd_factor<128, 4>(c, a);
+    }
+    return hipErrorInvalidValue;
+}
+
+static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace) {
+    switch (qd_tier(a.g)) {
+        case 16: return qd_columns<16>(c, a, col0, ncol, trace);
+        case 32: return qd_columns<32>(c, a, col0, ncol, trace);
+        case 64: return qd_columns<64>(c, a, col0, ncol, trace);
+        case 128: return qd_columns<128>(c, a, col0, ncol, trace);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_merge_setup(rmrcm_ctx* c, int d) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
-    if (a.xi <= kSX) {
-        hipLaunchKernelGGL(k_merge_small, dim3(a.nnodes), dim3(256), 0, c->stream, a, 0);
-        return hipGetLastError();
+    if (qd_tier(a.g)) {
+        hipError_t e = qd_factor_any(c, a);
+        if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
+        return qd_columns_any(c, a, 0, a.nslot, true);
     }
     hipLaunchKernelGGL(k_merge_assemble, dim3(a.nnodes, (a.xi * a.xi + 255) / 256), dim3(256), 0,
                        c->stream, a);
-    hipError_t e;
-    if (a.xi <= kBX) {
-        e = lu_blocked(c, a);
-    } else {
-        hipLaunchKernelGGL(k_merge_lu, dim3(a.nnodes), dim3(256), 0, c->stream, a);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
+    hipLaunchKernelGGL(k_merge_lu, dim3(a.nnodes), dim3(256), 0, c->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || d == 0) return e;
     hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi * a.nslot + 255) / 256), dim3(256), 0,
                        c->stream, a, 0, a.nslot);
-    e = a.xi <= kBX ? solve_cols_blocked(c, a, 0, a.nslot) : solve_cols_generic(c, a, 0, a.nslot);
+    e = solve_cols_generic(c, a, 0, a.nslot);
     if (e != hipSuccess) return e;
     const size_t tot = (size_t)a.nslot * a.nslot;
     hipLaunchKernelGGL(k_merge_trace, dim3(a.nnodes, (unsigned)((tot + 255) / 256)), dim3(256), 0,
@@ -991,14 +843,10 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d) {
 hipError_t launch_merge_particular(rmrcm_ctx* c, int d) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
-    if (a.xi <= kSX) {
-        hipLaunchKernelGGL(k_merge_small, dim3(a.nnodes), dim3(256), 0, c->stream, a, 1);
-        return hipGetLastError();
-    }
+    if (qd_tier(a.g)) return qd_columns_any(c, a, a.nslot, 1, d != 0);
     hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi + 255) / 256), dim3(256), 0, c->stream, a,
                        a.nslot, 1);
-    hipError_t e = a.xi <= kBX ? solve_cols_blocked(c, a, a.nslot, 1)
-                               : solve_cols_generic(c, a, a.nslot, 1);
+    hipError_t e = solve_cols_generic(c, a, a.nslot, 1);
     if (e != hipSuccess) return e;
     if (d == 0) return hipSuccess;
     hipLaunchKernelGGL(k_merge_trace, dim3(a.nnodes, (unsigned)((a.nslot + 255) / 256)), dim3(256),
