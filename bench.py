@@ -168,19 +168,25 @@ def main():
         S.set_stream(stream.cuda_stream)
 
         def step():
-            S.refactor(K)
+            S.refactor(K, wait=False)
             S.solve(q, bcv, p_out, f_out)
 
         for _ in range(args.warmup):
             step()
+        S.sync()
         torch.cuda.synchronize()
-        phases = []
         t0 = time.perf_counter()
         for _ in range(args.steps):
             step()
-            phases.append(S.stats())
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        S.sync()                   # deferred device-side status of the refactors
+        # per-phase times from the library's HIP events, on untimed extra steps
+        phases = []
+        for _ in range(min(args.steps, 5)):
+            step()
+            phases.append(S.stats())
+        S.sync()
         S.close()
         return (t1 - t0) * 1e3 / args.steps, phases, p_out, f_out
 

@@ -117,10 +117,20 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm,
  * rmrcm_setup without its allocations and table building): Robin
  * parameters, local factorisations, basis and the upward merges.
  *   perm: nx*ny permeabilities, finite and > 0 (host or device).
- * Errors: EINVAL (perm NULL, or a value <= 0 / not finite, detected on the
- * device; the context then holds no valid factorisation until the next
- * successful refactor), EDEVICE, ESINGULAR. */
+ * Asynchronous: returns once the work is enqueued on the context's stream
+ * (perm must stay valid until that work has run).  Errors found on the
+ * device (a permeability <= 0 or not finite: EINVAL; a singular merge:
+ * ESINGULAR) are returned by the next rmrcm_sync, or by rmrcm_solve when
+ * that call waits for the stream (host outputs, or no caller stream set);
+ * the context then holds no valid factorisation until the next successful
+ * refactor.
+ * Errors returned directly: EINVAL (ctx or perm NULL), EDEVICE. */
 int rmrcm_refactor(rmrcm_ctx* ctx, const double* perm);
+
+/* Wait for every call enqueued on the context's stream and return the
+ * status that an asynchronous rmrcm_refactor left (OK, EINVAL, ESINGULAR),
+ * or EDEVICE. */
+int rmrcm_sync(rmrcm_ctx* ctx);
 
 /* Solve for one right-hand side: the particular local solutions (source
  * and outer boundary data, additive split of Section 2.1), their columns

@@ -13,6 +13,7 @@ from .rmrcm import (  # noqa: F401
     rmrcm_default_params,
     rmrcm_setup,
     rmrcm_refactor,
+    rmrcm_sync,
     rmrcm_solve,
     rmrcm_get_interface,
     rmrcm_counts,

@@ -324,7 +324,7 @@ int mixed_local_setup(rmrcm_ctx* c) {
     return RMRCM_OK;
 }
 
-int run_setup(rmrcm_ctx* c) {
+int run_setup(rmrcm_ctx* c, bool wait) {
     HIP_TRY(hipEventRecord(c->ev[0], c->stream));
     HIP_TRY(hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
     HIP_TRY(rmrcm::launch_check_perm(c));
@@ -339,8 +339,12 @@ int run_setup(rmrcm_ctx* c) {
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d));
     HIP_TRY(hipEventRecord(c->ev[3], c->stream));
     c->setup_recorded = true;
-    TRY(check_flags(c));
-    return RMRCM_OK;
+    if (!wait) {
+        c->check_pending = true;
+        return RMRCM_OK;
+    }
+    c->check_pending = false;
+    return check_flags(c);
 }
 
 }  // namespace
@@ -463,7 +467,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
         hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return fail(RMRCM_EDEVICE);
     c->n_local_solves = 2 * (int64_t)g.nseg + (int64_t)nsub;
-    if ((r = run_setup(c)) != RMRCM_OK) return fail(r);
+    if ((r = run_setup(c, true)) != RMRCM_OK) return fail(r);
     *out = c;
     return RMRCM_OK;
 }
@@ -474,7 +478,7 @@ int rmrcm_refactor(rmrcm_ctx* c, const double* perm) {
     const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
     c->solved = false;
     HIP_TRY(hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream));
-    return run_setup(c);
+    return run_setup(c, false);
 }
 
 int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, double* pressure,
@@ -534,9 +538,24 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
     HIP_TRY(hipEventRecord(c->ev[10], c->stream));
     c->solve_recorded = true;
     const bool host_out = !is_device_ptr(pressure) || !is_device_ptr(flux);
-    if (host_out || c->stream == c->own_stream) HIP_TRY(hipStreamSynchronize(c->stream));
     c->solved = true;
+    if (host_out || c->stream == c->own_stream) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (c->check_pending) {
+            c->check_pending = false;
+            return check_flags(c);
+        }
+    }
     return RMRCM_OK;
+}
+
+int rmrcm_sync(rmrcm_ctx* c) {
+    if (!c) return RMRCM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!c->check_pending) return RMRCM_OK;
+    c->check_pending = false;
+    return check_flags(c);
 }
 
 int rmrcm_get_interface(rmrcm_ctx* c, double* U, double* P) {

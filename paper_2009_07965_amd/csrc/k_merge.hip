@@ -319,72 +319,120 @@ struct QdGrid {
 
 // In-place Gauss-Jordan inversion without pivoting of the register-resident
 // g x g matrix v (zero outside g x g).  rowb/colb: [2][GT] LDS buffers.
+// Without pivoting the elimination order is free; it runs over the local
+// tile index kl first, so that register indices stay compile-time constants
+// (pivot k = kt + TG kl is owned by thread row / column kt).
 template <int GT, int TL>
 __device__ void gj_invert(int g, double (&v)[TL][TL], double* rowb, double* colb, int* bad) {
     constexpr int TG = QdGrid<GT, TL>::TG;
     const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
-    for (int k = 0; k < g; ++k) {
-        double* rb = rowb + (k & 1) * GT;
-        double* cb = colb + (k & 1) * GT;
-        const int kt = k % TG, kl = k / TG;
-        if (ti == kt)
+    int step = 0;
 #pragma unroll
-            for (int b = 0; b < TL; ++b) rb[tj + TG * b] = v[kl][b];
-        if (tj == kt)
+    for (int kl = 0; kl < TL; ++kl) {
+        for (int kt = 0; kt < TG; ++kt, ++step) {
+            const int k = kt + TG * kl;
+            if (k >= g) break;
+            double* rb = rowb + (step & 1) * GT;
+            double* cb = colb + (step & 1) * GT;
+            const bool rown = ti == kt, coln = tj == kt;
+            if (rown)
 #pragma unroll
-            for (int a = 0; a < TL; ++a) cb[ti + TG * a] = v[a][kl];
-        __syncthreads();
-        const double piv = cb[k];
-        if (threadIdx.x == 0 && !(piv != 0.0 && isfinite(piv))) *bad = 1;
-        const double p = 1.0 / piv;
-        double r[TL], c[TL];
+                for (int b = 0; b < TL; ++b) rb[tj + TG * b] = v[kl][b];
+            if (coln)
 #pragma unroll
-        for (int b = 0; b < TL; ++b) {
-            const int j = tj + TG * b;
-            r[b] = j == k ? 1.0 : rb[j];
-        }
+                for (int a = 0; a < TL; ++a) cb[ti + TG * a] = v[a][kl];
+            __syncthreads();
+            const double piv = cb[k];
+            if (threadIdx.x == 0 && !(piv != 0.0 && isfinite(piv))) *bad = 1;
+            const double p = 1.0 / piv;
+            double c[TL], r[TL];
 #pragma unroll
-        for (int a = 0; a < TL; ++a) {
-            const int i = ti + TG * a;
-            c[a] = i == k ? -p : cb[i] * p;
-        }
+            for (int a = 0; a < TL; ++a) c[a] = cb[ti + TG * a] * p;
 #pragma unroll
-        for (int a = 0; a < TL; ++a)
+            for (int b = 0; b < TL; ++b) r[b] = rb[tj + TG * b];
+            // pivot row becomes row/piv, pivot column -col/piv, pivot 1/piv
+            if (rown) {
+                c[kl] = -p;
 #pragma unroll
-            for (int b = 0; b < TL; ++b) {
-                const int i = ti + TG * a, j = tj + TG * b;
-                const double base = (i == k || j == k) ? 0.0 : v[a][b];
-                v[a][b] = base - c[a] * r[b];
+                for (int b = 0; b < TL; ++b) v[kl][b] = 0.0;
             }
+            if (coln) {
+                r[kl] = 1.0;
+#pragma unroll
+                for (int a = 0; a < TL; ++a) v[a][kl] = 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < TL; ++a)
+#pragma unroll
+                for (int b = 0; b < TL; ++b) v[a][b] -= c[a] * r[b];
+        }
     }
     __syncthreads();
 }
 
-// acc += A B over k < g, with PW-wide panels of A (columns) and B (rows)
-// published into LDS by pubA(k0, bufA[GT][PW]) and pubB(k0, bufB[PW][GT]).
-template <int GT, int TL, class PubA, class PubB>
-__device__ void summa(int g, double (&acc)[TL][TL], double* bufA, double* bufB, PubA pubA,
-                      PubB pubB) {
+// acc += (SGN) A B over k < g.  One operand is register-resident and
+// published PW columns (A) or rows (B) at a time through the ping-pong
+// buffer buf[2][GT][PW] / buf[2][PW][GT]; the other is whole in LDS
+// (row-major, leading dimension GT).
+template <int GT, int TL, int SGN>
+__device__ void summa_reg_lds(int g, double (&acc)[TL][TL], const double (&ar)[TL][TL],
+                              const double* Bl, double* buf) {
     constexpr int TG = QdGrid<GT, TL>::TG, PW = QdGrid<GT, TL>::PW;
     const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
     int pp = 0;
     for (int k0 = 0; k0 < g; k0 += PW, pp ^= 1) {
-        double* A = bufA + pp * GT * PW;
-        double* B = bufB + pp * PW * GT;
-        pubA(k0, A);
-        pubB(k0, B);
+        double* A = buf + pp * GT * PW;
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int j = tj + TG * q;
+            if (j >= k0 && j < k0 + PW)
+#pragma unroll
+                for (int p = 0; p < TL; ++p) A[(ti + TG * p) * PW + (j - k0)] = ar[p][q];
+        }
         __syncthreads();
         const int kw = min(PW, g - k0);
         for (int kk = 0; kk < kw; ++kk) {
             double av[TL], bv[TL];
 #pragma unroll
-            for (int a = 0; a < TL; ++a) av[a] = A[(ti + TG * a) * PW + kk];
+            for (int p = 0; p < TL; ++p) av[p] = A[(ti + TG * p) * PW + kk];
 #pragma unroll
-            for (int b = 0; b < TL; ++b) bv[b] = B[kk * GT + tj + TG * b];
+            for (int q = 0; q < TL; ++q) bv[q] = Bl[(k0 + kk) * GT + tj + TG * q];
 #pragma unroll
-            for (int a = 0; a < TL; ++a)
+            for (int p = 0; p < TL; ++p)
 #pragma unroll
-                for (int b = 0; b < TL; ++b) acc[a][b] += av[a] * bv[b];
+                for (int q = 0; q < TL; ++q) acc[p][q] += SGN * av[p] * bv[q];
+        }
+    }
+    __syncthreads();
+}
+
+template <int GT, int TL, int SGN>
+__device__ void summa_lds_reg(int g, double (&acc)[TL][TL], const double* Al,
+                              const double (&br)[TL][TL], double* buf) {
+    constexpr int TG = QdGrid<GT, TL>::TG, PW = QdGrid<GT, TL>::PW;
+    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
+    int pp = 0;
+    for (int k0 = 0; k0 < g; k0 += PW, pp ^= 1) {
+        double* B = buf + pp * PW * GT;
+#pragma unroll
+        for (int p = 0; p < TL; ++p) {
+            const int i = ti + TG * p;
+            if (i >= k0 && i < k0 + PW)
+#pragma unroll
+                for (int q = 0; q < TL; ++q) B[(i - k0) * GT + tj + TG * q] = br[p][q];
+        }
+        __syncthreads();
+        const int kw = min(PW, g - k0);
+        for (int kk = 0; kk < kw; ++kk) {
+            double av[TL], bv[TL];
+#pragma unroll
+            for (int p = 0; p < TL; ++p) av[p] = Al[(ti + TG * p) * GT + k0 + kk];
+#pragma unroll
+            for (int q = 0; q < TL; ++q) bv[q] = B[kk * GT + tj + TG * q];
+#pragma unroll
+            for (int p = 0; p < TL; ++p)
+#pragma unroll
+                for (int q = 0; q < TL; ++q) acc[p][q] += SGN * av[p] * bv[q];
         }
     }
     __syncthreads();
@@ -393,8 +441,9 @@ __device__ void summa(int g, double (&acc)[TL][TL], double* bufA, double* bufB, 
 template <int GT, int TL>
 __global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a) {
     constexpr int TG = QdGrid<GT, TL>::TG, NT = QdGrid<GT, TL>::NT, PW = QdGrid<GT, TL>::PW;
+    __shared__ double Bl[GT * GT];               // B = T2gg - T1gg, resident
+    __shared__ double buf[2 * GT * PW];
     __shared__ double rowb[2 * GT], colb[2 * GT];
-    __shared__ double bufA[2 * GT * PW], bufB[2 * PW * GT];
     __shared__ double wv[GT];
     __shared__ int gi1[GT], gi2[GT];
     __shared__ int bad;
@@ -418,19 +467,29 @@ __global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a
     double* Eg = Dg + gg;
     double* Sg = Eg + gg;
     double* Bg = Sg + gg;
-    double v[TL][TL];
+    // the gamma blocks of both children: every load issued before any store
+    double v[TL][TL], u[TL][TL];
 #pragma unroll
     for (int p = 0; p < TL; ++p)
 #pragma unroll
         for (int q = 0; q < TL; ++q) {
             const int i = ti + TG * p, j = tj + TG * q;
-            v[p][q] = 0.0;
+            const bool in = i < g && j < g;
+            v[p][q] = in ? T1[(size_t)gi1[i] * a.cld + gi1[j]] : 0.0;
+            u[p][q] = in ? T2[(size_t)gi2[i] * a.cld + gi2[j]] : 0.0;
+        }
+#pragma unroll
+    for (int p = 0; p < TL; ++p)
+#pragma unroll
+        for (int q = 0; q < TL; ++q) {
+            const int i = ti + TG * p, j = tj + TG * q;
+            const double b = u[p][q] - v[p][q], nv = v[p][q] + u[p][q];
+            Bl[(ti + TG * p) * GT + tj + TG * q] = b;
             if (i < g && j < g) {
-                const double t1 = T1[(size_t)gi1[i] * a.cld + gi1[j]];
-                const double t2 = T2[(size_t)gi2[i] * a.cld + gi2[j]];
-                v[p][q] = t1 + t2 + (i == j ? 4.0 * wv[i] : 0.0);
-                Bg[(size_t)i * g + j] = t2 - t1;
+                Bg[(size_t)i * g + j] = b;
+                Sg[(size_t)i * g + j] = nv;     // N = T1gg + T2gg, parked until the Schur step
             }
+            v[p][q] = nv + (i == j && i < g ? 4.0 * wv[i] : 0.0);    // D
         }
     gj_invert<GT, TL>(g, v, rowb, colb, &bad);     // v = D^{-1}
 #pragma unroll
@@ -440,154 +499,124 @@ __global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a
             const int i = ti + TG * p, j = tj + TG * q;
             if (i < g && j < g) Dg[(size_t)i * g + j] = v[p][q];
         }
-    // E = D^{-1} B: A panels (columns of D^{-1}) from registers, B panels
-    // (rows of B) gathered from the children's traces
-    double acc[TL][TL];
+    // E = D^{-1} B
 #pragma unroll
     for (int p = 0; p < TL; ++p)
 #pragma unroll
-        for (int q = 0; q < TL; ++q) acc[p][q] = 0.0;
-    summa<GT, TL>(
-        g, acc, bufA, bufB,
-        [&](int k0, double* A) {
-#pragma unroll
-            for (int q = 0; q < TL; ++q) {
-                const int j = tj + TG * q;
-                if (j >= k0 && j < k0 + PW)
-#pragma unroll
-                    for (int p = 0; p < TL; ++p) A[(ti + TG * p) * PW + (j - k0)] = v[p][q];
-            }
-        },
-        [&](int k0, double* B) {
-            for (int t = tid; t < PW * GT; t += NT) {
-                const int kk = t / GT, j = t % GT, i = k0 + kk;
-                B[t] = (j < g && i < g) ? T2[(size_t)gi2[i] * a.cld + gi2[j]] -
-                                              T1[(size_t)gi1[i] * a.cld + gi1[j]]
-                                        : 0.0;
-            }
-        });
+        for (int q = 0; q < TL; ++q) u[p][q] = 0.0;
+    summa_reg_lds<GT, TL, 1>(g, u, v, Bl, buf);
 #pragma unroll
     for (int p = 0; p < TL; ++p)
 #pragma unroll
         for (int q = 0; q < TL; ++q) {
             const int i = ti + TG * p, j = tj + TG * q;
-            if (i < g && j < g) Eg[(size_t)i * g + j] = acc[p][q];
+            if (i < g && j < g) Eg[(size_t)i * g + j] = u[p][q];
         }
-    // S = N - B E: A panels (columns of -B) gathered, B panels (rows of E)
-    // from registers
+    // S = N - B E (each thread reads back only the N entries it stored)
+    double nn[TL][TL];
 #pragma unroll
     for (int p = 0; p < TL; ++p)
 #pragma unroll
         for (int q = 0; q < TL; ++q) {
             const int i = ti + TG * p, j = tj + TG * q;
-            v[p][q] = (i < g && j < g) ? T1[(size_t)gi1[i] * a.cld + gi1[j]] +
-                                             T2[(size_t)gi2[i] * a.cld + gi2[j]]
-                                       : 0.0;
+            nn[p][q] = (i < g && j < g) ? Sg[(size_t)i * g + j] : 0.0;
         }
-    summa<GT, TL>(
-        g, v, bufA, bufB,
-        [&](int k0, double* A) {
-            for (int t = tid; t < GT * PW; t += NT) {
-                const int i = t / PW, kk = t % PW, j = k0 + kk;
-                A[t] = (i < g && j < g) ? T1[(size_t)gi1[i] * a.cld + gi1[j]] -
-                                              T2[(size_t)gi2[i] * a.cld + gi2[j]]
-                                        : 0.0;
-            }
-        },
-        [&](int k0, double* B) {
-#pragma unroll
-            for (int p = 0; p < TL; ++p) {
-                const int i = ti + TG * p;
-                if (i >= k0 && i < k0 + PW)
-#pragma unroll
-                    for (int q = 0; q < TL; ++q) B[(i - k0) * GT + tj + TG * q] = acc[p][q];
-            }
-        });
+    summa_lds_reg<GT, TL, -1>(g, nn, Bl, u, buf);
     if (a.pin) {
 #pragma unroll
         for (int p = 0; p < TL; ++p)
 #pragma unroll
             for (int q = 0; q < TL; ++q) {
                 const int i = ti + TG * p, j = tj + TG * q;
-                if (i == g - 1 || j == g - 1) v[p][q] = (i == j) ? 1.0 : 0.0;
+                if (i == g - 1 || j == g - 1) nn[p][q] = (i == j) ? 1.0 : 0.0;
             }
     }
-    gj_invert<GT, TL>(g, v, rowb, colb, &bad);     // v = S^{-1}
+    gj_invert<GT, TL>(g, nn, rowb, colb, &bad);    // nn = S^{-1}
 #pragma unroll
     for (int p = 0; p < TL; ++p)
 #pragma unroll
         for (int q = 0; q < TL; ++q) {
             const int i = ti + TG * p, j = tj + TG * q;
-            if (i < g && j < g) Sg[(size_t)i * g + j] = (a.pin && i == g - 1 && j == g - 1) ? 0.0 : v[p][q];
+            if (i < g && j < g)
+                Sg[(size_t)i * g + j] = (a.pin && i == g - 1 && j == g - 1) ? 0.0 : nn[p][q];
         }
     if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
 }
 
 // Gamma coefficients of columns [col0, col0 + ncol): X = -M^{-1} R through
-// the stored blocks, kCT columns per workgroup.
-constexpr int kCT = 16;
-constexpr int kKP = 16;       // k-panel width of the block products
+// the stored blocks, CT columns per workgroup (CT = 1 for the particular
+// column alone); each g x g block is brought into LDS whole (all its loads
+// in flight at once, rows padded against bank conflicts) before its product.
+template <int GT>
+__host__ __device__ constexpr int qd_ct() { return GT >= 128 ? 8 : 16; }
 
-// out[i][c] (= or -=) sum_k A[i][k] in[k][c] for i < g, c < kCT; A g x g
-// row-major in global memory, staged in kKP-wide panels; in/out in LDS.
-template <int GT, bool SUB>
+// out[i][c] (= or -=) sum_k A[i][k] in[k][c] for i < g, c < CT; A g x g
+// row-major in global memory, staged in Al with leading dimension g + 1.
+template <int GT, int CT, bool SUB>
 __device__ void qd_prod(int g, const double* __restrict__ A, const double* in, double* out,
-                        double* pan) {
-    constexpr int RPT = (GT + 15) / 16;      // rows per thread
-    const int tid = threadIdx.x, c = tid % kCT, r0 = tid / kCT;
+                        double* Al) {
+    constexpr int RG = 256 / CT, RPT = (GT + RG - 1) / RG;
+    constexpr int NL = (GT * GT + 255) / 256, CH = NL > 32 ? 32 : NL;
+    const int tid = threadIdx.x, c = tid % CT, r0 = tid / CT;
+    const int n = g * g, L = g + 1;
+    for (int l0 = 0; l0 < NL; l0 += CH) {      // chunks of CH loads in flight per thread
+        double ld[CH];
+#pragma unroll
+        for (int l = 0; l < CH; ++l) {
+            const int t = tid + 256 * (l0 + l);
+            ld[l] = t < n ? A[t] : 0.0;
+        }
+#pragma unroll
+        for (int l = 0; l < CH; ++l) {
+            const int t = tid + 256 * (l0 + l);
+            if (t < n) Al[(t / g) * L + t % g] = ld[l];
+        }
+    }
+    __syncthreads();
     double acc[RPT];
 #pragma unroll
     for (int u = 0; u < RPT; ++u) acc[u] = 0.0;
-    for (int k0 = 0; k0 < g; k0 += kKP) {
-        const int kw = min(kKP, g - k0);
-        for (int t = tid; t < g * kKP; t += 256) {
-            const int i = t / kKP, kk = t % kKP;
-            pan[t] = kk < kw ? A[(size_t)i * g + k0 + kk] : 0.0;
-        }
-        __syncthreads();
-        for (int kk = 0; kk < kw; ++kk) {
-            const double x = in[(k0 + kk) * kCT + c];
+    for (int k = 0; k < g; ++k) {
+        const double x = in[k * CT + c];
 #pragma unroll
-            for (int u = 0; u < RPT; ++u) {
-                const int i = r0 + 16 * u;
-                if (i < g) acc[u] += pan[i * kKP + kk] * x;
-            }
+        for (int u = 0; u < RPT; ++u) {
+            const int i = r0 + RG * u;
+            if (i < g) acc[u] += Al[i * L + k] * x;
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < RPT; ++u) {
-        const int i = r0 + 16 * u;
-        if (i < g) out[i * kCT + c] = SUB ? out[i * kCT + c] - acc[u] : acc[u];
+        const int i = r0 + RG * u;
+        if (i < g) out[i * CT + c] = SUB ? out[i * CT + c] - acc[u] : acc[u];
     }
     __syncthreads();
 }
 
-template <int GT>
+template <int GT, int CT>
 __global__ __launch_bounds__(256) void k_qd_apply(MergeArgs a, int col0, int ncol) {
-    __shared__ double rs[GT * kCT], rd[GT * kCT], tt[GT * kCT];
-    __shared__ double pan[GT * kKP];
+    __shared__ double rs[GT * CT], rd[GT * CT], tt[GT * CT];
+    __shared__ double Al[GT * (GT + 1)];
     const int node = blockIdx.x, g = a.g;
-    const int cb = col0 + blockIdx.y * kCT;
-    const int nc = min(kCT, col0 + ncol - cb);
+    const int cb = col0 + blockIdx.y * CT;
+    const int nc = min(CT, col0 + ncol - cb);
     int c1, c2;
     children(a, node, &c1, &c2);
     const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
     const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
     const int* g1 = a.gmap;
     const int* g2 = a.gmap + g;
-    batched<4>(g * kCT,
+    batched<4>(g * CT,
                [&](int t) {
-                   const int i = t / kCT, cc = t % kCT, col = cb + cc;
+                   const int i = t / CT, cc = t % CT, col = cb + cc;
                    if (cc >= nc) return 0.0;
                    if (col == a.nslot) return T1[(size_t)g1[i] * a.cld + a.cld - 1];
                    const int pm = a.pmap[col];
                    return (pm >> 24) == 0 ? T1[(size_t)g1[i] * a.cld + (pm & 0xffffff)] : 0.0;
                },
                [&](int t, double v) { rs[t] = v; });
-    batched<4>(g * kCT,
+    batched<4>(g * CT,
                [&](int t) {
-                   const int i = t / kCT, cc = t % kCT, col = cb + cc;
+                   const int i = t / CT, cc = t % CT, col = cb + cc;
                    if (cc >= nc) return 0.0;
                    if (col == a.nslot) return T2[(size_t)g2[i] * a.cld + a.cld - 1];
                    const int pm = a.pmap[col];
@@ -595,7 +624,7 @@ __global__ __launch_bounds__(256) void k_qd_apply(MergeArgs a, int col0, int nco
                },
                [&](int t, double v) { rd[t] = v; });
     __syncthreads();
-    for (int t = threadIdx.x; t < g * kCT; t += 256) {
+    for (int t = threadIdx.x; t < g * CT; t += 256) {
         const double r1 = rs[t], r2 = rd[t];
         rs[t] = r1 + r2;
         rd[t] = r2 - r1;
@@ -606,13 +635,13 @@ __global__ __launch_bounds__(256) void k_qd_apply(MergeArgs a, int col0, int nco
     const double* Eg = Dg + gg;
     const double* Sg = Eg + gg;
     const double* Bg = Sg + gg;
-    qd_prod<GT, false>(g, Dg, rd, tt, pan);     // t = D^{-1} (r2 - r1)
-    qd_prod<GT, true>(g, Bg, tt, rs, pan);      // u = r1 + r2 - B t
-    qd_prod<GT, false>(g, Sg, rs, rd, pan);     // s = S^{-1} u
-    qd_prod<GT, true>(g, Eg, rd, tt, pan);      // d = t - E s
+    qd_prod<GT, CT, false>(g, Dg, rd, tt, Al);     // t = D^{-1} (r2 - r1)
+    qd_prod<GT, CT, true>(g, Bg, tt, rs, Al);      // u = r1 + r2 - B t
+    qd_prod<GT, CT, false>(g, Sg, rs, rd, Al);     // s = S^{-1} u
+    qd_prod<GT, CT, true>(g, Eg, rd, tt, Al);      // d = t - E s
     double* X = a.X + (size_t)node * a.xi * a.ld;
-    for (int t = threadIdx.x; t < g * kCT; t += 256) {
-        const int i = t / kCT, cc = t % kCT;
+    for (int t = threadIdx.x; t < g * CT; t += 256) {
+        const int i = t / CT, cc = t % CT;
         if (cc >= nc) continue;
         const double s = rd[t], d = tt[t];
         X[(size_t)i * a.ld + cb + cc] = -(s - d);
@@ -788,8 +817,13 @@ static hipError_t qd_factor(rmrcm_ctx* c, const MergeArgs& a) {
 
 template <int GT>
 static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace) {
-    hipLaunchKernelGGL(k_qd_apply<GT>, dim3(a.nnodes, (ncol + kCT - 1) / kCT), dim3(256), 0, c->stream,
-                       a, col0, ncol);
+    constexpr int CT = qd_ct<GT>();
+    if (ncol == 1)
+        hipLaunchKernelGGL((k_qd_apply<GT, 1>), dim3(a.nnodes, 1), dim3(256), 0, c->stream, a, col0,
+                           ncol);
+    else
+        hipLaunchKernelGGL((k_qd_apply<GT, CT>), dim3(a.nnodes, (ncol + CT - 1) / CT), dim3(256), 0,
+                           c->stream, a, col0, ncol);
     if (trace)
         hipLaunchKernelGGL(k_qd_trace<GT>,
                            dim3(a.nnodes, (a.nslot + kTRR - 1) / kTRR, (ncol + kTRC - 1) / kTRC),

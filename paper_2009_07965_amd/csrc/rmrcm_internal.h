@@ -67,6 +67,7 @@ struct rmrcm_ctx {
     hipStream_t stream = nullptr;
     bool any_dirichlet = false;
     bool solved = false;
+    bool check_pending = false;   // device-detected errors of an asynchronous refactor
     bool setup_recorded = false;
     bool solve_recorded = false;
     // device arrays

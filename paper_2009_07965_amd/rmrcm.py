@@ -45,7 +45,8 @@ class rmrcm_params(ctypes.Structure):
 
 
 EXPORTS = [
-    "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_solve", "rmrcm_get_interface",
+    "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve",
+    "rmrcm_get_interface",
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
     "rmrcm_strerror",
 ]
@@ -68,6 +69,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_setup.restype = ctypes.c_int
     lib.rmrcm_refactor.argtypes = [vp, dp]
     lib.rmrcm_refactor.restype = ctypes.c_int
+    lib.rmrcm_sync.argtypes = [vp]
+    lib.rmrcm_sync.restype = ctypes.c_int
     lib.rmrcm_solve.argtypes = [vp, dp, dp, dp, dp]
     lib.rmrcm_solve.restype = ctypes.c_int
     lib.rmrcm_get_interface.argtypes = [vp, dp, dp]
@@ -132,6 +135,10 @@ def rmrcm_refactor(ctx, perm):
     _check(lib().rmrcm_refactor(ctx, kp), "rmrcm_refactor")
 
 
+def rmrcm_sync(ctx):
+    _check(lib().rmrcm_sync(ctx), "rmrcm_sync")
+
+
 def rmrcm_solve(ctx, source, bc_value, pressure, flux):
     sp, _s = _ptr(source, np.float64)
     bp, _b = _ptr(bc_value, np.float64)
@@ -194,8 +201,15 @@ class Solver:
         return cls(prob.nx, prob.ny, prob.K, prob.bc_type, prob.sub_nx, prob.sub_ny,
                    prob.seg, alpha=prob.alpha, lx=prob.lx, ly=prob.ly, **kw)
 
-    def refactor(self, K):
+    def refactor(self, K, wait=True):
+        """New permeability, same geometry.  wait=False leaves the work
+        enqueued (errors then surface at the next sync or waiting solve)."""
         rmrcm_refactor(self.ctx, K)
+        if wait:
+            rmrcm_sync(self.ctx)
+
+    def sync(self):
+        rmrcm_sync(self.ctx)
 
     def solve(self, q, bc_value, pressure=None, flux=None):
         """Returns (pressure (ny, nx), flux (4, ny, nx)); NumPy unless

@@ -171,3 +171,43 @@ def test_full_size_1024(Solver):
     # conservation: backward error per cell (contrast ~5e6 here)
     assert cell_backward_error(prob, p, F) < 1e-12
     assert cell_backward_error(prob, ref.p, ref.F) < 1e-12
+
+
+def test_async_refactor_new_field(Solver):
+    """rmrcm_refactor is asynchronous; a solve that returns host arrays waits
+    for it and gives the oracle's answer for the new field."""
+    p1 = make_problem(128, b=16, seg=4, log_var=2.0, seed=11)
+    p2 = make_problem(128, b=16, seg=4, log_var=4.0, lam=0.05, seed=12, source=True)
+    S = Solver.from_problem(p1)
+    try:
+        say("[gpu] async refactor")
+        S.refactor(p2.K, wait=False)
+        p, F = S.solve(p2.q, p2.bc_value)
+        ref = mrcm_solve(p2)
+        assert rel_l2(p, ref.p) <= TOL and rel_l2(F, ref.F) <= TOL
+    finally:
+        S.close()
+
+
+def test_bad_permeability_reported_at_sync(Solver):
+    """A non-positive permeability passed to refactor is found on the device
+    and returned by the next sync (EINVAL); the next valid refactor
+    restores the context."""
+    from paper_2009_07965_amd import RMRCMError
+    prob = make_problem(64, b=16, seg=4, log_var=1.0)
+    S = Solver.from_problem(prob)
+    try:
+        say("[gpu] bad permeability")
+        Kbad = prob.K.copy()
+        Kbad[5, 7] = -1.0
+        S.refactor(Kbad, wait=False)
+        with pytest.raises(RMRCMError) as ei:
+            S.sync()
+        assert ei.value.status == -1
+        S.sync()                                   # the status was consumed
+        S.refactor(prob.K)
+        p, F = S.solve(prob.q, prob.bc_value)
+        ref = mrcm_solve(prob)
+        assert rel_l2(p, ref.p) <= TOL and rel_l2(F, ref.F) <= TOL
+    finally:
+        S.close()
