@@ -174,6 +174,60 @@ void rmrcm_destroy(rmrcm_ctx* ctx);
 /* Static message for a status code. */
 const char* rmrcm_strerror(int status);
 
+/* Time the candidate column tiles (4, 8, 16 columns per workgroup) of the
+ * interface-merge products of every level of this context on its own
+ * shapes and keep the fastest; choices are cached per merge shape (gamma
+ * length, parent slots, merges per level) for the process.  Results do not
+ * depend on the choice (each column is computed the same way).  Runs on
+ * the context's stream and waits for it.  Errors: EINVAL, EDEVICE. */
+int rmrcm_autotune(rmrcm_ctx* ctx);
+
+/* ---- Ensembles: many independent problems on one device ----------------
+ * Members may differ in grid, subdomain size, segment length, boundary
+ * types and precision.  Every member is an ordinary context (set up by
+ * rmrcm_setup); the batch enqueues the members' work on a pool of streams,
+ * largest member first, so that small members fill the device together.
+ * For FP64 members the permeability-dependent work and the solve are each
+ * captured once as a HIP graph and replayed; mixed-precision members are
+ * enqueued directly (their refinement waits on the host between passes).
+ * All-Neumann members check the compatibility of their data on the device
+ * (EINVAL at the next rmrcm_batch_sync when violated). */
+typedef struct rmrcm_batch rmrcm_batch;
+
+/* Build a batch of `count` members; prms[i], perms[i] (nx*ny, host or
+ * device), bc_types[i] as for rmrcm_setup.  autotune != 0 runs
+ * rmrcm_autotune on every member and picks the number of pool streams
+ * (1, 2, 4, 8 or 16) by timing a full refactor + solve pass of the batch;
+ * otherwise 4 streams.  All members must use the same device.
+ * Errors: those of rmrcm_setup for the first failing member, EINVAL,
+ * ENOMEM, EDEVICE. */
+int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* const* perms,
+                       const int8_t* const* bc_types, int32_t autotune, rmrcm_batch** out);
+
+/* rmrcm_refactor for every member (perms: count pointers).  Asynchronous;
+ * device-detected errors are returned by rmrcm_batch_sync. */
+int rmrcm_batch_refactor(rmrcm_batch* b, const double* const* perms);
+
+/* rmrcm_solve for every member: sources (count pointers, or NULL for all
+ * zero; an entry may be NULL), bc_values, pressures (nx*ny) and fluxes
+ * (4*nx*ny) per member, host or device.  Asynchronous: outputs are
+ * complete after rmrcm_batch_sync. */
+int rmrcm_batch_solve(rmrcm_batch* b, const double* const* sources, const double* const* bc_values,
+                      double* const* pressures, double* const* fluxes);
+
+/* Wait for all enqueued batch work; status (count entries, may be NULL)
+ * receives each member's status; returns the first non-OK one. */
+int rmrcm_batch_sync(rmrcm_batch* b, int32_t* status);
+
+/* JSON: members, pool streams, graph-captured members, cells, local
+ * solves, device bytes, last refactor / solve times (ms, from events on
+ * the batch's master stream) and the merge column tiles per member and
+ * level.  Returns the length needed including the terminator. */
+int rmrcm_batch_get_stats(rmrcm_batch* b, char* json, size_t cap);
+
+/* Release every member and the batch's streams and graphs. */
+void rmrcm_batch_destroy(rmrcm_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,8 @@ binding raises on first use.
 
 from .rmrcm import (  # noqa: F401
     Solver,
+    Batch,
+    rmrcm_autotune,
     RMRCMError,
     load_library,
     rmrcm_default_params,

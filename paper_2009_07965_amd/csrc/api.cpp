@@ -8,6 +8,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
+#include <array>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -258,10 +262,10 @@ void free_all(rmrcm_ctx* c) {
 }
 
 int check_flags(rmrcm_ctx* c) {
-    int h[4] = {0, 0, 0, 0};
+    int h[rmrcm::kNumFlags] = {};
     HIP_TRY(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (h[rmrcm::FLAG_BAD_PERM]) return RMRCM_EINVAL;
+    if (h[rmrcm::FLAG_BAD_PERM] || h[rmrcm::FLAG_BAD_DATA]) return RMRCM_EINVAL;
     if (h[rmrcm::FLAG_LOCAL_SINGULAR] || h[rmrcm::FLAG_MERGE_SINGULAR]) return RMRCM_ESINGULAR;
     return RMRCM_OK;
 }
@@ -301,7 +305,7 @@ int refine_loop(rmrcm_ctx* c, int part, int* iters, double* last) {
 // the tolerance, traces.
 int mixed_local_setup(rmrcm_ctx* c) {
     const int nsub = c->geo.mx * c->geo.my;
-    HIP_TRY(hipMemsetAsync(c->fb, 0, nsub * sizeof(int), c->stream));
+    HIP_TRY(rmrcm::launch_fill_i32(c, c->fb, nsub, 0));
     HIP_TRY(rmrcm::launch_local_setup(c, true, nullptr, 0, 0));
     int it = 0;
     double last = 0.0;
@@ -312,7 +316,7 @@ int mixed_local_setup(rmrcm_ctx* c) {
     if (st == RMRCM_ENOTCONV) {
         HIP_TRY(rmrcm::launch_local_refine(c, 0, 0));   // measure only
         HIP_TRY(rmrcm::launch_mark_fallback(c, c->prm.ir_tol));
-        int h[4];
+        int h[rmrcm::kNumFlags];
         HIP_TRY(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         c->n_fallback = h[rmrcm::FLAG_FALLBACK];
@@ -324,20 +328,33 @@ int mixed_local_setup(rmrcm_ctx* c) {
     return RMRCM_OK;
 }
 
-int run_setup(rmrcm_ctx* c, bool wait) {
-    HIP_TRY(hipEventRecord(c->ev[0], c->stream));
-    HIP_TRY(hipMemsetAsync(c->flags, 0, 4 * sizeof(int), c->stream));
+// Event i of the phase timers, unless the work is being captured in a graph.
+int mark(rmrcm_ctx* c, int i) {
+    if (!c->capturing) HIP_TRY(hipEventRecord(c->ev[i], c->stream));
+    return RMRCM_OK;
+}
+
+// Every permeability-dependent step, enqueued on c->stream (no host
+// synchronisation in FP64 mode, so that it can be captured in a graph).
+int enqueue_setup(rmrcm_ctx* c) {
+    TRY(mark(c, 0));
+    HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
     HIP_TRY(rmrcm::launch_check_perm(c));
     HIP_TRY(rmrcm::launch_beta(c));
-    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    TRY(mark(c, 1));
     if (mixed(c)) {
         TRY(mixed_local_setup(c));
     } else {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
     }
-    HIP_TRY(hipEventRecord(c->ev[2], c->stream));
+    TRY(mark(c, 2));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d));
-    HIP_TRY(hipEventRecord(c->ev[3], c->stream));
+    TRY(mark(c, 3));
+    return RMRCM_OK;
+}
+
+int run_setup(rmrcm_ctx* c, bool wait) {
+    TRY(enqueue_setup(c));
     c->setup_recorded = true;
     if (!wait) {
         c->check_pending = true;
@@ -345,6 +362,57 @@ int run_setup(rmrcm_ctx* c, bool wait) {
     }
     c->check_pending = false;
     return check_flags(c);
+}
+
+// Inputs of a solve into the context's staging buffers.
+int solve_inputs(rmrcm_ctx* c, const double* source, const double* bc_value) {
+    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+    const size_t nbf = 2 * (size_t)c->geo.nx + 2 * (size_t)c->geo.ny;
+    TRY(mark(c, 4));
+    if (source) {
+        HIP_TRY(hipMemcpyAsync(c->q, source, ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    } else {
+        HIP_TRY(rmrcm::launch_fill_f64(c, c->q, ncell, 0.0));
+    }
+    HIP_TRY(hipMemcpyAsync(c->bcv, bc_value, nbf * sizeof(double), hipMemcpyDefault, c->stream));
+    TRY(mark(c, 5));
+    return RMRCM_OK;
+}
+
+// Particular solutions, their merges, the top solve, the downward pass and
+// the reconstruction, enqueued on c->stream (graph-capturable in FP64 mode).
+int enqueue_solve(rmrcm_ctx* c) {
+    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_compat_check(c));
+    if (mixed(c)) {
+        HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 0, 0));
+        if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));
+        int it = 0;
+        double last = 0.0;
+        const int st = refine_loop(c, 1, &it, &last);
+        c->ir_iters_solve = it;
+        c->ir_resid_solve = last;
+        if (st != RMRCM_OK) return st;
+        HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
+    } else {
+        HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
+    }
+    TRY(mark(c, 6));
+    for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
+    TRY(mark(c, 7));
+    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    TRY(mark(c, 8));
+    HIP_TRY(rmrcm::launch_reconstruct(c));
+    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
+    TRY(mark(c, 9));
+    return RMRCM_OK;
+}
+
+int solve_outputs(rmrcm_ctx* c, double* pressure, double* flux) {
+    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+    HIP_TRY(hipMemcpyAsync(pressure, c->pout, ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    HIP_TRY(hipMemcpyAsync(flux, c->fout, 4 * ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    TRY(mark(c, 10));
+    return RMRCM_OK;
 }
 
 }  // namespace
@@ -453,7 +521,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
         (r = dalloc(c, &c->q, ncell)) || (r = dalloc(c, &c->bcv, nbf)) ||
         (r = dalloc(c, &c->pout, ncell)) || (r = dalloc(c, &c->fout, 4 * ncell)) ||
         (r = dalloc(c, &c->Uout, g.nseg)) || (r = dalloc(c, &c->Pout, g.nseg)) ||
-        (r = dalloc(c, &c->flags, 4)) || (r = dalloc(c, &c->gauge, 256)) ||
+        (r = dalloc(c, &c->flags, rmrcm::kNumFlags)) || (r = dalloc(c, &c->gauge, 256)) ||
         (r = dalloc(c, &c->dscal, 1)))
         return fail(r);
     if (prm->precision != RMRCM_FP64) {
@@ -504,38 +572,9 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
         for (double v : hb) s -= v, sa += std::fabs(v);
         if (!(std::fabs(s) <= 1e-12 * sa + 1e-300)) return RMRCM_EINVAL;
     }
-    HIP_TRY(hipEventRecord(c->ev[4], c->stream));
-    if (source) {
-        HIP_TRY(hipMemcpyAsync(c->q, source, ncell * sizeof(double), hipMemcpyDefault, c->stream));
-    } else {
-        HIP_TRY(hipMemsetAsync(c->q, 0, ncell * sizeof(double), c->stream));
-    }
-    HIP_TRY(hipMemcpyAsync(c->bcv, bc_value, nbf * sizeof(double), hipMemcpyDefault, c->stream));
-    HIP_TRY(hipEventRecord(c->ev[5], c->stream));
-    if (mixed(c)) {
-        HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 0, 0));
-        if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));
-        int it = 0;
-        double last = 0.0;
-        const int st = refine_loop(c, 1, &it, &last);
-        c->ir_iters_solve = it;
-        c->ir_resid_solve = last;
-        if (st != RMRCM_OK) return st;
-        HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
-    } else {
-        HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
-    }
-    HIP_TRY(hipEventRecord(c->ev[6], c->stream));
-    for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
-    HIP_TRY(hipEventRecord(c->ev[7], c->stream));
-    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
-    HIP_TRY(hipEventRecord(c->ev[8], c->stream));
-    HIP_TRY(rmrcm::launch_reconstruct(c));
-    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
-    HIP_TRY(hipEventRecord(c->ev[9], c->stream));
-    HIP_TRY(hipMemcpyAsync(pressure, c->pout, ncell * sizeof(double), hipMemcpyDefault, c->stream));
-    HIP_TRY(hipMemcpyAsync(flux, c->fout, 4 * ncell * sizeof(double), hipMemcpyDefault, c->stream));
-    HIP_TRY(hipEventRecord(c->ev[10], c->stream));
+    TRY(solve_inputs(c, source, bc_value));
+    TRY(enqueue_solve(c));
+    TRY(solve_outputs(c, pressure, flux));
     c->solve_recorded = true;
     const bool host_out = !is_device_ptr(pressure) || !is_device_ptr(flux);
     c->solved = true;
@@ -631,6 +670,353 @@ void rmrcm_destroy(rmrcm_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
+}
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, int> g_tune_cache;   // (g, nslot, nnodes, ld) -> column tile
+}  // namespace
+
+int rmrcm_autotune(rmrcm_ctx* c) {
+    if (!c) return RMRCM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int d = 1; d < c->D; ++d) {
+        if (!rmrcm::merge_apply_tunable(c, d)) continue;
+        const Level& L = c->levels[d];
+        const std::array<int, 4> key{L.g, L.nslot, L.nnodes, L.ld};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                c->ct_tune[d] = it->second;
+                continue;
+            }
+        }
+        int best = 0;
+        float bt = 1e30f;
+        for (int ct : {4, 8, 16}) {
+            HIP_TRY(rmrcm::launch_merge_apply(c, d, ct));      // warm-up
+            HIP_TRY(hipEventRecord(c->ev[11], c->stream));
+            for (int r = 0; r < 3; ++r) HIP_TRY(rmrcm::launch_merge_apply(c, d, ct));
+            HIP_TRY(hipEventRecord(c->ev[12], c->stream));
+            HIP_TRY(hipEventSynchronize(c->ev[12]));
+            const float ms = elapsed(c->ev[11], c->ev[12]);
+            if (ms >= 0.f && ms < bt) {
+                bt = ms;
+                best = ct;
+            }
+        }
+        c->ct_tune[d] = best;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    return RMRCM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+struct rmrcm_batch {
+    int device = 0;
+    std::vector<rmrcm_ctx*> m;             // members
+    std::vector<int> order;                // largest member first
+    std::vector<hipGraphExec_t> gsetup;    // per member (null: enqueued eagerly)
+    std::vector<hipGraphExec_t> gsolve;
+    std::vector<hipStream_t> streams;      // pool
+    int nstreams = 1;
+    hipStream_t master = nullptr;
+    hipEvent_t e[4] = {};                  // refactor start/end, solve start/end
+    std::vector<hipEvent_t> done;          // per pool stream
+    bool ref_recorded = false, sol_recorded = false;
+    int64_t cells = 0, local_solves = 0;
+    size_t device_bytes = 0;
+    int graphs = 0;
+};
+
+namespace {
+
+constexpr int kMaxStreams = 16;
+
+void batch_free(rmrcm_batch* b) {
+    (void)hipSetDevice(b->device);
+    if (b->master) (void)hipStreamSynchronize(b->master);
+    for (hipStream_t s : b->streams) (void)hipStreamSynchronize(s);
+    for (auto g : b->gsetup)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (auto g : b->gsolve)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (rmrcm_ctx* c : b->m) {
+        if (c) c->stream = c->own_stream;
+        rmrcm_destroy(c);
+    }
+    for (hipEvent_t e : b->done)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->e)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+    if (b->master) (void)hipStreamDestroy(b->master);
+    delete b;
+}
+
+// Capture one member's enqueued work into an executable graph.
+template <typename F>
+int capture(rmrcm_ctx* c, hipStream_t cap, F enqueue, hipGraphExec_t* out) {
+    *out = nullptr;
+    hipStream_t saved = c->stream;
+    c->stream = cap;
+    c->capturing = true;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        c->stream = saved;
+        c->capturing = false;
+        return RMRCM_EDEVICE;
+    }
+    const int r = enqueue(c);
+    const hipError_t e = hipStreamEndCapture(cap, &graph);
+    c->stream = saved;
+    c->capturing = false;
+    if (r != RMRCM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess) return RMRCM_EDEVICE;
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    return ei == hipSuccess ? RMRCM_OK : RMRCM_EDEVICE;
+}
+
+// Fork: every pool stream in use waits for the master; join: the master
+// waits for every pool stream.
+int fork_streams(rmrcm_batch* b, hipEvent_t start) {
+    HIP_TRY(hipEventRecord(start, b->master));
+    for (int k = 0; k < b->nstreams; ++k) HIP_TRY(hipStreamWaitEvent(b->streams[k], start, 0));
+    return RMRCM_OK;
+}
+
+int join_streams(rmrcm_batch* b, hipEvent_t end) {
+    for (int k = 0; k < b->nstreams; ++k) {
+        HIP_TRY(hipEventRecord(b->done[k], b->streams[k]));
+        HIP_TRY(hipStreamWaitEvent(b->master, b->done[k], 0));
+    }
+    HIP_TRY(hipEventRecord(end, b->master));
+    return RMRCM_OK;
+}
+
+int batch_refactor(rmrcm_batch* b, const double* const* perms) {
+    TRY(fork_streams(b, b->e[0]));
+    for (size_t r = 0; r < b->order.size(); ++r) {
+        const int i = b->order[r];
+        rmrcm_ctx* c = b->m[i];
+        c->stream = b->streams[r % b->nstreams];
+        c->solved = false;
+        if (perms && perms[i]) {
+            const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+            HIP_TRY(hipMemcpyAsync(c->K, perms[i], ncell * sizeof(double), hipMemcpyDefault, c->stream));
+        }
+        if (b->gsetup[i]) {
+            HIP_TRY(hipGraphLaunch(b->gsetup[i], c->stream));
+        } else {
+            TRY(enqueue_setup(c));
+        }
+        c->setup_recorded = !b->gsetup[i];
+        c->check_pending = true;
+    }
+    TRY(join_streams(b, b->e[1]));
+    b->ref_recorded = true;
+    return RMRCM_OK;
+}
+
+int batch_solve(rmrcm_batch* b, const double* const* sources, const double* const* bcv,
+                double* const* pressures, double* const* fluxes) {
+    TRY(fork_streams(b, b->e[2]));
+    for (size_t r = 0; r < b->order.size(); ++r) {
+        const int i = b->order[r];
+        rmrcm_ctx* c = b->m[i];
+        c->stream = b->streams[r % b->nstreams];
+        if (bcv) TRY(solve_inputs(c, sources ? sources[i] : nullptr, bcv[i]));
+        if (b->gsolve[i]) {
+            HIP_TRY(hipGraphLaunch(b->gsolve[i], c->stream));
+        } else {
+            TRY(enqueue_solve(c));
+        }
+        if (pressures && fluxes) TRY(solve_outputs(c, pressures[i], fluxes[i]));
+        c->solve_recorded = !b->gsolve[i];
+        c->solved = true;
+    }
+    TRY(join_streams(b, b->e[3]));
+    b->sol_recorded = true;
+    return RMRCM_OK;
+}
+
+// Pick the number of pool streams by timing one refactor + solve pass of
+// the whole batch for each candidate.
+int tune_streams(rmrcm_batch* b) {
+    const int cands[] = {1, 2, 4, 8, 16};
+    int best = b->nstreams;
+    float bt = 1e30f;
+    for (int ns : cands) {
+        if (ns > (int)b->m.size() || ns > kMaxStreams) break;
+        b->nstreams = ns;
+        for (int rep = 0; rep < 2; ++rep) {     // the first pass warms up
+            TRY(batch_refactor(b, nullptr));
+            TRY(batch_solve(b, nullptr, nullptr, nullptr, nullptr));
+        }
+        HIP_TRY(hipEventSynchronize(b->e[3]));
+        const float ms = elapsed(b->e[0], b->e[3]);
+        if (ms >= 0.f && ms < bt) {
+            bt = ms;
+            best = ns;
+        }
+    }
+    b->nstreams = best;
+    return RMRCM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* const* perms,
+                       const int8_t* const* bc_types, int32_t autotune, rmrcm_batch** out) {
+    if (!out) return RMRCM_EINVAL;
+    *out = nullptr;
+    if (count <= 0 || !prms || !perms || !bc_types) return RMRCM_EINVAL;
+    for (int i = 0; i < count; ++i)
+        if (prms[i].device != prms[0].device || !perms[i] || !bc_types[i]) return RMRCM_EINVAL;
+    rmrcm_batch* b = new (std::nothrow) rmrcm_batch();
+    if (!b) return RMRCM_ENOMEM;
+    b->device = prms[0].device;
+    b->m.assign(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        const int r = rmrcm_setup(&prms[i], perms[i], bc_types[i], &b->m[i]);
+        if (r != RMRCM_OK) {
+            batch_free(b);
+            return r;
+        }
+        const rmrcm_ctx* c = b->m[i];
+        b->cells += (int64_t)c->geo.nx * c->geo.ny;
+        b->local_solves += c->n_local_solves;
+        b->device_bytes += c->device_bytes;
+    }
+    if (hipSetDevice(b->device) != hipSuccess) {
+        batch_free(b);
+        return RMRCM_EDEVICE;
+    }
+    // largest local work first (cells x subdomain width ~ band-Cholesky flops)
+    b->order.resize(count);
+    for (int i = 0; i < count; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+        const rmrcm_ctx* a = b->m[x];
+        const rmrcm_ctx* c = b->m[y];
+        return (int64_t)a->geo.nx * a->geo.ny * a->geo.bx > (int64_t)c->geo.nx * c->geo.ny * c->geo.bx;
+    });
+    auto fail = [&](int r) {
+        batch_free(b);
+        return r;
+    };
+    if (hipStreamCreateWithFlags(&b->master, hipStreamNonBlocking) != hipSuccess) return fail(RMRCM_EDEVICE);
+    b->streams.assign(kMaxStreams, nullptr);
+    b->done.assign(kMaxStreams, nullptr);
+    for (int k = 0; k < kMaxStreams; ++k)
+        if (hipStreamCreateWithFlags(&b->streams[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreate(&b->done[k]) != hipSuccess)
+            return fail(RMRCM_EDEVICE);
+    for (auto& e : b->e)
+        if (hipEventCreate(&e) != hipSuccess) return fail(RMRCM_EDEVICE);
+    if (autotune)
+        for (rmrcm_ctx* c : b->m) {
+            const int r = rmrcm_autotune(c);
+            if (r != RMRCM_OK) return fail(r);
+        }
+    // graphs of the FP64 members (the mixed path synchronises with the host
+    // between refinement passes and is enqueued eagerly)
+    b->gsetup.assign(count, nullptr);
+    b->gsolve.assign(count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        rmrcm_ctx* c = b->m[i];
+        if (mixed(c)) continue;
+        int r = capture(c, b->streams[0], enqueue_setup, &b->gsetup[i]);
+        if (r == RMRCM_OK) r = capture(c, b->streams[0], enqueue_solve, &b->gsolve[i]);
+        if (r != RMRCM_OK) return fail(r);
+        ++b->graphs;
+    }
+    b->nstreams = count < 4 ? count : 4;
+    if (autotune) {
+        const int r = tune_streams(b);
+        if (r != RMRCM_OK) return fail(r);
+    }
+    if (hipStreamSynchronize(b->master) != hipSuccess) return fail(RMRCM_EDEVICE);
+    for (rmrcm_ctx* c : b->m) c->check_pending = false;
+    *out = b;
+    return RMRCM_OK;
+}
+
+int rmrcm_batch_refactor(rmrcm_batch* b, const double* const* perms) {
+    if (!b || !perms) return RMRCM_EINVAL;
+    for (size_t i = 0; i < b->m.size(); ++i)
+        if (!perms[i]) return RMRCM_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return RMRCM_EDEVICE;
+    return batch_refactor(b, perms);
+}
+
+int rmrcm_batch_solve(rmrcm_batch* b, const double* const* sources, const double* const* bc_values,
+                      double* const* pressures, double* const* fluxes) {
+    if (!b || !bc_values || !pressures || !fluxes) return RMRCM_EINVAL;
+    for (size_t i = 0; i < b->m.size(); ++i)
+        if (!bc_values[i] || !pressures[i] || !fluxes[i]) return RMRCM_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return RMRCM_EDEVICE;
+    return batch_solve(b, sources, bc_values, pressures, fluxes);
+}
+
+int rmrcm_batch_sync(rmrcm_batch* b, int32_t* status) {
+    if (!b) return RMRCM_EINVAL;
+    if (hipSetDevice(b->device) != hipSuccess) return RMRCM_EDEVICE;
+    HIP_TRY(hipStreamSynchronize(b->master));
+    int first = RMRCM_OK;
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        rmrcm_ctx* c = b->m[i];
+        c->check_pending = false;
+        const int r = check_flags(c);
+        if (status) status[i] = r;
+        if (first == RMRCM_OK) first = r;
+    }
+    return first;
+}
+
+int rmrcm_batch_get_stats(rmrcm_batch* b, char* json, size_t cap) {
+    if (!b) return RMRCM_EINVAL;
+    (void)hipSetDevice(b->device);
+    float tr = -1.f, ts = -1.f;
+    if (b->ref_recorded && hipEventSynchronize(b->e[1]) == hipSuccess) tr = elapsed(b->e[0], b->e[1]);
+    if (b->sol_recorded && hipEventSynchronize(b->e[3]) == hipSuccess) ts = elapsed(b->e[2], b->e[3]);
+    std::string ct = "[";
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        const rmrcm_ctx* c = b->m[i];
+        ct += i ? ", [" : "[";
+        for (int d = 1; d < c->D; ++d) ct += (d > 1 ? ", " : "") + std::to_string(c->ct_tune[d]);
+        ct += "]";
+    }
+    ct += "]";
+    std::string buf = "{\"members\": " + std::to_string(b->m.size()) +
+                      ", \"streams\": " + std::to_string(b->nstreams) +
+                      ", \"graph_members\": " + std::to_string(b->graphs) +
+                      ", \"cells\": " + std::to_string(b->cells) +
+                      ", \"local_solves\": " + std::to_string(b->local_solves) +
+                      ", \"device_bytes\": " + std::to_string(b->device_bytes) +
+                      ", \"refactor_ms\": " + std::to_string(tr) +
+                      ", \"solve_ms\": " + std::to_string(ts) +
+                      ", \"merge_column_tiles\": " + ct + "}";
+    if (json && cap > 0) {
+        std::strncpy(json, buf.c_str(), cap - 1);
+        json[cap - 1] = '\0';
+    }
+    return (int)buf.size() + 1;
+}
+
+void rmrcm_batch_destroy(rmrcm_batch* b) {
+    if (b) batch_free(b);
 }
 
 }  // extern "C"

@@ -816,14 +816,27 @@ static hipError_t qd_factor(rmrcm_ctx* c, const MergeArgs& a) {
 }
 
 template <int GT>
-static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace) {
-    constexpr int CT = qd_ct<GT>();
-    if (ncol == 1)
-        hipLaunchKernelGGL((k_qd_apply<GT, 1>), dim3(a.nnodes, 1), dim3(256), 0, c->stream, a, col0,
-                           ncol);
-    else
-        hipLaunchKernelGGL((k_qd_apply<GT, CT>), dim3(a.nnodes, (ncol + CT - 1) / CT), dim3(256), 0,
-                           c->stream, a, col0, ncol);
+static hipError_t qd_apply(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, int ct) {
+    if (ncol == 1) ct = 1;
+    else if (ct <= 0) ct = qd_ct<GT>();
+    if (GT >= 128 && ct > 8) ct = 8;           // LDS: the 128-segment block fills most of it
+    const dim3 grid(a.nnodes, (ncol + ct - 1) / ct);
+    switch (ct) {
+        case 1: hipLaunchKernelGGL((k_qd_apply<GT, 1>), grid, dim3(256), 0, c->stream, a, col0, ncol); break;
+        case 4: hipLaunchKernelGGL((k_qd_apply<GT, 4>), grid, dim3(256), 0, c->stream, a, col0, ncol); break;
+        case 8: hipLaunchKernelGGL((k_qd_apply<GT, 8>), grid, dim3(256), 0, c->stream, a, col0, ncol); break;
+        default:
+            hipLaunchKernelGGL((k_qd_apply<GT, (GT >= 128 ? 8 : 16)>),
+                               dim3(a.nnodes, (ncol + (GT >= 128 ? 8 : 16) - 1) / (GT >= 128 ? 8 : 16)),
+                               dim3(256), 0, c->stream, a, col0, ncol);
+    }
+    return hipGetLastError();
+}
+
+template <int GT>
+static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace, int ct) {
+    hipError_t e = qd_apply<GT>(c, a, col0, ncol, ct);
+    if (e != hipSuccess) return e;
     if (trace)
         hipLaunchKernelGGL(k_qd_trace<GT>,
                            dim3(a.nnodes, (a.nslot + kTRR - 1) / kTRR, (ncol + kTRC - 1) / kTRC),
@@ -841,12 +854,29 @@ static hipError_t qd_factor_any(rmrcm_ctx* c, const MergeArgs& a) {
     return hipErrorInvalidValue;
 }
 
-static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace) {
+static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace,
+                                 int ct) {
     switch (qd_tier(a.g)) {
-        case 16: return qd_columns<16>(c, a, col0, ncol, trace);
-        case 32: return qd_columns<32>(c, a, col0, ncol, trace);
-        case 64: return qd_columns<64>(c, a, col0, ncol, trace);
-        case 128: return qd_columns<128>(c, a, col0, ncol, trace);
+        case 16: return qd_columns<16>(c, a, col0, ncol, trace, ct);
+        case 32: return qd_columns<32>(c, a, col0, ncol, trace, ct);
+        case 64: return qd_columns<64>(c, a, col0, ncol, trace, ct);
+        case 128: return qd_columns<128>(c, a, col0, ncol, trace, ct);
+    }
+    return hipErrorInvalidValue;
+}
+
+bool merge_apply_tunable(rmrcm_ctx* c, int d) {
+    return d > 0 && d < c->D && qd_tier(c->levels[d].g) != 0;
+}
+
+hipError_t launch_merge_apply(rmrcm_ctx* c, int d, int ct) {
+    if (!merge_apply_tunable(c, d)) return hipErrorInvalidValue;
+    MergeArgs a = make_args(c, d);
+    switch (qd_tier(a.g)) {
+        case 16: return qd_apply<16>(c, a, 0, a.nslot, ct);
+        case 32: return qd_apply<32>(c, a, 0, a.nslot, ct);
+        case 64: return qd_apply<64>(c, a, 0, a.nslot, ct);
+        case 128: return qd_apply<128>(c, a, 0, a.nslot, ct);
     }
     return hipErrorInvalidValue;
 }
@@ -857,7 +887,7 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d) {
     if (qd_tier(a.g)) {
         hipError_t e = qd_factor_any(c, a);
         if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
-        return qd_columns_any(c, a, 0, a.nslot, true);
+        return qd_columns_any(c, a, 0, a.nslot, true, c->ct_tune[d]);
     }
     hipLaunchKernelGGL(k_merge_assemble, dim3(a.nnodes, (a.xi * a.xi + 255) / 256), dim3(256), 0,
                        c->stream, a);
@@ -877,7 +907,7 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d) {
 hipError_t launch_merge_particular(rmrcm_ctx* c, int d) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
-    if (qd_tier(a.g)) return qd_columns_any(c, a, a.nslot, 1, d != 0);
+    if (qd_tier(a.g)) return qd_columns_any(c, a, a.nslot, 1, d != 0, 1);
     hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi + 255) / 256), dim3(256), 0, c->stream, a,
                        a.nslot, 1);
     hipError_t e = solve_cols_generic(c, a, a.nslot, 1);

@@ -141,6 +141,64 @@ __global__ __launch_bounds__(256) void k_pressure_shift(double* __restrict__ p, 
     }
 }
 
+// Plain fills (used instead of memset nodes, so that enqueued work can be
+// captured in a graph).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ p, size_t n, T v) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
+}
+
+// Compatibility of all-Neumann data (net source = net prescribed outflow),
+// checked on the device: one workgroup, fixed summation order.
+__global__ __launch_bounds__(1024) void k_compat(const double* __restrict__ q, size_t ncell,
+                                                 const double* __restrict__ bcv, size_t nbf,
+                                                 int* __restrict__ flags) {
+    __shared__ double s1[1024], s2[1024];
+    double a = 0.0, b = 0.0;
+    for (size_t t = threadIdx.x; t < ncell; t += 1024) {
+        a += q[t];
+        b += fabs(q[t]);
+    }
+    for (size_t t = threadIdx.x; t < nbf; t += 1024) {
+        a -= bcv[t];
+        b += fabs(bcv[t]);
+    }
+    s1[threadIdx.x] = a;
+    s2[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            s1[threadIdx.x] += s1[threadIdx.x + w];
+            s2[threadIdx.x] += s2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flags[FLAG_BAD_DATA] = (fabs(s1[0]) <= 1e-12 * s2[0] + 1e-300) ? 0 : 1;
+}
+
+static unsigned fill_blocks(size_t n) {
+    const size_t b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : b > 4096 ? 4096 : b);
+}
+
+hipError_t launch_fill_i32(rmrcm_ctx* c, int* p, size_t n, int v) {
+    hipLaunchKernelGGL(k_fill<int>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(rmrcm_ctx* c, double* p, size_t n, double v) {
+    hipLaunchKernelGGL(k_fill<double>, dim3(fill_blocks(n)), dim3(256), 0, c->stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_compat_check(rmrcm_ctx* c) {
+    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+    const size_t nbf = 2 * (size_t)c->geo.nx + 2 * (size_t)c->geo.ny;
+    hipLaunchKernelGGL(k_compat, dim3(1), dim3(1024), 0, c->stream, c->q, ncell, c->bcv, nbf, c->flags);
+    return hipGetLastError();
+}
+
 hipError_t launch_gauge(rmrcm_ctx* c) {
     const size_t n = (size_t)c->geo.nx * c->geo.ny;
     hipLaunchKernelGGL(k_pressure_partial, dim3(kGB), dim3(256), 0, c->stream, c->pout, n, c->gauge);

@@ -70,6 +70,8 @@ struct rmrcm_ctx {
     bool check_pending = false;   // device-detected errors of an asynchronous refactor
     bool setup_recorded = false;
     bool solve_recorded = false;
+    bool capturing = false;       // enqueueing into a graph capture: no events, no host sync
+    int ct_tune[32] = {};         // per depth: column tile of the merge apply (0 = default)
     // device arrays
     double* K = nullptr;                     // [ny][nx]
     int8_t* bct = nullptr;                   // [2ny + 2nx]
@@ -91,7 +93,7 @@ struct rmrcm_ctx {
     double* fout = nullptr;
     double* Uout = nullptr;
     double* Pout = nullptr;
-    int* flags = nullptr;                    // [4] device error flags
+    int* flags = nullptr;                    // [kNumFlags] device error flags
     double* gauge = nullptr;                 // partial sums of the zero-mean gauge
     std::vector<rmrcm::Level> levels;        // index = depth
     size_t device_bytes = 0;
@@ -122,8 +124,16 @@ hipError_t launch_down(rmrcm_ctx* c, int depth);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
 hipError_t launch_interface_values(rmrcm_ctx* c);
 hipError_t launch_gauge(rmrcm_ctx* c);
+hipError_t launch_fill_i32(rmrcm_ctx* c, int* p, size_t n, int v);
+hipError_t launch_fill_f64(rmrcm_ctx* c, double* p, size_t n, double v);
+hipError_t launch_compat_check(rmrcm_ctx* c);
+// Merge apply of the basis columns of one depth with column tile ct (the
+// autotuner times it; ct in {4, 8, 16}).
+hipError_t launch_merge_apply(rmrcm_ctx* c, int depth, int ct);
+bool merge_apply_tunable(rmrcm_ctx* c, int depth);
 
 // Device error flag slots.
-enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2, FLAG_FALLBACK = 3 };
+enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2, FLAG_FALLBACK = 3,
+       FLAG_BAD_DATA = 4, kNumFlags = 8 };
 
 }  // namespace rmrcm

@@ -48,7 +48,8 @@ EXPORTS = [
     "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve",
     "rmrcm_get_interface",
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
-    "rmrcm_strerror",
+    "rmrcm_strerror", "rmrcm_autotune", "rmrcm_batch_create", "rmrcm_batch_refactor",
+    "rmrcm_batch_solve", "rmrcm_batch_sync", "rmrcm_batch_get_stats", "rmrcm_batch_destroy",
 ]
 
 
@@ -85,6 +86,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_destroy.restype = None
     lib.rmrcm_strerror.argtypes = [ctypes.c_int]
     lib.rmrcm_strerror.restype = ctypes.c_char_p
+    lib.rmrcm_autotune.argtypes = [vp]
+    lib.rmrcm_autotune.restype = ctypes.c_int
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    lib.rmrcm_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(rmrcm_params), pp, pp,
+                                       ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.rmrcm_batch_create.restype = ctypes.c_int
+    lib.rmrcm_batch_refactor.argtypes = [vp, pp]
+    lib.rmrcm_batch_refactor.restype = ctypes.c_int
+    lib.rmrcm_batch_solve.argtypes = [vp, pp, pp, pp, pp]
+    lib.rmrcm_batch_solve.restype = ctypes.c_int
+    lib.rmrcm_batch_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.rmrcm_batch_sync.restype = ctypes.c_int
+    lib.rmrcm_batch_get_stats.argtypes = [vp, ctypes.c_char_p, ctypes.c_size_t]
+    lib.rmrcm_batch_get_stats.restype = ctypes.c_int
+    lib.rmrcm_batch_destroy.argtypes = [vp]
+    lib.rmrcm_batch_destroy.restype = None
     return lib
 
 
@@ -180,6 +197,95 @@ def rmrcm_strerror(status: int) -> str:
     return lib().rmrcm_strerror(status).decode()
 
 
+def rmrcm_autotune(ctx):
+    _check(lib().rmrcm_autotune(ctx), "rmrcm_autotune")
+
+
+def _ptr_array(items, dtype):
+    """ctypes array of raw pointers (None allowed) plus the objects kept alive."""
+    keep, raw = [], []
+    for a in items:
+        p, k = _ptr(a, dtype)
+        keep.append(k)
+        raw.append(p.value if p is not None else None)
+    return (ctypes.c_void_p * len(raw))(*raw), keep
+
+
+class Batch:
+    """An ensemble of independent problems enqueued together (see
+    rmrcm_batch_create): refactor / solve all members, then sync."""
+
+    def __init__(self, problems, precision=RMRCM_FP64, autotune=True, device=0):
+        self.problems = list(problems)
+        n = len(self.problems)
+        prms = (rmrcm_params * n)()
+        for i, pr in enumerate(self.problems):
+            p = rmrcm_default_params()
+            p.nx, p.ny, p.lx, p.ly = pr.nx, pr.ny, pr.lx, pr.ly
+            p.sub_nx, p.sub_ny, p.seg, p.alpha = pr.sub_nx, pr.sub_ny, pr.seg, pr.alpha
+            p.precision, p.device = precision, device
+            prms[i] = p
+        kp, self._k = _ptr_array([pr.K for pr in self.problems], np.float64)
+        tp, self._t = _ptr_array([pr.bc_type for pr in self.problems], np.int8)
+        b = ctypes.c_void_p()
+        _check(lib().rmrcm_batch_create(n, prms, ctypes.cast(kp, ctypes.POINTER(ctypes.c_void_p)),
+                                        ctypes.cast(tp, ctypes.POINTER(ctypes.c_void_p)),
+                                        1 if autotune else 0, ctypes.byref(b)),
+               "rmrcm_batch_create")
+        self.b = b
+        self._keep = []
+
+    def refactor(self, perms):
+        kp, keep = _ptr_array(perms, np.float64)
+        self._keep = [keep]
+        _check(lib().rmrcm_batch_refactor(self.b, ctypes.cast(kp, ctypes.POINTER(ctypes.c_void_p))),
+               "rmrcm_batch_refactor")
+
+    def solve(self, sources, bc_values, pressures=None, fluxes=None, wait=True):
+        """Enqueue every member's solve; with wait, sync and return the
+        (pressure, flux) arrays."""
+        if pressures is None:
+            pressures = [np.zeros((pr.ny, pr.nx)) for pr in self.problems]
+        if fluxes is None:
+            fluxes = [np.zeros((4, pr.ny, pr.nx)) for pr in self.problems]
+        sp, k1 = _ptr_array(sources, np.float64)
+        bp, k2 = _ptr_array(bc_values, np.float64)
+        pp, k3 = _ptr_array(pressures, np.float64)
+        fp, k4 = _ptr_array(fluxes, np.float64)
+        self._keep.append((k1, k2, k3, k4))
+        cast = lambda a: ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p))  # noqa: E731
+        _check(lib().rmrcm_batch_solve(self.b, cast(sp), cast(bp), cast(pp), cast(fp)),
+               "rmrcm_batch_solve")
+        if wait:
+            self.sync()
+        return pressures, fluxes
+
+    def sync(self):
+        st = (ctypes.c_int32 * len(self.problems))()
+        r = lib().rmrcm_batch_sync(self.b, st)
+        self._keep = []
+        if r != RMRCM_OK:
+            raise RMRCMError(r, "rmrcm_batch_sync (member statuses %s)" % list(st))
+        return list(st)
+
+    def stats(self) -> dict:
+        need = lib().rmrcm_batch_get_stats(self.b, None, 0)
+        buf = ctypes.create_string_buffer(need)
+        lib().rmrcm_batch_get_stats(self.b, buf, need)
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            lib().rmrcm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One setup (permeability + boundary-condition types), many solves."""
 
@@ -229,6 +335,9 @@ class Solver:
 
     def set_stream(self, handle):
         rmrcm_set_stream(self.ctx, handle)
+
+    def autotune(self):
+        rmrcm_autotune(self.ctx)
 
     def stats(self):
         return rmrcm_get_stats(self.ctx)
