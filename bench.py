@@ -131,6 +131,48 @@ def cpu_baseline(prob, budget_s=30.0):
                       % (prob.nx, prob.ny, reps, t)}
 
 
+def ensemble_bench(nmem, steps, warmup):
+    """Throughput of an ensemble batch (members 0..nmem-1 of the five-spot
+    ensemble: n in {128,256,512}^2, b in {8,16,32}), inputs and outputs
+    resident on the device; one step = refactor + solve of every member."""
+    import torch
+    from paper_2009_07965_amd import Batch
+    from workloads import ensemble_member
+    t0 = time.perf_counter()
+    probs = [ensemble_member(m) for m in range(nmem)]
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    Ks = [torch.from_numpy(p.K).to(dev) for p in probs]
+    qs = [torch.from_numpy(p.q).to(dev) for p in probs]
+    bvs = [torch.from_numpy(p.bc_value).to(dev) for p in probs]
+    Ps = [torch.zeros((p.ny, p.nx), dtype=torch.float64, device=dev) for p in probs]
+    Fs = [torch.zeros((4, p.ny, p.nx), dtype=torch.float64, device=dev) for p in probs]
+    t0 = time.perf_counter()
+    B = Batch(probs, autotune=True)
+    t_create = time.perf_counter() - t0
+    try:
+        for _ in range(warmup):
+            B.refactor(Ks)
+            B.solve(qs, bvs, Ps, Fs, wait=False)
+        B.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.refactor(Ks)
+            B.solve(qs, bvs, Ps, Fs, wait=False)
+        B.sync()
+        dt = (time.perf_counter() - t0) / steps
+        st = B.stats()
+    finally:
+        B.close()
+    cells = sum(p.ncells for p in probs)
+    return {"members": nmem, "cells": cells, "ms_per_step": dt * 1e3,
+            "cells_per_s": cells / dt, "local_solves_per_s": st["local_solves"] / dt,
+            "streams": st["streams"], "graph_members": st["graph_members"],
+            "refactor_ms_events": st["refactor_ms"], "solve_ms_events": st["solve_ms"],
+            "sizes": "n in {128,256,512}^2, b in {8,16,32}, seg b/4, all no-flow, five-spot wells",
+            "setup_s": t_create, "generate_s": t_gen}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +183,8 @@ def main():
                          "path is always measured beside it")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ensemble", type=int, default=64,
+                    help="members of the ensemble batch measured beside the main line (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the method's single-GPU path is the "
@@ -261,6 +305,8 @@ def main():
                                                   "fp64_fallback_subdomains")},
         "roofline": roof,
     }
+    if args.ensemble > 0:
+        out["ensemble"] = ensemble_bench(args.ensemble, max(3, args.steps // 4), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
