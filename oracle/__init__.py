@@ -28,6 +28,9 @@ formulation and parallel implementation of multiscale mixed methods"):
 * ``recursive``  — O-5: Algorithm 1 (recursive formulation, Section 3)
                    over the nested binary hierarchy.
 * ``metrics``    — norms and conservation / interface-equation residuals.
+* ``cnn``        — the local-basis surrogate network (forward, loss,
+                   gradients, input features) in FP64, for checking the GPU
+                   training and inference kernels.
 
 Every floating-point value is float64.  Parity status of each function is
 stated in its docstring; all are pinned by the ``-m "not gpu"`` tests.
