@@ -67,7 +67,17 @@ enum {
  * FP64.  RMRCM_MIXED: local factorisations and sweeps in FP32, accuracy
  * recovered by iterative refinement with FP64 residuals (the basis and the
  * particular solutions are stored in FP64); subdomains whose refinement
- * does not reach ir_tol are factored again in FP64. */
+ * does not reach ir_tol are factored again in FP64.
+ * RMRCM_MIXED_LEARNED: as RMRCM_MIXED, but the local basis of every
+ * interior subdomain (no face on the outer boundary) is first predicted by
+ * the surrogate network loaded from cnn_weights (rmrcm_cnn_save format,
+ * patch side = sub_nx = sub_ny, outputs = boundary segments per subdomain).
+ * A prediction is accepted only when, for every basis column, the FP64
+ * residual of the local Robin system |A y - e|_2 / |e|_2 <= gate_tol; an
+ * accepted subdomain keeps the predicted basis and computes only its FP32
+ * factor (for its particular solutions), the others run the RMRCM_MIXED
+ * path.  gate_tol = 0 accepts nothing (the result is then that of
+ * RMRCM_MIXED). */
 enum { RMRCM_FP64 = 0, RMRCM_MIXED = 1, RMRCM_MIXED_LEARNED = 2 };
 
 enum { RMRCM_BC_NEUMANN = 0, RMRCM_BC_DIRICHLET = 1 };
@@ -86,8 +96,8 @@ typedef struct {
     int32_t ir_max_iter;     /* mixed: refinement passes before the subdomains still above
                                 ir_tol are redone in FP64 (setup) or ENOTCONV (solve);
                                 default 6 */
-    double gate_tol;         /* learned: residual gate tau */
-    const char* cnn_weights; /* learned: weight file or NULL */
+    double gate_tol;         /* learned: residual gate tau >= 0; default 1e-6 */
+    const char* cnn_weights; /* learned: weight file (required in that mode) */
     int32_t device;          /* HIP device ordinal */
 } rmrcm_params;
 
@@ -225,8 +235,61 @@ int rmrcm_batch_sync(rmrcm_batch* b, int32_t* status);
  * level.  Returns the length needed including the terminator. */
 int rmrcm_batch_get_stats(rmrcm_batch* b, char* json, size_t cap);
 
+/* Training pairs for the local-basis surrogate from a context's last
+ * setup (square subdomains only, else ENOTSUP): features (device, FP32
+ * [nsub][2][S][S], as the learned mode computes them), basis (host or
+ * device, FP64 [nsub][R][S*S], may be NULL: the exact local basis),
+ * interior (host [nsub], may be NULL: 1 when every boundary segment of the
+ * subdomain is a Robin segment).  Waits for the context's stream. */
+int rmrcm_export_local(rmrcm_ctx* ctx, float* features, double* basis, int32_t* interior);
+
 /* Release every member and the batch's streams and graphs. */
 void rmrcm_batch_destroy(rmrcm_batch* b);
+
+/* ---- Local-basis surrogate network -------------------------------------
+ * A small convolutional network mapping a subdomain's input features
+ * (2 channels of S x S: the centred log-permeability, and on boundary cells
+ * the log Robin parameter of the face's segment plus the mean
+ * log-permeability) to its R local basis fields, the solutions of the basis
+ * problems of Section 2.1 (R x S x S).  L 3x3 convolution layers of width
+ * C with zero padding and ReLU between them, plus a learned mean field per
+ * output.  FP32 compute and accumulation; convolution weights enter in
+ * bfloat16 (round to nearest even of FP32 master weights).  Parameter
+ * vector: per layer W [co][ci][3][3] then b [co]; then the mean field
+ * [R][S][S].  Feature, input and output arrays are device pointers,
+ * [n][channel][j][i] row-major, FP32.  Training is deterministic (fixed
+ * reduction order). */
+typedef struct rmrcm_cnn rmrcm_cnn;
+
+/* S in {8, 16, 32}; 1 <= C <= 32; 2 <= L <= 16; 1 <= R <= 32; max_batch:
+ * largest batch of a forward / training call.  Parameters start at zero:
+ * set them with rmrcm_cnn_set_params.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int rmrcm_cnn_create(int32_t S, int32_t C, int32_t L, int32_t R, int32_t max_batch, int32_t device,
+                     rmrcm_cnn** out);
+int rmrcm_cnn_num_params(const rmrcm_cnn* net, int64_t* n);
+/* Caller stream (NULL: the network's own).  Calls below are ordered on it. */
+int rmrcm_cnn_set_stream(rmrcm_cnn* net, void* hip_stream);
+/* Host FP32 parameter vector in / out; setting resets the Adam state.
+ * EINVAL for non-finite values. */
+int rmrcm_cnn_set_params(rmrcm_cnn* net, const float* theta);
+int rmrcm_cnn_get_params(rmrcm_cnn* net, float* theta);
+/* y[nb][R][S][S] = network(x[nb][2][S][S]); 1 <= nb <= max_batch. */
+int rmrcm_cnn_forward(rmrcm_cnn* net, int32_t nb, const float* x, float* y);
+/* Mean squared error against t[nb][R][S][S] and its gradient with respect
+ * to every parameter (through the rounded weights); loss (host, may be
+ * NULL) and grad (host, np values, may be NULL) are filled when the call
+ * returns. */
+int rmrcm_cnn_loss_grad(rmrcm_cnn* net, int32_t nb, const float* x, const float* t, double* loss,
+                        float* grad);
+/* loss_grad followed by one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected) of the master parameters with learning rate lr; loss
+ * (host) may be NULL, then the call does not wait for the device. */
+int rmrcm_cnn_train_step(rmrcm_cnn* net, int32_t nb, const float* x, const float* t, float lr,
+                         double* loss);
+/* Binary file: "RMRCMCNN", int32 S, C, L, R, int64 np, np FP32 parameters. */
+int rmrcm_cnn_save(rmrcm_cnn* net, const char* path);
+int rmrcm_cnn_load(const char* path, int32_t max_batch, int32_t device, rmrcm_cnn** out);
+void rmrcm_cnn_destroy(rmrcm_cnn* net);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,8 @@ binding raises on first use.
 from .rmrcm import (  # noqa: F401
     Solver,
     Batch,
+    Net,
+    rmrcm_export_local,
     rmrcm_autotune,
     RMRCMError,
     load_library,

@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "rmrcm_cnn.h"
 #include "rmrcm_internal.h"
 
 using rmrcm::Geo;
@@ -85,8 +86,11 @@ int validate(const rmrcm_params* p) {
     if (p->precision < RMRCM_FP64 || p->precision > RMRCM_MIXED_LEARNED) return RMRCM_EINVAL;
     if (p->sub_nx != 4 && p->sub_nx != 8 && p->sub_nx != 16 && p->sub_nx != 32) return RMRCM_ENOTSUP;
     if (p->sub_ny > 64) return RMRCM_ENOTSUP;
-    if (p->precision == RMRCM_MIXED_LEARNED) return RMRCM_ENOTSUP;
-    if (p->precision == RMRCM_MIXED && (!(p->ir_tol > 0) || p->ir_max_iter < 1)) return RMRCM_EINVAL;
+    if (p->precision != RMRCM_FP64 && (!(p->ir_tol > 0) || p->ir_max_iter < 1)) return RMRCM_EINVAL;
+    if (p->precision == RMRCM_MIXED_LEARNED) {
+        if (!p->cnn_weights || !(p->gate_tol >= 0)) return RMRCM_EINVAL;
+        if (p->sub_nx != p->sub_ny || p->sub_nx < 8) return RMRCM_ENOTSUP;
+    }
     // the basis block of one subdomain row must fit the local kernel's LDS
     const int R = 2 * (p->sub_nx + p->sub_ny) / p->seg;
     const size_t lds = sizeof(double) * (size_t)(3 * p->sub_nx * p->sub_nx + 2 * p->sub_nx * R + 4 * p->sub_nx);
@@ -256,6 +260,11 @@ void free_all(rmrcm_ctx* c) {
     f(c->Wsc);
     f(c->resid);
     f(c->fb);
+    f(c->lx);
+    f(c->ly);
+    f(c->lint);
+    if (c->net) rmrcm_cnn_destroy(c->net);
+    c->net = nullptr;
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -289,7 +298,7 @@ int refine_loop(rmrcm_ctx* c, int part, int* iters, double* last) {
     *last = 0.0;
     for (int it = 0; it < c->prm.ir_max_iter; ++it) {
         HIP_TRY(rmrcm::launch_local_refine(c, part, 1));
-        HIP_TRY(rmrcm::launch_max_resid(c, c->dscal));
+        HIP_TRY(rmrcm::launch_max_resid(c, part, c->dscal));
         double m = 0.0;
         HIP_TRY(hipMemcpyAsync(&m, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
@@ -303,10 +312,35 @@ int refine_loop(rmrcm_ctx* c, int part, int* iters, double* last) {
 // Local phase of the mixed-precision mode: FP32 factorisation and basis,
 // FP64-residual refinement, FP64 redo of the subdomains that do not reach
 // the tolerance, traces.
+bool learned(const rmrcm_ctx* c) { return c->prm.precision == RMRCM_MIXED_LEARNED; }
+
+// Learned mode: features of every subdomain, the surrogate's basis, and
+// the residual gate (fb = 2 for accepted subdomains, whose basis is then
+// the surrogate's; fb = 0 for the others).
+int surrogate_basis(rmrcm_ctx* c) {
+    const int nsub = c->geo.mx * c->geo.my;
+    const size_t n = (size_t)c->geo.bx * c->geo.by;
+    const int R = c->levels[c->D].nslot;
+    HIP_TRY(rmrcm::launch_features(c, c->lx, c->lint));
+    c->net->stream = c->stream;
+    for (int k = 0; k < nsub; k += c->net->maxnb) {
+        const int nb = nsub - k < c->net->maxnb ? nsub - k : c->net->maxnb;
+        HIP_TRY(rmrcm::cnn_forward(c->net, nb, c->lx + (size_t)k * 2 * n, c->ly + (size_t)k * R * n));
+    }
+    HIP_TRY(rmrcm::launch_gate(c, c->ly, c->lint, c->prm.gate_tol));
+    return RMRCM_OK;
+}
+
 int mixed_local_setup(rmrcm_ctx* c) {
     const int nsub = c->geo.mx * c->geo.my;
     HIP_TRY(rmrcm::launch_fill_i32(c, c->fb, nsub, 0));
-    HIP_TRY(rmrcm::launch_local_setup(c, true, nullptr, 0, 0));
+    if (learned(c)) {
+        TRY(surrogate_basis(c));
+        HIP_TRY(rmrcm::launch_local_setup(c, true, c->fb, 0, 0, 1));   // rejected: factor + basis
+        HIP_TRY(rmrcm::launch_local_setup(c, true, c->fb, 2, 0, 0));   // accepted: factor only
+    } else {
+        HIP_TRY(rmrcm::launch_local_setup(c, true, nullptr, 0, 0));
+    }
     int it = 0;
     double last = 0.0;
     const int st = refine_loop(c, 0, &it, &last);
@@ -325,6 +359,7 @@ int mixed_local_setup(rmrcm_ctx* c) {
         return st;
     }
     HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 0));
+    if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 2));
     return RMRCM_OK;
 }
 
@@ -385,6 +420,7 @@ int enqueue_solve(rmrcm_ctx* c) {
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_compat_check(c));
     if (mixed(c)) {
         HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 0, 0));
+        if (learned(c)) HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 2, 0));
         if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));
         int it = 0;
         double last = 0.0;
@@ -393,6 +429,7 @@ int enqueue_solve(rmrcm_ctx* c) {
         c->ir_resid_solve = last;
         if (st != RMRCM_OK) return st;
         HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
+        if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 2));
     } else {
         HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
     }
@@ -530,6 +567,14 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
             (r = dalloc(c, &c->fb, nsub)))
             return fail(r);
     }
+    if (prm->precision == RMRCM_MIXED_LEARNED) {
+        const int R = c->levels[c->D].nslot;
+        if ((r = rmrcm_cnn_load(prm->cnn_weights, 256, prm->device, &c->net)) != RMRCM_OK) return fail(r);
+        if (c->net->S != g.bx || c->net->R != R) return fail(RMRCM_EINVAL);
+        if ((r = dalloc(c, &c->lx, nsub * 2 * n)) || (r = dalloc(c, &c->ly, nsub * R * n)) ||
+            (r = dalloc(c, &c->lint, nsub)))
+            return fail(r);
+    }
     if ((r = alloc_levels(c)) != RMRCM_OK) return fail(r);
     if (hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream) != hipSuccess)
@@ -642,6 +687,11 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         c->t_solve_ms[5] = elapsed(c->ev[9], c->ev[10]);
         c->t_solve_ms[6] = elapsed(c->ev[4], c->ev[10]);
     }
+    if (c->net && c->setup_recorded) {
+        int h[rmrcm::kNumFlags] = {};
+        if (hipMemcpy(h, c->flags, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess)
+            c->n_accepted = h[rmrcm::FLAG_ACCEPTED];
+    }
     char buf[2048];
     const int n = std::snprintf(
         buf, sizeof(buf),
@@ -651,12 +701,13 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         "\"levels\": %d, \"nseg\": %d, \"subdomains\": %d, \"local_solves\": %lld, "
         "\"device_bytes\": %zu, \"precision\": %d, \"ir_iters_setup\": %d, "
         "\"ir_iters_solve\": %d, \"ir_resid_setup\": %.3e, \"ir_resid_solve\": %.3e, "
-        "\"fp64_fallback_subdomains\": %d}",
+        "\"fp64_fallback_subdomains\": %d, \"surrogate_accepted_subdomains\": %d, "
+        "\"gate_tol\": %.3e}",
         c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
         c->t_solve_ms[1], c->t_solve_ms[2], c->t_solve_ms[3], c->t_solve_ms[4], c->t_solve_ms[5],
         c->t_solve_ms[6], c->D, c->geo.nseg, c->geo.mx * c->geo.my, (long long)c->n_local_solves,
         c->device_bytes, c->prm.precision, c->ir_iters_setup, c->ir_iters_solve, c->ir_resid_setup,
-        c->ir_resid_solve, c->n_fallback);
+        c->ir_resid_solve, c->n_fallback, c->n_accepted, c->prm.gate_tol);
     if (json && cap > 0) {
         std::strncpy(json, buf, cap - 1);
         json[cap - 1] = '\0';
@@ -670,6 +721,33 @@ void rmrcm_destroy(rmrcm_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
+}
+
+// Training pairs for the local-basis surrogate: the network's input
+// features of every subdomain (device, FP32 [nsub][2][S][S]), the exact
+// local basis from the last setup (host or device, FP64 [nsub][R][S*S]) and
+// the interior mask (host, [nsub]).
+int rmrcm_export_local(rmrcm_ctx* c, float* features, double* basis, int32_t* interior) {
+    if (!c || !features) return RMRCM_EINVAL;
+    if (c->geo.bx != c->geo.by) return RMRCM_ENOTSUP;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    const size_t nsub = (size_t)c->geo.mx * c->geo.my;
+    const size_t n = (size_t)c->geo.bx * c->geo.by;
+    const int R = c->levels[c->D].nslot;
+    int* dint = nullptr;
+    HIP_TRY(hipMallocAsync((void**)&dint, nsub * sizeof(int), c->stream));
+    hipError_t e = rmrcm::launch_features(c, features, dint);
+    if (e == hipSuccess && basis)
+        e = hipMemcpyAsync(basis, c->Psi, nsub * R * n * sizeof(double), hipMemcpyDefault, c->stream);
+    std::vector<int> hi(nsub);
+    if (e == hipSuccess) e = hipMemcpyAsync(hi.data(), dint, nsub * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFreeAsync(dint, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return RMRCM_EDEVICE;
+    if (interior)
+        for (size_t k = 0; k < nsub; ++k) interior[k] = hi[k];
+    return RMRCM_OK;
 }
 
 // ---------------------------------------------------------------- autotuner

@@ -252,11 +252,12 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
                                                     double* __restrict__ T, int ld,
                                                     int* __restrict__ flags,
                                                     const int* __restrict__ mask, int want,
-                                                    int do_traces) {
+                                                    int do_traces, int basis) {
     const int sub = blockIdx.x;
     if (mask && mask[sub] != want) return;
     extern __shared__ __align__(16) char smem[];
     constexpr int LT = BX + 1;             // padded row of L^{-T}
+    const int ncol = basis ? R : 0;        // basis = 0: factor store only
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
     char* cur = smem;
     S* LTs = carve<S>(cur, BX * LT);        // row c = column c of L^{-1}
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
 #pragma unroll
             for (int r = 0; r < BX; ++r) Ps[(size_t)j * BX * BX + r * BX + c] = p[r];
             // w_j = P_j z_j: lane c computes row c (P symmetric)
-            for (int q = 0; q < R; ++q) {
+            for (int q = 0; q < ncol; ++q) {
                 S s = S(0);
 #pragma unroll
                 for (int k = 0; k < BX; ++k) s = fma(p[k], Z[k * R + q], s);
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
                 a[i] = v;
             }
             // z_{j+1} = F_{j+1} + D_j w_j
-            for (int t = lane; t < BX * R; t += 64) Z[t] = tys[j * BX + t / R] * Wl[t];
+            for (int t = lane; t < BX * ncol; t += 64) Z[t] = tys[j * BX + t / R] * Wl[t];
             __syncthreads();
             const int jn = j + 1;
             if (lane == 0 && rs[jn] >= 0) Z[rs[jn]] += S(cf[jn]);
@@ -379,6 +380,10 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
     // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j D_j x_{j+1}
     // Wl holds x_{j+1}; lane c loads row c of P_j (= column c) and its own
     // row of w_j one step ahead.
+    if (!basis) {
+        if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+        return;
+    }
     S pn[BX];
     double wn[kWPre];
     if (scol && BY > 1) {
@@ -539,7 +544,9 @@ __global__ __launch_bounds__(64) void k_local_refine(Geo g, const double* __rest
                                                      double* __restrict__ resid,
                                                      const int* __restrict__ mask, int apply) {
     const int sub = blockIdx.x;
-    if (mask && mask[sub] != 0) return;
+    // mask: 0 plain, 1 redone in FP64 (skipped), 2 basis accepted from the
+    // surrogate (FP32 factor only: its particular solution is refined)
+    if (mask && (part ? mask[sub] == 1 : mask[sub] != 0)) return;
     extern __shared__ __align__(16) char smem[];
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
     const int ncol = part ? 1 : R;
@@ -685,7 +692,7 @@ __global__ __launch_bounds__(64) void k_local_refine(Geo g, const double* __rest
 __global__ void k_mark_fallback(int nsub, const double* __restrict__ resid, double tol,
                                 int* __restrict__ fb, int* __restrict__ flags) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsub) return;
+    if (s >= nsub || fb[s] != 0) return;
     const int f = !(resid[s] <= tol);
     fb[s] = f;
     if (f) atomicAdd(&flags[FLAG_FALLBACK], 1);
@@ -694,12 +701,12 @@ __global__ void k_mark_fallback(int nsub, const double* __restrict__ resid, doub
 // Largest residual over all subdomains that are not marked (in flags[..]
 // order: one block, fixed summation order).
 __global__ __launch_bounds__(256) void k_max_resid(int nsub, const double* __restrict__ resid,
-                                                   const int* __restrict__ mask,
+                                                   const int* __restrict__ mask, int part,
                                                    double* __restrict__ out) {
     __shared__ double s[256];
     double m = 0.0;
     for (int t = threadIdx.x; t < nsub; t += 256)
-        if (!mask || mask[t] == 0) m = fmax(m, resid[t]);
+        if (!mask || mask[t] == 0 || (part && mask[t] == 2)) m = fmax(m, resid[t]);
     s[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -830,7 +837,7 @@ __global__ __launch_bounds__(64) void k_local_particular(
 
 // ---------------------------------------------------------------- launchers
 template <int BX, typename S>
-static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do_traces) {
+static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do_traces, int basis) {
     const Level& L = c->levels[c->D];
     const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY);
     const size_t lds = carve_bytes(BX * (BX + 1), sizeof(S)) + 2 * carve_bytes(BX * R, sizeof(S)) +
@@ -841,7 +848,7 @@ static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do
     const int nsub = c->geo.mx * c->geo.my;
     hipLaunchKernelGGL((k_local_setup<BX, S>), dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
                        c->bct, c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask, want,
-                       do_traces);
+                       do_traces, basis);
     return hipGetLastError();
 }
 
@@ -911,17 +918,18 @@ hipError_t launch_check_perm(rmrcm_ctx* c) {
     }                                                 \
     return hipErrorInvalidValue;
 
-hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces) {
+hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces,
+                              int basis) {
     if (fp32) {
-        RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces)),
-                        (setup_bx<8, float>(c, c->P32, mask, want, do_traces)),
-                        (setup_bx<16, float>(c, c->P32, mask, want, do_traces)),
-                        (setup_bx<32, float>(c, c->P32, mask, want, do_traces)))
+        RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces, basis)),
+                        (setup_bx<8, float>(c, c->P32, mask, want, do_traces, basis)),
+                        (setup_bx<16, float>(c, c->P32, mask, want, do_traces, basis)),
+                        (setup_bx<32, float>(c, c->P32, mask, want, do_traces, basis)))
     }
-    RMRCM_BX_SWITCH((setup_bx<4, double>(c, c->Pstore, mask, want, do_traces)),
-                    (setup_bx<8, double>(c, c->Pstore, mask, want, do_traces)),
-                    (setup_bx<16, double>(c, c->Pstore, mask, want, do_traces)),
-                    (setup_bx<32, double>(c, c->Pstore, mask, want, do_traces)))
+    RMRCM_BX_SWITCH((setup_bx<4, double>(c, c->Pstore, mask, want, do_traces, basis)),
+                    (setup_bx<8, double>(c, c->Pstore, mask, want, do_traces, basis)),
+                    (setup_bx<16, double>(c, c->Pstore, mask, want, do_traces, basis)),
+                    (setup_bx<32, double>(c, c->Pstore, mask, want, do_traces, basis)))
 }
 
 hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,
@@ -948,6 +956,172 @@ hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want
                     (traces_bx<16>(c, part, mask, want)), (traces_bx<32>(c, part, mask, want)))
 }
 
+// Input features of the local-basis surrogate network for every subdomain
+// (square subdomains): channel 0 the log-permeability minus its mean over
+// the subdomain, channel 1 on boundary cells the mean over the cell's
+// Robin faces of log(beta) + that mean (0 elsewhere).  Both are unchanged
+// when K is scaled (beta scales inversely, Section 5.1), as is the basis.
+// interior[sub] = 1 when every boundary slot of the subdomain is a Robin
+// slot (no face on the outer boundary).
+__global__ __launch_bounds__(256) void k_features(Geo g, const double* __restrict__ K,
+                                                  const double* __restrict__ beta,
+                                                  const int* __restrict__ slotseg, int R,
+                                                  float* __restrict__ x, int* __restrict__ interior) {
+    __shared__ double red[256];
+    const int sub = blockIdx.x, tid = threadIdx.x;
+    const int I = sub % g.mx, J = sub / g.mx, S = g.bx, n = S * S;
+    const int* ss = slotseg + (size_t)sub * R;
+    double acc = 0.0;
+    for (int c = tid; c < n; c += 256) acc += log(K[(size_t)(J * S + c / S) * g.nx + I * S + c % S]);
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double m = red[0] / n;
+    float* x0 = x + (size_t)sub * 2 * n;
+    float* x1 = x0 + n;
+    for (int c = tid; c < n; c += 256) {
+        const int i = c % S, j = c / S;
+        x0[c] = (float)(log(K[(size_t)(J * S + j) * g.nx + I * S + i]) - m);
+        const int sl[4] = {i == 0 ? j / g.sg : -1, i == S - 1 ? g.nsy + j / g.sg : -1,
+                           j == 0 ? 2 * g.nsy + i / g.sg : -1,
+                           j == S - 1 ? 2 * g.nsy + g.nsx + i / g.sg : -1};
+        double a = 0.0;
+        int k = 0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (sl[s] < 0) continue;
+            const int code = ss[sl[s]];
+            if (code < 0) continue;
+            a += log(beta[code >> 1]) + m;
+            ++k;
+        }
+        x1[c] = k ? (float)(a / k) : 0.f;
+    }
+    if (tid == 0) {
+        int all = 1;
+        for (int a = 0; a < R; ++a) all &= ss[a] >= 0;
+        interior[sub] = all;
+    }
+}
+
+// Residual gate of the surrogate's basis: for every column a of an interior
+// subdomain, rel_a = |A y_a - e_a|_2 / |e_a|_2 in FP64, with A the local
+// Robin matrix and e_a the right-hand side of the basis problem of slot a
+// (the Robin conductance on the slot's faces).  The subdomain is accepted
+// (fb = 2, its basis written to Psi in FP64) when every rel_a <= tau; the
+// largest rel_a goes to resid, accepted subdomains are counted.
+template <int BX>
+__global__ __launch_bounds__(256) void k_gate(Geo g, const double* __restrict__ K,
+                                              const int8_t* __restrict__ bct,
+                                              const double* __restrict__ beta,
+                                              const int* __restrict__ slotseg, int R,
+                                              const float* __restrict__ Y,
+                                              const int* __restrict__ interior, double tau,
+                                              double* __restrict__ Psi, int* __restrict__ fb,
+                                              double* __restrict__ resid, int* __restrict__ flags) {
+    __shared__ double cf[2 * (32 + 64)];
+    __shared__ int rs[2 * (32 + 64)], of[2 * (32 + 64)];
+    __shared__ double co[3 * BX * 64];      // per cell: diagonal, coupling right, coupling up
+    __shared__ double ys[BX * 64];
+    __shared__ double r2[256], e2[256];
+    const int sub = blockIdx.x, tid = threadIdx.x;
+    const int BY = g.by, n = BX * BY;
+    if (!interior[sub]) {
+        if (tid == 0) {
+            fb[sub] = 0;
+            resid[sub] = INFINITY;
+        }
+        return;
+    }
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    __syncthreads();
+    for (int c = tid; c < n; c += 256) {
+        double kv[5], dg, txr, tyu;
+        load_kstencil<BX>(g, K, I, J, c % BX, c / BX, kv);
+        stencil_coeffs<BX>(g, kv, cf, c % BX, c / BX, &dg, &txr, &tyu);
+        co[3 * c] = dg;
+        co[3 * c + 1] = txr;
+        co[3 * c + 2] = tyu;
+    }
+    const float* Ys = Y + (size_t)sub * R * n;
+    double worst = 0.0;
+    for (int a = 0; a < R; ++a) {
+        __syncthreads();
+        for (int c = tid; c < n; c += 256) ys[c] = (double)Ys[(size_t)a * n + c];
+        __syncthreads();
+        double rr = 0.0, ee = 0.0;
+        for (int c = tid; c < n; c += 256) {
+            const int i = c % BX, j = c / BX;
+            double v = co[3 * c] * ys[c];
+            if (i > 0) v -= co[3 * (c - 1) + 1] * ys[c - 1];
+            if (i < BX - 1) v -= co[3 * c + 1] * ys[c + 1];
+            if (j > 0) v -= co[3 * (c - BX) + 2] * ys[c - BX];
+            if (j < BY - 1) v -= co[3 * c + 2] * ys[c + BX];
+            double e = 0.0;
+            if (i == 0 && rs[j] == a) e += cf[j];
+            if (i == BX - 1 && rs[BY + j] == a) e += cf[BY + j];
+            if (j == 0 && rs[2 * BY + i] == a) e += cf[2 * BY + i];
+            if (j == BY - 1 && rs[2 * BY + BX + i] == a) e += cf[2 * BY + BX + i];
+            rr += (v - e) * (v - e);
+            ee += e * e;
+        }
+        r2[tid] = rr;
+        e2[tid] = ee;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) {
+                r2[tid] += r2[tid + w];
+                e2[tid] += e2[tid + w];
+            }
+            __syncthreads();
+        }
+        const double rel = e2[0] > 0.0 ? sqrt(r2[0] / e2[0]) : 0.0;
+        worst = fmax(worst, rel);
+    }
+    const bool acc = worst <= tau;
+    if (acc) {
+        double* Ps = Psi + (size_t)sub * R * n;
+        for (int t = tid; t < R * n; t += 256) Ps[t] = (double)Ys[t];
+    }
+    if (tid == 0) {
+        fb[sub] = acc ? 2 : 0;
+        resid[sub] = worst;
+        if (acc) atomicAdd(&flags[FLAG_ACCEPTED], 1);
+    }
+}
+
+template <int BX>
+static hipError_t gate_bx(rmrcm_ctx* c, const float* Y, const int* interior, double tau) {
+    const Level& L = c->levels[c->D];
+    hipLaunchKernelGGL(k_gate<BX>, dim3(c->geo.mx * c->geo.my), dim3(256), 0, c->stream, c->geo, c->K,
+                       c->bct, c->beta, L.slotseg, L.nslot, Y, interior, tau, c->Psi, c->fb, c->resid,
+                       c->flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate(rmrcm_ctx* c, const float* Y, const int* interior, double tau) {
+    if (c->geo.by > 64) return hipErrorInvalidValue;
+    switch (c->geo.bx) {
+        case 8: return gate_bx<8>(c, Y, interior, tau);
+        case 16: return gate_bx<16>(c, Y, interior, tau);
+        case 32: return gate_bx<32>(c, Y, interior, tau);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_features(rmrcm_ctx* c, float* x, int* interior) {
+    if (c->geo.bx != c->geo.by) return hipErrorInvalidValue;
+    const Level& L = c->levels[c->D];
+    hipLaunchKernelGGL(k_features, dim3(c->geo.mx * c->geo.my), dim3(256), 0, c->stream, c->geo, c->K,
+                       c->beta, L.slotseg, L.nslot, x, interior);
+    return hipGetLastError();
+}
+
 hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol) {
     const int nsub = c->geo.mx * c->geo.my;
     hipLaunchKernelGGL(k_mark_fallback, dim3((nsub + 255) / 256), dim3(256), 0, c->stream, nsub,
@@ -955,9 +1129,9 @@ hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol) {
     return hipGetLastError();
 }
 
-hipError_t launch_max_resid(rmrcm_ctx* c, double* out) {
+hipError_t launch_max_resid(rmrcm_ctx* c, int part, double* out) {
     const int nsub = c->geo.mx * c->geo.my;
-    hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(256), 0, c->stream, nsub, c->resid, c->fb, out);
+    hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(256), 0, c->stream, nsub, c->resid, c->fb, part, out);
     return hipGetLastError();
 }
 

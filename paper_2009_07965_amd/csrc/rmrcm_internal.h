@@ -103,6 +103,12 @@ struct rmrcm_ctx {
     double t_solve_ms[8] = {};
     int64_t n_local_solves = 0;
     int ir_iters_setup = 0, ir_iters_solve = 0, n_fallback = 0;
+    // learned mode: surrogate network, its inputs / outputs, accepted count
+    struct rmrcm_cnn* net = nullptr;
+    float* lx = nullptr;                     // [nsub][2][S][S] features
+    float* ly = nullptr;                     // [nsub][R][S][S] predicted basis
+    int* lint = nullptr;                     // [nsub] interior mask
+    int n_accepted = 0;
     double ir_resid_setup = 0.0, ir_resid_solve = 0.0;
 };
 
@@ -111,13 +117,14 @@ namespace rmrcm {
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_beta(rmrcm_ctx* c);
 hipError_t launch_check_perm(rmrcm_ctx* c);
-hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces);
+hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces,
+                              int basis = 1);
 hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,
                                    int do_traces);
 hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply);
 hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want);
 hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol);
-hipError_t launch_max_resid(rmrcm_ctx* c, double* out);
+hipError_t launch_max_resid(rmrcm_ctx* c, int part, double* out);
 hipError_t launch_merge_setup(rmrcm_ctx* c, int depth);
 hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
@@ -127,6 +134,8 @@ hipError_t launch_gauge(rmrcm_ctx* c);
 hipError_t launch_fill_i32(rmrcm_ctx* c, int* p, size_t n, int v);
 hipError_t launch_fill_f64(rmrcm_ctx* c, double* p, size_t n, double v);
 hipError_t launch_compat_check(rmrcm_ctx* c);
+hipError_t launch_features(rmrcm_ctx* c, float* x, int* interior);
+hipError_t launch_gate(rmrcm_ctx* c, const float* Y, const int* interior, double tau);
 // Merge apply of the basis columns of one depth with column tile ct (the
 // autotuner times it; ct in {4, 8, 16}).
 hipError_t launch_merge_apply(rmrcm_ctx* c, int depth, int ct);
@@ -134,6 +143,6 @@ bool merge_apply_tunable(rmrcm_ctx* c, int depth);
 
 // Device error flag slots.
 enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2, FLAG_FALLBACK = 3,
-       FLAG_BAD_DATA = 4, kNumFlags = 8 };
+       FLAG_BAD_DATA = 4, FLAG_ACCEPTED = 5, kNumFlags = 8 };
 
 }  // namespace rmrcm

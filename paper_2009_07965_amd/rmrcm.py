@@ -50,6 +50,9 @@ EXPORTS = [
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
     "rmrcm_strerror", "rmrcm_autotune", "rmrcm_batch_create", "rmrcm_batch_refactor",
     "rmrcm_batch_solve", "rmrcm_batch_sync", "rmrcm_batch_get_stats", "rmrcm_batch_destroy",
+    "rmrcm_export_local", "rmrcm_cnn_create", "rmrcm_cnn_num_params", "rmrcm_cnn_set_stream",
+    "rmrcm_cnn_set_params", "rmrcm_cnn_get_params", "rmrcm_cnn_forward", "rmrcm_cnn_loss_grad",
+    "rmrcm_cnn_train_step", "rmrcm_cnn_save", "rmrcm_cnn_load", "rmrcm_cnn_destroy",
 ]
 
 
@@ -102,6 +105,32 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_batch_get_stats.restype = ctypes.c_int
     lib.rmrcm_batch_destroy.argtypes = [vp]
     lib.rmrcm_batch_destroy.restype = None
+    lib.rmrcm_export_local.argtypes = [vp, vp, vp, vp]
+    lib.rmrcm_export_local.restype = ctypes.c_int
+    i32 = ctypes.c_int32
+    lib.rmrcm_cnn_create.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.POINTER(vp)]
+    lib.rmrcm_cnn_create.restype = ctypes.c_int
+    lib.rmrcm_cnn_num_params.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.rmrcm_cnn_num_params.restype = ctypes.c_int
+    lib.rmrcm_cnn_set_stream.argtypes = [vp, vp]
+    lib.rmrcm_cnn_set_stream.restype = ctypes.c_int
+    lib.rmrcm_cnn_set_params.argtypes = [vp, vp]
+    lib.rmrcm_cnn_set_params.restype = ctypes.c_int
+    lib.rmrcm_cnn_get_params.argtypes = [vp, vp]
+    lib.rmrcm_cnn_get_params.restype = ctypes.c_int
+    lib.rmrcm_cnn_forward.argtypes = [vp, i32, vp, vp]
+    lib.rmrcm_cnn_forward.restype = ctypes.c_int
+    lib.rmrcm_cnn_loss_grad.argtypes = [vp, i32, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.rmrcm_cnn_loss_grad.restype = ctypes.c_int
+    lib.rmrcm_cnn_train_step.argtypes = [vp, i32, vp, vp, ctypes.c_float,
+                                         ctypes.POINTER(ctypes.c_double)]
+    lib.rmrcm_cnn_train_step.restype = ctypes.c_int
+    lib.rmrcm_cnn_save.argtypes = [vp, ctypes.c_char_p]
+    lib.rmrcm_cnn_save.restype = ctypes.c_int
+    lib.rmrcm_cnn_load.argtypes = [ctypes.c_char_p, i32, i32, ctypes.POINTER(vp)]
+    lib.rmrcm_cnn_load.restype = ctypes.c_int
+    lib.rmrcm_cnn_destroy.argtypes = [vp]
+    lib.rmrcm_cnn_destroy.restype = None
     return lib
 
 
@@ -209,6 +238,91 @@ def _ptr_array(items, dtype):
         keep.append(k)
         raw.append(p.value if p is not None else None)
     return (ctypes.c_void_p * len(raw))(*raw), keep
+
+
+def rmrcm_export_local(ctx, features, basis=None):
+    """features: device float32 tensor [nsub, 2, S, S]; basis: float64
+    array/tensor [nsub, R, S*S] or None.  Returns the interior mask."""
+    nsub = features.shape[0]
+    interior = np.zeros(nsub, dtype=np.int32)
+    fp, _f = _ptr(features, np.float32)
+    bp, _b = _ptr(basis, np.float64)
+    _check(lib().rmrcm_export_local(ctx, fp, bp, ctypes.c_void_p(interior.ctypes.data)),
+           "rmrcm_export_local")
+    return interior
+
+
+class Net:
+    """The local-basis surrogate network (rmrcm_cnn_*): S x S patches, width
+    C, L convolution layers, R outputs.  Inputs / outputs are device
+    float32 tensors."""
+
+    def __init__(self, S, C, L, R, max_batch=256, device=0, _handle=None):
+        self.S, self.C, self.L, self.R, self.max_batch = S, C, L, R, max_batch
+        if _handle is None:
+            h = ctypes.c_void_p()
+            _check(lib().rmrcm_cnn_create(S, C, L, R, max_batch, device, ctypes.byref(h)),
+                   "rmrcm_cnn_create")
+            _handle = h
+        self.h = _handle
+        n = ctypes.c_int64()
+        _check(lib().rmrcm_cnn_num_params(self.h, ctypes.byref(n)), "rmrcm_cnn_num_params")
+        self.num_params = n.value
+
+    @classmethod
+    def load(cls, path, max_batch=256, device=0):
+        h = ctypes.c_void_p()
+        _check(lib().rmrcm_cnn_load(path.encode(), max_batch, device, ctypes.byref(h)), "rmrcm_cnn_load")
+        with open(path, "rb") as f:
+            hdr = np.frombuffer(f.read(24)[8:24], dtype=np.int32)
+        return cls(int(hdr[0]), int(hdr[1]), int(hdr[2]), int(hdr[3]), max_batch, device, _handle=h)
+
+    def set_stream(self, handle):
+        _check(lib().rmrcm_cnn_set_stream(self.h, ctypes.c_void_p(handle)), "rmrcm_cnn_set_stream")
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.num_params
+        _check(lib().rmrcm_cnn_set_params(self.h, ctypes.c_void_p(a.ctypes.data)), "rmrcm_cnn_set_params")
+
+    def get_params(self):
+        a = np.zeros(self.num_params, dtype=np.float32)
+        _check(lib().rmrcm_cnn_get_params(self.h, ctypes.c_void_p(a.ctypes.data)), "rmrcm_cnn_get_params")
+        return a
+
+    def forward(self, x, y):
+        _check(lib().rmrcm_cnn_forward(self.h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr())), "rmrcm_cnn_forward")
+
+    def loss_grad(self, x, t):
+        loss = ctypes.c_double()
+        g = np.zeros(self.num_params, dtype=np.float32)
+        _check(lib().rmrcm_cnn_loss_grad(self.h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(t.data_ptr()), ctypes.byref(loss),
+                                         ctypes.c_void_p(g.ctypes.data)), "rmrcm_cnn_loss_grad")
+        return loss.value, g
+
+    def train_step(self, x, t, lr, want_loss=False):
+        loss = ctypes.c_double()
+        _check(lib().rmrcm_cnn_train_step(self.h, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(t.data_ptr()), ctypes.c_float(lr),
+                                          ctypes.byref(loss) if want_loss else None),
+               "rmrcm_cnn_train_step")
+        return loss.value if want_loss else None
+
+    def save(self, path):
+        _check(lib().rmrcm_cnn_save(self.h, path.encode()), "rmrcm_cnn_save")
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lib().rmrcm_cnn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:
