@@ -450,6 +450,277 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
     if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
 }
 
+// ---------------------------------------------------------------- K1 (MFMA)
+// The same factorisation and basis solves for subdomains 16 or 32 cells wide,
+// with the dense products on the matrix cores (v_mfma 16x16x4, FP64 or FP32
+// by the compute type S): per block row j the inverse P_j = L^{-T} L^{-1}
+// (L^{-1} from the register Cholesky above, staged in LDS) and the
+// multi-column sweeps w_j = P_j z_j (forward) and x_j = w_j + P_j D_j x_{j+1}
+// (backward, P_j re-read from the factor store one row ahead).  Operands are
+// read from LDS in the MFMA lane layout: A[i][k] from lane i + 16 k,
+// B[k][j] from lane j + 16 k; rows of LDS matrices are padded by 4 to spread
+// the banks.
+
+template <typename S>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // row of the 16 x 16 result held by lane l in register v (column l % 16)
+    static __device__ inline int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <int BX, typename S>
+__global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __restrict__ K,
+                                                         const int8_t* __restrict__ bct,
+                                                         const double* __restrict__ beta,
+                                                         const int* __restrict__ slotseg, int R,
+                                                         S* __restrict__ Pstore,
+                                                         double* __restrict__ Psi,
+                                                         double* __restrict__ T, int ld,
+                                                         int* __restrict__ flags,
+                                                         const int* __restrict__ mask, int want,
+                                                         int do_traces, int basis) {
+    static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
+    typedef Mfma<S> M;
+    typedef typename M::v4 v4;
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != want) return;
+    extern __shared__ __align__(16) char smem[];
+    constexpr int LT = BX + 4;              // padded row length
+    constexpr int NTL = BX / 16;            // tiles per dimension
+    constexpr int PPL = BX * BX / 64;       // factor-store entries per lane
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
+    const int RP = (R + 15) & ~15;          // columns padded to whole tiles
+    const int nct = basis ? RP / 16 : 0;    // column tiles of the sweeps
+    char* cur = smem;
+    S* LTs = carve<S>(cur, BX * LT);        // row c = column c of L^{-1}
+    S* Pl = carve<S>(cur, BX * LT);         // P_j, row-major
+    S* Z = carve<S>(cur, BX * RP);          // z_j, later D_j x_{j+1}
+    S* Wl = carve<S>(cur, BX * RP);         // w_j, later x_j
+    S* tys = carve<S>(cur, BY * BX);        // couplings D_j
+    double* cf = carve<double>(cur, NF);
+    int* rs = carve<int>(cur, NF);
+    int* of = carve<int>(cur, NF);
+
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    S* Ps = Pstore + (size_t)sub * BY * BX * BX;
+    double* Psub = Psi + (size_t)sub * R * n;
+
+    const bool scol = lane < BX;
+    const bool icol = lane >= BX && lane < 2 * BX;
+    const int c = scol ? lane : (icol ? lane - BX : 0);
+
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    double kv[5], kn[5];
+    load_kstencil<BX>(g, K, I, J, c, 0, kv);
+    for (int t = lane; t < BX * RP; t += 64) Z[t] = S(0);
+    __syncthreads();
+
+    S a[BX];
+    S p[BX];
+    int sing = 0;
+    double dg, txr, tyu;
+    stencil_coeffs<BX>(g, kv, cf, c, 0, &dg, &txr, &tyu);
+    double txl = __shfl(txr, lane > 0 ? lane - 1 : 0, 64);
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        double v = 0.0;
+        if (scol) v = (i == c) ? dg : (i == c + 1) ? -txr : (i + 1 == c) ? -txl : 0.0;
+        else if (icol) v = (i == c) ? 1.0 : 0.0;
+        a[i] = S(v);
+    }
+    if (lane == 0 && rs[0] >= 0) Z[rs[0]] += S(cf[0]);
+    if (lane == 1 && rs[BY] >= 0) Z[(BX - 1) * RP + rs[BY]] += S(cf[BY]);
+    __syncthreads();
+    if (lane < BX && rs[2 * BY + lane] >= 0) Z[lane * RP + rs[2 * BY + lane]] += S(cf[2 * BY + lane]);
+    if (BY == 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+        Z[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
+    __syncthreads();
+
+    for (int j = 0; j < BY; ++j) {
+        if (j + 1 < BY) load_kstencil<BX>(g, K, I, J, c, j + 1, kn);
+        // ---- Cholesky of S_j fused with the inversion of its factor
+#pragma unroll
+        for (int k = 0; k < BX; ++k) {
+            S d = readlane_s(a[k], k);
+            if (!(d > S(0))) {
+                sing = 1;
+                d = S(1);
+            }
+            const S r = inv_sqrt(d);
+            a[k] *= r;
+#pragma unroll
+            for (int i = k + 1; i < BX; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
+        }
+        if (icol) {
+#pragma unroll
+            for (int i = 0; i < BX; ++i) LTs[c * LT + i] = a[i];
+        }
+        if (scol) tys[j * BX + c] = S(tyu);    // D_j
+        __syncthreads();
+        // ---- P_j[r][c] = sum_{i >= max(r,c)} L^{-1}[i][r] L^{-1}[i][c] on the matrix cores
+#pragma unroll
+        for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < NTL; ++tc) {
+                v4 acc = {S(0), S(0), S(0), S(0)};
+                const int k0 = 16 * (tr > tc ? tr : tc);
+#pragma unroll
+                for (int kk = k0; kk < BX; kk += 4) {
+                    const S av = LTs[(16 * tr + li) * LT + kk + lk];
+                    const S bv = LTs[(16 * tc + li) * LT + kk + lk];
+                    acc = M::op(av, bv, acc);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v), cc = 16 * tc + li;
+                    Pl[r * LT + cc] = acc[v];
+                    Ps[(size_t)j * BX * BX + r * BX + cc] = acc[v];
+                }
+            }
+        __syncthreads();
+        // ---- forward sweep w_j = P_j z_j
+        for (int ct = 0; ct < nct; ++ct) {
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr) {
+                v4 acc = {S(0), S(0), S(0), S(0)};
+#pragma unroll
+                for (int kk = 0; kk < BX; kk += 4) {
+                    const S av = Pl[(16 * tr + li) * LT + kk + lk];
+                    const S bv = Z[(kk + lk) * RP + 16 * ct + li];
+                    acc = M::op(av, bv, acc);
+                }
+                const int q = 16 * ct + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    Wl[r * RP + q] = acc[v];
+                    if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[v];
+                }
+            }
+        }
+        __syncthreads();
+        if (j + 1 < BY) {
+            // ---- trailing update S_{j+1} = A_{j+1} - D_j P_j D_j (lane c: column c)
+            if (scol) {
+#pragma unroll
+                for (int r = 0; r < BX; ++r) p[r] = Pl[r * LT + c];
+            }
+            const S dc = S(tyu);
+            stencil_coeffs<BX>(g, kn, cf, c, j + 1, &dg, &txr, &tyu);
+            txl = __shfl(txr, lane > 0 ? lane - 1 : 0, 64);
+#pragma unroll
+            for (int i = 0; i < BX; ++i) {
+                S v = S(0);
+                if (scol) {
+                    v = -p[i] * (tys[j * BX + i] * dc);
+                    if (i == c) v += S(dg);
+                    else if (i == c + 1) v -= S(txr);
+                    else if (i + 1 == c) v -= S(txl);
+                } else if (icol) {
+                    v = (i == c) ? S(1) : S(0);
+                }
+                a[i] = v;
+            }
+            // z_{j+1} = F_{j+1} + D_j w_j
+            for (int t = lane; t < BX * RP * (nct > 0); t += 64) Z[t] = tys[j * BX + t / RP] * Wl[t];
+            __syncthreads();
+            const int jn = j + 1;
+            if (lane == 0 && rs[jn] >= 0) Z[rs[jn]] += S(cf[jn]);
+            if (lane == 1 && rs[BY + jn] >= 0) Z[(BX - 1) * RP + rs[BY + jn]] += S(cf[BY + jn]);
+            __syncthreads();
+            if (jn == BY - 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+                Z[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
+            __syncthreads();
+        }
+    }
+    if (!basis) {
+        if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+        return;
+    }
+    // ---- backward sweep: x_{BY-1} = w_{BY-1} (in Wl); x_j = w_j + P_j (D_j x_{j+1})
+    S pr[PPL];
+    if (BY > 1) {
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(BY - 2) * BX * BX + lane + 64 * u];
+    }
+    for (int j = BY - 2; j >= 0; --j) {
+        for (int t = lane; t < BX * RP; t += 64) Z[t] = tys[j * BX + t / RP] * Wl[t];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            const int e = lane + 64 * u;
+            Pl[(e / BX) * LT + e % BX] = pr[u];
+        }
+        __syncthreads();
+        if (j > 0) {
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(j - 1) * BX * BX + lane + 64 * u];
+        }
+        for (int ct = 0; ct < nct; ++ct) {
+            const int q = 16 * ct + li;
+            v4 acc[NTL];
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    acc[tr][v] = q < R ? S(Psub[(size_t)q * n + j * BX + r]) : S(0);
+                }
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr) {
+#pragma unroll
+                for (int kk = 0; kk < BX; kk += 4) {
+                    const S av = Pl[(16 * tr + li) * LT + kk + lk];
+                    const S bv = Z[(kk + lk) * RP + q];
+                    acc[tr] = M::op(av, bv, acc[tr]);
+                }
+            }
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    Wl[r * RP + q] = acc[tr][v];
+                    if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[tr][v];
+                }
+        }
+        __syncthreads();
+    }
+    if (do_traces) {
+        // traces T[a][b] = sum_{f in slot a} c_f (x_b(cell f) - delta_ab)
+        double* Tsub = T + (size_t)sub * R * ld;
+        for (int t = lane; t < R * R; t += 64) {
+            const int ar = t / R, b = t % R;
+            double s = 0.0;
+            if (ss[ar] >= 0 && ss[b] >= 0) {
+                const double* col = Psub + (size_t)b * n;
+                for (int u = 0; u < g.sg; ++u) {
+                    const int f = face_of_slot(g, BX, ar, u);
+                    int side, i, jj;
+                    face_cell(g, BX, f, &side, &i, &jj);
+                    s += cf[f] * (col[jj * BX + i] - (ar == b ? 1.0 : 0.0));
+                }
+            }
+            Tsub[(size_t)ar * ld + b] = s;
+        }
+    }
+    if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+}
+
 // Traces of the basis (columns 0..R-1) or of the particular solution
 // (column R) of the subdomains whose mask entry equals `want`, from the
 // stored cell values.
@@ -838,6 +1109,20 @@ __global__ __launch_bounds__(64) void k_local_particular(
 // ---------------------------------------------------------------- launchers
 template <int BX, typename S>
 static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do_traces, int basis) {
+    if constexpr (BX >= 16) {
+        const Level& L = c->levels[c->D];
+        const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY), RP = (R + 15) & ~15;
+        const size_t lds = 2 * carve_bytes(BX * (BX + 4), sizeof(S)) + 2 * carve_bytes(BX * RP, sizeof(S)) +
+                           carve_bytes(BY * BX, sizeof(S)) + carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4);
+        hipError_t e = hipFuncSetAttribute((const void*)k_local_setup_mfma<BX, S>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        const int nsub = c->geo.mx * c->geo.my;
+        hipLaunchKernelGGL((k_local_setup_mfma<BX, S>), dim3(nsub), dim3(64), lds, c->stream, c->geo,
+                           c->K, c->bct, c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask,
+                           want, do_traces, basis);
+        return hipGetLastError();
+    }
     const Level& L = c->levels[c->D];
     const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY);
     const size_t lds = carve_bytes(BX * (BX + 1), sizeof(S)) + 2 * carve_bytes(BX * R, sizeof(S)) +
