@@ -721,6 +721,212 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
 }
 
+// One refinement pass on the matrix cores (subdomains 16 or 32 cells wide):
+// r = b - A x in FP64 for every column, the correction A32^{-1} r from the
+// FP32 factor store by the two sweeps as v_mfma_f32 16x16x4 products, and
+// x += correction.  resid[sub] = max over columns of |r|_inf / |b|_inf
+// (measured before the correction).  The residual of row j uses lanes as
+// (cell c = lane % BX, columns lane / BX + (64 / BX) t); the largest |r| and
+// |b| per column are kept per lane and reduced once at the end.
+template <int BX>
+__global__ __launch_bounds__(64) void k_local_refine_mfma(Geo g, const double* __restrict__ K,
+                                                          const int8_t* __restrict__ bct,
+                                                          const double* __restrict__ beta,
+                                                          const int* __restrict__ slotseg, int R,
+                                                          const float* __restrict__ P32,
+                                                          double* __restrict__ X, int part,
+                                                          const double* __restrict__ q,
+                                                          const double* __restrict__ bcv,
+                                                          float* __restrict__ Wsc,
+                                                          double* __restrict__ resid,
+                                                          const int* __restrict__ mask, int apply) {
+    static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
+    typedef Mfma<float> M;
+    typedef M::v4 v4;
+    constexpr int LT = BX + 4, NTL = BX / 16, PPL = BX * BX / 64, H = 64 / BX;
+    constexpr int MAXC = 16;                // columns per lane kept in registers (ncol <= 16 H)
+    const int sub = blockIdx.x;
+    if (mask && (part ? mask[sub] == 1 : mask[sub] != 0)) return;
+    extern __shared__ __align__(16) char smem[];
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
+    const int ncol = part ? 1 : R;
+    const int RP = (ncol + 15) & ~15, nct = RP / 16;
+    char* cur = smem;
+    double* x3 = carve<double>(cur, 3 * BX * ncol);   // rows j-1, j, j+1 of x (ring)
+    float* zf = carve<float>(cur, BX * RP);           // z_j, later D_j dx_{j+1}
+    float* wf = carve<float>(cur, BX * RP);           // w_j, later dx_j
+    float* Pl = carve<float>(cur, BX * LT);           // P_j
+    float* tys = carve<float>(cur, BY * BX);          // D_j
+    double* cf = carve<double>(cur, NF);
+    int* rs = carve<int>(cur, NF);
+    int* of = carve<int>(cur, NF);
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    const float* Ps = P32 + (size_t)sub * BY * BX * BX;
+    double* Xs = X + (size_t)sub * ncol * n;
+    float* Ws = Wsc + (size_t)sub * ncol * n;
+    const int c = lane % BX, h = lane / BX;           // residual mapping
+
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    if (part) {
+        // a particular problem with zero data has the solution 0 (set by
+        // the particular solve): nothing to refine
+        __syncthreads();
+        bool nz = false;
+        for (int j = 0; j < BY && !nz; ++j) {
+            const double qv = q ? q[(size_t)(J * BY + j) * g.nx + I * BX + c] : 0.0;
+            nz = part_rhs<BX>(g, cf, of, bct, bcv, qv, c, j) != 0.0;
+        }
+        if (__ballot(nz) == 0ull) {
+            if (lane == 0) resid[sub] = 0.0;
+            return;
+        }
+    }
+    for (int t = lane; t < BX * RP; t += 64) zf[t] = 0.f, wf[t] = 0.f;
+    for (int t = lane; t < BX * ncol; t += 64) {
+        const int i = t % BX, qq = t / BX;
+        x3[(1 * BX + i) * ncol + qq] = Xs[(size_t)qq * n + i];
+        x3[(2 * BX + i) * ncol + qq] = BY > 1 ? Xs[(size_t)qq * n + BX + i] : 0.0;
+    }
+    float pr[PPL];
+#pragma unroll
+    for (int u = 0; u < PPL; ++u) pr[u] = Ps[lane + 64 * u];
+    double bmax[MAXC], rmax[MAXC];
+#pragma unroll
+    for (int t = 0; t < MAXC; ++t) bmax[t] = 0.0, rmax[t] = 0.0;
+    __syncthreads();
+    double kv[5];
+    for (int j = 0; j < BY; ++j) {
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            const int e = lane + 64 * u;
+            Pl[(e / BX) * LT + e % BX] = pr[u];
+        }
+        if (j + 1 < BY) {
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(j + 1) * BX * BX + lane + 64 * u];
+        }
+        load_kstencil<BX>(g, K, I, J, c, j, kv);
+        double dg, txr, tyu;
+        stencil_coeffs<BX>(g, kv, cf, c, j, &dg, &txr, &tyu);
+        const double txl = c > 0 ? tpx(g, kv[1], kv[0]) : 0.0;
+        const double tyd = j > 0 ? tpy(g, kv[3], kv[0]) : 0.0;
+        const int rc = (j + 1) % 3, rp = (j + 2) % 3;  // ring slots of rows j and j+1 (j-1: j % 3)
+        if (h == 0) tys[j * BX + c] = (float)tyu;
+        const double qv = (part && q) ? q[(size_t)(J * BY + j) * g.nx + I * BX + c] : 0.0;
+        const double bpart = part ? part_rhs<BX>(g, cf, of, bct, bcv, qv, c, j) : 0.0;
+#pragma unroll
+        for (int t = 0; t < MAXC; ++t) {
+            const int qq = h + H * t;
+            if (qq >= ncol) break;
+            double b = bpart;
+            if (!part) {
+                if (c == 0 && rs[j] == qq) b += cf[j];
+                if (c == BX - 1 && rs[BY + j] == qq) b += cf[BY + j];
+                if (j == 0 && rs[2 * BY + c] == qq) b += cf[2 * BY + c];
+                if (j == BY - 1 && rs[2 * BY + BX + c] == qq) b += cf[2 * BY + BX + c];
+            }
+            double ax = dg * x3[(rc * BX + c) * ncol + qq];
+            if (c > 0) ax -= txl * x3[(rc * BX + c - 1) * ncol + qq];
+            if (c < BX - 1) ax -= txr * x3[(rc * BX + c + 1) * ncol + qq];
+            if (j > 0) ax -= tyd * x3[((j % 3) * BX + c) * ncol + qq];
+            if (j < BY - 1) ax -= tyu * x3[(rp * BX + c) * ncol + qq];
+            const double r = b - ax;
+            bmax[t] = fmax(bmax[t], fabs(b));
+            rmax[t] = fmax(rmax[t], fabs(r));
+            // z_j = r_j + D_{j-1} w_{j-1}
+            zf[c * RP + qq] = (float)r + (j > 0 ? tys[(j - 1) * BX + c] * wf[c * RP + qq] : 0.0f);
+        }
+        __syncthreads();
+        // w_j = P_j z_j
+        for (int ct = 0; ct < nct; ++ct) {
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr) {
+                v4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < BX; kk += 4)
+                    acc = M::op(Pl[(16 * tr + li) * LT + kk + lk], zf[(kk + lk) * RP + 16 * ct + li], acc);
+                const int qq = 16 * ct + li;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    wf[r * RP + qq] = acc[v];
+                    if (qq < ncol) Ws[(size_t)qq * n + j * BX + r] = acc[v];
+                }
+            }
+        }
+        // shift the ring: row j+2 of x into the slot of row j-1
+        if (j + 2 < BY)
+            for (int t = lane; t < BX * ncol; t += 64) {
+                const int i = t % BX, qq = t / BX;
+                x3[((j % 3) * BX + i) * ncol + qq] = Xs[(size_t)qq * n + (j + 2) * BX + i];
+            }
+        __syncthreads();
+    }
+    // per-column norms: reduce over the lanes of the same column set
+    double m = 0.0;
+#pragma unroll
+    for (int t = 0; t < MAXC; ++t) {
+        double ab = bmax[t], ar = rmax[t];
+#pragma unroll
+        for (int off = 1; off < BX; off <<= 1) {
+            ab = fmax(ab, __shfl_xor(ab, off));
+            ar = fmax(ar, __shfl_xor(ar, off));
+        }
+        const int qq = h + H * t;
+        if (qq < ncol) m = fmax(m, ab > 0.0 ? ar / ab : (ar > 0.0 ? 1.0 : 0.0));
+    }
+    for (int off = BX; off < 64; off <<= 1) m = fmax(m, __shfl_xor(m, off));
+    if (lane == 0) resid[sub] = m;
+    if (!apply) return;
+    // backward: dx_{BY-1} = w_{BY-1}; dx_j = w_j + P_j D_j dx_{j+1}; x_j += dx_j
+    for (int t = lane; t < BX * ncol; t += 64) {
+        const int i = t % BX, qq = t / BX;
+        Xs[(size_t)qq * n + (BY - 1) * BX + i] += (double)wf[i * RP + qq];
+    }
+    if (BY > 1) {
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(BY - 2) * BX * BX + lane + 64 * u];
+    }
+    for (int j = BY - 2; j >= 0; --j) {
+        for (int t = lane; t < BX * RP; t += 64) zf[t] = tys[j * BX + t / RP] * wf[t];
+#pragma unroll
+        for (int u = 0; u < PPL; ++u) {
+            const int e = lane + 64 * u;
+            Pl[(e / BX) * LT + e % BX] = pr[u];
+        }
+        __syncthreads();
+        if (j > 0) {
+#pragma unroll
+            for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(j - 1) * BX * BX + lane + 64 * u];
+        }
+        for (int ct = 0; ct < nct; ++ct) {
+            const int qq = 16 * ct + li;
+            v4 acc[NTL];
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[tr][v] = qq < ncol ? Ws[(size_t)qq * n + j * BX + 16 * tr + M::row(lane, v)] : 0.f;
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int kk = 0; kk < BX; kk += 4)
+                    acc[tr] = M::op(Pl[(16 * tr + li) * LT + kk + lk], zf[(kk + lk) * RP + qq], acc[tr]);
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    wf[r * RP + qq] = acc[tr][v];
+                    if (qq < ncol) Xs[(size_t)qq * n + j * BX + r] += (double)acc[tr][v];
+                }
+        }
+        __syncthreads();
+    }
+}
+
 // Traces of the basis (columns 0..R-1) or of the particular solution
 // (column R) of the subdomains whose mask entry equals `want`, from the
 // stored cell values.
@@ -1158,6 +1364,22 @@ static hipError_t refine_bx(rmrcm_ctx* c, int part, int apply) {
     const Level& L = c->levels[c->D];
     const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY);
     const int ncol = part ? 1 : R;
+    if constexpr (BX >= 16) {
+        if (ncol <= 16 * (64 / BX)) {
+            const int RP = (ncol + 15) & ~15;
+            const size_t lds = carve_bytes(3 * BX * ncol, 8) + 2 * carve_bytes(BX * RP, 4) +
+                               carve_bytes(BX * (BX + 4), 4) + carve_bytes(BY * BX, 4) +
+                               carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4);
+            hipError_t e = hipFuncSetAttribute((const void*)k_local_refine_mfma<BX>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            const int nsub = c->geo.mx * c->geo.my;
+            hipLaunchKernelGGL(k_local_refine_mfma<BX>, dim3(nsub), dim3(64), lds, c->stream, c->geo,
+                               c->K, c->bct, c->beta, L.slotseg, R, c->P32, part ? c->pbar : c->Psi,
+                               part, c->q, c->bcv, c->Wsc, c->resid, c->fb, apply);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = carve_bytes(3 * BX * ncol, 8) + 2 * carve_bytes(BX * ncol, 4) +
                        carve_bytes(BY * BX, 4) + 2 * carve_bytes(ncol, 8) + carve_bytes(NF, 8) +
                        2 * carve_bytes(NF, 4);
