@@ -178,6 +178,45 @@ def ensemble_bench(nmem, steps, warmup):
             "setup_s": t_create, "generate_s": t_gen}
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_local_setup_grf1024_fp64_traffic.md")
+TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2009_07965_amd", "csrc", "k_local.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 local-setup kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
+    None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            txt = f.read()
+        with open(TRAFFIC_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in txt.splitlines():
+        if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_per_launch")):
+            k, v = line.split(":", 1)
+            vals[k.strip().lstrip("- ")] = v.strip().strip("`")
+    if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def copy_calibration(mib=512, reps=3):
+    """A plain device copy of known size (reads and writes mib MiB per
+    dispatch) to scale the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": n * 8, "bytes_written": n * 8, "dispatches": reps}
+
+
 def train_quick_surrogate(prob, path, npairs, seed=4000):
     """A small surrogate for the workload's subdomain size, trained on the
     GPU on pairs from the local solver (the learned mode needs one)."""
@@ -209,6 +248,9 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=3000)
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-only", action="store_true", help="time the FP64 mode only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 512 MiB device copy first (counter calibration)")
     ap.add_argument("--ensemble", type=int, default=64,
                     help="members of the ensemble batch measured beside the main line (0: skip)")
     args = ap.parse_args()
@@ -264,10 +306,12 @@ def main():
     def _rel(a, b):
         return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
+    calib = copy_calibration() if args.copy_calibration else None
     runs = {"fp64": measure(RMRCM_FP64)}
-    runs["mixed"] = measure(RMRCM_MIXED, ir_tol=args.ir_tol)
+    if not args.fp64_only:
+        runs["mixed"] = measure(RMRCM_MIXED, ir_tol=args.ir_tol)
     learned_info = None
-    if not args.no_learned:
+    if not args.no_learned and not args.fp64_only:
         wdir = tempfile.mkdtemp()
         wpath = os.path.join(wdir, "surrogate.bin")
         learned_info = train_quick_surrogate(prob, wpath, args.learned_pairs)
@@ -316,7 +360,8 @@ def main():
     achieved = amount / (t_k * 1e-3)
     roof = {"kernel": dom, "bound": bound, "achieved": achieved / scale,
             "peak": peak / scale, "unit": unit, "frac": achieved / peak,
-            "traffic": None, "avg_ms": t_k,
+            "traffic": measured_traffic() if (dom == "k_local_setup" and fp64_best) else None,
+            "avg_ms": t_k,
             "algorithmic": amount,
             "algorithmic_unit": "flop" if bound == "alu" else "byte"}
     out = {
@@ -341,11 +386,13 @@ def main():
                       "local_particular": t_part, "merge_particular": t_merge_p,
                       "down": t_down, "reconstruct": t_recon},
         "modes": modes,
-        "speedup_vs_fp64": modes.get("mixed+learned", modes["mixed"])["speedup_vs_fp64"],
+        "speedup_vs_fp64": modes.get("mixed+learned", modes.get("mixed", modes["fp64"]))["speedup_vs_fp64"],
         "roofline": roof,
     }
     if learned_info:
         out["surrogate"] = learned_info
+    if calib:
+        out["copy_calibration"] = calib
     if args.ensemble > 0:
         out["ensemble"] = ensemble_bench(args.ensemble, max(3, args.steps // 4), 1)
     if not args.no_cpu_baseline:
