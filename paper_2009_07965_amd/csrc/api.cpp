@@ -267,6 +267,14 @@ void free_all(rmrcm_ctx* c) {
     c->net = nullptr;
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->lev)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {c->ev_ls, c->ev_done, c->ev_aux})
+        if (e) (void)hipEventDestroy(e);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
 }
 
@@ -369,6 +377,11 @@ int mark(rmrcm_ctx* c, int i) {
     return RMRCM_OK;
 }
 
+// FP64 contexts outside graph capture run the particular chain (local
+// particular solves, merges of the particular column below the top) on the
+// auxiliary stream, each level after its own setup merge.
+bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c); }
+
 // Every permeability-dependent step, enqueued on c->stream (no host
 // synchronisation in FP64 mode, so that it can be captured in a graph).
 int enqueue_setup(rmrcm_ctx* c) {
@@ -383,7 +396,13 @@ int enqueue_setup(rmrcm_ctx* c) {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
     }
     TRY(mark(c, 2));
-    for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d));
+    const bool ov = overlap(c);
+    if (ov) HIP_TRY(hipEventRecord(c->ev_ls, c->stream));
+    for (int d = c->D - 1; d >= 0; --d) {
+        HIP_TRY(rmrcm::launch_merge_setup(c, d));
+        if (ov) HIP_TRY(hipEventRecord(c->lev[d], c->stream));
+    }
+    c->lev_recorded = ov;
     TRY(mark(c, 3));
     return RMRCM_OK;
 }
@@ -414,6 +433,43 @@ int solve_inputs(rmrcm_ctx* c, const double* source, const double* bc_value) {
     return RMRCM_OK;
 }
 
+// Solve with the particular chain on the auxiliary stream (FP64, see
+// overlap): the inputs (after the previous solve has finished with them),
+// the local particular solves (after the local setup) and the particular
+// column of every merge level below the top (each after that level's setup
+// merge); the main stream joins for the top level, the downward pass and
+// the reconstruction.
+int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value) {
+    hipStream_t main = c->stream;
+    c->stream = c->aux;
+    int r = RMRCM_OK;
+    hipError_t e = c->done_recorded ? hipStreamWaitEvent(c->aux, c->ev_done, 0) : hipSuccess;
+    if (e == hipSuccess) r = solve_inputs(c, source, bc_value);
+    if (e == hipSuccess && r == RMRCM_OK && !c->any_dirichlet) e = rmrcm::launch_compat_check(c);
+    if (e == hipSuccess && r == RMRCM_OK) e = hipStreamWaitEvent(c->aux, c->ev_ls, 0);
+    if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 1);
+    for (int d = c->D - 1; d >= 1 && e == hipSuccess && r == RMRCM_OK; --d) {
+        e = hipStreamWaitEvent(c->aux, c->lev[d], 0);
+        if (e == hipSuccess) e = rmrcm::launch_merge_particular(c, d);
+    }
+    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev_aux, c->aux);
+    c->stream = main;
+    TRY(r);
+    HIP_TRY(e);
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_aux, 0));
+    TRY(mark(c, 6));
+    HIP_TRY(rmrcm::launch_merge_particular(c, 0));
+    TRY(mark(c, 7));
+    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    TRY(mark(c, 8));
+    HIP_TRY(rmrcm::launch_reconstruct(c));
+    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
+    TRY(mark(c, 9));
+    HIP_TRY(hipEventRecord(c->ev_done, c->stream));
+    c->done_recorded = true;
+    return RMRCM_OK;
+}
+
 // Particular solutions, their merges, the top solve, the downward pass and
 // the reconstruction, enqueued on c->stream (graph-capturable in FP64 mode).
 int enqueue_solve(rmrcm_ctx* c) {
@@ -430,9 +486,8 @@ int enqueue_solve(rmrcm_ctx* c) {
         if (st != RMRCM_OK) return st;
         HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
         if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 2));
-    } else {
-        HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
     }
+    if (!mixed(c)) HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
     TRY(mark(c, 6));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
     TRY(mark(c, 7));
@@ -545,6 +600,17 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
     c->stream = c->own_stream;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return fail(RMRCM_EDEVICE);
+    if (prm->precision == RMRCM_FP64 && c->D > 0 && c->D <= 32) {
+        if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess)
+            return fail(RMRCM_EDEVICE);
+        for (int d = 0; d < c->D; ++d)
+            if (hipEventCreateWithFlags(&c->lev[d], hipEventDisableTiming) != hipSuccess)
+                return fail(RMRCM_EDEVICE);
+        if (hipEventCreateWithFlags(&c->ev_ls, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess)
+            return fail(RMRCM_EDEVICE);
+    }
     const Geo& g = c->geo;
     const size_t nsub = (size_t)g.mx * g.my;
     const size_t n = (size_t)g.bx * g.by;
@@ -617,8 +683,12 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
         for (double v : hb) s -= v, sa += std::fabs(v);
         if (!(std::fabs(s) <= 1e-12 * sa + 1e-300)) return RMRCM_EINVAL;
     }
-    TRY(solve_inputs(c, source, bc_value));
-    TRY(enqueue_solve(c));
+    if (overlap(c) && c->lev_recorded) {
+        TRY(solve_overlapped(c, source, bc_value));
+    } else {
+        TRY(solve_inputs(c, source, bc_value));
+        TRY(enqueue_solve(c));
+    }
     TRY(solve_outputs(c, pressure, flux));
     c->solve_recorded = true;
     const bool host_out = !is_device_ptr(pressure) || !is_device_ptr(flux);

@@ -99,6 +99,13 @@ struct rmrcm_ctx {
     size_t device_bytes = 0;
     // timing
     hipEvent_t ev[16] = {};
+    // FP64 overlap of the particular chain with the setup merges: an
+    // auxiliary stream, one event per merge level of the setup, the end of
+    // the local setup, the inputs of a solve and the end of the aux work
+    hipStream_t aux = nullptr;
+    hipEvent_t lev[32] = {};
+    hipEvent_t ev_ls = nullptr, ev_done = nullptr, ev_aux = nullptr;
+    bool lev_recorded = false, done_recorded = false;
     double t_setup_ms[8] = {};
     double t_solve_ms[8] = {};
     int64_t n_local_solves = 0;
