@@ -270,11 +270,15 @@ def main():
     bct = torch.from_numpy(prob.bc_type).to(dev)
     q = torch.from_numpy(prob.q).to(dev)
     bcv = torch.from_numpy(prob.bc_value).to(dev)
-    stream = torch.cuda.current_stream()
+    # a caller stream (not the null stream): the library then enqueues
+    # refactor and solve without waiting on the host between steps
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
 
     def measure(precision, **extra):
         p_out = torch.zeros((prob.ny, prob.nx), dtype=torch.float64, device=dev)
         f_out = torch.zeros((4, prob.ny, prob.nx), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
         S = Solver(prob.nx, prob.ny, K, bct, prob.sub_nx, prob.sub_ny, prob.seg,
                    alpha=prob.alpha, precision=precision, **extra)
         S.set_stream(stream.cuda_stream)

@@ -447,7 +447,9 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     if (e == hipSuccess) r = solve_inputs(c, source, bc_value);
     if (e == hipSuccess && r == RMRCM_OK && !c->any_dirichlet) e = rmrcm::launch_compat_check(c);
     if (e == hipSuccess && r == RMRCM_OK) e = hipStreamWaitEvent(c->aux, c->ev_ls, 0);
+    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[13], c->aux);
     if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 1);
+    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[14], c->aux);
     for (int d = c->D - 1; d >= 1 && e == hipSuccess && r == RMRCM_OK; --d) {
         e = hipStreamWaitEvent(c->aux, c->lev[d], 0);
         if (e == hipSuccess) e = rmrcm::launch_merge_particular(c, d);
@@ -467,6 +469,7 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     TRY(mark(c, 9));
     HIP_TRY(hipEventRecord(c->ev_done, c->stream));
     c->done_recorded = true;
+    c->solve_overlapped = true;
     return RMRCM_OK;
 }
 
@@ -683,6 +686,7 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
         for (double v : hb) s -= v, sa += std::fabs(v);
         if (!(std::fabs(s) <= 1e-12 * sa + 1e-300)) return RMRCM_EINVAL;
     }
+    c->solve_overlapped = false;
     if (overlap(c) && c->lev_recorded) {
         TRY(solve_overlapped(c, source, bc_value));
     } else {
@@ -750,7 +754,9 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
     }
     if (c->solve_recorded && hipEventSynchronize(c->ev[10]) == hipSuccess) {
         c->t_solve_ms[0] = elapsed(c->ev[4], c->ev[5]);
-        c->t_solve_ms[1] = elapsed(c->ev[5], c->ev[6]);
+        // overlapped solves: the local particular solves run on the
+        // auxiliary stream, between events 13 and 14
+        c->t_solve_ms[1] = c->solve_overlapped ? elapsed(c->ev[13], c->ev[14]) : elapsed(c->ev[5], c->ev[6]);
         c->t_solve_ms[2] = elapsed(c->ev[6], c->ev[7]);
         c->t_solve_ms[3] = elapsed(c->ev[7], c->ev[8]);
         c->t_solve_ms[4] = elapsed(c->ev[8], c->ev[9]);
@@ -772,12 +778,13 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         "\"device_bytes\": %zu, \"precision\": %d, \"ir_iters_setup\": %d, "
         "\"ir_iters_solve\": %d, \"ir_resid_setup\": %.3e, \"ir_resid_solve\": %.3e, "
         "\"fp64_fallback_subdomains\": %d, \"surrogate_accepted_subdomains\": %d, "
-        "\"gate_tol\": %.3e}",
+        "\"gate_tol\": %.3e, \"particular_overlapped\": %s}",
         c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
         c->t_solve_ms[1], c->t_solve_ms[2], c->t_solve_ms[3], c->t_solve_ms[4], c->t_solve_ms[5],
         c->t_solve_ms[6], c->D, c->geo.nseg, c->geo.mx * c->geo.my, (long long)c->n_local_solves,
         c->device_bytes, c->prm.precision, c->ir_iters_setup, c->ir_iters_solve, c->ir_resid_setup,
-        c->ir_resid_solve, c->n_fallback, c->n_accepted, c->prm.gate_tol);
+        c->ir_resid_solve, c->n_fallback, c->n_accepted, c->prm.gate_tol,
+        c->solve_overlapped ? "true" : "false");
     if (json && cap > 0) {
         std::strncpy(json, buf, cap - 1);
         json[cap - 1] = '\0';

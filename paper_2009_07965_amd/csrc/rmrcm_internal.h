@@ -106,6 +106,7 @@ struct rmrcm_ctx {
     hipEvent_t lev[32] = {};
     hipEvent_t ev_ls = nullptr, ev_done = nullptr, ev_aux = nullptr;
     bool lev_recorded = false, done_recorded = false;
+    bool solve_overlapped = false;  // the last solve ran the particular chain on aux
     double t_setup_ms[8] = {};
     double t_solve_ms[8] = {};
     int64_t n_local_solves = 0;
