@@ -196,9 +196,10 @@ def measured_traffic():
         return None
     vals = {}
     for line in txt.splitlines():
-        if ":" in line and line.strip().startswith(("source_sha256", "traffic_bytes_per_launch")):
+        line = line.strip().lstrip("-").strip()
+        if ":" in line and line.startswith(("source_sha256", "traffic_bytes_per_launch")):
             k, v = line.split(":", 1)
-            vals[k.strip().lstrip("- ")] = v.strip().strip("`")
+            vals[k.strip()] = v.strip().strip("`")
     if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
         return None
     return float(vals["traffic_bytes_per_launch"])

@@ -215,13 +215,16 @@ int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* co
                        const int8_t* const* bc_types, int32_t autotune, rmrcm_batch** out);
 
 /* rmrcm_refactor for every member (perms: count pointers).  Asynchronous;
- * device-detected errors are returned by rmrcm_batch_sync. */
+ * device-detected errors are returned by rmrcm_batch_sync.  Host arrays are
+ * copied into the member's pinned buffers before the call returns (they
+ * may be reused at once); device arrays are read in stream order. */
 int rmrcm_batch_refactor(rmrcm_batch* b, const double* const* perms);
 
 /* rmrcm_solve for every member: sources (count pointers, or NULL for all
  * zero; an entry may be NULL), bc_values, pressures (nx*ny) and fluxes
  * (4*nx*ny) per member, host or device.  Asynchronous: outputs are
- * complete after rmrcm_batch_sync. */
+ * complete after rmrcm_batch_sync (host outputs are copied from the
+ * member's pinned buffers by that call, or by the next rmrcm_batch_solve). */
 int rmrcm_batch_solve(rmrcm_batch* b, const double* const* sources, const double* const* bc_values,
                       double* const* pressures, double* const* fluxes);
 

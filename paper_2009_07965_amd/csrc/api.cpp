@@ -888,6 +888,22 @@ struct rmrcm_batch {
     int64_t cells = 0, local_solves = 0;
     size_t device_bytes = 0;
     int graphs = 0;
+    // Host arrays travel through pinned buffers of each member: inputs are
+    // copied there on the host and sent by DMA in stream order (a buffer is
+    // rewritten only once its previous DMA has completed); host outputs
+    // land there and are copied to the caller's arrays at the next sync.
+    struct Stage {
+        double* K = nullptr;
+        double* q = nullptr;
+        double* bcv = nullptr;
+        double* p = nullptr;
+        double* f = nullptr;
+        hipEvent_t in = nullptr;       // after the last DMA out of K / q / bcv
+        bool in_pending = false;
+        double* user_p = nullptr;      // host outputs to deliver at sync
+        double* user_f = nullptr;
+    };
+    std::vector<Stage> stage;
 };
 
 namespace {
@@ -902,6 +918,11 @@ void batch_free(rmrcm_batch* b) {
         if (g) (void)hipGraphExecDestroy(g);
     for (auto g : b->gsolve)
         if (g) (void)hipGraphExecDestroy(g);
+    for (auto& st : b->stage) {
+        for (double* p : {st.K, st.q, st.bcv, st.p, st.f})
+            if (p) (void)hipHostFree(p);
+        if (st.in) (void)hipEventDestroy(st.in);
+    }
     for (rmrcm_ctx* c : b->m) {
         if (c) c->stream = c->own_stream;
         rmrcm_destroy(c);
@@ -959,6 +980,45 @@ int join_streams(rmrcm_batch* b, hipEvent_t end) {
     return RMRCM_OK;
 }
 
+// Host-to-device copy of a member's input through its pinned buffer (a
+// device source is copied directly).
+int stage_in(rmrcm_batch::Stage& st, hipStream_t s, double* dst, const double* src, double* pin,
+             size_t count) {
+    if (is_device_ptr(src)) {
+        HIP_TRY(hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return RMRCM_OK;
+    }
+    if (st.in_pending) {
+        HIP_TRY(hipEventSynchronize(st.in));
+        st.in_pending = false;
+    }
+    std::memcpy(pin, src, count * sizeof(double));
+    HIP_TRY(hipMemcpyAsync(dst, pin, count * sizeof(double), hipMemcpyHostToDevice, s));
+    return RMRCM_OK;
+}
+
+int stage_in_done(rmrcm_batch::Stage& st, hipStream_t s) {
+    HIP_TRY(hipEventRecord(st.in, s));
+    st.in_pending = true;
+    return RMRCM_OK;
+}
+
+// Host outputs of the last solve, once the device has produced them.
+int deliver_outputs(rmrcm_batch* b) {
+    bool any = false;
+    for (auto& st : b->stage) any |= st.user_p || st.user_f;
+    if (!any) return RMRCM_OK;
+    HIP_TRY(hipStreamSynchronize(b->master));
+    for (size_t i = 0; i < b->m.size(); ++i) {
+        auto& st = b->stage[i];
+        const size_t ncell = (size_t)b->m[i]->geo.nx * b->m[i]->geo.ny;
+        if (st.user_p) std::memcpy(st.user_p, st.p, ncell * sizeof(double));
+        if (st.user_f) std::memcpy(st.user_f, st.f, 4 * ncell * sizeof(double));
+        st.user_p = st.user_f = nullptr;
+    }
+    return RMRCM_OK;
+}
+
 int batch_refactor(rmrcm_batch* b, const double* const* perms) {
     TRY(fork_streams(b, b->e[0]));
     for (size_t r = 0; r < b->order.size(); ++r) {
@@ -968,7 +1028,9 @@ int batch_refactor(rmrcm_batch* b, const double* const* perms) {
         c->solved = false;
         if (perms && perms[i]) {
             const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
-            HIP_TRY(hipMemcpyAsync(c->K, perms[i], ncell * sizeof(double), hipMemcpyDefault, c->stream));
+            auto& st = b->stage[i];
+            TRY(stage_in(st, c->stream, c->K, perms[i], st.K, ncell));
+            TRY(stage_in_done(st, c->stream));
         }
         if (b->gsetup[i]) {
             HIP_TRY(hipGraphLaunch(b->gsetup[i], c->stream));
@@ -985,18 +1047,35 @@ int batch_refactor(rmrcm_batch* b, const double* const* perms) {
 
 int batch_solve(rmrcm_batch* b, const double* const* sources, const double* const* bcv,
                 double* const* pressures, double* const* fluxes) {
+    TRY(deliver_outputs(b));        // host outputs of a previous solve first
     TRY(fork_streams(b, b->e[2]));
     for (size_t r = 0; r < b->order.size(); ++r) {
         const int i = b->order[r];
         rmrcm_ctx* c = b->m[i];
+        auto& st = b->stage[i];
         c->stream = b->streams[r % b->nstreams];
-        if (bcv) TRY(solve_inputs(c, sources ? sources[i] : nullptr, bcv[i]));
+        const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+        const size_t nbf = 2 * (size_t)c->geo.nx + 2 * (size_t)c->geo.ny;
+        if (bcv) {
+            if (sources && sources[i]) TRY(stage_in(st, c->stream, c->q, sources[i], st.q, ncell));
+            else HIP_TRY(rmrcm::launch_fill_f64(c, c->q, ncell, 0.0));
+            TRY(stage_in(st, c->stream, c->bcv, bcv[i], st.bcv, nbf));
+            TRY(stage_in_done(st, c->stream));
+        }
         if (b->gsolve[i]) {
             HIP_TRY(hipGraphLaunch(b->gsolve[i], c->stream));
         } else {
             TRY(enqueue_solve(c));
         }
-        if (pressures && fluxes) TRY(solve_outputs(c, pressures[i], fluxes[i]));
+        if (pressures && fluxes) {
+            const bool dp = is_device_ptr(pressures[i]), df = is_device_ptr(fluxes[i]);
+            HIP_TRY(hipMemcpyAsync(dp ? pressures[i] : st.p, c->pout, ncell * sizeof(double),
+                                   dp ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipMemcpyAsync(df ? fluxes[i] : st.f, c->fout, 4 * ncell * sizeof(double),
+                                   df ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+            st.user_p = dp ? nullptr : pressures[i];
+            st.user_f = df ? nullptr : fluxes[i];
+        }
         c->solve_recorded = !b->gsolve[i];
         c->solved = true;
     }
@@ -1058,6 +1137,22 @@ int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* co
     if (hipSetDevice(b->device) != hipSuccess) {
         batch_free(b);
         return RMRCM_EDEVICE;
+    }
+    b->stage.assign(count, rmrcm_batch::Stage());
+    for (int i = 0; i < count; ++i) {
+        auto& st = b->stage[i];
+        const size_t ncell = (size_t)b->m[i]->geo.nx * b->m[i]->geo.ny;
+        const size_t nbf = 2 * (size_t)b->m[i]->geo.nx + 2 * (size_t)b->m[i]->geo.ny;
+        if (hipHostMalloc((void**)&st.K, ncell * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&st.q, ncell * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&st.bcv, nbf * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&st.p, ncell * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&st.f, 4 * ncell * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&st.in, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            batch_free(b);
+            return RMRCM_ENOMEM;
+        }
     }
     // largest local work first (cells x subdomain width ~ band-Cholesky flops)
     b->order.resize(count);
@@ -1129,6 +1224,7 @@ int rmrcm_batch_sync(rmrcm_batch* b, int32_t* status) {
     if (!b) return RMRCM_EINVAL;
     if (hipSetDevice(b->device) != hipSuccess) return RMRCM_EDEVICE;
     HIP_TRY(hipStreamSynchronize(b->master));
+    TRY(deliver_outputs(b));
     int first = RMRCM_OK;
     for (size_t i = 0; i < b->m.size(); ++i) {
         rmrcm_ctx* c = b->m[i];
