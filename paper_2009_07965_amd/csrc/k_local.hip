@@ -522,7 +522,7 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     S* LTs = carve<S>(cur, BX * LT);        // row c = column c of L^{-1}
     S* Pl = carve<S>(cur, BX * LT);         // P_j, row-major
     S* Z = carve<S>(cur, BX * RP);          // z_j, later D_j x_{j+1}
-    S* Wl = carve<S>(cur, BX * RP);         // w_j, later x_j
+    S* Z2 = carve<S>(cur, BX * RP);         // the next row's z (double buffer)
     S* tys = carve<S>(cur, BY * BX);        // couplings D_j
     double* cf = carve<double>(cur, NF);
     int* rs = carve<int>(cur, NF);
@@ -606,7 +606,9 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
                 }
             }
         __syncthreads();
-        // ---- forward sweep w_j = P_j z_j
+        // ---- forward sweep w_j = P_j z_j; also D_j w_j, the next row's right-hand
+        // side (for the last row D_{BY-2} w_{BY-1}, the backward sweep's first)
+        const int jz = (j + 1 < BY) ? j : j - 1;
         for (int ct = 0; ct < nct; ++ct) {
 #pragma unroll
             for (int tr = 0; tr < NTL; ++tr) {
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * tr + M::row(lane, v);
-                    Wl[r * RP + q] = acc[v];
+                    if (jz >= 0) Z2[r * RP + q] = tys[jz * BX + r] * acc[v];
                     if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[v];
                 }
             }
@@ -649,9 +651,12 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
                 }
                 a[i] = v;
             }
-            // z_{j+1} = F_{j+1} + D_j w_j
-            for (int t = lane; t < BX * RP * (nct > 0); t += 64) Z[t] = tys[j * BX + t / RP] * Wl[t];
-            __syncthreads();
+            // z_{j+1} = F_{j+1} + D_j w_j (D_j w_j written by the sweep)
+            {
+                S* t = Z;
+                Z = Z2;
+                Z2 = t;
+            }
             const int jn = j + 1;
             if (lane == 0 && rs[jn] >= 0) Z[rs[jn]] += S(cf[jn]);
             if (lane == 1 && rs[BY + jn] >= 0) Z[(BX - 1) * RP + rs[BY + jn]] += S(cf[BY + jn]);
@@ -665,14 +670,18 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
         if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
         return;
     }
-    // ---- backward sweep: x_{BY-1} = w_{BY-1} (in Wl); x_j = w_j + P_j (D_j x_{j+1})
+    // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j (D_j x_{j+1})
     S pr[PPL];
     if (BY > 1) {
 #pragma unroll
         for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(BY - 2) * BX * BX + lane + 64 * u];
     }
     for (int j = BY - 2; j >= 0; --j) {
-        for (int t = lane; t < BX * RP; t += 64) Z[t] = tys[j * BX + t / RP] * Wl[t];
+        {                       // Z = D_j x_{j+1}, written by the previous sweep
+            S* t = Z;
+            Z = Z2;
+            Z2 = t;
+        }
 #pragma unroll
         for (int u = 0; u < PPL; ++u) {
             const int e = lane + 64 * u;
@@ -707,7 +716,7 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * tr + M::row(lane, v);
-                    Wl[r * RP + q] = acc[tr][v];
+                    if (j > 0) Z2[r * RP + q] = tys[(j - 1) * BX + r] * acc[tr][v];
                     if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[tr][v];
                 }
         }
