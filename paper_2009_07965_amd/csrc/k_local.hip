@@ -204,6 +204,30 @@ __device__ inline void stencil_coeffs(const Geo& g, const double kv[5], const do
 
 // Value of a register of lane l (l uniform, a compile-time constant at every
 // call) as a wave-uniform scalar.
+// Row coefficients of row j for a wave whose lane holds column c, from the
+// permeability k of its own cell and ku of the cell above (ku unused on the
+// top row).  The half-cell resistances are formed once per cell and shared
+// with the neighbours: h/(2k) of the right neighbour by a lane shuffle, the
+// coupling to the row below carried over from the previous row in tyd.  The
+// operands and their order are those of the two-point harmonic mean above, so
+// the coefficients are the same numbers.
+template <int BX>
+__device__ inline void row_coeffs(const Geo& g, const double* cf, int lane, int c, int j, double k,
+                                  double ku, double tyd, double* dg, double* txr, double* txl,
+                                  double* tyu) {
+    const int BY = g.by;
+    const double rx = g.hx / (2.0 * k);
+    const double rxr = __shfl(rx, lane < 63 ? lane + 1 : 63, 64);
+    const double tr = c < BX - 1 ? g.hy / (rx + rxr) : 0.0;
+    const double tl = __shfl(tr, lane > 0 ? lane - 1 : 0, 64);
+    const double tu = j < BY - 1 ? g.hx / (g.hy / (2.0 * k) + g.hy / (2.0 * ku)) : 0.0;
+    const double tlc = c > 0 ? tl : cf[j];
+    *dg = tlc + (c < BX - 1 ? tr : cf[BY + j]) + tyd + (j < BY - 1 ? tu : cf[2 * BY + BX + c]);
+    *txr = tr;
+    *txl = tl;
+    *tyu = tu;
+}
+
 __device__ inline double readlane_s(double v, int l) {
     const unsigned long long u = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), l);
@@ -539,17 +563,20 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     const int c = scol ? lane : (icol ? lane - BX : 0);
 
     face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
-    double kv[5], kn[5];
-    load_kstencil<BX>(g, K, I, J, c, 0, kv);
+    // permeability of column c, row by row: kq (row being set up), kq1 (the
+    // row above), kq2 (two rows above, in flight during a row's work)
+    const double* Kc = K + (size_t)J * BY * g.nx + (size_t)I * BX + c;
+    double kq = Kc[0];
+    double kq1 = BY > 1 ? Kc[g.nx] : 1.0;
+    double kq2 = 1.0;
     for (int t = lane; t < BX * RP; t += 64) Z[t] = S(0);
     __syncthreads();
 
     S a[BX];
     S p[BX];
     int sing = 0;
-    double dg, txr, tyu;
-    stencil_coeffs<BX>(g, kv, cf, c, 0, &dg, &txr, &tyu);
-    double txl = __shfl(txr, lane > 0 ? lane - 1 : 0, 64);
+    double dg, txr, txl, tyu;
+    row_coeffs<BX>(g, cf, lane, c, 0, kq, kq1, cf[2 * BY + c], &dg, &txr, &txl, &tyu);
 #pragma unroll
     for (int i = 0; i < BX; ++i) {
         double v = 0.0;
@@ -566,7 +593,7 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     __syncthreads();
 
     for (int j = 0; j < BY; ++j) {
-        if (j + 1 < BY) load_kstencil<BX>(g, K, I, J, c, j + 1, kn);
+        if (j + 2 < BY) kq2 = Kc[(size_t)(j + 2) * g.nx];
         // ---- Cholesky of S_j fused with the inversion of its factor
 #pragma unroll
         for (int k = 0; k < BX; ++k) {
@@ -585,7 +612,10 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
         }
         if (scol) tys[j * BX + c] = S(tyu);    // D_j
         __syncthreads();
-        // ---- P_j[r][c] = sum_{i >= max(r,c)} L^{-1}[i][r] L^{-1}[i][c] on the matrix cores
+        // ---- P_j[r][c] = sum_{i >= max(r,c)} L^{-1}[i][r] L^{-1}[i][c] on the matrix cores;
+        // once every tile is formed, L^{-1} is dead and its buffer takes the
+        // Schur term -(D_j P_j D_j)[r][c] of the next row, row-major
+        v4 pacc[NTL][NTL];
 #pragma unroll
         for (int tr = 0; tr < NTL; ++tr)
 #pragma unroll
@@ -598,13 +628,21 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
                     const S bv = LTs[(16 * tc + li) * LT + kk + lk];
                     acc = M::op(av, bv, acc);
                 }
+                pacc[tr][tc] = acc;
+            }
+        const bool trail = j + 1 < BY;
+#pragma unroll
+        for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < NTL; ++tc)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * tr + M::row(lane, v), cc = 16 * tc + li;
-                    Pl[r * LT + cc] = acc[v];
-                    Ps[(size_t)j * BX * BX + r * BX + cc] = acc[v];
+                    const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
+                    const S pv = pacc[tr][tc][v];
+                    Pl[r * LT + cq] = pv;
+                    Ps[(size_t)j * BX * BX + r * BX + cq] = pv;
+                    if (trail) LTs[r * LT + cq] = -(pv * (tys[j * BX + r] * tys[j * BX + cq]));
                 }
-            }
         __syncthreads();
         // ---- forward sweep w_j = P_j z_j; also D_j w_j, the next row's right-hand
         // side (for the last row D_{BY-2} w_{BY-1}, the backward sweep's first)
@@ -631,25 +669,23 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
         __syncthreads();
         if (j + 1 < BY) {
             // ---- trailing update S_{j+1} = A_{j+1} - D_j P_j D_j (lane c: column c)
-            if (scol) {
 #pragma unroll
-                for (int r = 0; r < BX; ++r) p[r] = Pl[r * LT + c];
-            }
-            const S dc = S(tyu);
-            stencil_coeffs<BX>(g, kn, cf, c, j + 1, &dg, &txr, &tyu);
-            txl = __shfl(txr, lane > 0 ? lane - 1 : 0, 64);
+            for (int r = 0; r < BX; ++r) p[r] = LTs[r * LT + c];     // -(D_j P_j D_j), column c
+            kq = kq1;
+            kq1 = kq2;
+            row_coeffs<BX>(g, cf, lane, c, j + 1, kq, kq1, tyu, &dg, &txr, &txl, &tyu);
+            // Selects rather than branches; cc is opaque to the optimiser so that
+            // the lane-dependent compares are formed here, not kept live across
+            // the whole row loop.
+            int cc = c;
+            asm volatile("" : "+v"(cc));
+            const S od = S(dg), orr = -S(txr), ol = -S(txl);
 #pragma unroll
             for (int i = 0; i < BX; ++i) {
-                S v = S(0);
-                if (scol) {
-                    v = -p[i] * (tys[j * BX + i] * dc);
-                    if (i == c) v += S(dg);
-                    else if (i == c + 1) v -= S(txr);
-                    else if (i + 1 == c) v -= S(txl);
-                } else if (icol) {
-                    v = (i == c) ? S(1) : S(0);
-                }
-                a[i] = v;
+                S off = (i == cc) ? od : S(0);
+                off = (i == cc + 1) ? orr : off;
+                off = (i + 1 == cc) ? ol : off;
+                a[i] = scol ? p[i] + off : ((icol && i == cc) ? S(1) : S(0));
             }
             // z_{j+1} = F_{j+1} + D_j w_j (D_j w_j written by the sweep)
             {

@@ -305,149 +305,202 @@ __global__ __launch_bounds__(256) void k_merge_trace(MergeArgs a, int col0, int 
 //     y1 = s - d,  y2 = s + d.
 // The all-Neumann top pins s of the last gamma segment to zero.
 //
-// Factor: one workgroup per merge; each g x g matrix is held in registers as
-// a cyclic (GT/TL)^2 thread grid of TL x TL tiles (row i = ti + TG a, column
-// j = tj + TG b), inverted by Gauss-Jordan elimination with one barrier per
-// step, and multiplied by panels of PW columns staged in LDS.
+// Factor, on the matrix cores (v_mfma_f64_16x16x4f64), one workgroup of
+// GT/16 waves per merge.
+//
+// Each g x g block is padded to GT x GT and split into 16 x 16 tiles; wave w
+// owns block column w and keeps its tiles in registers in the accumulator
+// layout: lane l, register v holds row l/16 + 4v, column l%16 of the tile.
+// That layout is also the B operand of the next product (k-slice s = v), so
+// the tiles a wave owns never leave its registers.
+//
+// Inversion: blocked Gauss-Jordan without pivoting, one 16-wide pivot block K
+// per step:  P = M_KK^{-1},  R_J = P M_KJ,  M_IJ -= M_IK R_J (I, J != K),
+// M_IK = -M_IK P,  M_KK = P.  The owner of block column K publishes it to LDS
+// (one barrier per step); every wave forms P itself from the symmetric block
+// by an LDL^T factorisation without pivoting, with L^{-1} built alongside:
+// P = L^{-T} diag(1/d) L^{-1}.  It needs only nonzero pivots (the blocks of D
+// and S are definite; those of a learned trace need not be).  Padding rows
+// and columns are identity rows and columns.  The products E = D^{-1} B and
+// N - B E take the shared operand block column by block column through LDS
+// panels, the next panel's loads in flight during the current one's MFMAs.
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ inline v4d mfma_f64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
-template <int GT, int TL>
-struct QdGrid {
-    static constexpr int TG = GT / TL;
-    static constexpr int NT = TG * TG;
-    static constexpr int PW = 8;
+template <int GT>
+struct QdM {
+    static constexpr int T = GT / 16;            // tiles per dimension = waves
+    static constexpr int NT = 64 * T;
+    static constexpr int CPL = 17;               // row stride of a column panel
+    static constexpr int LTL = 20;               // row stride of a wave's L^{-1}
 };
 
-// In-place Gauss-Jordan inversion without pivoting of the register-resident
-// g x g matrix v (zero outside g x g).  rowb/colb: [2][GT] LDS buffers.
-// Without pivoting the elimination order is free; it runs over the local
-// tile index kl first, so that register indices stay compile-time constants
-// (pivot k = kt + TG kl is owned by thread row / column kt).
-template <int GT, int TL>
-__device__ void gj_invert(int g, double (&v)[TL][TL], double* rowb, double* colb, int* bad) {
-    constexpr int TG = QdGrid<GT, TL>::TG;
-    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
-    int step = 0;
+__device__ inline double readlane_d(double v, int l) {
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), l);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// 1/d: hardware estimate and two Newton-Raphson steps y <- y + y (1 - d y).
+__device__ inline double rcp_refined(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    y = fma(y, fma(-d, y, 1.0), y);
+    y = fma(y, fma(-d, y, 1.0), y);
+    return y;
+}
+
+// P = M_KK^{-1} of the symmetric 16 x 16 block at rows 16K.. of the column
+// panel cpk (row stride CPL), returned in the accumulator layout.  lt, ls:
+// this wave's two 16 x LTL scratch blocks.  Lanes 0-15 hold the columns of
+// M_KK, lanes 16-31 the identity; eliminating below each pivot (multipliers
+// from the pivot row, by symmetry) leaves L^{-1} in lanes 16-31.
+__device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double* lt, double* ls,
+                                                 int* bad) {
+    typedef QdM<16> Q;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const bool scol = lane < 16, icol = lane >= 16 && lane < 32;
+    double a[16], rd[16];
 #pragma unroll
-    for (int kl = 0; kl < TL; ++kl) {
-        for (int kt = 0; kt < TG; ++kt, ++step) {
-            const int k = kt + TG * kl;
-            if (k >= g) break;
-            double* rb = rowb + (step & 1) * GT;
-            double* cb = colb + (step & 1) * GT;
-            const bool rown = ti == kt, coln = tj == kt;
-            if (rown)
+    for (int i = 0; i < 16; ++i)
+        a[i] = scol ? cpk[(16 * K + i) * Q::CPL + li] : ((icol && i == li) ? 1.0 : 0.0);
+    int sing = 0;
 #pragma unroll
-                for (int b = 0; b < TL; ++b) rb[tj + TG * b] = v[kl][b];
-            if (coln)
+    for (int k = 0; k < 16; ++k) {
+        double d = readlane_d(a[k], k);
+        if (!(d != 0.0 && isfinite(d))) {
+            sing = 1;
+            d = 1.0;
+        }
+        rd[k] = rcp_refined(d);
+        const double lrow = a[k] * rd[k];          // row k of L^T
 #pragma unroll
-                for (int a = 0; a < TL; ++a) cb[ti + TG * a] = v[a][kl];
-            __syncthreads();
-            const double piv = cb[k];
-            if (threadIdx.x == 0 && !(piv != 0.0 && isfinite(piv))) *bad = 1;
-            const double p = 1.0 / piv;
-            double c[TL], r[TL];
+        for (int i = k + 1; i < 16; ++i) a[i] = fma(-readlane_d(lrow, i), a[k], a[i]);
+    }
+    if (sing && lane == 0) *bad = 1;
+    if (icol) {
 #pragma unroll
-            for (int a = 0; a < TL; ++a) c[a] = cb[ti + TG * a] * p;
-#pragma unroll
-            for (int b = 0; b < TL; ++b) r[b] = rb[tj + TG * b];
-            // pivot row becomes row/piv, pivot column -col/piv, pivot 1/piv
-            if (rown) {
-                c[kl] = -p;
-#pragma unroll
-                for (int b = 0; b < TL; ++b) v[kl][b] = 0.0;
-            }
-            if (coln) {
-                r[kl] = 1.0;
-#pragma unroll
-                for (int a = 0; a < TL; ++a) v[a][kl] = 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < TL; ++a)
-#pragma unroll
-                for (int b = 0; b < TL; ++b) v[a][b] -= c[a] * r[b];
+        for (int i = 0; i < 16; ++i) {
+            lt[li * Q::LTL + i] = a[i];             // row c = column c of L^{-1}
+            ls[li * Q::LTL + i] = a[i] * rd[i];     // the same scaled by 1/d_i
         }
     }
     __syncthreads();
+    // P[r][c] = sum_i L^{-1}[i][r] (1/d_i) L^{-1}[i][c]
+    v4d P = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        P = mfma_f64(lt[li * Q::LTL + 4 * s + lk], ls[li * Q::LTL + 4 * s + lk], P);
+    return P;
 }
 
-// acc += (SGN) A B over k < g.  One operand is register-resident and
-// published PW columns (A) or rows (B) at a time through the ping-pong
-// buffer buf[2][GT][PW] / buf[2][PW][GT]; the other is whole in LDS
-// (row-major, leading dimension GT).
-template <int GT, int TL, int SGN>
-__device__ void summa_reg_lds(int g, double (&acc)[TL][TL], const double (&ar)[TL][TL],
-                              const double* Bl, double* buf) {
-    constexpr int TG = QdGrid<GT, TL>::TG, PW = QdGrid<GT, TL>::PW;
-    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
-    int pp = 0;
-    for (int k0 = 0; k0 < g; k0 += PW, pp ^= 1) {
-        double* A = buf + pp * GT * PW;
+// In-place inversion of the register-resident matrix m (block column w of
+// the wave).  cp: two column panels.
+template <int GT>
+__device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* lt, double* ls, double* pw,
+                           int* bad) {
+    typedef QdM<GT> Q;
+    constexpr int T = Q::T, CPL = Q::CPL;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    for (int K = 0; K < T; ++K) {
+        double* c = cp + (K & 1) * GT * CPL;
+        // the owner publishes block column K (before any update of this step)
+        if (w == K) {
 #pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int j = tj + TG * q;
-            if (j >= k0 && j < k0 + PW)
+            for (int I = 0; I < T; ++I)
 #pragma unroll
-                for (int p = 0; p < TL; ++p) A[(ti + TG * p) * PW + (j - k0)] = ar[p][q];
+                for (int v = 0; v < 4; ++v) c[(16 * I + lk + 4 * v) * CPL + li] = m[I][v];
         }
         __syncthreads();
-        const int kw = min(PW, g - k0);
-        for (int kk = 0; kk < kw; ++kk) {
-            double av[TL], bv[TL];
+        const v4d P = qd_pivot_inverse(c, K, lt, ls, bad);
+        if (w == K) {
+            // pivot block column: M_IK = -M_IK P, M_KK = P
 #pragma unroll
-            for (int p = 0; p < TL; ++p) av[p] = A[(ti + TG * p) * PW + kk];
+            for (int I = 0; I < T; ++I) {
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < TL; ++q) bv[q] = Bl[(k0 + kk) * GT + tj + TG * q];
+                for (int s = 0; s < 4; ++s)
+                    acc = mfma_f64(-c[(16 * I + li) * CPL + 4 * s + lk], P[s], acc);
+                m[I] = (I == K) ? P : acc;
+            }
+        } else {
+            // P as an A operand (lane l: P[l%16][4s + l/16]) through this wave's LDS
 #pragma unroll
-            for (int p = 0; p < TL; ++p)
+            for (int v = 0; v < 4; ++v) pw[(lk + 4 * v) * 17 + li] = P[v];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            double pa[4];
 #pragma unroll
-                for (int q = 0; q < TL; ++q) acc[p][q] += SGN * av[p] * bv[q];
+            for (int s = 0; s < 4; ++s) pa[s] = pw[li * 17 + 4 * s + lk];
+            v4d mk = m[0];
+#pragma unroll
+            for (int I = 1; I < T; ++I)
+                if (I == K) mk = m[I];
+            v4d R = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) R = mfma_f64(pa[s], mk[s], R);
+#pragma unroll
+            for (int I = 0; I < T; ++I) {
+                if (I == K) {
+                    m[I] = R;
+                    continue;
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    m[I] = mfma_f64(-c[(16 * I + li) * CPL + 4 * s + lk], R[s], m[I]);
+            }
         }
     }
     __syncthreads();
 }
 
-template <int GT, int TL, int SGN>
-__device__ void summa_lds_reg(int g, double (&acc)[TL][TL], const double* Al,
-                              const double (&br)[TL][TL], double* buf) {
-    constexpr int TG = QdGrid<GT, TL>::TG, PW = QdGrid<GT, TL>::PW;
-    const int ti = threadIdx.x / TG, tj = threadIdx.x % TG;
-    int pp = 0;
-    for (int k0 = 0; k0 < g; k0 += PW, pp ^= 1) {
-        double* B = buf + pp * PW * GT;
+// Stores the wave's tiles (rows and columns below g) to the row-major g x g
+// block X; pin: the all-Neumann top's pinned entry is stored as zero.
+template <int GT>
+__device__ void qd_store(const v4d (&m)[QdM<GT>::T], int g, double* X, bool pin) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
 #pragma unroll
-        for (int p = 0; p < TL; ++p) {
-            const int i = ti + TG * p;
-            if (i >= k0 && i < k0 + PW)
+    for (int I = 0; I < QdM<GT>::T; ++I)
 #pragma unroll
-                for (int q = 0; q < TL; ++q) B[(i - k0) * GT + tj + TG * q] = br[p][q];
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + lk + 4 * v, j = 16 * w + li;
+            if (i < g && j < g) X[(size_t)i * g + j] = (pin && i == g - 1 && j == g - 1) ? 0.0 : m[I][v];
         }
-        __syncthreads();
-        const int kw = min(PW, g - k0);
-        for (int kk = 0; kk < kw; ++kk) {
-            double av[TL], bv[TL];
-#pragma unroll
-            for (int p = 0; p < TL; ++p) av[p] = Al[(ti + TG * p) * GT + k0 + kk];
-#pragma unroll
-            for (int q = 0; q < TL; ++q) bv[q] = B[kk * GT + tj + TG * q];
-#pragma unroll
-            for (int p = 0; p < TL; ++p)
-#pragma unroll
-                for (int q = 0; q < TL; ++q) acc[p][q] += SGN * av[p] * bv[q];
-        }
-    }
-    __syncthreads();
 }
 
-template <int GT, int TL>
-__global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a) {
-    constexpr int TG = QdGrid<GT, TL>::TG, NT = QdGrid<GT, TL>::NT, PW = QdGrid<GT, TL>::PW;
-    __shared__ double Bl[GT * GT];               // B = T2gg - T1gg, resident
-    __shared__ double buf[2 * GT * PW];
-    __shared__ double rowb[2 * GT], colb[2 * GT];
+// Block column K of the row-major g x g block X (zero outside g x g): four
+// entries per thread, consecutive threads on consecutive columns.
+template <int GT>
+__device__ inline void qd_panel_load(const double* X, int g, int K, double (&r)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + QdM<GT>::NT * q, row = e >> 4, col = 16 * K + (e & 15);
+        r[q] = (row < g && col < g) ? X[(size_t)row * g + col] : 0.0;
+    }
+}
+template <int GT>
+__device__ inline void qd_panel_put(double* pn, const double (&r)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + QdM<GT>::NT * q;
+        pn[(e >> 4) * QdM<GT>::CPL + (e & 15)] = r[q];
+    }
+}
+
+template <int GT>
+__global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
+    typedef QdM<GT> Q;
+    constexpr int T = Q::T, CPL = Q::CPL;
+    __shared__ double cp[2 * GT * CPL];
+    __shared__ double lts[2 * T * 16 * Q::LTL];
+    __shared__ double pws[T * 16 * 17];
     __shared__ double wv[GT];
     __shared__ int gi1[GT], gi2[GT];
     __shared__ int bad;
-    const int tid = threadIdx.x, ti = tid / TG, tj = tid % TG;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int node = blockIdx.x, g = a.g;
     int c1, c2;
     children(a, node, &c1, &c2);
@@ -455,7 +508,7 @@ __global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a
     const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
     const int* ss1 = a.css + (size_t)c1 * a.cnslot;
     if (tid == 0) bad = 0;
-    for (int t = tid; t < g; t += NT) {
+    for (int t = tid; t < g; t += Q::NT) {
         gi1[t] = a.gmap[t];
         gi2[t] = a.gmap[g + t];
         const int e = ss1[gi1[t]] >> 1;
@@ -467,79 +520,123 @@ __global__ __launch_bounds__((GT / TL) * (GT / TL)) void k_qd_factor(MergeArgs a
     double* Eg = Dg + gg;
     double* Sg = Eg + gg;
     double* Bg = Sg + gg;
-    // the gamma blocks of both children: every load issued before any store
-    double v[TL][TL], u[TL][TL];
+    double* lt = lts + 2 * w * 16 * Q::LTL;
+    double* ls = lt + 16 * Q::LTL;
+    double* pw = pws + w * 16 * 17;
+    const int j = 16 * w + li;                   // the column this lane holds
+    // the gamma blocks of both children: B and N to global memory, D in
+    // registers (four tiles' loads in flight at a time)
+    constexpr int CI = T < 4 ? T : 4;
+    v4d m[T];
 #pragma unroll
-    for (int p = 0; p < TL; ++p)
+    for (int I0 = 0; I0 < T; I0 += CI) {
+        double t1[CI][4], t2[CI][4];
 #pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int i = ti + TG * p, j = tj + TG * q;
-            const bool in = i < g && j < g;
-            v[p][q] = in ? T1[(size_t)gi1[i] * a.cld + gi1[j]] : 0.0;
-            u[p][q] = in ? T2[(size_t)gi2[i] * a.cld + gi2[j]] : 0.0;
-        }
+        for (int u = 0; u < CI; ++u)
 #pragma unroll
-    for (int p = 0; p < TL; ++p)
-#pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int i = ti + TG * p, j = tj + TG * q;
-            const double b = u[p][q] - v[p][q], nv = v[p][q] + u[p][q];
-            Bl[(ti + TG * p) * GT + tj + TG * q] = b;
-            if (i < g && j < g) {
-                Bg[(size_t)i * g + j] = b;
-                Sg[(size_t)i * g + j] = nv;     // N = T1gg + T2gg, parked until the Schur step
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * (I0 + u) + lk + 4 * v;
+                const bool in = i < g && j < g;
+                t1[u][v] = in ? T1[(size_t)gi1[i] * a.cld + gi1[j]] : 0.0;
+                t2[u][v] = in ? T2[(size_t)gi2[i] * a.cld + gi2[j]] : 0.0;
             }
-            v[p][q] = nv + (i == j && i < g ? 4.0 * wv[i] : 0.0);    // D
-        }
-    gj_invert<GT, TL>(g, v, rowb, colb, &bad);     // v = D^{-1}
 #pragma unroll
-    for (int p = 0; p < TL; ++p)
+        for (int u = 0; u < CI; ++u)
 #pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int i = ti + TG * p, j = tj + TG * q;
-            if (i < g && j < g) Dg[(size_t)i * g + j] = v[p][q];
-        }
-    // E = D^{-1} B
-#pragma unroll
-    for (int p = 0; p < TL; ++p)
-#pragma unroll
-        for (int q = 0; q < TL; ++q) u[p][q] = 0.0;
-    summa_reg_lds<GT, TL, 1>(g, u, v, Bl, buf);
-#pragma unroll
-    for (int p = 0; p < TL; ++p)
-#pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int i = ti + TG * p, j = tj + TG * q;
-            if (i < g && j < g) Eg[(size_t)i * g + j] = u[p][q];
-        }
-    // S = N - B E (each thread reads back only the N entries it stored)
-    double nn[TL][TL];
-#pragma unroll
-    for (int p = 0; p < TL; ++p)
-#pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int i = ti + TG * p, j = tj + TG * q;
-            nn[p][q] = (i < g && j < g) ? Sg[(size_t)i * g + j] : 0.0;
-        }
-    summa_lds_reg<GT, TL, -1>(g, nn, Bl, u, buf);
-    if (a.pin) {
-#pragma unroll
-        for (int p = 0; p < TL; ++p)
-#pragma unroll
-            for (int q = 0; q < TL; ++q) {
-                const int i = ti + TG * p, j = tj + TG * q;
-                if (i == g - 1 || j == g - 1) nn[p][q] = (i == j) ? 1.0 : 0.0;
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * (I0 + u) + lk + 4 * v;
+                const double nv = t1[u][v] + t2[u][v];
+                if (i < g && j < g) {
+                    Bg[(size_t)i * g + j] = t2[u][v] - t1[u][v];
+                    Sg[(size_t)i * g + j] = nv;         // N, parked until the Schur step
+                    m[I0 + u][v] = nv + (i == j ? 4.0 * wv[i] : 0.0);
+                } else {
+                    m[I0 + u][v] = (i == j) ? 1.0 : 0.0;
+                }
             }
     }
-    gj_invert<GT, TL>(g, nn, rowb, colb, &bad);    // nn = S^{-1}
+    qd_gj_mfma<GT>(m, cp, lt, ls, pw, &bad);              // D^{-1}
+    qd_store<GT>(m, g, Dg, false);
+    __syncthreads();                                       // D^{-1}, B, N visible to the workgroup
+    // E = D^{-1} B (block column w): block column K of D^{-1} staged in LDS
+    // (the next one in flight meanwhile), B_KJ from global memory
+    {
+        double r[4], bcur[4], bnext[4];
+        qd_panel_load<GT>(Dg, g, 0, r);
+        qd_panel_put<GT>(cp, r);
 #pragma unroll
-    for (int p = 0; p < TL; ++p)
-#pragma unroll
-        for (int q = 0; q < TL; ++q) {
-            const int i = ti + TG * p, j = tj + TG * q;
-            if (i < g && j < g)
-                Sg[(size_t)i * g + j] = (a.pin && i == g - 1 && j == g - 1) ? 0.0 : nn[p][q];
+        for (int s = 0; s < 4; ++s) {
+            const int k = 4 * s + lk;
+            bcur[s] = (k < g && j < g) ? Bg[(size_t)k * g + j] : 0.0;
         }
+        __syncthreads();
+#pragma unroll
+        for (int I = 0; I < T; ++I) m[I] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int K = 0; K < T; ++K) {
+            const double* pn = cp + (K & 1) * GT * CPL;
+            if (K + 1 < T) {
+                qd_panel_load<GT>(Dg, g, K + 1, r);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int k = 16 * (K + 1) + 4 * s + lk;
+                    bnext[s] = (k < g && j < g) ? Bg[(size_t)k * g + j] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int s = 0; s < 4; ++s) m[I] = mfma_f64(pn[(16 * I + li) * CPL + 4 * s + lk], bcur[s], m[I]);
+            if (K + 1 < T) {
+                qd_panel_put<GT>(cp + ((K + 1) & 1) * GT * CPL, r);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) bcur[s] = bnext[s];
+            }
+            __syncthreads();
+        }
+    }
+    qd_store<GT>(m, g, Eg, false);
+    // S = N - B E (block column w; E_KJ is the wave's own tile m[K]): block
+    // column K of B staged in LDS
+    {
+        v4d acc[T];
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + lk + 4 * v;
+                acc[I][v] = (i < g && j < g) ? Sg[(size_t)i * g + j] : (i == j ? 1.0 : 0.0);
+            }
+        double r[4];
+        qd_panel_load<GT>(Bg, g, 0, r);
+        qd_panel_put<GT>(cp, r);
+        __syncthreads();
+#pragma unroll
+        for (int K = 0; K < T; ++K) {
+            const double* pn = cp + (K & 1) * GT * CPL;
+            if (K + 1 < T) qd_panel_load<GT>(Bg, g, K + 1, r);
+#pragma unroll
+            for (int I = 0; I < T; ++I)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[I] = mfma_f64(-pn[(16 * I + li) * CPL + 4 * s + lk], m[K][s], acc[I]);
+            if (K + 1 < T) qd_panel_put<GT>(cp + ((K + 1) & 1) * GT * CPL, r);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int I = 0; I < T; ++I) m[I] = acc[I];
+    }
+    if (a.pin) {
+        // all-Neumann top: s of the last gamma segment is pinned
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + lk + 4 * v;
+                if (i == g - 1 || j == g - 1) m[I][v] = (i == j) ? 1.0 : 0.0;
+            }
+    }
+    qd_gj_mfma<GT>(m, cp, lt, ls, pw, &bad);              // S^{-1}
+    qd_store<GT>(m, g, Sg, a.pin);
     if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
 }
 
@@ -553,8 +650,8 @@ __host__ __device__ constexpr int qd_ct() { return GT >= 128 ? 8 : 16; }
 // out[i][c] (= or -=) sum_k A[i][k] in[k][c] for i < g, c < CT; A g x g
 // row-major in global memory, staged in Al with leading dimension g + 1.
 template <int GT, int CT, bool SUB>
-__device__ void qd_prod(int g, const double* __restrict__ A, const double* in, double* out,
-                        double* Al) {
+__device__ __forceinline__ void qd_prod(int g, const double* __restrict__ A, const double* in,
+                                        double* out, double* Al) {
     constexpr int RG = 256 / CT, RPT = (GT + RG - 1) / RG;
     constexpr int NL = (GT * GT + 255) / 256, CH = NL > 32 ? 32 : NL;
     const int tid = threadIdx.x, c = tid % CT, r0 = tid / CT;
@@ -808,13 +905,6 @@ static hipError_t solve_cols_generic(rmrcm_ctx* c, const MergeArgs& a, int col0,
 // Size class of the pivot-free path (0: gamma too long, generic LU path).
 static int qd_tier(int g) { return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : 0; }
 
-template <int GT, int TL>
-static hipError_t qd_factor(rmrcm_ctx* c, const MergeArgs& a) {
-    hipLaunchKernelGGL((k_qd_factor<GT, TL>), dim3(a.nnodes), dim3(QdGrid<GT, TL>::NT), 0, c->stream,
-                       a);
-    return hipGetLastError();
-}
-
 template <int GT>
 static hipError_t qd_apply(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, int ct) {
     if (ncol == 1) ct = 1;
@@ -844,12 +934,18 @@ static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int nco
     return hipGetLastError();
 }
 
+template <int GT>
+static hipError_t qd_factor_mfma(rmrcm_ctx* c, const MergeArgs& a) {
+    hipLaunchKernelGGL(k_qd_factor_mfma<GT>, dim3(a.nnodes), dim3(QdM<GT>::NT), 0, c->stream, a);
+    return hipGetLastError();
+}
+
 static hipError_t qd_factor_any(rmrcm_ctx* c, const MergeArgs& a) {
     switch (qd_tier(a.g)) {
-        case 16: return qd_factor<16, 2>(c, a);
-        case 32: return qd_factor<32, 4>(c, a);
-        case 64: return qd_factor<64, 4>(c, a);
-        case 128: return qd_factor<128, 4>(c, a);
+        case 16: return qd_factor_mfma<16>(c, a);
+        case 32: return qd_factor_mfma<32>(c, a);
+        case 64: return qd_factor_mfma<64>(c, a);
+        case 128: return qd_factor_mfma<128>(c, a);
     }
     return hipErrorInvalidValue;
 }
