@@ -706,11 +706,27 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
         if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
         return;
     }
-    // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j (D_j x_{j+1})
+    // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j (D_j x_{j+1}).
+    // P_{j-1} and w_{j-1} (of the first WCT column tiles) are loaded one row
+    // ahead.
+    constexpr int WCT = 2;
     S pr[PPL];
+    v4 wn[WCT][NTL];
+    auto load_w = [&](int jr) {
+#pragma unroll
+        for (int ct = 0; ct < WCT; ++ct)
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = 16 * ct + li, r = 16 * tr + M::row(lane, v);
+                    wn[ct][tr][v] = (ct < nct && q < R) ? S(Psub[(size_t)q * n + jr * BX + r]) : S(0);
+                }
+    };
     if (BY > 1) {
 #pragma unroll
         for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(BY - 2) * BX * BX + lane + 64 * u];
+        load_w(BY - 2);
     }
     for (int j = BY - 2; j >= 0; --j) {
         {                       // Z = D_j x_{j+1}, written by the previous sweep
@@ -723,21 +739,19 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
             const int e = lane + 64 * u;
             Pl[(e / BX) * LT + e % BX] = pr[u];
         }
+        v4 wc[WCT][NTL];
+#pragma unroll
+        for (int ct = 0; ct < WCT; ++ct)
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr) wc[ct][tr] = wn[ct][tr];
         __syncthreads();
         if (j > 0) {
 #pragma unroll
             for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(j - 1) * BX * BX + lane + 64 * u];
+            load_w(j - 1);
         }
-        for (int ct = 0; ct < nct; ++ct) {
+        auto tile = [&](int ct, v4 (&acc)[NTL]) {
             const int q = 16 * ct + li;
-            v4 acc[NTL];
-#pragma unroll
-            for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * tr + M::row(lane, v);
-                    acc[tr][v] = q < R ? S(Psub[(size_t)q * n + j * BX + r]) : S(0);
-                }
 #pragma unroll
             for (int tr = 0; tr < NTL; ++tr) {
 #pragma unroll
@@ -755,6 +769,21 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
                     if (j > 0) Z2[r * RP + q] = tys[(j - 1) * BX + r] * acc[tr][v];
                     if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[tr][v];
                 }
+        };
+#pragma unroll
+        for (int ct = 0; ct < WCT; ++ct)
+            if (ct < nct) tile(ct, wc[ct]);
+        for (int ct = WCT; ct < nct; ++ct) {
+            const int q = 16 * ct + li;
+            v4 acc[NTL];
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    acc[tr][v] = q < R ? S(Psub[(size_t)q * n + j * BX + r]) : S(0);
+                }
+            tile(ct, acc);
         }
         __syncthreads();
     }

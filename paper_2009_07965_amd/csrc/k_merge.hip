@@ -337,6 +337,13 @@ struct QdM {
     static constexpr int LTL = 20;               // row stride of a wave's L^{-1}
 };
 
+// Orders this wave's LDS writes before its later LDS reads by other lanes.
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline double readlane_d(double v, int l) {
     const unsigned long long u = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), l);
@@ -387,7 +394,7 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
             ls[li * Q::LTL + i] = a[i] * rd[i];     // the same scaled by 1/d_i
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     // P[r][c] = sum_i L^{-1}[i][r] (1/d_i) L^{-1}[i][c]
     v4d P = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -397,24 +404,41 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
 }
 
 // In-place inversion of the register-resident matrix m (block column w of
-// the wave).  cp: two column panels.
+// the wave).  cp: two column panels, pt: two 16 x 17 tiles for P.  Look-ahead:
+// in step K the owner of block column K + 1 updates its column first, then
+// publishes it and forms P_{K+1} while the other waves finish step K.
 template <int GT>
-__device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* lt, double* ls, double* pw,
+__device__ __forceinline__ void qd_publish(const v4d (&m)[QdM<GT>::T], double* c) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int I = 0; I < QdM<GT>::T; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) c[(16 * I + lk + 4 * v) * QdM<GT>::CPL + li] = m[I][v];
+    wave_lds_sync();
+}
+
+template <int GT>
+__device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* pt, double* lt, double* ls,
                            int* bad) {
     typedef QdM<GT> Q;
     constexpr int T = Q::T, CPL = Q::CPL;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    if (w == 0) {
+        qd_publish<GT>(m, cp);
+        const v4d P = qd_pivot_inverse(cp, 0, lt, ls, bad);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pt[(lk + 4 * v) * 17 + li] = P[v];
+    }
+    __syncthreads();
     for (int K = 0; K < T; ++K) {
-        double* c = cp + (K & 1) * GT * CPL;
-        // the owner publishes block column K (before any update of this step)
-        if (w == K) {
+        const double* c = cp + (K & 1) * GT * CPL;
+        const double* pk = pt + (K & 1) * 16 * 17;
+        v4d P;
+        double pa[4];
 #pragma unroll
-            for (int I = 0; I < T; ++I)
+        for (int v = 0; v < 4; ++v) P[v] = pk[(lk + 4 * v) * 17 + li];     // B operand layout
 #pragma unroll
-                for (int v = 0; v < 4; ++v) c[(16 * I + lk + 4 * v) * CPL + li] = m[I][v];
-        }
-        __syncthreads();
-        const v4d P = qd_pivot_inverse(c, K, lt, ls, bad);
+        for (int s = 0; s < 4; ++s) pa[s] = pk[li * 17 + 4 * s + lk];      // A operand layout
         if (w == K) {
             // pivot block column: M_IK = -M_IK P, M_KK = P
 #pragma unroll
@@ -426,15 +450,6 @@ __device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* lt, double*
                 m[I] = (I == K) ? P : acc;
             }
         } else {
-            // P as an A operand (lane l: P[l%16][4s + l/16]) through this wave's LDS
-#pragma unroll
-            for (int v = 0; v < 4; ++v) pw[(lk + 4 * v) * 17 + li] = P[v];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            double pa[4];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) pa[s] = pw[li * 17 + 4 * s + lk];
             v4d mk = m[0];
 #pragma unroll
             for (int I = 1; I < T; ++I)
@@ -452,9 +467,17 @@ __device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* lt, double*
                 for (int s = 0; s < 4; ++s)
                     m[I] = mfma_f64(-c[(16 * I + li) * CPL + 4 * s + lk], R[s], m[I]);
             }
+            if (w == K + 1) {
+                double* cn = cp + ((K + 1) & 1) * GT * CPL;
+                qd_publish<GT>(m, cn);
+                const v4d Pn = qd_pivot_inverse(cn, K + 1, lt, ls, bad);
+                double* pn = pt + ((K + 1) & 1) * 16 * 17;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pn[(lk + 4 * v) * 17 + li] = Pn[v];
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // Stores the wave's tiles (rows and columns below g) to the row-major g x g
@@ -496,7 +519,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
     constexpr int T = Q::T, CPL = Q::CPL;
     __shared__ double cp[2 * GT * CPL];
     __shared__ double lts[2 * T * 16 * Q::LTL];
-    __shared__ double pws[T * 16 * 17];
+    __shared__ double pt[2 * 16 * 17];
     __shared__ double wv[GT];
     __shared__ int gi1[GT], gi2[GT];
     __shared__ int bad;
@@ -522,7 +545,6 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
     double* Bg = Sg + gg;
     double* lt = lts + 2 * w * 16 * Q::LTL;
     double* ls = lt + 16 * Q::LTL;
-    double* pw = pws + w * 16 * 17;
     const int j = 16 * w + li;                   // the column this lane holds
     // the gamma blocks of both children: B and N to global memory, D in
     // registers (four tiles' loads in flight at a time)
@@ -555,7 +577,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
                 }
             }
     }
-    qd_gj_mfma<GT>(m, cp, lt, ls, pw, &bad);              // D^{-1}
+    qd_gj_mfma<GT>(m, cp, pt, lt, ls, &bad);              // D^{-1}
     qd_store<GT>(m, g, Dg, false);
     __syncthreads();                                       // D^{-1}, B, N visible to the workgroup
     // E = D^{-1} B (block column w): block column K of D^{-1} staged in LDS
@@ -635,7 +657,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
                 if (i == g - 1 || j == g - 1) m[I][v] = (i == j) ? 1.0 : 0.0;
             }
     }
-    qd_gj_mfma<GT>(m, cp, lt, ls, pw, &bad);              // S^{-1}
+    qd_gj_mfma<GT>(m, cp, pt, lt, ls, &bad);              // S^{-1}
     qd_store<GT>(m, g, Sg, a.pin);
     if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
 }
@@ -743,6 +765,150 @@ __global__ __launch_bounds__(256) void k_qd_apply(MergeArgs a, int col0, int nco
         const double s = rd[t], d = tt[t];
         X[(size_t)i * a.ld + cb + cc] = -(s - d);
         X[(size_t)(g + i) * a.ld + cb + cc] = -(s + d);
+    }
+}
+
+// The same columns on the matrix cores, 16 per workgroup: each of the four
+// products is A (g x g, row-major in global memory) times a g x 16 block held
+// in LDS (rows padded to GT, leading dimension kAL); wave w forms row tiles
+// I = w, w + NW, .. with every k-slice of A for the tile loaded at once.
+constexpr int kAL = 17;
+template <int GT>
+__host__ __device__ constexpr int qd_apply_waves() { return GT / 16 > 4 ? GT / 16 : 4; }
+
+template <int GT>
+__device__ __forceinline__ void qd_prod_mfma(int g, const double* __restrict__ A, const double* in,
+                                             double* out, bool sub) {
+    constexpr int T = GT / 16, KS = GT / 4, NW = qd_apply_waves<GT>();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    for (int I = w; I < T; I += NW) {
+        const int i = 16 * I + li;
+        double av[KS];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const int k = 4 * q + lk;
+            av[q] = (i < g && k < g) ? A[(size_t)i * g + k] : 0.0;
+        }
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < KS; ++q) acc = mfma_f64(av[q], in[(4 * q + lk) * kAL + li], acc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * I + lk + 4 * v;
+            out[r * kAL + li] = sub ? out[r * kAL + li] - acc[v] : acc[v];
+        }
+    }
+    __syncthreads();
+}
+
+template <int GT>
+__global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(MergeArgs a, int col0,
+                                                                             int ncol) {
+    constexpr int CT = 16, NT = 64 * qd_apply_waves<GT>();
+    __shared__ double rs[GT * kAL], rd[GT * kAL], tt[GT * kAL];
+    const int node = blockIdx.x, g = a.g;
+    const int cb = col0 + blockIdx.y * CT;
+    const int nc = min(CT, col0 + ncol - cb);
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    const int* g1 = a.gmap;
+    const int* g2 = a.gmap + g;
+    // r1, r2 of the columns (zero outside g x nc), as r1 + r2 and r2 - r1
+    batched<4>(GT * CT,
+               [&](int t) {
+                   const int i = t / CT, cc = t % CT, col = cb + cc;
+                   if (cc >= nc || i >= g) return 0.0;
+                   if (col == a.nslot) return T1[(size_t)g1[i] * a.cld + a.cld - 1];
+                   const int pm = a.pmap[col];
+                   return (pm >> 24) == 0 ? T1[(size_t)g1[i] * a.cld + (pm & 0xffffff)] : 0.0;
+               },
+               [&](int t, double v) { rs[(t / CT) * kAL + t % CT] = v; });
+    batched<4>(GT * CT,
+               [&](int t) {
+                   const int i = t / CT, cc = t % CT, col = cb + cc;
+                   if (cc >= nc || i >= g) return 0.0;
+                   if (col == a.nslot) return T2[(size_t)g2[i] * a.cld + a.cld - 1];
+                   const int pm = a.pmap[col];
+                   return (pm >> 24) == 1 ? T2[(size_t)g2[i] * a.cld + (pm & 0xffffff)] : 0.0;
+               },
+               [&](int t, double v) { rd[(t / CT) * kAL + t % CT] = v; });
+    __syncthreads();
+    for (int t = threadIdx.x; t < GT * CT; t += NT) {
+        const int e = (t / CT) * kAL + t % CT;
+        const double r1 = rs[e], r2 = rd[e];
+        rs[e] = r1 + r2;
+        rd[e] = r2 - r1;
+    }
+    __syncthreads();
+    const size_t gg = (size_t)g * g;
+    const double* Dg = a.M + (size_t)node * 4 * gg;
+    const double* Eg = Dg + gg;
+    const double* Sg = Eg + gg;
+    const double* Bg = Sg + gg;
+    qd_prod_mfma<GT>(g, Dg, rd, tt, false);     // t = D^{-1} (r2 - r1)
+    qd_prod_mfma<GT>(g, Bg, tt, rs, true);      // u = r1 + r2 - B t
+    qd_prod_mfma<GT>(g, Sg, rs, rd, false);     // s = S^{-1} u
+    qd_prod_mfma<GT>(g, Eg, rd, tt, true);      // d = t - E s
+    double* X = a.X + (size_t)node * a.xi * a.ld;
+    for (int t = threadIdx.x; t < g * CT; t += NT) {
+        const int i = t / CT, cc = t % CT;
+        if (cc >= nc) continue;
+        const double s = rd[i * kAL + cc], d = tt[i * kAL + cc];
+        X[(size_t)i * a.ld + cb + cc] = -(s - d);
+        X[(size_t)(g + i) * a.ld + cb + cc] = -(s + d);
+    }
+}
+
+// Parent traces on the matrix cores: T_p[o][col] = direct(o, col)
+// + sum_i A_1[o][i] X_1[i][col] + sum_i A_2[o][i] X_2[i][col], with A_k[o][i]
+// = T_k[o, gamma_k(i)] on the rows o that child k owns and zero on the
+// others (an MFMA's B operand is shared by all rows of the tile).  Wave w of
+// a workgroup forms the 16 x 16 tile of rows 16 (4 y + w).., columns 16 z..
+template <int GT>
+__global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, int ncol) {
+    constexpr int KS = GT / 4;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    const int node = blockIdx.x, g = a.g;
+    const int o0 = 16 * (4 * blockIdx.y + w), cb = col0 + 16 * blockIdx.z;
+    if (o0 >= a.nslot) return;
+    const int ce = col0 + ncol;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* Tk[2] = {a.Tc + (size_t)c1 * a.cnslot * a.cld, a.Tc + (size_t)c2 * a.cnslot * a.cld};
+    const double* X = a.X + (size_t)node * a.xi * a.ld;
+    // the A row of this lane
+    const int oa = o0 + li;
+    const int pa = oa < a.nslot ? a.pmap[oa] : -1;
+    const int ka = pa >= 0 ? (pa >> 24) : -1;
+    const double* ta = pa >= 0 ? Tk[ka] + (size_t)(pa & 0xffffff) * a.cld : nullptr;
+    const int col = cb + li;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        double av[KS], bv[KS];
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const int i = 4 * q + lk;
+            av[q] = (ka == k && i < g) ? ta[a.gmap[k * g + i]] : 0.0;
+            bv[q] = (i < g && col < ce) ? X[(size_t)(k * g + i) * a.ld + col] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) acc = mfma_f64(av[q], bv[q], acc);
+    }
+    if (col >= ce) return;
+    const int pc = col < a.nslot ? a.pmap[col] : -1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = o0 + lk + 4 * v;
+        if (o >= a.nslot) continue;
+        const int pm = a.pmap[o], k = pm >> 24;
+        const double* tr = Tk[k] + (size_t)(pm & 0xffffff) * a.cld;
+        double d;
+        if (col == a.nslot) d = tr[a.cld - 1];
+        else d = (pc >> 24) == k ? tr[pc & 0xffffff] : 0.0;
+        a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = d + acc[v];
     }
 }
 
@@ -907,19 +1073,10 @@ static int qd_tier(int g) { return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : 
 
 template <int GT>
 static hipError_t qd_apply(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, int ct) {
-    if (ncol == 1) ct = 1;
-    else if (ct <= 0) ct = qd_ct<GT>();
-    if (GT >= 128 && ct > 8) ct = 8;           // LDS: the 128-segment block fills most of it
-    const dim3 grid(a.nnodes, (ncol + ct - 1) / ct);
-    switch (ct) {
-        case 1: hipLaunchKernelGGL((k_qd_apply<GT, 1>), grid, dim3(256), 0, c->stream, a, col0, ncol); break;
-        case 4: hipLaunchKernelGGL((k_qd_apply<GT, 4>), grid, dim3(256), 0, c->stream, a, col0, ncol); break;
-        case 8: hipLaunchKernelGGL((k_qd_apply<GT, 8>), grid, dim3(256), 0, c->stream, a, col0, ncol); break;
-        default:
-            hipLaunchKernelGGL((k_qd_apply<GT, (GT >= 128 ? 8 : 16)>),
-                               dim3(a.nnodes, (ncol + (GT >= 128 ? 8 : 16) - 1) / (GT >= 128 ? 8 : 16)),
-                               dim3(256), 0, c->stream, a, col0, ncol);
-    }
+    (void)ct;
+    const dim3 grid(a.nnodes, (ncol + 15) / 16);
+    hipLaunchKernelGGL(k_qd_apply_mfma<GT>, grid, dim3(64 * qd_apply_waves<GT>()), 0, c->stream, a,
+                       col0, ncol);
     return hipGetLastError();
 }
 
@@ -928,8 +1085,7 @@ static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int nco
     hipError_t e = qd_apply<GT>(c, a, col0, ncol, ct);
     if (e != hipSuccess) return e;
     if (trace)
-        hipLaunchKernelGGL(k_qd_trace<GT>,
-                           dim3(a.nnodes, (a.nslot + kTRR - 1) / kTRR, (ncol + kTRC - 1) / kTRC),
+        hipLaunchKernelGGL(k_qd_trace_mfma<GT>, dim3(a.nnodes, (a.nslot + 63) / 64, (ncol + 15) / 16),
                            dim3(256), 0, c->stream, a, col0, ncol);
     return hipGetLastError();
 }
