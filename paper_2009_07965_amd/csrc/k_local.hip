@@ -228,6 +228,14 @@ __device__ inline void row_coeffs(const Geo& g, const double* cf, int lane, int 
     *tyu = tu;
 }
 
+// Orders this wave's LDS writes before its later LDS reads by other lanes
+// (the workgroup is this one wave).
+__device__ inline void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline double readlane_s(double v, int l) {
     const unsigned long long u = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffull), l);
@@ -594,17 +602,37 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
 
     for (int j = 0; j < BY; ++j) {
         if (j + 2 < BY) kq2 = Kc[(size_t)(j + 2) * g.nx];
-        // ---- Cholesky of S_j fused with the inversion of its factor
+        // ---- Cholesky of S_j fused with the inversion of its factor, NB pivots
+        // at a time: inside a block the multipliers are read from their lanes;
+        // the rows below take the block's updates with the multipliers
+        // broadcast from LDS (Pl is free until the P_j product).  Every entry
+        // sees the same operations in the same order as pivot by pivot.
+        constexpr int NB = 8;
 #pragma unroll
-        for (int k = 0; k < BX; ++k) {
-            S d = readlane_s(a[k], k);
-            if (!(d > S(0))) {
-                sing = 1;
-                d = S(1);
+        for (int kb = 0; kb < BX; kb += NB) {
+#pragma unroll
+            for (int k = kb; k < kb + NB; ++k) {
+                S d = readlane_s(a[k], k);
+                if (!(d > S(0))) {
+                    sing = 1;
+                    d = S(1);
+                }
+                a[k] *= rsqrt_nr(d);
+#pragma unroll
+                for (int i = k + 1; i < kb + NB; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
             }
-            a[k] *= rsqrt_nr(d);
+            if (kb + NB < BX) {
+                if (scol) {
 #pragma unroll
-            for (int i = k + 1; i < BX; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
+                    for (int k = kb; k < kb + NB; ++k) Pl[(k - kb) * BX + c] = a[k];
+                }
+                wave_lds_sync();
+#pragma unroll
+                for (int i = kb + NB; i < BX; ++i)
+#pragma unroll
+                    for (int k = kb; k < kb + NB; ++k) a[i] = fma(-Pl[(k - kb) * BX + i], a[k], a[i]);
+                wave_lds_sync();
+            }
         }
         if (icol) {
 #pragma unroll
