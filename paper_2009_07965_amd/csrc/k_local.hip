@@ -707,13 +707,18 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
             // the whole row loop.
             int cc = c;
             asm volatile("" : "+v"(cc));
-            const S od = S(dg), orr = -S(txr), ol = -S(txl);
+            // a[i] = p[i] ms + e_i: ms = 1 on the lanes of S (0 elsewhere); e_i
+            // holds the tridiagonal entries there and the identity on the lanes
+            // that carry it (p[i] 1 is exact, so the sums are p[i] + entry)
+            const S ms = scol ? S(1) : S(0);
+            const S od = scol ? S(dg) : (icol ? S(1) : S(0));
+            const S orr = scol ? -S(txr) : S(0), ol = scol ? -S(txl) : S(0);
 #pragma unroll
             for (int i = 0; i < BX; ++i) {
-                S off = (i == cc) ? od : S(0);
-                off = (i == cc + 1) ? orr : off;
-                off = (i + 1 == cc) ? ol : off;
-                a[i] = scol ? p[i] + off : ((icol && i == cc) ? S(1) : S(0));
+                S e = (i == cc) ? od : S(0);
+                e = (i == cc + 1) ? orr : e;
+                e = (i + 1 == cc) ? ol : e;
+                a[i] = fma(p[i], ms, e);
             }
             // z_{j+1} = F_{j+1} + D_j w_j (D_j w_j written by the sweep)
             {
