@@ -283,6 +283,7 @@ def main():
         S = Solver(prob.nx, prob.ny, K, bct, prob.sub_nx, prob.sub_ny, prob.seg,
                    alpha=prob.alpha, precision=precision, **extra)
         S.set_stream(stream.cuda_stream)
+        S.autotune()               # merge column tiles, chosen once outside the timed region
 
         def step():
             S.refactor(K, wait=False)

@@ -184,7 +184,8 @@ void rmrcm_destroy(rmrcm_ctx* ctx);
 /* Static message for a status code. */
 const char* rmrcm_strerror(int status);
 
-/* Time the candidate column tiles (4, 8, 16 columns per workgroup) of the
+/* Time the candidate column tiles (16 or 32 columns per workgroup; 32 reuses
+ * each loaded block of the merge for two 16-column tiles) of the
  * interface-merge products of every level of this context on its own
  * shapes and keep the fastest; choices are cached per merge shape (gamma
  * length, parent slots, merges per level) for the process.  Results do not

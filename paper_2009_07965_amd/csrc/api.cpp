@@ -851,7 +851,7 @@ int rmrcm_autotune(rmrcm_ctx* c) {
         }
         int best = 0;
         float bt = 1e30f;
-        for (int ct : {4, 8, 16}) {
+        for (int ct : {16, 32}) {
             HIP_TRY(rmrcm::launch_merge_apply(c, d, ct));      // warm-up
             HIP_TRY(hipEventRecord(c->ev[11], c->stream));
             for (int r = 0; r < 3; ++r) HIP_TRY(rmrcm::launch_merge_apply(c, d, ct));

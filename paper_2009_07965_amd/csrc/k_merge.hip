@@ -395,7 +395,9 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
         }
     }
     wave_lds_sync();
-    // P[r][c] = sum_i L^{-1}[i][r] (1/d_i) L^{-1}[i][c]
+    // P[r][c] = sum_i L^{-1}[i][r] (1/d_i) L^{-1}[i][c], on the vector units
+    // (the matrix cores are busy with the other waves' updates), in the
+    // accumulator layout: lane l forms rows l/16 + 4v of column l%16
     v4d P = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -405,8 +407,9 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
 
 // In-place inversion of the register-resident matrix m (block column w of
 // the wave).  cp: two column panels, pt: two 16 x 17 tiles for P.  Look-ahead:
-// in step K the owner of block column K + 1 updates its column first, then
-// publishes it and forms P_{K+1} while the other waves finish step K.
+// in step K the owner of block column K + 1 updates its diagonal tile first
+// and forms P_{K+1} from it, then updates and publishes the rest of its
+// column, while the other waves finish step K.
 template <int GT>
 __device__ __forceinline__ void qd_publish(const v4d (&m)[QdM<GT>::T], double* c) {
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -457,24 +460,41 @@ __device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* pt, double*
             v4d R = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 4; ++s) R = mfma_f64(pa[s], mk[s], R);
+            const bool la = w == K + 1;
+            double* cn = cp + ((K + 1) & 1) * GT * CPL;
+            if (la) {
+                // look-ahead: the next pivot block first, inverted at once, at a
+                // raised issue priority (every wave waits for it at the barrier)
+                v4d dt = m[0];
+#pragma unroll
+                for (int I = 1; I < T; ++I)
+                    if (I == K + 1) dt = m[I];
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    dt = mfma_f64(-c[(16 * (K + 1) + li) * CPL + 4 * s + lk], R[s], dt);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cn[(16 * (K + 1) + lk + 4 * v) * CPL + li] = dt[v];
+                wave_lds_sync();
+                const v4d Pn = qd_pivot_inverse(cn, K + 1, lt, ls, bad);
+                double* pn = pt + ((K + 1) & 1) * 16 * 17;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) pn[(lk + 4 * v) * 17 + li] = Pn[v];
+#pragma unroll
+                for (int I = 0; I < T; ++I)
+                    if (I == K + 1) m[I] = dt;
+            }
 #pragma unroll
             for (int I = 0; I < T; ++I) {
                 if (I == K) {
                     m[I] = R;
                     continue;
                 }
+                if (la && I == K + 1) continue;
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
                     m[I] = mfma_f64(-c[(16 * I + li) * CPL + 4 * s + lk], R[s], m[I]);
             }
-            if (w == K + 1) {
-                double* cn = cp + ((K + 1) & 1) * GT * CPL;
-                qd_publish<GT>(m, cn);
-                const v4d Pn = qd_pivot_inverse(cn, K + 1, lt, ls, bad);
-                double* pn = pt + ((K + 1) & 1) * 16 * 17;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) pn[(lk + 4 * v) * 17 + li] = Pn[v];
-            }
+            if (la) qd_publish<GT>(m, cn);
         }
         __syncthreads();
     }
@@ -663,123 +683,18 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
 }
 
 // Gamma coefficients of columns [col0, col0 + ncol): X = -M^{-1} R through
-// the stored blocks, CT columns per workgroup (CT = 1 for the particular
-// column alone); each g x g block is brought into LDS whole (all its loads
-// in flight at once, rows padded against bank conflicts) before its product.
-template <int GT>
-__host__ __device__ constexpr int qd_ct() { return GT >= 128 ? 8 : 16; }
-
-// out[i][c] (= or -=) sum_k A[i][k] in[k][c] for i < g, c < CT; A g x g
-// row-major in global memory, staged in Al with leading dimension g + 1.
-template <int GT, int CT, bool SUB>
-__device__ __forceinline__ void qd_prod(int g, const double* __restrict__ A, const double* in,
-                                        double* out, double* Al) {
-    constexpr int RG = 256 / CT, RPT = (GT + RG - 1) / RG;
-    constexpr int NL = (GT * GT + 255) / 256, CH = NL > 32 ? 32 : NL;
-    const int tid = threadIdx.x, c = tid % CT, r0 = tid / CT;
-    const int n = g * g, L = g + 1;
-    for (int l0 = 0; l0 < NL; l0 += CH) {      // chunks of CH loads in flight per thread
-        double ld[CH];
-#pragma unroll
-        for (int l = 0; l < CH; ++l) {
-            const int t = tid + 256 * (l0 + l);
-            ld[l] = t < n ? A[t] : 0.0;
-        }
-#pragma unroll
-        for (int l = 0; l < CH; ++l) {
-            const int t = tid + 256 * (l0 + l);
-            if (t < n) Al[(t / g) * L + t % g] = ld[l];
-        }
-    }
-    __syncthreads();
-    double acc[RPT];
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) acc[u] = 0.0;
-    for (int k = 0; k < g; ++k) {
-        const double x = in[k * CT + c];
-#pragma unroll
-        for (int u = 0; u < RPT; ++u) {
-            const int i = r0 + RG * u;
-            if (i < g) acc[u] += Al[i * L + k] * x;
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < RPT; ++u) {
-        const int i = r0 + RG * u;
-        if (i < g) out[i * CT + c] = SUB ? out[i * CT + c] - acc[u] : acc[u];
-    }
-    __syncthreads();
-}
-
-template <int GT, int CT>
-__global__ __launch_bounds__(256) void k_qd_apply(MergeArgs a, int col0, int ncol) {
-    __shared__ double rs[GT * CT], rd[GT * CT], tt[GT * CT];
-    __shared__ double Al[GT * (GT + 1)];
-    const int node = blockIdx.x, g = a.g;
-    const int cb = col0 + blockIdx.y * CT;
-    const int nc = min(CT, col0 + ncol - cb);
-    int c1, c2;
-    children(a, node, &c1, &c2);
-    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
-    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
-    const int* g1 = a.gmap;
-    const int* g2 = a.gmap + g;
-    batched<4>(g * CT,
-               [&](int t) {
-                   const int i = t / CT, cc = t % CT, col = cb + cc;
-                   if (cc >= nc) return 0.0;
-                   if (col == a.nslot) return T1[(size_t)g1[i] * a.cld + a.cld - 1];
-                   const int pm = a.pmap[col];
-                   return (pm >> 24) == 0 ? T1[(size_t)g1[i] * a.cld + (pm & 0xffffff)] : 0.0;
-               },
-               [&](int t, double v) { rs[t] = v; });
-    batched<4>(g * CT,
-               [&](int t) {
-                   const int i = t / CT, cc = t % CT, col = cb + cc;
-                   if (cc >= nc) return 0.0;
-                   if (col == a.nslot) return T2[(size_t)g2[i] * a.cld + a.cld - 1];
-                   const int pm = a.pmap[col];
-                   return (pm >> 24) == 1 ? T2[(size_t)g2[i] * a.cld + (pm & 0xffffff)] : 0.0;
-               },
-               [&](int t, double v) { rd[t] = v; });
-    __syncthreads();
-    for (int t = threadIdx.x; t < g * CT; t += 256) {
-        const double r1 = rs[t], r2 = rd[t];
-        rs[t] = r1 + r2;
-        rd[t] = r2 - r1;
-    }
-    __syncthreads();
-    const size_t gg = (size_t)g * g;
-    const double* Dg = a.M + (size_t)node * 4 * gg;
-    const double* Eg = Dg + gg;
-    const double* Sg = Eg + gg;
-    const double* Bg = Sg + gg;
-    qd_prod<GT, CT, false>(g, Dg, rd, tt, Al);     // t = D^{-1} (r2 - r1)
-    qd_prod<GT, CT, true>(g, Bg, tt, rs, Al);      // u = r1 + r2 - B t
-    qd_prod<GT, CT, false>(g, Sg, rs, rd, Al);     // s = S^{-1} u
-    qd_prod<GT, CT, true>(g, Eg, rd, tt, Al);      // d = t - E s
-    double* X = a.X + (size_t)node * a.xi * a.ld;
-    for (int t = threadIdx.x; t < g * CT; t += 256) {
-        const int i = t / CT, cc = t % CT;
-        if (cc >= nc) continue;
-        const double s = rd[t], d = tt[t];
-        X[(size_t)i * a.ld + cb + cc] = -(s - d);
-        X[(size_t)(g + i) * a.ld + cb + cc] = -(s + d);
-    }
-}
-
-// The same columns on the matrix cores, 16 per workgroup: each of the four
-// products is A (g x g, row-major in global memory) times a g x 16 block held
-// in LDS (rows padded to GT, leading dimension kAL); wave w forms row tiles
-// I = w, w + NW, .. with every k-slice of A for the tile loaded at once.
-constexpr int kAL = 17;
+// the stored blocks, on the matrix cores, 16 NCT columns per workgroup: each
+// of the four products is A (g x g, row-major in global memory) times a
+// g x 16 NCT block held in LDS (rows padded to GT, leading dimension
+// 16 NCT + 1); wave w forms row tiles I = w, w + NW, .. with every k-slice
+// of A for the tile loaded at once and used for all NCT column tiles.
 template <int GT>
 __host__ __device__ constexpr int qd_apply_waves() { return GT / 16 > 4 ? GT / 16 : 4; }
 
-template <int GT>
+template <int GT, int NCT>
 __device__ __forceinline__ void qd_prod_mfma(int g, const double* __restrict__ A, const double* in,
                                              double* out, bool sub) {
-    constexpr int T = GT / 16, KS = GT / 4, NW = qd_apply_waves<GT>();
+    constexpr int T = GT / 16, KS = GT / 4, NW = qd_apply_waves<GT>(), AL = 16 * NCT + 1;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
     for (int I = w; I < T; I += NW) {
         const int i = 16 * I + li;
@@ -789,23 +704,26 @@ __device__ __forceinline__ void qd_prod_mfma(int g, const double* __restrict__ A
             const int k = 4 * q + lk;
             av[q] = (i < g && k < g) ? A[(size_t)i * g + k] : 0.0;
         }
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < KS; ++q) acc = mfma_f64(av[q], in[(4 * q + lk) * kAL + li], acc);
+        for (int ct = 0; ct < NCT; ++ct) {
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = 16 * I + lk + 4 * v;
-            out[r * kAL + li] = sub ? out[r * kAL + li] - acc[v] : acc[v];
+            for (int q = 0; q < KS; ++q) acc = mfma_f64(av[q], in[(4 * q + lk) * AL + 16 * ct + li], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int e = (16 * I + lk + 4 * v) * AL + 16 * ct + li;
+                out[e] = sub ? out[e] - acc[v] : acc[v];
+            }
         }
     }
     __syncthreads();
 }
 
-template <int GT>
+template <int GT, int NCT>
 __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(MergeArgs a, int col0,
                                                                              int ncol) {
-    constexpr int CT = 16, NT = 64 * qd_apply_waves<GT>();
-    __shared__ double rs[GT * kAL], rd[GT * kAL], tt[GT * kAL];
+    constexpr int CT = 16 * NCT, AL = CT + 1, NT = 64 * qd_apply_waves<GT>();
+    __shared__ double rs[GT * AL], rd[GT * AL], tt[GT * AL];
     const int node = blockIdx.x, g = a.g;
     const int cb = col0 + blockIdx.y * CT;
     const int nc = min(CT, col0 + ncol - cb);
@@ -824,7 +742,7 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
                    const int pm = a.pmap[col];
                    return (pm >> 24) == 0 ? T1[(size_t)g1[i] * a.cld + (pm & 0xffffff)] : 0.0;
                },
-               [&](int t, double v) { rs[(t / CT) * kAL + t % CT] = v; });
+               [&](int t, double v) { rs[(t / CT) * AL + t % CT] = v; });
     batched<4>(GT * CT,
                [&](int t) {
                    const int i = t / CT, cc = t % CT, col = cb + cc;
@@ -833,10 +751,10 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
                    const int pm = a.pmap[col];
                    return (pm >> 24) == 1 ? T2[(size_t)g2[i] * a.cld + (pm & 0xffffff)] : 0.0;
                },
-               [&](int t, double v) { rd[(t / CT) * kAL + t % CT] = v; });
+               [&](int t, double v) { rd[(t / CT) * AL + t % CT] = v; });
     __syncthreads();
     for (int t = threadIdx.x; t < GT * CT; t += NT) {
-        const int e = (t / CT) * kAL + t % CT;
+        const int e = (t / CT) * AL + t % CT;
         const double r1 = rs[e], r2 = rd[e];
         rs[e] = r1 + r2;
         rd[e] = r2 - r1;
@@ -847,15 +765,15 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
     const double* Eg = Dg + gg;
     const double* Sg = Eg + gg;
     const double* Bg = Sg + gg;
-    qd_prod_mfma<GT>(g, Dg, rd, tt, false);     // t = D^{-1} (r2 - r1)
-    qd_prod_mfma<GT>(g, Bg, tt, rs, true);      // u = r1 + r2 - B t
-    qd_prod_mfma<GT>(g, Sg, rs, rd, false);     // s = S^{-1} u
-    qd_prod_mfma<GT>(g, Eg, rd, tt, true);      // d = t - E s
+    qd_prod_mfma<GT, NCT>(g, Dg, rd, tt, false);     // t = D^{-1} (r2 - r1)
+    qd_prod_mfma<GT, NCT>(g, Bg, tt, rs, true);      // u = r1 + r2 - B t
+    qd_prod_mfma<GT, NCT>(g, Sg, rs, rd, false);     // s = S^{-1} u
+    qd_prod_mfma<GT, NCT>(g, Eg, rd, tt, true);      // d = t - E s
     double* X = a.X + (size_t)node * a.xi * a.ld;
     for (int t = threadIdx.x; t < g * CT; t += NT) {
         const int i = t / CT, cc = t % CT;
         if (cc >= nc) continue;
-        const double s = rd[i * kAL + cc], d = tt[i * kAL + cc];
+        const double s = rd[i * AL + cc], d = tt[i * AL + cc];
         X[(size_t)i * a.ld + cb + cc] = -(s - d);
         X[(size_t)(g + i) * a.ld + cb + cc] = -(s + d);
     }
@@ -912,66 +830,6 @@ __global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, in
     }
 }
 
-// Parent traces T_p[o][col] = direct + T_k[o, gamma_k] X_k[:, col] for a
-// tile of kTRR rows and kTRC columns; the gamma rows of the owning children
-// and both children's coefficient blocks staged in LDS.
-constexpr int kTRR = 32, kTRC = 32;
-
-template <int GT>
-__global__ __launch_bounds__(256) void k_qd_trace(MergeArgs a, int col0, int ncol) {
-    __shared__ double Tg[kTRR * GT];
-    __shared__ double Xs[2 * GT * kTRC];
-    __shared__ int qk[kTRR];
-    const int node = blockIdx.x, g = a.g;
-    const int o0 = blockIdx.y * kTRR, cb = col0 + blockIdx.z * kTRC;
-    const int nr = min(kTRR, a.nslot - o0), nc = min(kTRC, col0 + ncol - cb);
-    int c1, c2;
-    children(a, node, &c1, &c2);
-    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
-    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
-    const double* X = a.X + (size_t)node * a.xi * a.ld;
-    for (int q = threadIdx.x; q < nr; q += 256) qk[q] = a.pmap[o0 + q] >> 24;
-    batched<4>(nr * g,
-               [&](int t) {
-                   const int q = t / g, i = t % g;
-                   const int pm = a.pmap[o0 + q];
-                   const int k = pm >> 24, oc = pm & 0xffffff;
-                   return (k == 0 ? T1 : T2)[(size_t)oc * a.cld + a.gmap[k * g + i]];
-               },
-               [&](int t, double v) { Tg[(t / g) * GT + t % g] = v; });
-    batched<8>(2 * g * kTRC,
-               [&](int t) {
-                   const int r = t / kTRC, cc = t % kTRC;
-                   return cc < nc ? X[(size_t)r * a.ld + cb + cc] : 0.0;
-               },
-               [&](int t, double v) { Xs[t] = v; });
-    __syncthreads();
-    const int cc = threadIdx.x % kTRC;
-    if (cc >= nc) return;
-    const int col = cb + cc;
-    for (int q = threadIdx.x / kTRC; q < nr; q += 256 / kTRC) {
-        const int o = o0 + q, k = qk[q];
-        const int pm = a.pmap[o];
-        const double* Tk = (k == 0 ? T1 : T2) + (size_t)(pm & 0xffffff) * a.cld;
-        double v;
-        if (col == a.nslot) {
-            v = Tk[a.cld - 1];
-        } else {
-            const int pc = a.pmap[col];
-            v = (pc >> 24) == k ? Tk[pc & 0xffffff] : 0.0;
-        }
-        const double* tg = Tg + q * GT;
-        const double* xk = Xs + (size_t)k * g * kTRC + cc;
-        double s0 = 0.0, s1 = 0.0;
-        int i = 0;
-        for (; i + 1 < g; i += 2) {
-            s0 += tg[i] * xk[i * kTRC];
-            s1 += tg[i + 1] * xk[(i + 1) * kTRC];
-        }
-        if (i < g) s0 += tg[i] * xk[i * kTRC];
-        a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = v + (s0 + s1);
-    }
-}
 
 // Downward pass at one level: gamma data y = X [d; 1] from the node's
 // boundary data d, written to the low / high Robin data of the gamma
@@ -1071,12 +929,16 @@ static hipError_t solve_cols_generic(rmrcm_ctx* c, const MergeArgs& a, int col0,
 // Size class of the pivot-free path (0: gamma too long, generic LU path).
 static int qd_tier(int g) { return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : 0; }
 
+// ct: columns per workgroup, 16 or 32 (0: 16).
 template <int GT>
 static hipError_t qd_apply(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, int ct) {
-    (void)ct;
-    const dim3 grid(a.nnodes, (ncol + 15) / 16);
-    hipLaunchKernelGGL(k_qd_apply_mfma<GT>, grid, dim3(64 * qd_apply_waves<GT>()), 0, c->stream, a,
-                       col0, ncol);
+    const dim3 block(64 * qd_apply_waves<GT>());
+    if (ct == 32 && ncol > 16)
+        hipLaunchKernelGGL((k_qd_apply_mfma<GT, 2>), dim3(a.nnodes, (ncol + 31) / 32), block, 0,
+                           c->stream, a, col0, ncol);
+    else
+        hipLaunchKernelGGL((k_qd_apply_mfma<GT, 1>), dim3(a.nnodes, (ncol + 15) / 16), block, 0,
+                           c->stream, a, col0, ncol);
     return hipGetLastError();
 }
 
