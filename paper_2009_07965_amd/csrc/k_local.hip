@@ -527,17 +527,28 @@ struct Mfma<float> {
     static __device__ inline int row(int l, int v) { return 4 * (l >> 4) + v; }
 };
 
+// Pivots per block of the local Cholesky (BX: one block, multipliers by lane
+// reads only; a smaller block adds rank-NB updates through an LDS buffer of
+// NB x BX entries).  Chosen so that the kernel fits the 256 registers of two
+// waves per SIMD without spilling.
 template <int BX, typename S>
-__global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __restrict__ K,
-                                                         const int8_t* __restrict__ bct,
-                                                         const double* __restrict__ beta,
-                                                         const int* __restrict__ slotseg, int R,
-                                                         S* __restrict__ Pstore,
-                                                         double* __restrict__ Psi,
-                                                         double* __restrict__ T, int ld,
-                                                         int* __restrict__ flags,
-                                                         const int* __restrict__ mask, int want,
-                                                         int do_traces, int basis) {
+__host__ __device__ constexpr int chol_block() { return (BX > 16 && sizeof(S) == 8) ? 16 : BX; }
+template <int BX, typename S>
+__host__ __device__ constexpr int chol_wb_entries() {
+    return chol_block<BX, S>() < BX ? chol_block<BX, S>() * BX : 0;
+}
+
+template <int BX, typename S>
+__global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double* __restrict__ K,
+                                                          const int8_t* __restrict__ bct,
+                                                          const double* __restrict__ beta,
+                                                          const int* __restrict__ slotseg, int R,
+                                                          S* __restrict__ Pstore,
+                                                          double* __restrict__ Psi,
+                                                          double* __restrict__ T, int ld,
+                                                          int* __restrict__ flags,
+                                                          const int* __restrict__ mask, int want,
+                                                          int do_traces, int basis) {
     static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
     typedef Mfma<S> M;
     typedef typename M::v4 v4;
@@ -546,13 +557,13 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     extern __shared__ __align__(16) char smem[];
     constexpr int LT = BX + 4;              // padded row length
     constexpr int NTL = BX / 16;            // tiles per dimension
-    constexpr int PPL = BX * BX / 64;       // factor-store entries per lane
+    constexpr int NB = chol_block<BX, S>(); // pivots per Cholesky block
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
     const int RP = (R + 15) & ~15;          // columns padded to whole tiles
     const int nct = basis ? RP / 16 : 0;    // column tiles of the sweeps
     char* cur = smem;
-    S* LTs = carve<S>(cur, BX * LT);        // row c = column c of L^{-1}
-    S* Pl = carve<S>(cur, BX * LT);         // P_j, row-major
+    S* LTs = carve<S>(cur, BX * LT);        // wave A: row c = column c of L^{-1}, then -D P D
+    S* Wb = carve<S>(cur, chol_wb_entries<BX, S>());   // wave A: multipliers of one block
     S* Z = carve<S>(cur, BX * RP);          // z_j, later D_j x_{j+1}
     S* Z2 = carve<S>(cur, BX * RP);         // the next row's z (double buffer)
     S* tys = carve<S>(cur, BY * BX);        // couplings D_j
@@ -560,7 +571,9 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     int* rs = carve<int>(cur, NF);
     int* of = carve<int>(cur, NF);
 
-    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    // wave A (w = 0) runs the factorisation chain; wave B (w = 1) the forward
+    // sweep of each row one barrier behind it; both share the backward sweep
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int I = sub % g.mx, J = sub / g.mx;
     const int* ss = slotseg + (size_t)sub * R;
     S* Ps = Pstore + (size_t)sub * BY * BX * BX;
@@ -571,131 +584,156 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
     const int c = scol ? lane : (icol ? lane - BX : 0);
 
     face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
-    // permeability of column c, row by row: kq (row being set up), kq1 (the
-    // row above), kq2 (two rows above, in flight during a row's work)
-    const double* Kc = K + (size_t)J * BY * g.nx + (size_t)I * BX + c;
-    double kq = Kc[0];
-    double kq1 = BY > 1 ? Kc[g.nx] : 1.0;
-    double kq2 = 1.0;
-    for (int t = lane; t < BX * RP; t += 64) Z[t] = S(0);
+    for (int t = tid; t < BX * RP; t += 128) Z[t] = S(0);
     __syncthreads();
 
+    // permeability of column c, row by row (wave A): kq (row being set up),
+    // kq1 (the row above), kq2 (two rows above, in flight during a row's work)
+    const double* Kc = K + (size_t)J * BY * g.nx + (size_t)I * BX + c;
+    double kq = 1.0, kq1 = 1.0, kq2 = 1.0;
     S a[BX];
     S p[BX];
     int sing = 0;
-    double dg, txr, txl, tyu;
-    row_coeffs<BX>(g, cf, lane, c, 0, kq, kq1, cf[2 * BY + c], &dg, &txr, &txl, &tyu);
+    double dg = 0.0, txr = 0.0, txl = 0.0, tyu = 0.0;
+    if (w == 0) {
+        kq = Kc[0];
+        kq1 = BY > 1 ? Kc[g.nx] : 1.0;
+        row_coeffs<BX>(g, cf, lane, c, 0, kq, kq1, cf[2 * BY + c], &dg, &txr, &txl, &tyu);
 #pragma unroll
-    for (int i = 0; i < BX; ++i) {
-        double v = 0.0;
-        if (scol) v = (i == c) ? dg : (i == c + 1) ? -txr : (i + 1 == c) ? -txl : 0.0;
-        else if (icol) v = (i == c) ? 1.0 : 0.0;
-        a[i] = S(v);
+        for (int i = 0; i < BX; ++i) {
+            double v = 0.0;
+            if (scol) v = (i == c) ? dg : (i == c + 1) ? -txr : (i + 1 == c) ? -txl : 0.0;
+            else if (icol) v = (i == c) ? 1.0 : 0.0;
+            a[i] = S(v);
+        }
+    } else {
+        if (lane == 0 && rs[0] >= 0) Z[rs[0]] += S(cf[0]);
+        if (lane == 1 && rs[BY] >= 0) Z[(BX - 1) * RP + rs[BY]] += S(cf[BY]);
+        wave_lds_sync();
+        if (lane < BX && rs[2 * BY + lane] >= 0) Z[lane * RP + rs[2 * BY + lane]] += S(cf[2 * BY + lane]);
+        if (BY == 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+            Z[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
     }
-    if (lane == 0 && rs[0] >= 0) Z[rs[0]] += S(cf[0]);
-    if (lane == 1 && rs[BY] >= 0) Z[(BX - 1) * RP + rs[BY]] += S(cf[BY]);
-    __syncthreads();
-    if (lane < BX && rs[2 * BY + lane] >= 0) Z[lane * RP + rs[2 * BY + lane]] += S(cf[2 * BY + lane]);
-    if (BY == 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
-        Z[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
-    __syncthreads();
 
     for (int j = 0; j < BY; ++j) {
-        if (j + 2 < BY) kq2 = Kc[(size_t)(j + 2) * g.nx];
-        // ---- Cholesky of S_j fused with the inversion of its factor, NB pivots
-        // at a time: inside a block the multipliers are read from their lanes;
-        // the rows below take the block's updates with the multipliers
-        // broadcast from LDS (Pl is free until the P_j product).  Every entry
-        // sees the same operations in the same order as pivot by pivot.
-        constexpr int NB = 8;
+        if (w == 0) {
+            if (j + 2 < BY) kq2 = Kc[(size_t)(j + 2) * g.nx];
+            // ---- Cholesky of S_j fused with the inversion of its factor, NB
+            // pivots at a time: inside a block the multipliers are read from
+            // their lanes; the rows below take the block's updates with the
+            // multipliers broadcast from LDS.  Every entry sees the same
+            // operations in the same order as pivot by pivot.
 #pragma unroll
-        for (int kb = 0; kb < BX; kb += NB) {
+            for (int kb = 0; kb < BX; kb += NB) {
 #pragma unroll
-            for (int k = kb; k < kb + NB; ++k) {
-                S d = readlane_s(a[k], k);
-                if (!(d > S(0))) {
-                    sing = 1;
-                    d = S(1);
+                for (int k = kb; k < kb + NB; ++k) {
+                    S d = readlane_s(a[k], k);
+                    if (!(d > S(0))) {
+                        sing = 1;
+                        d = S(1);
+                    }
+                    a[k] *= rsqrt_nr(d);
+#pragma unroll
+                    for (int i = k + 1; i < kb + NB; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
                 }
-                a[k] *= rsqrt_nr(d);
+                if (kb + NB < BX) {
+                    if (scol) {
 #pragma unroll
-                for (int i = k + 1; i < kb + NB; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
+                        for (int k = kb; k < kb + NB; ++k) Wb[(k - kb) * BX + c] = a[k];
+                    }
+                    wave_lds_sync();
+                    // four rows at a time: bounds the multipliers held in registers
+#pragma unroll
+                    for (int i0 = kb + NB; i0 < BX; i0 += 4) {
+#pragma unroll
+                        for (int i = i0; i < i0 + 4; ++i)
+#pragma unroll
+                            for (int k = kb; k < kb + NB; ++k) a[i] = fma(-Wb[(k - kb) * BX + i], a[k], a[i]);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    wave_lds_sync();
+                }
             }
-            if (kb + NB < BX) {
-                if (scol) {
+            if (icol) {
 #pragma unroll
-                    for (int k = kb; k < kb + NB; ++k) Pl[(k - kb) * BX + c] = a[k];
+                for (int i = 0; i < BX; ++i) LTs[c * LT + i] = a[i];
+            }
+            if (scol) tys[j * BX + c] = S(tyu);    // D_j
+            wave_lds_sync();
+            // ---- P_j[r][c] = sum_{i >= max(r,c)} L^{-1}[i][r] L^{-1}[i][c] on the
+            // matrix cores, to the factor store; once every tile is formed,
+            // L^{-1} is dead and its buffer takes the Schur term
+            // -(D_j P_j D_j)[r][c] of the next row, row-major
+            v4 pacc[NTL][NTL];
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NTL; ++tc) {
+                    v4 acc = {S(0), S(0), S(0), S(0)};
+                    const int k0 = 16 * (tr > tc ? tr : tc);
+#pragma unroll
+                    for (int kk = k0; kk < BX; kk += 4) {
+                        const S av = LTs[(16 * tr + li) * LT + kk + lk];
+                        const S bv = LTs[(16 * tc + li) * LT + kk + lk];
+                        acc = M::op(av, bv, acc);
+                    }
+                    pacc[tr][tc] = acc;
                 }
+            const bool trail = j + 1 < BY;
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NTL; ++tc)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
+                        const S pv = pacc[tr][tc][v];
+                        Ps[(size_t)j * BX * BX + r * BX + cq] = pv;
+                        if (trail) LTs[r * LT + cq] = -(pv * (tys[j * BX + r] * tys[j * BX + cq]));
+                    }
+        }
+        __syncthreads();                   // P_j in the factor store, D_j in tys
+        if (w == 1) {
+            // ---- forward sweep w_j = P_j z_j (P_j as the A operand from the
+            // factor store); also D_j w_j, the next row's right-hand side (for
+            // the last row D_{BY-2} w_{BY-1}, the backward sweep's first)
+            const int jz = (j + 1 < BY) ? j : j - 1;
+            if (nct > 0) {
+                S av[NTL][BX / 4];
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                    for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                        av[tr][kq4] = Ps[(size_t)j * BX * BX + (16 * tr + li) * BX + 4 * kq4 + lk];
+                for (int ct = 0; ct < nct; ++ct) {
+#pragma unroll
+                    for (int tr = 0; tr < NTL; ++tr) {
+                        v4 acc = {S(0), S(0), S(0), S(0)};
+#pragma unroll
+                        for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                            acc = M::op(av[tr][kq4], Z[(4 * kq4 + lk) * RP + 16 * ct + li], acc);
+                        const int q = 16 * ct + li;
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int r = 16 * tr + M::row(lane, v);
+                            if (jz >= 0) Z2[r * RP + q] = tys[jz * BX + r] * acc[v];
+                            if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[v];
+                        }
+                    }
+                }
+            }
+            if (j + 1 < BY) {
+                // z_{j+1} = F_{j+1} + D_j w_j
                 wave_lds_sync();
-#pragma unroll
-                for (int i = kb + NB; i < BX; ++i)
-#pragma unroll
-                    for (int k = kb; k < kb + NB; ++k) a[i] = fma(-Pl[(k - kb) * BX + i], a[k], a[i]);
+                const int jn = j + 1;
+                if (lane == 0 && rs[jn] >= 0) Z2[rs[jn]] += S(cf[jn]);
+                if (lane == 1 && rs[BY + jn] >= 0) Z2[(BX - 1) * RP + rs[BY + jn]] += S(cf[BY + jn]);
+                wave_lds_sync();
+                if (jn == BY - 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+                    Z2[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
                 wave_lds_sync();
             }
-        }
-        if (icol) {
-#pragma unroll
-            for (int i = 0; i < BX; ++i) LTs[c * LT + i] = a[i];
-        }
-        if (scol) tys[j * BX + c] = S(tyu);    // D_j
-        __syncthreads();
-        // ---- P_j[r][c] = sum_{i >= max(r,c)} L^{-1}[i][r] L^{-1}[i][c] on the matrix cores;
-        // once every tile is formed, L^{-1} is dead and its buffer takes the
-        // Schur term -(D_j P_j D_j)[r][c] of the next row, row-major
-        v4 pacc[NTL][NTL];
-#pragma unroll
-        for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-            for (int tc = 0; tc < NTL; ++tc) {
-                v4 acc = {S(0), S(0), S(0), S(0)};
-                const int k0 = 16 * (tr > tc ? tr : tc);
-#pragma unroll
-                for (int kk = k0; kk < BX; kk += 4) {
-                    const S av = LTs[(16 * tr + li) * LT + kk + lk];
-                    const S bv = LTs[(16 * tc + li) * LT + kk + lk];
-                    acc = M::op(av, bv, acc);
-                }
-                pacc[tr][tc] = acc;
-            }
-        const bool trail = j + 1 < BY;
-#pragma unroll
-        for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-            for (int tc = 0; tc < NTL; ++tc)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
-                    const S pv = pacc[tr][tc][v];
-                    Pl[r * LT + cq] = pv;
-                    Ps[(size_t)j * BX * BX + r * BX + cq] = pv;
-                    if (trail) LTs[r * LT + cq] = -(pv * (tys[j * BX + r] * tys[j * BX + cq]));
-                }
-        __syncthreads();
-        // ---- forward sweep w_j = P_j z_j; also D_j w_j, the next row's right-hand
-        // side (for the last row D_{BY-2} w_{BY-1}, the backward sweep's first)
-        const int jz = (j + 1 < BY) ? j : j - 1;
-        for (int ct = 0; ct < nct; ++ct) {
-#pragma unroll
-            for (int tr = 0; tr < NTL; ++tr) {
-                v4 acc = {S(0), S(0), S(0), S(0)};
-#pragma unroll
-                for (int kk = 0; kk < BX; kk += 4) {
-                    const S av = Pl[(16 * tr + li) * LT + kk + lk];
-                    const S bv = Z[(kk + lk) * RP + 16 * ct + li];
-                    acc = M::op(av, bv, acc);
-                }
-                const int q = 16 * ct + li;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * tr + M::row(lane, v);
-                    if (jz >= 0) Z2[r * RP + q] = tys[jz * BX + r] * acc[v];
-                    if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[v];
-                }
-            }
-        }
-        __syncthreads();
-        if (j + 1 < BY) {
+        } else if (j + 1 < BY) {
             // ---- trailing update S_{j+1} = A_{j+1} - D_j P_j D_j (lane c: column c)
 #pragma unroll
             for (int r = 0; r < BX; ++r) p[r] = LTs[r * LT + c];     // -(D_j P_j D_j), column c
@@ -720,110 +758,87 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
                 e = (i + 1 == cc) ? ol : e;
                 a[i] = fma(p[i], ms, e);
             }
-            // z_{j+1} = F_{j+1} + D_j w_j (D_j w_j written by the sweep)
-            {
-                S* t = Z;
-                Z = Z2;
-                Z2 = t;
-            }
-            const int jn = j + 1;
-            if (lane == 0 && rs[jn] >= 0) Z[rs[jn]] += S(cf[jn]);
-            if (lane == 1 && rs[BY + jn] >= 0) Z[(BX - 1) * RP + rs[BY + jn]] += S(cf[BY + jn]);
-            __syncthreads();
-            if (jn == BY - 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
-                Z[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
-            __syncthreads();
+        }
+        if (j + 1 < BY) {
+            S* t = Z;
+            Z = Z2;
+            Z2 = t;
         }
     }
+    __syncthreads();                       // the last forward sweep
     if (!basis) {
-        if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+        if (tid == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
         return;
     }
     // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j (D_j x_{j+1}).
-    // P_{j-1} and w_{j-1} (of the first WCT column tiles) are loaded one row
-    // ahead.
+    // Wave w forms row tile w (BX = 32) or wave 0 the only one (BX = 16); the
+    // tile's rows of P_{j-1} and of w_{j-1} (first WCT column tiles) are
+    // loaded one row ahead.
     constexpr int WCT = 2;
-    S pr[PPL];
-    v4 wn[WCT][NTL];
-    auto load_w = [&](int jr) {
+    const int tr = w;
+    const bool act = tr < NTL;
+    S pn[BX / 4];
+    v4 wn[WCT];
+    auto load_row = [&](int jr) {
+#pragma unroll
+        for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+            pn[kq4] = Ps[(size_t)jr * BX * BX + (16 * tr + li) * BX + 4 * kq4 + lk];
 #pragma unroll
         for (int ct = 0; ct < WCT; ++ct)
 #pragma unroll
-            for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int q = 16 * ct + li, r = 16 * tr + M::row(lane, v);
-                    wn[ct][tr][v] = (ct < nct && q < R) ? S(Psub[(size_t)q * n + jr * BX + r]) : S(0);
-                }
+            for (int v = 0; v < 4; ++v) {
+                const int q = 16 * ct + li, r = 16 * tr + M::row(lane, v);
+                wn[ct][v] = (ct < nct && q < R) ? S(Psub[(size_t)q * n + jr * BX + r]) : S(0);
+            }
     };
-    if (BY > 1) {
-#pragma unroll
-        for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(BY - 2) * BX * BX + lane + 64 * u];
-        load_w(BY - 2);
-    }
+    if (act && BY > 1) load_row(BY - 2);
     for (int j = BY - 2; j >= 0; --j) {
         {                       // Z = D_j x_{j+1}, written by the previous sweep
             S* t = Z;
             Z = Z2;
             Z2 = t;
         }
+        S pc[BX / 4];
+        v4 wc[WCT];
 #pragma unroll
-        for (int u = 0; u < PPL; ++u) {
-            const int e = lane + 64 * u;
-            Pl[(e / BX) * LT + e % BX] = pr[u];
-        }
-        v4 wc[WCT][NTL];
+        for (int kq4 = 0; kq4 < BX / 4; ++kq4) pc[kq4] = pn[kq4];
 #pragma unroll
-        for (int ct = 0; ct < WCT; ++ct)
-#pragma unroll
-            for (int tr = 0; tr < NTL; ++tr) wc[ct][tr] = wn[ct][tr];
+        for (int ct = 0; ct < WCT; ++ct) wc[ct] = wn[ct];
         __syncthreads();
-        if (j > 0) {
+        if (act) {
+            if (j > 0) load_row(j - 1);
+            auto tile = [&](int ct, v4 acc) {
+                const int q = 16 * ct + li;
 #pragma unroll
-            for (int u = 0; u < PPL; ++u) pr[u] = Ps[(size_t)(j - 1) * BX * BX + lane + 64 * u];
-            load_w(j - 1);
-        }
-        auto tile = [&](int ct, v4 (&acc)[NTL]) {
-            const int q = 16 * ct + li;
+                for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                    acc = M::op(pc[kq4], Z[(4 * kq4 + lk) * RP + q], acc);
 #pragma unroll
-            for (int tr = 0; tr < NTL; ++tr) {
-#pragma unroll
-                for (int kk = 0; kk < BX; kk += 4) {
-                    const S av = Pl[(16 * tr + li) * LT + kk + lk];
-                    const S bv = Z[(kk + lk) * RP + q];
-                    acc[tr] = M::op(av, bv, acc[tr]);
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    if (j > 0) Z2[r * RP + q] = tys[(j - 1) * BX + r] * acc[v];
+                    if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[v];
                 }
+            };
+#pragma unroll
+            for (int ct = 0; ct < WCT; ++ct)
+                if (ct < nct) tile(ct, wc[ct]);
+            for (int ct = WCT; ct < nct; ++ct) {
+                const int q = 16 * ct + li;
+                v4 acc;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v);
+                    acc[v] = q < R ? S(Psub[(size_t)q * n + j * BX + r]) : S(0);
+                }
+                tile(ct, acc);
             }
-#pragma unroll
-            for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * tr + M::row(lane, v);
-                    if (j > 0) Z2[r * RP + q] = tys[(j - 1) * BX + r] * acc[tr][v];
-                    if (q < R) Psub[(size_t)q * n + j * BX + r] = (double)acc[tr][v];
-                }
-        };
-#pragma unroll
-        for (int ct = 0; ct < WCT; ++ct)
-            if (ct < nct) tile(ct, wc[ct]);
-        for (int ct = WCT; ct < nct; ++ct) {
-            const int q = 16 * ct + li;
-            v4 acc[NTL];
-#pragma unroll
-            for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = 16 * tr + M::row(lane, v);
-                    acc[tr][v] = q < R ? S(Psub[(size_t)q * n + j * BX + r]) : S(0);
-                }
-            tile(ct, acc);
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (do_traces) {
         // traces T[a][b] = sum_{f in slot a} c_f (x_b(cell f) - delta_ab)
         double* Tsub = T + (size_t)sub * R * ld;
-        for (int t = lane; t < R * R; t += 64) {
+        for (int t = tid; t < R * R; t += 128) {
             const int ar = t / R, b = t % R;
             double s = 0.0;
             if (ss[ar] >= 0 && ss[b] >= 0) {
@@ -838,7 +853,7 @@ __global__ __launch_bounds__(64) void k_local_setup_mfma(Geo g, const double* __
             Tsub[(size_t)ar * ld + b] = s;
         }
     }
-    if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+    if (tid == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
 }
 
 // One refinement pass on the matrix cores (subdomains 16 or 32 cells wide):
@@ -1438,13 +1453,14 @@ static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do
     if constexpr (BX >= 16) {
         const Level& L = c->levels[c->D];
         const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY), RP = (R + 15) & ~15;
-        const size_t lds = 2 * carve_bytes(BX * (BX + 4), sizeof(S)) + 2 * carve_bytes(BX * RP, sizeof(S)) +
-                           carve_bytes(BY * BX, sizeof(S)) + carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4);
+        const size_t lds = carve_bytes(BX * (BX + 4), sizeof(S)) + carve_bytes(chol_wb_entries<BX, S>(), sizeof(S)) +
+                           2 * carve_bytes(BX * RP, sizeof(S)) + carve_bytes(BY * BX, sizeof(S)) +
+                           carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4);
         hipError_t e = hipFuncSetAttribute((const void*)k_local_setup_mfma<BX, S>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         const int nsub = c->geo.mx * c->geo.my;
-        hipLaunchKernelGGL((k_local_setup_mfma<BX, S>), dim3(nsub), dim3(64), lds, c->stream, c->geo,
+        hipLaunchKernelGGL((k_local_setup_mfma<BX, S>), dim3(nsub), dim3(128), lds, c->stream, c->geo,
                            c->K, c->bct, c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask,
                            want, do_traces, basis);
         return hipGetLastError();
