@@ -691,27 +691,52 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
 template <int GT>
 __host__ __device__ constexpr int qd_apply_waves() { return GT / 16 > 4 ? GT / 16 : 4; }
 
-template <int GT, int NCT>
-__device__ __forceinline__ void qd_prod_mfma(int g, const double* __restrict__ A, const double* in,
-                                             double* out, bool sub) {
-    constexpr int T = GT / 16, KS = GT / 4, NW = qd_apply_waves<GT>(), AL = 16 * NCT + 1;
+// The row tile w of A (g x g, row-major) as MFMA A operands: k-slice
+// q = 4u + h of lane l holds k = 16u + 4(l/16) + h, so that a lane loads four
+// consecutive entries of its row at once (the sum over k is taken in this
+// order on both operands).  Zero outside g x g and for waves without a tile.
+template <int GT>
+__device__ __forceinline__ void qd_load_tile(int g, const double* __restrict__ A, double (&av)[GT / 4]) {
+    constexpr int KS = GT / 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
-    for (int I = w; I < T; I += NW) {
-        const int i = 16 * I + li;
-        double av[KS];
+    const int i = 16 * w + li;
+    if ((g & 3) == 0 && i < g) {
+        const double* Ai = A + (size_t)i * g;
+#pragma unroll
+        for (int u = 0; u < KS / 4; ++u) {
+            const int k0 = 16 * u + 4 * lk;
+            const double4 v = k0 < g ? *(const double4*)(Ai + k0) : double4{0.0, 0.0, 0.0, 0.0};
+            av[4 * u] = v.x;
+            av[4 * u + 1] = v.y;
+            av[4 * u + 2] = v.z;
+            av[4 * u + 3] = v.w;
+        }
+    } else {
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
-            const int k = 4 * q + lk;
+            const int k = 16 * (q >> 2) + 4 * lk + (q & 3);
             av[q] = (i < g && k < g) ? A[(size_t)i * g + k] : 0.0;
         }
+    }
+}
+
+// out (=, or -= when sub) A in for the row tile of this wave, A given as
+// loaded by qd_load_tile; in and out g x 16 NCT blocks in LDS.
+template <int GT, int NCT>
+__device__ __forceinline__ void qd_prod_mfma(const double (&av)[GT / 4], const double* in, double* out,
+                                             bool sub) {
+    constexpr int T = GT / 16, KS = GT / 4, AL = 16 * NCT + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    if (w < T) {
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
             v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < KS; ++q) acc = mfma_f64(av[q], in[(4 * q + lk) * AL + 16 * ct + li], acc);
+            for (int q = 0; q < KS; ++q)
+                acc = mfma_f64(av[q], in[(16 * (q >> 2) + 4 * lk + (q & 3)) * AL + 16 * ct + li], acc);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int e = (16 * I + lk + 4 * v) * AL + 16 * ct + li;
+                const int e = (16 * w + lk + 4 * v) * AL + 16 * ct + li;
                 out[e] = sub ? out[e] - acc[v] : acc[v];
             }
         }
@@ -733,42 +758,58 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
     const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
     const int* g1 = a.gmap;
     const int* g2 = a.gmap + g;
-    // r1, r2 of the columns (zero outside g x nc), as r1 + r2 and r2 - r1
-    batched<4>(GT * CT,
-               [&](int t) {
-                   const int i = t / CT, cc = t % CT, col = cb + cc;
-                   if (cc >= nc || i >= g) return 0.0;
-                   if (col == a.nslot) return T1[(size_t)g1[i] * a.cld + a.cld - 1];
-                   const int pm = a.pmap[col];
-                   return (pm >> 24) == 0 ? T1[(size_t)g1[i] * a.cld + (pm & 0xffffff)] : 0.0;
-               },
-               [&](int t, double v) { rs[(t / CT) * AL + t % CT] = v; });
-    batched<4>(GT * CT,
-               [&](int t) {
-                   const int i = t / CT, cc = t % CT, col = cb + cc;
-                   if (cc >= nc || i >= g) return 0.0;
-                   if (col == a.nslot) return T2[(size_t)g2[i] * a.cld + a.cld - 1];
-                   const int pm = a.pmap[col];
-                   return (pm >> 24) == 1 ? T2[(size_t)g2[i] * a.cld + (pm & 0xffffff)] : 0.0;
-               },
-               [&](int t, double v) { rd[(t / CT) * AL + t % CT] = v; });
-    __syncthreads();
-    for (int t = threadIdx.x; t < GT * CT; t += NT) {
-        const int e = (t / CT) * AL + t % CT;
-        const double r1 = rs[e], r2 = rd[e];
-        rs[e] = r1 + r2;
-        rd[e] = r2 - r1;
-    }
-    __syncthreads();
     const size_t gg = (size_t)g * g;
     const double* Dg = a.M + (size_t)node * 4 * gg;
     const double* Eg = Dg + gg;
     const double* Sg = Eg + gg;
     const double* Bg = Sg + gg;
-    qd_prod_mfma<GT, NCT>(g, Dg, rd, tt, false);     // t = D^{-1} (r2 - r1)
-    qd_prod_mfma<GT, NCT>(g, Bg, tt, rs, true);      // u = r1 + r2 - B t
-    qd_prod_mfma<GT, NCT>(g, Sg, rs, rd, false);     // s = S^{-1} u
-    qd_prod_mfma<GT, NCT>(g, Eg, rd, tt, true);      // d = t - E s
+    double av[GT / 4], an[GT / 4];
+    qd_load_tile<GT>(g, Dg, av);                     // in flight during the gathers
+    qd_load_tile<GT>(g, Bg, an);
+    // r1, r2 of the columns (zero outside g x nc), as r1 + r2 and r2 - r1;
+    // four entries per thread in flight
+    for (int t0 = 0; t0 < GT * CT; t0 += 4 * NT) {
+        double v1[4], v2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NT + threadIdx.x;
+            const int i = t / CT, cc = t % CT, col = cb + cc;
+            v1[u] = 0.0;
+            v2[u] = 0.0;
+            if (t < GT * CT && cc < nc && i < g) {
+                if (col == a.nslot) {
+                    v1[u] = T1[(size_t)g1[i] * a.cld + a.cld - 1];
+                    v2[u] = T2[(size_t)g2[i] * a.cld + a.cld - 1];
+                } else {
+                    const int pm = a.pmap[col], off = pm & 0xffffff;
+                    if ((pm >> 24) == 0) v1[u] = T1[(size_t)g1[i] * a.cld + off];
+                    else v2[u] = T2[(size_t)g2[i] * a.cld + off];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NT + threadIdx.x;
+            if (t < GT * CT) {
+                const int e = (t / CT) * AL + t % CT;
+                rs[e] = v1[u] + v2[u];
+                rd[e] = v2[u] - v1[u];
+            }
+        }
+    }
+    __syncthreads();
+    // the four products; each block's tile is loaded while the previous
+    // product runs
+    qd_prod_mfma<GT, NCT>(av, rd, tt, false);       // t = D^{-1} (r2 - r1)
+#pragma unroll
+    for (int q = 0; q < GT / 4; ++q) av[q] = an[q];
+    qd_load_tile<GT>(g, Sg, an);
+    qd_prod_mfma<GT, NCT>(av, tt, rs, true);        // u = r1 + r2 - B t
+#pragma unroll
+    for (int q = 0; q < GT / 4; ++q) av[q] = an[q];
+    qd_load_tile<GT>(g, Eg, an);
+    qd_prod_mfma<GT, NCT>(av, rs, rd, false);       // s = S^{-1} u
+    qd_prod_mfma<GT, NCT>(an, rd, tt, true);        // d = t - E s
     double* X = a.X + (size_t)node * a.xi * a.ld;
     for (int t = threadIdx.x; t < g * CT; t += NT) {
         const int i = t / CT, cc = t % CT;
