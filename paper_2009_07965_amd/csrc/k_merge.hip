@@ -568,7 +568,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
     const int j = 16 * w + li;                   // the column this lane holds
     // the gamma blocks of both children: B and N to global memory, D in
     // registers (four tiles' loads in flight at a time)
-    constexpr int CI = T < 4 ? T : 4;
+    constexpr int CI = T;
     v4d m[T];
 #pragma unroll
     for (int I0 = 0; I0 < T; I0 += CI) {
