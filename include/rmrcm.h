@@ -142,6 +142,22 @@ int rmrcm_refactor(rmrcm_ctx* ctx, const double* perm);
  * or EDEVICE. */
 int rmrcm_sync(rmrcm_ctx* ctx);
 
+/* rmrcm_refactor(perm) followed by rmrcm_solve(source, bc_value, pressure,
+ * flux) as one unit, with the same arguments and results.  For an FP64
+ * context whose arrays are all in device memory the whole step is captured
+ * once as a HIP graph and replayed (the particular chain of Section 3.2 runs
+ * beside the setup merges on the context's auxiliary stream; pressures and
+ * fluxes are written in place); the graph is captured again when any
+ * pointer differs from the previous call's; the phase timers of
+ * rmrcm_get_stats keep the values of the last refactor or solve run outside
+ * such a graph.  Asynchronous on a stream set
+ * with rmrcm_set_stream (device errors, including incompatible all-Neumann
+ * data, are returned by rmrcm_sync); otherwise waits.  Other contexts and
+ * host arrays: exactly rmrcm_refactor + rmrcm_solve.
+ * Errors: those of rmrcm_refactor and rmrcm_solve. */
+int rmrcm_step(rmrcm_ctx* ctx, const double* perm, const double* source, const double* bc_value,
+               double* pressure, double* flux);
+
 /* Solve for one right-hand side: the particular local solutions (source
  * and outer boundary data, additive split of Section 2.1), their columns
  * through the merges, the top interface solve, the downward propagation of

@@ -42,10 +42,21 @@ bool is_device_ptr(const void* p) {
     return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// With RMRCM_DEBUG set in the environment, a failing HIP call is reported
+// on stderr (file, line, HIP's message) before its status is returned.
+bool debug_enabled() {
+    static const bool on = std::getenv("RMRCM_DEBUG") != nullptr;
+    return on;
+}
+void report_hip(hipError_t e, const char* what, int line) {
+    if (debug_enabled()) std::fprintf(stderr, "rmrcm: %s failed at api.cpp:%d: %s\n", what, line, hipGetErrorString(e));
+}
+
 #define HIP_TRY(expr)                                 \
     do {                                              \
         hipError_t e_ = (expr);                       \
         if (e_ != hipSuccess) {                       \
+            report_hip(e_, #expr, __LINE__);          \
             if (e_ == hipErrorOutOfMemory) return RMRCM_ENOMEM; \
             return RMRCM_EDEVICE;                     \
         }                                             \
@@ -269,8 +280,10 @@ void free_all(rmrcm_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->lev)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {c->ev_ls, c->ev_done, c->ev_aux})
+    for (hipEvent_t e : {c->ev_ls, c->ev_done, c->ev_aux, c->ev_fork})
         if (e) (void)hipEventDestroy(e);
+    if (c->gstep) (void)hipGraphExecDestroy(c->gstep);
+    c->gstep = nullptr;
     if (c->aux) {
         (void)hipStreamSynchronize(c->aux);
         (void)hipStreamDestroy(c->aux);
@@ -371,7 +384,8 @@ int mixed_local_setup(rmrcm_ctx* c) {
     return RMRCM_OK;
 }
 
-// Event i of the phase timers, unless the work is being captured in a graph.
+// Event i of the phase timers, unless the work is being captured in a graph
+// (the timers then keep the values of the last run outside a graph).
 int mark(rmrcm_ctx* c, int i) {
     if (!c->capturing) HIP_TRY(hipEventRecord(c->ev[i], c->stream));
     return RMRCM_OK;
@@ -380,7 +394,7 @@ int mark(rmrcm_ctx* c, int i) {
 // FP64 contexts outside graph capture run the particular chain (local
 // particular solves, merges of the particular column below the top) on the
 // auxiliary stream, each level after its own setup merge.
-bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c); }
+bool overlap(const rmrcm_ctx* c) { return c->aux && (!c->capturing || c->step_capture) && !mixed(c); }
 
 // Every permeability-dependent step, enqueued on c->stream (no host
 // synchronisation in FP64 mode, so that it can be captured in a graph).
@@ -443,13 +457,15 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     hipStream_t main = c->stream;
     c->stream = c->aux;
     int r = RMRCM_OK;
-    hipError_t e = c->done_recorded ? hipStreamWaitEvent(c->aux, c->ev_done, 0) : hipSuccess;
+    // in a step graph the chain starts at the fork recorded before the setup
+    hipError_t e = c->capturing ? hipStreamWaitEvent(c->aux, c->ev_fork, 0)
+                   : c->done_recorded ? hipStreamWaitEvent(c->aux, c->ev_done, 0) : hipSuccess;
     if (e == hipSuccess) r = solve_inputs(c, source, bc_value);
     if (e == hipSuccess && r == RMRCM_OK && !c->any_dirichlet) e = rmrcm::launch_compat_check(c);
     if (e == hipSuccess && r == RMRCM_OK) e = hipStreamWaitEvent(c->aux, c->ev_ls, 0);
-    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[13], c->aux);
+    if (e == hipSuccess && r == RMRCM_OK && !c->capturing) e = hipEventRecord(c->ev[13], c->aux);
     if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 1);
-    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[14], c->aux);
+    if (e == hipSuccess && r == RMRCM_OK && !c->capturing) e = hipEventRecord(c->ev[14], c->aux);
     for (int d = c->D - 1; d >= 1 && e == hipSuccess && r == RMRCM_OK; --d) {
         e = hipStreamWaitEvent(c->aux, c->lev[d], 0);
         if (e == hipSuccess) e = rmrcm::launch_merge_particular(c, d);
@@ -467,8 +483,10 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
     TRY(mark(c, 9));
-    HIP_TRY(hipEventRecord(c->ev_done, c->stream));
-    c->done_recorded = true;
+    if (!c->capturing) {
+        HIP_TRY(hipEventRecord(c->ev_done, c->stream));
+        c->done_recorded = true;
+    }
     c->solve_overlapped = true;
     return RMRCM_OK;
 }
@@ -611,7 +629,8 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
                 return fail(RMRCM_EDEVICE);
         if (hipEventCreateWithFlags(&c->ev_ls, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess)
+            hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
             return fail(RMRCM_EDEVICE);
     }
     const Geo& g = c->geo;
@@ -951,6 +970,7 @@ int capture(rmrcm_ctx* c, hipStream_t cap, F enqueue, hipGraphExec_t* out) {
     }
     const int r = enqueue(c);
     const hipError_t e = hipStreamEndCapture(cap, &graph);
+    if (e != hipSuccess) report_hip(e, "hipStreamEndCapture", __LINE__);
     c->stream = saved;
     c->capturing = false;
     if (r != RMRCM_OK) {
@@ -959,6 +979,7 @@ int capture(rmrcm_ctx* c, hipStream_t cap, F enqueue, hipGraphExec_t* out) {
     }
     if (e != hipSuccess) return RMRCM_EDEVICE;
     const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) report_hip(ei, "hipGraphInstantiate", __LINE__);
     (void)hipGraphDestroy(graph);
     return ei == hipSuccess ? RMRCM_OK : RMRCM_EDEVICE;
 }
@@ -1268,6 +1289,66 @@ int rmrcm_batch_get_stats(rmrcm_batch* b, char* json, size_t cap) {
 
 void rmrcm_batch_destroy(rmrcm_batch* b) {
     if (b) batch_free(b);
+}
+
+// Refactor and solve as one unit (rmrcm.h).  FP64 contexts with all arrays
+// in device memory replay a captured graph of the whole step: the setup on
+// the context's stream, the particular chain on the auxiliary stream forked
+// at the start, the outputs written in place.  The graph is captured again
+// when a pointer differs from those of the last capture.
+int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const double* bc_value,
+               double* pressure, double* flux) {
+    if (!c || !perm || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    const bool dev = is_device_ptr(perm) && (!source || is_device_ptr(source)) &&
+                     is_device_ptr(bc_value) && is_device_ptr(pressure) && is_device_ptr(flux);
+    if (mixed(c) || !c->aux || !dev) {
+        TRY(rmrcm_refactor(c, perm));
+        return rmrcm_solve(c, source, bc_value, pressure, flux);
+    }
+    const void* key[5] = {perm, source, bc_value, pressure, flux};
+    bool same = c->gstep != nullptr;
+    for (int i = 0; i < 5 && same; ++i) same = key[i] == c->gstep_key[i];
+    if (!same) {
+        if (c->gstep) {
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            (void)hipGraphExecDestroy(c->gstep);
+            c->gstep = nullptr;
+        }
+        double* po = c->pout;
+        double* fo = c->fout;
+        c->pout = pressure;                 // the reconstruction writes the caller's arrays
+        c->fout = flux;
+        c->step_capture = true;
+        const int r = capture(
+            c, c->stream,
+            [&](rmrcm_ctx* cc) -> int {
+                HIP_TRY(hipEventRecord(cc->ev_fork, cc->stream));
+                const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
+                HIP_TRY(hipMemcpyAsync(cc->K, perm, ncell * sizeof(double), hipMemcpyDeviceToDevice,
+                                       cc->stream));
+                TRY(enqueue_setup(cc));
+                return solve_overlapped(cc, source, bc_value);
+            },
+            &c->gstep);
+        c->step_capture = false;
+        c->pout = po;
+        c->fout = fo;
+        if (r != RMRCM_OK) return r;
+        for (int i = 0; i < 5; ++i) c->gstep_key[i] = key[i];
+    }
+    HIP_TRY(hipGraphLaunch(c->gstep, c->stream));
+    HIP_TRY(hipEventRecord(c->ev_done, c->stream));
+    c->done_recorded = true;
+    c->lev_recorded = true;
+    c->solved = true;
+    c->check_pending = true;
+    if (c->stream == c->own_stream) {
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        c->check_pending = false;
+        return check_flags(c);
+    }
+    return RMRCM_OK;
 }
 
 }  // extern "C"

@@ -71,6 +71,9 @@ struct rmrcm_ctx {
     bool setup_recorded = false;
     bool solve_recorded = false;
     bool capturing = false;       // enqueueing into a graph capture: no events, no host sync
+    bool step_capture = false;    // capturing rmrcm_step: overlap kept, timers as graph nodes
+    hipGraphExec_t gstep = nullptr;            // rmrcm_step graph (FP64 contexts)
+    const void* gstep_key[5] = {};             // the pointers it was captured with
     int ct_tune[32] = {};         // per depth: column tile of the merge apply (0 = default)
     // device arrays
     double* K = nullptr;                     // [ny][nx]
@@ -104,7 +107,7 @@ struct rmrcm_ctx {
     // the local setup, the inputs of a solve and the end of the aux work
     hipStream_t aux = nullptr;
     hipEvent_t lev[32] = {};
-    hipEvent_t ev_ls = nullptr, ev_done = nullptr, ev_aux = nullptr;
+    hipEvent_t ev_ls = nullptr, ev_done = nullptr, ev_aux = nullptr, ev_fork = nullptr;
     bool lev_recorded = false, done_recorded = false;
     bool solve_overlapped = false;  // the last solve ran the particular chain on aux
     double t_setup_ms[8] = {};

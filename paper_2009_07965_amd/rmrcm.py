@@ -45,7 +45,7 @@ class rmrcm_params(ctypes.Structure):
 
 
 EXPORTS = [
-    "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve",
+    "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve", "rmrcm_step",
     "rmrcm_get_interface",
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
     "rmrcm_strerror", "rmrcm_autotune", "rmrcm_batch_create", "rmrcm_batch_refactor",
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_sync.restype = ctypes.c_int
     lib.rmrcm_solve.argtypes = [vp, dp, dp, dp, dp]
     lib.rmrcm_solve.restype = ctypes.c_int
+    lib.rmrcm_step.argtypes = [vp, dp, dp, dp, dp, dp]
+    lib.rmrcm_step.restype = ctypes.c_int
     lib.rmrcm_get_interface.argtypes = [vp, dp, dp]
     lib.rmrcm_get_interface.restype = ctypes.c_int
     lib.rmrcm_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -191,6 +193,15 @@ def rmrcm_solve(ctx, source, bc_value, pressure, flux):
     pp, _p = _ptr(pressure, np.float64)
     fp, _f = _ptr(flux, np.float64)
     _check(lib().rmrcm_solve(ctx, sp, bp, pp, fp), "rmrcm_solve")
+
+
+def rmrcm_step(ctx, perm, source, bc_value, pressure, flux):
+    kp, _k = _ptr(perm, np.float64)
+    sp, _s = _ptr(source, np.float64)
+    bp, _b = _ptr(bc_value, np.float64)
+    pp, _p = _ptr(pressure, np.float64)
+    fp, _f = _ptr(flux, np.float64)
+    _check(lib().rmrcm_step(ctx, kp, sp, bp, pp, fp), "rmrcm_step")
 
 
 def rmrcm_get_interface(ctx, U, P):
@@ -439,6 +450,16 @@ class Solver:
         if flux is None:
             flux = np.zeros((4, self.ny, self.nx))
         rmrcm_solve(self.ctx, q, bc_value, pressure, flux)
+        return pressure, flux
+
+    def step(self, K, q, bc_value, pressure=None, flux=None):
+        """refactor(K) and solve(q, bc_value) as one unit (a replayed graph
+        for FP64 contexts with device arrays); returns (pressure, flux)."""
+        if pressure is None:
+            pressure = np.zeros((self.ny, self.nx))
+        if flux is None:
+            flux = np.zeros((4, self.ny, self.nx))
+        rmrcm_step(self.ctx, K, q, bc_value, pressure, flux)
         return pressure, flux
 
     def interface(self):
