@@ -414,7 +414,7 @@ int enqueue_setup(rmrcm_ctx* c) {
     if (ov) HIP_TRY(hipEventRecord(c->ev_ls, c->stream));
     for (int d = c->D - 1; d >= 0; --d) {
         HIP_TRY(rmrcm::launch_merge_setup(c, d));
-        if (ov) HIP_TRY(hipEventRecord(c->lev[d], c->stream));
+        if (ov && (d == 1 || d == 2)) HIP_TRY(hipEventRecord(c->lev[d], c->stream));
     }
     c->lev_recorded = ov;
     TRY(mark(c, 3));
@@ -450,9 +450,9 @@ int solve_inputs(rmrcm_ctx* c, const double* source, const double* bc_value) {
 // Solve with the particular chain on the auxiliary stream (FP64, see
 // overlap): the inputs (after the previous solve has finished with them),
 // the local particular solves (after the local setup) and the particular
-// column of every merge level below the top (each after that level's setup
-// merge); the main stream joins for the top level, the downward pass and
-// the reconstruction.
+// column of every merge level below the top (after the setup merges of
+// level 2, and of level 1 for that level); the main stream joins for the
+// top level, the downward pass and the reconstruction.
 int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value) {
     hipStream_t main = c->stream;
     c->stream = c->aux;
@@ -466,8 +466,13 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     if (e == hipSuccess && r == RMRCM_OK && !c->capturing) e = hipEventRecord(c->ev[13], c->aux);
     if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 1);
     if (e == hipSuccess && r == RMRCM_OK && !c->capturing) e = hipEventRecord(c->ev[14], c->aux);
+    // the particular merges of levels 2 and deeper start once the setup
+    // merges have reached level 2, that of level 1 after its own: two
+    // cross-stream dependencies only (each costs the setup chain, the longer
+    // one, a few microseconds)
     for (int d = c->D - 1; d >= 1 && e == hipSuccess && r == RMRCM_OK; --d) {
-        e = hipStreamWaitEvent(c->aux, c->lev[d], 0);
+        if (d == c->D - 1 && d >= 2) e = hipStreamWaitEvent(c->aux, c->lev[2], 0);
+        if (d == 1 && e == hipSuccess) e = hipStreamWaitEvent(c->aux, c->lev[1], 0);
         if (e == hipSuccess) e = rmrcm::launch_merge_particular(c, d);
     }
     if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev_aux, c->aux);
@@ -1317,6 +1322,7 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
         }
         double* po = c->pout;
         double* fo = c->fout;
+        double* ko = c->K;
         c->pout = pressure;                 // the reconstruction writes the caller's arrays
         c->fout = flux;
         c->step_capture = true;
@@ -1324,9 +1330,12 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
             c, c->stream,
             [&](rmrcm_ctx* cc) -> int {
                 HIP_TRY(hipEventRecord(cc->ev_fork, cc->stream));
+                // the kernels read the caller's permeability; the library's
+                // copy (for later calls) is made on the auxiliary branch
                 const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
-                HIP_TRY(hipMemcpyAsync(cc->K, perm, ncell * sizeof(double), hipMemcpyDeviceToDevice,
-                                       cc->stream));
+                HIP_TRY(hipStreamWaitEvent(cc->aux, cc->ev_fork, 0));
+                HIP_TRY(hipMemcpyAsync(ko, perm, ncell * sizeof(double), hipMemcpyDeviceToDevice, cc->aux));
+                cc->K = const_cast<double*>(perm);
                 TRY(enqueue_setup(cc));
                 return solve_overlapped(cc, source, bc_value);
             },
@@ -1334,6 +1343,7 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
         c->step_capture = false;
         c->pout = po;
         c->fout = fo;
+        c->K = ko;
         if (r != RMRCM_OK) return r;
         for (int i = 0; i < 5; ++i) c->gstep_key[i] = key[i];
     }
