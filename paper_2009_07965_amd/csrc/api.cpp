@@ -525,6 +525,31 @@ int enqueue_solve(rmrcm_ctx* c) {
     return RMRCM_OK;
 }
 
+// Refactor and solve as one chain on c->stream (the body of a step graph):
+// the particular problem is carried as one more column beside the basis,
+// through the local sweeps (subdomains 16 or 32 cells wide; otherwise its
+// own local solve follows the setup) and every merge below the top, so that
+// the particular chain of a separate solve is not needed.  c->K, c->q and
+// c->bcv point at the step's inputs.
+int enqueue_step_fused(rmrcm_ctx* c) {
+    HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
+    HIP_TRY(rmrcm::launch_check_perm(c));
+    HIP_TRY(rmrcm::launch_beta(c));
+    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_compat_check(c));
+    if (rmrcm::local_setup_solves_particular(c, false)) {
+        HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1, 1, 1));
+    } else {
+        HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
+        HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
+    }
+    for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d, true));
+    if (c->D > 0) HIP_TRY(rmrcm::launch_merge_particular(c, 0));   // the top's particular column
+    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    HIP_TRY(rmrcm::launch_reconstruct(c));
+    if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
+    return RMRCM_OK;
+}
+
 int solve_outputs(rmrcm_ctx* c, double* pressure, double* flux) {
     const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
     HIP_TRY(hipMemcpyAsync(pressure, c->pout, ncell * sizeof(double), hipMemcpyDefault, c->stream));
@@ -1323,6 +1348,8 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
         double* po = c->pout;
         double* fo = c->fout;
         double* ko = c->K;
+        double* qo = c->q;
+        double* bo = c->bcv;
         c->pout = pressure;                 // the reconstruction writes the caller's arrays
         c->fout = flux;
         c->step_capture = true;
@@ -1330,27 +1357,35 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
             c, c->stream,
             [&](rmrcm_ctx* cc) -> int {
                 HIP_TRY(hipEventRecord(cc->ev_fork, cc->stream));
-                // the kernels read the caller's permeability; the library's
-                // copy (for later calls) is made on the auxiliary branch
+                // the kernels read the caller's permeability, source and
+                // boundary data; the library's copy of the permeability (for
+                // later calls) is made on the auxiliary branch
                 const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
                 HIP_TRY(hipStreamWaitEvent(cc->aux, cc->ev_fork, 0));
                 HIP_TRY(hipMemcpyAsync(ko, perm, ncell * sizeof(double), hipMemcpyDeviceToDevice, cc->aux));
+                HIP_TRY(hipEventRecord(cc->ev_aux, cc->aux));
                 cc->K = const_cast<double*>(perm);
-                TRY(enqueue_setup(cc));
-                return solve_overlapped(cc, source, bc_value);
+                cc->bcv = const_cast<double*>(bc_value);
+                if (source) cc->q = const_cast<double*>(source);
+                else HIP_TRY(rmrcm::launch_fill_f64(cc, cc->q, ncell, 0.0));
+                TRY(enqueue_step_fused(cc));
+                HIP_TRY(hipStreamWaitEvent(cc->stream, cc->ev_aux, 0));
+                return RMRCM_OK;
             },
             &c->gstep);
         c->step_capture = false;
         c->pout = po;
         c->fout = fo;
         c->K = ko;
+        c->q = qo;
+        c->bcv = bo;
         if (r != RMRCM_OK) return r;
         for (int i = 0; i < 5; ++i) c->gstep_key[i] = key[i];
     }
     HIP_TRY(hipGraphLaunch(c->gstep, c->stream));
     HIP_TRY(hipEventRecord(c->ev_done, c->stream));
     c->done_recorded = true;
-    c->lev_recorded = true;
+    c->lev_recorded = false;                // a later solve runs its particular chain in order
     c->solved = true;
     c->check_pending = true;
     if (c->stream == c->own_stream) {

@@ -22,6 +22,7 @@
 // P_j is kept for every row (the factor store), so a later right-hand side
 // (the particular solution at solve time) needs only the two sweeps.
 
+#include <type_traits>
 #include "rmrcm_internal.h"
 
 namespace rmrcm {
@@ -226,6 +227,29 @@ __device__ inline void row_coeffs(const Geo& g, const double* cf, int lane, int 
     *txr = tr;
     *txl = tl;
     *tyu = tu;
+}
+
+// The same for an elimination from the top row down: kd is the permeability
+// of the cell below (unused on the bottom row), tyu the coupling to the row
+// above carried from the previous step (the north boundary conductance on the
+// top row), and *tyd returns the coupling to the row below, with the operands
+// of the harmonic mean in the order of the upward form (lower cell first), so
+// that both directions give the same numbers.
+template <int BX>
+__device__ inline void row_coeffs_down(const Geo& g, const double* cf, int lane, int c, int j,
+                                       double k, double kd, double tyu, double* dg, double* txr,
+                                       double* txl, double* tyd) {
+    const int BY = g.by;
+    const double rx = g.hx / (2.0 * k);
+    const double rxr = __shfl(rx, lane < 63 ? lane + 1 : 63, 64);
+    const double tr = c < BX - 1 ? g.hy / (rx + rxr) : 0.0;
+    const double tl = __shfl(tr, lane > 0 ? lane - 1 : 0, 64);
+    const double td = j > 0 ? g.hx / (g.hy / (2.0 * kd) + g.hy / (2.0 * k)) : 0.0;
+    const double tlc = c > 0 ? tl : cf[j];
+    *dg = tlc + (c < BX - 1 ? tr : cf[BY + j]) + (j > 0 ? td : cf[2 * BY + c]) + tyu;
+    *txr = tr;
+    *txl = tl;
+    *tyd = td;
 }
 
 // Orders this wave's LDS writes before its later LDS reads by other lanes
@@ -538,6 +562,157 @@ __host__ __device__ constexpr int chol_wb_entries() {
     return chol_block<BX, S>() < BX ? chol_block<BX, S>() * BX : 0;
 }
 
+// Right-hand side of the particular problem at cell (i, j): the source plus
+// the outer boundary data (Dirichlet |f|/rho g_D, Neumann -g_N).
+template <int BX>
+__device__ inline double part_rhs(const Geo& g, const double* cf, const int* of,
+                                  const int8_t* __restrict__ bct, const double* __restrict__ bcv,
+                                  double qv, int i, int j) {
+    const int BY = g.by;
+    double f = qv;
+    const int faces[4] = {i == 0 ? j : -1, i == BX - 1 ? BY + j : -1, j == 0 ? 2 * BY + i : -1,
+                          j == BY - 1 ? 2 * BY + BX + i : -1};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int fc = faces[s];
+        if (fc < 0) continue;
+        const int o = of[fc];
+        if (o >= 0) f += bct[o] == RMRCM_BC_DIRICHLET ? cf[fc] * bcv[o] : -bcv[o];
+    }
+    return f;
+}
+
+// Adds the boundary right-hand side of block row j (the Robin faces of its
+// W and E ends, and of the S / N sides on the first / last row) to the basis
+// columns of a right-hand side block Zb (row c = cell c, ld RP); one wave.
+template <int BX, typename S>
+__device__ inline void add_row_forcing(const Geo& g, const double* cf, const int* rs, S* Zb, int RP,
+                                       int lane, int j) {
+    const int BY = g.by;
+    if (lane == 0 && rs[j] >= 0) Zb[rs[j]] += S(cf[j]);
+    if (lane == 1 && rs[BY + j] >= 0) Zb[(BX - 1) * RP + rs[BY + j]] += S(cf[BY + j]);
+    wave_lds_sync();
+    if (j == 0 && lane < BX && rs[2 * BY + lane] >= 0) Zb[lane * RP + rs[2 * BY + lane]] += S(cf[2 * BY + lane]);
+    wave_lds_sync();
+    if (j == BY - 1 && lane < BX && rs[2 * BY + BX + lane] >= 0)
+        Zb[lane * RP + rs[2 * BY + BX + lane]] += S(cf[2 * BY + BX + lane]);
+    wave_lds_sync();
+}
+
+// Cholesky of the block held in a[] (lane c < BX: column c of S_j; lane
+// BX + c: column c of the identity) fused with the inversion of its factor:
+// afterwards lanes BX..2BX-1 hold L^{-1} (lane BX + c: column c), and sing
+// is set on a pivot that is not positive.  NB pivots at a time: inside a
+// block the multipliers are read from their lanes; the rows below take the
+// block's updates with the multipliers broadcast from LDS (Wb, NB x BX
+// entries).  Every entry sees the same operations in the same order as
+// pivot by pivot.
+template <int BX, typename S>
+__device__ __forceinline__ void chol_invert(S (&a)[BX], S* Wb, bool scol, int c, int& sing) {
+    constexpr int NB = chol_block<BX, S>();
+#pragma unroll
+    for (int kb = 0; kb < BX; kb += NB) {
+#pragma unroll
+        for (int k = kb; k < kb + NB; ++k) {
+            S d = readlane_s(a[k], k);
+            if (!(d > S(0))) {
+                sing = 1;
+                d = S(1);
+            }
+            a[k] *= rsqrt_nr(d);
+#pragma unroll
+            for (int i = k + 1; i < kb + NB; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
+        }
+        if (kb + NB < BX) {
+            if (scol) {
+#pragma unroll
+                for (int k = kb; k < kb + NB; ++k) Wb[(k - kb) * BX + c] = a[k];
+            }
+            wave_lds_sync();
+            // four rows at a time: bounds the multipliers held in registers
+#pragma unroll
+            for (int i0 = kb + NB; i0 < BX; i0 += 4) {
+#pragma unroll
+                for (int i = i0; i < i0 + 4; ++i)
+#pragma unroll
+                    for (int k = kb; k < kb + NB; ++k) a[i] = fma(-Wb[(k - kb) * BX + i], a[k], a[i]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+// The block [S_j | I] of a row: a[i] = p[i] ms + e_i, with p the Schur term
+// (column c on lane c), ms = 1 on the lanes of S (0 elsewhere), and e_i the
+// tridiagonal entries of A_jj there and the identity on the lanes that carry
+// it (p[i] 1 is exact, so the sums are p[i] + entry).  Selects rather than
+// branches; cc is opaque to the optimiser so that the lane-dependent compares
+// are formed here, not kept live across the caller's row loop.
+template <int BX, typename S>
+__device__ __forceinline__ void build_block(S (&a)[BX], const S (&p)[BX], double dg, double txr,
+                                            double txl, bool scol, bool icol, int c) {
+    int cc = c;
+    asm volatile("" : "+v"(cc));
+    const S ms = scol ? S(1) : S(0);
+    const S od = scol ? S(dg) : (icol ? S(1) : S(0));
+    const S orr = scol ? -S(txr) : S(0), ol = scol ? -S(txl) : S(0);
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        S e = (i == cc) ? od : S(0);
+        e = (i == cc + 1) ? orr : e;
+        e = (i + 1 == cc) ? ol : e;
+        a[i] = fma(p[i], ms, e);
+    }
+}
+
+// The same with the Schur term read from LDS (row-major, padded rows of
+// BX + 4; t1 null on the first row of a chain) plus a second term t2 when
+// not null: a[i] = (t1[i][c] + t2[i][c]) ms + e_i.
+template <int BX, typename S>
+__device__ __forceinline__ void build_block_lds(S (&a)[BX], const S* t1, const S* t2, double dg,
+                                                double txr, double txl, bool scol, bool icol,
+                                                int c) {
+    constexpr int LT = BX + 4;
+    int cc = c;
+    asm volatile("" : "+v"(cc));
+    const S ms = scol ? S(1) : S(0);
+    const S od = scol ? S(dg) : (icol ? S(1) : S(0));
+    const S orr = scol ? -S(txr) : S(0), ol = scol ? -S(txl) : S(0);
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+        S e = (i == cc) ? od : S(0);
+        e = (i == cc + 1) ? orr : e;
+        e = (i + 1 == cc) ? ol : e;
+        S pv = t1 ? t1[i * LT + c] : S(0);
+        if (t2) pv += t2[i * LT + c];
+        a[i] = fma(pv, ms, e);
+    }
+}
+
+// P[r][c] = sum_{i >= max(r,c)} L^{-1}[i][r] L^{-1}[i][c] on the matrix
+// cores, from LTs (row c = column c of L^{-1}, rows padded to BX + 4); tile
+// (tr, tc) in the accumulator layout.
+template <int BX, typename S>
+__device__ __forceinline__ void form_inverse(const S* LTs, int li, int lk,
+                                             typename Mfma<S>::v4 (&pacc)[BX / 16][BX / 16]) {
+    constexpr int LT = BX + 4, NTL = BX / 16;
+#pragma unroll
+    for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+        for (int tc = 0; tc < NTL; ++tc) {
+            typename Mfma<S>::v4 acc = {S(0), S(0), S(0), S(0)};
+            const int k0 = 16 * (tr > tc ? tr : tc);
+#pragma unroll
+            for (int kk = k0; kk < BX; kk += 4) {
+                const S av = LTs[(16 * tr + li) * LT + kk + lk];
+                const S bv = LTs[(16 * tc + li) * LT + kk + lk];
+                acc = Mfma<S>::op(av, bv, acc);
+            }
+            pacc[tr][tc] = acc;
+        }
+}
+
 template <int BX, typename S>
 __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double* __restrict__ K,
                                                           const int8_t* __restrict__ bct,
@@ -618,42 +793,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
     for (int j = 0; j < BY; ++j) {
         if (w == 0) {
             if (j + 2 < BY) kq2 = Kc[(size_t)(j + 2) * g.nx];
-            // ---- Cholesky of S_j fused with the inversion of its factor, NB
-            // pivots at a time: inside a block the multipliers are read from
-            // their lanes; the rows below take the block's updates with the
-            // multipliers broadcast from LDS.  Every entry sees the same
-            // operations in the same order as pivot by pivot.
-#pragma unroll
-            for (int kb = 0; kb < BX; kb += NB) {
-#pragma unroll
-                for (int k = kb; k < kb + NB; ++k) {
-                    S d = readlane_s(a[k], k);
-                    if (!(d > S(0))) {
-                        sing = 1;
-                        d = S(1);
-                    }
-                    a[k] *= rsqrt_nr(d);
-#pragma unroll
-                    for (int i = k + 1; i < kb + NB; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
-                }
-                if (kb + NB < BX) {
-                    if (scol) {
-#pragma unroll
-                        for (int k = kb; k < kb + NB; ++k) Wb[(k - kb) * BX + c] = a[k];
-                    }
-                    wave_lds_sync();
-                    // four rows at a time: bounds the multipliers held in registers
-#pragma unroll
-                    for (int i0 = kb + NB; i0 < BX; i0 += 4) {
-#pragma unroll
-                        for (int i = i0; i < i0 + 4; ++i)
-#pragma unroll
-                            for (int k = kb; k < kb + NB; ++k) a[i] = fma(-Wb[(k - kb) * BX + i], a[k], a[i]);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                    wave_lds_sync();
-                }
-            }
+            chol_invert<BX, S>(a, Wb, scol, c, sing);
             if (icol) {
 #pragma unroll
                 for (int i = 0; i < BX; ++i) LTs[c * LT + i] = a[i];
@@ -665,20 +805,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
             // L^{-1} is dead and its buffer takes the Schur term
             // -(D_j P_j D_j)[r][c] of the next row, row-major
             v4 pacc[NTL][NTL];
-#pragma unroll
-            for (int tr = 0; tr < NTL; ++tr)
-#pragma unroll
-                for (int tc = 0; tc < NTL; ++tc) {
-                    v4 acc = {S(0), S(0), S(0), S(0)};
-                    const int k0 = 16 * (tr > tc ? tr : tc);
-#pragma unroll
-                    for (int kk = k0; kk < BX; kk += 4) {
-                        const S av = LTs[(16 * tr + li) * LT + kk + lk];
-                        const S bv = LTs[(16 * tc + li) * LT + kk + lk];
-                        acc = M::op(av, bv, acc);
-                    }
-                    pacc[tr][tc] = acc;
-                }
+            form_inverse<BX, S>(LTs, li, lk, pacc);
             const bool trail = j + 1 < BY;
 #pragma unroll
             for (int tr = 0; tr < NTL; ++tr)
@@ -740,24 +867,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
             kq = kq1;
             kq1 = kq2;
             row_coeffs<BX>(g, cf, lane, c, j + 1, kq, kq1, tyu, &dg, &txr, &txl, &tyu);
-            // Selects rather than branches; cc is opaque to the optimiser so that
-            // the lane-dependent compares are formed here, not kept live across
-            // the whole row loop.
-            int cc = c;
-            asm volatile("" : "+v"(cc));
-            // a[i] = p[i] ms + e_i: ms = 1 on the lanes of S (0 elsewhere); e_i
-            // holds the tridiagonal entries there and the identity on the lanes
-            // that carry it (p[i] 1 is exact, so the sums are p[i] + entry)
-            const S ms = scol ? S(1) : S(0);
-            const S od = scol ? S(dg) : (icol ? S(1) : S(0));
-            const S orr = scol ? -S(txr) : S(0), ol = scol ? -S(txl) : S(0);
-#pragma unroll
-            for (int i = 0; i < BX; ++i) {
-                S e = (i == cc) ? od : S(0);
-                e = (i == cc + 1) ? orr : e;
-                e = (i + 1 == cc) ? ol : e;
-                a[i] = fma(p[i], ms, e);
-            }
+            build_block<BX, S>(a, p, dg, txr, txl, scol, icol, c);
         }
         if (j + 1 < BY) {
             S* t = Z;
@@ -854,6 +964,424 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
         }
     }
     if (tid == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+}
+
+// The particular column's product w = P z on the vector units, with P in the
+// accumulator layout of form_inverse (P symmetric: lane l, register v of tile
+// (k, r) holds P[16 r + l % 16][16 k + l / 16 + 4 v]) and z in LDS: each
+// lane sums its 2 BX / 4 terms of row 16 r + l % 16, and the sums of the
+// four lanes l % 16 + 16 i are added across lanes (every one of them ends
+// with the same value).
+template <int BX>
+__device__ __forceinline__ void part_product(const typename Mfma<double>::v4 (&pacc)[BX / 16][BX / 16],
+                                             const double* z, int lk, double (&out)[BX / 16]) {
+    constexpr int NTL = BX / 16;
+#pragma unroll
+    for (int tr = 0; tr < NTL; ++tr) {
+        double s = 0.0;
+#pragma unroll
+        for (int kt = 0; kt < NTL; ++kt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s = fma(pacc[kt][tr][v], z[16 * kt + lk + 4 * v], s);
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        out[tr] = s;
+    }
+}
+
+// ---------------------------------------------------------------- K1 (twisted)
+// FP64 factorisation and basis solves for subdomains 16 or 32 cells wide,
+// eliminated from both ends at once (a twisted block factorisation).  With
+// m = by / 2, wave 0 eliminates rows 0 .. m-1 upwards as above,
+//     S_0 = A_0,          S_{j+1} = A_{j+1} - D_j P_j D_j,
+// and wave 1 rows by-1 .. m+1 downwards,
+//     S_{by-1} = A_{by-1}, S_{j-1} = A_{j-1} - D_{j-1} P_j D_{j-1},
+// each with its forward sweep (w_j = P_j z_j, the right-hand side carried
+// towards row m).  Row m takes both Schur terms,
+//     S_m = A_m - D_{m-1} P_{m-1} D_{m-1} - D_m P_{m+1} D_m,
+//     x_m = P_m (f_m + D_{m-1} w_{m-1} + D_m w_{m+1}),
+// and the backward sweeps run outwards from it, one per wave:
+//     x_j = w_j + P_j D_j x_{j+1}      (j < m),
+//     x_j = w_j + P_j D_{j-1} x_{j-1}  (j > m).
+// The chain of dependent block rows is m + 1 long instead of by.  The factor
+// store holds P_j of this elimination for every row, and the particular
+// solve sweeps it the same way.  Each wave has its own L^{-1} / Schur-term
+// buffer (also the multiplier buffer of the blocked Cholesky, which is used
+// only while the buffer is free) and right-hand side block in LDS.  The
+// forward sweep takes P_j straight from the accumulators: P_j is symmetric,
+// so tile (k, r) in the accumulator layout (lane l, register v: row
+// 16 k + l / 16 + 4 v, column 16 r + l % 16) is the A operand of row tile r
+// and k-slices 4 k .. 4 k + 3.
+//
+// With part = 1 the particular problem (source qsrc, outer boundary data
+// bcv) is solved beside the basis: a single column, so its products are
+// matrix-vector products on the vector units (each lane sums its share of
+// a row of P_j from the registers that hold P_j, and the four partial sums
+// of a row are added across lanes), with its right-hand side as a vector in
+// LDS.  Its solution goes to pbar and, with do_traces, its traces to column
+// ld - 1 of T.
+template <int BX, int NCT>
+__global__ __launch_bounds__(128, 2) void k_local_setup_twist(
+    Geo g, const double* __restrict__ K, const int8_t* __restrict__ bct,
+    const double* __restrict__ beta, const int* __restrict__ slotseg, int R,
+    double* __restrict__ Pstore, double* __restrict__ Psi, double* __restrict__ T, int ld,
+    int* __restrict__ flags, const int* __restrict__ mask, int want, int do_traces, int basis,
+    const double* __restrict__ qsrc, const double* __restrict__ bcv, double* __restrict__ pbar,
+    int part) {
+    static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
+    typedef double S;
+    typedef Mfma<S> M;
+    typedef typename M::v4 v4;
+    constexpr int LT = BX + 4;              // padded row length
+    constexpr int NTL = BX / 16;            // tiles per dimension
+    static_assert(chol_wb_entries<BX, S>() <= BX * LT, "multipliers fit the L^{-1} buffer");
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != want) return;
+    extern __shared__ __align__(16) char smem[];
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
+    // NCT > 0: the column tiles of the sweeps as a constant (basis, and
+    // (R + 15) / 16 == NCT), so that the memory waits after each row's
+    // stores are counted rather than drained
+    const int NC = basis ? R : 0;           // basis columns of the sweeps
+    const int RP = (NC + 15) & ~15;         // padded to whole tiles
+    const int nct = NCT > 0 ? NCT : RP / 16;
+    part = basis ? part : 0;
+    const int m = BY / 2;                   // the row where the eliminations meet
+    char* cur = smem;
+    S* LTa = carve<S>(cur, 2 * BX * LT);    // per wave: L^{-1} rows, multipliers, Schur term
+    S* Za = carve<S>(cur, 2 * BX * RP);     // per wave: right-hand side block
+    S* tys = carve<S>(cur, BY * BX);        // couplings D_j
+    S* zpa = carve<S>(cur, 2 * BX);         // per wave: right-hand side of the particular
+    double* cf = carve<double>(cur, NF);
+    int* rs = carve<int>(cur, NF);
+    int* of = carve<int>(cur, NF);
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const bool top = w == 1;                // wave 1 starts from the top row
+    const int nrow = top ? BY - 1 - m : m;  // rows of this wave's chain (m >= either)
+    const int dir = top ? -1 : 1;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    S* Ps = Pstore + (size_t)sub * BY * BX * BX;
+    double* Psub = Psi + (size_t)sub * R * n;
+    double* pb = pbar + (size_t)sub * n;
+    S* LTs = LTa + w * BX * LT;
+    S* Z = Za + w * BX * RP;
+    S* zp = zpa + w * BX;
+
+    const bool scol = lane < BX;
+    const bool icol = lane >= BX && lane < 2 * BX;
+    const int c = scol ? lane : (icol ? lane - BX : 0);
+
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    for (int t = tid; t < 2 * BX * RP; t += 128) Za[t] = S(0);
+    if (tid < 2 * BX) zpa[tid] = S(0);
+    __syncthreads();
+    if (part) {
+        // the particular right-hand side of every cell, staged in pbar: the
+        // chains read row j + 1 of it during row j, before they overwrite it
+        for (int t = tid; t < n; t += 128) {
+            const int i = t % BX, jj = t / BX;
+            const double qv = qsrc ? qsrc[(size_t)(J * BY + jj) * g.nx + I * BX + i] : 0.0;
+            pb[t] = part_rhs<BX>(g, cf, of, bct, bcv, qv, i, jj);
+        }
+        __syncthreads();
+    }
+    if (!top || nrow > 0) {                 // f of the first row of each chain
+        const int jf = top ? BY - 1 : 0;
+        if (nct > 0) add_row_forcing<BX>(g, cf, rs, Z, RP, lane, jf);
+        if (part && scol) zp[c] = S(pb[jf * BX + c]);
+    }
+
+    // permeability of column c: kq (row being set up), kq1 (the next row of
+    // the chain), kq2 (the one after, in flight during a row's work)
+    const double* Kc = K + (size_t)J * BY * g.nx + (size_t)I * BX + c;
+    // (rows clamped to the subdomain: every load is issued, so that the
+    // compiler can count the memory operations in flight)
+    auto rowc = [&](int jr) { return jr < 0 ? 0 : (jr >= BY ? BY - 1 : jr); };
+    const int j0 = top ? BY - 1 : 0;
+    double kq = Kc[(size_t)j0 * g.nx];
+    double kq1 = Kc[(size_t)rowc(j0 + dir) * g.nx];
+    double kq2 = 1.0;
+    // coupling to the previous row of the chain (boundary conductance first)
+    double carry = top ? cf[2 * BY + BX + c] : cf[2 * BY + c];
+    S a[BX];
+    int sing = 0;
+
+    for (int t = 0; t < m; ++t) {
+        if (t < nrow) {
+            const int j = top ? BY - 1 - t : t;
+            const int jd = top ? j - 1 : j;         // coupling to the next row of the chain
+            const int jn = j + dir;
+            kq2 = Kc[(size_t)rowc(jn + dir) * g.nx];
+            const bool fnext = !top || jn > m;      // row m takes f from the lower chain
+            const double fpn = pb[jn * BX + c];     // f of the next row (unused without part)
+            double dg, txr, txl, tnx;
+            if (top) row_coeffs_down<BX>(g, cf, lane, c, j, kq, kq1, carry, &dg, &txr, &txl, &tnx);
+            else row_coeffs<BX>(g, cf, lane, c, j, kq, kq1, carry, &dg, &txr, &txl, &tnx);
+            build_block_lds<BX, S>(a, t > 0 ? LTs : nullptr, nullptr, dg, txr, txl, scol, icol, c);
+            wave_lds_sync();                        // the Schur term is read
+            chol_invert<BX, S>(a, LTs, scol, c, sing);
+            if (icol) {
+#pragma unroll
+                for (int i = 0; i < BX; ++i) LTs[c * LT + i] = a[i];
+            }
+            if (scol) tys[jd * BX + c] = S(tnx);
+            wave_lds_sync();
+            // P_j to the factor store; L^{-1} is dead once every tile is
+            // formed, and its buffer takes the next row's Schur term
+            // -(D P_j D)[r][c], row-major
+            v4 pacc[NTL][NTL];
+            form_inverse<BX, S>(LTs, li, lk, pacc);
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                for (int tc = 0; tc < NTL; ++tc)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
+                        const S pv = pacc[tr][tc][v];
+                        Ps[(size_t)j * BX * BX + r * BX + cq] = pv;
+                        LTs[r * LT + cq] = -(pv * (tys[jd * BX + r] * tys[jd * BX + cq]));
+                    }
+            // forward sweep w_j = P_j z_j, then z of the next row = D w_j + f
+            for (int ct = 0; ct < nct; ++ct) {
+                const int q = 16 * ct + li;
+                v4 acc[NTL];
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr) {
+                    acc[tr] = v4{S(0), S(0), S(0), S(0)};
+#pragma unroll
+                    for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                        acc[tr] = M::op(pacc[kq4 >> 2][tr][kq4 & 3], Z[(4 * kq4 + lk) * RP + q], acc[tr]);
+                }
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * tr + M::row(lane, v);
+                        if (q < NC) Psub[(size_t)q * n + j * BX + r] = acc[tr][v];
+                        Z[r * RP + q] = tys[jd * BX + r] * acc[tr][v];
+                    }
+            }
+            if (part) {
+                S wv[NTL];
+                part_product<BX>(pacc, zp, lk, wv);
+                wave_lds_sync();
+                if (lk == 0) {
+#pragma unroll
+                    for (int tr = 0; tr < NTL; ++tr) {
+                        const int r = 16 * tr + li;
+                        pb[j * BX + r] = wv[tr];
+                        zp[r] = tys[jd * BX + r] * wv[tr];
+                    }
+                }
+            }
+            if (fnext) {
+                wave_lds_sync();
+                if (nct > 0) add_row_forcing<BX>(g, cf, rs, Z, RP, lane, jn);
+                if (part && scol) zp[c] += S(fpn);
+            }
+            wave_lds_sync();
+            carry = tnx;
+            kq = kq1;
+            kq1 = kq2;
+        }
+    }
+    __syncthreads();                        // both chains at row m
+    S* Z0 = Za;
+    S* Z1 = Za + BX * RP;
+    const bool has_lo = m > 0, has_hi = BY - 1 - m > 0;
+    if (!top) {
+        // ---- row m
+        double dg, txr, txl, tnx;
+        row_coeffs<BX>(g, cf, lane, c, m, kq, kq1, carry, &dg, &txr, &txl, &tnx);
+        build_block_lds<BX, S>(a, has_lo ? LTs : nullptr, has_hi ? LTa + BX * LT : nullptr, dg, txr,
+                               txl, scol, icol, c);
+        wave_lds_sync();
+        chol_invert<BX, S>(a, LTs, scol, c, sing);
+        if (icol) {
+#pragma unroll
+            for (int i = 0; i < BX; ++i) LTs[c * LT + i] = a[i];
+        }
+        wave_lds_sync();
+        v4 pacc[NTL][NTL];
+        form_inverse<BX, S>(LTs, li, lk, pacc);
+#pragma unroll
+        for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+            for (int tc = 0; tc < NTL; ++tc)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
+                    Ps[(size_t)m * BX * BX + r * BX + cq] = pacc[tr][tc][v];
+                }
+        if (has_hi) {
+            for (int t = lane; t < BX * RP; t += 64) Z0[t] += Z1[t];
+            if (part && scol) zpa[c] += zpa[BX + c];
+            wave_lds_sync();
+        }
+        if (part) {
+            S xv[NTL];
+            part_product<BX>(pacc, zpa, lk, xv);
+            wave_lds_sync();
+            if (lk == 0) {
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr) {
+                    const int r = 16 * tr + li;
+                    pb[m * BX + r] = xv[tr];
+                    if (has_lo) zpa[r] = tys[(m - 1) * BX + r] * xv[tr];
+                    if (has_hi) zpa[BX + r] = tys[m * BX + r] * xv[tr];
+                }
+            }
+        }
+        if (nct > 0) {
+            // x_m = P_m z_m; the backward sweeps start from D_{m-1} x_m and D_m x_m
+            for (int ct = 0; ct < nct; ++ct) {
+                const int q = 16 * ct + li;
+                v4 acc[NTL];
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr) {
+                    acc[tr] = v4{S(0), S(0), S(0), S(0)};
+#pragma unroll
+                    for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                        acc[tr] = M::op(pacc[kq4 >> 2][tr][kq4 & 3], Z0[(4 * kq4 + lk) * RP + q], acc[tr]);
+                }
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * tr + M::row(lane, v);
+                        if (q < NC) Psub[(size_t)q * n + m * BX + r] = acc[tr][v];
+                        if (has_lo) Z0[r * RP + q] = tys[(m - 1) * BX + r] * acc[tr][v];
+                        if (has_hi) Z1[r * RP + q] = tys[m * BX + r] * acc[tr][v];
+                    }
+            }
+        }
+    }
+    __syncthreads();                        // x_m; the factor store and w_j of both chains
+    if (!basis) {
+        if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+        return;
+    }
+    // ---- backward sweeps, outwards from row m: the rows of P_j and of w_j
+    // (first WCT column tiles, and the particular) are loaded one row ahead
+    constexpr int WCT = 2;
+    S pn[NTL][BX / 4];
+    v4 wn[NTL][WCT];
+    S wpn[NTL];
+    auto load_row = [&](int jr) {
+#pragma unroll
+        for (int tr = 0; tr < NTL; ++tr) {
+#pragma unroll
+            for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                pn[tr][kq4] = Ps[(size_t)jr * BX * BX + (16 * tr + li) * BX + 4 * kq4 + lk];
+#pragma unroll
+            for (int ct = 0; ct < WCT; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q = 16 * ct + li, r = 16 * tr + M::row(lane, v);
+                    const S x = Psub[(size_t)(q < NC ? q : 0) * n + jr * BX + r];
+                    wn[tr][ct][v] = q < NC ? x : S(0);
+                }
+            wpn[tr] = pb[jr * BX + 16 * tr + li];    // (unused without part)
+        }
+    };
+    if (nrow > 0) load_row(top ? m + 1 : m - 1);
+    for (int t = 0; t < m; ++t) {
+        if (t < nrow) {
+            const int j = top ? m + 1 + t : m - 1 - t;
+            const int jd = top ? j : j - 1;         // coupling to the next row of the sweep
+            const bool more = t + 1 < nrow;
+            S pc[NTL][BX / 4];
+            v4 wc[NTL][WCT];
+            S wpc[NTL];
+#pragma unroll
+            for (int tr = 0; tr < NTL; ++tr) {
+#pragma unroll
+                for (int kq4 = 0; kq4 < BX / 4; ++kq4) pc[tr][kq4] = pn[tr][kq4];
+#pragma unroll
+                for (int ct = 0; ct < WCT; ++ct) wc[tr][ct] = wn[tr][ct];
+                wpc[tr] = wpn[tr];
+            }
+            if (more) load_row(j - dir);
+            for (int ct = 0; ct < nct; ++ct) {
+                const int q = 16 * ct + li;
+                v4 acc[NTL];
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr) {
+                    if (ct < WCT) {
+#pragma unroll
+                        for (int u = 0; u < WCT; ++u)
+                            if (u == ct) acc[tr] = wc[tr][u];
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int r = 16 * tr + M::row(lane, v);
+                            acc[tr][v] = q < NC ? Psub[(size_t)q * n + j * BX + r] : S(0);
+                        }
+                    }
+#pragma unroll
+                    for (int kq4 = 0; kq4 < BX / 4; ++kq4)
+                        acc[tr] = M::op(pc[tr][kq4], Z[(4 * kq4 + lk) * RP + q], acc[tr]);
+                }
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int r = 16 * tr + M::row(lane, v);
+                        if (q < NC) Psub[(size_t)q * n + j * BX + r] = acc[tr][v];
+                        if (more) Z[r * RP + q] = tys[jd * BX + r] * acc[tr][v];
+                    }
+            }
+            if (part) {
+                // x_j = w_j + P_j z, P_j as held for the products above
+                S xv[NTL];
+#pragma unroll
+                for (int tr = 0; tr < NTL; ++tr) {
+                    S sacc = S(0);
+#pragma unroll
+                    for (int kq4 = 0; kq4 < BX / 4; ++kq4) sacc = fma(pc[tr][kq4], zp[4 * kq4 + lk], sacc);
+                    sacc += __shfl_xor(sacc, 16, 64);
+                    sacc += __shfl_xor(sacc, 32, 64);
+                    xv[tr] = wpc[tr] + sacc;
+                }
+                wave_lds_sync();
+                if (lk == 0) {
+#pragma unroll
+                    for (int tr = 0; tr < NTL; ++tr) {
+                        const int r = 16 * tr + li;
+                        pb[j * BX + r] = xv[tr];
+                        if (more) zp[r] = tys[jd * BX + r] * xv[tr];
+                    }
+                }
+            }
+            wave_lds_sync();
+        }
+    }
+    __syncthreads();
+    if (do_traces) {
+        // traces T[a][b] = sum_{f in slot a} c_f (x_b(cell f) - delta_ab); the
+        // particular column (no delta) to column ld - 1
+        double* Tsub = T + (size_t)sub * R * ld;
+        const int ncolt = R + part;
+        for (int t = tid; t < R * ncolt; t += 128) {
+            const int ar = t / ncolt, b = t % ncolt;
+            const bool pc = b == R;
+            double s = 0.0;
+            if (ss[ar] >= 0 && (pc || ss[b] >= 0)) {
+                const double* col = pc ? pb : Psub + (size_t)b * n;
+                for (int u = 0; u < g.sg; ++u) {
+                    const int f = face_of_slot(g, BX, ar, u);
+                    int side, i, jj;
+                    face_cell(g, BX, f, &side, &i, &jj);
+                    s += cf[f] * (col[jj * BX + i] - (ar == b ? 1.0 : 0.0));
+                }
+            }
+            Tsub[(size_t)ar * ld + (pc ? ld - 1 : b)] = s;
+        }
+    }
+    if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
 }
 
 // One refinement pass on the matrix cores (subdomains 16 or 32 cells wide):
@@ -1114,26 +1642,6 @@ __global__ __launch_bounds__(64) void k_local_traces(Geo g, const double* __rest
         }
         Tsub[(size_t)ar * ld + b] = s;
     }
-}
-
-// Right-hand side of the particular problem at cell (i, j): the source plus
-// the outer boundary data (Dirichlet |f|/rho g_D, Neumann -g_N).
-template <int BX>
-__device__ inline double part_rhs(const Geo& g, const double* cf, const int* of,
-                                  const int8_t* __restrict__ bct, const double* __restrict__ bcv,
-                                  double qv, int i, int j) {
-    const int BY = g.by;
-    double f = qv;
-    const int faces[4] = {i == 0 ? j : -1, i == BX - 1 ? BY + j : -1, j == 0 ? 2 * BY + i : -1,
-                          j == BY - 1 ? 2 * BY + BX + i : -1};
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int fc = faces[s];
-        if (fc < 0) continue;
-        const int o = of[fc];
-        if (o >= 0) f += bct[o] == RMRCM_BC_DIRICHLET ? cf[fc] * bcv[o] : -bcv[o];
-    }
-    return f;
 }
 
 // ---------------------------------------------------------------- refinement
@@ -1447,10 +1955,170 @@ __global__ __launch_bounds__(64) void k_local_particular(
         }
 }
 
+// Particular solution with the FP64 factor store of the twisted elimination
+// (subdomains 16 or 32 cells wide): lanes 0..BX-1 sweep rows 0..m-1
+// upwards, lanes BX..2BX-1 rows by-1..m+1 downwards (lane c of a chain
+// holding row c of P_j), both meet at row m, and the backward sweeps run
+// outwards from it.  Output as above.
+template <int BX>
+__global__ __launch_bounds__(64) void k_local_particular_twist(
+    Geo g, const double* __restrict__ K, const int8_t* __restrict__ bct,
+    const double* __restrict__ beta, const int* __restrict__ slotseg, int R,
+    const double* __restrict__ q, const double* __restrict__ bcv,
+    const double* __restrict__ Pstore, double* __restrict__ pbar, double* __restrict__ T, int ld,
+    const int* __restrict__ mask, int want, int do_traces) {
+    static_assert(2 * BX <= 64, "two chains of BX lanes");
+    const int sub = blockIdx.x;
+    if (mask && mask[sub] != want) return;
+    extern __shared__ __align__(16) char smem[];
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY), m = BY / 2;
+    char* cur = smem;
+    double* fs = carve<double>(cur, n);     // right-hand side, then w, then x
+    double* zb = carve<double>(cur, 2 * BX);
+    double* cf = carve<double>(cur, NF);
+    int* rs = carve<int>(cur, NF);
+    int* of = carve<int>(cur, NF);
+    __shared__ int nonzero;
+    const int lane = threadIdx.x;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    const double* Ps = Pstore + (size_t)sub * BY * BX * BX;
+    double* pb = pbar + (size_t)sub * n;
+    double* Tsub = T + (size_t)sub * R * ld;
+    const int h = lane / BX;                // 0: upwards from row 0, 1: downwards from the top
+    const int c = lane % BX;
+    const int nrow = h == 0 ? m : (h == 1 ? BY - 1 - m : 0);
+    const int dir = h == 0 ? 1 : -1;
+
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    if (lane == 0) nonzero = 0;
+    __syncthreads();
+    bool nz = false;
+    for (int t = lane; t < n; t += 64) {
+        const int i = t % BX, j = t / BX;
+        const double qv = q ? q[(size_t)(J * BY + j) * g.nx + I * BX + i] : 0.0;
+        const double f = part_rhs<BX>(g, cf, of, bct, bcv, qv, i, j);
+        fs[t] = f;
+        nz |= f != 0.0;
+    }
+    if (nz) nonzero = 1;
+    __syncthreads();
+    if (!nonzero) {
+        for (int t = lane; t < n; t += 64) pb[t] = 0.0;
+        if (do_traces)
+            for (int a = lane; a < R; a += 64) Tsub[(size_t)a * ld + ld - 1] = 0.0;
+        return;
+    }
+    const double* Kc = K + (size_t)J * BY * g.nx + (size_t)I * BX + c;
+    double p[BX], pn[BX];
+    auto load_p = [&](int jr) {
+#pragma unroll
+        for (int k = 0; k < BX; ++k) pn[k] = Ps[(size_t)jr * BX * BX + k * BX + c];
+    };
+    if (nrow > 0) load_p(h == 0 ? 0 : BY - 1);
+    double wv = 0.0, dprev = 0.0;
+    for (int t = 0; t < m; ++t) {
+        const bool on = t < nrow;
+        const int j = h == 0 ? t : BY - 1 - t;
+        const int jd = h == 0 ? j : j - 1;      // coupling to the next row of the chain
+#pragma unroll
+        for (int k = 0; k < BX; ++k) p[k] = pn[k];
+        if (on && t + 1 < nrow) load_p(j + dir);
+        double klo = 1.0, khi = 1.0;
+        if (on) {
+            klo = Kc[(size_t)jd * g.nx];
+            khi = Kc[(size_t)(jd + 1) * g.nx];
+            zb[h * BX + c] = fs[j * BX + c] + dprev * wv;
+        }
+        __syncthreads();
+        if (on) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < BX; ++k) s = fma(p[k], zb[h * BX + k], s);
+            wv = s;
+            fs[j * BX + c] = s;
+            dprev = tpy(g, klo, khi);
+            pb[jd * BX + c] = dprev;            // D staged in the output; overwritten at the end
+        }
+        __syncthreads();
+    }
+    // row m: z_m = f_m + D_{m-1} w_{m-1} + D_m w_{m+1}
+    if (h == 1) zb[BX + c] = dprev * wv;
+    if (h == 0) load_p(m);
+    __syncthreads();
+    if (h == 0) zb[c] = (fs[m * BX + c] + dprev * wv) + zb[BX + c];
+    __syncthreads();
+    if (h == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < BX; ++k) s = fma(pn[k], zb[k], s);
+        wv = s;
+        fs[m * BX + c] = s;
+    }
+    __syncthreads();
+    if (h == 1) wv = fs[m * BX + c];
+    if (nrow > 0) load_p(m - dir);
+    for (int t = 0; t < m; ++t) {
+        const bool on = t < nrow;
+        const int j = h == 0 ? m - 1 - t : m + 1 + t;
+        const int jd = h == 0 ? j : j - 1;      // coupling to the row solved before
+#pragma unroll
+        for (int k = 0; k < BX; ++k) p[k] = pn[k];
+        if (on && t + 1 < nrow) load_p(j - dir);
+        if (on) zb[h * BX + c] = pb[jd * BX + c] * wv;
+        __syncthreads();
+        if (on) {
+            double s = fs[j * BX + c];
+#pragma unroll
+            for (int k = 0; k < BX; ++k) s = fma(p[k], zb[h * BX + k], s);
+            wv = s;
+            fs[j * BX + c] = s;
+        }
+        __syncthreads();
+    }
+    for (int t = lane; t < n; t += 64) pb[t] = fs[t];
+    __syncthreads();
+    if (do_traces)
+        for (int a = lane; a < R; a += 64) {
+            double s = 0.0;
+            if (ss[a] >= 0)
+                for (int u = 0; u < g.sg; ++u) {
+                    const int f = face_of_slot(g, BX, a, u);
+                    int side, i, jj;
+                    face_cell(g, BX, f, &side, &i, &jj);
+                    s += cf[f] * fs[jj * BX + i];
+                }
+            Tsub[(size_t)a * ld + ld - 1] = s;
+        }
+}
+
 // ---------------------------------------------------------------- launchers
 template <int BX, typename S>
-static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do_traces, int basis) {
-    if constexpr (BX >= 16) {
+static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do_traces, int basis,
+                            int part) {
+    if constexpr (BX >= 16 && std::is_same<S, double>::value) {
+        const Level& L = c->levels[c->D];
+        const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY);
+        const int RP = basis ? (R + 15) & ~15 : 0;
+        const size_t lds = carve_bytes(2 * BX * (BX + 4), 8) + carve_bytes(2 * BX * RP, 8) +
+                           carve_bytes(BY * BX, 8) + carve_bytes(2 * BX, 8) + carve_bytes(NF, 8) +
+                           2 * carve_bytes(NF, 4);
+        const int nsub = c->geo.mx * c->geo.my;
+        auto go = [&](auto kern) -> hipError_t {
+            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3(nsub), dim3(128), lds, c->stream, c->geo, c->K, c->bct,
+                               c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask, want,
+                               do_traces, basis, c->q, c->bcv, c->pbar, part);
+            return hipGetLastError();
+        };
+        switch (RP / 16) {
+            case 1: return go(k_local_setup_twist<BX, 1>);
+            case 2: return go(k_local_setup_twist<BX, 2>);
+            default: return go(k_local_setup_twist<BX, 0>);
+        }
+    } else if constexpr (BX >= 16) {
         const Level& L = c->levels[c->D];
         const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY), RP = (R + 15) & ~15;
         const size_t lds = carve_bytes(BX * (BX + 4), sizeof(S)) + carve_bytes(chol_wb_entries<BX, S>(), sizeof(S)) +
@@ -1483,6 +2151,19 @@ template <int BX, typename S>
 static hipError_t part_bx(rmrcm_ctx* c, const S* P, const int* mask, int want, int do_traces) {
     const Level& L = c->levels[c->D];
     const int BY = c->geo.by, NF = 2 * (BX + BY);
+    if constexpr (BX >= 16 && std::is_same<S, double>::value) {
+        // the factor store of the twisted elimination
+        const size_t lds = carve_bytes(BX * BY, 8) + carve_bytes(2 * BX, 8) + carve_bytes(NF, 8) +
+                           2 * carve_bytes(NF, 4);
+        hipError_t e = hipFuncSetAttribute((const void*)k_local_particular_twist<BX>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        const int nsub = c->geo.mx * c->geo.my;
+        hipLaunchKernelGGL((k_local_particular_twist<BX>), dim3(nsub), dim3(64), lds, c->stream,
+                           c->geo, c->K, c->bct, c->beta, L.slotseg, L.nslot, c->q, c->bcv, P,
+                           c->pbar, L.T, L.ld, mask, want, do_traces);
+        return hipGetLastError();
+    }
     const size_t lds = carve_bytes(BX * BY, 8) + carve_bytes(BX, sizeof(S)) + carve_bytes(NF, 8) +
                        2 * carve_bytes(NF, 4);
     hipError_t e = hipFuncSetAttribute((const void*)k_local_particular<BX, S>,
@@ -1562,17 +2243,22 @@ hipError_t launch_check_perm(rmrcm_ctx* c) {
     return hipErrorInvalidValue;
 
 hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces,
-                              int basis) {
+                              int basis, int part) {
+    if (part && !local_setup_solves_particular(c, fp32)) return hipErrorInvalidValue;
     if (fp32) {
-        RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces, basis)),
-                        (setup_bx<8, float>(c, c->P32, mask, want, do_traces, basis)),
-                        (setup_bx<16, float>(c, c->P32, mask, want, do_traces, basis)),
-                        (setup_bx<32, float>(c, c->P32, mask, want, do_traces, basis)))
+        RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces, basis, 0)),
+                        (setup_bx<8, float>(c, c->P32, mask, want, do_traces, basis, 0)),
+                        (setup_bx<16, float>(c, c->P32, mask, want, do_traces, basis, 0)),
+                        (setup_bx<32, float>(c, c->P32, mask, want, do_traces, basis, 0)))
     }
-    RMRCM_BX_SWITCH((setup_bx<4, double>(c, c->Pstore, mask, want, do_traces, basis)),
-                    (setup_bx<8, double>(c, c->Pstore, mask, want, do_traces, basis)),
-                    (setup_bx<16, double>(c, c->Pstore, mask, want, do_traces, basis)),
-                    (setup_bx<32, double>(c, c->Pstore, mask, want, do_traces, basis)))
+    RMRCM_BX_SWITCH((setup_bx<4, double>(c, c->Pstore, mask, want, do_traces, basis, 0)),
+                    (setup_bx<8, double>(c, c->Pstore, mask, want, do_traces, basis, 0)),
+                    (setup_bx<16, double>(c, c->Pstore, mask, want, do_traces, basis, part)),
+                    (setup_bx<32, double>(c, c->Pstore, mask, want, do_traces, basis, part)))
+}
+
+bool local_setup_solves_particular(const rmrcm_ctx* c, bool fp32) {
+    return !fp32 && (c->geo.bx == 16 || c->geo.bx == 32);
 }
 
 hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,

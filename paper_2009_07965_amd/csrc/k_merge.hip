@@ -1036,26 +1036,27 @@ hipError_t launch_merge_apply(rmrcm_ctx* c, int d, int ct) {
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_merge_setup(rmrcm_ctx* c, int d) {
+hipError_t launch_merge_setup(rmrcm_ctx* c, int d, bool part) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
+    const int ncol = a.nslot + (part ? 1 : 0);
     if (qd_tier(a.g)) {
         hipError_t e = qd_factor_any(c, a);
         if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
-        return qd_columns_any(c, a, 0, a.nslot, true, c->ct_tune[d]);
+        return qd_columns_any(c, a, 0, ncol, true, c->ct_tune[d]);
     }
     hipLaunchKernelGGL(k_merge_assemble, dim3(a.nnodes, (a.xi * a.xi + 255) / 256), dim3(256), 0,
                        c->stream, a);
     hipLaunchKernelGGL(k_merge_lu, dim3(a.nnodes), dim3(256), 0, c->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || d == 0) return e;
-    hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi * a.nslot + 255) / 256), dim3(256), 0,
-                       c->stream, a, 0, a.nslot);
-    e = solve_cols_generic(c, a, 0, a.nslot);
+    hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi * ncol + 255) / 256), dim3(256), 0,
+                       c->stream, a, 0, ncol);
+    e = solve_cols_generic(c, a, 0, ncol);
     if (e != hipSuccess) return e;
-    const size_t tot = (size_t)a.nslot * a.nslot;
+    const size_t tot = (size_t)a.nslot * ncol;
     hipLaunchKernelGGL(k_merge_trace, dim3(a.nnodes, (unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       c->stream, a, 0, a.nslot);
+                       c->stream, a, 0, ncol);
     return hipGetLastError();
 }
 

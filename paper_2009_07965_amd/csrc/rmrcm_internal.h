@@ -128,15 +128,21 @@ namespace rmrcm {
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_beta(rmrcm_ctx* c);
 hipError_t launch_check_perm(rmrcm_ctx* c);
+// part = 1: the particular problem solved beside the basis (FP64, subdomains
+// 16 or 32 cells wide: local_setup_solves_particular), its solution to
+// pbar and its traces to the last column of the finest T.
 hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces,
-                              int basis = 1);
+                              int basis = 1, int part = 0);
+bool local_setup_solves_particular(const rmrcm_ctx* c, bool fp32);
 hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,
                                    int do_traces);
 hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply);
 hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want);
 hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol);
 hipError_t launch_max_resid(rmrcm_ctx* c, int part, double* out);
-hipError_t launch_merge_setup(rmrcm_ctx* c, int depth);
+// part: the particular column is eliminated with the basis columns (their
+// traces already hold it), as launch_merge_particular would below the top.
+hipError_t launch_merge_setup(rmrcm_ctx* c, int depth, bool part = false);
 hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
 hipError_t launch_reconstruct(rmrcm_ctx* c);

@@ -1,11 +1,16 @@
 """rmrcm_step (refactor + solve as one unit, a replayed HIP graph for FP64
 contexts with device arrays) on the GPU.
 
-The graph runs the same kernels on the same data as rmrcm_refactor followed
-by rmrcm_solve, so results are compared bit for bit with that path, and with
-the oracle at the FP64 bar; replays with new permeability and sources at the
-same pointers, new output arrays (a new capture), host arrays (the eager
-path) and an incompatible all-Neumann source (EINVAL at sync).
+The graph carries the particular problem as one more column of the local
+sweeps and of the merges below the top, where rmrcm_refactor followed by
+rmrcm_solve runs it as a chain of its own: the two differ only in the order
+of the particular sweeps' sums, so they are compared at STEP_TOL (rounding
+of the sweeps, 1e-16, times the growth through the hierarchy), and both
+with the oracle at the FP64 bar.  Replays with new permeability and sources
+at the same pointers, new output arrays (a new capture, bit for bit), host
+arrays (the eager path, bit for bit), subdomains 8, 16 and 32 cells wide
+(8: the particular solve follows the local setup in the same chain) and an
+incompatible all-Neumann source (EINVAL at sync).
 """
 
 import sys
@@ -20,6 +25,7 @@ from oracle.mrcm import mrcm_solve
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
+STEP_TOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -52,10 +58,11 @@ def eager(L, prob):
         S.close()
 
 
-def test_step_equals_refactor_and_solve(env):
+@pytest.mark.parametrize("n,b,seg", [(256, 32, 8), (128, 16, 4), (64, 8, 2)])
+def test_step_equals_refactor_and_solve(env, n, b, seg):
     L, torch = env
-    base = make_problem(256, b=32, seg=8, log_var=2.0, seed=31)
-    probs = [make_problem(256, b=32, seg=8, log_var=lv, lam=0.08, seed=40 + k, source=True)
+    base = make_problem(n, b=b, seg=seg, log_var=2.0, seed=31)
+    probs = [make_problem(n, b=b, seg=seg, log_var=lv, lam=0.08, seed=40 + k, source=True)
              for k, lv in enumerate((1.0, 3.0, 4.5))]
     S = L.Solver.from_problem(base)
     stream = torch.cuda.Stream()
@@ -63,7 +70,7 @@ def test_step_equals_refactor_and_solve(env):
         S.set_stream(stream.cuda_stream)
         K, q, bv, pd, fd = dev_arrays(torch, probs[0])
         for k, pr in enumerate(probs):
-            say("[gpu] step %d" % k)
+            say("[gpu] step %d, n %d, b %d" % (k, n, b))
             K.copy_(torch.from_numpy(pr.K))
             q.copy_(torch.from_numpy(pr.q))
             bv.copy_(torch.from_numpy(pr.bc_value))
@@ -72,7 +79,7 @@ def test_step_equals_refactor_and_solve(env):
             S.sync()
             p, F = pd.cpu().numpy(), fd.cpu().numpy()
             pe, Fe = eager(L, pr)
-            assert np.array_equal(p, pe) and np.array_equal(F, Fe), k
+            assert rel_l2(p, pe) <= STEP_TOL and rel_l2(F, Fe) <= STEP_TOL, k
             ref = mrcm_solve(pr)
             assert rel_l2(p, ref.p) <= TOL and rel_l2(F, ref.F) <= TOL
         st = S.stats()              # timers of the last run outside the graph
@@ -85,7 +92,7 @@ def test_step_equals_refactor_and_solve(env):
         assert torch.equal(pd2, pd) and torch.equal(fd2, fd)
         # an ordinary solve after steps (eager path, same context)
         p3, F3 = S.solve(probs[-1].q, probs[-1].bc_value)
-        assert np.array_equal(p3, pd.cpu().numpy()) and np.array_equal(F3, fd.cpu().numpy())
+        assert rel_l2(p3, pd.cpu().numpy()) <= STEP_TOL and rel_l2(F3, fd.cpu().numpy()) <= STEP_TOL
     finally:
         S.close()
 
