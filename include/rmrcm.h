@@ -143,14 +143,16 @@ int rmrcm_refactor(rmrcm_ctx* ctx, const double* perm);
 int rmrcm_sync(rmrcm_ctx* ctx);
 
 /* rmrcm_refactor(perm) followed by rmrcm_solve(source, bc_value, pressure,
- * flux) as one unit, with the same arguments and results.  For an FP64
- * context whose arrays are all in device memory the whole step is captured
- * once as a HIP graph and replayed (the particular chain of Section 3.2 runs
- * beside the setup merges on the context's auxiliary stream; pressures and
- * fluxes are written in place); the graph is captured again when any
- * pointer differs from the previous call's; the phase timers of
- * rmrcm_get_stats keep the values of the last refactor or solve run outside
- * such a graph.  Asynchronous on a stream set
+ * flux) as one unit, with the same arguments and results up to rounding.
+ * For an FP64 context whose arrays are all in device memory the whole step
+ * is captured once as a HIP graph of one chain and replayed: the particular
+ * problem (Section 2.1) is solved beside the basis in the local setup and
+ * its column eliminated with the basis columns in every merge (Section 3.2),
+ * the kernels read the caller's arrays and write pressures and fluxes in
+ * place; the graph is captured again when any pointer differs from the
+ * previous call's; the phase timers of rmrcm_get_stats keep the values of
+ * the last refactor or solve run outside such a graph.  Asynchronous on a
+ * stream set
  * with rmrcm_set_stream (device errors, including incompatible all-Neumann
  * data, are returned by rmrcm_sync); otherwise waits.  Other contexts and
  * host arrays: exactly rmrcm_refactor + rmrcm_solve.

@@ -280,7 +280,7 @@ void free_all(rmrcm_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->lev)
         if (e) (void)hipEventDestroy(e);
-    for (hipEvent_t e : {c->ev_ls, c->ev_done, c->ev_aux, c->ev_fork})
+    for (hipEvent_t e : {c->ev_ls, c->ev_done, c->ev_aux})
         if (e) (void)hipEventDestroy(e);
     if (c->gstep) (void)hipGraphExecDestroy(c->gstep);
     c->gstep = nullptr;
@@ -394,7 +394,7 @@ int mark(rmrcm_ctx* c, int i) {
 // FP64 contexts outside graph capture run the particular chain (local
 // particular solves, merges of the particular column below the top) on the
 // auxiliary stream, each level after its own setup merge.
-bool overlap(const rmrcm_ctx* c) { return c->aux && (!c->capturing || c->step_capture) && !mixed(c); }
+bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c); }
 
 // Every permeability-dependent step, enqueued on c->stream (no host
 // synchronisation in FP64 mode, so that it can be captured in a graph).
@@ -457,15 +457,13 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     hipStream_t main = c->stream;
     c->stream = c->aux;
     int r = RMRCM_OK;
-    // in a step graph the chain starts at the fork recorded before the setup
-    hipError_t e = c->capturing ? hipStreamWaitEvent(c->aux, c->ev_fork, 0)
-                   : c->done_recorded ? hipStreamWaitEvent(c->aux, c->ev_done, 0) : hipSuccess;
+    hipError_t e = c->done_recorded ? hipStreamWaitEvent(c->aux, c->ev_done, 0) : hipSuccess;
     if (e == hipSuccess) r = solve_inputs(c, source, bc_value);
     if (e == hipSuccess && r == RMRCM_OK && !c->any_dirichlet) e = rmrcm::launch_compat_check(c);
     if (e == hipSuccess && r == RMRCM_OK) e = hipStreamWaitEvent(c->aux, c->ev_ls, 0);
-    if (e == hipSuccess && r == RMRCM_OK && !c->capturing) e = hipEventRecord(c->ev[13], c->aux);
+    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[13], c->aux);
     if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 1);
-    if (e == hipSuccess && r == RMRCM_OK && !c->capturing) e = hipEventRecord(c->ev[14], c->aux);
+    if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[14], c->aux);
     // the particular merges of levels 2 and deeper start once the setup
     // merges have reached level 2, that of level 1 after its own: two
     // cross-stream dependencies only (each costs the setup chain, the longer
@@ -488,10 +486,8 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
     TRY(mark(c, 9));
-    if (!c->capturing) {
-        HIP_TRY(hipEventRecord(c->ev_done, c->stream));
-        c->done_recorded = true;
-    }
+    HIP_TRY(hipEventRecord(c->ev_done, c->stream));
+    c->done_recorded = true;
     c->solve_overlapped = true;
     return RMRCM_OK;
 }
@@ -530,10 +526,11 @@ int enqueue_solve(rmrcm_ctx* c) {
 // through the local sweeps (subdomains 16 or 32 cells wide; otherwise its
 // own local solve follows the setup) and every merge below the top, so that
 // the particular chain of a separate solve is not needed.  c->K, c->q and
-// c->bcv point at the step's inputs.
-int enqueue_step_fused(rmrcm_ctx* c) {
+// c->bcv point at the step's inputs; the permeability check also copies the
+// permeability to kcopy (the library's own copy, for later calls).
+int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
     HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
-    HIP_TRY(rmrcm::launch_check_perm(c));
+    HIP_TRY(rmrcm::launch_check_perm(c, kcopy));
     HIP_TRY(rmrcm::launch_beta(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_compat_check(c));
     if (rmrcm::local_setup_solves_particular(c, false)) {
@@ -659,8 +656,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
                 return fail(RMRCM_EDEVICE);
         if (hipEventCreateWithFlags(&c->ev_ls, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
+            hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess)
             return fail(RMRCM_EDEVICE);
     }
     const Geo& g = c->geo;
@@ -1332,7 +1328,7 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
     if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
     const bool dev = is_device_ptr(perm) && (!source || is_device_ptr(source)) &&
                      is_device_ptr(bc_value) && is_device_ptr(pressure) && is_device_ptr(flux);
-    if (mixed(c) || !c->aux || !dev) {
+    if (mixed(c) || !dev) {
         TRY(rmrcm_refactor(c, perm));
         return rmrcm_solve(c, source, bc_value, pressure, flux);
     }
@@ -1352,28 +1348,20 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
         double* bo = c->bcv;
         c->pout = pressure;                 // the reconstruction writes the caller's arrays
         c->fout = flux;
-        c->step_capture = true;
         const int r = capture(
             c, c->stream,
             [&](rmrcm_ctx* cc) -> int {
-                HIP_TRY(hipEventRecord(cc->ev_fork, cc->stream));
                 // the kernels read the caller's permeability, source and
                 // boundary data; the library's copy of the permeability (for
-                // later calls) is made on the auxiliary branch
+                // later calls) is written by the permeability check
                 const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
-                HIP_TRY(hipStreamWaitEvent(cc->aux, cc->ev_fork, 0));
-                HIP_TRY(hipMemcpyAsync(ko, perm, ncell * sizeof(double), hipMemcpyDeviceToDevice, cc->aux));
-                HIP_TRY(hipEventRecord(cc->ev_aux, cc->aux));
                 cc->K = const_cast<double*>(perm);
                 cc->bcv = const_cast<double*>(bc_value);
                 if (source) cc->q = const_cast<double*>(source);
                 else HIP_TRY(rmrcm::launch_fill_f64(cc, cc->q, ncell, 0.0));
-                TRY(enqueue_step_fused(cc));
-                HIP_TRY(hipStreamWaitEvent(cc->stream, cc->ev_aux, 0));
-                return RMRCM_OK;
+                return enqueue_step_fused(cc, ko);
             },
             &c->gstep);
-        c->step_capture = false;
         c->pout = po;
         c->fout = fo;
         c->K = ko;

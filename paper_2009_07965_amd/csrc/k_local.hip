@@ -119,12 +119,15 @@ __global__ void k_beta(Geo g, const double* __restrict__ K, double* __restrict__
 }
 
 // Flags a permeability that is not finite and positive.
-__global__ void k_check_perm(const double* __restrict__ K, size_t n, int* __restrict__ flags) {
+// With copy non-null the values are also copied there.
+__global__ void k_check_perm(const double* __restrict__ K, size_t n, int* __restrict__ flags,
+                             double* __restrict__ copy) {
     bool bad = false;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (size_t)gridDim.x * blockDim.x) {
         const double v = K[t];
         bad |= !(v > 0.0) || !(v <= 1.7976931348623157e308);
+        if (copy) copy[t] = v;
     }
     if (bad) atomicOr(&flags[FLAG_BAD_PERM], 1);
 }
@@ -2227,9 +2230,9 @@ hipError_t launch_beta(rmrcm_ctx* c) {
     return hipGetLastError();
 }
 
-hipError_t launch_check_perm(rmrcm_ctx* c) {
+hipError_t launch_check_perm(rmrcm_ctx* c, double* copy) {
     const size_t n = (size_t)c->geo.nx * c->geo.ny;
-    hipLaunchKernelGGL(k_check_perm, dim3(1024), dim3(256), 0, c->stream, c->K, n, c->flags);
+    hipLaunchKernelGGL(k_check_perm, dim3(1024), dim3(256), 0, c->stream, c->K, n, c->flags, copy);
     return hipGetLastError();
 }
 

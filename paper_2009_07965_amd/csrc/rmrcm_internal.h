@@ -71,7 +71,6 @@ struct rmrcm_ctx {
     bool setup_recorded = false;
     bool solve_recorded = false;
     bool capturing = false;       // enqueueing into a graph capture: no events, no host sync
-    bool step_capture = false;    // capturing rmrcm_step: overlap kept, timers as graph nodes
     hipGraphExec_t gstep = nullptr;            // rmrcm_step graph (FP64 contexts)
     const void* gstep_key[5] = {};             // the pointers it was captured with
     int ct_tune[32] = {};         // per depth: column tile of the merge apply (0 = default)
@@ -107,7 +106,7 @@ struct rmrcm_ctx {
     // the local setup, the inputs of a solve and the end of the aux work
     hipStream_t aux = nullptr;
     hipEvent_t lev[32] = {};
-    hipEvent_t ev_ls = nullptr, ev_done = nullptr, ev_aux = nullptr, ev_fork = nullptr;
+    hipEvent_t ev_ls = nullptr, ev_done = nullptr, ev_aux = nullptr;
     bool lev_recorded = false, done_recorded = false;
     bool solve_overlapped = false;  // the last solve ran the particular chain on aux
     double t_setup_ms[8] = {};
@@ -127,7 +126,8 @@ namespace rmrcm {
 
 // Kernel launchers (return hipError_t of the launch).
 hipError_t launch_beta(rmrcm_ctx* c);
-hipError_t launch_check_perm(rmrcm_ctx* c);
+// copy non-null: the permeability is also copied there in the same pass.
+hipError_t launch_check_perm(rmrcm_ctx* c, double* copy = nullptr);
 // part = 1: the particular problem solved beside the basis (FP64, subdomains
 // 16 or 32 cells wide: local_setup_solves_particular), its solution to
 // pbar and its traces to the last column of the finest T.
