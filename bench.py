@@ -98,8 +98,10 @@ def algorithmic_work(prob):
     nsub = len(r_act)
     ncell = prob.nx * prob.ny
     w = {}
-    # band Cholesky (half-bandwidth bx) of every subdomain + 2 sweeps per basis column
+    # band Cholesky (half-bandwidth bx) of every subdomain + 2 sweeps per basis
+    # column, and per the particular column (the local setup of a step)
     w["local_setup_flops"] = float(np.sum(n * (bx * bx + 3 * bx) + 4.0 * n * bx * r_act))
+    w["local_step_flops"] = float(np.sum(n * (bx * bx + 3 * bx) + 4.0 * n * bx * (r_act + 1)))
     # particular: two sweeps reading the factor store once each way, q in, pbar out
     w["local_part_bytes"] = float(nsub * (2 * 8 * by * bx * bx) + ncell * (8 + 8 + 8))
     # reconstruction: basis read once, pbar + K in, p + 4 fluxes out
@@ -299,13 +301,15 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         S.sync()                   # deferred device-side status of the refactors
-        # per-phase times from the library's HIP events, on untimed extra steps
-        # run outside the step graph (refactor, then solve)
+        # per-phase times from the library's HIP events on the context's
+        # stream, on untimed extra steps that run the step's chain of kernels
+        # launch by launch (the graph records no events)
         phases = []
+        S.set_step_graph(False)
         for _ in range(min(args.steps, 5)):
-            S.refactor(K, wait=False)
-            S.solve(q, bcv, p_out, f_out)
+            step()
             phases.append(S.stats())
+        S.set_step_graph(True)
         S.sync()
         S.close()
         return {"ms": (t1 - t0) * 1e3 / args.steps, "phases": phases,
@@ -357,18 +361,25 @@ def main():
     t_recon = avg("solve_ms", "reconstruct")
     work = algorithmic_work(prob)
     fp64_best = best == "fp64"
+    # FP64: the step's local setup solves the particular problem beside the
+    # basis (one more column); the mixed modes run refactor + solve
     cands = {
-        "k_local_setup": (t_local, "alu", work["local_setup_flops"],
+        "k_local_setup": (t_local, "alu", work["local_step_flops" if fp64_best else "local_setup_flops"],
                           PEAK_FP64 if fp64_best else PEAK_FP32, "TFLOP/s", 1e12),
         "k_reconstruct": (t_recon, "hbm", work["recon_bytes"], PEAK_HBM, "GB/s", 1e9),
-        "k_local_particular": (t_part, "hbm", work["local_part_bytes"], PEAK_HBM, "GB/s", 1e9),
     }
+    if not fp64_best:
+        cands["k_local_particular"] = (t_part, "hbm", work["local_part_bytes"], PEAK_HBM, "GB/s", 1e9)
     dom = max(cands, key=lambda k: cands[k][0])
     t_k, bound, amount, peak, unit, scale = cands[dom]
     achieved = amount / (t_k * 1e-3)
+    if dom == "k_local_setup" and fp64_best and prob.sub_nx in (16, 32):
+        # the template instance in the step (column tiles, the particular solved beside)
+        nct = -(-(2 * (prob.sub_nx + prob.sub_ny) // prob.seg) // 16)
+        dom = "k_local_setup_twist<%d, %d, true>" % (prob.sub_nx, nct if nct <= 2 else 0)
     roof = {"kernel": dom, "bound": bound, "achieved": achieved / scale,
             "peak": peak / scale, "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic() if (dom == "k_local_setup" and fp64_best) else None,
+            "traffic": measured_traffic() if (dom.startswith("k_local_setup") and fp64_best) else None,
             "avg_ms": t_k,
             "algorithmic": amount,
             "algorithmic_unit": "flop" if bound == "alu" else "byte"}

@@ -160,6 +160,16 @@ int rmrcm_sync(rmrcm_ctx* ctx);
 int rmrcm_step(rmrcm_ctx* ctx, const double* perm, const double* source, const double* bc_value,
                double* pressure, double* flux);
 
+/* enabled = 0: rmrcm_step runs the same single chain of kernels as its graph
+ * (for an FP64 context with device arrays), enqueued launch by launch, and
+ * the phase timers of rmrcm_get_stats record it (setup: beta, the local
+ * setup with the particular problem, the merges with the particular column;
+ * solve: the top's particular column, the downward pass, the
+ * reconstruction).  enabled = 1 (the default): the captured graph.  For
+ * timing and testing; results are the same either way.
+ * Errors: EINVAL (ctx NULL). */
+int rmrcm_set_step_graph(rmrcm_ctx* ctx, int enabled);
+
 /* Solve for one right-hand side: the particular local solutions (source
  * and outer boundary data, additive split of Section 2.1), their columns
  * through the merges, the top interface solve, the downward propagation of

@@ -529,21 +529,34 @@ int enqueue_solve(rmrcm_ctx* c) {
 // c->bcv point at the step's inputs; the permeability check also copies the
 // permeability to kcopy (the library's own copy, for later calls).
 int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
+    // phase timers outside a graph: setup (beta, local, merges with the
+    // particular column), then the top's particular column, the downward
+    // pass and the reconstruction (no inputs to upload, no separate local
+    // particular solves)
+    TRY(mark(c, 0));
     HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
     HIP_TRY(rmrcm::launch_check_perm(c, kcopy));
     HIP_TRY(rmrcm::launch_beta(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_compat_check(c));
+    TRY(mark(c, 1));
     if (rmrcm::local_setup_solves_particular(c, false)) {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1, 1, 1));
     } else {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
         HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
     }
+    TRY(mark(c, 2));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d, true));
+    TRY(mark(c, 3));
+    for (int i = 4; i <= 6; ++i) TRY(mark(c, i));
     if (c->D > 0) HIP_TRY(rmrcm::launch_merge_particular(c, 0));   // the top's particular column
+    TRY(mark(c, 7));
     for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    TRY(mark(c, 8));
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
+    TRY(mark(c, 9));
+    TRY(mark(c, 10));
     return RMRCM_OK;
 }
 
@@ -1322,6 +1335,12 @@ void rmrcm_batch_destroy(rmrcm_batch* b) {
 // the context's stream, the particular chain on the auxiliary stream forked
 // at the start, the outputs written in place.  The graph is captured again
 // when a pointer differs from those of the last capture.
+int rmrcm_set_step_graph(rmrcm_ctx* c, int enabled) {
+    if (!c) return RMRCM_EINVAL;
+    c->step_graph = enabled != 0;
+    return RMRCM_OK;
+}
+
 int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const double* bc_value,
                double* pressure, double* flux) {
     if (!c || !perm || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
@@ -1332,45 +1351,63 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
         TRY(rmrcm_refactor(c, perm));
         return rmrcm_solve(c, source, bc_value, pressure, flux);
     }
-    const void* key[5] = {perm, source, bc_value, pressure, flux};
-    bool same = c->gstep != nullptr;
-    for (int i = 0; i < 5 && same; ++i) same = key[i] == c->gstep_key[i];
-    if (!same) {
-        if (c->gstep) {
-            HIP_TRY(hipStreamSynchronize(c->stream));
-            (void)hipGraphExecDestroy(c->gstep);
-            c->gstep = nullptr;
-        }
-        double* po = c->pout;
-        double* fo = c->fout;
-        double* ko = c->K;
-        double* qo = c->q;
-        double* bo = c->bcv;
-        c->pout = pressure;                 // the reconstruction writes the caller's arrays
-        c->fout = flux;
-        const int r = capture(
-            c, c->stream,
-            [&](rmrcm_ctx* cc) -> int {
-                // the kernels read the caller's permeability, source and
-                // boundary data; the library's copy of the permeability (for
-                // later calls) is written by the permeability check
-                const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
-                cc->K = const_cast<double*>(perm);
-                cc->bcv = const_cast<double*>(bc_value);
-                if (source) cc->q = const_cast<double*>(source);
-                else HIP_TRY(rmrcm::launch_fill_f64(cc, cc->q, ncell, 0.0));
-                return enqueue_step_fused(cc, ko);
-            },
-            &c->gstep);
+    // the step's inputs and outputs in place of the context's own buffers
+    double* po = c->pout;
+    double* fo = c->fout;
+    double* ko = c->K;
+    double* qo = c->q;
+    double* bo = c->bcv;
+    auto point = [&](rmrcm_ctx* cc) -> int {
+        // the kernels read the caller's permeability, source and boundary
+        // data; the library's copy of the permeability (for later calls) is
+        // written by the permeability check
+        const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
+        cc->pout = pressure;
+        cc->fout = flux;
+        cc->K = const_cast<double*>(perm);
+        cc->bcv = const_cast<double*>(bc_value);
+        if (source) cc->q = const_cast<double*>(source);
+        else HIP_TRY(rmrcm::launch_fill_f64(cc, cc->q, ncell, 0.0));
+        return RMRCM_OK;
+    };
+    auto restore = [&]() {
         c->pout = po;
         c->fout = fo;
         c->K = ko;
         c->q = qo;
         c->bcv = bo;
-        if (r != RMRCM_OK) return r;
-        for (int i = 0; i < 5; ++i) c->gstep_key[i] = key[i];
+    };
+    if (!c->step_graph) {
+        int r = point(c);
+        if (r == RMRCM_OK) r = enqueue_step_fused(c, ko);
+        restore();
+        TRY(r);
+        c->setup_recorded = true;
+        c->solve_recorded = true;
+        c->solve_overlapped = false;
+    } else {
+        const void* key[5] = {perm, source, bc_value, pressure, flux};
+        bool same = c->gstep != nullptr;
+        for (int i = 0; i < 5 && same; ++i) same = key[i] == c->gstep_key[i];
+        if (!same) {
+            if (c->gstep) {
+                HIP_TRY(hipStreamSynchronize(c->stream));
+                (void)hipGraphExecDestroy(c->gstep);
+                c->gstep = nullptr;
+            }
+            const int r = capture(
+                c, c->stream,
+                [&](rmrcm_ctx* cc) -> int {
+                    TRY(point(cc));
+                    return enqueue_step_fused(cc, ko);
+                },
+                &c->gstep);
+            restore();
+            if (r != RMRCM_OK) return r;
+            for (int i = 0; i < 5; ++i) c->gstep_key[i] = key[i];
+        }
+        HIP_TRY(hipGraphLaunch(c->gstep, c->stream));
     }
-    HIP_TRY(hipGraphLaunch(c->gstep, c->stream));
     HIP_TRY(hipEventRecord(c->ev_done, c->stream));
     c->done_recorded = true;
     c->lev_recorded = false;                // a later solve runs its particular chain in order

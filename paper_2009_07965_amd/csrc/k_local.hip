@@ -1016,21 +1016,20 @@ __device__ __forceinline__ void part_product(const typename Mfma<double>::v4 (&p
 // 16 k + l / 16 + 4 v, column 16 r + l % 16) is the A operand of row tile r
 // and k-slices 4 k .. 4 k + 3.
 //
-// With part = 1 the particular problem (source qsrc, outer boundary data
-// bcv) is solved beside the basis: a single column, so its products are
+// With PART (and basis) the particular problem (source qsrc, outer boundary
+// data bcv) is solved beside the basis: a single column, so its products are
 // matrix-vector products on the vector units (each lane sums its share of
 // a row of P_j from the registers that hold P_j, and the four partial sums
 // of a row are added across lanes), with its right-hand side as a vector in
 // LDS.  Its solution goes to pbar and, with do_traces, its traces to column
 // ld - 1 of T.
-template <int BX, int NCT>
+template <int BX, int NCT, bool PART>
 __global__ __launch_bounds__(128, 2) void k_local_setup_twist(
     Geo g, const double* __restrict__ K, const int8_t* __restrict__ bct,
     const double* __restrict__ beta, const int* __restrict__ slotseg, int R,
     double* __restrict__ Pstore, double* __restrict__ Psi, double* __restrict__ T, int ld,
     int* __restrict__ flags, const int* __restrict__ mask, int want, int do_traces, int basis,
-    const double* __restrict__ qsrc, const double* __restrict__ bcv, double* __restrict__ pbar,
-    int part) {
+    const double* __restrict__ qsrc, const double* __restrict__ bcv, double* __restrict__ pbar) {
     static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
     typedef double S;
     typedef Mfma<S> M;
@@ -1048,7 +1047,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_twist(
     const int NC = basis ? R : 0;           // basis columns of the sweeps
     const int RP = (NC + 15) & ~15;         // padded to whole tiles
     const int nct = NCT > 0 ? NCT : RP / 16;
-    part = basis ? part : 0;
+    constexpr int part = PART ? 1 : 0;
     const int m = BY / 2;                   // the row where the eliminations meet
     char* cur = smem;
     S* LTa = carve<S>(cur, 2 * BX * LT);    // per wave: L^{-1} rows, multipliers, Schur term
@@ -2113,13 +2112,20 @@ static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kern, dim3(nsub), dim3(128), lds, c->stream, c->geo, c->K, c->bct,
                                c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask, want,
-                               do_traces, basis, c->q, c->bcv, c->pbar, part);
+                               do_traces, basis, c->q, c->bcv, c->pbar);
             return hipGetLastError();
         };
+        if (part && basis) {
+            switch (RP / 16) {
+                case 1: return go(k_local_setup_twist<BX, 1, true>);
+                case 2: return go(k_local_setup_twist<BX, 2, true>);
+                default: return go(k_local_setup_twist<BX, 0, true>);
+            }
+        }
         switch (RP / 16) {
-            case 1: return go(k_local_setup_twist<BX, 1>);
-            case 2: return go(k_local_setup_twist<BX, 2>);
-            default: return go(k_local_setup_twist<BX, 0>);
+            case 1: return go(k_local_setup_twist<BX, 1, false>);
+            case 2: return go(k_local_setup_twist<BX, 2, false>);
+            default: return go(k_local_setup_twist<BX, 0, false>);
         }
     } else if constexpr (BX >= 16) {
         const Level& L = c->levels[c->D];

@@ -71,6 +71,7 @@ struct rmrcm_ctx {
     bool setup_recorded = false;
     bool solve_recorded = false;
     bool capturing = false;       // enqueueing into a graph capture: no events, no host sync
+    bool step_graph = true;       // rmrcm_step replays a captured graph (FP64, device arrays)
     hipGraphExec_t gstep = nullptr;            // rmrcm_step graph (FP64 contexts)
     const void* gstep_key[5] = {};             // the pointers it was captured with
     int ct_tune[32] = {};         // per depth: column tile of the merge apply (0 = default)

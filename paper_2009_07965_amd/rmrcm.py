@@ -46,6 +46,7 @@ class rmrcm_params(ctypes.Structure):
 
 EXPORTS = [
     "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve", "rmrcm_step",
+    "rmrcm_set_step_graph",
     "rmrcm_get_interface",
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
     "rmrcm_strerror", "rmrcm_autotune", "rmrcm_batch_create", "rmrcm_batch_refactor",
@@ -79,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_solve.restype = ctypes.c_int
     lib.rmrcm_step.argtypes = [vp, dp, dp, dp, dp, dp]
     lib.rmrcm_step.restype = ctypes.c_int
+    lib.rmrcm_set_step_graph.argtypes = [vp, ctypes.c_int]
+    lib.rmrcm_set_step_graph.restype = ctypes.c_int
     lib.rmrcm_get_interface.argtypes = [vp, dp, dp]
     lib.rmrcm_get_interface.restype = ctypes.c_int
     lib.rmrcm_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -214,6 +217,10 @@ def rmrcm_counts(ctx):
     a, b = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().rmrcm_counts(ctx, ctypes.byref(a), ctypes.byref(b)), "rmrcm_counts")
     return a.value, b.value
+
+
+def rmrcm_set_step_graph(ctx, enabled):
+    _check(lib().rmrcm_set_step_graph(ctx, 1 if enabled else 0), "rmrcm_set_step_graph")
 
 
 def rmrcm_set_stream(ctx, stream_handle):
@@ -470,6 +477,11 @@ class Solver:
 
     def set_stream(self, handle):
         rmrcm_set_stream(self.ctx, handle)
+
+    def set_step_graph(self, enabled):
+        """step() as a replayed graph (True, the default) or launch by launch
+        with the phase timers recording it (False); same results."""
+        rmrcm_set_step_graph(self.ctx, enabled)
 
     def autotune(self):
         rmrcm_autotune(self.ctx)

@@ -7,8 +7,9 @@ rmrcm_solve runs it as a chain of its own: the two differ only in the order
 of the particular sweeps' sums, so they are compared at STEP_TOL (rounding
 of the sweeps, 1e-16, times the growth through the hierarchy), and both
 with the oracle at the FP64 bar.  Replays with new permeability and sources
-at the same pointers, new output arrays (a new capture, bit for bit), host
-arrays (the eager path, bit for bit), subdomains 8, 16 and 32 cells wide
+at the same pointers, new output arrays (a new capture, bit for bit), the
+same chain without a graph (bit for bit), host arrays (the eager path, bit
+for bit), subdomains 8, 16 and 32 cells wide
 (8: the particular solve follows the local setup in the same chain) and an
 incompatible all-Neumann source (EINVAL at sync).
 """
@@ -93,6 +94,38 @@ def test_step_equals_refactor_and_solve(env, n, b, seg):
         # an ordinary solve after steps (eager path, same context)
         p3, F3 = S.solve(probs[-1].q, probs[-1].bc_value)
         assert rel_l2(p3, pd.cpu().numpy()) <= STEP_TOL and rel_l2(F3, fd.cpu().numpy()) <= STEP_TOL
+    finally:
+        S.close()
+
+
+@pytest.mark.parametrize("n,b,seg", [(256, 32, 8), (64, 8, 2)])
+def test_step_without_graph_equals_graph(env, n, b, seg):
+    """rmrcm_set_step_graph(0): the same chain launch by launch, bit for bit
+    the graph's results, with the phase timers recording it."""
+    L, torch = env
+    pr = make_problem(n, b=b, seg=seg, log_var=3.0, lam=0.08, seed=61, source=True)
+    S = L.Solver.from_problem(pr)
+    stream = torch.cuda.Stream()
+    try:
+        S.set_stream(stream.cuda_stream)
+        K, q, bv, pd, fd = dev_arrays(torch, pr)
+        say("[gpu] step graph vs launch by launch, n %d, b %d" % (n, b))
+        S.step(K, q, bv, pd, fd)
+        S.sync()
+        pg, Fg = pd.clone(), fd.clone()
+        S.set_step_graph(False)
+        pd.zero_()
+        fd.zero_()
+        S.step(K, q, bv, pd, fd)
+        S.sync()
+        assert torch.equal(pd, pg) and torch.equal(fd, Fg)
+        st = S.stats()
+        assert st["setup_ms"]["local"] > 0 and st["setup_ms"]["merge"] > 0
+        assert st["solve_ms"]["down"] > 0 and st["solve_ms"]["reconstruct"] > 0
+        S.set_step_graph(True)
+        S.step(K, q, bv, pd, fd)
+        S.sync()
+        assert torch.equal(pd, pg) and torch.equal(fd, Fg)
     finally:
         S.close()
 
