@@ -820,6 +820,86 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
     }
 }
 
+// The particular column alone (the top's, where one merge is one workgroup)
+// as matrix-vector products on the vector units: the same four products as
+// k_qd_apply_mfma, t = D^{-1} (r2 - r1), u = r1 + r2 - B t, s = S^{-1} u,
+// d = t - E s.  Row i of a g x g block is summed by 8 consecutive threads,
+// thread c8 taking entries c8, c8 + 8, ... (each load reads runs of 8
+// consecutive entries), and the partial sums added across those lanes; the
+// next block's entries are loaded while the current product is reduced.
+template <int GT>
+__device__ __forceinline__ void qd_vec_load(const double* A, int g, int i, int c8, double (&r)[GT / 8]) {
+    constexpr int CW = GT / 8;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) {
+        const int j = c8 + 8 * q;
+        r[q] = (i < g && j < g) ? A[(size_t)i * g + j] : 0.0;
+    }
+}
+template <int GT>
+__device__ __forceinline__ double qd_vec_dot(const double (&r)[GT / 8], const double* x, int c8) {
+    constexpr int CW = GT / 8;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < CW; ++q) s = fma(r[q], x[c8 + 8 * q], s);
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    s += __shfl_xor(s, 4, 64);
+    return s;
+}
+
+template <int GT>
+__global__ __launch_bounds__(8 * GT) void k_qd_apply_vec(MergeArgs a, int col) {
+    __shared__ double rs[GT], rd[GT], tt[GT], uu[GT];
+    const int node = blockIdx.x, g = a.g;
+    const int tid = threadIdx.x, i = tid >> 3, c8 = tid & 7;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const size_t gg = (size_t)g * g;
+    const double* Dg = a.M + (size_t)node * 4 * gg;
+    const double* Eg = Dg + gg;
+    const double* Sg = Eg + gg;
+    const double* Bg = Sg + gg;
+    double ra[GT / 8], rb[GT / 8];
+    qd_vec_load<GT>(Dg, g, i, c8, ra);                 // in flight during the gathers
+    qd_vec_load<GT>(Bg, g, i, c8, rb);
+    if (tid < GT) {
+        double v1 = 0.0, v2 = 0.0;
+        if (tid < g) {
+            const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+            const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+            if (col == a.nslot) {
+                v1 = T1[(size_t)a.gmap[tid] * a.cld + a.cld - 1];
+                v2 = T2[(size_t)a.gmap[g + tid] * a.cld + a.cld - 1];
+            } else {
+                const int pm = a.pmap[col], off = pm & 0xffffff;
+                if ((pm >> 24) == 0) v1 = T1[(size_t)a.gmap[tid] * a.cld + off];
+                else v2 = T2[(size_t)a.gmap[g + tid] * a.cld + off];
+            }
+        }
+        rs[tid] = v1 + v2;
+        rd[tid] = v2 - v1;
+    }
+    __syncthreads();
+    const double t = qd_vec_dot<GT>(ra, rd, c8);      // t = D^{-1} (r2 - r1)
+    if (c8 == 0) tt[i] = t;
+    qd_vec_load<GT>(Sg, g, i, c8, ra);
+    __syncthreads();
+    const double u = rs[i] - qd_vec_dot<GT>(rb, tt, c8);   // u = r1 + r2 - B t
+    if (c8 == 0) uu[i] = u;
+    qd_vec_load<GT>(Eg, g, i, c8, rb);
+    __syncthreads();
+    const double sv = qd_vec_dot<GT>(ra, uu, c8);     // s = S^{-1} u
+    if (c8 == 0) rs[i] = sv;
+    __syncthreads();
+    const double d = tt[i] - qd_vec_dot<GT>(rb, rs, c8);   // d = t - E s
+    if (c8 == 0 && i < g) {
+        double* X = a.X + (size_t)node * a.xi * a.ld;
+        X[(size_t)i * a.ld + col] = -(sv - d);
+        X[(size_t)(g + i) * a.ld + col] = -(sv + d);
+    }
+}
+
 // Parent traces on the matrix cores: T_p[o][col] = direct(o, col)
 // + sum_i A_1[o][i] X_1[i][col] + sum_i A_2[o][i] X_2[i][col], with A_k[o][i]
 // = T_k[o, gamma_k(i)] on the rows o that child k owns and zero on the
@@ -1063,6 +1143,15 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d, bool part) {
 hipError_t launch_merge_particular(rmrcm_ctx* c, int d) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
+    if (d == 0) {
+        // the top: one merge, one column
+        switch (qd_tier(a.g)) {
+            case 16: hipLaunchKernelGGL(k_qd_apply_vec<16>, dim3(a.nnodes), dim3(128), 0, c->stream, a, a.nslot); return hipGetLastError();
+            case 32: hipLaunchKernelGGL(k_qd_apply_vec<32>, dim3(a.nnodes), dim3(256), 0, c->stream, a, a.nslot); return hipGetLastError();
+            case 64: hipLaunchKernelGGL(k_qd_apply_vec<64>, dim3(a.nnodes), dim3(512), 0, c->stream, a, a.nslot); return hipGetLastError();
+            case 128: hipLaunchKernelGGL(k_qd_apply_vec<128>, dim3(a.nnodes), dim3(1024), 0, c->stream, a, a.nslot); return hipGetLastError();
+        }
+    }
     if (qd_tier(a.g)) return qd_columns_any(c, a, a.nslot, 1, d != 0, 1);
     hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi + 255) / 256), dim3(256), 0, c->stream, a,
                        a.nslot, 1);
