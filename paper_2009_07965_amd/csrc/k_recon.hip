@@ -15,8 +15,10 @@ __device__ inline double kc(const double* __restrict__ K, const Geo& g, int gi, 
     return K[(size_t)gj * g.nx + gi];
 }
 
+// One thread per cell (up to 1024 per workgroup); the basis sum is unrolled
+// so that the loads of a cell's coefficients are in flight together.
 template <int BX>
-__global__ __launch_bounds__(256) void k_reconstruct(Geo g, const double* __restrict__ K,
+__global__ __launch_bounds__(1024) void k_reconstruct(Geo g, const double* __restrict__ K,
                                                      const int8_t* __restrict__ bct,
                                                      const double* __restrict__ bcv,
                                                      const double* __restrict__ beta,
@@ -43,6 +45,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(Geo g, const double* __rest
     const double* pb = pbar + (size_t)sub * n;
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
         double s = pb[c];
+#pragma unroll 16
         for (int a = 0; a < R; ++a) s += Ps[(size_t)a * n + c] * gs[a];
         ps[c] = s;
         const int i = c % BX, j = c / BX;
@@ -215,7 +218,8 @@ static hipError_t recon_bx(rmrcm_ctx* c) {
     hipError_t e = hipFuncSetAttribute((const void*)k_reconstruct<BX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reconstruct<BX>, dim3(nsub), dim3(256), lds, c->stream, c->geo, c->K,
+    const int nt = BX * c->geo.by < 1024 ? ((BX * c->geo.by + 63) / 64) * 64 : 1024;
+    hipLaunchKernelGGL(k_reconstruct<BX>, dim3(nsub), dim3(nt), lds, c->stream, c->geo, c->K,
                        c->bct, c->bcv, c->beta, L.slotseg, L.nslot, c->Psi, c->pbar, c->glo,
                        c->ghi, c->pout, c->fout);
     return hipGetLastError();
