@@ -533,8 +533,10 @@ __device__ inline void qd_panel_put(double* pn, const double (&r)[4]) {
     }
 }
 
+// phase 0: the whole factorisation; 1: up to D^{-1} (B and N stored);
+// 2: S^{-1} from S in Sg (the products in between by k_qd_es_mfma).
 template <int GT>
-__global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
+__global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int phase) {
     typedef QdM<GT> Q;
     constexpr int T = Q::T, CPL = Q::CPL;
     __shared__ double cp[2 * GT * CPL];
@@ -566,10 +568,20 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
     double* lt = lts + 2 * w * 16 * Q::LTL;
     double* ls = lt + 16 * Q::LTL;
     const int j = 16 * w + li;                   // the column this lane holds
+    v4d m[T];
+    if (phase == 2) {
+        // S (identity outside g x g)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + lk + 4 * v;
+                m[I][v] = (i < g && j < g) ? Sg[(size_t)i * g + j] : (i == j ? 1.0 : 0.0);
+            }
+    } else {
     // the gamma blocks of both children: B and N to global memory, D in
     // registers (four tiles' loads in flight at a time)
     constexpr int CI = T;
-    v4d m[T];
 #pragma unroll
     for (int I0 = 0; I0 < T; I0 += CI) {
         double t1[CI][4], t2[CI][4];
@@ -599,6 +611,10 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
     }
     qd_gj_mfma<GT>(m, cp, pt, lt, ls, &bad);              // D^{-1}
     qd_store<GT>(m, g, Dg, false);
+    if (phase == 1) {
+        if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
+        return;
+    }
     __syncthreads();                                       // D^{-1}, B, N visible to the workgroup
     // E = D^{-1} B (block column w): block column K of D^{-1} staged in LDS
     // (the next one in flight meanwhile), B_KJ from global memory
@@ -667,6 +683,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
 #pragma unroll
         for (int I = 0; I < T; ++I) m[I] = acc[I];
     }
+    }
     if (a.pin) {
         // all-Neumann top: s of the last gamma segment is pinned
 #pragma unroll
@@ -680,6 +697,63 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a) {
     qd_gj_mfma<GT>(m, cp, pt, lt, ls, &bad);              // S^{-1}
     qd_store<GT>(m, g, Sg, a.pin);
     if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
+}
+
+// The two products between the inversions of k_qd_factor_mfma, E = D^{-1} B
+// and S = N - B E, spread over workgroups: block column w = blockIdx.y of
+// one merge per workgroup (S's block column needs only E's), wave r forming
+// row tile r of E's block column, shared in LDS, then of S's.  The matrix
+// core sequences are those of the single-workgroup form, so the numbers are
+// the same; for merges that are few and large (one workgroup per merge would
+// leave the chip idle).
+template <int GT>
+__global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
+    constexpr int T = QdM<GT>::T;
+    __shared__ double Es[GT * 17];
+    const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int node = blockIdx.x, w = blockIdx.y, g = a.g;
+    const size_t gg = (size_t)g * g;
+    const double* Dg = a.M + (size_t)node * 4 * gg;
+    double* Eg = a.M + (size_t)node * 4 * gg + gg;
+    double* Sg = Eg + gg;
+    const double* Bg = Sg + gg;
+    const int j = 16 * w + li, ia = 16 * r + li;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int K = 0; K < T; ++K)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int ka = 16 * K + 4 * s + lk;
+            const double av = (ia < g && ka < g) ? Dg[(size_t)ia * g + ka] : 0.0;
+            const double bv = (ka < g && j < g) ? Bg[(size_t)ka * g + j] : 0.0;
+            acc = mfma_f64(av, bv, acc);
+        }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 16 * r + lk + 4 * v;
+        Es[i * 17 + li] = acc[v];
+        if (i < g && j < g) Eg[(size_t)i * g + j] = acc[v];
+    }
+    __syncthreads();
+    v4d sc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 16 * r + lk + 4 * v;
+        sc[v] = (i < g && j < g) ? Sg[(size_t)i * g + j] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int K = 0; K < T; ++K)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int ka = 16 * K + 4 * s + lk;
+            const double bv = (ia < g && ka < g) ? Bg[(size_t)ia * g + ka] : 0.0;
+            sc = mfma_f64(-bv, Es[ka * 17 + li], sc);
+        }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = 16 * r + lk + 4 * v;
+        if (i < g && j < g) Sg[(size_t)i * g + j] = sc[v];
+    }
 }
 
 // Gamma coefficients of columns [col0, col0 + ncol): X = -M^{-1} R through
@@ -1075,7 +1149,15 @@ static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int nco
 
 template <int GT>
 static hipError_t qd_factor_mfma(rmrcm_ctx* c, const MergeArgs& a) {
-    hipLaunchKernelGGL(k_qd_factor_mfma<GT>, dim3(a.nnodes), dim3(QdM<GT>::NT), 0, c->stream, a);
+    if (GT == 128) {
+        // the largest tier (the top merges): the products between the two
+        // inversions on T workgroups per merge
+        hipLaunchKernelGGL(k_qd_factor_mfma<GT>, dim3(a.nnodes), dim3(QdM<GT>::NT), 0, c->stream, a, 1);
+        hipLaunchKernelGGL(k_qd_es_mfma<GT>, dim3(a.nnodes, QdM<GT>::T), dim3(QdM<GT>::NT), 0, c->stream, a);
+        hipLaunchKernelGGL(k_qd_factor_mfma<GT>, dim3(a.nnodes), dim3(QdM<GT>::NT), 0, c->stream, a, 2);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_qd_factor_mfma<GT>, dim3(a.nnodes), dim3(QdM<GT>::NT), 0, c->stream, a, 0);
     return hipGetLastError();
 }
 
