@@ -718,16 +718,23 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
     double* Sg = Eg + gg;
     const double* Bg = Sg + gg;
     const int j = 16 * w + li, ia = 16 * r + li;
+    // every operand of a product is loaded before the product runs (the
+    // loads in flight together), B's row tile for S before the barrier
+    double av[4 * T], bv[4 * T], b2[4 * T];
+#pragma unroll
+    for (int q = 0; q < 4 * T; ++q) {
+        const int ka = 4 * q + lk;          // 16 K + 4 s + lk with q = 4 K + s
+        av[q] = (ia < g && ka < g) ? Dg[(size_t)ia * g + ka] : 0.0;
+        bv[q] = (ka < g && j < g) ? Bg[(size_t)ka * g + j] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4 * T; ++q) {
+        const int ka = 4 * q + lk;
+        b2[q] = (ia < g && ka < g) ? Bg[(size_t)ia * g + ka] : 0.0;
+    }
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int K = 0; K < T; ++K)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int ka = 16 * K + 4 * s + lk;
-            const double av = (ia < g && ka < g) ? Dg[(size_t)ia * g + ka] : 0.0;
-            const double bv = (ka < g && j < g) ? Bg[(size_t)ka * g + j] : 0.0;
-            acc = mfma_f64(av, bv, acc);
-        }
+    for (int q = 0; q < 4 * T; ++q) acc = mfma_f64(av[q], bv[q], acc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 16 * r + lk + 4 * v;
@@ -742,13 +749,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
         sc[v] = (i < g && j < g) ? Sg[(size_t)i * g + j] : (i == j ? 1.0 : 0.0);
     }
 #pragma unroll
-    for (int K = 0; K < T; ++K)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int ka = 16 * K + 4 * s + lk;
-            const double bv = (ia < g && ka < g) ? Bg[(size_t)ia * g + ka] : 0.0;
-            sc = mfma_f64(-bv, Es[ka * 17 + li], sc);
-        }
+    for (int q = 0; q < 4 * T; ++q) sc = mfma_f64(-b2[q], Es[(4 * q + lk) * 17 + li], sc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 16 * r + lk + 4 * v;
