@@ -229,6 +229,8 @@ int alloc_levels(rmrcm_ctx* c) {
             TRY(dalloc(c, &L.M, (size_t)L.nnodes * L.xi * L.xi));
             TRY(dalloc(c, &L.piv, (size_t)L.nnodes * L.xi));
             TRY(dalloc(c, &L.X, (size_t)L.nnodes * L.xi * L.ld));
+            const size_t wk = rmrcm::merge_work_doubles(L);
+            if (wk) TRY(dalloc(c, &L.work, (size_t)L.nnodes * wk));
         }
     }
     // the root level keeps a trace buffer only when it is also the leaf level
@@ -248,6 +250,7 @@ void free_all(rmrcm_ctx* c) {
         f(L.M);
         f(L.piv);
         f(L.X);
+        f(L.work);
     }
     f(c->K);
     f(c->bct);

@@ -43,6 +43,7 @@ struct MergeArgs {
     const double* seglen;
     int* flags;
     int pin;                    // 1 at the root of an all-Neumann problem
+    double* work;               // scratch of merges with g > 128 (see kBigWork)
 };
 
 // Element-wise copy t -> st(t, ld(t)) for t < n over the workgroup, in
@@ -1080,6 +1081,296 @@ __global__ __launch_bounds__(256) void k_down(DownArgs a) {
     }
 }
 
+// ---------------------------------------------------------------- g in (128, 256]
+// Merges whose gamma blocks exceed the register-resident inversion (one
+// workgroup holds at most 128 x 128 in registers): the same quasi-definite
+// elimination with the blocks in global memory.  D^{-1} and S^{-1} by a 2 x 2
+// split, [[A, C^T], [C, F]] with A of order 128: A^{-1} in registers (the
+// blocked Gauss-Jordan above), Y = A^{-1} C^T, the Schur block F - C Y and its
+// inverse the same way, then W = Y F'^{-1} and the four blocks of the inverse
+// (A^{-1} + W Y^T, -W, -W^T, F'^{-1}); E = D^{-1} B and S = N - B E, and the
+// four products of the column apply, as matrix products on the FP64 matrix
+// cores (k_gemm_f64), batched over the level's merges.
+
+// C = beta C + alpha op(A) op(B) (row-major; ta / tb: the operand is stored
+// transposed), one 64 x 64 tile of C per workgroup, batch blockIdx.z with
+// the given strides; four waves, each a 32 x 32 sub-tile (2 x 2 matrix-core
+// tiles), K in steps of 16 through LDS.
+struct GemmArgs {
+    int m, n, k, ta, tb;
+    const double* A;
+    long long lda, sa;
+    const double* B;
+    long long ldb, sb;
+    double* C;
+    long long ldc, sc;
+    double alpha, beta;
+};
+
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
+    __shared__ double As[64 * 17];
+    __shared__ double Bs[16 * 65];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64, z = blockIdx.z;
+    const double* A = g.A + (size_t)z * g.sa;
+    const double* B = g.B + (size_t)z * g.sb;
+    double* C = g.C + (size_t)z * g.sc;
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < g.k; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e >> 4, kk = e & 15, gr = bm + r, gk = k0 + kk;
+            As[r * 17 + kk] = (gr < g.m && gk < g.k)
+                                  ? (g.ta ? A[(size_t)gk * g.lda + gr] : A[(size_t)gr * g.lda + gk])
+                                  : 0.0;
+            const int kb = e >> 6, cb = e & 63, gkb = k0 + kb, gc = bn + cb;
+            Bs[kb * 65 + cb] = (gkb < g.k && gc < g.n)
+                                   ? (g.tb ? B[(size_t)gc * g.ldb + gkb] : B[(size_t)gkb * g.ldb + gc])
+                                   : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = mfma_f64(As[(wr + 16 * a + li) * 17 + 4 * s4 + lk],
+                                         Bs[(4 * s4 + lk) * 65 + wc + 16 * b + li], acc[a][b]);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = bm + wr + 16 * a + lk + 4 * v, cc = bn + wc + 16 * b + li;
+                if (r < g.m && cc < g.n) {
+                    double* cp = C + (size_t)r * g.ldc + cc;
+                    *cp = g.beta == 0.0 ? g.alpha * acc[a][b][v] : g.beta * *cp + g.alpha * acc[a][b][v];
+                }
+            }
+}
+
+static hipError_t gemm(rmrcm_ctx* c, int batch, int m, int n, int k, int ta, const double* A,
+                       long long lda, long long sa, int tb, const double* B, long long ldb, long long sb,
+                       double* C, long long ldc, long long sc, double alpha, double beta) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    GemmArgs g{m, n, k, ta, tb, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta};
+    hipLaunchKernelGGL(k_gemm_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
+    return hipGetLastError();
+}
+
+// In-place inverse of the n x n block (n <= 128) at X (row stride ld, batch
+// stride sx), blocked Gauss-Jordan in registers as in k_qd_factor_mfma.
+__global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long long ld, long long sx,
+                                                                  int n, int* flags) {
+    typedef QdM<128> Q;
+    constexpr int T = Q::T;
+    __shared__ double cp[2 * 128 * Q::CPL];
+    __shared__ double lts[2 * T * 16 * Q::LTL];
+    __shared__ double pt[2 * 16 * 17];
+    __shared__ int bad;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    double* Xb = X + (size_t)blockIdx.x * sx;
+    if (tid == 0) bad = 0;
+    const int j = 16 * w + li;
+    v4d m[T];
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + lk + 4 * v;
+            m[I][v] = (i < n && j < n) ? Xb[(size_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+        }
+    __syncthreads();
+    double* lt = lts + 2 * w * 16 * Q::LTL;
+    qd_gj_mfma<128>(m, cp, pt, lt, lt + 16 * Q::LTL, &bad);
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * I + lk + 4 * v;
+            if (i < n && j < n) Xb[(size_t)i * ld + j] = m[I][v];
+        }
+    if (tid == 0 && bad) atomicOr(&flags[FLAG_MERGE_SINGULAR], 1);
+}
+
+// D, B and N of every merge of the level (one thread per entry; D to the D
+// block, N parked in the S block).
+__global__ __launch_bounds__(256) void k_qd_gather_big(MergeArgs a) {
+    const int node = blockIdx.y, g = a.g;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= g * g) return;
+    const int i = t / g, j = t % g;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    const int gi = a.gmap[i], gj = a.gmap[j];
+    const double t1 = T1[(size_t)gi * a.cld + gj];
+    const double t2 = T2[(size_t)a.gmap[g + i] * a.cld + a.gmap[g + j]];
+    const size_t gg = (size_t)g * g;
+    double* Dg = a.M + (size_t)node * 4 * gg;
+    double* Sg = Dg + 2 * gg;
+    double* Bg = Dg + 3 * gg;
+    const double nv = t1 + t2;
+    double dv = nv;
+    if (i == j) {
+        const int e = a.css[(size_t)c1 * a.cnslot + gi] >> 1;
+        dv = nv + 4.0 * (a.seglen[e] / (2.0 * a.beta[e]));
+    }
+    Bg[t] = t2 - t1;
+    Sg[t] = nv;
+    Dg[t] = dv;
+}
+
+// Blocks of the inverse from W (128 x r): X[0:128][128:] = -W and
+// X[128:][0:128] = -W^T; mode 1: the all-Neumann top's pinned row and column
+// of S set to the identity (before the inversion), mode 2: its pinned entry
+// stored as zero (after).
+__global__ __launch_bounds__(256) void k_qd_big_fix(double* X, long long ld, long long sx,
+                                                    const double* W, long long sw, int r, int mode,
+                                                    int g) {
+    double* Xb = X + (size_t)blockIdx.y * sx;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (mode == 0) {
+        if (t >= 128 * r) return;
+        const int i = t / r, q = t % r;
+        const double v = -W[(size_t)blockIdx.y * sw + t];
+        Xb[(size_t)i * ld + 128 + q] = v;
+        Xb[(size_t)(128 + q) * ld + i] = v;
+    } else if (mode == 1) {
+        if (t >= g) return;
+        Xb[(size_t)(g - 1) * ld + t] = t == g - 1 ? 1.0 : 0.0;
+        Xb[(size_t)t * ld + g - 1] = t == g - 1 ? 1.0 : 0.0;
+    } else if (t == 0) {
+        Xb[(size_t)(g - 1) * ld + g - 1] = 0.0;
+    }
+}
+
+// Symmetric inverse in place of the g x g block at X (128 < g <= 256) of
+// every merge; Y and W: 128 x (g - 128) scratch per merge (merge stride sy).
+static hipError_t qd_big_inverse(rmrcm_ctx* c, const MergeArgs& a, double* X, double* Y, double* W,
+                                 long long sy) {
+    const int g = a.g, r = g - 128, nb = a.nnodes;
+    const long long gg = (long long)g * g, sx = 4 * gg;
+    hipError_t e;
+    hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, (long long)g, sx, 128, a.flags);
+    // Y = A^{-1} C^T (C^T: the top right block)
+    if ((e = gemm(c, nb, 128, r, 128, 0, X, g, sx, 0, X + 128, g, sx, Y, r, sy, 1.0, 0.0))) return e;
+    // F <- F - C Y (C = rows 128.., columns ..128)
+    if ((e = gemm(c, nb, r, r, 128, 0, X + 128LL * g, g, sx, 0, Y, r, sy, X + 128LL * g + 128, g, sx, -1.0, 1.0))) return e;
+    hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X + 128LL * g + 128, (long long)g, sx, r, a.flags);
+    // W = Y F'^{-1};  A^{-1} <- A^{-1} + W Y^T
+    if ((e = gemm(c, nb, 128, r, r, 0, Y, r, sy, 0, X + 128LL * g + 128, g, sx, W, r, sy, 1.0, 0.0))) return e;
+    if ((e = gemm(c, nb, 128, 128, r, 0, W, r, sy, 1, Y, r, sy, X, g, sx, 1.0, 1.0))) return e;
+    hipLaunchKernelGGL(k_qd_big_fix, dim3((128 * r + 255) / 256, nb), dim3(256), 0, c->stream, X, (long long)g, sx,
+                       (const double*)W, sy, r, 0, g);
+    return hipGetLastError();
+}
+
+__host__ inline size_t big_work(int g, int nslot) {
+    return 2 * 128 * 128 + 3 * (size_t)g * (nslot + 1);
+}
+
+// Scratch per merge with g > 128 (merge stride big_work): Y and W of the
+// inverses, then three g x (nslot + 1) column blocks of the apply.
+static hipError_t qd_factor_big(rmrcm_ctx* c, const MergeArgs& a) {
+    const int g = a.g, nb = a.nnodes;
+    const long long gg = (long long)g * g, sx = 4 * gg, sw = (long long)big_work(g, a.nslot);
+    double* Y = a.work;
+    double* W = a.work + 128 * 128;
+    double* D = a.M;
+    double* E = a.M + gg;
+    double* S = a.M + 2 * gg;
+    double* B = a.M + 3 * gg;
+    hipLaunchKernelGGL(k_qd_gather_big, dim3((g * g + 255) / 256, nb), dim3(256), 0, c->stream, a);
+    hipError_t e;
+    if ((e = qd_big_inverse(c, a, D, Y, W, sw))) return e;
+    // E = D^{-1} B;  S = N - B E
+    if ((e = gemm(c, nb, g, g, g, 0, D, g, sx, 0, B, g, sx, E, g, sx, 1.0, 0.0))) return e;
+    if ((e = gemm(c, nb, g, g, g, 0, B, g, sx, 0, E, g, sx, S, g, sx, -1.0, 1.0))) return e;
+    if (a.pin)
+        hipLaunchKernelGGL(k_qd_big_fix, dim3((g + 255) / 256, nb), dim3(256), 0, c->stream, S, (long long)g, sx,
+                           (const double*)nullptr, 0LL, 0, 1, g);
+    if ((e = qd_big_inverse(c, a, S, Y, W, sw))) return e;
+    if (a.pin)
+        hipLaunchKernelGGL(k_qd_big_fix, dim3(1, nb), dim3(256), 0, c->stream, S, (long long)g, sx,
+                           (const double*)nullptr, 0LL, 0, 2, g);
+    return hipGetLastError();
+}
+
+// r1 + r2 and r2 - r1 of columns [col0, col0 + ncol) (row stride ncol), and
+// the coefficients X from s and d.
+__global__ __launch_bounds__(256) void k_qd_rhs_big(MergeArgs a, int col0, int ncol, double* RS,
+                                                    double* RD, long long sw) {
+    const int node = blockIdx.y, g = a.g;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= g * ncol) return;
+    const int i = t / ncol, cc = t % ncol, col = col0 + cc;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    double v1 = 0.0, v2 = 0.0;
+    if (col == a.nslot) {
+        v1 = T1[(size_t)a.gmap[i] * a.cld + a.cld - 1];
+        v2 = T2[(size_t)a.gmap[g + i] * a.cld + a.cld - 1];
+    } else {
+        const int pm = a.pmap[col], off = pm & 0xffffff;
+        if ((pm >> 24) == 0) v1 = T1[(size_t)a.gmap[i] * a.cld + off];
+        else v2 = T2[(size_t)a.gmap[g + i] * a.cld + off];
+    }
+    RS[(size_t)node * sw + t] = v1 + v2;
+    RD[(size_t)node * sw + t] = v2 - v1;
+}
+
+__global__ __launch_bounds__(256) void k_qd_x_big(MergeArgs a, int col0, int ncol, const double* Sv,
+                                                  const double* Dv, long long sw) {
+    const int node = blockIdx.y, g = a.g;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= g * ncol) return;
+    const int i = t / ncol, cc = t % ncol;
+    const double s = Sv[(size_t)node * sw + t], d = Dv[(size_t)node * sw + t];
+    double* X = a.X + (size_t)node * a.xi * a.ld;
+    X[(size_t)i * a.ld + col0 + cc] = -(s - d);
+    X[(size_t)(g + i) * a.ld + col0 + cc] = -(s + d);
+}
+
+static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
+    const int g = a.g, nb = a.nnodes;
+    const long long gg = (long long)g * g, sx = 4 * gg;
+    const size_t per = big_work(g, a.nslot);
+    if ((size_t)ncol > (size_t)a.nslot + 1) return hipErrorInvalidValue;
+    // per merge: RS, RD, TT of g x ncol each, after Y and W
+    double* RS = a.work + 2 * 128 * 128;
+    double* RD = RS + (size_t)g * (a.nslot + 1);
+    double* TT = RD + (size_t)g * (a.nslot + 1);
+    const long long sw = (long long)per;
+    const double* D = a.M;
+    const double* E = a.M + gg;
+    const double* S = a.M + 2 * gg;
+    const double* B = a.M + 3 * gg;
+    const dim3 grid((g * ncol + 255) / 256, nb);
+    hipLaunchKernelGGL(k_qd_rhs_big, grid, dim3(256), 0, c->stream, a, col0, ncol, RS, RD, sw);
+    hipError_t e;
+    if ((e = gemm(c, nb, g, ncol, g, 0, D, g, sx, 0, RD, ncol, sw, TT, ncol, sw, 1.0, 0.0))) return e;   // t
+    if ((e = gemm(c, nb, g, ncol, g, 0, B, g, sx, 0, TT, ncol, sw, RS, ncol, sw, -1.0, 1.0))) return e;  // u
+    if ((e = gemm(c, nb, g, ncol, g, 0, S, g, sx, 0, RS, ncol, sw, RD, ncol, sw, 1.0, 0.0))) return e;   // s
+    if ((e = gemm(c, nb, g, ncol, g, 0, E, g, sx, 0, RD, ncol, sw, TT, ncol, sw, -1.0, 1.0))) return e;  // d
+    hipLaunchKernelGGL(k_qd_x_big, grid, dim3(256), 0, c->stream, a, col0, ncol, (const double*)RD,
+                       (const double*)TT, sw);
+    return hipGetLastError();
+}
+
 static MergeArgs make_args(rmrcm_ctx* c, int d) {
     Level& P = c->levels[d];
     Level& C = c->levels[d + 1];
@@ -1105,6 +1396,7 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     a.seglen = c->seglen;
     a.flags = c->flags;
     a.pin = (d == 0 && !c->any_dirichlet) ? 1 : 0;
+    a.work = P.work;
     return a;
 }
 
@@ -1123,7 +1415,9 @@ static hipError_t solve_cols_generic(rmrcm_ctx* c, const MergeArgs& a, int col0,
 }
 
 // Size class of the pivot-free path (0: gamma too long, generic LU path).
-static int qd_tier(int g) { return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : 0; }
+static int qd_tier(int g) {
+    return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : g <= 256 ? 256 : 0;
+}
 
 // ct: columns per workgroup, 16 or 32 (0: 16).
 template <int GT>
@@ -1164,6 +1458,7 @@ static hipError_t qd_factor_mfma(rmrcm_ctx* c, const MergeArgs& a) {
 
 static hipError_t qd_factor_any(rmrcm_ctx* c, const MergeArgs& a) {
     switch (qd_tier(a.g)) {
+        case 256: return qd_factor_big(c, a);
         case 16: return qd_factor_mfma<16>(c, a);
         case 32: return qd_factor_mfma<32>(c, a);
         case 64: return qd_factor_mfma<64>(c, a);
@@ -1179,12 +1474,25 @@ static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int
         case 32: return qd_columns<32>(c, a, col0, ncol, trace, ct);
         case 64: return qd_columns<64>(c, a, col0, ncol, trace, ct);
         case 128: return qd_columns<128>(c, a, col0, ncol, trace, ct);
+        case 256: {
+            hipError_t e = qd_apply_big(c, a, col0, ncol);
+            if (e != hipSuccess || !trace) return e;
+            hipLaunchKernelGGL(k_qd_trace_mfma<256>, dim3(a.nnodes, (a.nslot + 63) / 64, (ncol + 15) / 16),
+                               dim3(256), 0, c->stream, a, col0, ncol);
+            return hipGetLastError();
+        }
     }
     return hipErrorInvalidValue;
 }
 
+size_t merge_work_doubles(const Level& L) {
+    return (L.g > 128 && L.g <= 256) ? big_work(L.g, L.nslot) : 0;
+}
+
 bool merge_apply_tunable(rmrcm_ctx* c, int d) {
-    return d > 0 && d < c->D && qd_tier(c->levels[d].g) != 0;
+    if (!(d > 0 && d < c->D)) return false;
+    const int t = qd_tier(c->levels[d].g);
+    return t != 0 && t != 256;
 }
 
 hipError_t launch_merge_apply(rmrcm_ctx* c, int d, int ct) {

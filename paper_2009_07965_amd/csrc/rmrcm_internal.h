@@ -53,6 +53,7 @@ struct Level {
     double* M = nullptr;       // [nnodes][xi][xi] LU factors (in place)
     int* piv = nullptr;        // [nnodes][xi]
     double* X = nullptr;       // [nnodes][xi][ld] coefficients of every column
+    double* work = nullptr;    // scratch of merges with 128 < g <= 256 (merge_work_doubles per node)
     std::vector<int> h_pmap, h_gmap, h_slotseg;
 };
 
@@ -144,6 +145,8 @@ hipError_t launch_max_resid(rmrcm_ctx* c, int part, double* out);
 // part: the particular column is eliminated with the basis columns (their
 // traces already hold it), as launch_merge_particular would below the top.
 hipError_t launch_merge_setup(rmrcm_ctx* c, int depth, bool part = false);
+// Scratch doubles per merge of a level (nonzero for 128 < g <= 256).
+size_t merge_work_doubles(const Level& L);
 hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
 hipError_t launch_reconstruct(rmrcm_ctx* c);

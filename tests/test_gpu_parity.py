@@ -9,7 +9,8 @@ Robin data divided by 2 beta).
 Sizes: the oracle finishes each case in seconds; cases span many
 subdomains, every supported subdomain width, rectangular grids and
 subdomains, segment lengths from one face to a whole side, the degenerate
-single-subdomain and two-subdomain decompositions, and the full 1024^2
+single-subdomain and two-subdomain decompositions, interfaces of 256 segments (the
+merges whose blocks exceed one workgroup's registers), and the full 1024^2
 workload (32^2 subdomains of 32^2 cells, 10 levels) in the launch
 configuration the benchmark times.
 """
@@ -78,6 +79,11 @@ CASES = {
     "all_neumann_fivespot_b32": lambda: make_problem(256, b=32, seg=8, bc="fivespot", log_var=3.0),
     "all_neumann_fivespot_big_root": lambda: make_problem(256, b=8, seg=2, bc="fivespot",
                                                           log_var=1.0, lam=0.1),
+    # 256 gamma segments at the two top levels: the merges with blocks in
+    # global memory (2 x 2 split inverses, matrix-product applies)
+    "gamma256": lambda: make_problem(256, b=8, seg=1, log_var=2.0, lam=0.1, source=True),
+    "gamma256_all_neumann": lambda: make_problem(256, b=8, seg=1, bc="fivespot", log_var=1.0,
+                                                 lam=0.1),
 }
 
 

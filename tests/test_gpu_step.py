@@ -98,7 +98,7 @@ def test_step_equals_refactor_and_solve(env, n, b, seg):
         S.close()
 
 
-@pytest.mark.parametrize("n,b,seg", [(256, 32, 8), (64, 8, 2)])
+@pytest.mark.parametrize("n,b,seg", [(256, 32, 8), (64, 8, 2), (256, 8, 1)])
 def test_step_without_graph_equals_graph(env, n, b, seg):
     """rmrcm_set_step_graph(0): the same chain launch by launch, bit for bit
     the graph's results, with the phase timers recording it."""
