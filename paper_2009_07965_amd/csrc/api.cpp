@@ -227,7 +227,6 @@ int alloc_levels(rmrcm_ctx* c) {
             HIP_TRY(hipMemcpyAsync(L.gmap, L.h_gmap.data(), L.h_gmap.size() * sizeof(int),
                                    hipMemcpyHostToDevice, c->stream));
             TRY(dalloc(c, &L.M, (size_t)L.nnodes * L.xi * L.xi));
-            TRY(dalloc(c, &L.piv, (size_t)L.nnodes * L.xi));
             TRY(dalloc(c, &L.X, (size_t)L.nnodes * L.xi * L.ld));
             const size_t wk = rmrcm::merge_work_doubles(L);
             if (wk) TRY(dalloc(c, &L.work, (size_t)L.nnodes * wk));
@@ -248,7 +247,6 @@ void free_all(rmrcm_ctx* c) {
         f(L.pmap);
         f(L.gmap);
         f(L.M);
-        f(L.piv);
         f(L.X);
         f(L.work);
     }

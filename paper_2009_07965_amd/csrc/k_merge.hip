@@ -20,8 +20,9 @@
 //     T_p[o, s] = T_k[o, s] (if s belongs to child k) + T_k[o, gamma] y_k[:, s].
 // M is factored once and kept with X for the downward pass (the Remark of
 // Section 3.2: coefficients are tracked back to the finest level instead of
-// storing coarse basis functions).  Merges with g <= 128 use the pivot-free
-// quasi-definite form below; longer interfaces an LU with partial pivoting.
+// storing coarse basis functions).  Every merge uses the pivot-free
+// quasi-definite form below: gamma blocks of up to 128 segments in
+// registers, longer ones in global memory.
 
 #include "rmrcm_internal.h"
 
@@ -35,8 +36,7 @@ struct MergeArgs {
     const int* css;             // child slot codes
     const int* pmap;            // [nslot]
     const int* gmap;            // [2][g]
-    double* M;                  // [nnodes][xi][xi]
-    int* piv;                   // [nnodes][xi]
+    double* M;                  // [nnodes][4 g^2]: D^{-1}, E, S^{-1}, B
     double* X;                  // [nnodes][xi][ld]
     double* Tp;                 // [nnodes][nslot][ld] (null at the root)
     const double* beta;
@@ -78,216 +78,9 @@ __device__ inline void children(const MergeArgs& a, int node, int* c1, int* c2) 
     }
 }
 
-// Interface matrix of every merge of the level.
-__global__ __launch_bounds__(256) void k_merge_assemble(MergeArgs a) {
-    const int node = blockIdx.x;
-    const int t0 = blockIdx.y * blockDim.x + threadIdx.x;
-    if (t0 >= a.xi * a.xi) return;
-    int c1, c2;
-    children(a, node, &c1, &c2);
-    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
-    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
-    const int* g1 = a.gmap;
-    const int* g2 = a.gmap + a.g;
-    const int* ss1 = a.css + (size_t)c1 * a.cnslot;
-    double* M = a.M + (size_t)node * a.xi * a.xi;
-    const int g = a.g;
-    {
-        const int t = t0;
-        const int r = t / a.xi, c = t % a.xi;
-        const int rr = r % g, cc = c % g;
-        double v = 0.0;
-        double wdiag = 0.0;
-        if (rr == cc) {
-            const int e = ss1[g1[rr]] >> 1;
-            wdiag = a.seglen[e] / (2.0 * a.beta[e]);
-        }
-        if (r < g && c < g) v = T1[(size_t)g1[r] * a.cld + g1[c]] + wdiag;
-        else if (r >= g && c >= g) v = T2[(size_t)g2[rr] * a.cld + g2[cc]] + wdiag;
-        else v = -wdiag;
-        if (a.pin && r == a.xi - 1) v = c == a.xi - 1 ? 1.0 : 0.0;
-        M[t] = v;
-    }
-}
-
-// In-place LU with partial pivoting, one workgroup per merge (row swaps
-// applied to whole rows, LAPACK getrf convention for piv).
-__global__ __launch_bounds__(256) void k_merge_lu(MergeArgs a) {
-    const int node = blockIdx.x;
-    const int n = a.xi;
-    double* M = a.M + (size_t)node * n * n;
-    int* piv = a.piv + (size_t)node * n;
-    __shared__ double sval[256];
-    __shared__ int sidx[256];
-    __shared__ int sing;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (tid == 0) sing = 0;
-    for (int k = 0; k < n; ++k) {
-        // pivot search in column k
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + tid; i < n; i += nt) {
-            const double v = fabs(M[(size_t)i * n + k]);
-            if (v > best) { best = v; bi = i; }
-        }
-        sval[tid] = best;
-        sidx[tid] = bi;
-        __syncthreads();
-        for (int s = nt / 2; s > 0; s >>= 1) {
-            if (tid < s) {
-                if (sval[tid + s] > sval[tid] ||
-                    (sval[tid + s] == sval[tid] && sidx[tid + s] < sidx[tid])) {
-                    sval[tid] = sval[tid + s];
-                    sidx[tid] = sidx[tid + s];
-                }
-            }
-            __syncthreads();
-        }
-        const int p = sidx[0];
-        const double pv = sval[0];
-        __syncthreads();
-        if (tid == 0) {
-            piv[k] = p;
-            if (!(pv > 0.0)) sing = 1;
-        }
-        if (p != k) {
-            for (int c = tid; c < n; c += nt) {
-                const double t0 = M[(size_t)k * n + c];
-                M[(size_t)k * n + c] = M[(size_t)p * n + c];
-                M[(size_t)p * n + c] = t0;
-            }
-        }
-        __syncthreads();
-        const double d = M[(size_t)k * n + k];
-        const double inv = d != 0.0 ? 1.0 / d : 0.0;
-        for (int i = k + 1 + tid; i < n; i += nt) M[(size_t)i * n + k] *= inv;
-        __syncthreads();
-        const int m = n - 1 - k;
-        for (int t = tid; t < m * m; t += nt) {
-            const int i = k + 1 + t / m, c = k + 1 + t % m;
-            M[(size_t)i * n + c] -= M[(size_t)i * n + k] * M[(size_t)k * n + c];
-        }
-        __syncthreads();
-    }
-    if (tid == 0 && sing) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
-}
-
-// Right-hand sides (negated) of parent columns [col0, col0 + ncol).  A
-// column < nslot is the parent basis column of that slot; col == nslot is
-// the particular column.
-__global__ __launch_bounds__(256) void k_merge_rhs(MergeArgs a, int col0, int ncol) {
-    const int node = blockIdx.x;
-    const int t0 = blockIdx.y * blockDim.x + threadIdx.x;
-    if (t0 >= a.xi * ncol) return;
-    int c1, c2;
-    children(a, node, &c1, &c2);
-    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
-    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
-    const int* g1 = a.gmap;
-    const int* g2 = a.gmap + a.g;
-    double* X = a.X + (size_t)node * a.xi * a.ld;
-    const int g = a.g;
-    {
-        const int t = t0;
-        const int r = t / ncol, col = col0 + t % ncol;
-        const int rr = r % g;
-        double v;
-        if (col == a.nslot) {
-            v = r < g ? T1[(size_t)g1[rr] * a.cld + a.cld - 1] : T2[(size_t)g2[rr] * a.cld + a.cld - 1];
-        } else {
-            const int pm = a.pmap[col];
-            const int k = pm >> 24, o = pm & 0xffffff;
-            if (k == 0) v = r < g ? T1[(size_t)g1[rr] * a.cld + o] : 0.0;
-            else v = r >= g ? T2[(size_t)g2[rr] * a.cld + o] : 0.0;
-        }
-        if (a.pin && r == a.xi - 1) v = 0.0;
-        X[(size_t)r * a.ld + col] = -v;
-    }
-}
-
-// X[:, cols] <- M^{-1} X[:, cols] with the LU factors; one workgroup per
-// (merge, chunk of CW columns), the chunk held in LDS.
-template <int CW>
-__global__ __launch_bounds__(256) void k_merge_solve(MergeArgs a, int col0, int ncol) {
-    extern __shared__ double xs[];     // xi x CW
-    const int node = blockIdx.x;
-    const int cbase = col0 + blockIdx.y * CW;
-    const int nc = min(CW, col0 + ncol - cbase);
-    if (nc <= 0) return;
-    const int n = a.xi;
-    const double* M = a.M + (size_t)node * n * n;
-    const int* piv = a.piv + (size_t)node * n;
-    double* X = a.X + (size_t)node * n * a.ld;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int t = tid; t < n * CW; t += nt) {
-        const int r = t / CW, c = t % CW;
-        xs[t] = c < nc ? X[(size_t)r * a.ld + cbase + c] : 0.0;
-    }
-    __syncthreads();
-    // row interchanges
-    if (tid < CW) {
-        for (int k = 0; k < n; ++k) {
-            const int p = piv[k];
-            if (p != k) {
-                const double t0 = xs[k * CW + tid];
-                xs[k * CW + tid] = xs[p * CW + tid];
-                xs[p * CW + tid] = t0;
-            }
-        }
-    }
-    __syncthreads();
-    // forward: unit lower
-    for (int k = 0; k < n - 1; ++k) {
-        const int m = n - 1 - k;
-        for (int t = tid; t < m * CW; t += nt) {
-            const int i = k + 1 + t / CW, c = t % CW;
-            xs[i * CW + c] -= M[(size_t)i * n + k] * xs[k * CW + c];
-        }
-        __syncthreads();
-    }
-    // backward: upper
-    for (int k = n - 1; k >= 0; --k) {
-        const double inv = 1.0 / M[(size_t)k * n + k];
-        if (tid < CW) xs[k * CW + tid] *= inv;
-        __syncthreads();
-        for (int t = tid; t < k * CW; t += nt) {
-            const int i = t / CW, c = t % CW;
-            xs[i * CW + c] -= M[(size_t)i * n + k] * xs[k * CW + c];
-        }
-        __syncthreads();
-    }
-    for (int t = tid; t < n * CW; t += nt) {
-        const int r = t / CW, c = t % CW;
-        if (c < nc) X[(size_t)r * a.ld + cbase + c] = xs[t];
-    }
-}
-
-// Parent traces for columns [col0, col0 + ncol): one thread per entry.
-__global__ __launch_bounds__(256) void k_merge_trace(MergeArgs a, int col0, int ncol) {
-    const int node = blockIdx.x;
-    const size_t t = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (t >= (size_t)a.nslot * ncol) return;
-    const int o = (int)(t / ncol), col = col0 + (int)(t % ncol);
-    int c1, c2;
-    children(a, node, &c1, &c2);
-    const int pm = a.pmap[o];
-    const int k = pm >> 24, oc = pm & 0xffffff;
-    const double* Tk = a.Tc + (size_t)(k == 0 ? c1 : c2) * a.cnslot * a.cld + (size_t)oc * a.cld;
-    const int* gk = a.gmap + k * a.g;
-    const double* X = a.X + (size_t)node * a.xi * a.ld + (size_t)(k * a.g) * a.ld + col;
-    double v;
-    if (col == a.nslot) {
-        v = Tk[a.cld - 1];
-    } else {
-        const int pc = a.pmap[col];
-        v = (pc >> 24) == k ? Tk[pc & 0xffffff] : 0.0;
-    }
-    for (int i = 0; i < a.g; ++i) v += Tk[gk[i]] * X[(size_t)i * a.ld];
-    a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = v;
-}
 
 // ---------------------------------------------------------------------------
-// Merges with g <= 128: pivot-free elimination in sum/difference variables.
+// Pivot-free elimination in sum/difference variables.
 //
 // With s = (y1 + y2) / 2 and d = (y2 - y1) / 2 (the interface pressure and
 // beta times the interface flux density of each gamma segment), the system
@@ -1081,16 +874,17 @@ __global__ __launch_bounds__(256) void k_down(DownArgs a) {
     }
 }
 
-// ---------------------------------------------------------------- g in (128, 256]
+// ---------------------------------------------------------------- g > 128
 // Merges whose gamma blocks exceed the register-resident inversion (one
 // workgroup holds at most 128 x 128 in registers): the same quasi-definite
 // elimination with the blocks in global memory.  D^{-1} and S^{-1} by a 2 x 2
 // split, [[A, C^T], [C, F]] with A of order 128: A^{-1} in registers (the
 // blocked Gauss-Jordan above), Y = A^{-1} C^T, the Schur block F - C Y and its
-// inverse the same way, then W = Y F'^{-1} and the four blocks of the inverse
-// (A^{-1} + W Y^T, -W, -W^T, F'^{-1}); E = D^{-1} B and S = N - B E, and the
-// four products of the column apply, as matrix products on the FP64 matrix
-// cores (k_gemm_f64), batched over the level's merges.
+// inverse in the same way (recursively while it exceeds 128), then
+// W = Y F'^{-1} and the four blocks of the inverse (A^{-1} + W Y^T, -W, -W^T,
+// F'^{-1}); E = D^{-1} B and S = N - B E, the four products of the column
+// apply, and beyond 256 the parent traces, as matrix products on the FP64
+// matrix cores (k_gemm_f64), batched over the level's merges.
 
 // C = beta C + alpha op(A) op(B) (row-major; ta / tb: the operand is stored
 // transposed), one 64 x 64 tile of C per workgroup, batch blockIdx.z with
@@ -1256,29 +1050,45 @@ __global__ __launch_bounds__(256) void k_qd_big_fix(double* X, long long ld, lon
     }
 }
 
-// Symmetric inverse in place of the g x g block at X (128 < g <= 256) of
-// every merge; Y and W: 128 x (g - 128) scratch per merge (merge stride sy).
-static hipError_t qd_big_inverse(rmrcm_ctx* c, const MergeArgs& a, double* X, double* Y, double* W,
-                                 long long sy) {
-    const int g = a.g, r = g - 128, nb = a.nnodes;
-    const long long gg = (long long)g * g, sx = 4 * gg;
+// Scratch of the inverse of order n: Y and W (128 x (n - 128)) per split.
+__host__ inline size_t big_inv_work(int n) {
+    size_t w = 0;
+    for (int r = n - 128; r > 0; r -= 128) w += 2 * 128 * (size_t)r;
+    return w;
+}
+
+// Symmetric inverse in place of the n x n block at X (row stride ld, merge
+// stride sx) of every merge; scratch from Yb (merge stride sy).
+static hipError_t qd_big_inverse(rmrcm_ctx* c, const MergeArgs& a, double* X, int n, long long ld,
+                                 long long sx, double* Yb, long long sy) {
+    const int nb = a.nnodes;
+    if (n <= 128) {
+        hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, ld, sx, n, a.flags);
+        return hipGetLastError();
+    }
+    const int r = n - 128;
+    double* Y = Yb;
+    double* W = Yb + 128 * (size_t)r;
     hipError_t e;
-    hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, (long long)g, sx, 128, a.flags);
+    hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, ld, sx, 128, a.flags);
     // Y = A^{-1} C^T (C^T: the top right block)
-    if ((e = gemm(c, nb, 128, r, 128, 0, X, g, sx, 0, X + 128, g, sx, Y, r, sy, 1.0, 0.0))) return e;
+    if ((e = gemm(c, nb, 128, r, 128, 0, X, ld, sx, 0, X + 128, ld, sx, Y, r, sy, 1.0, 0.0))) return e;
     // F <- F - C Y (C = rows 128.., columns ..128)
-    if ((e = gemm(c, nb, r, r, 128, 0, X + 128LL * g, g, sx, 0, Y, r, sy, X + 128LL * g + 128, g, sx, -1.0, 1.0))) return e;
-    hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X + 128LL * g + 128, (long long)g, sx, r, a.flags);
+    double* F = X + 128 * ld + 128;
+    if ((e = gemm(c, nb, r, r, 128, 0, X + 128 * ld, ld, sx, 0, Y, r, sy, F, ld, sx, -1.0, 1.0))) return e;
+    if ((e = qd_big_inverse(c, a, F, r, ld, sx, W + 128 * (size_t)r, sy))) return e;
     // W = Y F'^{-1};  A^{-1} <- A^{-1} + W Y^T
-    if ((e = gemm(c, nb, 128, r, r, 0, Y, r, sy, 0, X + 128LL * g + 128, g, sx, W, r, sy, 1.0, 0.0))) return e;
-    if ((e = gemm(c, nb, 128, 128, r, 0, W, r, sy, 1, Y, r, sy, X, g, sx, 1.0, 1.0))) return e;
-    hipLaunchKernelGGL(k_qd_big_fix, dim3((128 * r + 255) / 256, nb), dim3(256), 0, c->stream, X, (long long)g, sx,
-                       (const double*)W, sy, r, 0, g);
+    if ((e = gemm(c, nb, 128, r, r, 0, Y, r, sy, 0, F, ld, sx, W, r, sy, 1.0, 0.0))) return e;
+    if ((e = gemm(c, nb, 128, 128, r, 0, W, r, sy, 1, Y, r, sy, X, ld, sx, 1.0, 1.0))) return e;
+    hipLaunchKernelGGL(k_qd_big_fix, dim3((128 * r + 255) / 256, nb), dim3(256), 0, c->stream, X, ld, sx,
+                       (const double*)W, sy, r, 0, n);
     return hipGetLastError();
 }
 
+// Scratch per merge with g > 128: the inverses', three g x (nslot + 1) column
+// blocks of the apply, and beyond 256 the gathered trace rows (nslot x 2g).
 __host__ inline size_t big_work(int g, int nslot) {
-    return 2 * 128 * 128 + 3 * (size_t)g * (nslot + 1);
+    return big_inv_work(g) + 3 * (size_t)g * (nslot + 1) + (g > 256 ? (size_t)nslot * 2 * g : 0);
 }
 
 // Scratch per merge with g > 128 (merge stride big_work): Y and W of the
@@ -1286,22 +1096,20 @@ __host__ inline size_t big_work(int g, int nslot) {
 static hipError_t qd_factor_big(rmrcm_ctx* c, const MergeArgs& a) {
     const int g = a.g, nb = a.nnodes;
     const long long gg = (long long)g * g, sx = 4 * gg, sw = (long long)big_work(g, a.nslot);
-    double* Y = a.work;
-    double* W = a.work + 128 * 128;
     double* D = a.M;
     double* E = a.M + gg;
     double* S = a.M + 2 * gg;
     double* B = a.M + 3 * gg;
     hipLaunchKernelGGL(k_qd_gather_big, dim3((g * g + 255) / 256, nb), dim3(256), 0, c->stream, a);
     hipError_t e;
-    if ((e = qd_big_inverse(c, a, D, Y, W, sw))) return e;
+    if ((e = qd_big_inverse(c, a, D, g, g, sx, a.work, sw))) return e;
     // E = D^{-1} B;  S = N - B E
     if ((e = gemm(c, nb, g, g, g, 0, D, g, sx, 0, B, g, sx, E, g, sx, 1.0, 0.0))) return e;
     if ((e = gemm(c, nb, g, g, g, 0, B, g, sx, 0, E, g, sx, S, g, sx, -1.0, 1.0))) return e;
     if (a.pin)
         hipLaunchKernelGGL(k_qd_big_fix, dim3((g + 255) / 256, nb), dim3(256), 0, c->stream, S, (long long)g, sx,
                            (const double*)nullptr, 0LL, 0, 1, g);
-    if ((e = qd_big_inverse(c, a, S, Y, W, sw))) return e;
+    if ((e = qd_big_inverse(c, a, S, g, g, sx, a.work, sw))) return e;
     if (a.pin)
         hipLaunchKernelGGL(k_qd_big_fix, dim3(1, nb), dim3(256), 0, c->stream, S, (long long)g, sx,
                            (const double*)nullptr, 0LL, 0, 2, g);
@@ -1345,13 +1153,64 @@ __global__ __launch_bounds__(256) void k_qd_x_big(MergeArgs a, int col0, int nco
     X[(size_t)(g + i) * a.ld + col0 + cc] = -(s + d);
 }
 
+// Parent traces of merges beyond 256 gamma segments as a matrix product:
+// Tp = direct + A X with A[o][k g + i] = T_k[o's slot in child k][gamma_k(i)]
+// for the child k that owns slot o (zero in the other child's half), the
+// terms and their sum being those of k_qd_trace_mfma.
+__global__ __launch_bounds__(256) void k_qd_trace_rows_big(MergeArgs a, double* Ar, long long sw) {
+    const int node = blockIdx.y, g = a.g;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)a.nslot * 2 * g) return;
+    const int o = (int)(t / (2 * g)), q = (int)(t % (2 * g)), k = q / g, i = q % g;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const int pm = a.pmap[o];
+    double v = 0.0;
+    if ((pm >> 24) == k) {
+        const double* Tk = a.Tc + (size_t)(k == 0 ? c1 : c2) * a.cnslot * a.cld;
+        v = Tk[(size_t)(pm & 0xffffff) * a.cld + a.gmap[k * g + i]];
+    }
+    Ar[(size_t)node * sw + t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_qd_trace_direct_big(MergeArgs a, int col0, int ncol) {
+    const int node = blockIdx.y;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)a.nslot * ncol) return;
+    const int o = (int)(t / ncol), col = col0 + (int)(t % ncol);
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const int pm = a.pmap[o], k = pm >> 24;
+    const double* tr = a.Tc + (size_t)(k == 0 ? c1 : c2) * a.cnslot * a.cld + (size_t)(pm & 0xffffff) * a.cld;
+    const int pc = col < a.nslot ? a.pmap[col] : -1;
+    const double d = col == a.nslot ? tr[a.cld - 1] : ((pc >> 24) == k ? tr[pc & 0xffffff] : 0.0);
+    a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = d;
+}
+
+static hipError_t qd_trace_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
+    const int g = a.g, nb = a.nnodes;
+    if (g <= 256) {
+        hipLaunchKernelGGL(k_qd_trace_mfma<256>, dim3(nb, (a.nslot + 63) / 64, (ncol + 15) / 16), dim3(256), 0,
+                           c->stream, a, col0, ncol);
+        return hipGetLastError();
+    }
+    const long long sw = (long long)big_work(g, a.nslot);
+    double* Ar = a.work + big_inv_work(g) + 3 * (size_t)g * (a.nslot + 1);
+    const long long nr = (long long)a.nslot * 2 * g, nd = (long long)a.nslot * ncol;
+    hipLaunchKernelGGL(k_qd_trace_rows_big, dim3((unsigned)((nr + 255) / 256), nb), dim3(256), 0, c->stream, a, Ar, sw);
+    hipLaunchKernelGGL(k_qd_trace_direct_big, dim3((unsigned)((nd + 255) / 256), nb), dim3(256), 0, c->stream, a,
+                       col0, ncol);
+    return gemm(c, nb, a.nslot, ncol, 2 * g, 0, Ar, 2 * g, sw, 0, a.X + col0, a.ld, (long long)a.xi * a.ld,
+                a.Tp + col0, a.ld, (long long)a.nslot * a.ld, 1.0, 1.0);
+}
+
 static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
     const int g = a.g, nb = a.nnodes;
     const long long gg = (long long)g * g, sx = 4 * gg;
     const size_t per = big_work(g, a.nslot);
     if ((size_t)ncol > (size_t)a.nslot + 1) return hipErrorInvalidValue;
-    // per merge: RS, RD, TT of g x ncol each, after Y and W
-    double* RS = a.work + 2 * 128 * 128;
+    // per merge: RS, RD, TT of g x ncol each, after the inverses' scratch
+    double* RS = a.work + big_inv_work(g);
     double* RD = RS + (size_t)g * (a.nslot + 1);
     double* TT = RD + (size_t)g * (a.nslot + 1);
     const long long sw = (long long)per;
@@ -1389,7 +1248,6 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     a.pmap = P.pmap;
     a.gmap = P.gmap;
     a.M = P.M;
-    a.piv = P.piv;
     a.X = P.X;
     a.Tp = P.T;
     a.beta = c->beta;
@@ -1400,24 +1258,10 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     return a;
 }
 
-static constexpr int kCW = 16;
 
-// Generic column solve (any xi, factors read from global memory step by step).
-static hipError_t solve_cols_generic(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
-    const int nchunk = (ncol + kCW - 1) / kCW;
-    const size_t lds = sizeof(double) * (size_t)a.xi * kCW;
-    hipError_t e = hipFuncSetAttribute((const void*)k_merge_solve<kCW>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_solve<kCW>, dim3(a.nnodes, nchunk), dim3(256), lds, c->stream, a,
-                       col0, ncol);
-    return hipGetLastError();
-}
-
-// Size class of the pivot-free path (0: gamma too long, generic LU path).
-static int qd_tier(int g) {
-    return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : g <= 256 ? 256 : 0;
-}
+// Size class of the merge: register-resident tiers up to 128; 256 stands for
+// every larger gamma (the blocks in global memory).
+static int qd_tier(int g) { return g <= 16 ? 16 : g <= 32 ? 32 : g <= 64 ? 64 : g <= 128 ? 128 : 256; }
 
 // ct: columns per workgroup, 16 or 32 (0: 16).
 template <int GT>
@@ -1477,22 +1321,18 @@ static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int
         case 256: {
             hipError_t e = qd_apply_big(c, a, col0, ncol);
             if (e != hipSuccess || !trace) return e;
-            hipLaunchKernelGGL(k_qd_trace_mfma<256>, dim3(a.nnodes, (a.nslot + 63) / 64, (ncol + 15) / 16),
-                               dim3(256), 0, c->stream, a, col0, ncol);
-            return hipGetLastError();
+            return qd_trace_big(c, a, col0, ncol);
         }
     }
     return hipErrorInvalidValue;
 }
 
-size_t merge_work_doubles(const Level& L) {
-    return (L.g > 128 && L.g <= 256) ? big_work(L.g, L.nslot) : 0;
-}
+size_t merge_work_doubles(const Level& L) { return L.g > 128 ? big_work(L.g, L.nslot) : 0; }
 
 bool merge_apply_tunable(rmrcm_ctx* c, int d) {
     if (!(d > 0 && d < c->D)) return false;
     const int t = qd_tier(c->levels[d].g);
-    return t != 0 && t != 256;
+    return t != 256;
 }
 
 hipError_t launch_merge_apply(rmrcm_ctx* c, int d, int ct) {
@@ -1511,24 +1351,9 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d, bool part) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
     const int ncol = a.nslot + (part ? 1 : 0);
-    if (qd_tier(a.g)) {
-        hipError_t e = qd_factor_any(c, a);
-        if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
-        return qd_columns_any(c, a, 0, ncol, true, c->ct_tune[d]);
-    }
-    hipLaunchKernelGGL(k_merge_assemble, dim3(a.nnodes, (a.xi * a.xi + 255) / 256), dim3(256), 0,
-                       c->stream, a);
-    hipLaunchKernelGGL(k_merge_lu, dim3(a.nnodes), dim3(256), 0, c->stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || d == 0) return e;
-    hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi * ncol + 255) / 256), dim3(256), 0,
-                       c->stream, a, 0, ncol);
-    e = solve_cols_generic(c, a, 0, ncol);
-    if (e != hipSuccess) return e;
-    const size_t tot = (size_t)a.nslot * ncol;
-    hipLaunchKernelGGL(k_merge_trace, dim3(a.nnodes, (unsigned)((tot + 255) / 256)), dim3(256), 0,
-                       c->stream, a, 0, ncol);
-    return hipGetLastError();
+    hipError_t e = qd_factor_any(c, a);
+    if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
+    return qd_columns_any(c, a, 0, ncol, true, c->ct_tune[d]);
 }
 
 hipError_t launch_merge_particular(rmrcm_ctx* c, int d) {
@@ -1543,15 +1368,7 @@ hipError_t launch_merge_particular(rmrcm_ctx* c, int d) {
             case 128: hipLaunchKernelGGL(k_qd_apply_vec<128>, dim3(a.nnodes), dim3(1024), 0, c->stream, a, a.nslot); return hipGetLastError();
         }
     }
-    if (qd_tier(a.g)) return qd_columns_any(c, a, a.nslot, 1, d != 0, 1);
-    hipLaunchKernelGGL(k_merge_rhs, dim3(a.nnodes, (a.xi + 255) / 256), dim3(256), 0, c->stream, a,
-                       a.nslot, 1);
-    hipError_t e = solve_cols_generic(c, a, a.nslot, 1);
-    if (e != hipSuccess) return e;
-    if (d == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge_trace, dim3(a.nnodes, (unsigned)((a.nslot + 255) / 256)), dim3(256),
-                       0, c->stream, a, a.nslot, 1);
-    return hipGetLastError();
+    return qd_columns_any(c, a, a.nslot, 1, d != 0, 1);
 }
 
 hipError_t launch_down(rmrcm_ctx* c, int d) {

@@ -50,8 +50,7 @@ struct Level {
     int xi = 0;                // 2 g interface unknowns (one Robin datum per side)
     int* pmap = nullptr;       // [nslot] (child << 24) | child slot
     int* gmap = nullptr;       // [2][g] gamma -> child-1 slot, child-2 slot
-    double* M = nullptr;       // [nnodes][xi][xi] LU factors (in place)
-    int* piv = nullptr;        // [nnodes][xi]
+    double* M = nullptr;       // [nnodes][4 g^2]: D^{-1}, E, S^{-1}, B of the merge
     double* X = nullptr;       // [nnodes][xi][ld] coefficients of every column
     double* work = nullptr;    // scratch of merges with 128 < g <= 256 (merge_work_doubles per node)
     std::vector<int> h_pmap, h_gmap, h_slotseg;

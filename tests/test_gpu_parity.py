@@ -9,8 +9,9 @@ Robin data divided by 2 beta).
 Sizes: the oracle finishes each case in seconds; cases span many
 subdomains, every supported subdomain width, rectangular grids and
 subdomains, segment lengths from one face to a whole side, the degenerate
-single-subdomain and two-subdomain decompositions, interfaces of 256 segments (the
-merges whose blocks exceed one workgroup's registers), and the full 1024^2
+single-subdomain and two-subdomain decompositions, interfaces of 256 to 1024
+segments (the merges whose blocks exceed one workgroup's registers), and the
+full 1024^2
 workload (32^2 subdomains of 32^2 cells, 10 levels) in the launch
 configuration the benchmark times.
 """
@@ -106,6 +107,20 @@ def test_seg1_equals_fine_solution(Solver, b):
     pf, Ff = fine_solve(prob)
     p, F, U, P = run_gpu(Solver, prob, "seg1_b%d" % b)
     assert rel_l2(p, pf) <= TOL and rel_l2(F, Ff) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,b,bc", [(512, 512, 16, "we"), (1024, 512, 32, "we"),
+                                        (512, 512, 16, "fivespot"), (1024, 1024, 32, "we")])
+def test_long_gamma_seg1_equals_fine_solution(Solver, nx, ny, b, bc):
+    """Interfaces of 512 and 1024 segments (one fine face each) at the top
+    levels: the merges with blocks in global memory (recursively split
+    inverses, matrix-product applies and parent traces) reproduce the fine
+    solve, with Dirichlet data and all-Neumann (the pinned top)."""
+    prob = make_problem(nx, ny=ny, b=b, seg=1, log_var=2.0, lam=0.1, source=(bc == "we"), bc=bc)
+    pf, Ff = fine_solve(prob)
+    p, F, U, P = run_gpu(Solver, prob, "gamma_long_%dx%d_b%d_%s" % (nx, ny, b, bc))
+    assert rel_l2(p, pf) <= TOL, rel_l2(p, pf)
+    assert rel_l2(F, Ff) <= TOL, rel_l2(F, Ff)
 
 
 def test_invariants_on_gpu_output(Solver):
