@@ -496,10 +496,12 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int
 // The two products between the inversions of k_qd_factor_mfma, E = D^{-1} B
 // and S = N - B E, spread over workgroups: block column w = blockIdx.y of
 // one merge per workgroup (S's block column needs only E's), wave r forming
-// row tile r of E's block column, shared in LDS, then of S's.  The matrix
-// core sequences are those of the single-workgroup form, so the numbers are
-// the same; for merges that are few and large (one workgroup per merge would
-// leave the chip idle).
+// row tile r of E's block column, shared in LDS, then of S's; for merges
+// that are few and large (one workgroup per merge would leave the chip
+// idle).
+template <int GT>
+__device__ __forceinline__ void qd_load_tile(int g, const double* __restrict__ A, double (&av)[GT / 4]);
+
 template <int GT>
 __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
     constexpr int T = QdM<GT>::T;
@@ -513,19 +515,18 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
     const double* Bg = Sg + gg;
     const int j = 16 * w + li, ia = 16 * r + li;
     // every operand of a product is loaded before the product runs (the
-    // loads in flight together), B's row tile for S before the barrier
+    // loads in flight together), B's row tile for S before the barrier; the
+    // k-slices as in qd_load_tile (slice q: k = 16 (q / 4) + 4 lk + q % 4, a
+    // lane's row entries read four at a time)
     double av[4 * T], bv[4 * T], b2[4 * T];
+    qd_load_tile<GT>(g, Dg, av);
+    qd_load_tile<GT>(g, Bg, b2);
 #pragma unroll
     for (int q = 0; q < 4 * T; ++q) {
-        const int ka = 4 * q + lk;          // 16 K + 4 s + lk with q = 4 K + s
-        av[q] = (ia < g && ka < g) ? Dg[(size_t)ia * g + ka] : 0.0;
+        const int ka = 16 * (q >> 2) + 4 * lk + (q & 3);
         bv[q] = (ka < g && j < g) ? Bg[(size_t)ka * g + j] : 0.0;
     }
-#pragma unroll
-    for (int q = 0; q < 4 * T; ++q) {
-        const int ka = 4 * q + lk;
-        b2[q] = (ia < g && ka < g) ? Bg[(size_t)ia * g + ka] : 0.0;
-    }
+    (void)ia;
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 4 * T; ++q) acc = mfma_f64(av[q], bv[q], acc);
@@ -543,7 +544,8 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
         sc[v] = (i < g && j < g) ? Sg[(size_t)i * g + j] : (i == j ? 1.0 : 0.0);
     }
 #pragma unroll
-    for (int q = 0; q < 4 * T; ++q) sc = mfma_f64(-b2[q], Es[(4 * q + lk) * 17 + li], sc);
+    for (int q = 0; q < 4 * T; ++q)
+        sc = mfma_f64(-b2[q], Es[(16 * (q >> 2) + 4 * lk + (q & 3)) * 17 + li], sc);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int i = 16 * r + lk + 4 * v;
