@@ -222,6 +222,18 @@ int alloc_levels(rmrcm_ctx* c) {
         if (d < c->D) {
             TRY(dalloc(c, &L.pmap, L.h_pmap.size()));
             TRY(dalloc(c, &L.gmap, L.h_gmap.size()));
+            // gamma segment t of merge n: the code of gamma slot t in child 1
+            const Level& C = c->levels[d + 1];
+            L.h_gseg.assign((size_t)L.nnodes * L.g, 0);
+            for (int n = 0; n < L.nnodes; ++n) {
+                const int ix = n % L.nodes_x, iy = n / L.nodes_x;
+                const int c1 = L.cut == 0 ? iy * (2 * L.nodes_x) + 2 * ix : (2 * iy) * L.nodes_x + ix;
+                for (int t = 0; t < L.g; ++t)
+                    L.h_gseg[(size_t)n * L.g + t] = C.h_slotseg[(size_t)c1 * C.nslot + L.h_gmap[t]] >> 1;
+            }
+            TRY(dalloc(c, &L.gseg, L.h_gseg.size()));
+            HIP_TRY(hipMemcpyAsync(L.gseg, L.h_gseg.data(), L.h_gseg.size() * sizeof(int),
+                                   hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipMemcpyAsync(L.pmap, L.h_pmap.data(), L.h_pmap.size() * sizeof(int),
                                    hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipMemcpyAsync(L.gmap, L.h_gmap.data(), L.h_gmap.size() * sizeof(int),
@@ -234,6 +246,10 @@ int alloc_levels(rmrcm_ctx* c) {
     }
     // the root level keeps a trace buffer only when it is also the leaf level
     if (c->D == 0) TRY(dalloc(c, &c->levels[0].T, (size_t)c->levels[0].nslot * c->levels[0].ld));
+    if (c->D > 0) {
+        TRY(dalloc(c, &c->dlev, rmrcm::down_table_bytes(c)));
+        HIP_TRY(rmrcm::upload_down_levels(c));
+    }
     return RMRCM_OK;
 }
 
@@ -241,11 +257,14 @@ void free_all(rmrcm_ctx* c) {
     auto f = [](void* p) {
         if (p) (void)hipFree(p);
     };
+    f(c->dlev);
+    c->dlev = nullptr;
     for (Level& L : c->levels) {
         f(L.T);
         f(L.slotseg);
         f(L.pmap);
         f(L.gmap);
+        f(L.gseg);
         f(L.M);
         f(L.X);
         f(L.work);
@@ -482,7 +501,7 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     TRY(mark(c, 6));
     HIP_TRY(rmrcm::launch_merge_particular(c, 0));
     TRY(mark(c, 7));
-    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    HIP_TRY(rmrcm::launch_down_all(c));
     TRY(mark(c, 8));
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
@@ -514,7 +533,7 @@ int enqueue_solve(rmrcm_ctx* c) {
     TRY(mark(c, 6));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
     TRY(mark(c, 7));
-    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    HIP_TRY(rmrcm::launch_down_all(c));
     TRY(mark(c, 8));
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
@@ -552,7 +571,7 @@ int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
     for (int i = 4; i <= 6; ++i) TRY(mark(c, i));
     if (c->D > 0) HIP_TRY(rmrcm::launch_merge_particular(c, 0));   // the top's particular column
     TRY(mark(c, 7));
-    for (int d = 0; d < c->D; ++d) HIP_TRY(rmrcm::launch_down(c, d));
+    HIP_TRY(rmrcm::launch_down_all(c));
     TRY(mark(c, 8));
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));

@@ -24,6 +24,8 @@
 // quasi-definite form below: gamma blocks of up to 128 segments in
 // registers, longer ones in global memory.
 
+#include <algorithm>
+#include <vector>
 #include "rmrcm_internal.h"
 
 namespace rmrcm {
@@ -36,6 +38,7 @@ struct MergeArgs {
     const int* css;             // child slot codes
     const int* pmap;            // [nslot]
     const int* gmap;            // [2][g]
+    const int* gseg;            // [nnodes][g] global segment of gamma segment t
     double* M;                  // [nnodes][4 g^2]: D^{-1}, E, S^{-1}, B
     double* X;                  // [nnodes][xi][ld]
     double* Tp;                 // [nnodes][nslot][ld] (null at the root)
@@ -157,9 +160,11 @@ __device__ inline double rcp_refined(double d) {
 // panel cpk (row stride CPL), returned in the accumulator layout.  lt, ls:
 // this wave's two 16 x LTL scratch blocks.  Lanes 0-15 hold the columns of
 // M_KK, lanes 16-31 the identity; eliminating below each pivot (multipliers
-// from the pivot row, by symmetry) leaves L^{-1} in lanes 16-31.
+// from the pivot row, by symmetry) leaves L^{-1} in lanes 16-31.  kmax: the
+// rows and columns from kmax on are identity ones, whose elimination steps
+// change nothing and are skipped.
 __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double* lt, double* ls,
-                                                 int* bad) {
+                                                 int* bad, int kmax = 16) {
     typedef QdM<16> Q;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const bool scol = lane < 16, icol = lane >= 16 && lane < 32;
@@ -170,6 +175,10 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
     int sing = 0;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
+        if (k >= kmax) {
+            rd[k] = 1.0;
+            continue;
+        }
         double d = readlane_d(a[k], k);
         if (!(d != 0.0 && isfinite(d))) {
             sing = 1;
@@ -822,6 +831,267 @@ __global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, in
     }
 }
 
+// ---------------------------------------------------------------- g <= 16
+// Merges below the root whose gamma block is one 16 x 16 tile: factor,
+// column apply and parent traces in one workgroup per merge, one wave per
+// 16-column tile (at least four).  At these sizes every step is bound by
+// load latency, so the kernel keeps the dependent global round trips to
+// two before the factorisation: the level's maps and the gamma segments'
+// numbers, then everything else at once.  Wave 0 gathers the gamma blocks
+// and factors them in registers (the pivot chains stopping at g); the other
+// waves stage in LDS the right-hand sides of every column (r1 + r2 and
+// r2 - r1) and the child trace entries of every parent slot against gamma
+// (the left operand of the trace product); every wave meanwhile loads the
+// direct terms of its columns' parent traces.  After the factorisation each
+// wave applies it to its column tile in registers (a result in the
+// accumulator layout is the next product's B operand), writes X and forms
+// the parent traces of its columns.  Layouts as in the tiers above:
+// accumulator lane l, register v = row l/16 + 4v, column l%16.
+__host__ __device__ inline int small_cw(int ncol) { return 16 * ((ncol + 15) / 16) + 1; }
+__host__ __device__ inline int small_ns16(int nslot) { return 16 * ((nslot + 15) / 16); }
+__host__ __device__ inline int small_waves(int ncol) { return max(4, (ncol + 15) / 16); }
+__host__ __device__ inline size_t small_lds_bytes(int ncol, int nslot) {
+    const size_t nd = (size_t)32 * small_cw(ncol) + (size_t)small_ns16(nslot) * 17 + 5 * 272 + 2 * 16 * 20;
+    return nd * sizeof(double) + (size_t)(48 + small_ns16(nslot) + 1) * sizeof(int);
+}
+
+__global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
+    extern __shared__ double sm[];
+    const int CW = small_cw(ncol), NS16 = small_ns16(a.nslot), CT = (ncol + 15) / 16, NRT = NS16 / 16;
+    double* rs = sm;                 // [16][CW]  r1 + r2
+    double* rd = rs + 16 * CW;       // [16][CW]  r2 - r1
+    double* ar = rd + 16 * CW;       // [NS16][17] T_k(o)[o, gamma_k(i)]
+    double* dl = ar + NS16 * 17;     // D^{-1}, B, E, S^{-1}: [16][17] each
+    double* bl = dl + 272;
+    double* el = bl + 272;
+    double* sl = el + 272;
+    double* cp = sl + 272;           // the block being inverted
+    double* lt = cp + 272;
+    double* ls = lt + 16 * 20;
+    int* gi1 = (int*)(ls + 16 * 20);
+    int* gi2 = gi1 + 16;
+    int* ge = gi2 + 16;              // global segment of gamma segment i
+    int* pms = ge + 16;              // [NS16] parent slot map
+    int* bad = pms + NS16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int nt = blockDim.x, node = blockIdx.x, g = a.g, nslot = a.nslot;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    if (tid < 16) {
+        gi1[tid] = tid < g ? a.gmap[tid] : 0;
+        gi2[tid] = tid < g ? a.gmap[g + tid] : 0;
+        ge[tid] = tid < g ? a.gseg[(size_t)node * g + tid] : 0;
+    }
+    if (tid >= 16)
+        for (int o = tid - 16; o < NS16; o += nt - 16) pms[o] = o < nslot ? a.pmap[o] : -1;
+    if (tid == 0) *bad = 0;
+    __syncthreads();
+    // this wave's column tile and the direct terms of its parent traces:
+    // T_k[o, col] where slot o and column col belong to the same child k
+    // (the particular column: T_k's own)
+    const int col = 16 * w + li;
+    const bool cin = col < ncol;
+    double dv[8][4];
+    auto load_direct = [&]() {
+        const int pc = (cin && col < nslot) ? pms[col] : -1;
+#pragma unroll
+        for (int ot = 0; ot < 8; ++ot)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 16 * ot + lk + 4 * v;
+                double x = 0.0;
+                if (ot < NRT && o < nslot && cin) {
+                    const int pm = pms[o], k = pm >> 24;
+                    const double* tr = (k ? T2 : T1) + (size_t)(pm & 0xffffff) * a.cld;
+                    if (col == nslot) x = tr[a.cld - 1];
+                    else if ((pc >> 24) == k) x = tr[pc & 0xffffff];
+                }
+                dv[ot][v] = x;
+            }
+    };
+    const size_t gg = (size_t)g * g;
+    double* Dg = a.M + (size_t)node * 4 * gg;
+    double* Eg = Dg + gg;
+    double* Sg = Eg + gg;
+    double* Bg = Sg + gg;
+    if (w == 0) {
+        // D = N + 4W, B = T2gg - T1gg, N = T1gg + T2gg (identity / zero padding)
+        double t1[4], t2[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = lk + 4 * v;
+            const bool in = i < g && li < g;
+            t1[v] = in ? T1[(size_t)gi1[i] * a.cld + gi1[li]] : 0.0;
+            t2[v] = in ? T2[(size_t)gi2[i] * a.cld + gi2[li]] : 0.0;
+        }
+        const int eg = ge[li];
+        const double wl = li < g ? a.seglen[eg] / (2.0 * a.beta[eg]) : 0.0;
+        load_direct();
+        v4d Dm, Nm, Bm;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = lk + 4 * v;
+            const bool in = i < g && li < g;
+            Nm[v] = t1[v] + t2[v];
+            Bm[v] = t2[v] - t1[v];
+            Dm[v] = in ? Nm[v] + (i == li ? 4.0 * wl : 0.0) : (i == li ? 1.0 : 0.0);
+            cp[i * 17 + li] = Dm[v];
+            bl[i * 17 + li] = Bm[v];
+        }
+        wave_lds_sync();
+        const v4d Dinv = qd_pivot_inverse(cp, 0, lt, ls, bad, g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dl[(lk + 4 * v) * 17 + li] = Dinv[v];
+        wave_lds_sync();
+        // E = D^{-1} B, S = N - B E
+        v4d E = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) E = mfma_f64(dl[li * 17 + 4 * s + lk], Bm[s], E);
+        v4d S = Nm;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) S = mfma_f64(-bl[li * 17 + 4 * s + lk], E[s], S);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = lk + 4 * v;
+            const bool in = i < g && li < g;
+            el[i * 17 + li] = E[v];
+            cp[i * 17 + li] = in ? S[v] : (i == li ? 1.0 : 0.0);
+        }
+        wave_lds_sync();
+        const v4d Sinv = qd_pivot_inverse(cp, 0, lt, ls, bad, g);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = lk + 4 * v;
+            sl[i * 17 + li] = Sinv[v];
+            if (i < g && li < g) {
+                const size_t e = (size_t)i * g + li;
+                Dg[e] = Dinv[v];
+                Eg[e] = E[v];
+                Sg[e] = Sinv[v];
+                Bg[e] = Bm[v];
+            }
+        }
+        if (lane == 0 && *bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
+    } else {
+        load_direct();
+        // right-hand sides of the columns, four loads in flight per thread
+        const int t2 = tid - 64, ns = nt - 64, CC = 16 * CT;
+        for (int t0 = 0; t0 < 16 * CC; t0 += 4 * ns) {
+            double v1[4], v2[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + ns * u + t2, i = t / CC, cc = t % CC;
+                v1[u] = 0.0;
+                v2[u] = 0.0;
+                if (t < 16 * CC && i < g && cc < ncol) {
+                    if (cc == nslot) {
+                        v1[u] = T1[(size_t)gi1[i] * a.cld + a.cld - 1];
+                        v2[u] = T2[(size_t)gi2[i] * a.cld + a.cld - 1];
+                    } else {
+                        const int pm = pms[cc], off = pm & 0xffffff;
+                        if ((pm >> 24) == 0) v1[u] = T1[(size_t)gi1[i] * a.cld + off];
+                        else v2[u] = T2[(size_t)gi2[i] * a.cld + off];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + ns * u + t2;
+                if (t < 16 * CC) {
+                    const int e = (t / CC) * CW + t % CC;
+                    rs[e] = v1[u] + v2[u];
+                    rd[e] = v2[u] - v1[u];
+                }
+            }
+        }
+        // the trace product's left operand: row o, gamma segment i of the
+        // child that owns slot o
+        for (int t0 = 0; t0 < 16 * NS16; t0 += 4 * ns) {
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + ns * u + t2, o = t >> 4, i = t & 15;
+                v[u] = 0.0;
+                if (t < 16 * NS16 && o < nslot && i < g) {
+                    const int pm = pms[o], k = pm >> 24;
+                    const double* tr = (k ? T2 : T1) + (size_t)(pm & 0xffffff) * a.cld;
+                    v[u] = tr[k ? gi2[i] : gi1[i]];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + ns * u + t2;
+                if (t < 16 * NS16) ar[(t >> 4) * 17 + (t & 15)] = v[u];
+            }
+        }
+    }
+    __syncthreads();
+    if (w >= CT) return;
+    double DA[4], BA[4], SA[4], EA[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int e = li * 17 + 4 * s + lk;
+        DA[s] = dl[e];
+        BA[s] = bl[e];
+        SA[s] = sl[e];
+        EA[s] = el[e];
+    }
+    // t = D^{-1} (r2 - r1), u = r1 + r2 - B t, s = S^{-1} u, d = t - E s
+    v4d t = {0.0, 0.0, 0.0, 0.0}, u, sv = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) t = mfma_f64(DA[s], rd[(4 * s + lk) * CW + col], t);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = rs[(lk + 4 * v) * CW + col];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) u = mfma_f64(-BA[s], t[s], u);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) sv = mfma_f64(SA[s], u[s], sv);
+    v4d dd = t;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) dd = mfma_f64(-EA[s], sv[s], dd);
+    v4d x1, x2;
+    double* X = a.X + (size_t)node * a.xi * a.ld;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        x1[v] = -(sv[v] - dd[v]);
+        x2[v] = -(sv[v] + dd[v]);
+        const int i = lk + 4 * v;
+        if (i < g && cin) {
+            X[(size_t)i * a.ld + col] = x1[v];
+            X[(size_t)(g + i) * a.ld + col] = x2[v];
+        }
+    }
+    // T_p[o, col] = direct + sum_i A_1[o][i] X_1[i][col] + A_2[o][i] X_2[i][col]
+    double* Tp = a.Tp + (size_t)node * nslot * a.ld;
+#pragma unroll
+    for (int ot = 0; ot < 8; ++ot) {
+        if (ot >= NRT) break;
+        const int o = 16 * ot + li;
+        const int ko = o < nslot ? (pms[o] >> 24) : -1;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double val = ar[o * 17 + 4 * q + lk];
+            acc = mfma_f64(ko == 0 ? val : 0.0, x1[q], acc);
+            acc = mfma_f64(ko == 1 ? val : 0.0, x2[q], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int oo = 16 * ot + lk + 4 * v;
+            if (oo < nslot && cin) Tp[(size_t)oo * a.ld + col] = dv[ot][v] + acc[v];
+        }
+    }
+}
+
+// The fused merge above serves a level when its gamma fits one tile, it is
+// not the root, and the staged operands fit 64 KiB of LDS.
+static bool small_merge_ok(const MergeArgs& a, int d, int ncol) {
+    return d > 0 && a.g <= 16 && !a.pin && a.nslot <= 127 && ncol <= 128 &&
+           small_lds_bytes(ncol, a.nslot) <= 64 * 1024;
+}
+
 
 // Downward pass at one level: gamma data y = X [d; 1] from the node's
 // boundary data d, written to the low / high Robin data of the gamma
@@ -1232,6 +1502,88 @@ static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int n
     return hipGetLastError();
 }
 
+// Per-depth description of the downward pass (device table, one entry per
+// merge depth d < D: that depth's merges and the slots of their children).
+struct DownLevel {
+    int nodes_x, nodes_y, g, xi, nslot, ld, cut, cnslot;
+    const double* X;
+    const int* ss;      // node slot codes
+    const int* css;     // child slot codes
+    const int* gmap;
+};
+
+// The downward pass of depths d0 .. d1 - 1 (short interfaces) for the
+// subtree of one depth-d0 merge per workgroup.  A merge's gamma data depend
+// on its ancestors only, so the depths follow one another inside the
+// workgroup (barriers, no synchronisation between workgroups).  Per depth:
+// the data vector of every merge of the subtree (Robin data of its slots, 1
+// for the particular column) to LDS, then every (merge, gamma row) pair as
+// one thread's dot product with that row of X, written to the datum of the
+// row's side of its segment.
+__global__ __launch_bounds__(256) void k_down_sub(const DownLevel* __restrict__ L, int d0, int d1,
+                                                  double* __restrict__ glo, double* __restrict__ ghi) {
+    extern __shared__ double dvec[];
+    const int tid = threadIdx.x;
+    const int rx0 = L[d0].nodes_x, ry0 = L[d0].nodes_y;
+    const int ix0 = blockIdx.x % rx0, iy0 = blockIdx.x / rx0;
+    for (int d = d0; d < d1; ++d) {
+        const DownLevel a = L[d];
+        const int fx = a.nodes_x / rx0, fy = a.nodes_y / ry0;   // the subtree at depth d: fx x fy merges
+        const int nsub = fx * fy, w = a.nslot + 1;
+        auto node_of = [&](int k) { return (iy0 * fy + k / fx) * a.nodes_x + ix0 * fx + k % fx; };
+        for (int t = tid; t < nsub * w; t += blockDim.x) {
+            const int k = t / w, sl = t % w;
+            double v = 1.0;
+            if (sl < a.nslot) {
+                const int code = a.ss[(size_t)node_of(k) * a.nslot + sl];
+                v = code < 0 ? 0.0 : ((code & 1) ? glo[code >> 1] : ghi[code >> 1]);
+            }
+            dvec[t] = v;
+        }
+        __syncthreads();
+        for (int p = tid; p < nsub * a.xi; p += blockDim.x) {
+            const int k = p / a.xi, r = p % a.xi;
+            const int node = node_of(k);
+            const int ix = node % a.nodes_x, iy = node / a.nodes_x;
+            const int c1 = a.cut == 0 ? iy * (2 * a.nodes_x) + 2 * ix : (2 * iy) * a.nodes_x + ix;
+            const double* xr = a.X + ((size_t)node * a.xi + r) * a.ld;
+            const double* dv = dvec + (size_t)k * w;
+            double s = 0.0;
+#pragma unroll 8
+            for (int q = 0; q < a.ld; ++q) s = fma(xr[q], dv[q], s);
+            const int e = a.css[(size_t)c1 * a.cnslot + a.gmap[r % a.g]] >> 1;
+            if (r < a.g) glo[e] = s;
+            else ghi[e] = s;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t upload_down_levels(rmrcm_ctx* c) {
+    if (c->D == 0) return hipSuccess;
+    std::vector<DownLevel> h((size_t)c->D);
+    for (int d = 0; d < c->D; ++d) {
+        const Level& P = c->levels[d];
+        const Level& C = c->levels[d + 1];
+        DownLevel& a = h[(size_t)d];
+        a.nodes_x = P.nodes_x;
+        a.nodes_y = P.nodes_y;
+        a.g = P.g;
+        a.xi = P.xi;
+        a.nslot = P.nslot;
+        a.ld = P.ld;
+        a.cut = P.cut;
+        a.cnslot = C.nslot;
+        a.X = P.X;
+        a.ss = P.slotseg;
+        a.css = C.slotseg;
+        a.gmap = P.gmap;
+    }
+    return hipMemcpy(c->dlev, h.data(), h.size() * sizeof(DownLevel), hipMemcpyHostToDevice);
+}
+
+size_t down_table_bytes(const rmrcm_ctx* c) { return (size_t)c->D * sizeof(DownLevel); }
+
 static MergeArgs make_args(rmrcm_ctx* c, int d) {
     Level& P = c->levels[d];
     Level& C = c->levels[d + 1];
@@ -1249,6 +1601,7 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     a.css = C.slotseg;
     a.pmap = P.pmap;
     a.gmap = P.gmap;
+    a.gseg = P.gseg;
     a.M = P.M;
     a.X = P.X;
     a.Tp = P.T;
@@ -1333,8 +1686,9 @@ size_t merge_work_doubles(const Level& L) { return L.g > 128 ? big_work(L.g, L.n
 
 bool merge_apply_tunable(rmrcm_ctx* c, int d) {
     if (!(d > 0 && d < c->D)) return false;
-    const int t = qd_tier(c->levels[d].g);
-    return t != 256;
+    const MergeArgs a = make_args(c, d);
+    if (small_merge_ok(a, d, a.nslot) || small_merge_ok(a, d, a.nslot + 1)) return false;   // fused merge
+    return qd_tier(a.g) != 256;
 }
 
 hipError_t launch_merge_apply(rmrcm_ctx* c, int d, int ct) {
@@ -1353,6 +1707,11 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d, bool part) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
     const int ncol = a.nslot + (part ? 1 : 0);
+    if (small_merge_ok(a, d, ncol)) {
+        hipLaunchKernelGGL(k_qd_small, dim3(a.nnodes), dim3(64 * small_waves(ncol)), small_lds_bytes(ncol, a.nslot),
+                           c->stream, a, ncol);
+        return hipGetLastError();
+    }
     hipError_t e = qd_factor_any(c, a);
     if (e != hipSuccess || d == 0) return e;     // the root has no boundary columns
     return qd_columns_any(c, a, 0, ncol, true, c->ct_tune[d]);
@@ -1392,6 +1751,30 @@ hipError_t launch_down(rmrcm_ctx* c, int d) {
     a.ghi = c->ghi;
     const size_t lds = sizeof(double) * (size_t)(P.nslot + 1);
     hipLaunchKernelGGL(k_down, dim3(P.nnodes, (P.xi + 3) / 4), dim3(256), lds, c->stream, a);
+    return hipGetLastError();
+}
+
+// The downward pass of every depth: one launch per depth while the
+// interfaces are long, then the remaining depths with interfaces of at most
+// kDownSubXi unknowns in one launch (k_down_sub), if their data vectors fit
+// LDS.
+static constexpr int kDownSubXi = 32;
+
+hipError_t launch_down_all(rmrcm_ctx* c) {
+    int ds = c->D;
+    while (ds > 0 && c->levels[ds - 1].xi <= kDownSubXi) --ds;
+    size_t lds = 0;
+    for (int d = ds; d < c->D; ++d)
+        lds = std::max(lds, (size_t)(c->levels[d].nnodes / c->levels[ds].nnodes) * (c->levels[d].nslot + 1) *
+                                sizeof(double));
+    if (ds == c->D || c->D - ds < 2 || lds > 48 * 1024 || !c->dlev) ds = c->D;
+    for (int d = 0; d < ds; ++d) {
+        hipError_t e = launch_down(c, d);
+        if (e != hipSuccess) return e;
+    }
+    if (ds == c->D) return hipSuccess;
+    hipLaunchKernelGGL(k_down_sub, dim3(c->levels[ds].nnodes), dim3(256), lds, c->stream,
+                       (const DownLevel*)c->dlev, ds, c->D, c->glo, c->ghi);
     return hipGetLastError();
 }
 

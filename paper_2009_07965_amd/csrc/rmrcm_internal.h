@@ -50,10 +50,11 @@ struct Level {
     int xi = 0;                // 2 g interface unknowns (one Robin datum per side)
     int* pmap = nullptr;       // [nslot] (child << 24) | child slot
     int* gmap = nullptr;       // [2][g] gamma -> child-1 slot, child-2 slot
+    int* gseg = nullptr;       // [nnodes][g] global segment of every gamma segment
     double* M = nullptr;       // [nnodes][4 g^2]: D^{-1}, E, S^{-1}, B of the merge
     double* X = nullptr;       // [nnodes][xi][ld] coefficients of every column
     double* work = nullptr;    // scratch of merges with 128 < g <= 256 (merge_work_doubles per node)
-    std::vector<int> h_pmap, h_gmap, h_slotseg;
+    std::vector<int> h_pmap, h_gmap, h_slotseg, h_gseg;
 };
 
 }  // namespace rmrcm
@@ -75,6 +76,7 @@ struct rmrcm_ctx {
     hipGraphExec_t gstep = nullptr;            // rmrcm_step graph (FP64 contexts)
     const void* gstep_key[5] = {};             // the pointers it was captured with
     int ct_tune[32] = {};         // per depth: column tile of the merge apply (0 = default)
+    unsigned char* dlev = nullptr;  // device table of the downward pass (one entry per depth < D)
     // device arrays
     double* K = nullptr;                     // [ny][nx]
     int8_t* bct = nullptr;                   // [2ny + 2nx]
@@ -148,6 +150,12 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int depth, bool part = false);
 size_t merge_work_doubles(const Level& L);
 hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
+// The downward pass of every depth (the deep, short-interface depths in one launch).
+hipError_t launch_down_all(rmrcm_ctx* c);
+// Device table of the downward pass: its size, and its contents (into
+// c->dlev, after the levels are allocated).
+size_t down_table_bytes(const rmrcm_ctx* c);
+hipError_t upload_down_levels(rmrcm_ctx* c);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
 hipError_t launch_interface_values(rmrcm_ctx* c);
 hipError_t launch_gauge(rmrcm_ctx* c);
