@@ -209,10 +209,11 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
 }
 
 // In-place inversion of the register-resident matrix m (block column w of
-// the wave).  cp: two column panels, pt: two 16 x 17 tiles for P.  Look-ahead:
-// in step K the owner of block column K + 1 updates its diagonal tile first
-// and forms P_{K+1} from it, then updates and publishes the rest of its
-// column, while the other waves finish step K.
+// the wave).  cp: two column panels, pt: two 16 x 17 tiles for P.  Step K,
+// two barriers: first every wave updates its block column with P_K (the
+// owner of block column K + 1 publishes it), then the owner of block column
+// K inverts the next pivot block, P_{K+1}, alone: run beside the other
+// waves' matrix-core updates the pivot chain takes more than twice as long.
 template <int GT>
 __device__ __forceinline__ void qd_publish(const v4d (&m)[QdM<GT>::T], double* c) {
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -239,6 +240,7 @@ __device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* pt, double*
     for (int K = 0; K < T; ++K) {
         const double* c = cp + (K & 1) * GT * CPL;
         const double* pk = pt + (K & 1) * 16 * 17;
+        double* cn = cp + ((K + 1) & 1) * GT * CPL;
         v4d P;
         double pa[4];
 #pragma unroll
@@ -256,6 +258,7 @@ __device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* pt, double*
                 m[I] = (I == K) ? P : acc;
             }
         } else {
+            // R_J = P M_KJ, M_IJ -= M_IK R_J (I != K), M_KJ = R_J
             v4d mk = m[0];
 #pragma unroll
             for (int I = 1; I < T; ++I)
@@ -263,41 +266,24 @@ __device__ void qd_gj_mfma(v4d (&m)[QdM<GT>::T], double* cp, double* pt, double*
             v4d R = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < 4; ++s) R = mfma_f64(pa[s], mk[s], R);
-            const bool la = w == K + 1;
-            double* cn = cp + ((K + 1) & 1) * GT * CPL;
-            if (la) {
-                // look-ahead: the next pivot block first, inverted at once, at a
-                // raised issue priority (every wave waits for it at the barrier)
-                v4d dt = m[0];
-#pragma unroll
-                for (int I = 1; I < T; ++I)
-                    if (I == K + 1) dt = m[I];
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    dt = mfma_f64(-c[(16 * (K + 1) + li) * CPL + 4 * s + lk], R[s], dt);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) cn[(16 * (K + 1) + lk + 4 * v) * CPL + li] = dt[v];
-                wave_lds_sync();
-                const v4d Pn = qd_pivot_inverse(cn, K + 1, lt, ls, bad);
-                double* pn = pt + ((K + 1) & 1) * 16 * 17;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) pn[(lk + 4 * v) * 17 + li] = Pn[v];
-#pragma unroll
-                for (int I = 0; I < T; ++I)
-                    if (I == K + 1) m[I] = dt;
-            }
 #pragma unroll
             for (int I = 0; I < T; ++I) {
                 if (I == K) {
                     m[I] = R;
                     continue;
                 }
-                if (la && I == K + 1) continue;
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
                     m[I] = mfma_f64(-c[(16 * I + li) * CPL + 4 * s + lk], R[s], m[I]);
             }
-            if (la) qd_publish<GT>(m, cn);
+            if (w == K + 1) qd_publish<GT>(m, cn);
+        }
+        __syncthreads();
+        if (w == K && K + 1 < T) {
+            const v4d Pn = qd_pivot_inverse(cn, K + 1, lt, ls, bad);
+            double* pn = pt + ((K + 1) & 1) * 16 * 17;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) pn[(lk + 4 * v) * 17 + li] = Pn[v];
         }
         __syncthreads();
     }
