@@ -246,10 +246,7 @@ int alloc_levels(rmrcm_ctx* c) {
     }
     // the root level keeps a trace buffer only when it is also the leaf level
     if (c->D == 0) TRY(dalloc(c, &c->levels[0].T, (size_t)c->levels[0].nslot * c->levels[0].ld));
-    if (c->D > 0) {
-        TRY(dalloc(c, &c->dlev, rmrcm::down_table_bytes(c)));
-        HIP_TRY(rmrcm::upload_down_levels(c));
-    }
+    TRY(rmrcm::build_down_sub(c));
     return RMRCM_OK;
 }
 
@@ -257,8 +254,8 @@ void free_all(rmrcm_ctx* c) {
     auto f = [](void* p) {
         if (p) (void)hipFree(p);
     };
-    f(c->dlev);
-    c->dlev = nullptr;
+    f(c->down_tab);
+    c->down_tab = nullptr;
     for (Level& L : c->levels) {
         f(L.T);
         f(L.slotseg);

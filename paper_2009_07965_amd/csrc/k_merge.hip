@@ -1094,7 +1094,24 @@ struct DownArgs {
 
 __global__ __launch_bounds__(256) void k_down(DownArgs a) {
     extern __shared__ double dvec[];   // nslot + 1
+    constexpr int EMAX = 12;           // X row entries per lane held in registers
     const int node = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int r = blockIdx.y * nw + wave;
+    const bool row = r < a.xi;
+    const int ix = node % a.nodes_x, iy = node / a.nodes_x;
+    const int c1 = a.cut == 0 ? iy * (2 * a.nodes_x) + 2 * ix : (2 * iy) * a.nodes_x + ix;
+    // loads that do not need the data vector, in flight during its gather:
+    // this wave's row of X and the segment its result goes to
+    const double* xr = a.X + ((size_t)node * a.xi + (row ? r : 0)) * a.ld;
+    double xv[EMAX];
+#pragma unroll
+    for (int u = 0; u < EMAX; ++u) {
+        const int q = u * 64 + lane;
+        xv[u] = (row && q < a.ld) ? xr[q] : 0.0;
+    }
+    int e = 0;
+    if (row && lane == 0) e = a.css[(size_t)c1 * a.cnslot + a.gmap[r % a.g]] >> 1;
     const int* ss = a.ss + (size_t)node * a.nslot;
     for (int s = threadIdx.x; s <= a.nslot; s += blockDim.x) {
         double v = 1.0;      // particular column
@@ -1105,30 +1122,18 @@ __global__ __launch_bounds__(256) void k_down(DownArgs a) {
         dvec[s] = v;
     }
     __syncthreads();
-    const int ix = node % a.nodes_x, iy = node / a.nodes_x;
-    const int c1 = a.cut == 0 ? iy * (2 * a.nodes_x) + 2 * ix : (2 * iy) * a.nodes_x + ix;
-    const int* ss1 = a.css + (size_t)c1 * a.cnslot;
-    const double* X = a.X + (size_t)node * a.xi * a.ld;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int r = blockIdx.y * nw + wave;
-    if (r >= a.xi) return;
-    double s = 0.0;
-    const double* xr = X + (size_t)r * a.ld;
-    for (int q0 = 0; q0 < a.ld; q0 += 256) {
-        double v[4];
+    if (!row) return;
+    double sum = 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = q0 + u * 64 + lane;
-            v[u] = q < a.ld ? xr[q] * dvec[q] : 0.0;
-        }
-        s += (v[0] + v[1]) + (v[2] + v[3]);
+    for (int u = 0; u < EMAX; ++u) {
+        const int q = u * 64 + lane;
+        if (q < a.ld) sum = fma(xv[u], dvec[q], sum);
     }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    for (int q = EMAX * 64 + lane; q < a.ld; q += 64) sum = fma(xr[q], dvec[q], sum);
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
     if (lane == 0) {
-        const int rr = r % a.g;
-        const int e = ss1[a.gmap[rr]] >> 1;
-        if (r < a.g) a.glo[e] = s;
-        else a.ghi[e] = s;
+        if (r < a.g) a.glo[e] = sum;
+        else a.ghi[e] = sum;
     }
 }
 
@@ -1488,87 +1493,133 @@ static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int n
     return hipGetLastError();
 }
 
-// Per-depth description of the downward pass (device table, one entry per
-// merge depth d < D: that depth's merges and the slots of their children).
+// One depth of the downward pass as k_down_sub takes it: that depth's merge
+// grid, gamma length, interface and slot counts, and X.
 struct DownLevel {
-    int nodes_x, nodes_y, g, xi, nslot, ld, cut, cnslot;
+    int nodes_x, nodes_y, g, xi, nslot, ld;
     const double* X;
-    const int* ss;      // node slot codes
-    const int* css;     // child slot codes
-    const int* gmap;
+};
+static constexpr int kDownSubMax = 6;     // depths per launch
+static constexpr int kDownZero = -1;      // source codes of data-vector entries
+static constexpr int kDownPart = -0x7fffffff;
+struct DownSubArgs {
+    DownLevel lv[kDownSubMax];
+    int toff[kDownSubMax], roff[kDownSubMax];
+    int n, entries, results;
+    const int* tab;     // [subtrees][entries]
+    double* glo;
+    double* ghi;
 };
 
-// The downward pass of depths d0 .. d1 - 1 (short interfaces) for the
-// subtree of one depth-d0 merge per workgroup.  A merge's gamma data depend
-// on its ancestors only, so the depths follow one another inside the
-// workgroup (barriers, no synchronisation between workgroups).  Per depth:
-// the data vector of every merge of the subtree (Robin data of its slots, 1
-// for the particular column) to LDS, then every (merge, gamma row) pair as
-// one thread's dot product with that row of X, written to the datum of the
-// row's side of its segment.
-__global__ __launch_bounds__(256) void k_down_sub(const DownLevel* __restrict__ L, int d0, int d1,
-                                                  double* __restrict__ glo, double* __restrict__ ghi) {
-    extern __shared__ double dvec[];
-    const int tid = threadIdx.x;
-    const int rx0 = L[d0].nodes_x, ry0 = L[d0].nodes_y;
+// The downward pass of n consecutive depths with short interfaces for the
+// subtree of one merge of the first of them per workgroup.  A merge's gamma
+// data depend on its ancestors only, so the depths follow one another inside
+// the workgroup, and the data an ancestor in the subtree produced are taken
+// from LDS: a table built at setup gives every entry of every depth's data
+// vectors its source (an earlier depth's result in LDS, the subtree
+// boundary's Robin datum in global memory, zero on the domain boundary, 1
+// for the particular column) and every result its segment.  Every global
+// load is issued at the start: the table, the boundary data and, for every
+// depth, this lane's entries of its row of X (each (merge, gamma row) pair of
+// a depth is one group of lpr consecutive lanes, each lane holding every
+// lpr-th entry of the row).  Then per depth the LDS-sourced entries are
+// copied, the partial dot products summed across each group, and the results
+// written to LDS and to the Robin datum of the row's side of its segment.
+static constexpr int kDownSubThreads = 512;
+static constexpr int kDownSubEntries = 12;   // X row entries per lane and depth held in registers
+
+__global__ __launch_bounds__(kDownSubThreads) void k_down_sub(DownSubArgs A) {
+    extern __shared__ double sm[];
+    constexpr int EMAX = kDownSubEntries;
+    double* dall = sm;                 // [entries] data vectors of every depth
+    double* res = dall + A.entries;    // [results] gamma data of every depth
+    int* src = (int*)(res + A.results);
+    int* dst = src + A.entries;        // [results] segment of every result
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int rx0 = A.lv[0].nodes_x, ry0 = A.lv[0].nodes_y;
     const int ix0 = blockIdx.x % rx0, iy0 = blockIdx.x / rx0;
-    for (int d = d0; d < d1; ++d) {
-        const DownLevel a = L[d];
-        const int fx = a.nodes_x / rx0, fy = a.nodes_y / ry0;   // the subtree at depth d: fx x fy merges
-        const int nsub = fx * fy, w = a.nslot + 1;
-        auto node_of = [&](int k) { return (iy0 * fy + k / fx) * a.nodes_x + ix0 * fx + k % fx; };
-        for (int t = tid; t < nsub * w; t += blockDim.x) {
-            const int k = t / w, sl = t % w;
-            double v = 1.0;
-            if (sl < a.nslot) {
-                const int code = a.ss[(size_t)node_of(k) * a.nslot + sl];
-                v = code < 0 ? 0.0 : ((code & 1) ? glo[code >> 1] : ghi[code >> 1]);
+    const int* tab = A.tab + (size_t)blockIdx.x * (A.entries + A.results);
+    // this lane's group at depth l: lanes per row, lane in the row, merge, row
+    auto lanes = [&](int l, int& lpr, int& j, int& k, int& r, bool& act) {
+        const DownLevel a = A.lv[l];
+        const int R = (a.nodes_x / rx0) * (a.nodes_y / ry0) * a.xi;
+        lpr = 64;
+        while (lpr > 1 && lpr * R > nt) lpr >>= 1;
+        const int p = tid / lpr;
+        j = tid % lpr;
+        act = p < R;
+        k = act ? p / a.xi : 0;
+        r = act ? p % a.xi : 0;
+    };
+    auto row_ptr = [&](int l, int k, int r) {
+        const DownLevel a = A.lv[l];
+        const int fx = a.nodes_x / rx0, fy = a.nodes_y / ry0;
+        const int node = (iy0 * fy + k / fx) * a.nodes_x + ix0 * fx + k % fx;
+        return a.X + ((size_t)node * a.xi + r) * a.ld;
+    };
+    double xv[kDownSubMax][EMAX];
+#pragma unroll
+    for (int l = 0; l < kDownSubMax; ++l) {
+        if (l < A.n) {
+            int lpr, j, k, r;
+            bool act;
+            lanes(l, lpr, j, k, r, act);
+            const double* xr = row_ptr(l, k, r);
+            const int ld = A.lv[l].ld;
+#pragma unroll
+            for (int u = 0; u < EMAX; ++u) {
+                const int q = j + u * lpr;
+                xv[l][u] = (act && q < ld) ? xr[q] : 0.0;
             }
-            dvec[t] = v;
+        }
+    }
+    for (int t = tid; t < A.entries; t += nt) {
+        const int sc = tab[t];
+        double v = 0.0;
+        if (sc == kDownPart) v = 1.0;
+        else if (sc <= -2) {
+            const int code = -2 - sc;
+            v = (code & 1) ? A.glo[code >> 1] : A.ghi[code >> 1];
+        }
+        src[t] = sc;
+        dall[t] = v;
+    }
+    for (int t = tid; t < A.results; t += nt) dst[t] = tab[A.entries + t];
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < kDownSubMax; ++l) {
+        if (l >= A.n) break;
+        const DownLevel a = A.lv[l];
+        const int w = a.nslot + 1, ne = (a.nodes_x / rx0) * (a.nodes_y / ry0) * w;
+        for (int t = A.toff[l] + tid; t < A.toff[l] + ne; t += nt) {
+            const int sc = src[t];
+            if (sc >= 0) dall[t] = res[sc];
         }
         __syncthreads();
-        for (int p = tid; p < nsub * a.xi; p += blockDim.x) {
-            const int k = p / a.xi, r = p % a.xi;
-            const int node = node_of(k);
-            const int ix = node % a.nodes_x, iy = node / a.nodes_x;
-            const int c1 = a.cut == 0 ? iy * (2 * a.nodes_x) + 2 * ix : (2 * iy) * a.nodes_x + ix;
-            const double* xr = a.X + ((size_t)node * a.xi + r) * a.ld;
-            const double* dv = dvec + (size_t)k * w;
-            double s = 0.0;
-#pragma unroll 8
-            for (int q = 0; q < a.ld; ++q) s = fma(xr[q], dv[q], s);
-            const int e = a.css[(size_t)c1 * a.cnslot + a.gmap[r % a.g]] >> 1;
-            if (r < a.g) glo[e] = s;
-            else ghi[e] = s;
+        int lpr, j, k, r;
+        bool act;
+        lanes(l, lpr, j, k, r, act);
+        const double* dv = dall + A.toff[l] + (size_t)k * w;
+        double sum = 0.0;
+#pragma unroll
+        for (int u = 0; u < EMAX; ++u) {
+            const int q = j + u * lpr;
+            if (act && q < a.ld) sum = fma(xv[l][u], dv[q], sum);
+        }
+        if (act && j + EMAX * lpr < a.ld) {
+            const double* xr = row_ptr(l, k, r);
+            for (int q = j + EMAX * lpr; q < a.ld; q += lpr) sum = fma(xr[q], dv[q], sum);
+        }
+        for (int off = lpr >> 1; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+        if (act && j == 0) {
+            const int o = A.roff[l] + k * a.xi + r;
+            res[o] = sum;
+            if (r < a.g) A.glo[dst[o]] = sum;
+            else A.ghi[dst[o]] = sum;
         }
         __syncthreads();
     }
 }
-
-hipError_t upload_down_levels(rmrcm_ctx* c) {
-    if (c->D == 0) return hipSuccess;
-    std::vector<DownLevel> h((size_t)c->D);
-    for (int d = 0; d < c->D; ++d) {
-        const Level& P = c->levels[d];
-        const Level& C = c->levels[d + 1];
-        DownLevel& a = h[(size_t)d];
-        a.nodes_x = P.nodes_x;
-        a.nodes_y = P.nodes_y;
-        a.g = P.g;
-        a.xi = P.xi;
-        a.nslot = P.nslot;
-        a.ld = P.ld;
-        a.cut = P.cut;
-        a.cnslot = C.nslot;
-        a.X = P.X;
-        a.ss = P.slotseg;
-        a.css = C.slotseg;
-        a.gmap = P.gmap;
-    }
-    return hipMemcpy(c->dlev, h.data(), h.size() * sizeof(DownLevel), hipMemcpyHostToDevice);
-}
-
-size_t down_table_bytes(const rmrcm_ctx* c) { return (size_t)c->D * sizeof(DownLevel); }
 
 static MergeArgs make_args(rmrcm_ctx* c, int d) {
     Level& P = c->levels[d];
@@ -1741,26 +1792,147 @@ hipError_t launch_down(rmrcm_ctx* c, int d) {
 }
 
 // The downward pass of every depth: one launch per depth while the
-// interfaces are long, then the remaining depths with interfaces of at most
-// kDownSubXi unknowns in one launch (k_down_sub), if their data vectors fit
-// LDS.
+// interfaces are long, then up to kDownSubMax remaining depths with
+// interfaces of at most kDownSubXi unknowns in one launch (k_down_sub), if
+// every depth's rows fit the workgroup and the data vectors, results and
+// source table fit LDS.  Sources: the writer of every (segment, side) datum
+// among the fused depths is found by the same rule k_down_sub applies.
 static constexpr int kDownSubXi = 32;
 
+int build_down_sub(rmrcm_ctx* c) {
+    const int D = c->D;
+    c->down_ds = D;
+    int ds = D;
+    while (ds > 0 && D - ds < kDownSubMax && c->levels[ds - 1].xi <= kDownSubXi) --ds;
+    if (D - ds < 2) return RMRCM_OK;
+    const int n = D - ds, NS = c->levels[ds].nnodes;
+    const int rx0 = c->levels[ds].nodes_x, ry0 = c->levels[ds].nodes_y;
+    int E = 0, RT = 0;
+    int toff[kDownSubMax], roff[kDownSubMax];
+    for (int l = 0; l < n; ++l) {
+        const Level& P = c->levels[ds + l];
+        const int nsub = P.nnodes / NS;
+        if (nsub * P.xi > kDownSubThreads) return RMRCM_OK;
+        toff[l] = E;
+        roff[l] = RT;
+        E += nsub * (P.nslot + 1);
+        RT += nsub * P.xi;
+    }
+    if ((size_t)(E + RT) * 12 > 48 * 1024) return RMRCM_OK;
+    // writer of every (segment, side) datum: depth l, global node, row
+    struct W {
+        int l, node, r;
+    };
+    std::vector<std::pair<long long, W>> writers;
+    for (int l = 0; l < n; ++l) {
+        const Level& P = c->levels[ds + l];
+        const Level& C = c->levels[ds + l + 1];
+        for (int m = 0; m < P.nnodes; ++m) {
+            const int ix = m % P.nodes_x, iy = m / P.nodes_x;
+            const int c1 = P.cut == 0 ? iy * (2 * P.nodes_x) + 2 * ix : (2 * iy) * P.nodes_x + ix;
+            for (int r = 0; r < P.xi; ++r) {
+                const int e = C.h_slotseg[(size_t)c1 * C.nslot + P.h_gmap[r % P.g]] >> 1;
+                writers.push_back({2LL * e + (r < P.g ? 1 : 0), W{l, m, r}});
+            }
+        }
+    }
+    std::sort(writers.begin(), writers.end(),
+              [](const std::pair<long long, W>& x, const std::pair<long long, W>& y) { return x.first < y.first; });
+    auto find = [&](long long key) -> const W* {
+        auto it = std::lower_bound(writers.begin(), writers.end(), key,
+                                   [](const std::pair<long long, W>& x, long long k) { return x.first < k; });
+        return (it != writers.end() && it->first == key) ? &it->second : nullptr;
+    };
+    const size_t TW = (size_t)E + RT;      // per subtree: sources, then result segments
+    std::vector<int> tab((size_t)NS * TW);
+    for (int st = 0; st < NS; ++st) {
+        const int ix0 = st % rx0, iy0 = st / rx0;
+        for (int l = 0; l < n; ++l) {
+            const Level& P = c->levels[ds + l];
+            const int fx = P.nodes_x / rx0, fy = P.nodes_y / ry0, w = P.nslot + 1;
+            for (int kk = 0; kk < fx * fy; ++kk) {
+                const int nd = (iy0 * fy + kk / fx) * P.nodes_x + ix0 * fx + kk % fx;
+                for (int sl = 0; sl < w; ++sl) {
+                    int sc;
+                    if (sl == P.nslot) {
+                        sc = kDownPart;
+                    } else {
+                        const int code = P.h_slotseg[(size_t)nd * P.nslot + sl];
+                        if (code < 0) {
+                            sc = kDownZero;
+                        } else {
+                            sc = -2 - code;
+                            const W* wr = find(2LL * (code >> 1) + (code & 1));
+                            if (wr && wr->l < l) {
+                                const Level& Q = c->levels[ds + wr->l];
+                                const int qx = Q.nodes_x / rx0, qy = Q.nodes_y / ry0;
+                                const int mx = wr->node % Q.nodes_x - ix0 * qx, my = wr->node / Q.nodes_x - iy0 * qy;
+                                if (mx >= 0 && mx < qx && my >= 0 && my < qy)
+                                    sc = roff[wr->l] + (my * qx + mx) * Q.xi + wr->r;
+                            }
+                        }
+                    }
+                    tab[(size_t)st * TW + toff[l] + kk * w + sl] = sc;
+                }
+            }
+            // the segment of every result (row r of merge kk)
+            const Level& C = c->levels[ds + l + 1];
+            for (int kk = 0; kk < fx * fy; ++kk) {
+                const int ix = ix0 * fx + kk % fx, iy = iy0 * fy + kk / fx;
+                const int c1 = P.cut == 0 ? iy * (2 * P.nodes_x) + 2 * ix : (2 * iy) * P.nodes_x + ix;
+                for (int r = 0; r < P.xi; ++r)
+                    tab[(size_t)st * TW + E + roff[l] + kk * P.xi + r] =
+                        C.h_slotseg[(size_t)c1 * C.nslot + P.h_gmap[r % P.g]] >> 1;
+            }
+        }
+    }
+    if (hipMalloc(&c->down_tab, tab.size() * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->down_tab = nullptr;
+        return RMRCM_ENOMEM;
+    }
+    c->device_bytes += tab.size() * sizeof(int);
+    if (hipMemcpy(c->down_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
+        return RMRCM_EDEVICE;
+    c->down_ds = ds;
+    c->down_entries = E;
+    c->down_results = RT;
+    for (int l = 0; l < n; ++l) {
+        c->down_toff[l] = toff[l];
+        c->down_roff[l] = roff[l];
+    }
+    return RMRCM_OK;
+}
+
 hipError_t launch_down_all(rmrcm_ctx* c) {
-    int ds = c->D;
-    while (ds > 0 && c->levels[ds - 1].xi <= kDownSubXi) --ds;
-    size_t lds = 0;
-    for (int d = ds; d < c->D; ++d)
-        lds = std::max(lds, (size_t)(c->levels[d].nnodes / c->levels[ds].nnodes) * (c->levels[d].nslot + 1) *
-                                sizeof(double));
-    if (ds == c->D || c->D - ds < 2 || lds > 48 * 1024 || !c->dlev) ds = c->D;
+    const int ds = c->down_ds;
     for (int d = 0; d < ds; ++d) {
         hipError_t e = launch_down(c, d);
         if (e != hipSuccess) return e;
     }
     if (ds == c->D) return hipSuccess;
-    hipLaunchKernelGGL(k_down_sub, dim3(c->levels[ds].nnodes), dim3(256), lds, c->stream,
-                       (const DownLevel*)c->dlev, ds, c->D, c->glo, c->ghi);
+    DownSubArgs A;
+    A.n = c->D - ds;
+    A.entries = c->down_entries;
+    A.results = c->down_results;
+    A.tab = c->down_tab;
+    A.glo = c->glo;
+    A.ghi = c->ghi;
+    for (int l = 0; l < A.n; ++l) {
+        const Level& P = c->levels[ds + l];
+        DownLevel& a = A.lv[l];
+        a.nodes_x = P.nodes_x;
+        a.nodes_y = P.nodes_y;
+        a.g = P.g;
+        a.xi = P.xi;
+        a.nslot = P.nslot;
+        a.ld = P.ld;
+        a.X = P.X;
+        A.toff[l] = c->down_toff[l];
+        A.roff[l] = c->down_roff[l];
+    }
+    const size_t lds = (size_t)(A.entries + A.results) * (sizeof(double) + sizeof(int));
+    hipLaunchKernelGGL(k_down_sub, dim3(c->levels[ds].nnodes), dim3(kDownSubThreads), lds, c->stream, A);
     return hipGetLastError();
 }
 

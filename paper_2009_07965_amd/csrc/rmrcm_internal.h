@@ -76,7 +76,12 @@ struct rmrcm_ctx {
     hipGraphExec_t gstep = nullptr;            // rmrcm_step graph (FP64 contexts)
     const void* gstep_key[5] = {};             // the pointers it was captured with
     int ct_tune[32] = {};         // per depth: column tile of the merge apply (0 = default)
-    unsigned char* dlev = nullptr;  // device table of the downward pass (one entry per depth < D)
+    // downward pass of the deepest short-interface depths in one launch
+    // (built by build_down_sub; down_ds == D: none)
+    int down_ds = 0;
+    int* down_tab = nullptr;      // [subtrees][entries] source of every data-vector entry
+    int down_entries = 0, down_results = 0;
+    int down_toff[8] = {}, down_roff[8] = {};
     // device arrays
     double* K = nullptr;                     // [ny][nx]
     int8_t* bct = nullptr;                   // [2ny + 2nx]
@@ -152,10 +157,9 @@ hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
 // The downward pass of every depth (the deep, short-interface depths in one launch).
 hipError_t launch_down_all(rmrcm_ctx* c);
-// Device table of the downward pass: its size, and its contents (into
-// c->dlev, after the levels are allocated).
-size_t down_table_bytes(const rmrcm_ctx* c);
-hipError_t upload_down_levels(rmrcm_ctx* c);
+// Chooses the depths of that launch and uploads its source table (after
+// the levels are allocated); RMRCM_* code.
+int build_down_sub(rmrcm_ctx* c);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
 hipError_t launch_interface_values(rmrcm_ctx* c);
 hipError_t launch_gauge(rmrcm_ctx* c);
