@@ -328,6 +328,11 @@ template <int GT>
 __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int phase) {
     typedef QdM<GT> Q;
     constexpr int T = Q::T, CPL = Q::CPL;
+    // up to 64 segments the products between the inversions take D^{-1} and
+    // B from LDS and B, N, E from registers (beyond, from global memory)
+    constexpr bool LP = GT <= 64;
+    constexpr int DLD = GT + 1;
+    __shared__ double DL[LP ? GT * DLD : 1], BL[LP ? GT * DLD : 1];
     __shared__ double cp[2 * GT * CPL];
     __shared__ double lts[2 * T * 16 * Q::LTL];
     __shared__ double pt[2 * 16 * 17];
@@ -340,12 +345,11 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int
     children(a, node, &c1, &c2);
     const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
     const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
-    const int* ss1 = a.css + (size_t)c1 * a.cnslot;
     if (tid == 0) bad = 0;
     for (int t = tid; t < g; t += Q::NT) {
         gi1[t] = a.gmap[t];
         gi2[t] = a.gmap[g + t];
-        const int e = ss1[gi1[t]] >> 1;
+        const int e = a.gseg[(size_t)node * g + t];
         wv[t] = a.seglen[e] / (2.0 * a.beta[e]);
     }
     __syncthreads();
@@ -358,6 +362,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int
     double* ls = lt + 16 * Q::LTL;
     const int j = 16 * w + li;                   // the column this lane holds
     v4d m[T];
+    v4d Bm[LP ? T : 1], Nm[LP ? T : 1];
     if (phase == 2) {
         // S (identity outside g x g)
 #pragma unroll
@@ -389,12 +394,17 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * (I0 + u) + lk + 4 * v;
                 const double nv = t1[u][v] + t2[u][v];
-                if (i < g && j < g) {
+                const bool in = i < g && j < g;
+                if (in) {
                     Bg[(size_t)i * g + j] = t2[u][v] - t1[u][v];
-                    Sg[(size_t)i * g + j] = nv;         // N, parked until the Schur step
+                    if (!LP) Sg[(size_t)i * g + j] = nv;         // N, parked until the Schur step
                     m[I0 + u][v] = nv + (i == j ? 4.0 * wv[i] : 0.0);
                 } else {
                     m[I0 + u][v] = (i == j) ? 1.0 : 0.0;
+                }
+                if constexpr (LP) {
+                    Bm[I0 + u][v] = in ? t2[u][v] - t1[u][v] : 0.0;
+                    Nm[I0 + u][v] = in ? nv : (i == j ? 1.0 : 0.0);
                 }
             }
     }
@@ -404,6 +414,42 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int
         if (tid == 0 && bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
         return;
     }
+    if constexpr (LP) {
+        // D^{-1} and B to LDS, then E = D^{-1} B and S = N - B E for block
+        // column w (B_KJ, N_IJ and E_KJ the wave's own tiles)
+#pragma unroll
+        for (int I = 0; I < T; ++I)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * I + lk + 4 * v;
+                DL[i * DLD + j] = m[I][v];
+                BL[i * DLD + j] = Bm[I][v];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int K = 0; K < T; ++K)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc = mfma_f64(DL[(16 * I + li) * DLD + 16 * K + 4 * s + lk], Bm[K][s], acc);
+            m[I] = acc;
+        }
+        qd_store<GT>(m, g, Eg, false);
+#pragma unroll
+        for (int I = 0; I < T; ++I) {
+            v4d acc = Nm[I];
+#pragma unroll
+            for (int K = 0; K < T; ++K)
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc = mfma_f64(-BL[(16 * I + li) * DLD + 16 * K + 4 * s + lk], m[K][s], acc);
+            Bm[I] = acc;
+        }
+#pragma unroll
+        for (int I = 0; I < T; ++I) m[I] = Bm[I];
+    } else {
     __syncthreads();                                       // D^{-1}, B, N visible to the workgroup
     // E = D^{-1} B (block column w): block column K of D^{-1} staged in LDS
     // (the next one in flight meanwhile), B_KJ from global memory
@@ -471,6 +517,7 @@ __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int
         }
 #pragma unroll
         for (int I = 0; I < T; ++I) m[I] = acc[I];
+    }
     }
     }
     if (a.pin) {
