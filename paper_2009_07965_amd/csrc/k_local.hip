@@ -275,9 +275,11 @@ __device__ inline float readlane_s(float v, int l) {
 __device__ inline double inv_sqrt(double d) { return 1.0 / sqrt(d); }
 __device__ inline float inv_sqrt(float d) { return 1.0f / sqrtf(d); }
 
-// 1/sqrt(d) for d > 0: the hardware estimate refined by Newton-Raphson steps
-// on f(y) = y^-2 - d, i.e. y <- y + (y / 2)(1 - d y^2), each step roughly
-// doubling the correct bits (two in FP64, one in FP32).
+// 1/sqrt(d) for d > 0: the hardware estimate (relative error below 2^-24 on
+// this part) refined by Newton-Raphson steps on f(y) = y^-2 - d,
+// y <- y + (y / 2)(1 - d y^2), each squaring the error: two in FP64 (one
+// leaves a one-sided error near 2^-48 in every pivot, which problems with
+// one-face segments amplify a hundredfold), one in FP32.
 __device__ inline double rsqrt_nr(double d) {
     double y = __builtin_amdgcn_rsq(d);
     y = fma(0.5 * y, fma(-d * y, y, 1.0), y);
@@ -617,11 +619,10 @@ __device__ __forceinline__ void chol_invert(S (&a)[BX], S* Wb, bool scol, int c,
     for (int kb = 0; kb < BX; kb += NB) {
 #pragma unroll
         for (int k = kb; k < kb + NB; ++k) {
-            S d = readlane_s(a[k], k);
-            if (!(d > S(0))) {
-                sing = 1;
-                d = S(1);
-            }
+            // a pivot that is not positive is flagged (the factor is then
+            // not used); the test stays off the pivot chain
+            const S d = readlane_s(a[k], k);
+            sing |= !(d > S(0));
             a[k] *= rsqrt_nr(d);
 #pragma unroll
             for (int i = k + 1; i < kb + NB; ++i) a[i] = fma(-readlane_s(a[k], i), a[k], a[i]);
