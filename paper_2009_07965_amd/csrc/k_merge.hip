@@ -735,6 +735,163 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
     }
 }
 
+// Column apply and parent traces of one 16-column tile of a merge in
+// workgroups of eight waves, for interfaces of 32 and 64 segments (as two
+// launches, each is bound by its own load latency and the traces wait for X
+// to reach memory).  The first waves apply the factorisation as
+// k_qd_apply_mfma does; X stays in LDS for the traces, whose row tiles the
+// gridDim.z workgroups of the tile share (each repeats the apply, the first
+// writes X), eight waves each.  The trace operands (the child trace rows
+// against gamma and the direct terms) of a wave's first row tile are loaded
+// before the apply, those of its next row tile while the current one's
+// products run.
+template <int GT>
+__global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int ncol) {
+    constexpr int CT = 16, AL = CT + 1, NT = 512, NW = NT / 64, KS = GT / 4;
+    __shared__ double rs[GT * AL], rd[GT * AL], tt[GT * AL];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int node = blockIdx.x, g = a.g, nslot = a.nslot;
+    const int cb = col0 + blockIdx.y * CT;
+    const int nc = min(CT, col0 + ncol - cb);
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* T1 = a.Tc + (size_t)c1 * a.cnslot * a.cld;
+    const double* T2 = a.Tc + (size_t)c2 * a.cnslot * a.cld;
+    const int* g1 = a.gmap;
+    const int* g2 = a.gmap + g;
+    const size_t gg = (size_t)g * g;
+    const double* Dg = a.M + (size_t)node * 4 * gg;
+    const double* Eg = Dg + gg;
+    const double* Sg = Eg + gg;
+    const double* Bg = Sg + gg;
+    // trace operands: this lane's column, gamma columns of both children,
+    // and a row tile's child trace rows and direct terms
+    const int col = cb + li;
+    const bool cin = li < nc;
+    const int pc = (cin && col < nslot) ? a.pmap[col] : -1;
+    const int nrt = (nslot + 15) / 16, ot0 = w + NW * blockIdx.z, ots = NW * gridDim.z;
+    int gm[2][KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        const int i = 4 * q + lk;
+        gm[0][q] = i < g ? g1[i] : 0;
+        gm[1][q] = i < g ? g2[i] : 0;
+    }
+    auto load_rows = [&](int ot, double (&av)[KS], double (&dr)[4], int& ka) {
+        const int oa = 16 * ot + li;
+        const int pa = (ot < nrt && oa < nslot) ? a.pmap[oa] : -1;
+        ka = pa >= 0 ? (pa >> 24) : -1;
+        const double* ta = (ka == 1 ? T2 : T1) + (size_t)(pa >= 0 ? (pa & 0xffffff) : 0) * a.cld;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+            const int i = 4 * q + lk;
+            av[q] = (ka >= 0 && i < g) ? ta[ka == 1 ? gm[1][q] : gm[0][q]] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 16 * ot + lk + 4 * v;
+            double d = 0.0;
+            if (ot < nrt && o < nslot && cin) {
+                const int pm = a.pmap[o], k = pm >> 24;
+                const double* tr = (k ? T2 : T1) + (size_t)(pm & 0xffffff) * a.cld;
+                if (col == nslot) d = tr[a.cld - 1];
+                else if ((pc >> 24) == k) d = tr[pc & 0xffffff];
+            }
+            dr[v] = d;
+        }
+    };
+    double av0[KS], dr0[4];
+    int ka0;
+    load_rows(ot0, av0, dr0, ka0);
+    // ---- the apply (k_qd_apply_mfma with one column tile)
+    double av[GT / 4], an[GT / 4];
+    qd_load_tile<GT>(g, Dg, av);
+    qd_load_tile<GT>(g, Bg, an);
+    for (int t0 = 0; t0 < GT * CT; t0 += 4 * NT) {
+        double v1[4], v2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NT + tid;
+            const int i = t / CT, cc = t % CT, cl = cb + cc;
+            v1[u] = 0.0;
+            v2[u] = 0.0;
+            if (t < GT * CT && cc < nc && i < g) {
+                if (cl == nslot) {
+                    v1[u] = T1[(size_t)g1[i] * a.cld + a.cld - 1];
+                    v2[u] = T2[(size_t)g2[i] * a.cld + a.cld - 1];
+                } else {
+                    const int pm = a.pmap[cl], off = pm & 0xffffff;
+                    if ((pm >> 24) == 0) v1[u] = T1[(size_t)g1[i] * a.cld + off];
+                    else v2[u] = T2[(size_t)g2[i] * a.cld + off];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int t = t0 + u * NT + tid;
+            if (t < GT * CT) {
+                const int e = (t / CT) * AL + t % CT;
+                rs[e] = v1[u] + v2[u];
+                rd[e] = v2[u] - v1[u];
+            }
+        }
+    }
+    __syncthreads();
+    qd_prod_mfma<GT, 1>(av, rd, tt, false);       // t = D^{-1} (r2 - r1)
+#pragma unroll
+    for (int q = 0; q < GT / 4; ++q) av[q] = an[q];
+    qd_load_tile<GT>(g, Sg, an);
+    qd_prod_mfma<GT, 1>(av, tt, rs, true);        // u = r1 + r2 - B t
+#pragma unroll
+    for (int q = 0; q < GT / 4; ++q) av[q] = an[q];
+    qd_load_tile<GT>(g, Eg, an);
+    qd_prod_mfma<GT, 1>(av, rs, rd, false);       // s = S^{-1} u
+    qd_prod_mfma<GT, 1>(an, rd, tt, true);        // d = t - E s
+    double* X = a.X + (size_t)node * a.xi * a.ld;
+    if (blockIdx.z == 0) {
+        for (int t = tid; t < g * CT; t += NT) {
+            const int i = t / CT, cc = t % CT;
+            if (cc >= nc) continue;
+            const double sv = rd[i * AL + cc], dv = tt[i * AL + cc];
+            X[(size_t)i * a.ld + cb + cc] = -(sv - dv);
+            X[(size_t)(g + i) * a.ld + cb + cc] = -(sv + dv);
+        }
+    }
+    // ---- parent traces of the tile: T_p[o, col] = direct + A_k(o) X_k[:, col]
+    double xb[2][KS];
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+        const int i = 4 * q + lk;
+        const double sv = rd[i * AL + li], dv = tt[i * AL + li];
+        const bool in = i < g && cin;
+        xb[0][q] = in ? -(sv - dv) : 0.0;
+        xb[1][q] = in ? -(sv + dv) : 0.0;
+    }
+    double* Tp = a.Tp + (size_t)node * nslot * a.ld;
+    for (int ot = ot0; ot < nrt; ot += ots) {
+        double av1[KS] = {}, dr1[4] = {};
+        int ka1 = -1;
+        if (ot + ots < nrt) load_rows(ot + ots, av1, dr1, ka1);
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 0 ? av0[q] : 0.0, xb[0][q], acc);
+#pragma unroll
+        for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 1 ? av0[q] : 0.0, xb[1][q], acc);
+        if (cin) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 16 * ot + lk + 4 * v;
+                if (o < nslot) Tp[(size_t)o * a.ld + col] = dr0[v] + acc[v];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KS; ++q) av0[q] = av1[q];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dr0[v] = dr1[v];
+        ka0 = ka1;
+    }
+}
+
 // The particular column alone (the top's, where one merge is one workgroup)
 // as matrix-vector products on the vector units: the same four products as
 // k_qd_apply_mfma, t = D^{-1} (r2 - r1), u = r1 + r2 - B t, s = S^{-1} u,
@@ -838,6 +995,21 @@ __global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, in
     const int ka = pa >= 0 ? (pa >> 24) : -1;
     const double* ta = pa >= 0 ? Tk[ka] + (size_t)(pa & 0xffffff) * a.cld : nullptr;
     const int col = cb + li;
+    // the direct terms of this lane's outputs, loaded with the operands
+    const int pc = col < a.nslot ? a.pmap[col] : -1;
+    double dr[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int o = o0 + lk + 4 * v;
+        double d = 0.0;
+        if (o < a.nslot && col < ce) {
+            const int pm = a.pmap[o], k = pm >> 24;
+            const double* tr = Tk[k] + (size_t)(pm & 0xffffff) * a.cld;
+            if (col == a.nslot) d = tr[a.cld - 1];
+            else if ((pc >> 24) == k) d = tr[pc & 0xffffff];
+        }
+        dr[v] = d;
+    }
     v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -852,17 +1024,11 @@ __global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, in
         for (int q = 0; q < KS; ++q) acc = mfma_f64(av[q], bv[q], acc);
     }
     if (col >= ce) return;
-    const int pc = col < a.nslot ? a.pmap[col] : -1;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int o = o0 + lk + 4 * v;
         if (o >= a.nslot) continue;
-        const int pm = a.pmap[o], k = pm >> 24;
-        const double* tr = Tk[k] + (size_t)(pm & 0xffffff) * a.cld;
-        double d;
-        if (col == a.nslot) d = tr[a.cld - 1];
-        else d = (pc >> 24) == k ? tr[pc & 0xffffff] : 0.0;
-        a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = d + acc[v];
+        a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = dr[v] + acc[v];
     }
 }
 
@@ -1717,8 +1883,22 @@ static hipError_t qd_apply(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol,
     return hipGetLastError();
 }
 
+// Levels whose column apply and parent traces run fused (k_qd_cols_mfma).
+static bool cols_fused(const MergeArgs& a, bool trace) {
+    return trace && a.g > 16 && a.g <= 64 && a.nslot <= 512;
+}
+
 template <int GT>
 static hipError_t qd_columns(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol, bool trace, int ct) {
+    if constexpr (GT == 32 || GT == 64) {
+        if (cols_fused(a, trace)) {
+            // at most one row tile per wave (up to four workgroups per tile)
+            const int z = std::min(4, ((a.nslot + 15) / 16 + 7) / 8);
+            hipLaunchKernelGGL(k_qd_cols_mfma<GT>, dim3(a.nnodes, (ncol + 15) / 16, std::max(z, 1)), dim3(512), 0,
+                               c->stream, a, col0, ncol);
+            return hipGetLastError();
+        }
+    }
     hipError_t e = qd_apply<GT>(c, a, col0, ncol, ct);
     if (e != hipSuccess) return e;
     if (trace)
@@ -1774,6 +1954,7 @@ bool merge_apply_tunable(rmrcm_ctx* c, int d) {
     if (!(d > 0 && d < c->D)) return false;
     const MergeArgs a = make_args(c, d);
     if (small_merge_ok(a, d, a.nslot) || small_merge_ok(a, d, a.nslot + 1)) return false;   // fused merge
+    if (cols_fused(a, true)) return false;                                                    // fused columns
     return qd_tier(a.g) != 256;
 }
 
