@@ -418,8 +418,7 @@ bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c); 
 int enqueue_setup(rmrcm_ctx* c) {
     TRY(mark(c, 0));
     HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
-    HIP_TRY(rmrcm::launch_check_perm(c));
-    HIP_TRY(rmrcm::launch_beta(c));
+    HIP_TRY(rmrcm::launch_check_beta(c, nullptr));
     TRY(mark(c, 1));
     if (mixed(c)) {
         TRY(mixed_local_setup(c));
@@ -552,8 +551,7 @@ int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
     // particular solves)
     TRY(mark(c, 0));
     HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
-    HIP_TRY(rmrcm::launch_check_perm(c, kcopy));
-    HIP_TRY(rmrcm::launch_beta(c));
+    HIP_TRY(rmrcm::launch_check_beta(c, kcopy));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_compat_check(c));
     TRY(mark(c, 1));
     if (rmrcm::local_setup_solves_particular(c, false)) {

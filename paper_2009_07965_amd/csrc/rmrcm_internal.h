@@ -136,6 +136,8 @@ namespace rmrcm {
 hipError_t launch_beta(rmrcm_ctx* c);
 // copy non-null: the permeability is also copied there in the same pass.
 hipError_t launch_check_perm(rmrcm_ctx* c, double* copy = nullptr);
+// The permeability check and the segment Robin parameters in one launch.
+hipError_t launch_check_beta(rmrcm_ctx* c, double* copy);
 // part = 1: the particular problem solved beside the basis (FP64, subdomains
 // 16 or 32 cells wide: local_setup_solves_particular), its solution to
 // pbar and its traces to the last column of the finest T.
