@@ -80,6 +80,12 @@ CASES = {
     "all_neumann_fivespot_b32": lambda: make_problem(256, b=32, seg=8, bc="fivespot", log_var=3.0),
     "all_neumann_fivespot_big_root": lambda: make_problem(256, b=8, seg=2, bc="fivespot",
                                                           log_var=1.0, lam=0.1),
+    # ten levels of 16-cell subdomains with 4-cell segments: merges of up to
+    # 16 segments fused per level, 32 and 64 with the column apply and
+    # traces fused (row tiles over two and three workgroups), the deepest
+    # five depths of the downward pass in one launch
+    "b16_512_seg4": lambda: make_problem(512, b=16, seg=4, log_var=3.0, lam=0.05),
+    "rect_512x256_b16_src": lambda: make_problem(512, ny=256, b=16, seg=4, source=True, log_var=2.0),
     # 256 gamma segments at the two top levels: the merges with blocks in
     # global memory (2 x 2 split inverses, matrix-product applies)
     "gamma256": lambda: make_problem(256, b=8, seg=1, log_var=2.0, lam=0.1, source=True),
