@@ -32,6 +32,7 @@ __global__ __launch_bounds__(1024) void k_reconstruct(Geo g, const double* __res
     extern __shared__ double sm[];
     double* gs = sm;            // R
     double* ps = gs + R;        // BX * BY
+    double* ks = ps + BX * g.by;   // BX * BY: the subdomain's permeabilities
     const int sub = blockIdx.x;
     const int I = sub % g.mx, J = sub / g.mx;
     const int BY = g.by, n = BX * BY;
@@ -49,6 +50,7 @@ __global__ __launch_bounds__(1024) void k_reconstruct(Geo g, const double* __res
         for (int a = 0; a < R; ++a) s += Ps[(size_t)a * n + c] * gs[a];
         ps[c] = s;
         const int i = c % BX, j = c / BX;
+        ks[c] = kc(K, g, I * BX + i, J * BY + j);
         p_out[(size_t)(J * BY + j) * g.nx + I * BX + i] = s;
     }
     __syncthreads();
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_reconstruct(Geo g, const double* __res
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
         const int i = c % BX, j = c / BX;
         const int gi = I * BX + i, gj = J * BY + j;
-        const double k0 = kc(K, g, gi, gj);
+        const double k0 = ks[c];
         const double p = ps[c];
         double F[4];
         for (int side = 0; side < 4; ++side) {
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_reconstruct(Geo g, const double* __res
             if (inside) {
                 const int ni = i + (side == 0 ? -1 : side == 1 ? 1 : 0);
                 const int nj = j + (side == 2 ? -1 : side == 3 ? 1 : 0);
-                const double rn = h / (2.0 * kc(K, g, I * BX + ni, J * BY + nj));
+                const double rn = h / (2.0 * ks[nj * BX + ni]);
                 F[side] = area / (rc + rn) * (p - ps[nj * BX + ni]);
                 continue;
             }
@@ -214,7 +216,7 @@ template <int BX>
 static hipError_t recon_bx(rmrcm_ctx* c) {
     const Level& L = c->levels[c->D];
     const int nsub = c->geo.mx * c->geo.my;
-    const size_t lds = sizeof(double) * (size_t)(L.nslot + BX * c->geo.by);
+    const size_t lds = sizeof(double) * (size_t)(L.nslot + 2 * BX * c->geo.by);
     hipError_t e = hipFuncSetAttribute((const void*)k_reconstruct<BX>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
