@@ -116,29 +116,12 @@ __device__ inline void beta_of(const Geo& g, const double* __restrict__ K, doubl
     seglen[e] = len;
 }
 
-__global__ void k_beta(Geo g, const double* __restrict__ K, double* __restrict__ beta,
-                       double* __restrict__ seglen) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < g.nseg) beta_of(g, K, beta, seglen, e);
-}
 
-// Flags a permeability that is not finite and positive.
-// With copy non-null the values are also copied there.
-__global__ void k_check_perm(const double* __restrict__ K, size_t n, int* __restrict__ flags,
-                             double* __restrict__ copy) {
-    bool bad = false;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-         t += (size_t)gridDim.x * blockDim.x) {
-        const double v = K[t];
-        bad |= !(v > 0.0) || !(v <= 1.7976931348623157e308);
-        if (copy) copy[t] = v;
-    }
-    if (bad) atomicOr(&flags[FLAG_BAD_PERM], 1);
-}
 
-// The permeability check (blocks below nbc, as k_check_perm) and the
-// segment Robin parameters (the others, as k_beta) in one launch: both read
-// only the permeability.
+// Blocks below nbc: flag a permeability that is not finite and positive
+// (with copy non-null the values are also copied there); the others: the
+// segment Robin parameters.  One launch, as both read only the
+// permeability.
 __global__ void k_check_beta(Geo g, const double* __restrict__ K, size_t n, int* __restrict__ flags,
                              double* __restrict__ copy, int nbc, double* __restrict__ beta,
                              double* __restrict__ seglen) {
@@ -2254,24 +2237,11 @@ static hipError_t traces_bx(rmrcm_ctx* c, int part, const int* mask, int want) {
     return hipGetLastError();
 }
 
-hipError_t launch_beta(rmrcm_ctx* c) {
-    if (c->geo.nseg == 0) return hipSuccess;
-    const int nb = (c->geo.nseg + 255) / 256;
-    hipLaunchKernelGGL(k_beta, dim3(nb), dim3(256), 0, c->stream, c->geo, c->K, c->beta, c->seglen);
-    return hipGetLastError();
-}
-
 hipError_t launch_check_beta(rmrcm_ctx* c, double* copy) {
     const size_t n = (size_t)c->geo.nx * c->geo.ny;
     const int nbc = 1024, nbb = (c->geo.nseg + 255) / 256;
     hipLaunchKernelGGL(k_check_beta, dim3(nbc + nbb), dim3(256), 0, c->stream, c->geo, c->K, n, c->flags, copy,
                        nbc, c->beta, c->seglen);
-    return hipGetLastError();
-}
-
-hipError_t launch_check_perm(rmrcm_ctx* c, double* copy) {
-    const size_t n = (size_t)c->geo.nx * c->geo.ny;
-    hipLaunchKernelGGL(k_check_perm, dim3(1024), dim3(256), 0, c->stream, c->K, n, c->flags, copy);
     return hipGetLastError();
 }
 

@@ -133,10 +133,8 @@ struct rmrcm_ctx {
 namespace rmrcm {
 
 // Kernel launchers (return hipError_t of the launch).
-hipError_t launch_beta(rmrcm_ctx* c);
+// The permeability check and the segment Robin parameters in one launch;
 // copy non-null: the permeability is also copied there in the same pass.
-hipError_t launch_check_perm(rmrcm_ctx* c, double* copy = nullptr);
-// The permeability check and the segment Robin parameters in one launch.
 hipError_t launch_check_beta(rmrcm_ctx* c, double* copy);
 // part = 1: the particular problem solved beside the basis (FP64, subdomains
 // 16 or 32 cells wide: local_setup_solves_particular), its solution to
