@@ -920,8 +920,12 @@ __device__ __forceinline__ double qd_vec_dot(const double (&r)[GT / 8], const do
     return s;
 }
 
+// With glo non-null the kernel also does the root's step of the downward
+// pass: every slot of the root lies on the domain boundary (datum 0), so
+// the gamma data are the particular column itself, written to the Robin
+// datum of each row's side of its segment.
 template <int GT>
-__global__ __launch_bounds__(8 * GT) void k_qd_apply_vec(MergeArgs a, int col) {
+__global__ __launch_bounds__(8 * GT) void k_qd_apply_vec(MergeArgs a, int col, double* glo, double* ghi) {
     __shared__ double rs[GT], rd[GT], tt[GT], uu[GT];
     const int node = blockIdx.x, g = a.g;
     const int tid = threadIdx.x, i = tid >> 3, c8 = tid & 7;
@@ -969,6 +973,11 @@ __global__ __launch_bounds__(8 * GT) void k_qd_apply_vec(MergeArgs a, int col) {
         double* X = a.X + (size_t)node * a.xi * a.ld;
         X[(size_t)i * a.ld + col] = -(sv - d);
         X[(size_t)(g + i) * a.ld + col] = -(sv + d);
+        if (glo) {
+            const int e = a.css[(size_t)c1 * a.cnslot + a.gmap[i]] >> 1;
+            glo[e] = -(sv - d);
+            ghi[e] = -(sv + d);
+        }
     }
 }
 
@@ -1988,12 +1997,15 @@ hipError_t launch_merge_particular(rmrcm_ctx* c, int d) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
     if (d == 0) {
-        // the top: one merge, one column
+        // the top: one merge, one column (and the root's downward step when
+        // root_down_fused)
+        double* gl = c->root_down_fused ? c->glo : nullptr;
+        double* gh = c->root_down_fused ? c->ghi : nullptr;
         switch (qd_tier(a.g)) {
-            case 16: hipLaunchKernelGGL(k_qd_apply_vec<16>, dim3(a.nnodes), dim3(128), 0, c->stream, a, a.nslot); return hipGetLastError();
-            case 32: hipLaunchKernelGGL(k_qd_apply_vec<32>, dim3(a.nnodes), dim3(256), 0, c->stream, a, a.nslot); return hipGetLastError();
-            case 64: hipLaunchKernelGGL(k_qd_apply_vec<64>, dim3(a.nnodes), dim3(512), 0, c->stream, a, a.nslot); return hipGetLastError();
-            case 128: hipLaunchKernelGGL(k_qd_apply_vec<128>, dim3(a.nnodes), dim3(1024), 0, c->stream, a, a.nslot); return hipGetLastError();
+            case 16: hipLaunchKernelGGL(k_qd_apply_vec<16>, dim3(a.nnodes), dim3(128), 0, c->stream, a, a.nslot, gl, gh); return hipGetLastError();
+            case 32: hipLaunchKernelGGL(k_qd_apply_vec<32>, dim3(a.nnodes), dim3(256), 0, c->stream, a, a.nslot, gl, gh); return hipGetLastError();
+            case 64: hipLaunchKernelGGL(k_qd_apply_vec<64>, dim3(a.nnodes), dim3(512), 0, c->stream, a, a.nslot, gl, gh); return hipGetLastError();
+            case 128: hipLaunchKernelGGL(k_qd_apply_vec<128>, dim3(a.nnodes), dim3(1024), 0, c->stream, a, a.nslot, gl, gh); return hipGetLastError();
         }
     }
     return qd_columns_any(c, a, a.nslot, 1, d != 0, 1);
@@ -2032,6 +2044,15 @@ static constexpr int kDownSubXi = 32;
 int build_down_sub(rmrcm_ctx* c) {
     const int D = c->D;
     c->down_ds = D;
+    // the root's downward step inside the top's particular column: when
+    // every root slot is on the domain boundary and the top takes the
+    // register-resident column kernel
+    c->root_down_fused = false;
+    if (D > 0 && c->levels[0].g <= 128 && c->levels[0].nnodes == 1) {
+        bool all_boundary = true;
+        for (int code : c->levels[0].h_slotseg) all_boundary = all_boundary && code < 0;
+        c->root_down_fused = all_boundary;
+    }
     int ds = D;
     while (ds > 0 && D - ds < kDownSubMax && c->levels[ds - 1].xi <= kDownSubXi) --ds;
     if (D - ds < 2) return RMRCM_OK;
@@ -2136,7 +2157,7 @@ int build_down_sub(rmrcm_ctx* c) {
 
 hipError_t launch_down_all(rmrcm_ctx* c) {
     const int ds = c->down_ds;
-    for (int d = 0; d < ds; ++d) {
+    for (int d = c->root_down_fused ? 1 : 0; d < ds; ++d) {
         hipError_t e = launch_down(c, d);
         if (e != hipSuccess) return e;
     }

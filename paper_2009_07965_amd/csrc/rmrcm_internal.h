@@ -79,6 +79,7 @@ struct rmrcm_ctx {
     // downward pass of the deepest short-interface depths in one launch
     // (built by build_down_sub; down_ds == D: none)
     int down_ds = 0;
+    bool root_down_fused = false; // the root's downward step done by the top's particular column
     int* down_tab = nullptr;      // [subtrees][entries] source of every data-vector entry
     int down_entries = 0, down_results = 0;
     int down_toff[8] = {}, down_roff[8] = {};
