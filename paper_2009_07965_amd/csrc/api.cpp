@@ -676,16 +676,19 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
     c->stream = c->own_stream;
     for (auto& e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return fail(RMRCM_EDEVICE);
+    // ev_done marks the end of a step (any context) or of an overlapped
+    // solve; the auxiliary stream and its events serve the overlapped
+    // particular chain of FP64 contexts with merges
+    if (hipEventCreateWithFlags(&c->ev_ls, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess)
+        return fail(RMRCM_EDEVICE);
     if (prm->precision == RMRCM_FP64 && c->D > 0 && c->D <= 32) {
         if (hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess)
             return fail(RMRCM_EDEVICE);
         for (int d = 0; d < c->D; ++d)
             if (hipEventCreateWithFlags(&c->lev[d], hipEventDisableTiming) != hipSuccess)
                 return fail(RMRCM_EDEVICE);
-        if (hipEventCreateWithFlags(&c->ev_ls, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_aux, hipEventDisableTiming) != hipSuccess)
-            return fail(RMRCM_EDEVICE);
     }
     const Geo& g = c->geo;
     const size_t nsub = (size_t)g.mx * g.my;
