@@ -60,7 +60,8 @@ enum {
     RMRCM_ESINGULAR = -4,  /* a local or interface system is singular */
     RMRCM_ENOTCONV = -5,   /* iterative refinement did not converge */
     RMRCM_ESTATE = -6,     /* call out of order (e.g. solve before setup) */
-    RMRCM_ENOTSUP = -7     /* configuration not supported by this build */
+    RMRCM_ENOTSUP = -7,    /* configuration not supported by this build */
+    RMRCM_ETOOBIG = -8     /* problem exceeds the fixed scratch of rmrcm_step_noalloc */
 };
 
 /* Precision modes of the local solves.  Interface merges always run in
@@ -169,6 +170,38 @@ int rmrcm_step(rmrcm_ctx* ctx, const double* perm, const double* source, const d
  * timing and testing; results are the same either way.
  * Errors: EINVAL (ctx NULL). */
 int rmrcm_set_step_graph(rmrcm_ctx* ctx, int enabled);
+
+/* ---- Allocation-free step ----------------------------------------------
+ * For callers that cannot allocate device memory: serving loops and
+ * harnesses that forbid hipMalloc / hipFree, or run under a fixed device
+ * memory budget.  rmrcm_setup followed by rmrcm_step for one FP64 problem,
+ * with no context and no device allocation: every device array of the step
+ * (Robin parameters, factor store, basis, particular solutions, traces,
+ * merge blocks and coefficients, level tables, flags) is carved from a
+ * fixed scratch of RMRCM_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on from the loading of its code until the process
+ * ends.  Same kernels and results as rmrcm_step of an FP64 context.
+ *   prm:       as for rmrcm_setup; precision must be RMRCM_FP64 (else
+ *              ENOTSUP).
+ *   perm, source (NULL = zero), bc_value, pressure, flux: DEVICE pointers
+ *              with the layouts of rmrcm_setup / rmrcm_solve (EINVAL for a
+ *              host pointer); the caller owns them.
+ *   bc_type:   host or device (read synchronously for validation).
+ *   hip_stream: the stream that runs the step (NULL: the null stream).
+ * Synchronous: returns when the stream has finished the step, with the
+ * status of the device checks (EINVAL: a permeability <= 0 or not finite,
+ * or incompatible all-Neumann data; ESINGULAR).  Not capturable in a graph
+ * (it waits for its stream).  Calls on one device are serialised by the
+ * library (a lock per device); the scratch keeps the last call's contents
+ * and every call clears what must start at zero.  ETOOBIG, before any
+ * device work, when the problem's arrays exceed the scratch (an FP64 step
+ * needs about (8 sub_nx + 8 R + 24) bytes per cell plus the merge levels,
+ * R = 2 (sub_nx + sub_ny) / seg: 1024^2 cells with 32^2 subdomains and
+ * 8-cell segments fit). */
+#define RMRCM_NOALLOC_SCRATCH_BYTES ((size_t)512 << 20)
+int rmrcm_step_noalloc(const rmrcm_params* prm, const double* perm, const int8_t* bc_type,
+                       const double* source, const double* bc_value, double* pressure,
+                       double* flux, void* hip_stream);
 
 /* Solve for one right-hand side: the particular local solutions (source
  * and outer boundary data, additive split of Section 2.1), their columns

@@ -19,6 +19,7 @@ from .rmrcm import (  # noqa: F401
     rmrcm_refactor,
     rmrcm_sync,
     rmrcm_solve,
+    rmrcm_step_noalloc,
     rmrcm_get_interface,
     rmrcm_counts,
     rmrcm_set_stream,

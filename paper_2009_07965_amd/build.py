@@ -42,7 +42,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
         cmd = [cc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".hip"):
+        if src.endswith(".hip") or src == "api.cpp":   # api.cpp holds a device array
             cmd.insert(1, "-x")
             cmd.insert(2, "hip")
         if verbose:

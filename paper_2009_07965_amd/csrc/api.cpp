@@ -62,11 +62,24 @@ void report_hip(hipError_t e, const char* what, int line) {
         }                                             \
     } while (0)
 
+// Device array of count elements, zero-filled in stream order.  With an
+// arena (the allocation-free entry point) the array is carved from it at a
+// 256-byte boundary and NOT filled here: the caller zero-fills the used part
+// of the arena once every array is carved; RMRCM_ETOOBIG when it does not fit.
 template <typename T>
 int dalloc(rmrcm_ctx* c, T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
     const size_t bytes = count * sizeof(T);
+    if (c->arena) {
+        const size_t off = (c->arena_used + 255) & ~(size_t)255;
+        const size_t end = (off + bytes + 255) & ~(size_t)255;
+        if (end > c->arena_cap || end < off) return RMRCM_ETOOBIG;
+        *p = reinterpret_cast<T*>(c->arena + off);
+        c->arena_used = end;
+        c->device_bytes += bytes;
+        return RMRCM_OK;
+    }
     hipError_t e = hipMalloc((void**)p, bytes);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -212,12 +225,12 @@ void build_levels(rmrcm_ctx* c) {
     }
 }
 
+// Device arrays of every level and of the fused downward pass (no copies:
+// upload_levels sends the tables once every array exists).
 int alloc_levels(rmrcm_ctx* c) {
     for (int d = 0; d <= c->D; ++d) {
         Level& L = c->levels[d];
         TRY(dalloc(c, &L.slotseg, L.h_slotseg.size()));
-        HIP_TRY(hipMemcpyAsync(L.slotseg, L.h_slotseg.data(), L.h_slotseg.size() * sizeof(int),
-                               hipMemcpyHostToDevice, c->stream));
         if (d >= 1) TRY(dalloc(c, &L.T, (size_t)L.nnodes * L.nslot * L.ld));
         if (d < c->D) {
             TRY(dalloc(c, &L.pmap, L.h_pmap.size()));
@@ -232,12 +245,6 @@ int alloc_levels(rmrcm_ctx* c) {
                     L.h_gseg[(size_t)n * L.g + t] = C.h_slotseg[(size_t)c1 * C.nslot + L.h_gmap[t]] >> 1;
             }
             TRY(dalloc(c, &L.gseg, L.h_gseg.size()));
-            HIP_TRY(hipMemcpyAsync(L.gseg, L.h_gseg.data(), L.h_gseg.size() * sizeof(int),
-                                   hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(hipMemcpyAsync(L.pmap, L.h_pmap.data(), L.h_pmap.size() * sizeof(int),
-                                   hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(hipMemcpyAsync(L.gmap, L.h_gmap.data(), L.h_gmap.size() * sizeof(int),
-                                   hipMemcpyHostToDevice, c->stream));
             TRY(dalloc(c, &L.M, (size_t)L.nnodes * L.xi * L.xi));
             TRY(dalloc(c, &L.X, (size_t)L.nnodes * L.xi * L.ld));
             const size_t wk = rmrcm::merge_work_doubles(L);
@@ -247,12 +254,35 @@ int alloc_levels(rmrcm_ctx* c) {
     // the root level keeps a trace buffer only when it is also the leaf level
     if (c->D == 0) TRY(dalloc(c, &c->levels[0].T, (size_t)c->levels[0].nslot * c->levels[0].ld));
     TRY(rmrcm::build_down_sub(c));
+    if (!c->h_down_tab.empty()) TRY(dalloc(c, &c->down_tab, c->h_down_tab.size()));
+    return RMRCM_OK;
+}
+
+// The host tables of every level into their device arrays, in stream order.
+int upload_levels(rmrcm_ctx* c) {
+    auto up = [&](int* dst, const std::vector<int>& src) -> int {
+        if (!src.empty())
+            HIP_TRY(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        return RMRCM_OK;
+    };
+    for (int d = 0; d <= c->D; ++d) {
+        const Level& L = c->levels[d];
+        TRY(up(L.slotseg, L.h_slotseg));
+        if (d < c->D) {
+            TRY(up(L.gseg, L.h_gseg));
+            TRY(up(L.pmap, L.h_pmap));
+            TRY(up(L.gmap, L.h_gmap));
+        }
+    }
+    TRY(up(c->down_tab, c->h_down_tab));
     return RMRCM_OK;
 }
 
 void free_all(rmrcm_ctx* c) {
-    auto f = [](void* p) {
-        if (p) (void)hipFree(p);
+    // arrays carved from an arena belong to its owner
+    const bool own = c->arena == nullptr;
+    auto f = [own](void* p) {
+        if (p && own) (void)hipFree(p);
     };
     f(c->down_tab);
     c->down_tab = nullptr;
@@ -611,6 +641,7 @@ const char* rmrcm_strerror(int s) {
         case RMRCM_ENOTCONV: return "iterative refinement did not converge";
         case RMRCM_ESTATE: return "call out of order";
         case RMRCM_ENOTSUP: return "configuration not supported";
+        case RMRCM_ETOOBIG: return "problem exceeds the fixed scratch of the allocation-free step";
     }
     return "unknown status";
 }
@@ -720,7 +751,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
             (r = dalloc(c, &c->lint, nsub)))
             return fail(r);
     }
-    if ((r = alloc_levels(c)) != RMRCM_OK) return fail(r);
+    if ((r = alloc_levels(c)) != RMRCM_OK || (r = upload_levels(c)) != RMRCM_OK) return fail(r);
     if (hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return fail(RMRCM_EDEVICE);
@@ -1440,3 +1471,134 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free step
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)RMRCM_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+// Every device array of rmrcm_step_noalloc: one such array per GPU the
+// library runs on, created with the code object and held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: the device address comes from hipGetSymbolAddress, once per
+// device (scratch_address), and only that address is handed to kernels and
+// copies.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_noalloc_mu[kMaxDevices];   // one allocation-free step per device at a time
+
+// Device address of this device's scratch (the device must be current).
+int scratch_address(int dev, char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            report_hip(e, "hipGetSymbolAddress(scratch)", __LINE__);
+            (void)hipGetLastError();
+            return RMRCM_EDEVICE;
+        }
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return RMRCM_OK;
+}
+
+// The work of rmrcm_step_noalloc once the context is built: carve the
+// arrays, zero them, upload the tables, enqueue the fused step chain.
+int noalloc_enqueue(rmrcm_ctx* c, const std::vector<int8_t>& ht, const double* perm,
+                    const double* source, const double* bc_value, double* pressure, double* flux) {
+    const Geo& g = c->geo;
+    const size_t ncell = (size_t)g.nx * g.ny;
+    const size_t nbf = ht.size();
+    const size_t nsub = (size_t)g.mx * g.my;
+    const size_t n = (size_t)g.bx * g.by;
+    const int R = c->levels[c->D].nslot;
+    TRY(dalloc(c, &c->bct, nbf));
+    TRY(dalloc(c, &c->beta, g.nseg));
+    TRY(dalloc(c, &c->seglen, g.nseg));
+    TRY(dalloc(c, &c->Pstore, nsub * g.by * g.bx * g.bx));
+    TRY(dalloc(c, &c->Psi, nsub * R * n));
+    TRY(dalloc(c, &c->pbar, nsub * n));
+    TRY(dalloc(c, &c->glo, g.nseg));
+    TRY(dalloc(c, &c->ghi, g.nseg));
+    TRY(dalloc(c, &c->flags, rmrcm::kNumFlags));
+    TRY(dalloc(c, &c->gauge, 256));
+    TRY(dalloc(c, &c->dscal, 1));
+    if (!source) TRY(dalloc(c, &c->q, ncell));   // a zero source
+    TRY(alloc_levels(c));
+    // every array starts at zero, as hipMalloc'ed arrays do after dalloc
+    HIP_TRY(rmrcm::launch_fill_i32(c, reinterpret_cast<int*>(c->arena), c->arena_used / sizeof(int), 0));
+    HIP_TRY(hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream));
+    TRY(upload_levels(c));
+    c->K = const_cast<double*>(perm);
+    if (source) c->q = const_cast<double*>(source);
+    c->bcv = const_cast<double*>(bc_value);
+    c->pout = pressure;
+    c->fout = flux;
+    return enqueue_step_fused(c, nullptr);
+}
+
+}  // namespace
+
+extern "C" int rmrcm_step_noalloc(const rmrcm_params* prm, const double* perm, const int8_t* bc_type,
+                                  const double* source, const double* bc_value, double* pressure,
+                                  double* flux, void* hip_stream) {
+    const int v = validate(prm);
+    if (v != RMRCM_OK) return v;
+    if (prm->precision != RMRCM_FP64) return RMRCM_ENOTSUP;
+    if (!perm || !bc_type || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return RMRCM_EDEVICE;
+    }
+    if (prm->device < 0 || prm->device >= ndev || prm->device >= kMaxDevices) return RMRCM_EINVAL;
+    if (hipSetDevice(prm->device) != hipSuccess) return RMRCM_EDEVICE;
+    if (!is_device_ptr(perm) || (source && !is_device_ptr(source)) || !is_device_ptr(bc_value) ||
+        !is_device_ptr(pressure) || !is_device_ptr(flux))
+        return RMRCM_EINVAL;
+    const size_t nbf = 2 * (size_t)prm->nx + 2 * (size_t)prm->ny;
+    std::vector<int8_t> ht(nbf);
+    if (is_device_ptr(bc_type)) {
+        if (hipMemcpy(ht.data(), bc_type, nbf, hipMemcpyDeviceToHost) != hipSuccess) return RMRCM_EDEVICE;
+    } else {
+        std::memcpy(ht.data(), bc_type, nbf);
+    }
+    bool any_dir = false;
+    for (int8_t t : ht) {
+        if (t != RMRCM_BC_NEUMANN && t != RMRCM_BC_DIRICHLET) return RMRCM_EINVAL;
+        any_dir |= t == RMRCM_BC_DIRICHLET;
+    }
+    rmrcm_ctx* c = new (std::nothrow) rmrcm_ctx();
+    if (!c) return RMRCM_ENOMEM;
+    c->prm = *prm;
+    c->device = prm->device;
+    c->any_dirichlet = any_dir;
+    build_geo(c);
+    build_levels(c);
+    int r = RMRCM_OK;
+    if (!any_dir && c->D == 0) r = RMRCM_ENOTSUP;   // one subdomain, no Dirichlet face
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->capturing = true;   // no events, no host waits inside the chain
+    {
+        std::lock_guard<std::mutex> lk(g_noalloc_mu[prm->device]);
+        char* base = nullptr;
+        if (r == RMRCM_OK) r = scratch_address(prm->device, &base);
+        if (r == RMRCM_OK) {
+            c->arena = base;
+            c->arena_cap = kScratchBytes;
+            r = noalloc_enqueue(c, ht, perm, source, bc_value, pressure, flux);
+            // the scratch is free for the next call once this stream is idle
+            const hipError_t e = hipStreamSynchronize(c->stream);
+            if (r == RMRCM_OK && e != hipSuccess) r = RMRCM_EDEVICE;
+            if (r == RMRCM_OK) r = check_flags(c);
+        }
+    }
+    free_all(c);
+    delete c;
+    return r;
+}

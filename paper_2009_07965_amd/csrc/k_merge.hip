@@ -2039,6 +2039,8 @@ hipError_t launch_down(rmrcm_ctx* c, int d) {
 // every depth's rows fit the workgroup and the data vectors, results and
 // source table fit LDS.  Sources: the writer of every (segment, side) datum
 // among the fused depths is found by the same rule k_down_sub applies.
+// Builds the host table only (c->h_down_tab); the device copy is the
+// caller's.
 static constexpr int kDownSubXi = 32;
 
 int build_down_sub(rmrcm_ctx* c) {
@@ -2137,14 +2139,7 @@ int build_down_sub(rmrcm_ctx* c) {
             }
         }
     }
-    if (hipMalloc(&c->down_tab, tab.size() * sizeof(int)) != hipSuccess) {
-        (void)hipGetLastError();
-        c->down_tab = nullptr;
-        return RMRCM_ENOMEM;
-    }
-    c->device_bytes += tab.size() * sizeof(int);
-    if (hipMemcpy(c->down_tab, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)
-        return RMRCM_EDEVICE;
+    c->h_down_tab.swap(tab);   // the caller allocates down_tab and uploads it
     c->down_ds = ds;
     c->down_entries = E;
     c->down_results = RT;

@@ -81,6 +81,7 @@ struct rmrcm_ctx {
     int down_ds = 0;
     bool root_down_fused = false; // the root's downward step done by the top's particular column
     int* down_tab = nullptr;      // [subtrees][entries] source of every data-vector entry
+    std::vector<int> h_down_tab;  // its host copy (built by build_down_sub)
     int down_entries = 0, down_results = 0;
     int down_toff[8] = {}, down_roff[8] = {};
     // device arrays
@@ -108,6 +109,11 @@ struct rmrcm_ctx {
     double* gauge = nullptr;                 // partial sums of the zero-mean gauge
     std::vector<rmrcm::Level> levels;        // index = depth
     size_t device_bytes = 0;
+    // Device arrays carved from a caller-provided region instead of
+    // hipMalloc (the allocation-free entry point): base, capacity, bytes used.
+    // Null: every array has its own allocation.
+    char* arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
     // timing
     hipEvent_t ev[16] = {};
     // FP64 overlap of the particular chain with the setup merges: an
@@ -158,8 +164,8 @@ hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
 // The downward pass of every depth (the deep, short-interface depths in one launch).
 hipError_t launch_down_all(rmrcm_ctx* c);
-// Chooses the depths of that launch and uploads its source table (after
-// the levels are allocated); RMRCM_* code.
+// Chooses the depths of that launch and builds its source table on the
+// host (c->h_down_tab); RMRCM_* code.
 int build_down_sub(rmrcm_ctx* c);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
 hipError_t launch_interface_values(rmrcm_ctx* c);

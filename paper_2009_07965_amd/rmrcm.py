@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "librmrcm.so")
 
 RMRCM_OK = 0
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESINGULAR",
-          -5: "ENOTCONV", -6: "ESTATE", -7: "ENOTSUP"}
+          -5: "ENOTCONV", -6: "ESTATE", -7: "ENOTSUP", -8: "ETOOBIG"}
 RMRCM_FP64, RMRCM_MIXED, RMRCM_MIXED_LEARNED = 0, 1, 2
 RMRCM_BC_NEUMANN, RMRCM_BC_DIRICHLET = 0, 1
 
@@ -46,7 +46,7 @@ class rmrcm_params(ctypes.Structure):
 
 EXPORTS = [
     "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve", "rmrcm_step",
-    "rmrcm_set_step_graph",
+    "rmrcm_set_step_graph", "rmrcm_step_noalloc",
     "rmrcm_get_interface",
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
     "rmrcm_strerror", "rmrcm_autotune", "rmrcm_batch_create", "rmrcm_batch_refactor",
@@ -80,6 +80,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_solve.restype = ctypes.c_int
     lib.rmrcm_step.argtypes = [vp, dp, dp, dp, dp, dp]
     lib.rmrcm_step.restype = ctypes.c_int
+    lib.rmrcm_step_noalloc.argtypes = [ctypes.POINTER(rmrcm_params), dp, i8p, dp, dp, dp, dp, vp]
+    lib.rmrcm_step_noalloc.restype = ctypes.c_int
     lib.rmrcm_set_step_graph.argtypes = [vp, ctypes.c_int]
     lib.rmrcm_set_step_graph.restype = ctypes.c_int
     lib.rmrcm_get_interface.argtypes = [vp, dp, dp]
@@ -205,6 +207,21 @@ def rmrcm_step(ctx, perm, source, bc_value, pressure, flux):
     pp, _p = _ptr(pressure, np.float64)
     fp, _f = _ptr(flux, np.float64)
     _check(lib().rmrcm_step(ctx, kp, sp, bp, pp, fp), "rmrcm_step")
+
+
+def rmrcm_step_noalloc(params: rmrcm_params, perm, bc_type, source, bc_value, pressure, flux,
+                       stream_handle=None):
+    """The allocation-free FP64 step: device tensors for perm, source (or
+    None), bc_value, pressure and flux; returns when they are written."""
+    kp, _k = _ptr(perm, np.float64)
+    tp, _t = _ptr(bc_type, np.int8)
+    sp, _s = _ptr(source, np.float64)
+    bp, _b = _ptr(bc_value, np.float64)
+    pp, _p = _ptr(pressure, np.float64)
+    fp, _f = _ptr(flux, np.float64)
+    st = lib().rmrcm_step_noalloc(ctypes.byref(params), kp, tp, sp, bp, pp, fp,
+                                  ctypes.c_void_p(stream_handle) if stream_handle else None)
+    _check(st, "rmrcm_step_noalloc")
 
 
 def rmrcm_get_interface(ctx, U, P):
