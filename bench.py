@@ -1,26 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark: fine cells per second per full solve of the recursive MRCM.
 
-One step = one full solve of the 1024x1024 log-normal workload (32x32
-subdomains of 32x32 cells, 8-cell interface segments, alpha 1, p = 1 on W
-and 0 on E): rmrcm_refactor (Robin parameters, every local factorisation
-and basis, the upward merges) followed by rmrcm_solve (particular
-solutions, merges of the particular column, top solve, downward pass,
-reconstruction of pressures and fluxes).  Inputs and outputs stay in HBM;
-the timed region is bracketed by torch.cuda.synchronize().
+One step = one full solve of the 8192x8192 channelized workload (67M
+cells; 256x256 subdomains of 32x32 cells, 8-cell interface segments,
+alpha 1, p = 1 on W and 0 on E, no flow on S and N, 16 levels):
+rmrcm_step, i.e. the Robin parameters, every local factorisation, basis and
+particular solution, the upward merges, the top solve, the downward pass
+and the reconstruction of pressures and fluxes.  Inputs and outputs stay
+in HBM; the timed region is bracketed by torch.cuda.synchronize().
 
 Three modes are timed on the same input: plain FP64, mixed precision
 (FP32 local factorisations with FP64-residual refinement to --ir-tol) and
-mixed + learned (the local-basis surrogate, trained here on the GPU for a
-few seconds on pairs from the local solver, behind the FP64 residual gate
---gate-tol).  Each mode's flux error against the FP64 GPU output is
-measured; the reported value is the throughput of the fastest mode whose
-flux error is within 1e-6, every mode listed beside it.  Printed: one JSON
-line with the metric, the roofline of the dominant kernel (its duration
-from the library's HIP events on the launch stream), the ensemble batch
-throughput and the CPU oracle timed on a bounded sample.
+mixed + learned (the local-basis surrogate, trained here on the GPU on
+pairs from the local solver, behind the FP64 residual gate --gate-tol).
+Each mode's flux error against the FP64 GPU output is measured; the
+reported value is the throughput of the fastest mode whose flux error is
+within 1e-6, every mode listed beside it.  Printed: one JSON line with the
+metric, each phase against its roofline and the roofline of the dominant
+kernel (durations from the library's HIP events on the launch stream), the
+same modes on the 1024^2 and 2048^2 workloads, the ensemble batch
+throughput and the CPU oracle timed on a bounded sample (a 1024^2 crop).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--ir-tol T] [--gate-tol G]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--config 5] [--fp64-only]
 """
 
 from __future__ import annotations
@@ -109,33 +110,75 @@ def algorithmic_work(prob):
     mf = 0.0
     for lev in levels:
         for (xi, c, g) in lev:
-            mf += (2.0 / 3.0) * xi ** 3 + 2.0 * xi * xi * c + 2.0 * 2 * g * c * g
+            # LU of the 2g x 2g interface matrix, its solve for the c parent
+            # columns (boundary slots + particular), and the parent traces:
+            # o = c - 1 rows, each the product of g trace entries of its
+            # child with the g coefficients of every column
+            mf += (2.0 / 3.0) * xi ** 3 + 2.0 * xi * xi * c + 2.0 * (c - 1) * g * c
     w["merge_flops"] = mf
     return w
 
 
-def cpu_baseline(prob, budget_s=30.0):
-    """The oracle (plain non-recursive MRCM, FP64, SuperLU) on the same
-    workload, single-threaded, timed on this host."""
-    from oracle.mrcm import mrcm_solve
+def host_cpu():
+    """CPU model and logical core count of this host."""
+    model = "unknown"
     try:
-        from threadpoolctl import threadpool_limits
-        ctx = threadpool_limits(limits=1)
-    except Exception:          # pragma: no cover
-        ctx = None
-    reps, t_tot = 0, 0.0
-    while reps == 0 or (t_tot < 0.5 * budget_s and reps < 3):
-        t0 = time.perf_counter()
-        mrcm_solve(prob)
-        t_tot += time.perf_counter() - t0
-        reps += 1
-    if ctx is not None:
-        ctx.unregister() if hasattr(ctx, "unregister") else None
-    t = t_tot / reps
-    return {"value": prob.ncells / t, "unit": "cells/s", "cores": 1, "kind": "oracle",
-            "sample": "full %dx%d workload, %d full solve(s) (non-recursive MRCM: local "
-                      "SuperLU solves + global interface system), %.2f s each"
-                      % (prob.nx, prob.ny, reps, t)}
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def crop(prob, n):
+    """The n x n lower-left corner of a workload with its subdomain and
+    segment sizes and the same boundary-condition pattern."""
+    from workloads import dirichlet_we
+    if prob.nx <= n:
+        return prob
+    t, v = dirichlet_we(n, n)
+    return prob.with_(nx=n, ny=n, K=np.ascontiguousarray(prob.K[:n, :n]), q=np.zeros((n, n)),
+                      bc_type=t, bc_value=v)
+
+
+def cpu_baseline(prob, budget_s=30.0, crop_n=1024):
+    """The oracle (plain non-recursive MRCM, FP64: local SuperLU solves and
+    the global interface system) timed on this host on a bounded sample of
+    the workload: the full grid up to 1024^2, else a 1024^2 crop with the
+    same subdomain and segment sizes; once limited to one thread, once with
+    every thread the numerical libraries take."""
+    from oracle.mrcm import mrcm_solve
+    from threadpoolctl import threadpool_limits, threadpool_info
+    sample = crop(prob, crop_n)
+    model, ncpu = host_cpu()
+
+    def timed(limit):
+        reps, t_tot = 0, 0.0
+        with threadpool_limits(limits=limit):
+            threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+            while reps == 0 or (t_tot < 0.25 * budget_s and reps < 2):
+                t0 = time.perf_counter()
+                mrcm_solve(sample)
+                t_tot += time.perf_counter() - t0
+                reps += 1
+        return t_tot / reps, reps, threads
+
+    t1, r1, _ = timed(1)
+    ta, ra, threads = timed(None)
+    best_t, cores = (t1, 1) if t1 <= ta else (ta, threads)
+    return {"value": sample.ncells / best_t, "unit": "cells/s", "cores": cores, "kind": "oracle",
+            "sample": "%dx%d %s of the workload (%s subdomains of %dx%d, %d-cell segments): "
+                      "the full non-recursive MRCM solve (local SuperLU solves + global "
+                      "interface system), %.2f s with 1 thread (%d runs), %.2f s with %d "
+                      "threads (%d runs); value = cells of the sample / the faster time"
+                      % (sample.nx, sample.ny, "crop" if sample is not prob else "whole",
+                         (sample.nx // sample.sub_nx) * (sample.ny // sample.sub_ny),
+                         sample.sub_nx, sample.sub_ny, sample.seg, t1, r1, ta, threads, ra),
+            "single_thread_value": sample.ncells / t1, "all_threads_value": sample.ncells / ta,
+            "threads_all": threads, "host_cpu": model, "nproc": ncpu}
 
 
 def ensemble_bench(nmem, steps, warmup):
@@ -180,17 +223,18 @@ def ensemble_bench(nmem, steps, warmup):
             "setup_s": t_create, "generate_s": t_gen}
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_local_setup_grf1024_fp64_traffic.md")
 TRAFFIC_SOURCE = os.path.join(ROOT, "paper_2009_07965_amd", "csrc", "k_local.hip")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP64 local-setup kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or
-    None when the kernel source has changed since the counters were taken."""
+def measured_traffic(workload):
+    """HBM bytes per launch of the FP64 local-setup kernel on this workload
+    from the committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or None when there is none or the kernel source has
+    changed since the counters were taken."""
     import hashlib
+    path = os.path.join(ROOT, "profiles", "k_local_setup_%s_fp64_traffic.md" % workload)
     try:
-        with open(TRAFFIC_SUMMARY) as f:
+        with open(path) as f:
             txt = f.read()
         with open(TRAFFIC_SOURCE, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
@@ -239,153 +283,205 @@ def train_quick_surrogate(prob, path, npairs, seed=4000):
             "train_s": time.perf_counter() - t0}
 
 
+WORKLOADS = {
+    1: "grf64: 64x64 log-normal GRF (corr 0.1, log-var 1), 4x4 subdomains of 16x16 cells, "
+       "4-cell segments, alpha 1, 4 levels",
+    2: "grf1024: 1024x1024 log-normal GRF (corr 0.05, log-var 4), 32x32 subdomains of 32x32 "
+       "cells, 8-cell segments, alpha 1, 10 levels",
+    4: "grf2048: 2048x2048 log-normal GRF (corr 0.05, log-var 4), 128x128 subdomains of "
+       "16x16 cells, 4-cell segments, alpha 1, 14 levels",
+    5: "channel8192: 8192x8192 channelized bimodal field (24 sinusoidal channels 8-32 cells "
+       "wide, k 1000 / 1, 5% log-noise), 256x256 subdomains of 32x32 cells, 8-cell segments, "
+       "alpha 1, 16 levels",
+}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def measure(prob, precision, steps, warmup, stream, arrays, **extra):
+    """Time `steps` full solves (rmrcm_step: refactor + solve; a replayed HIP
+    graph for FP64) after `warmup`; then a few untimed steps launch by
+    launch for the library's phase timers."""
+    import torch
+    from paper_2009_07965_amd import Solver
+    K, bct, q, bcv = arrays
+    dev = K.device
+    p_out = torch.zeros((prob.ny, prob.nx), dtype=torch.float64, device=dev)
+    f_out = torch.zeros((4, prob.ny, prob.nx), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    S = Solver(prob.nx, prob.ny, K, bct, prob.sub_nx, prob.sub_ny, prob.seg,
+               alpha=prob.alpha, precision=precision, **extra)
+    try:
+        S.set_stream(stream.cuda_stream)
+        S.autotune()               # merge column tiles, chosen once outside the timed region
+
+        def step():
+            S.step(K, q, bcv, p_out, f_out)
+
+        for _ in range(warmup):
+            step()
+        S.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S.sync()                   # deferred device-side status of the refactors
+        phases = []
+        S.set_step_graph(False)
+        for _ in range(min(steps, 5)):
+            step()
+            phases.append(S.stats())
+        S.set_step_graph(True)
+        S.sync()
+    finally:
+        S.close()
+    out = {"ms": (t1 - t0) * 1e3 / steps, "phases": phases,
+           "p": p_out.cpu().numpy(), "f": f_out.cpu().numpy()}
+    del p_out, f_out
+    return out
+
+
+def run_workload(cfg, modes, args, stream):
+    """Every requested mode on one workload; flux and pressure errors of
+    each against the FP64 GPU output."""
+    import tempfile
+    import torch
+    from paper_2009_07965_amd import RMRCM_FP64, RMRCM_MIXED, RMRCM_MIXED_LEARNED
+    from workloads import config_problem
+    t0 = time.perf_counter()
+    prob = config_problem(cfg)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    arrays = (torch.from_numpy(prob.K).to(dev), torch.from_numpy(prob.bc_type).to(dev),
+              torch.from_numpy(prob.q).to(dev), torch.from_numpy(prob.bc_value).to(dev))
+    runs, learned_info = {}, None
+    runs["fp64"] = measure(prob, RMRCM_FP64, args.steps, args.warmup, stream, arrays)
+    if "mixed" in modes:
+        runs["mixed"] = measure(prob, RMRCM_MIXED, args.steps, args.warmup, stream, arrays,
+                                ir_tol=args.ir_tol)
+    if "mixed+learned" in modes:
+        wdir = tempfile.mkdtemp()
+        wpath = os.path.join(wdir, "surrogate.bin")
+        learned_info = train_quick_surrogate(prob, wpath, args.learned_pairs)
+        runs["mixed+learned"] = measure(prob, RMRCM_MIXED_LEARNED, args.steps, args.warmup, stream,
+                                        arrays, ir_tol=args.ir_tol, gate_tol=args.gate_tol,
+                                        cnn_weights=wpath.encode())
+        os.remove(wpath)
+        os.rmdir(wdir)
+    ref = runs["fp64"]
+    res = {}
+    for name, r in runs.items():
+        last = r["phases"][-1]
+        res[name] = {"value": prob.ncells / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                     "flux_rel_err_vs_fp64": _rel(r["f"], ref["f"]),
+                     "pressure_rel_err_vs_fp64": _rel(r["p"], ref["p"]),
+                     "speedup_vs_fp64": ref["ms"] / r["ms"],
+                     "ir_iters": [last["ir_iters_setup"], last["ir_iters_solve"]],
+                     "fp64_fallback_subdomains": last["fp64_fallback_subdomains"],
+                     "surrogate_accepted_subdomains": last["surrogate_accepted_subdomains"]}
+    for r in runs.values():
+        r.pop("p")
+        r.pop("f")
+    del arrays
+    torch.cuda.empty_cache()
+    return prob, runs, res, learned_info, t_gen
+
+
+def phase_report(prob, runs, best):
+    """Per-phase times of the reported mode (the library's events on
+    untimed launch-by-launch steps), each phase against its roofline, and
+    the roofline of the dominant kernel."""
+    phases = runs[best]["phases"]
+
+    def avg(key, sub):
+        return float(np.mean([x[key][sub] for x in phases]))
+
+    t = {"beta": avg("setup_ms", "beta"), "local_setup": avg("setup_ms", "local"),
+         "merges": avg("setup_ms", "merge") + avg("solve_ms", "merge"),
+         "local_particular": avg("solve_ms", "local"), "down": avg("solve_ms", "down"),
+         "reconstruct": avg("solve_ms", "reconstruct")}
+    total = sum(t.values())
+    work = algorithmic_work(prob)
+    fp64 = best == "fp64"
+    lflops = work["local_step_flops" if fp64 else "local_setup_flops"]
+    lpeak = PEAK_FP64 if fp64 else PEAK_FP32
+    pr = {
+        "local_setup": {"bound": "alu", "algorithmic": lflops, "unit": "TFLOP/s",
+                        "achieved": lflops / (t["local_setup"] * 1e-3) / 1e12, "peak": lpeak / 1e12},
+        "merges": {"bound": "alu", "algorithmic": work["merge_flops"], "unit": "TFLOP/s",
+                   "achieved": work["merge_flops"] / (t["merges"] * 1e-3) / 1e12,
+                   "peak": PEAK_FP64 / 1e12},
+        "reconstruct": {"bound": "hbm", "algorithmic": work["recon_bytes"], "unit": "GB/s",
+                        "achieved": work["recon_bytes"] / (t["reconstruct"] * 1e-3) / 1e9,
+                        "peak": PEAK_HBM / 1e9},
+    }
+    for k, v in pr.items():
+        v["ms"] = t[k]
+        v["frac"] = v["achieved"] / v["peak"]
+        v["share_of_step"] = t[k] / total if total > 0 else None
+    # the dominant kernel: the longest single launch (the local setup is one
+    # launch in FP64, the reconstruction one launch in every mode; the
+    # merges are some 10 launches per level)
+    dom = "local_setup" if t["local_setup"] >= t["reconstruct"] else "reconstruct"
+    d = pr[dom]
+    if dom == "local_setup" and fp64 and prob.sub_nx in (16, 32):
+        nct = -(-(2 * (prob.sub_nx + prob.sub_ny) // prob.seg) // 16)
+        kname = "k_local_setup_twist<%d, %d, true>" % (prob.sub_nx, nct if nct <= 2 else 0)
+    else:
+        kname = "k_local_setup" if dom == "local_setup" else "k_reconstruct<%d>" % prob.sub_nx
+    scale = 1e12 if d["unit"] == "TFLOP/s" else 1e9
+    roof = {"kernel": kname, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
+            "unit": d["unit"], "frac": d["frac"],
+            "traffic": measured_traffic(prob.name) if (dom == "local_setup" and fp64) else None,
+            "avg_ms": d["ms"], "algorithmic": d["algorithmic"],
+            "algorithmic_unit": "flop" if d["bound"] == "alu" else "byte"}
+    assert abs(roof["achieved"] - d["algorithmic"] / (d["ms"] * 1e-3) / scale) < 1e-6 * roof["achieved"]
+    return t, pr, roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--modes", default="fp64,mixed,mixed+learned")
+    ap.add_argument("--secondary", default="2:fp64,mixed;4:fp64,mixed,mixed+learned",
+                    help="further workloads and modes measured beside the main line ('' for none)")
     ap.add_argument("--ir-tol", type=float, default=1e-8,
                     help="refinement tolerance of the mixed modes (chosen for the 1e-6 flux target)")
     ap.add_argument("--gate-tol", type=float, default=1e-8, help="residual gate of the learned mode")
     ap.add_argument("--learned-pairs", type=int, default=3000)
-    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-only", action="store_true", help="time the FP64 mode only")
+    ap.add_argument("--fp64-only", action="store_true", help="FP64 only, no secondary workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration)")
-    ap.add_argument("--ensemble", type=int, default=64,
+    ap.add_argument("--ensemble", type=int, default=256,
                     help="members of the ensemble batch measured beside the main line (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU (multi-GPU sharding of the hierarchy is "
               "design-only); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
-
-    import tempfile
     import torch
-    from paper_2009_07965_amd import Solver, RMRCM_FP64, RMRCM_MIXED, RMRCM_MIXED_LEARNED
-    from workloads import config_problem
-
-    prob = config_problem(args.config)
-    dev = torch.device("cuda:0")
-    K = torch.from_numpy(prob.K).to(dev)
-    bct = torch.from_numpy(prob.bc_type).to(dev)
-    q = torch.from_numpy(prob.q).to(dev)
-    bcv = torch.from_numpy(prob.bc_value).to(dev)
-    # a caller stream (not the null stream): the library then enqueues
-    # refactor and solve without waiting on the host between steps
-    stream = torch.cuda.Stream()
-    torch.cuda.synchronize()
-
-    def measure(precision, **extra):
-        p_out = torch.zeros((prob.ny, prob.nx), dtype=torch.float64, device=dev)
-        f_out = torch.zeros((4, prob.ny, prob.nx), dtype=torch.float64, device=dev)
-        torch.cuda.synchronize()
-        S = Solver(prob.nx, prob.ny, K, bct, prob.sub_nx, prob.sub_ny, prob.seg,
-                   alpha=prob.alpha, precision=precision, **extra)
-        S.set_stream(stream.cuda_stream)
-        S.autotune()               # merge column tiles, chosen once outside the timed region
-
-        def step():
-            # refactor + solve as one unit (a replayed HIP graph for FP64)
-            S.step(K, q, bcv, p_out, f_out)
-
-        for _ in range(args.warmup):
-            step()
-        S.sync()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        S.sync()                   # deferred device-side status of the refactors
-        # per-phase times from the library's HIP events on the context's
-        # stream, on untimed extra steps that run the step's chain of kernels
-        # launch by launch (the graph records no events)
-        phases = []
-        S.set_step_graph(False)
-        for _ in range(min(args.steps, 5)):
-            step()
-            phases.append(S.stats())
-        S.set_step_graph(True)
-        S.sync()
-        S.close()
-        return {"ms": (t1 - t0) * 1e3 / args.steps, "phases": phases,
-                "p": p_out.cpu().numpy(), "f": f_out.cpu().numpy()}
-
-    def _rel(a, b):
-        return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
-
+    if args.fp64_only:
+        args.modes, args.secondary = "fp64", ""
+    stream = torch.cuda.Stream()     # a caller stream: no host waits between steps
     calib = copy_calibration() if args.copy_calibration else None
-    runs = {"fp64": measure(RMRCM_FP64)}
-    if not args.fp64_only:
-        runs["mixed"] = measure(RMRCM_MIXED, ir_tol=args.ir_tol)
-    learned_info = None
-    if not args.no_learned and not args.fp64_only:
-        wdir = tempfile.mkdtemp()
-        wpath = os.path.join(wdir, "surrogate.bin")
-        learned_info = train_quick_surrogate(prob, wpath, args.learned_pairs)
-        runs["mixed+learned"] = measure(RMRCM_MIXED_LEARNED, ir_tol=args.ir_tol,
-                                        gate_tol=args.gate_tol, cnn_weights=wpath.encode())
-        os.remove(wpath)
-        os.rmdir(wdir)
-    ref = runs["fp64"]
-    modes = {}
-    for name, r in runs.items():
-        last = r["phases"][-1]
-        modes[name] = {"value": prob.ncells / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
-                       "flux_rel_err_vs_fp64": _rel(r["f"], ref["f"]),
-                       "pressure_rel_err_vs_fp64": _rel(r["p"], ref["p"]),
-                       "speedup_vs_fp64": ref["ms"] / r["ms"],
-                       "ir_iters": [last["ir_iters_setup"], last["ir_iters_solve"]],
-                       "fp64_fallback_subdomains": last["fp64_fallback_subdomains"],
-                       "surrogate_accepted_subdomains": last["surrogate_accepted_subdomains"]}
-    # the reported value: the fastest mode that meets the 1e-6 flux target
-    ok = [m for m in modes if modes[m]["flux_rel_err_vs_fp64"] <= 1e-6]
-    best = min(ok, key=lambda m: modes[m]["ms_per_step"])
-    r = runs[best]
-    phases = r["phases"]
-    ms = r["ms"]
-    value = prob.ncells / (ms * 1e-3)
-
-    def avg(key, sub, ph=None):
-        return float(np.mean([x[key][sub] for x in (ph or phases)]))
-
-    t_local = avg("setup_ms", "local")
-    t_merge_s = avg("setup_ms", "merge")
-    t_part = avg("solve_ms", "local")
-    t_merge_p = avg("solve_ms", "merge")
-    t_down = avg("solve_ms", "down")
-    t_recon = avg("solve_ms", "reconstruct")
-    work = algorithmic_work(prob)
-    fp64_best = best == "fp64"
-    # FP64: the step's local setup solves the particular problem beside the
-    # basis (one more column); the mixed modes run refactor + solve
-    cands = {
-        "k_local_setup": (t_local, "alu", work["local_step_flops" if fp64_best else "local_setup_flops"],
-                          PEAK_FP64 if fp64_best else PEAK_FP32, "TFLOP/s", 1e12),
-        "k_reconstruct": (t_recon, "hbm", work["recon_bytes"], PEAK_HBM, "GB/s", 1e9),
-    }
-    if not fp64_best:
-        cands["k_local_particular"] = (t_part, "hbm", work["local_part_bytes"], PEAK_HBM, "GB/s", 1e9)
-    dom = max(cands, key=lambda k: cands[k][0])
-    t_k, bound, amount, peak, unit, scale = cands[dom]
-    achieved = amount / (t_k * 1e-3)
-    if dom == "k_local_setup" and fp64_best and prob.sub_nx in (16, 32):
-        # the template instance in the step (column tiles, the particular solved beside)
-        nct = -(-(2 * (prob.sub_nx + prob.sub_ny) // prob.seg) // 16)
-        dom = "k_local_setup_twist<%d, %d, true>" % (prob.sub_nx, nct if nct <= 2 else 0)
-    roof = {"kernel": dom, "bound": bound, "achieved": achieved / scale,
-            "peak": peak / scale, "unit": unit, "frac": achieved / peak,
-            "traffic": measured_traffic() if (dom.startswith("k_local_setup") and fp64_best) else None,
-            "avg_ms": t_k,
-            "algorithmic": amount,
-            "algorithmic_unit": "flop" if bound == "alu" else "byte"}
+    modes = [m for m in args.modes.split(",") if m]
+    print("[bench] workload %d: %s" % (args.config, ",".join(modes)), file=sys.stderr, flush=True)
+    prob, runs, res, learned_info, t_gen = run_workload(args.config, modes, args, stream)
+    ok = [m for m in res if res[m]["flux_rel_err_vs_fp64"] <= 1e-6]
+    best = min(ok, key=lambda m: res[m]["ms_per_step"])
+    t, pr, roof = phase_report(prob, runs, best)
+    ms = res[best]["ms_per_step"]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": prob.ncells / (ms * 1e-3),
         "unit": "cells/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -394,27 +490,40 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if fp64_best else "f32+f64",
+        "dtype": "f64" if best == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "grf1024: 1024x1024 log-normal GRF (corr 0.05, log-var 4), "
-                               "32x32 subdomains of 32x32 cells, 8-cell segments, alpha 1, "
-                               "10 levels", "mode": best,
-                   "cells": prob.ncells, "subdomains": (prob.nx // prob.sub_nx) ** 2,
-                   "ir_tol": args.ir_tol, "gate_tol": args.gate_tol},
-        "phases_ms": {"local_setup": t_local, "merge_setup": t_merge_s,
-                      "local_particular": t_part, "merge_particular": t_merge_p,
-                      "down": t_down, "reconstruct": t_recon},
-        "modes": modes,
-        "speedup_vs_fp64": modes.get("mixed+learned", modes.get("mixed", modes["fp64"]))["speedup_vs_fp64"],
+        "config": {"workload": WORKLOADS[args.config], "mode": best, "cells": prob.ncells,
+                   "subdomains": (prob.nx // prob.sub_nx) * (prob.ny // prob.sub_ny),
+                   "ir_tol": args.ir_tol, "gate_tol": args.gate_tol,
+                   "generate_s": t_gen},
+        "phases_ms": t,
+        "phase_roofline": pr,
+        "modes": res,
+        "speedup_vs_fp64": res.get("mixed+learned", res.get("mixed", res["fp64"]))["speedup_vs_fp64"],
         "roofline": roof,
     }
     if learned_info:
         out["surrogate"] = learned_info
     if calib:
         out["copy_calibration"] = calib
+    sec = {}
+    for item in [x for x in args.secondary.split(";") if x]:
+        k, ms_ = item.split(":")
+        k = int(k)
+        print("[bench] secondary workload %d" % k, file=sys.stderr, flush=True)
+        p2, runs2, res2, li2, _ = run_workload(k, [m for m in ms_.split(",") if m], args, stream)
+        t2, pr2, _r2 = phase_report(p2, runs2, "fp64")
+        sec[p2.name] = {"workload": WORKLOADS[k], "modes": res2, "fp64_phases_ms": t2,
+                        "fp64_phase_roofline": pr2}
+        if li2:
+            sec[p2.name]["surrogate"] = li2
+    if sec:
+        out["secondary"] = sec
     if args.ensemble > 0:
-        out["ensemble"] = ensemble_bench(args.ensemble, max(3, args.steps // 4), 1)
+        print("[bench] ensemble", file=sys.stderr, flush=True)
+        out["ensemble"] = ensemble_bench(args.ensemble, max(3, args.steps // 2), 1)
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob)
     print(json.dumps(out), flush=True)
 

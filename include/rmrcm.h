@@ -73,12 +73,13 @@ enum {
  * interior subdomain (no face on the outer boundary) is first predicted by
  * the surrogate network loaded from cnn_weights (rmrcm_cnn_save format,
  * patch side = sub_nx = sub_ny, outputs = boundary segments per subdomain).
- * A prediction is accepted only when, for every basis column, the FP64
- * residual of the local Robin system |A y - e|_2 / |e|_2 <= gate_tol; an
- * accepted subdomain keeps the predicted basis and computes only its FP32
- * factor (for its particular solutions), the others run the RMRCM_MIXED
- * path.  gate_tol = 0 accepts nothing (the result is then that of
- * RMRCM_MIXED). */
+ * A prediction is accepted when, for every basis column, the FP64 residual
+ * of the local Robin system |A y - e|_2 / |e|_2 <= gate_tol; an accepted
+ * subdomain computes only its FP32 factor and takes the prediction as the
+ * starting iterate of the FP64-residual refinement (instead of the FP32
+ * solve), so that its basis meets ir_tol like every other; the others run
+ * the RMRCM_MIXED path.  gate_tol = 0 accepts nothing (the result is then
+ * that of RMRCM_MIXED). */
 enum { RMRCM_FP64 = 0, RMRCM_MIXED = 1, RMRCM_MIXED_LEARNED = 2 };
 
 enum { RMRCM_BC_NEUMANN = 0, RMRCM_BC_DIRICHLET = 1 };
@@ -307,6 +308,16 @@ int rmrcm_batch_get_stats(rmrcm_batch* b, char* json, size_t cap);
  * interior (host [nsub], may be NULL: 1 when every boundary segment of the
  * subdomain is a Robin segment).  Waits for the context's stream. */
 int rmrcm_export_local(rmrcm_ctx* ctx, float* features, double* basis, int32_t* interior);
+
+/* Learned mode: the residual gate of the last setup, per subdomain (mx*my
+ * host entries in the order of the subdomains, J * mx + I; either pointer
+ * may be NULL): residual[s] = max over basis columns a of
+ * |A y_a - e_a|_2 / |e_a|_2 for the network's prediction y (FP64 residual of
+ * the local Robin system), +inf for subdomains with a face on the outer
+ * boundary (not predicted); accepted[s] = 1 when residual[s] <= gate_tol.
+ * Waits for the context's stream.  Errors: EINVAL (not a learned context),
+ * ESTATE (no setup yet), EDEVICE. */
+int rmrcm_get_gate(rmrcm_ctx* ctx, double* residual, int32_t* accepted);
 
 /* Release every member and the batch's streams and graphs. */
 void rmrcm_batch_destroy(rmrcm_batch* b);

@@ -11,6 +11,7 @@ from .rmrcm import (  # noqa: F401
     Batch,
     Net,
     rmrcm_export_local,
+    rmrcm_get_gate,
     rmrcm_autotune,
     RMRCMError,
     load_library,

@@ -249,6 +249,16 @@ int alloc_levels(rmrcm_ctx* c) {
             TRY(dalloc(c, &L.X, (size_t)L.nnodes * L.xi * L.ld));
             const size_t wk = rmrcm::merge_work_doubles(L);
             if (wk) TRY(dalloc(c, &L.work, (size_t)L.nnodes * wk));
+            // 64-slot tiles of every node that hold an active slot or the
+            // particular column (the merge products skip the others)
+            const int nt = (L.nslot + 1 + 63) / 64;
+            L.h_tflag.assign((size_t)L.nnodes * nt, 0);
+            for (int n = 0; n < L.nnodes; ++n) {
+                for (int s = 0; s < L.nslot; ++s)
+                    if (L.h_slotseg[(size_t)n * L.nslot + s] >= 0) L.h_tflag[(size_t)n * nt + s / 64] = 1;
+                L.h_tflag[(size_t)n * nt + L.nslot / 64] = 1;
+            }
+            TRY(dalloc(c, &L.tflag, L.h_tflag.size()));
         }
     }
     // the root level keeps a trace buffer only when it is also the leaf level
@@ -269,6 +279,9 @@ int upload_levels(rmrcm_ctx* c) {
         const Level& L = c->levels[d];
         TRY(up(L.slotseg, L.h_slotseg));
         if (d < c->D) {
+            if (!L.h_tflag.empty())
+                HIP_TRY(hipMemcpyAsync(L.tflag, L.h_tflag.data(), L.h_tflag.size(), hipMemcpyHostToDevice,
+                                       c->stream));
             TRY(up(L.gseg, L.h_gseg));
             TRY(up(L.pmap, L.h_pmap));
             TRY(up(L.gmap, L.h_gmap));
@@ -295,6 +308,7 @@ void free_all(rmrcm_ctx* c) {
         f(L.M);
         f(L.X);
         f(L.work);
+        f(L.tflag);
     }
     f(c->K);
     f(c->bct);
@@ -318,9 +332,12 @@ void free_all(rmrcm_ctx* c) {
     f(c->Wsc);
     f(c->resid);
     f(c->fb);
+    f(c->irst);
+    f(c->irhist);
     f(c->lx);
     f(c->ly);
     f(c->lint);
+    f(c->gres);
     if (c->net) rmrcm_cnn_destroy(c->net);
     c->net = nullptr;
     for (auto& e : c->ev)
@@ -344,6 +361,7 @@ int check_flags(rmrcm_ctx* c) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (h[rmrcm::FLAG_BAD_PERM] || h[rmrcm::FLAG_BAD_DATA]) return RMRCM_EINVAL;
     if (h[rmrcm::FLAG_LOCAL_SINGULAR] || h[rmrcm::FLAG_MERGE_SINGULAR]) return RMRCM_ESINGULAR;
+    if (h[rmrcm::FLAG_NOTCONV]) return RMRCM_ENOTCONV;
     return RMRCM_OK;
 }
 
@@ -358,23 +376,17 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 bool mixed(const rmrcm_ctx* c) { return c->prm.precision != RMRCM_FP64; }
 
-// Refinement passes until the largest relative residual measured before a
-// correction is below ir_tol (then the corrected iterate is better still).
-// Returns the number of passes and the last measured residual.
-int refine_loop(rmrcm_ctx* c, int part, int* iters, double* last) {
-    *iters = 0;
-    *last = 0.0;
+// Refinement passes, enqueued without host synchronisation (so that the
+// mixed path can be captured in a graph): ir_max_iter passes of correction
+// and residual, each pass returning at once on the device after the largest
+// relative residual measured before a correction was within ir_tol.
+int refine_loop(rmrcm_ctx* c, int part) {
+    HIP_TRY(rmrcm::launch_fill_i32(c, c->irst + 2 * part, 2, 0));
     for (int it = 0; it < c->prm.ir_max_iter; ++it) {
         HIP_TRY(rmrcm::launch_local_refine(c, part, 1));
-        HIP_TRY(rmrcm::launch_max_resid(c, part, c->dscal));
-        double m = 0.0;
-        HIP_TRY(hipMemcpyAsync(&m, c->dscal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        *iters = it + 1;
-        *last = m;
-        if (m <= c->prm.ir_tol) return RMRCM_OK;
+        HIP_TRY(rmrcm::launch_max_resid(c, part));
     }
-    return RMRCM_ENOTCONV;
+    return RMRCM_OK;
 }
 
 // Local phase of the mixed-precision mode: FP32 factorisation and basis,
@@ -409,25 +421,15 @@ int mixed_local_setup(rmrcm_ctx* c) {
     } else {
         HIP_TRY(rmrcm::launch_local_setup(c, true, nullptr, 0, 0));
     }
-    int it = 0;
-    double last = 0.0;
-    const int st = refine_loop(c, 0, &it, &last);
-    c->ir_iters_setup = it;
-    c->ir_resid_setup = last;
-    c->n_fallback = 0;
-    if (st == RMRCM_ENOTCONV) {
-        HIP_TRY(rmrcm::launch_local_refine(c, 0, 0));   // measure only
-        HIP_TRY(rmrcm::launch_mark_fallback(c, c->prm.ir_tol));
-        int h[rmrcm::kNumFlags];
-        HIP_TRY(hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        c->n_fallback = h[rmrcm::FLAG_FALLBACK];
-        if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_setup(c, false, c->fb, 1, 1));
-    } else if (st != RMRCM_OK) {
-        return st;
-    }
+    TRY(refine_loop(c, 0));
+    // subdomains still above ir_tol (only if the refinement did not
+    // converge: both kernels return at once otherwise) are redone in FP64
+    HIP_TRY(rmrcm::launch_local_refine(c, 0, 0));   // measure only
+    HIP_TRY(rmrcm::launch_mark_fallback(c, c->prm.ir_tol));
+    HIP_TRY(rmrcm::launch_local_setup(c, false, c->fb, 1, 1));
     HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 0));
     if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 2));
+    HIP_TRY(rmrcm::launch_trace_correct(c, 1, 0));
     return RMRCM_OK;
 }
 
@@ -445,15 +447,18 @@ bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c); 
 
 // Every permeability-dependent step, enqueued on c->stream (no host
 // synchronisation in FP64 mode, so that it can be captured in a graph).
-int enqueue_setup(rmrcm_ctx* c) {
+// kcopy non-null: the permeability check also copies the permeability there
+// (a step reading the caller's array keeps the library's copy current).
+int enqueue_setup(rmrcm_ctx* c, double* kcopy = nullptr) {
     TRY(mark(c, 0));
     HIP_TRY(rmrcm::launch_fill_i32(c, c->flags, rmrcm::kNumFlags, 0));
-    HIP_TRY(rmrcm::launch_check_beta(c, nullptr));
+    HIP_TRY(rmrcm::launch_check_beta(c, kcopy));
     TRY(mark(c, 1));
     if (mixed(c)) {
         TRY(mixed_local_setup(c));
     } else {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
+        HIP_TRY(rmrcm::launch_trace_correct(c, 1, 0));
     }
     TRY(mark(c, 2));
     const bool ov = overlap(c);
@@ -509,6 +514,7 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     if (e == hipSuccess && r == RMRCM_OK) e = hipStreamWaitEvent(c->aux, c->ev_ls, 0);
     if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[13], c->aux);
     if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 1);
+    if (e == hipSuccess && r == RMRCM_OK) e = rmrcm::launch_trace_correct(c, 0, 1);
     if (e == hipSuccess && r == RMRCM_OK) e = hipEventRecord(c->ev[14], c->aux);
     // the particular merges of levels 2 and deeper start once the setup
     // merges have reached level 2, that of level 1 after its own: two
@@ -545,17 +551,18 @@ int enqueue_solve(rmrcm_ctx* c) {
     if (mixed(c)) {
         HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 0, 0));
         if (learned(c)) HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 2, 0));
-        if (c->n_fallback > 0) HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));
-        int it = 0;
-        double last = 0.0;
-        const int st = refine_loop(c, 1, &it, &last);
-        c->ir_iters_solve = it;
-        c->ir_resid_solve = last;
-        if (st != RMRCM_OK) return st;
+        HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));   // FP64-redone subdomains
+        HIP_TRY(rmrcm::launch_fill_i32(c, c->flags + rmrcm::FLAG_NOTCONV, 1, 0));
+        TRY(refine_loop(c, 1));
+        HIP_TRY(rmrcm::launch_ir_notconv(c));
         HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
         if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 2));
+        HIP_TRY(rmrcm::launch_trace_correct(c, 0, 1));
     }
-    if (!mixed(c)) HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
+    if (!mixed(c)) {
+        HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
+        HIP_TRY(rmrcm::launch_trace_correct(c, 0, 1));
+    }
     TRY(mark(c, 6));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_particular(c, d));
     TRY(mark(c, 7));
@@ -590,6 +597,7 @@ int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
         HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
     }
+    HIP_TRY(rmrcm::launch_trace_correct(c, 1, 1));
     TRY(mark(c, 2));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d, true));
     TRY(mark(c, 3));
@@ -740,7 +748,8 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
     if (prm->precision != RMRCM_FP64) {
         if ((r = dalloc(c, &c->P32, nsub * g.by * g.bx * g.bx)) ||
             (r = dalloc(c, &c->Wsc, nsub * R * n)) || (r = dalloc(c, &c->resid, nsub)) ||
-            (r = dalloc(c, &c->fb, nsub)))
+            (r = dalloc(c, &c->fb, nsub)) || (r = dalloc(c, &c->irst, 4)) ||
+            (r = dalloc(c, &c->irhist, 2 * rmrcm::kIrHist)))
             return fail(r);
     }
     if (prm->precision == RMRCM_MIXED_LEARNED) {
@@ -748,7 +757,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
         if ((r = rmrcm_cnn_load(prm->cnn_weights, 256, prm->device, &c->net)) != RMRCM_OK) return fail(r);
         if (c->net->S != g.bx || c->net->R != R) return fail(RMRCM_EINVAL);
         if ((r = dalloc(c, &c->lx, nsub * 2 * n)) || (r = dalloc(c, &c->ly, nsub * R * n)) ||
-            (r = dalloc(c, &c->lint, nsub)))
+            (r = dalloc(c, &c->lint, nsub)) || (r = dalloc(c, &c->gres, nsub)))
             return fail(r);
     }
     if ((r = alloc_levels(c)) != RMRCM_OK || (r = upload_levels(c)) != RMRCM_OK) return fail(r);
@@ -804,6 +813,7 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
     c->solve_recorded = true;
     const bool host_out = !is_device_ptr(pressure) || !is_device_ptr(flux);
     c->solved = true;
+    if (mixed(c)) c->check_pending = true;   // the refinement's convergence is known on the device
     if (host_out || c->stream == c->own_stream) {
         HIP_TRY(hipStreamSynchronize(c->stream));
         if (c->check_pending) {
@@ -870,10 +880,25 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         c->t_solve_ms[5] = elapsed(c->ev[9], c->ev[10]);
         c->t_solve_ms[6] = elapsed(c->ev[4], c->ev[10]);
     }
-    if (c->net && c->setup_recorded) {
+    if (mixed(c) && hipStreamSynchronize(c->stream) == hipSuccess) {
+        // refinement passes, last residuals, fallbacks and accepted
+        // surrogate bases of the last setup and solve, kept on the device
         int h[rmrcm::kNumFlags] = {};
-        if (hipMemcpy(h, c->flags, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess)
+        int st[4] = {};
+        double hist[2 * rmrcm::kIrHist] = {};
+        if (hipMemcpy(h, c->flags, sizeof(h), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(st, c->irst, sizeof(st), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(hist, c->irhist, sizeof(hist), hipMemcpyDeviceToHost) == hipSuccess) {
             c->n_accepted = h[rmrcm::FLAG_ACCEPTED];
+            c->n_fallback = h[rmrcm::FLAG_FALLBACK];
+            c->ir_iters_setup = st[1];
+            c->ir_iters_solve = st[3];
+            const int k0 = std::min(st[1], rmrcm::kIrHist), k1 = std::min(st[3], rmrcm::kIrHist);
+            c->ir_resid_setup = k0 > 0 ? hist[k0 - 1] : 0.0;
+            c->ir_resid_solve = k1 > 0 ? hist[rmrcm::kIrHist + k1 - 1] : 0.0;
+        } else {
+            (void)hipGetLastError();
+        }
     }
     char buf[2048];
     const int n = std::snprintf(
@@ -931,6 +956,21 @@ int rmrcm_export_local(rmrcm_ctx* c, float* features, double* basis, int32_t* in
     if (e != hipSuccess) return RMRCM_EDEVICE;
     if (interior)
         for (size_t k = 0; k < nsub; ++k) interior[k] = hi[k];
+    return RMRCM_OK;
+}
+
+int rmrcm_get_gate(rmrcm_ctx* c, double* residual, int32_t* accepted) {
+    if (!c || c->prm.precision != RMRCM_MIXED_LEARNED) return RMRCM_EINVAL;
+    if (!c->setup_recorded && !c->gstep) return RMRCM_ESTATE;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    const size_t nsub = (size_t)c->geo.mx * c->geo.my;
+    std::vector<double> r(nsub);
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(r.data(), c->gres, nsub * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < nsub; ++k) {
+        if (residual) residual[k] = r[k];
+        if (accepted) accepted[k] = r[k] <= c->prm.gate_tol ? 1 : 0;
+    }
     return RMRCM_OK;
 }
 
@@ -1289,14 +1329,13 @@ int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* co
             const int r = rmrcm_autotune(c);
             if (r != RMRCM_OK) return fail(r);
         }
-    // graphs of the FP64 members (the mixed path synchronises with the host
-    // between refinement passes and is enqueued eagerly)
+    // graphs of every member (the mixed path's refinement loop runs on the
+    // device, without host synchronisation)
     b->gsetup.assign(count, nullptr);
     b->gsolve.assign(count, nullptr);
     for (int i = 0; i < count; ++i) {
         rmrcm_ctx* c = b->m[i];
-        if (mixed(c)) continue;
-        int r = capture(c, b->streams[0], enqueue_setup, &b->gsetup[i]);
+        int r = capture(c, b->streams[0], [](rmrcm_ctx* cc) { return enqueue_setup(cc); }, &b->gsetup[i]);
         if (r == RMRCM_OK) r = capture(c, b->streams[0], enqueue_solve, &b->gsolve[i]);
         if (r != RMRCM_OK) return fail(r);
         ++b->graphs;
@@ -1396,10 +1435,21 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
     if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
     const bool dev = is_device_ptr(perm) && (!source || is_device_ptr(source)) &&
                      is_device_ptr(bc_value) && is_device_ptr(pressure) && is_device_ptr(flux);
-    if (mixed(c) || !dev) {
+    if (!dev) {
         TRY(rmrcm_refactor(c, perm));
         return rmrcm_solve(c, source, bc_value, pressure, flux);
     }
+    // FP64: the fused chain (the particular column carried through the local
+    // solves and the merges); mixed modes: the setup followed by the solve,
+    // their refinement loops on the device
+    auto body = [&](rmrcm_ctx* cc, double* kcopy) -> int {
+        if (!mixed(cc)) return enqueue_step_fused(cc, kcopy);
+        TRY(enqueue_setup(cc, kcopy));
+        TRY(mark(cc, 4));          // no inputs to upload
+        TRY(mark(cc, 5));
+        TRY(enqueue_solve(cc));
+        return mark(cc, 10);       // no outputs to download
+    };
     // the step's inputs and outputs in place of the context's own buffers
     double* po = c->pout;
     double* fo = c->fout;
@@ -1428,7 +1478,7 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
     };
     if (!c->step_graph) {
         int r = point(c);
-        if (r == RMRCM_OK) r = enqueue_step_fused(c, ko);
+        if (r == RMRCM_OK) r = body(c, ko);
         restore();
         TRY(r);
         c->setup_recorded = true;
@@ -1448,7 +1498,7 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
                 c, c->stream,
                 [&](rmrcm_ctx* cc) -> int {
                     TRY(point(cc));
-                    return enqueue_step_fused(cc, ko);
+                    return body(cc, ko);
                 },
                 &c->gstep);
             restore();

@@ -1412,14 +1412,16 @@ __global__ __launch_bounds__(64) void k_local_refine_mfma(Geo g, const double* _
                                                           const double* __restrict__ bcv,
                                                           float* __restrict__ Wsc,
                                                           double* __restrict__ resid,
-                                                          const int* __restrict__ mask, int apply) {
+                                                          const int* __restrict__ mask, int apply,
+                                                          const int* __restrict__ stop) {
     static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
     typedef Mfma<float> M;
     typedef M::v4 v4;
     constexpr int LT = BX + 4, NTL = BX / 16, PPL = BX * BX / 64, H = 64 / BX;
     constexpr int MAXC = 16;                // columns per lane kept in registers (ncol <= 16 H)
     const int sub = blockIdx.x;
-    if (mask && (part ? mask[sub] == 1 : mask[sub] != 0)) return;
+    if (stop && *stop) return;                   // the refinement has converged
+    if (mask && mask[sub] == 1) return;          // redone in FP64
     extern __shared__ __align__(16) char smem[];
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
     const int ncol = part ? 1 : R;
@@ -1654,6 +1656,339 @@ __global__ __launch_bounds__(64) void k_local_traces(Geo g, const double* __rest
     }
 }
 
+// ---------------------------------------------------------------- trace correction
+// First-order correction of the traces for the rounding of the local solves.
+// A trace is a linear functional of a local solution, T[a][b] = t_a . x_b
+// (less the conductance of the unit datum itself when a = b), where t_a, the
+// Robin conductances on the faces of slot a, is also the right-hand side e_a
+// of basis problem a (Section 2.1).  The local matrix A is symmetric, so for
+// the exact solution x*_b = A^{-1} e_b
+//     t_a . x*_b = t_a . x_b + (A^{-1} e_a) . (e_b - A x_b)
+//                = T[a][b] + Psi*_a . r_b,
+// and T[a][b] += Psi_a . r_b, with the residual r_b = e_b - A x_b formed in
+// FP64, gives the traces of the once-refined solutions up to terms of
+// second order, without the correction sweeps (the particular column alike,
+// with the particular right-hand side).  Where the local operator is stiff
+// (permeability contrast, small Robin parameter) a trace is a small
+// difference of cell pressures near a unit datum, and without the
+// correction its rounding reaches the interface values through the merges.
+//
+// One workgroup of four waves per subdomain, each wave a quarter of the
+// cells.  The products Psi^T R run on the matrix cores, 16 x 16 output
+// tiles: for the k-slice of cells c0 .. c0 + 3, lane l = x + 16 k holds
+// Psi_{16 ta + x}(c0 + k) as A operand and r_{16 tb + x}(c0 + k) as B
+// operand, the residual formed from the stencil coefficients staged in LDS
+// and the neighbouring basis values.  Up to 2 x 2 tiles per pass; the waves'
+// partial tiles are added in a fixed order.  basis: columns 0 .. R-1;
+// part: the particular column ld - 1 (source q, outer data bcv, solution
+// pbar).
+template <int BX>
+__global__ __launch_bounds__(256) void k_trace_correct(Geo g, const double* __restrict__ K,
+                                                       const int8_t* __restrict__ bct,
+                                                       const double* __restrict__ beta,
+                                                       const int* __restrict__ slotseg, int R,
+                                                       const double* __restrict__ Psi,
+                                                       const double* __restrict__ pbar,
+                                                       const double* __restrict__ q,
+                                                       const double* __restrict__ bcv,
+                                                       double* __restrict__ T, int ld, int basis,
+                                                       int part, const int* __restrict__ list) {
+    typedef Mfma<double>::v4 v4;
+    extern __shared__ __align__(16) char smem[];
+    const int sub = list ? list[blockIdx.x] : blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    const int TT = (R + 15) / 16;                 // 16-column tiles
+    const int TG = TT < 2 ? TT : 2;               // tiles per dimension and pass
+    char* sp = smem;
+    double* cf = carve<double>(sp, NF);
+    int* rs = carve<int>(sp, NF);
+    int* of = carve<int>(sp, NF);
+    double* co = carve<double>(sp, 3 * n);        // per cell: diagonal, coupling right, coupling up
+    double* red = carve<double>(sp, 4 * TG * TG * 256);
+    double* redp = carve<double>(sp, 4 * 16 * TT);
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    __syncthreads();
+    for (int c = tid; c < n; c += 256) {
+        double kv[5], dg, txr, tyu;
+        load_kstencil<BX>(g, K, I, J, c % BX, c / BX, kv);
+        stencil_coeffs<BX>(g, kv, cf, c % BX, c / BX, &dg, &txr, &tyu);
+        co[3 * c] = dg;
+        co[3 * c + 1] = txr;
+        co[3 * c + 2] = tyu;
+    }
+    __syncthreads();
+    // (A x)(c) for the column x of this subdomain
+    auto apply = [&](const double* x, int c) -> double {
+        const int i = c % BX, j = c / BX;
+        double v = co[3 * c] * x[c];
+        if (i > 0) v -= co[3 * (c - 1) + 1] * x[c - 1];
+        if (i < BX - 1) v -= co[3 * c + 1] * x[c + 1];
+        if (j > 0) v -= co[3 * (c - BX) + 2] * x[c - BX];
+        if (j < BY - 1) v -= co[3 * c + 2] * x[c + BX];
+        return v;
+    };
+    // right-hand side of basis problem b at cell c: the conductances of the
+    // cell's faces on slot b
+    auto ebasis = [&](int b, int c) -> double {
+        const int i = c % BX, j = c / BX;
+        double e = 0.0;
+        if (i == 0 && rs[j] == b) e += cf[j];
+        if (i == BX - 1 && rs[BY + j] == b) e += cf[BY + j];
+        if (j == 0 && rs[2 * BY + i] == b) e += cf[2 * BY + i];
+        if (j == BY - 1 && rs[2 * BY + BX + i] == b) e += cf[2 * BY + BX + i];
+        return e;
+    };
+    const size_t nn = (size_t)n;
+    const double* Ps = Psi + (size_t)sub * R * nn;
+    double* Ts = T + (size_t)sub * R * ld;
+    const int CW = ((n + 15) / 16) * 4;           // cells per wave, a multiple of 4
+    const int cb = w * CW;
+    if (basis) {
+        for (int ta0 = 0; ta0 < TT; ta0 += TG)
+            for (int tb0 = 0; tb0 < TT; tb0 += TG) {
+                v4 acc[2][2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) acc[u][v] = v4{0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < CW; k0 += 4) {
+                    const int c = cb + k0 + lk;
+                    double bo[2], ao[2];
+#pragma unroll
+                    for (int v = 0; v < 2; ++v) {
+                        const int b = 16 * (tb0 + v) + li;
+                        bo[v] = 0.0;
+                        if (c < n && b < R && tb0 + v < TT) {
+                            const double* xb = Ps + (size_t)b * nn;
+                            bo[v] = ebasis(b, c) - apply(xb, c);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const int a = 16 * (ta0 + u) + li;
+                        ao[u] = (c < n && a < R && ta0 + u < TT) ? Ps[(size_t)a * nn + c] : 0.0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+#pragma unroll
+                        for (int v = 0; v < 2; ++v) acc[u][v] = Mfma<double>::op(ao[u], bo[v], acc[u][v]);
+                }
+                for (int u = 0; u < TG; ++u)
+                    for (int v = 0; v < TG; ++v)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            red[((w * TG + u) * TG + v) * 256 + Mfma<double>::row(lane, r) * 16 + li] =
+                                acc[u][v][r];
+                __syncthreads();
+                for (int t = tid; t < TG * TG * 256; t += 256) {
+                    const int uv = t / 256, e = t % 256;
+                    const int a = 16 * (ta0 + uv / TG) + e / 16, b = 16 * (tb0 + uv % TG) + e % 16;
+                    const double s = ((red[t] + red[TG * TG * 256 + t]) + red[2 * TG * TG * 256 + t]) +
+                                     red[3 * TG * TG * 256 + t];
+                    if (ta0 + uv / TG < TT && tb0 + uv % TG < TT && a < R && b < R && ss[a] >= 0 &&
+                        ss[b] >= 0)
+                        Ts[(size_t)a * ld + b] += s;
+                }
+                __syncthreads();
+            }
+    }
+    if (part) {
+        const double* qs = q;
+        const double* pb = pbar + (size_t)sub * nn;
+        for (int ta = 0; ta < TT; ++ta) {
+            const int a = 16 * ta + li;
+            double acc = 0.0;
+            for (int k0 = 0; k0 < CW; k0 += 4) {
+                const int c = cb + k0 + lk;
+                if (c < n && a < R) {
+                    const int i = c % BX, j = c / BX;
+                    const double qv = qs[(size_t)(J * BY + j) * g.nx + I * BX + i];
+                    const double rp = part_rhs<BX>(g, cf, of, bct, bcv, qv, i, j) - apply(pb, c);
+                    acc += Ps[(size_t)a * nn + c] * rp;
+                }
+            }
+            acc += __shfl_xor(acc, 16);
+            acc += __shfl_xor(acc, 32);
+            if (lk == 0) redp[w * 16 * TT + a] = acc;
+        }
+        __syncthreads();
+        for (int a = tid; a < R; a += 256) {
+            const double s = ((redp[a] + redp[16 * TT + a]) + redp[2 * 16 * TT + a]) + redp[3 * 16 * TT + a];
+            if (ss[a] >= 0) Ts[(size_t)a * ld + ld - 1] += s;
+        }
+    }
+}
+
+// The same correction for at most 32 slots, shaped for memory-level
+// parallelism: sixteen waves per subdomain, wave w taking 4 KS consecutive
+// cells, KB products (4 cells each) per batch whose global loads (every
+// column's value at the cell and its four neighbours, and with part the
+// particular solution's and the source) are all issued before any is used.
+// Lane l = x + 16 k of a product holds column 16 t + x (tile t) at cell
+// c0 + k: the A operand is that value, the B operand the residual the lane
+// forms from it and its neighbours with the stencil coefficients staged in
+// LDS.  The waves' partial tiles are added in a fixed order.
+template <int BX, int TT>
+__global__ __launch_bounds__(1024) void k_trace_correct_mlp(Geo g, const double* __restrict__ K,
+                                                           const int8_t* __restrict__ bct,
+                                                           const double* __restrict__ beta,
+                                                           const int* __restrict__ slotseg, int R,
+                                                           const double* __restrict__ Psi,
+                                                           const double* __restrict__ pbar,
+                                                           const double* __restrict__ q,
+                                                           const double* __restrict__ bcv,
+                                                           double* __restrict__ T, int ld, int basis,
+                                                           int part) {
+    typedef Mfma<double>::v4 v4;
+    constexpr int KB = 4;                          // products per batch
+    constexpr int NW = 16;                         // waves
+    extern __shared__ __align__(16) char smem[];
+    const int sub = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int* ss = slotseg + (size_t)sub * R;
+    char* sp = smem;
+    double* cf = carve<double>(sp, NF);
+    int* rs = carve<int>(sp, NF);
+    int* of = carve<int>(sp, NF);
+    double* co = carve<double>(sp, 3 * n);
+    double* red = carve<double>(sp, NW * TT * TT * 256);
+    double* redp = carve<double>(sp, NW * 32);
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    __syncthreads();
+    for (int c = tid; c < n; c += 1024) {
+        double kv[5], dg, txr, tyu;
+        load_kstencil<BX>(g, K, I, J, c % BX, c / BX, kv);
+        stencil_coeffs<BX>(g, kv, cf, c % BX, c / BX, &dg, &txr, &tyu);
+        co[3 * c] = dg;
+        co[3 * c + 1] = txr;
+        co[3 * c + 2] = tyu;
+    }
+    __syncthreads();
+    const size_t nn = (size_t)n;
+    const double* Ps = Psi + (size_t)sub * R * nn;
+    const double* pb = pbar + (size_t)sub * nn;
+    const double* qs = q + (size_t)(J * BY) * g.nx + (size_t)I * BX;
+    double* Ts = T + (size_t)sub * R * ld;
+    const int KS = (n / 4 + NW - 1) / NW;          // products per wave
+    v4 acc[TT][TT];
+#pragma unroll
+    for (int u = 0; u < TT; ++u)
+#pragma unroll
+        for (int v = 0; v < TT; ++v) acc[u][v] = v4{0.0, 0.0, 0.0, 0.0};
+    double pp[TT];
+#pragma unroll
+    for (int u = 0; u < TT; ++u) pp[u] = 0.0;
+    for (int kb = 0; kb < KS; kb += KB) {
+        double x[KB][TT][5];                       // centre, left, right, below, above
+        double xp[KB][6];                          // the same of the particular, and the source
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int c = 4 * (w * KS + kb + k) + lk;
+            const bool in = kb + k < KS && c < n;
+            const int i = c % BX, j = c / BX;
+#pragma unroll
+            for (int t = 0; t < TT; ++t) {
+                const int b = 16 * t + li;
+                const double* xb = Ps + (size_t)(b < R ? b : 0) * nn;
+                const bool ok = in && b < R;
+                x[k][t][0] = ok ? xb[c] : 0.0;
+                x[k][t][1] = ok && i > 0 ? xb[c - 1] : 0.0;
+                x[k][t][2] = ok && i < BX - 1 ? xb[c + 1] : 0.0;
+                x[k][t][3] = ok && j > 0 ? xb[c - BX] : 0.0;
+                x[k][t][4] = ok && j < BY - 1 ? xb[c + BX] : 0.0;
+            }
+            if (part) {
+                xp[k][0] = in ? pb[c] : 0.0;
+                xp[k][1] = in && i > 0 ? pb[c - 1] : 0.0;
+                xp[k][2] = in && i < BX - 1 ? pb[c + 1] : 0.0;
+                xp[k][3] = in && j > 0 ? pb[c - BX] : 0.0;
+                xp[k][4] = in && j < BY - 1 ? pb[c + BX] : 0.0;
+                xp[k][5] = in ? qs[(size_t)j * g.nx + i] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int c = 4 * (w * KS + kb + k) + lk;
+            const bool in = kb + k < KS && c < n;
+            const int cc = in ? c : 0;
+            const int i = cc % BX, j = cc / BX;
+            const double d0 = co[3 * cc];
+            const double cl = i > 0 ? co[3 * (cc - 1) + 1] : 0.0;
+            const double cr = co[3 * cc + 1];
+            const double cd = j > 0 ? co[3 * (cc - BX) + 2] : 0.0;
+            const double cu = co[3 * cc + 2];
+            double ro[TT];
+#pragma unroll
+            for (int t = 0; t < TT; ++t) {
+                const int b = 16 * t + li;
+                double e = 0.0;
+                if (in && b < R) {
+                    if (i == 0 && rs[j] == b) e += cf[j];
+                    if (i == BX - 1 && rs[BY + j] == b) e += cf[BY + j];
+                    if (j == 0 && rs[2 * BY + i] == b) e += cf[2 * BY + i];
+                    if (j == BY - 1 && rs[2 * BY + BX + i] == b) e += cf[2 * BY + BX + i];
+                }
+                const double* xv = x[k][t];
+                const double av = d0 * xv[0] - cl * xv[1] - cr * xv[2] - cd * xv[3] - cu * xv[4];
+                ro[t] = (in && b < R) ? e - av : 0.0;
+            }
+            if (basis) {
+#pragma unroll
+                for (int u = 0; u < TT; ++u)
+#pragma unroll
+                    for (int v = 0; v < TT; ++v) acc[u][v] = Mfma<double>::op(x[k][u][0], ro[v], acc[u][v]);
+            }
+            if (part) {
+                const double* pv = xp[k];
+                const double av = d0 * pv[0] - cl * pv[1] - cr * pv[2] - cd * pv[3] - cu * pv[4];
+                const double rp = in ? part_rhs<BX>(g, cf, of, bct, bcv, pv[5], i, j) - av : 0.0;
+#pragma unroll
+                for (int u = 0; u < TT; ++u) pp[u] += x[k][u][0] * rp;
+            }
+        }
+    }
+    if (basis) {
+#pragma unroll
+        for (int u = 0; u < TT; ++u)
+#pragma unroll
+            for (int v = 0; v < TT; ++v)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    red[((w * TT + u) * TT + v) * 256 + Mfma<double>::row(lane, r) * 16 + li] = acc[u][v][r];
+    }
+    if (part) {
+#pragma unroll
+        for (int u = 0; u < TT; ++u) {
+            double a = pp[u];
+            a += __shfl_xor(a, 16);
+            a += __shfl_xor(a, 32);
+            if (lk == 0) redp[w * 32 + 16 * u + li] = a;
+        }
+    }
+    __syncthreads();
+    if (basis) {
+        const int W1 = TT * TT * 256;
+        for (int t = tid; t < W1; t += 1024) {
+            const int uv = t / 256, e = t % 256;
+            const int a = 16 * (uv / TT) + e / 16, b = 16 * (uv % TT) + e % 16;
+            double sm = 0.0;
+            for (int ww = 0; ww < NW; ++ww) sm += red[ww * W1 + t];
+            if (a < R && b < R && ss[a] >= 0 && ss[b] >= 0) Ts[(size_t)a * ld + b] += sm;
+        }
+    }
+    if (part)
+        for (int a = tid; a < R; a += 1024) {
+            double sm = 0.0;
+            for (int ww = 0; ww < NW; ++ww) sm += redp[ww * 32 + a];
+            if (ss[a] >= 0) Ts[(size_t)a * ld + ld - 1] += sm;
+        }
+}
+
 // ---------------------------------------------------------------- refinement
 // One step of iterative refinement of the mixed-precision local solves:
 //     r = b - A x   (FP64, the five-point operator applied on the fly)
@@ -1672,11 +2007,14 @@ __global__ __launch_bounds__(64) void k_local_refine(Geo g, const double* __rest
                                                      const double* __restrict__ bcv,
                                                      float* __restrict__ Wsc,
                                                      double* __restrict__ resid,
-                                                     const int* __restrict__ mask, int apply) {
+                                                     const int* __restrict__ mask, int apply,
+                                                     const int* __restrict__ stop) {
     const int sub = blockIdx.x;
-    // mask: 0 plain, 1 redone in FP64 (skipped), 2 basis accepted from the
-    // surrogate (FP32 factor only: its particular solution is refined)
-    if (mask && (part ? mask[sub] == 1 : mask[sub] != 0)) return;
+    // stop: set once the refinement has converged.  mask: 0 plain, 1 redone
+    // in FP64 (skipped), 2 basis taken from the surrogate as the starting
+    // iterate (FP32 factor only; refined like the others)
+    if (stop && *stop) return;
+    if (mask && mask[sub] == 1) return;
     extern __shared__ __align__(16) char smem[];
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
     const int ncol = part ? 1 : R;
@@ -1820,30 +2158,45 @@ __global__ __launch_bounds__(64) void k_local_refine(Geo g, const double* __rest
 // Subdomains whose refinement did not reach the tolerance are redone in
 // FP64: mask = 1 marks them; their number is added to flags[3].
 __global__ void k_mark_fallback(int nsub, const double* __restrict__ resid, double tol,
-                                int* __restrict__ fb, int* __restrict__ flags) {
+                                int* __restrict__ fb, int* __restrict__ flags,
+                                const int* __restrict__ conv) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nsub || fb[s] != 0) return;
+    if (*conv || s >= nsub || fb[s] == 1) return;
     const int f = !(resid[s] <= tol);
     fb[s] = f;
     if (f) atomicAdd(&flags[FLAG_FALLBACK], 1);
 }
 
-// Largest residual over all subdomains that are not marked (in flags[..]
-// order: one block, fixed summation order).
+// Largest residual of a refinement pass over the subdomains it refined (one
+// block, fixed order), kept in the pass history; st = {converged, passes}:
+// the pass count advances and converged is set once the residual measured
+// before a correction is within tol.  Nothing happens after convergence.
 __global__ __launch_bounds__(256) void k_max_resid(int nsub, const double* __restrict__ resid,
-                                                   const int* __restrict__ mask, int part,
-                                                   double* __restrict__ out) {
+                                                   const int* __restrict__ mask, double tol,
+                                                   int* __restrict__ st, double* __restrict__ hist,
+                                                   int nhist) {
     __shared__ double s[256];
+    if (st[0]) return;
     double m = 0.0;
     for (int t = threadIdx.x; t < nsub; t += 256)
-        if (!mask || mask[t] == 0 || (part && mask[t] == 2)) m = fmax(m, resid[t]);
+        if (!mask || mask[t] != 1) m = fmax(m, resid[t]);
     s[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = s[0];
+    if (threadIdx.x == 0) {
+        const int k = st[1];
+        if (k < nhist) hist[k] = s[0];
+        st[1] = k + 1;
+        if (s[0] <= tol) st[0] = 1;
+    }
+}
+
+// A refinement of the particular solutions that did not converge.
+__global__ void k_ir_notconv(const int* __restrict__ st, int* __restrict__ flags) {
+    if (!st[0]) flags[FLAG_NOTCONV] = 1;
 }
 
 // ---------------------------------------------------------------- K1p
@@ -2210,7 +2563,7 @@ static hipError_t refine_bx(rmrcm_ctx* c, int part, int apply) {
             const int nsub = c->geo.mx * c->geo.my;
             hipLaunchKernelGGL(k_local_refine_mfma<BX>, dim3(nsub), dim3(64), lds, c->stream, c->geo,
                                c->K, c->bct, c->beta, L.slotseg, R, c->P32, part ? c->pbar : c->Psi,
-                               part, c->q, c->bcv, c->Wsc, c->resid, c->fb, apply);
+                               part, c->q, c->bcv, c->Wsc, c->resid, c->fb, apply, c->irst + 2 * part);
             return hipGetLastError();
         }
     }
@@ -2223,7 +2576,7 @@ static hipError_t refine_bx(rmrcm_ctx* c, int part, int apply) {
     const int nsub = c->geo.mx * c->geo.my;
     hipLaunchKernelGGL(k_local_refine<BX>, dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
                        c->bct, c->beta, L.slotseg, R, c->P32, part ? c->pbar : c->Psi, part, c->q,
-                       c->bcv, c->Wsc, c->resid, c->fb, apply);
+                       c->bcv, c->Wsc, c->resid, c->fb, apply, c->irst + 2 * part);
     return hipGetLastError();
 }
 
@@ -2234,6 +2587,36 @@ static hipError_t traces_bx(rmrcm_ctx* c, int part, const int* mask, int want) {
     hipLaunchKernelGGL(k_local_traces<BX>, dim3(nsub), dim3(64), 0, c->stream, c->geo, c->K, c->bct,
                        c->beta, L.slotseg, L.nslot, part ? c->pbar : c->Psi, part, L.T, L.ld, mask,
                        want);
+    return hipGetLastError();
+}
+
+// The correction on the subdomains of list (nsub of them; null: all).
+template <int BX>
+static hipError_t trace_correct_bx(rmrcm_ctx* c, int basis, int part, const int* list, int nsub) {
+    const Level& L = c->levels[c->D];
+    const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY), n = BX * BY;
+    if (R <= 32) {
+        const int TT = (R + 15) / 16;
+        const size_t lds = carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4) + carve_bytes(3 * n, 8) +
+                           carve_bytes(16 * TT * TT * 256, 8) + carve_bytes(16 * 32, 8);
+        auto go = [&](auto kern) -> hipError_t {
+            hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3(nsub), dim3(1024), lds, c->stream, c->geo, c->K, c->bct, c->beta,
+                               L.slotseg, R, c->Psi, c->pbar, c->q, c->bcv, L.T, L.ld, basis, part);
+            return hipGetLastError();
+        };
+        return TT == 1 ? go(k_trace_correct_mlp<BX, 1>) : go(k_trace_correct_mlp<BX, 2>);
+    }
+    const int TT = (R + 15) / 16, TG = TT < 2 ? TT : 2;
+    const size_t lds = carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4) + carve_bytes(3 * n, 8) +
+                       carve_bytes(4 * TG * TG * 256, 8) + carve_bytes(4 * 16 * TT, 8);
+    hipError_t e = hipFuncSetAttribute((const void*)k_trace_correct<BX>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_trace_correct<BX>, dim3(nsub), dim3(256), lds, c->stream, c->geo, c->K, c->bct,
+                       c->beta, L.slotseg, R, c->Psi, c->pbar, c->q, c->bcv, L.T, L.ld, basis, part, list);
     return hipGetLastError();
 }
 
@@ -2290,6 +2673,14 @@ hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int
 hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply) {
     RMRCM_BX_SWITCH((refine_bx<4>(c, part, apply)), (refine_bx<8>(c, part, apply)),
                     (refine_bx<16>(c, part, apply)), (refine_bx<32>(c, part, apply)))
+}
+
+hipError_t launch_trace_correct(rmrcm_ctx* c, int basis, int part) {
+    const int nsub = c->geo.mx * c->geo.my;
+    RMRCM_BX_SWITCH((trace_correct_bx<4>(c, basis, part, nullptr, nsub)),
+                    (trace_correct_bx<8>(c, basis, part, nullptr, nsub)),
+                    (trace_correct_bx<16>(c, basis, part, nullptr, nsub)),
+                    (trace_correct_bx<32>(c, basis, part, nullptr, nsub)))
 }
 
 hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want) {
@@ -2351,9 +2742,10 @@ __global__ __launch_bounds__(256) void k_features(Geo g, const double* __restric
 // Residual gate of the surrogate's basis: for every column a of an interior
 // subdomain, rel_a = |A y_a - e_a|_2 / |e_a|_2 in FP64, with A the local
 // Robin matrix and e_a the right-hand side of the basis problem of slot a
-// (the Robin conductance on the slot's faces).  The subdomain is accepted
-// (fb = 2, its basis written to Psi in FP64) when every rel_a <= tau; the
-// largest rel_a goes to resid, accepted subdomains are counted.
+// (the Robin conductance on the slot's faces).  The prediction is accepted
+// (fb = 2, written to Psi in FP64 as the starting iterate of the FP64-residual
+// refinement) when every rel_a <= tau; the largest rel_a goes to resid (the
+// gate residual of the subdomain), accepted subdomains are counted.
 template <int BX>
 __global__ __launch_bounds__(256) void k_gate(Geo g, const double* __restrict__ K,
                                               const int8_t* __restrict__ bct,
@@ -2440,7 +2832,7 @@ template <int BX>
 static hipError_t gate_bx(rmrcm_ctx* c, const float* Y, const int* interior, double tau) {
     const Level& L = c->levels[c->D];
     hipLaunchKernelGGL(k_gate<BX>, dim3(c->geo.mx * c->geo.my), dim3(256), 0, c->stream, c->geo, c->K,
-                       c->bct, c->beta, L.slotseg, L.nslot, Y, interior, tau, c->Psi, c->fb, c->resid,
+                       c->bct, c->beta, L.slotseg, L.nslot, Y, interior, tau, c->Psi, c->fb, c->gres,
                        c->flags);
     return hipGetLastError();
 }
@@ -2466,13 +2858,19 @@ hipError_t launch_features(rmrcm_ctx* c, float* x, int* interior) {
 hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol) {
     const int nsub = c->geo.mx * c->geo.my;
     hipLaunchKernelGGL(k_mark_fallback, dim3((nsub + 255) / 256), dim3(256), 0, c->stream, nsub,
-                       c->resid, tol, c->fb, c->flags);
+                       c->resid, tol, c->fb, c->flags, (const int*)c->irst);
     return hipGetLastError();
 }
 
-hipError_t launch_max_resid(rmrcm_ctx* c, int part, double* out) {
+hipError_t launch_max_resid(rmrcm_ctx* c, int part) {
     const int nsub = c->geo.mx * c->geo.my;
-    hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(256), 0, c->stream, nsub, c->resid, c->fb, part, out);
+    hipLaunchKernelGGL(k_max_resid, dim3(1), dim3(256), 0, c->stream, nsub, c->resid, c->fb, c->prm.ir_tol,
+                       c->irst + 2 * part, c->irhist + kIrHist * part, kIrHist);
+    return hipGetLastError();
+}
+
+hipError_t launch_ir_notconv(rmrcm_ctx* c) {
+    hipLaunchKernelGGL(k_ir_notconv, dim3(1), dim3(1), 0, c->stream, (const int*)(c->irst + 2), c->flags);
     return hipGetLastError();
 }
 

@@ -47,6 +47,8 @@ struct MergeArgs {
     int* flags;
     int pin;                    // 1 at the root of an all-Neumann problem
     double* work;               // scratch of merges with g > 128 (see kBigWork)
+    const unsigned char* tflag; // [nnodes][ntiles]: 64-slot tiles holding an active slot
+    int ntiles;                 // (the particular column nslot counts as active)
 };
 
 // Element-wise copy t -> st(t, ld(t)) for t < n over the workgroup, in
@@ -1440,10 +1442,120 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
             }
 }
 
+// C = beta C + alpha A B for untransposed row-major operands, one 64 x 64
+// tile of C per workgroup and batch entry blockIdx.z, four waves of 32 x 32
+// (2 x 2 matrix-core tiles), K in steps of 32 through LDS with the next
+// step's operands loaded into registers while the current step's products
+// run (one load latency per step hidden behind 32 products per wave).  Each
+// load instruction reads whole rows of a tile (32 consecutive doubles of A,
+// 64 of B per group of lanes).  Optional tile flags skip the tiles of C whose
+// rows (rflag[z][tile row]) or columns (cflag[z][tile column]) are known to
+// be zero in A or B: the inactive boundary slots of a merge, whose trace
+// rows and columns are zero; such a tile is left as it is, or zeroed when
+// beta = 0.
+struct GemmNN {
+    int m, n, k;
+    const double* A;
+    long long lda, sa;
+    const double* B;
+    long long ldb, sb;
+    double* C;
+    long long ldc, sc;
+    double alpha, beta;
+    const unsigned char* rflag;   // [batch][rfs] or null
+    const unsigned char* cflag;   // [batch][cfs] or null
+    int rfs, cfs;
+    int skr0, skr1;               // row tiles [skr0, skr1) skipped in every batch entry
+};
+
+constexpr int kGemmKT = 32;
+
+__global__ __launch_bounds__(256) void k_gemm_nn_f64(GemmNN g) {
+    __shared__ double As[64 * (kGemmKT + 1)];
+    __shared__ double Bs[kGemmKT * 65];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64, z = blockIdx.z;
+    double* C = g.C + (size_t)z * g.sc;
+    const bool skip = (g.rflag && !g.rflag[(size_t)z * g.rfs + blockIdx.y]) ||
+                      (g.cflag && !g.cflag[(size_t)z * g.cfs + blockIdx.x]) ||
+                      ((int)blockIdx.y >= g.skr0 && (int)blockIdx.y < g.skr1);
+    if (skip) {
+        if (g.beta == 0.0)
+            for (int t = tid; t < 64 * 64; t += 256) {
+                const int r = bm + t / 64, cc = bn + t % 64;
+                if (r < g.m && cc < g.n) C[(size_t)r * g.ldc + cc] = 0.0;
+            }
+        return;
+    }
+    const double* A = g.A + (size_t)z * g.sa;
+    const double* B = g.B + (size_t)z * g.sb;
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    // loader roles: A rows (tid / 32) + 8 q, column tid % 32; B rows
+    // (tid / 64) + 4 q, column tid % 64
+    const int ar = tid >> 5, ak = tid & 31, br = tid >> 6, bc = tid & 63;
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = bm + ar + 8 * q, kk = k0 + ak;
+            ra[q] = (r < g.m && kk < g.k) ? A[(size_t)r * g.lda + kk] : 0.0;
+            const int kb = k0 + br + 4 * q, cc = bn + bc;
+            rb[q] = (kb < g.k && cc < g.n) ? B[(size_t)kb * g.ldb + cc] : 0.0;
+        }
+    };
+    v4d acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    for (int k0 = 0; k0 < g.k; k0 += kGemmKT) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            As[(ar + 8 * q) * (kGemmKT + 1) + ak] = ra[q];
+            Bs[(br + 4 * q) * 65 + bc] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + kGemmKT < g.k) load(k0 + kGemmKT);
+#pragma unroll
+        for (int s4 = 0; s4 < kGemmKT / 4; ++s4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[(wr + 16 * a + li) * (kGemmKT + 1) + 4 * s4 + lk];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[(4 * s4 + lk) * 65 + wc + 16 * b + li];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = bm + wr + 16 * a + lk + 4 * v, cc = bn + wc + 16 * b + li;
+                if (r < g.m && cc < g.n) {
+                    double* cp = C + (size_t)r * g.ldc + cc;
+                    *cp = g.beta == 0.0 ? g.alpha * acc[a][b][v] : g.beta * *cp + g.alpha * acc[a][b][v];
+                }
+            }
+}
+
 static hipError_t gemm(rmrcm_ctx* c, int batch, int m, int n, int k, int ta, const double* A,
                        long long lda, long long sa, int tb, const double* B, long long ldb, long long sb,
-                       double* C, long long ldc, long long sc, double alpha, double beta) {
+                       double* C, long long ldc, long long sc, double alpha, double beta,
+                       const unsigned char* rflag = nullptr, int rfs = 0,
+                       const unsigned char* cflag = nullptr, int cfs = 0, int skr0 = 0, int skr1 = 0) {
     if (m <= 0 || n <= 0) return hipSuccess;
+    if (!ta && !tb) {
+        GemmNN g{m, n, k, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta, rflag, cflag, rfs, cfs, skr0, skr1};
+        hipLaunchKernelGGL(k_gemm_nn_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
+        return hipGetLastError();
+    }
     GemmArgs g{m, n, k, ta, tb, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta};
     hipLaunchKernelGGL(k_gemm_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
     return hipGetLastError();
@@ -1537,45 +1649,87 @@ __global__ __launch_bounds__(256) void k_qd_big_fix(double* X, long long ld, lon
     }
 }
 
-// Scratch of the inverse of order n: Y and W (128 x (n - 128)) per split.
-__host__ inline size_t big_inv_work(int n) {
-    size_t w = 0;
-    for (int r = n - 128; r > 0; r -= 128) w += 2 * 128 * (size_t)r;
-    return w;
+// Scratch of the inverse of order n: the column panel (n x 128), the pivot
+// block (128 x 128) and the row panel (128 x n) of a Gauss-Jordan step.
+__host__ inline size_t big_inv_work(int n) { return 2 * 128 * (size_t)n + 128 * 128; }
+
+// Gauss-Jordan step at columns k0 .. k0 + kb - 1 of the n x n block X (row
+// stride ld, merge stride sx): the column panel C = X[:, k0:k0+kb] and the
+// pivot block Pw = X[k0:k0+kb, k0:k0+kb] into the merge's scratch.
+__global__ __launch_bounds__(256) void k_gj_prep(const double* X, long long ld, long long sx, int n,
+                                                 int k0, int kb, double* W, long long sw) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)n * kb) return;
+    const int i = (int)(t / kb), j = (int)(t % kb);
+    const double* Xb = X + (size_t)blockIdx.y * sx;
+    double* C = W + (size_t)blockIdx.y * sw;
+    double* Pw = C + (size_t)n * 128;
+    const double v = Xb[(size_t)i * ld + k0 + j];
+    C[(size_t)i * kb + j] = v;
+    if (i >= k0 && i < k0 + kb) Pw[(size_t)(i - k0) * kb + j] = v;
 }
 
-// Symmetric inverse in place of the n x n block at X (row stride ld, merge
-// stride sx) of every merge; scratch from Yb (merge stride sy).
+// End of the step: row panel K of X = R (the pivot rows times the inverted
+// pivot block), its diagonal block = the inverted pivot block.
+__global__ __launch_bounds__(256) void k_gj_finish(double* X, long long ld, long long sx, int n, int k0,
+                                                   int kb, const double* W, long long sw) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)n * kb) return;
+    const int i = (int)(t / n), j = (int)(t % n);
+    double* Xb = X + (size_t)blockIdx.y * sx;
+    const double* Pw = W + (size_t)blockIdx.y * sw + (size_t)n * 128;
+    const double* Rw = Pw + 128 * 128;
+    Xb[(size_t)(k0 + i) * ld + j] =
+        (j >= k0 && j < k0 + kb) ? Pw[(size_t)i * kb + (j - k0)] : Rw[(size_t)i * n + j];
+}
+
+// In-place inverse of the n x n block at X (row stride ld, merge stride sx)
+// of every merge, by blocked Gauss-Jordan without pivoting (the blocks of D
+// and S are definite, so their leading blocks and Schur complements are), in
+// panels of 128: per step K with pivot block P = X_KK^{-1} (registers, one
+// workgroup per merge),
+//     R = P X_K,:      X_I,: -= X_IK R  (I != K)      X_IK = -X_IK P      X_K,: = R, X_KK = P
+// with the old column panel X_:,K kept in scratch.  Every product has K = 128
+// (short chains over many workgroups); scratch per merge from Wb (stride sw).
 static hipError_t qd_big_inverse(rmrcm_ctx* c, const MergeArgs& a, double* X, int n, long long ld,
-                                 long long sx, double* Yb, long long sy) {
+                                 long long sx, double* Wb, long long sw) {
     const int nb = a.nnodes;
     if (n <= 128) {
         hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, ld, sx, n, a.flags);
         return hipGetLastError();
     }
-    const int r = n - 128;
-    double* Y = Yb;
-    double* W = Yb + 128 * (size_t)r;
+    double* Cw = Wb;                         // n x kb (row stride kb)
+    double* Pw = Wb + (size_t)n * 128;       // kb x kb
+    double* Rw = Pw + 128 * 128;             // kb x n
     hipError_t e;
-    hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, ld, sx, 128, a.flags);
-    // Y = A^{-1} C^T (C^T: the top right block)
-    if ((e = gemm(c, nb, 128, r, 128, 0, X, ld, sx, 0, X + 128, ld, sx, Y, r, sy, 1.0, 0.0))) return e;
-    // F <- F - C Y (C = rows 128.., columns ..128)
-    double* F = X + 128 * ld + 128;
-    if ((e = gemm(c, nb, r, r, 128, 0, X + 128 * ld, ld, sx, 0, Y, r, sy, F, ld, sx, -1.0, 1.0))) return e;
-    if ((e = qd_big_inverse(c, a, F, r, ld, sx, W + 128 * (size_t)r, sy))) return e;
-    // W = Y F'^{-1};  A^{-1} <- A^{-1} + W Y^T
-    if ((e = gemm(c, nb, 128, r, r, 0, Y, r, sy, 0, F, ld, sx, W, r, sy, 1.0, 0.0))) return e;
-    if ((e = gemm(c, nb, 128, 128, r, 0, W, r, sy, 1, Y, r, sy, X, ld, sx, 1.0, 1.0))) return e;
-    hipLaunchKernelGGL(k_qd_big_fix, dim3((128 * r + 255) / 256, nb), dim3(256), 0, c->stream, X, ld, sx,
-                       (const double*)W, sy, r, 0, n);
+    for (int k0 = 0; k0 < n; k0 += 128) {
+        const int kb = n - k0 < 128 ? n - k0 : 128;
+        const unsigned blocks = (unsigned)(((long long)n * kb + 255) / 256);
+        hipLaunchKernelGGL(k_gj_prep, dim3(blocks, nb), dim3(256), 0, c->stream, (const double*)X, ld, sx, n, k0,
+                           kb, Wb, sw);
+        hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, Pw, (long long)kb, sw,
+                           kb, a.flags);
+        // R = P X_K,:  (the pivot block's own columns give P X_KK = I, replaced at the end)
+        if ((e = gemm(c, nb, kb, n, kb, 0, Pw, kb, sw, 0, X + (size_t)k0 * ld, ld, sx, Rw, n, sw, 1.0, 0.0)))
+            return e;
+        const int s0 = k0 / 64, s1 = (k0 + kb + 63) / 64;     // row tiles of panel K
+        // X_I,: -= X_IK R for the other rows; then their column panel -X_IK P
+        if ((e = gemm(c, nb, n, n, kb, 0, Cw, kb, sw, 0, Rw, n, sw, X, ld, sx, -1.0, 1.0, nullptr, 0, nullptr, 0,
+                      s0, s1)))
+            return e;
+        if ((e = gemm(c, nb, n, kb, kb, 0, Cw, kb, sw, 0, Pw, kb, sw, X + k0, ld, sx, -1.0, 0.0, nullptr, 0,
+                      nullptr, 0, s0, s1)))
+            return e;
+        hipLaunchKernelGGL(k_gj_finish, dim3(blocks, nb), dim3(256), 0, c->stream, X, ld, sx, n, k0, kb,
+                           (const double*)Wb, sw);
+    }
     return hipGetLastError();
 }
 
 // Scratch per merge with g > 128: the inverses', three g x (nslot + 1) column
-// blocks of the apply, and beyond 256 the gathered trace rows (nslot x 2g).
+// blocks of the apply, and the gathered trace rows (nslot x 2g).
 __host__ inline size_t big_work(int g, int nslot) {
-    return big_inv_work(g) + 3 * (size_t)g * (nslot + 1) + (g > 256 ? (size_t)nslot * 2 * g : 0);
+    return big_inv_work(g) + 3 * (size_t)g * (nslot + 1) + (size_t)nslot * 2 * g;
 }
 
 // Scratch per merge with g > 128 (merge stride big_work): Y and W of the
@@ -1640,7 +1794,7 @@ __global__ __launch_bounds__(256) void k_qd_x_big(MergeArgs a, int col0, int nco
     X[(size_t)(g + i) * a.ld + col0 + cc] = -(s + d);
 }
 
-// Parent traces of merges beyond 256 gamma segments as a matrix product:
+// Parent traces of merges beyond 128 gamma segments as a matrix product:
 // Tp = direct + A X with A[o][k g + i] = T_k[o's slot in child k][gamma_k(i)]
 // for the child k that owns slot o (zero in the other child's half), the
 // terms and their sum being those of k_qd_trace_mfma.
@@ -1676,19 +1830,17 @@ __global__ __launch_bounds__(256) void k_qd_trace_direct_big(MergeArgs a, int co
 
 static hipError_t qd_trace_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
     const int g = a.g, nb = a.nnodes;
-    if (g <= 256) {
-        hipLaunchKernelGGL(k_qd_trace_mfma<256>, dim3(nb, (a.nslot + 63) / 64, (ncol + 15) / 16), dim3(256), 0,
-                           c->stream, a, col0, ncol);
-        return hipGetLastError();
-    }
     const long long sw = (long long)big_work(g, a.nslot);
     double* Ar = a.work + big_inv_work(g) + 3 * (size_t)g * (a.nslot + 1);
     const long long nr = (long long)a.nslot * 2 * g, nd = (long long)a.nslot * ncol;
     hipLaunchKernelGGL(k_qd_trace_rows_big, dim3((unsigned)((nr + 255) / 256), nb), dim3(256), 0, c->stream, a, Ar, sw);
     hipLaunchKernelGGL(k_qd_trace_direct_big, dim3((unsigned)((nd + 255) / 256), nb), dim3(256), 0, c->stream, a,
                        col0, ncol);
+    // rows of inactive parent slots are zero in Ar, columns of inactive slots
+    // zero in X
     return gemm(c, nb, a.nslot, ncol, 2 * g, 0, Ar, 2 * g, sw, 0, a.X + col0, a.ld, (long long)a.xi * a.ld,
-                a.Tp + col0, a.ld, (long long)a.nslot * a.ld, 1.0, 1.0);
+                a.Tp + col0, a.ld, (long long)a.nslot * a.ld, 1.0, 1.0, a.tflag, a.ntiles,
+                col0 == 0 ? a.tflag : nullptr, a.ntiles);
 }
 
 static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
@@ -1708,10 +1860,13 @@ static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int n
     const dim3 grid((g * ncol + 255) / 256, nb);
     hipLaunchKernelGGL(k_qd_rhs_big, grid, dim3(256), 0, c->stream, a, col0, ncol, RS, RD, sw);
     hipError_t e;
-    if ((e = gemm(c, nb, g, ncol, g, 0, D, g, sx, 0, RD, ncol, sw, TT, ncol, sw, 1.0, 0.0))) return e;   // t
-    if ((e = gemm(c, nb, g, ncol, g, 0, B, g, sx, 0, TT, ncol, sw, RS, ncol, sw, -1.0, 1.0))) return e;  // u
-    if ((e = gemm(c, nb, g, ncol, g, 0, S, g, sx, 0, RS, ncol, sw, RD, ncol, sw, 1.0, 0.0))) return e;   // s
-    if ((e = gemm(c, nb, g, ncol, g, 0, E, g, sx, 0, RD, ncol, sw, TT, ncol, sw, -1.0, 1.0))) return e;  // d
+    // columns of inactive slots are zero in every right-hand side block
+    const unsigned char* cf = col0 == 0 ? a.tflag : nullptr;
+    const int cs = a.ntiles;
+    if ((e = gemm(c, nb, g, ncol, g, 0, D, g, sx, 0, RD, ncol, sw, TT, ncol, sw, 1.0, 0.0, nullptr, 0, cf, cs))) return e;   // t
+    if ((e = gemm(c, nb, g, ncol, g, 0, B, g, sx, 0, TT, ncol, sw, RS, ncol, sw, -1.0, 1.0, nullptr, 0, cf, cs))) return e;  // u
+    if ((e = gemm(c, nb, g, ncol, g, 0, S, g, sx, 0, RS, ncol, sw, RD, ncol, sw, 1.0, 0.0, nullptr, 0, cf, cs))) return e;   // s
+    if ((e = gemm(c, nb, g, ncol, g, 0, E, g, sx, 0, RD, ncol, sw, TT, ncol, sw, -1.0, 1.0, nullptr, 0, cf, cs))) return e;  // d
     hipLaunchKernelGGL(k_qd_x_big, grid, dim3(256), 0, c->stream, a, col0, ncol, (const double*)RD,
                        (const double*)TT, sw);
     return hipGetLastError();
@@ -1871,6 +2026,8 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     a.flags = c->flags;
     a.pin = (d == 0 && !c->any_dirichlet) ? 1 : 0;
     a.work = P.work;
+    a.tflag = P.tflag;
+    a.ntiles = (P.nslot + 1 + 63) / 64;
     return a;
 }
 
@@ -1947,7 +2104,15 @@ static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int
         case 16: return qd_columns<16>(c, a, col0, ncol, trace, ct);
         case 32: return qd_columns<32>(c, a, col0, ncol, trace, ct);
         case 64: return qd_columns<64>(c, a, col0, ncol, trace, ct);
-        case 128: return qd_columns<128>(c, a, col0, ncol, trace, ct);
+        case 128:
+            // long parent columns: the products over many workgroups (the
+            // blocks are stored as for the longer interfaces)
+            if (a.work) {
+                hipError_t e = qd_apply_big(c, a, col0, ncol);
+                if (e != hipSuccess || !trace) return e;
+                return qd_trace_big(c, a, col0, ncol);
+            }
+            return qd_columns<128>(c, a, col0, ncol, trace, ct);
         case 256: {
             hipError_t e = qd_apply_big(c, a, col0, ncol);
             if (e != hipSuccess || !trace) return e;
@@ -1957,14 +2122,14 @@ static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int
     return hipErrorInvalidValue;
 }
 
-size_t merge_work_doubles(const Level& L) { return L.g > 128 ? big_work(L.g, L.nslot) : 0; }
+size_t merge_work_doubles(const Level& L) { return L.g >= 128 ? big_work(L.g, L.nslot) : 0; }
 
 bool merge_apply_tunable(rmrcm_ctx* c, int d) {
     if (!(d > 0 && d < c->D)) return false;
     const MergeArgs a = make_args(c, d);
     if (small_merge_ok(a, d, a.nslot) || small_merge_ok(a, d, a.nslot + 1)) return false;   // fused merge
     if (cols_fused(a, true)) return false;                                                    // fused columns
-    return qd_tier(a.g) != 256;
+    return qd_tier(a.g) < 128;
 }
 
 hipError_t launch_merge_apply(rmrcm_ctx* c, int d, int ct) {

@@ -53,8 +53,11 @@ struct Level {
     int* gseg = nullptr;       // [nnodes][g] global segment of every gamma segment
     double* M = nullptr;       // [nnodes][4 g^2]: D^{-1}, E, S^{-1}, B of the merge
     double* X = nullptr;       // [nnodes][xi][ld] coefficients of every column
-    double* work = nullptr;    // scratch of merges with 128 < g <= 256 (merge_work_doubles per node)
+    double* work = nullptr;    // scratch of merges with g > 128 (merge_work_doubles per node)
+    unsigned char* tflag = nullptr;   // [nnodes][(nslot + 64) / 64] 64-slot tiles with an active
+                                      // slot (or the particular column)
     std::vector<int> h_pmap, h_gmap, h_slotseg, h_gseg;
+    std::vector<unsigned char> h_tflag;
 };
 
 }  // namespace rmrcm
@@ -94,7 +97,9 @@ struct rmrcm_ctx {
     float* Wsc = nullptr;                    // mixed mode: sweep scratch [nsub][nslot][bx*by]
     double* resid = nullptr;                 // mixed mode: relative residual per subdomain
     int* fb = nullptr;                       // mixed mode: 1 = subdomain redone in FP64
-    double* dscal = nullptr;                 // device scalar (max residual)
+    double* dscal = nullptr;                 // device scalar
+    int* irst = nullptr;                     // mixed mode: {converged, passes} of setup, solve
+    double* irhist = nullptr;                // mixed mode: [2][kIrHist] residual per pass
     double* Psi = nullptr;                   // [nsub][nslot][bx*by] basis pressures
     double* pbar = nullptr;                  // [nsub][bx*by] particular pressures
     double* glo = nullptr;                   // [nseg] Robin datum on the low side
@@ -133,6 +138,7 @@ struct rmrcm_ctx {
     float* lx = nullptr;                     // [nsub][2][S][S] features
     float* ly = nullptr;                     // [nsub][R][S][S] predicted basis
     int* lint = nullptr;                     // [nsub] interior mask
+    double* gres = nullptr;                  // [nsub] gate residual of the prediction
     int n_accepted = 0;
     double ir_resid_setup = 0.0, ir_resid_solve = 0.0;
 };
@@ -153,8 +159,17 @@ hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int
                                    int do_traces);
 hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply);
 hipError_t launch_local_traces(rmrcm_ctx* c, int part, const int* mask, int want);
+// First-order correction of the finest traces for the rounding of the local
+// solves (basis: columns 0..R-1; part: the particular column), from the
+// FP64 residuals of the stored solutions.
+hipError_t launch_trace_correct(rmrcm_ctx* c, int basis, int part);
+// The device side of the mixed-precision refinement: irst[2 part] is set
+// once a pass measured every residual within ir_tol (later passes return at
+// once), irst[2 part + 1] counts the passes, irhist keeps their residuals;
+// the fallback marking runs only when the setup refinement did not converge.
 hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol);
-hipError_t launch_max_resid(rmrcm_ctx* c, int part, double* out);
+hipError_t launch_max_resid(rmrcm_ctx* c, int part);
+hipError_t launch_ir_notconv(rmrcm_ctx* c);
 // part: the particular column is eliminated with the basis columns (their
 // traces already hold it), as launch_merge_particular would below the top.
 hipError_t launch_merge_setup(rmrcm_ctx* c, int depth, bool part = false);
@@ -182,6 +197,9 @@ bool merge_apply_tunable(rmrcm_ctx* c, int depth);
 
 // Device error flag slots.
 enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2, FLAG_FALLBACK = 3,
-       FLAG_BAD_DATA = 4, FLAG_ACCEPTED = 5, kNumFlags = 8 };
+       FLAG_BAD_DATA = 4, FLAG_ACCEPTED = 5, FLAG_NOTCONV = 6, kNumFlags = 8 };
+
+// Residual history entries per refinement (setup, solve) kept on the device.
+constexpr int kIrHist = 16;
 
 }  // namespace rmrcm

@@ -51,7 +51,7 @@ EXPORTS = [
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
     "rmrcm_strerror", "rmrcm_autotune", "rmrcm_batch_create", "rmrcm_batch_refactor",
     "rmrcm_batch_solve", "rmrcm_batch_sync", "rmrcm_batch_get_stats", "rmrcm_batch_destroy",
-    "rmrcm_export_local", "rmrcm_cnn_create", "rmrcm_cnn_num_params", "rmrcm_cnn_set_stream",
+    "rmrcm_export_local", "rmrcm_get_gate", "rmrcm_cnn_create", "rmrcm_cnn_num_params", "rmrcm_cnn_set_stream",
     "rmrcm_cnn_set_params", "rmrcm_cnn_get_params", "rmrcm_cnn_forward", "rmrcm_cnn_loss_grad",
     "rmrcm_cnn_train_step", "rmrcm_cnn_save", "rmrcm_cnn_load", "rmrcm_cnn_destroy",
 ]
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.rmrcm_batch_destroy.restype = None
     lib.rmrcm_export_local.argtypes = [vp, vp, vp, vp]
     lib.rmrcm_export_local.restype = ctypes.c_int
+    lib.rmrcm_get_gate.argtypes = [vp, vp, vp]
+    lib.rmrcm_get_gate.restype = ctypes.c_int
     i32 = ctypes.c_int32
     lib.rmrcm_cnn_create.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.POINTER(vp)]
     lib.rmrcm_cnn_create.restype = ctypes.c_int
@@ -285,6 +287,16 @@ def rmrcm_export_local(ctx, features, basis=None):
     _check(lib().rmrcm_export_local(ctx, fp, bp, ctypes.c_void_p(interior.ctypes.data)),
            "rmrcm_export_local")
     return interior
+
+
+def rmrcm_get_gate(ctx, nsub):
+    """(residual [nsub] float64, accepted [nsub] int32) of the learned mode's
+    residual gate at the last setup."""
+    r = np.zeros(nsub)
+    a = np.zeros(nsub, dtype=np.int32)
+    _check(lib().rmrcm_get_gate(ctx, ctypes.c_void_p(r.ctypes.data), ctypes.c_void_p(a.ctypes.data)),
+           "rmrcm_get_gate")
+    return r, a
 
 
 class Net:

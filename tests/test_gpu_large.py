@@ -38,7 +38,10 @@ from workloads import config_problem
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-10
-STEP_TOL = 1e-12
+# step (particular column carried through the merges) vs setup + solve (a
+# particular chain of its own): each is within about 1e-11 of the exact
+# discrete solution on these fields, so they agree to that order
+STEP_TOL = 1e-11
 
 
 @pytest.fixture(scope="module")
@@ -103,24 +106,44 @@ def eager(L, prob):
         S.close()
 
 
-def interface_residuals(prob, F, U):
-    """eq. 13.2 (sum of the two one-sided segment fluxes) and eq. 14.2
-    divided by beta (their difference minus 2 |e| U) for every segment,
-    relative to the largest face flux; segments in the documented order."""
+def interface_residuals(prob, p, F, U):
+    """Backward errors of eq. 13.2 (the sum of the two one-sided fluxes of a
+    segment) and eq. 14.2 divided by beta (their difference minus 2 |e| U)
+    for every segment (documented order): each residual divided by the size
+    of the terms that cancel in it, the segment's Robin face conductances
+    |f| / (rho + beta) on both sides times max |p| (the one-sided fluxes
+    are those conductances times pressure differences)."""
     nx, ny, bx, by, sg = prob.nx, prob.ny, prob.sub_nx, prob.sub_ny, prob.seg
     mx, my = nx // bx, ny // by
     hx, hy = prob.lx / nx, prob.ly / ny
+    K = prob.K
     # vertical lines I = 1..mx-1: E faces of column I bx - 1, W faces of I bx
     flo_v = F[1][:, bx - 1:nx - 1:bx].reshape(ny // sg, sg, mx - 1).sum(1).T.ravel()
     fhi_v = F[0][:, bx:nx:bx].reshape(ny // sg, sg, mx - 1).sum(1).T.ravel()
     flo_h = F[3][by - 1:ny - 1:by, :].reshape(my - 1, nx // sg, sg).sum(2).ravel()
     fhi_h = F[2][by:ny:by, :].reshape(my - 1, nx // sg, sg).sum(2).ravel()
+
+    # conductance sums per segment
+    klo = K[:, bx - 1:nx - 1:bx]                      # (ny, mx-1)
+    khi = K[:, bx:nx:bx]
+    keff = (2 * klo * khi / (klo + khi)).reshape(ny // sg, sg, mx - 1).mean(1)   # (lines, mx-1)
+    beta = prob.alpha * sg * hy / keff
+    bf = np.repeat(beta, sg, axis=0)                  # per face (ny, mx-1)
+    cs_v = (hy / (hx / (2 * klo) + bf) + hy / (hx / (2 * khi) + bf))
+    cs_v = cs_v.reshape(ny // sg, sg, mx - 1).sum(1).T.ravel()
+    klo = K[by - 1:ny - 1:by, :]                      # (my-1, nx)
+    khi = K[by:ny:by, :]
+    keff = (2 * klo * khi / (klo + khi)).reshape(my - 1, nx // sg, sg).mean(2)
+    beta = prob.alpha * sg * hx / keff
+    bf = np.repeat(beta, sg, axis=1)
+    cs_h = (hx / (hy / (2 * klo) + bf) + hx / (hy / (2 * khi) + bf))
+    cs_h = cs_h.reshape(my - 1, nx // sg, sg).sum(2).ravel()
     flo = np.concatenate([flo_v, flo_h])
     fhi = np.concatenate([fhi_v, fhi_h])
+    scale = np.concatenate([cs_v, cs_h]) * np.abs(p).max()
     length = np.concatenate([np.full(flo_v.size, sg * hy), np.full(flo_h.size, sg * hx)])
-    scale = np.abs(F).max()
-    r13 = np.abs(flo + fhi).max() / scale
-    r14 = np.abs(flo - fhi - 2.0 * length * U).max() / scale
+    r13 = (np.abs(flo + fhi) / scale).max()
+    r14 = (np.abs(flo - fhi - 2.0 * length * U) / scale).max()
     return r13, r14
 
 
@@ -191,8 +214,9 @@ def test_full_size_invariants(env, big, k):
     p, F, U, P = bench_step(L, torch, prob)
     assert np.isfinite(p).all() and np.isfinite(F).all()
     assert cell_backward_error(prob, p, F) < 1e-12
-    r13, r14 = interface_residuals(prob, F, U)
-    assert r13 < 1e-10 and r14 < 1e-8, (r13, r14)
+    r13, r14 = interface_residuals(prob, p, F, U)
+    say("[gpu] interface backward errors %.3e %.3e" % (r13, r14))
+    assert r13 < 1e-12 and r14 < 1e-12, (r13, r14)
     assert p.min() >= -1e-9 and p.max() <= 1.0 + 1e-9, (p.min(), p.max())
     say("[gpu] full workload %d: setup + solve" % k)
     pe, Fe = eager(L, prob)
