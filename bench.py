@@ -105,6 +105,9 @@ def algorithmic_work(prob):
     w["local_step_flops"] = float(np.sum(n * (bx * bx + 3 * bx) + 4.0 * n * bx * (r_act + 1)))
     # particular: two sweeps reading the factor store once each way, q in, pbar out
     w["local_part_bytes"] = float(nsub * (2 * 8 * by * bx * bx) + ncell * (8 + 8 + 8))
+    # trace correction: the basis and the particular solution read once, with
+    # the source and the permeability (the traces written are negligible)
+    w["correct_bytes"] = float(8.0 * n * np.sum(r_act) + ncell * (8 + 8 + 8))
     # reconstruction: basis read once, pbar + K in, p + 4 fluxes out
     w["recon_bytes"] = float(8.0 * n * np.sum(r_act) + ncell * (8 + 8 + 8 + 32))
     mf = 0.0
@@ -300,12 +303,14 @@ def _rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def measure(prob, precision, steps, warmup, stream, arrays, **extra):
+def measure(prob, precision, steps, warmup, stream, arrays, downscale_reps=0, **extra):
     """Time `steps` full solves (rmrcm_step: refactor + solve; a replayed HIP
     graph for FP64) after `warmup`; then a few untimed steps launch by
-    launch for the library's phase timers."""
+    launch for the library's phase timers; with downscale_reps, that many
+    downscalings of the last solution (rmrcm_downscale on device arrays,
+    after one untimed call that allocates its buffers)."""
     import torch
-    from paper_2009_07965_amd import Solver
+    from paper_2009_07965_amd import Solver, rmrcm_downscale
     K, bct, q, bcv = arrays
     dev = K.device
     p_out = torch.zeros((prob.ny, prob.nx), dtype=torch.float64, device=dev)
@@ -337,9 +342,21 @@ def measure(prob, precision, steps, warmup, stream, arrays, **extra):
             phases.append(S.stats())
         S.set_step_graph(True)
         S.sync()
+        ds_ms = None
+        if downscale_reps:
+            pd = torch.zeros_like(p_out)
+            fd = torch.zeros_like(f_out)
+            rmrcm_downscale(S.ctx, q, bcv, p_out, f_out, pd, fd)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            for _ in range(downscale_reps):
+                rmrcm_downscale(S.ctx, q, bcv, p_out, f_out, pd, fd)
+            torch.cuda.synchronize()
+            ds_ms = (time.perf_counter() - t2) * 1e3 / downscale_reps
+            del pd, fd
     finally:
         S.close()
-    out = {"ms": (t1 - t0) * 1e3 / steps, "phases": phases,
+    out = {"ms": (t1 - t0) * 1e3 / steps, "phases": phases, "downscale_ms": ds_ms,
            "p": p_out.cpu().numpy(), "f": f_out.cpu().numpy()}
     del p_out, f_out
     return out
@@ -359,7 +376,8 @@ def run_workload(cfg, modes, args, stream):
     arrays = (torch.from_numpy(prob.K).to(dev), torch.from_numpy(prob.bc_type).to(dev),
               torch.from_numpy(prob.q).to(dev), torch.from_numpy(prob.bc_value).to(dev))
     runs, learned_info = {}, None
-    runs["fp64"] = measure(prob, RMRCM_FP64, args.steps, args.warmup, stream, arrays)
+    runs["fp64"] = measure(prob, RMRCM_FP64, args.steps, args.warmup, stream, arrays,
+                           downscale_reps=args.downscale_reps)
     if "mixed" in modes:
         runs["mixed"] = measure(prob, RMRCM_MIXED, args.steps, args.warmup, stream, arrays,
                                 ir_tol=args.ir_tol)
@@ -401,6 +419,7 @@ def phase_report(prob, runs, best):
         return float(np.mean([x[key][sub] for x in phases]))
 
     t = {"beta": avg("setup_ms", "beta"), "local_setup": avg("setup_ms", "local"),
+         "trace_correct": avg("setup_ms", "trace_correct"),
          "merges": avg("setup_ms", "merge") + avg("solve_ms", "merge"),
          "local_particular": avg("solve_ms", "local"), "down": avg("solve_ms", "down"),
          "reconstruct": avg("solve_ms", "reconstruct")}
@@ -412,6 +431,9 @@ def phase_report(prob, runs, best):
     pr = {
         "local_setup": {"bound": "alu", "algorithmic": lflops, "unit": "TFLOP/s",
                         "achieved": lflops / (t["local_setup"] * 1e-3) / 1e12, "peak": lpeak / 1e12},
+        "trace_correct": {"bound": "hbm", "algorithmic": work["correct_bytes"], "unit": "GB/s",
+                          "achieved": work["correct_bytes"] / (t["trace_correct"] * 1e-3) / 1e9,
+                          "peak": PEAK_HBM / 1e9},
         "merges": {"bound": "alu", "algorithmic": work["merge_flops"], "unit": "TFLOP/s",
                    "achieved": work["merge_flops"] / (t["merges"] * 1e-3) / 1e12,
                    "peak": PEAK_FP64 / 1e12},
@@ -423,14 +445,17 @@ def phase_report(prob, runs, best):
         v["ms"] = t[k]
         v["frac"] = v["achieved"] / v["peak"]
         v["share_of_step"] = t[k] / total if total > 0 else None
-    # the dominant kernel: the longest single launch (the local setup is one
-    # launch in FP64, the reconstruction one launch in every mode; the
-    # merges are some 10 launches per level)
-    dom = "local_setup" if t["local_setup"] >= t["reconstruct"] else "reconstruct"
+    # the dominant kernel: the longest single launch (the local setup, the
+    # trace correction and the reconstruction are one launch each in FP64;
+    # the merges are some 10 launches per level, reported as a phase)
+    dom = max(("local_setup", "trace_correct", "reconstruct"), key=lambda k: t[k])
     d = pr[dom]
     if dom == "local_setup" and fp64 and prob.sub_nx in (16, 32):
         nct = -(-(2 * (prob.sub_nx + prob.sub_ny) // prob.seg) // 16)
         kname = "k_local_setup_twist<%d, %d, true>" % (prob.sub_nx, nct if nct <= 2 else 0)
+    elif dom == "trace_correct":
+        R = 2 * (prob.sub_nx + prob.sub_ny) // prob.seg
+        kname = "k_trace_correct_lds<%d, %d, 64>" % (prob.sub_nx, 1 if R <= 16 else 2)
     else:
         kname = "k_local_setup" if dom == "local_setup" else "k_reconstruct<%d>" % prob.sub_nx
     scale = 1e12 if d["unit"] == "TFLOP/s" else 1e9
@@ -460,6 +485,8 @@ def main():
     ap.add_argument("--fp64-only", action="store_true", help="FP64 only, no secondary workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (counter calibration)")
+    ap.add_argument("--downscale-reps", type=int, default=3,
+                    help="timed downscalings of the FP64 solution of the main workload (0: skip)")
     ap.add_argument("--ensemble", type=int, default=256,
                     help="members of the ensemble batch measured beside the main line (0: skip)")
     args = ap.parse_args()
@@ -504,6 +531,13 @@ def main():
     }
     if learned_info:
         out["surrogate"] = learned_info
+    ds = runs["fp64"].get("downscale_ms")
+    if ds:
+        # the flux post-processing (not part of a step): the Neumann local
+        # factorisation and solve of every subdomain plus the averaged
+        # skeleton fluxes and the flux assembly
+        out["downscale"] = {"ms": ds, "cells_per_s": prob.ncells / (ds * 1e-3),
+                            "arrays": "device", "reps": args.downscale_reps}
     if calib:
         out["copy_calibration"] = calib
     sec = {}

@@ -101,11 +101,22 @@ typedef struct {
     double gate_tol;         /* learned: residual gate tau >= 0; default 1e-6 */
     const char* cnn_weights; /* learned: weight file (required in that mode) */
     int32_t device;          /* HIP device ordinal */
+    uint64_t mem_cap;        /* device bytes a context may take (the plan of
+                                rmrcm_plan_bytes); 0 = no limit.  A setup whose
+                                plan exceeds it returns RMRCM_ENOMEM before any
+                                device work. */
 } rmrcm_params;
 
 /* Fill *p with defaults (alpha 1, FP64, unit square, device 0); the
  * geometry fields are zeroed and must be set by the caller. */
 void rmrcm_default_params(rmrcm_params* p);
+
+/* Device memory plan of a context with these parameters, in bytes: every
+ * array rmrcm_setup would allocate (basis, factor store, traces and merge
+ * workspaces of every level, inputs, outputs; the surrogate network of the
+ * learned mode, which allocates its own, is not included).  Host arithmetic
+ * only: no device is needed.  Returns the status validation would. */
+int rmrcm_plan_bytes(const rmrcm_params* prm, uint64_t* bytes);
 
 /* Build a context: every step that depends on the permeability and on the
  * boundary-condition TYPES only (they enter the local operators):
@@ -144,20 +155,48 @@ int rmrcm_refactor(rmrcm_ctx* ctx, const double* perm);
  * or EDEVICE. */
 int rmrcm_sync(rmrcm_ctx* ctx);
 
+/* Downscaling (Section 4 leaves the recovery of fine-scale conservation
+ * across the skeleton to downscaling methods): from an MRCM solution of
+ * this context's problem (pressure ny*nx and the four one-sided outward
+ * fluxes 4*ny*nx, as rmrcm_solve returns them) and the same source (NULL:
+ * zero) and bc_value, a pressure and a flux that are single-valued on every
+ * face and conservative in every cell.  Each fine skeleton face takes the
+ * mean of its two one-sided fluxes, (F_a - F_b) / 2 outward from a; every
+ * subdomain's fine problem is solved again (FP64, band Cholesky of the
+ * local matrix without Robin terms) with these fluxes prescribed on its
+ * skeleton faces and the outer data; a subdomain with no Dirichlet face
+ * takes the input's mean pressure over its cells.  Interior fluxes come
+ * from the new pressure by the two-point law.  Arrays host or device; the
+ * call waits for its work.  The first call allocates a second factor store
+ * and staging (not part of rmrcm_plan_bytes; the memory cap applies).
+ * Errors: EINVAL, ENOMEM, EDEVICE, ESINGULAR. */
+int rmrcm_downscale(rmrcm_ctx* ctx, const double* source, const double* bc_value, const double* pressure,
+                    const double* flux, double* pressure_out, double* flux_out);
+
+/* Mixed modes: the refinement tolerance and pass count of later setups
+ * (rmrcm_refactor, rmrcm_step) and solves, in place of those the context
+ * was built with (rmrcm_params.ir_tol, ir_max_iter; same meaning).  A solve
+ * whose particular refinement does not reach ir_tol within ir_max_iter
+ * passes reports RMRCM_ENOTCONV.  RMRCM_ENOTSUP for an FP64 context,
+ * RMRCM_EINVAL for ir_tol <= 0 or ir_max_iter < 1.  A captured step graph
+ * is dropped (captured again by the next step). */
+int rmrcm_set_refinement(rmrcm_ctx* ctx, double ir_tol, int32_t ir_max_iter);
+
 /* rmrcm_refactor(perm) followed by rmrcm_solve(source, bc_value, pressure,
  * flux) as one unit, with the same arguments and results up to rounding.
- * For an FP64 context whose arrays are all in device memory the whole step
- * is captured once as a HIP graph of one chain and replayed: the particular
- * problem (Section 2.1) is solved beside the basis in the local setup and
- * its column eliminated with the basis columns in every merge (Section 3.2),
- * the kernels read the caller's arrays and write pressures and fluxes in
- * place; the graph is captured again when any pointer differs from the
- * previous call's; the phase timers of rmrcm_get_stats keep the values of
- * the last refactor or solve run outside such a graph.  Asynchronous on a
- * stream set
- * with rmrcm_set_stream (device errors, including incompatible all-Neumann
- * data, are returned by rmrcm_sync); otherwise waits.  Other contexts and
- * host arrays: exactly rmrcm_refactor + rmrcm_solve.
+ * When every array is in device memory the whole step is captured once as a
+ * HIP graph of one chain and replayed, the kernels reading the caller's
+ * arrays and writing pressures and fluxes in place; the graph is captured
+ * again when any pointer differs from the previous call's.  FP64 contexts:
+ * the particular problem (Section 2.1) is solved beside the basis in the
+ * local setup and its column eliminated with the basis columns in every
+ * merge (Section 3.2).  Mixed modes: the setup and the solve, their
+ * refinement loops running on the device.  The phase timers of
+ * rmrcm_get_stats keep the values of the last refactor or solve run outside
+ * such a graph.  Asynchronous on a stream set with rmrcm_set_stream (device
+ * errors, including incompatible all-Neumann data, are returned by
+ * rmrcm_sync); otherwise waits.  Host arrays: exactly rmrcm_refactor +
+ * rmrcm_solve.
  * Errors: those of rmrcm_refactor and rmrcm_solve. */
 int rmrcm_step(rmrcm_ctx* ctx, const double* perm, const double* source, const double* bc_value,
                double* pressure, double* flux);
@@ -260,9 +299,9 @@ int rmrcm_autotune(rmrcm_ctx* ctx);
  * types and precision.  Every member is an ordinary context (set up by
  * rmrcm_setup); the batch enqueues the members' work on a pool of streams,
  * largest member first, so that small members fill the device together.
- * For FP64 members the permeability-dependent work and the solve are each
- * captured once as a HIP graph and replayed; mixed-precision members are
- * enqueued directly (their refinement waits on the host between passes).
+ * Every member's permeability-dependent work and solve are each captured
+ * once as a HIP graph and replayed (the refinement loops of mixed-precision
+ * members run on the device, without host waits).
  * All-Neumann members check the compatibility of their data on the device
  * (EINVAL at the next rmrcm_batch_sync when violated). */
 typedef struct rmrcm_batch rmrcm_batch;

@@ -12,6 +12,9 @@ from .rmrcm import (  # noqa: F401
     Net,
     rmrcm_export_local,
     rmrcm_get_gate,
+    rmrcm_plan_bytes,
+    rmrcm_set_refinement,
+    rmrcm_downscale,
     rmrcm_autotune,
     RMRCMError,
     load_library,

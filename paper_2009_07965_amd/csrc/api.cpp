@@ -66,11 +66,18 @@ void report_hip(hipError_t e, const char* what, int line) {
 // arena (the allocation-free entry point) the array is carved from it at a
 // 256-byte boundary and NOT filled here: the caller zero-fills the used part
 // of the arena once every array is carved; RMRCM_ETOOBIG when it does not fit.
+// In a memory plan (c->counting) only the bytes are added up.  With a memory
+// cap, an array that would take the context past it is RMRCM_ENOMEM.
 template <typename T>
 int dalloc(rmrcm_ctx* c, T** p, size_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
     const size_t bytes = count * sizeof(T);
+    if (c->counting) {
+        c->device_bytes += bytes;
+        return RMRCM_OK;
+    }
+    if (!c->arena && c->prm.mem_cap && c->device_bytes + bytes > c->prm.mem_cap) return RMRCM_ENOMEM;
     if (c->arena) {
         const size_t off = (c->arena_used + 255) & ~(size_t)255;
         const size_t end = (off + bytes + 255) & ~(size_t)255;
@@ -268,6 +275,50 @@ int alloc_levels(rmrcm_ctx* c) {
     return RMRCM_OK;
 }
 
+// Every device array of a context built by rmrcm_setup (the surrogate
+// network of the learned mode allocates its own).
+int alloc_arrays(rmrcm_ctx* c) {
+    const Geo& g = c->geo;
+    const size_t ncell = (size_t)g.nx * g.ny;
+    const size_t nbf = 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+    const size_t nsub = (size_t)g.mx * g.my;
+    const size_t n = (size_t)g.bx * g.by;
+    const int R = c->levels[c->D].nslot;
+    TRY(dalloc(c, &c->K, ncell));
+    TRY(dalloc(c, &c->bct, nbf));
+    TRY(dalloc(c, &c->beta, g.nseg));
+    TRY(dalloc(c, &c->seglen, g.nseg));
+    TRY(dalloc(c, &c->Pstore, nsub * g.by * g.bx * g.bx));
+    TRY(dalloc(c, &c->Psi, nsub * R * n));
+    TRY(dalloc(c, &c->pbar, nsub * n));
+    TRY(dalloc(c, &c->glo, g.nseg));
+    TRY(dalloc(c, &c->ghi, g.nseg));
+    TRY(dalloc(c, &c->q, ncell));
+    TRY(dalloc(c, &c->bcv, nbf));
+    TRY(dalloc(c, &c->pout, ncell));
+    TRY(dalloc(c, &c->fout, 4 * ncell));
+    TRY(dalloc(c, &c->Uout, g.nseg));
+    TRY(dalloc(c, &c->Pout, g.nseg));
+    TRY(dalloc(c, &c->flags, rmrcm::kNumFlags));
+    TRY(dalloc(c, &c->gauge, 256));
+    TRY(dalloc(c, &c->dscal, 1));
+    if (c->prm.precision != RMRCM_FP64) {
+        TRY(dalloc(c, &c->P32, nsub * g.by * g.bx * g.bx));
+        TRY(dalloc(c, &c->Wsc, nsub * R * n));
+        TRY(dalloc(c, &c->resid, nsub));
+        TRY(dalloc(c, &c->fb, nsub));
+        TRY(dalloc(c, &c->irst, 4));
+        TRY(dalloc(c, &c->irhist, 2 * rmrcm::kIrHist));
+    }
+    if (c->prm.precision == RMRCM_MIXED_LEARNED) {
+        TRY(dalloc(c, &c->lx, nsub * 2 * n));
+        TRY(dalloc(c, &c->ly, nsub * R * n));
+        TRY(dalloc(c, &c->lint, nsub));
+        TRY(dalloc(c, &c->gres, nsub));
+    }
+    return alloc_levels(c);
+}
+
 // The host tables of every level into their device arrays, in stream order.
 int upload_levels(rmrcm_ctx* c) {
     auto up = [&](int* dst, const std::vector<int>& src) -> int {
@@ -298,6 +349,11 @@ void free_all(rmrcm_ctx* c) {
         if (p && own) (void)hipFree(p);
     };
     f(c->down_tab);
+    f(c->ds_P);
+    f(c->ds_q);
+    f(c->ds_pb);
+    f(c->ds_pin);
+    f(c->ds_stage);
     c->down_tab = nullptr;
     for (Level& L : c->levels) {
         f(L.T);
@@ -375,6 +431,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 bool mixed(const rmrcm_ctx* c) { return c->prm.precision != RMRCM_FP64; }
+int mark(rmrcm_ctx* c, int i);
 
 // Refinement passes, enqueued without host synchronisation (so that the
 // mixed path can be captured in a graph): ir_max_iter passes of correction
@@ -429,6 +486,7 @@ int mixed_local_setup(rmrcm_ctx* c) {
     HIP_TRY(rmrcm::launch_local_setup(c, false, c->fb, 1, 1));
     HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 0));
     if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 0, c->fb, 2));
+    TRY(mark(c, 15));
     HIP_TRY(rmrcm::launch_trace_correct(c, 1, 0));
     return RMRCM_OK;
 }
@@ -458,6 +516,7 @@ int enqueue_setup(rmrcm_ctx* c, double* kcopy = nullptr) {
         TRY(mixed_local_setup(c));
     } else {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
+        TRY(mark(c, 15));
         HIP_TRY(rmrcm::launch_trace_correct(c, 1, 0));
     }
     TRY(mark(c, 2));
@@ -597,6 +656,7 @@ int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
         HIP_TRY(rmrcm::launch_local_setup(c, false, nullptr, 0, 1));
         HIP_TRY(rmrcm::launch_local_particular(c, false, nullptr, 0, 1));
     }
+    TRY(mark(c, 15));
     HIP_TRY(rmrcm::launch_trace_correct(c, 1, 1));
     TRY(mark(c, 2));
     for (int d = c->D - 1; d >= 0; --d) HIP_TRY(rmrcm::launch_merge_setup(c, d, true));
@@ -654,6 +714,23 @@ const char* rmrcm_strerror(int s) {
     return "unknown status";
 }
 
+int rmrcm_plan_bytes(const rmrcm_params* prm, uint64_t* bytes) {
+    if (!bytes) return RMRCM_EINVAL;
+    *bytes = 0;
+    const int v = validate(prm);
+    if (v != RMRCM_OK) return v;
+    rmrcm_ctx* c = new (std::nothrow) rmrcm_ctx();
+    if (!c) return RMRCM_ENOMEM;
+    c->prm = *prm;
+    c->counting = true;
+    build_geo(c);
+    build_levels(c);
+    const int r = alloc_arrays(c);
+    if (r == RMRCM_OK) *bytes = c->device_bytes;
+    delete c;
+    return r;
+}
+
 int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_type,
                 rmrcm_ctx** out) {
     if (!out) return RMRCM_EINVAL;
@@ -661,6 +738,12 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
     int v = validate(prm);
     if (v != RMRCM_OK) return v;
     if (!perm || !bc_type) return RMRCM_EINVAL;
+    if (prm->mem_cap) {
+        // the memory plan against the cap before any device work
+        uint64_t need = 0;
+        if ((v = rmrcm_plan_bytes(prm, &need)) != RMRCM_OK) return v;
+        if (need > prm->mem_cap) return RMRCM_ENOMEM;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -729,42 +812,17 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
             if (hipEventCreateWithFlags(&c->lev[d], hipEventDisableTiming) != hipSuccess)
                 return fail(RMRCM_EDEVICE);
     }
-    const Geo& g = c->geo;
-    const size_t nsub = (size_t)g.mx * g.my;
-    const size_t n = (size_t)g.bx * g.by;
-    const int R = c->levels[c->D].nslot;
     int r = RMRCM_OK;
-    if ((r = dalloc(c, &c->K, ncell)) || (r = dalloc(c, &c->bct, nbf)) ||
-        (r = dalloc(c, &c->beta, g.nseg)) || (r = dalloc(c, &c->seglen, g.nseg)) ||
-        (r = dalloc(c, &c->Pstore, nsub * g.by * g.bx * g.bx)) ||
-        (r = dalloc(c, &c->Psi, nsub * R * n)) || (r = dalloc(c, &c->pbar, nsub * n)) ||
-        (r = dalloc(c, &c->glo, g.nseg)) || (r = dalloc(c, &c->ghi, g.nseg)) ||
-        (r = dalloc(c, &c->q, ncell)) || (r = dalloc(c, &c->bcv, nbf)) ||
-        (r = dalloc(c, &c->pout, ncell)) || (r = dalloc(c, &c->fout, 4 * ncell)) ||
-        (r = dalloc(c, &c->Uout, g.nseg)) || (r = dalloc(c, &c->Pout, g.nseg)) ||
-        (r = dalloc(c, &c->flags, rmrcm::kNumFlags)) || (r = dalloc(c, &c->gauge, 256)) ||
-        (r = dalloc(c, &c->dscal, 1)))
-        return fail(r);
-    if (prm->precision != RMRCM_FP64) {
-        if ((r = dalloc(c, &c->P32, nsub * g.by * g.bx * g.bx)) ||
-            (r = dalloc(c, &c->Wsc, nsub * R * n)) || (r = dalloc(c, &c->resid, nsub)) ||
-            (r = dalloc(c, &c->fb, nsub)) || (r = dalloc(c, &c->irst, 4)) ||
-            (r = dalloc(c, &c->irhist, 2 * rmrcm::kIrHist)))
-            return fail(r);
-    }
+    if ((r = alloc_arrays(c)) != RMRCM_OK) return fail(r);
     if (prm->precision == RMRCM_MIXED_LEARNED) {
-        const int R = c->levels[c->D].nslot;
         if ((r = rmrcm_cnn_load(prm->cnn_weights, 256, prm->device, &c->net)) != RMRCM_OK) return fail(r);
-        if (c->net->S != g.bx || c->net->R != R) return fail(RMRCM_EINVAL);
-        if ((r = dalloc(c, &c->lx, nsub * 2 * n)) || (r = dalloc(c, &c->ly, nsub * R * n)) ||
-            (r = dalloc(c, &c->lint, nsub)) || (r = dalloc(c, &c->gres, nsub)))
-            return fail(r);
+        if (c->net->S != c->geo.bx || c->net->R != c->levels[c->D].nslot) return fail(RMRCM_EINVAL);
     }
-    if ((r = alloc_levels(c)) != RMRCM_OK || (r = upload_levels(c)) != RMRCM_OK) return fail(r);
+    if ((r = upload_levels(c)) != RMRCM_OK) return fail(r);
     if (hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->bct, ht.data(), nbf, hipMemcpyHostToDevice, c->stream) != hipSuccess)
         return fail(RMRCM_EDEVICE);
-    c->n_local_solves = 2 * (int64_t)g.nseg + (int64_t)nsub;
+    c->n_local_solves = 2 * (int64_t)c->geo.nseg + (int64_t)c->geo.mx * c->geo.my;
     if ((r = run_setup(c, true)) != RMRCM_OK) return fail(r);
     *out = c;
     return RMRCM_OK;
@@ -865,7 +923,9 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
     // phase times of the last setup and solve, read from their events
     if (c->setup_recorded && hipEventSynchronize(c->ev[3]) == hipSuccess) {
         c->t_setup_ms[0] = elapsed(c->ev[0], c->ev[1]);
-        c->t_setup_ms[1] = elapsed(c->ev[1], c->ev[2]);
+        // the local phase and, within it, the trace correction (event 15)
+        c->t_setup_ms[1] = elapsed(c->ev[1], c->ev[15]);
+        c->t_setup_ms[4] = elapsed(c->ev[15], c->ev[2]);
         c->t_setup_ms[2] = elapsed(c->ev[2], c->ev[3]);
         c->t_setup_ms[3] = elapsed(c->ev[0], c->ev[3]);
     }
@@ -903,7 +963,8 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
     char buf[2048];
     const int n = std::snprintf(
         buf, sizeof(buf),
-        "{\"setup_ms\": {\"beta\": %.6f, \"local\": %.6f, \"merge\": %.6f, \"total\": %.6f}, "
+        "{\"setup_ms\": {\"beta\": %.6f, \"local\": %.6f, \"trace_correct\": %.6f, \"merge\": %.6f, "
+        "\"total\": %.6f}, "
         "\"solve_ms\": {\"upload\": %.6f, \"local\": %.6f, \"merge\": %.6f, \"down\": %.6f, "
         "\"reconstruct\": %.6f, \"download\": %.6f, \"total\": %.6f}, "
         "\"levels\": %d, \"nseg\": %d, \"subdomains\": %d, \"local_solves\": %lld, "
@@ -911,7 +972,7 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         "\"ir_iters_solve\": %d, \"ir_resid_setup\": %.3e, \"ir_resid_solve\": %.3e, "
         "\"fp64_fallback_subdomains\": %d, \"surrogate_accepted_subdomains\": %d, "
         "\"gate_tol\": %.3e, \"particular_overlapped\": %s}",
-        c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
+        c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[4], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
         c->t_solve_ms[1], c->t_solve_ms[2], c->t_solve_ms[3], c->t_solve_ms[4], c->t_solve_ms[5],
         c->t_solve_ms[6], c->D, c->geo.nseg, c->geo.mx * c->geo.my, (long long)c->n_local_solves,
         c->device_bytes, c->prm.precision, c->ir_iters_setup, c->ir_iters_solve, c->ir_resid_setup,
@@ -1426,6 +1487,99 @@ void rmrcm_batch_destroy(rmrcm_batch* b) {
 int rmrcm_set_step_graph(rmrcm_ctx* c, int enabled) {
     if (!c) return RMRCM_EINVAL;
     c->step_graph = enabled != 0;
+    return RMRCM_OK;
+}
+
+int rmrcm_downscale(rmrcm_ctx* c, const double* source, const double* bc_value, const double* pressure,
+                    const double* flux, double* pressure_out, double* flux_out) {
+    if (!c || !bc_value || !pressure || !flux || !pressure_out || !flux_out) return RMRCM_EINVAL;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    const Geo& g = c->geo;
+    const size_t ncell = (size_t)g.nx * g.ny;
+    const size_t nbf = 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+    const int nsub = g.mx * g.my;
+    if (!c->ds_P) {
+        // first call: the Neumann factor store and buffers, and the gauge
+        // flag of every subdomain without a Dirichlet face
+        std::vector<int8_t> ht(nbf);
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        HIP_TRY(hipMemcpy(ht.data(), c->bct, nbf, hipMemcpyDeviceToHost));
+        std::vector<int> pin(nsub, 1);
+        for (int J = 0; J < g.my; ++J)
+            for (int I = 0; I < g.mx; ++I) {
+                bool dir = false;
+                for (int j = 0; j < g.by; ++j) {
+                    if (I == 0) dir |= ht[J * g.by + j] == RMRCM_BC_DIRICHLET;
+                    if (I == g.mx - 1) dir |= ht[g.ny + J * g.by + j] == RMRCM_BC_DIRICHLET;
+                }
+                for (int i = 0; i < g.bx; ++i) {
+                    if (J == 0) dir |= ht[2 * g.ny + I * g.bx + i] == RMRCM_BC_DIRICHLET;
+                    if (J == g.my - 1) dir |= ht[2 * g.ny + g.nx + I * g.bx + i] == RMRCM_BC_DIRICHLET;
+                }
+                pin[J * g.mx + I] = dir ? 0 : 1;
+            }
+        int r = RMRCM_OK;
+        if ((r = dalloc(c, &c->ds_P, (size_t)nsub * g.by * g.bx * g.bx)) ||
+            (r = dalloc(c, &c->ds_q, ncell)) || (r = dalloc(c, &c->ds_pb, ncell)) ||
+            (r = dalloc(c, &c->ds_pin, nsub)) || (r = dalloc(c, &c->ds_stage, 10 * ncell)))
+            return r;
+        HIP_TRY(hipMemcpyAsync(c->ds_pin, pin.data(), nsub * sizeof(int), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    // inputs in device memory (host arrays staged)
+    const bool pdev = is_device_ptr(pressure), fdev = is_device_ptr(flux);
+    const bool podev = is_device_ptr(pressure_out), fodev = is_device_ptr(flux_out);
+    double* pin_d = pdev ? const_cast<double*>(pressure) : c->ds_stage;
+    double* fin_d = fdev ? const_cast<double*>(flux) : c->ds_stage + ncell;
+    double* pout_d = podev ? pressure_out : c->ds_stage + 5 * ncell;
+    double* fout_d = fodev ? flux_out : c->ds_stage + 6 * ncell;
+    if (!pdev) HIP_TRY(hipMemcpyAsync(pin_d, pressure, ncell * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (!fdev) HIP_TRY(hipMemcpyAsync(fin_d, flux, 4 * ncell * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->bcv, bc_value, nbf * sizeof(double), hipMemcpyDefault, c->stream));
+    if (source) HIP_TRY(hipMemcpyAsync(c->q, source, ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    HIP_TRY(rmrcm::launch_fill_i32(c, c->flags + rmrcm::FLAG_LOCAL_SINGULAR, 1, 0));
+    HIP_TRY(rmrcm::launch_ds_source(c, fin_d, source ? c->q : nullptr, c->ds_q));
+    HIP_TRY(rmrcm::launch_ds_compat(c, c->ds_pin, c->ds_q));
+    // the Neumann factorisation and solve: the local kernels with the
+    // geometry in Neumann mode and the downscaling buffers in place of the
+    // factor store, the source and the particular solution
+    const Geo g0 = c->geo;
+    double* const P0 = c->Pstore;
+    double* const q0 = c->q;
+    double* const pb0 = c->pbar;
+    c->geo.neumann = 1;
+    c->geo.pin = c->ds_pin;
+    c->Pstore = c->ds_P;
+    c->q = c->ds_q;
+    c->pbar = c->ds_pb;
+    hipError_t e = rmrcm::launch_local_setup(c, false, nullptr, 0, 0, 0, 0);
+    if (e == hipSuccess) e = rmrcm::launch_local_particular(c, false, nullptr, 0, 0);
+    c->geo = g0;
+    c->Pstore = P0;
+    c->q = q0;
+    c->pbar = pb0;
+    HIP_TRY(e);
+    HIP_TRY(rmrcm::launch_ds_finish(c, c->ds_pb, pin_d, fin_d, c->ds_pin, pout_d, fout_d));
+    if (!podev)
+        HIP_TRY(hipMemcpyAsync(pressure_out, pout_d, ncell * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (!fodev)
+        HIP_TRY(hipMemcpyAsync(flux_out, fout_d, 4 * ncell * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return check_flags(c);
+}
+
+int rmrcm_set_refinement(rmrcm_ctx* c, double ir_tol, int32_t ir_max_iter) {
+    if (!c || !(ir_tol > 0) || ir_max_iter < 1) return RMRCM_EINVAL;
+    if (!mixed(c)) return RMRCM_ENOTSUP;
+    if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
+    c->prm.ir_tol = ir_tol;
+    c->prm.ir_max_iter = ir_max_iter;
+    if (c->gstep) {
+        // the captured step holds the old pass count and tolerance
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        (void)hipGraphExecDestroy(c->gstep);
+        c->gstep = nullptr;
+    }
     return RMRCM_OK;
 }
 

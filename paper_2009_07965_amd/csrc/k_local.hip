@@ -73,6 +73,20 @@ __device__ inline double bface(const Geo& g, const double* __restrict__ K,
     const double rho = (side < 2 ? g.hx : g.hy) / (2.0 * kc);
     const int a = slot_of(g, side, side < 2 ? j : i);
     const int code = ss[a];
+    if (g.neumann) {
+        if (g.pin && g.pin[J * g.mx + I] && side == 0 && j == 0) {
+            // the gauge face: a face to a zero datum (the cell's equation
+            // keeps its right-hand side)
+            *slot = code >= 0 ? a : -1;
+            *outer = code >= 0 ? -1 : outer_face(g, side, gi, gj);
+            return area / rho;
+        }
+        if (code >= 0) {
+            *slot = a;
+            *outer = -1;
+            return 0.0;
+        }
+    }
     if (code >= 0) {
         *slot = a;
         *outer = -1;
@@ -1822,17 +1836,36 @@ __global__ __launch_bounds__(256) void k_trace_correct(Geo g, const double* __re
     }
 }
 
-// The same correction for at most 32 slots, shaped for memory-level
-// parallelism: sixteen waves per subdomain, wave w taking 4 KS consecutive
-// cells, KB products (4 cells each) per batch whose global loads (every
-// column's value at the cell and its four neighbours, and with part the
-// particular solution's and the source) are all issued before any is used.
-// Lane l = x + 16 k of a product holds column 16 t + x (tile t) at cell
-// c0 + k: the A operand is that value, the B operand the residual the lane
-// forms from it and its neighbours with the stencil coefficients staged in
-// LDS.  The waves' partial tiles are added in a fixed order.
-template <int BX, int TT>
-__global__ __launch_bounds__(1024) void k_trace_correct_mlp(Geo g, const double* __restrict__ K,
+// The same correction for at most 16 TT slots with the subdomain's columns
+// staged through LDS.  The basis columns (and with part the particular
+// solution and the source) are read in stages of CH consecutive cells (whole
+// grid rows), each column's stage one contiguous run of 16-byte loads from
+// per-thread base addresses, into a ring of four stages (a cell's neighbours
+// above and below lie in the stages before and after its own; the ring's
+// power-of-two length makes every neighbour position a mask).  The loads of
+// stage s + 2 are issued during stage s - 1 and stored after the work of
+// stage s,
+// together with the stage's x- and y-transmissibilities (one per thread, the
+// two-point harmonic means of the local matrix, zero where the coupling
+// leaves the subdomain), while the loads of stage s + 3 are in flight in a
+// second register set; that store goes to the ring slot of stage s - 2,
+// which no wave reads while working on stage s or s + 1, so one barrier per
+// stage suffices.  Wave w takes cells 16 w .. 16 w + 15 of each stage: its
+// lanes (cell 16 w + l % 16, column group l / 16) form -A x_b for the group's
+// columns b = l / 16 + 4 k from the ring and add the Robin forcing e_b on
+// boundary cells, into the wave's part of a residual buffer; then the same
+// wave takes those cells through the matrix cores, lane l = x + 16 k holding
+// column 16 t + x at cell 16 w + 4 kk + k from the ring (the A operand) and
+// from the residual buffer (the B operand).  The four waves' partial tiles
+// are added in a fixed order.
+template <int CH, int TT>
+__host__ __device__ constexpr int tc_ring_doubles(int nc) {  // ring, or the reduction buffers after it
+    return nc * (4 * CH + 4) > 4 * TT * TT * 256 + 4 * 32 ? nc * (4 * CH + 4)
+                                                          : 4 * TT * TT * 256 + 4 * 32;
+}
+
+template <int BX, int TT, int CH>
+__global__ __launch_bounds__(256) void k_trace_correct_lds(Geo g, const double* __restrict__ K,
                                                            const int8_t* __restrict__ bct,
                                                            const double* __restrict__ beta,
                                                            const int* __restrict__ slotseg, int R,
@@ -1843,123 +1876,201 @@ __global__ __launch_bounds__(1024) void k_trace_correct_mlp(Geo g, const double*
                                                            double* __restrict__ T, int ld, int basis,
                                                            int part) {
     typedef Mfma<double>::v4 v4;
-    constexpr int KB = 4;                          // products per batch
-    constexpr int NW = 16;                         // waves
+    static_assert(CH == 64 && CH % BX == 0, "a stage is whole grid rows, 16 cells per wave");
+    constexpr int NW = 4, RING = 4 * CH, RM = RING - 1;
+    constexpr int CS = RING + 4;                           // CS = 4 mod 64: lanes x + 16 k on distinct banks
+    constexpr int RS = CH + 4;                             // residual buffer row
+    constexpr int G = 4;                                   // column groups (lanes per cell)
+    constexpr int KC = (16 * TT + G - 1) / G;              // basis columns per lane (at most)
+    constexpr int PAIRS = CH / 2;                          // 16-byte loads per column stage
+    constexpr int ML = ((16 * TT + 2) * PAIRS + 255) / 256;
+    typedef double d2 __attribute__((ext_vector_type(2)));
     extern __shared__ __align__(16) char smem[];
     const int sub = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int BY = g.by, n = BX * BY, NF = 2 * (BX + BY);
     const int I = sub % g.mx, J = sub / g.mx;
+    const int NC = R + (part ? 2 : 0);                     // staged columns
+    const int NS = (n + CH - 1) / CH;
     const int* ss = slotseg + (size_t)sub * R;
     char* sp = smem;
     double* cf = carve<double>(sp, NF);
     int* rs = carve<int>(sp, NF);
     int* of = carve<int>(sp, NF);
-    double* co = carve<double>(sp, 3 * n);
-    double* red = carve<double>(sp, NW * TT * TT * 256);
-    double* redp = carve<double>(sp, NW * 32);
-    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
-    __syncthreads();
-    for (int c = tid; c < n; c += 1024) {
-        double kv[5], dg, txr, tyu;
-        load_kstencil<BX>(g, K, I, J, c % BX, c / BX, kv);
-        stencil_coeffs<BX>(g, kv, cf, c % BX, c / BX, &dg, &txr, &tyu);
-        co[3 * c] = dg;
-        co[3 * c + 1] = txr;
-        co[3 * c + 2] = tyu;
-    }
-    __syncthreads();
+    double* txa = carve<double>(sp, RING);                 // x-transmissibility to the right
+    double* tya = carve<double>(sp, RING);                 // y-transmissibility upwards
+    double* rb = carve<double>(sp, (size_t)(16 * TT + 1) * RS);
+    const int RD = tc_ring_doubles<CH, TT>(NC);
+    double* ring = carve<double>(sp, RD);
+    // every position the products read holds a finite value (a neighbour
+    // outside the subdomain is read and multiplied by a zero coefficient)
+    for (int t = tid; t < RD; t += 256) ring[t] = 0.0;
+    for (int t = tid; t < RING; t += 256) txa[t] = tya[t] = 0.0;
+
     const size_t nn = (size_t)n;
-    const double* Ps = Psi + (size_t)sub * R * nn;
-    const double* pb = pbar + (size_t)sub * nn;
-    const double* qs = q + (size_t)(J * BY) * g.nx + (size_t)I * BX;
-    double* Ts = T + (size_t)sub * R * ld;
-    const int KS = (n / 4 + NW - 1) / NW;          // products per wave
+    // per-thread sources of the stage loads: column col, pair pr of the stage
+    const double* src[ML];
+    bool row_major_q[ML];
+    int soff[ML];
+#pragma unroll
+    for (int m = 0; m < ML; ++m) {
+        const int e = tid + 256 * m, col = e / PAIRS, o2 = 2 * (e % PAIRS);
+        soff[m] = col < NC ? col * CS + o2 : -1;
+        row_major_q[m] = col == R + 1;
+        src[m] = col < R ? Psi + ((size_t)sub * R + col) * nn + o2
+                 : col == R ? pbar + (size_t)sub * nn + o2
+                            : q + (size_t)(J * BY + o2 / BX) * g.nx + (size_t)I * BX + o2 % BX;
+    }
+    // transmissibility of this thread (tid < 2 CH): x (tid < CH) or y
+    const int tco = tid % CH;
+    const bool tyd = tid >= CH;
+    // one stage in registers: the columns' 16-byte pieces of this thread and
+    // the two permeabilities of its transmissibility
+    struct Stage {
+        d2 v[ML];
+        double ka, kb;
+    };
+    auto load = [&](int st, Stage& S) {
+#pragma unroll
+        for (int m = 0; m < ML; ++m) {
+            d2 x = {0.0, 0.0};
+            const int c = st * CH + (soff[m] >= 0 ? soff[m] % CS : 0);
+            if (soff[m] >= 0 && c < n)
+                x = *(const d2*)(src[m] + (row_major_q[m] ? (size_t)st * (CH / BX) * g.nx : (size_t)st * CH));
+            S.v[m] = x;
+        }
+        const int c = st * CH + tco, i = c % BX, j = c / BX;
+        S.ka = S.kb = 1.0;
+        if (tid < 2 * CH && c < n) {
+            const double* kc = K + (size_t)(J * BY + j) * g.nx + (size_t)I * BX + i;
+            S.ka = kc[0];
+            S.kb = tyd ? (j < BY - 1 ? kc[g.nx] : 1.0) : (i < BX - 1 ? kc[1] : 1.0);
+        }
+    };
+    auto store = [&](int st, const Stage& S) {
+        const int base = (st * CH) & RM;
+#pragma unroll
+        for (int m = 0; m < ML; ++m)
+            if (soff[m] >= 0) *(d2*)&ring[soff[m] + base] = S.v[m];
+        const int c = st * CH + tco, i = c % BX, j = c / BX;
+        if (tid < 2 * CH && c < n) {
+            if (tyd) tya[base + tco] = j < BY - 1 ? tpy(g, S.ka, S.kb) : 0.0;
+            else txa[base + tco] = i < BX - 1 ? tpx(g, S.ka, S.kb) : 0.0;
+        }
+    };
+
+    // stages 0 and 1 in the ring, stage 2 in flight (register set A); stage
+    // s + 3 is loaded into the other set during stage s
+    Stage sa, sb;
+    face_prologue<BX>(g, K, bct, beta, ss, I, J, cf, rs, of);
+    load(0, sa);
+    if (NS > 1) load(1, sb);
+    __syncthreads();
+    store(0, sa);
+    if (NS > 1) store(1, sb);
+    if (NS > 2) load(2, sa);
+    __syncthreads();
+
     v4 acc[TT][TT];
 #pragma unroll
     for (int u = 0; u < TT; ++u)
 #pragma unroll
-        for (int v = 0; v < TT; ++v) acc[u][v] = v4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < TT; ++t) acc[u][t] = v4{0.0, 0.0, 0.0, 0.0};
     double pp[TT];
 #pragma unroll
     for (int u = 0; u < TT; ++u) pp[u] = 0.0;
-    for (int kb = 0; kb < KS; kb += KB) {
-        double x[KB][TT][5];                       // centre, left, right, below, above
-        double xp[KB][6];                          // the same of the particular, and the source
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const int c = 4 * (w * KS + kb + k) + lk;
-            const bool in = kb + k < KS && c < n;
+
+    // residual pass: lane on cell offset o of the stage (its wave's cells),
+    // columns h + G k
+    const int o = 16 * w + li, h = lk;
+    const double* xh = ring + (size_t)h * CS;
+    double* rh = rb + (size_t)h * RS + o;
+    auto stage = [&](int s, Stage& cur, Stage& nxt) {
+        if (s + 3 < NS) load(s + 3, nxt);
+        {
+            // a cell past the subdomain (ragged last stage) takes the first
+            // cell's indices and a zero residual
+            const int c0 = s * CH + o;
+            const bool in = c0 < n;
+            const int c = in ? c0 : s * CH;
             const int i = c % BX, j = c / BX;
+            const int p = c & RM, pl = (c - 1) & RM, pr = (c + 1) & RM;
+            const int pd = (c - BX) & RM, pu = (c + BX) & RM;   // the neighbour rows' stages are in the ring
+            const bool hl = i > 0, hr = i < BX - 1, hd = j > 0, hu = j < BY - 1;
+            const double cl = hl ? txa[pl] : 0.0, cr = txa[p];
+            const double cd = hd ? tya[pd] : 0.0, cu = tya[p];
+            const double d0 = (hl ? cl : cf[j]) + (hr ? cr : cf[BY + j]) + (hd ? cd : cf[2 * BY + i]) +
+                              (hu ? cu : cf[2 * BY + BX + i]);
 #pragma unroll
-            for (int t = 0; t < TT; ++t) {
-                const int b = 16 * t + li;
-                const double* xb = Ps + (size_t)(b < R ? b : 0) * nn;
-                const bool ok = in && b < R;
-                x[k][t][0] = ok ? xb[c] : 0.0;
-                x[k][t][1] = ok && i > 0 ? xb[c - 1] : 0.0;
-                x[k][t][2] = ok && i < BX - 1 ? xb[c + 1] : 0.0;
-                x[k][t][3] = ok && j > 0 ? xb[c - BX] : 0.0;
-                x[k][t][4] = ok && j < BY - 1 ? xb[c + BX] : 0.0;
+            for (int k = 0; k < KC; ++k) {
+                if (basis && h + G * k < R) {
+                    const double* x = xh + G * k * CS;
+                    const double av = d0 * x[p] - cl * x[pl] - cr * x[pr] - cd * x[pd] - cu * x[pu];
+                    rh[G * k * RS] = in ? -av : 0.0;
+                }
             }
-            if (part) {
-                xp[k][0] = in ? pb[c] : 0.0;
-                xp[k][1] = in && i > 0 ? pb[c - 1] : 0.0;
-                xp[k][2] = in && i < BX - 1 ? pb[c + 1] : 0.0;
-                xp[k][3] = in && j > 0 ? pb[c - BX] : 0.0;
-                xp[k][4] = in && j < BY - 1 ? pb[c + BX] : 0.0;
-                xp[k][5] = in ? qs[(size_t)j * g.nx + i] : 0.0;
+            // the Robin forcing of the cell's boundary faces (at most two,
+            // on different sides, so in different slots)
+            if (in && (!hl || !hr)) {
+                const int f = hl ? BY + j : j;
+                const int b = rs[f];
+                if (basis && b >= 0 && b % G == h) rb[b * RS + o] += cf[f];
+            }
+            if (in && (!hd || !hu)) {
+                const int f = hd ? 2 * BY + BX + i : 2 * BY + i;
+                const int b = rs[f];
+                if (basis && b >= 0 && b % G == h) rb[b * RS + o] += cf[f];
+            }
+            if (part && R % G == h) {
+                const double* x = ring + (size_t)R * CS;
+                const double av = d0 * x[p] - cl * x[pl] - cr * x[pr] - cd * x[pd] - cu * x[pu];
+                rb[R * RS + o] = in ? part_rhs<BX>(g, cf, of, bct, bcv, x[CS + p], i, j) - av : 0.0;
             }
         }
+        wave_lds_sync();                               // the wave reads only its own cells
+        const int sbase = (s * CH) & RM;
 #pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const int c = 4 * (w * KS + kb + k) + lk;
-            const bool in = kb + k < KS && c < n;
-            const int cc = in ? c : 0;
-            const int i = cc % BX, j = cc / BX;
-            const double d0 = co[3 * cc];
-            const double cl = i > 0 ? co[3 * (cc - 1) + 1] : 0.0;
-            const double cr = co[3 * cc + 1];
-            const double cd = j > 0 ? co[3 * (cc - BX) + 2] : 0.0;
-            const double cu = co[3 * cc + 2];
-            double ro[TT];
+        for (int kk = 0; kk < CH / (4 * NW); ++kk) {
+            const int oc = w * (CH / NW) + 4 * kk + lk;      // cell offset in the stage
+            double x0[TT];
 #pragma unroll
             for (int t = 0; t < TT; ++t) {
                 const int b = 16 * t + li;
-                double e = 0.0;
-                if (in && b < R) {
-                    if (i == 0 && rs[j] == b) e += cf[j];
-                    if (i == BX - 1 && rs[BY + j] == b) e += cf[BY + j];
-                    if (j == 0 && rs[2 * BY + i] == b) e += cf[2 * BY + i];
-                    if (j == BY - 1 && rs[2 * BY + BX + i] == b) e += cf[2 * BY + BX + i];
-                }
-                const double* xv = x[k][t];
-                const double av = d0 * xv[0] - cl * xv[1] - cr * xv[2] - cd * xv[3] - cu * xv[4];
-                ro[t] = (in && b < R) ? e - av : 0.0;
+                x0[t] = b < R ? ring[(size_t)b * CS + sbase + oc] : 0.0;   // zero past n
             }
             if (basis) {
 #pragma unroll
-                for (int u = 0; u < TT; ++u)
+                for (int t = 0; t < TT; ++t) {
+                    const int b = 16 * t + li;
+                    const double r = b < R ? rb[b * RS + oc] : 0.0;
 #pragma unroll
-                    for (int v = 0; v < TT; ++v) acc[u][v] = Mfma<double>::op(x[k][u][0], ro[v], acc[u][v]);
+                    for (int u = 0; u < TT; ++u) acc[u][t] = Mfma<double>::op(x0[u], r, acc[u][t]);
+                }
             }
             if (part) {
-                const double* pv = xp[k];
-                const double av = d0 * pv[0] - cl * pv[1] - cr * pv[2] - cd * pv[3] - cu * pv[4];
-                const double rp = in ? part_rhs<BX>(g, cf, of, bct, bcv, pv[5], i, j) - av : 0.0;
+                const double r = rb[R * RS + oc];
 #pragma unroll
-                for (int u = 0; u < TT; ++u) pp[u] += x[k][u][0] * rp;
+                for (int u = 0; u < TT; ++u) pp[u] += x0[u] * r;
             }
         }
+        if (s + 2 < NS) store(s + 2, cur);            // the slot of stage s - 2
+        __syncthreads();
+    };
+    for (int s = 0; s < NS; s += 2) {
+        stage(s, sa, sb);
+        if (s + 1 < NS) stage(s + 1, sb, sa);
     }
+
+    double* red = ring;                               // the ring is free after the last stage
+    double* redp = ring + NW * TT * TT * 256;
     if (basis) {
 #pragma unroll
         for (int u = 0; u < TT; ++u)
 #pragma unroll
-            for (int v = 0; v < TT; ++v)
+            for (int t = 0; t < TT; ++t)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    red[((w * TT + u) * TT + v) * 256 + Mfma<double>::row(lane, r) * 16 + li] = acc[u][v][r];
+                    red[((w * TT + u) * TT + t) * 256 + Mfma<double>::row(lane, r) * 16 + li] = acc[u][t][r];
     }
     if (part) {
 #pragma unroll
@@ -1971,9 +2082,10 @@ __global__ __launch_bounds__(1024) void k_trace_correct_mlp(Geo g, const double*
         }
     }
     __syncthreads();
+    double* Ts = T + (size_t)sub * R * ld;
     if (basis) {
         const int W1 = TT * TT * 256;
-        for (int t = tid; t < W1; t += 1024) {
+        for (int t = tid; t < W1; t += 256) {
             const int uv = t / 256, e = t % 256;
             const int a = 16 * (uv / TT) + e / 16, b = 16 * (uv % TT) + e % 16;
             double sm = 0.0;
@@ -1982,7 +2094,7 @@ __global__ __launch_bounds__(1024) void k_trace_correct_mlp(Geo g, const double*
         }
     }
     if (part)
-        for (int a = tid; a < R; a += 1024) {
+        for (int a = tid; a < R; a += 256) {
             double sm = 0.0;
             for (int ww = 0; ww < NW; ++ww) sm += redp[ww * 32 + a];
             if (ss[a] >= 0) Ts[(size_t)a * ld + ld - 1] += sm;
@@ -2596,18 +2708,19 @@ static hipError_t trace_correct_bx(rmrcm_ctx* c, int basis, int part, const int*
     const Level& L = c->levels[c->D];
     const int R = L.nslot, BY = c->geo.by, NF = 2 * (BX + BY), n = BX * BY;
     if (R <= 32) {
-        const int TT = (R + 15) / 16;
-        const size_t lds = carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4) + carve_bytes(3 * n, 8) +
-                           carve_bytes(16 * TT * TT * 256, 8) + carve_bytes(16 * 32, 8);
-        auto go = [&](auto kern) -> hipError_t {
+        const int NC = R + (part ? 2 : 0);
+        auto go = [&](auto kern, int tt, int ch, int ring) -> hipError_t {
+            const size_t lds = carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4) + 2 * carve_bytes(4 * ch, 8) +
+                               carve_bytes((size_t)(16 * tt + 1) * (ch + 4), 8) + carve_bytes(ring, 8);
             hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)lds);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kern, dim3(nsub), dim3(1024), lds, c->stream, c->geo, c->K, c->bct, c->beta,
+            hipLaunchKernelGGL(kern, dim3(nsub), dim3(256), lds, c->stream, c->geo, c->K, c->bct, c->beta,
                                L.slotseg, R, c->Psi, c->pbar, c->q, c->bcv, L.T, L.ld, basis, part);
             return hipGetLastError();
         };
-        return TT == 1 ? go(k_trace_correct_mlp<BX, 1>) : go(k_trace_correct_mlp<BX, 2>);
+        if (R <= 16) return go(k_trace_correct_lds<BX, 1, 64>, 1, 64, tc_ring_doubles<64, 1>(NC));
+        return go(k_trace_correct_lds<BX, 2, 64>, 2, 64, tc_ring_doubles<64, 2>(NC));
     }
     const int TT = (R + 15) / 16, TG = TT < 2 ? TT : 2;
     const size_t lds = carve_bytes(NF, 8) + 2 * carve_bytes(NF, 4) + carve_bytes(3 * n, 8) +

@@ -25,6 +25,12 @@ struct Geo {
     int nseg;          // total segments
     double hx, hy;
     double alpha;
+    // Neumann mode (the downscaling solves): faces on Robin slots carry no
+    // conductance, and a subdomain whose pin entry is nonzero (no Dirichlet
+    // face) gets the full half-cell conductance on the W face of its cell
+    // (0, 0) with no datum, which fixes the constant of its Neumann problem
+    int neumann = 0;
+    const int* pin = nullptr;
 };
 
 // Slot -> segment code: (segment id << 1) | low_side, or -1 if the slot lies
@@ -119,6 +125,9 @@ struct rmrcm_ctx {
     // Null: every array has its own allocation.
     char* arena = nullptr;
     size_t arena_cap = 0, arena_used = 0;
+    // Memory plan only: dalloc counts the bytes of every array and
+    // allocates nothing (rmrcm_plan_bytes).
+    bool counting = false;
     // timing
     hipEvent_t ev[16] = {};
     // FP64 overlap of the particular chain with the setup merges: an
@@ -139,6 +148,14 @@ struct rmrcm_ctx {
     float* ly = nullptr;                     // [nsub][R][S][S] predicted basis
     int* lint = nullptr;                     // [nsub] interior mask
     double* gres = nullptr;                  // [nsub] gate residual of the prediction
+    // downscaling (allocated by its first call): the Neumann factor store,
+    // the cell source of the Neumann problems, their solution (per-subdomain
+    // layout), the gauge flag per subdomain, staging of host inputs/outputs
+    double* ds_P = nullptr;
+    double* ds_q = nullptr;
+    double* ds_pb = nullptr;
+    int* ds_pin = nullptr;
+    double* ds_stage = nullptr;              // [10][ny][nx]: p in, F in, p out, F out
     int n_accepted = 0;
     double ir_resid_setup = 0.0, ir_resid_solve = 0.0;
 };
@@ -183,6 +200,10 @@ hipError_t launch_down_all(rmrcm_ctx* c);
 // host (c->h_down_tab); RMRCM_* code.
 int build_down_sub(rmrcm_ctx* c);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
+hipError_t launch_ds_source(rmrcm_ctx* c, const double* F, const double* q, double* qo);
+hipError_t launch_ds_compat(rmrcm_ctx* c, const int* pin, double* qo);
+hipError_t launch_ds_finish(rmrcm_ctx* c, const double* pb, const double* p_in, const double* F_in,
+                            const int* pin, double* p_out, double* f_out);
 hipError_t launch_interface_values(rmrcm_ctx* c);
 hipError_t launch_gauge(rmrcm_ctx* c);
 hipError_t launch_fill_i32(rmrcm_ctx* c, int* p, size_t n, int v);

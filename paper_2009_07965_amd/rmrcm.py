@@ -41,11 +41,12 @@ class rmrcm_params(ctypes.Structure):
         ("gate_tol", ctypes.c_double),
         ("cnn_weights", ctypes.c_char_p),
         ("device", ctypes.c_int32),
+        ("mem_cap", ctypes.c_uint64),
     ]
 
 
 EXPORTS = [
-    "rmrcm_default_params", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve", "rmrcm_step",
+    "rmrcm_default_params", "rmrcm_plan_bytes", "rmrcm_set_refinement", "rmrcm_downscale", "rmrcm_setup", "rmrcm_refactor", "rmrcm_sync", "rmrcm_solve", "rmrcm_step",
     "rmrcm_set_step_graph", "rmrcm_step_noalloc",
     "rmrcm_get_interface",
     "rmrcm_counts", "rmrcm_set_stream", "rmrcm_get_stats", "rmrcm_destroy",
@@ -70,6 +71,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     vp, dp, i8p = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p
     lib.rmrcm_default_params.argtypes = [ctypes.POINTER(rmrcm_params)]
     lib.rmrcm_default_params.restype = None
+    lib.rmrcm_plan_bytes.argtypes = [ctypes.POINTER(rmrcm_params), ctypes.POINTER(ctypes.c_uint64)]
+    lib.rmrcm_plan_bytes.restype = ctypes.c_int
+    lib.rmrcm_downscale.argtypes = [vp, dp, dp, dp, dp, dp, dp]
+    lib.rmrcm_downscale.restype = ctypes.c_int
+    lib.rmrcm_set_refinement.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
+    lib.rmrcm_set_refinement.restype = ctypes.c_int
     lib.rmrcm_setup.argtypes = [ctypes.POINTER(rmrcm_params), dp, i8p, ctypes.POINTER(vp)]
     lib.rmrcm_setup.restype = ctypes.c_int
     lib.rmrcm_refactor.argtypes = [vp, dp]
@@ -174,6 +181,30 @@ def rmrcm_default_params() -> rmrcm_params:
     p = rmrcm_params()
     lib().rmrcm_default_params(ctypes.byref(p))
     return p
+
+
+def rmrcm_plan_bytes(params: rmrcm_params) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().rmrcm_plan_bytes(ctypes.byref(params), ctypes.byref(b)), "rmrcm_plan_bytes")
+    return b.value
+
+
+def rmrcm_downscale(ctx, source, bc_value, pressure, flux, pressure_out, flux_out) -> None:
+    sp_, k1 = _ptr(source, np.float64)
+    bp, k2 = _ptr(bc_value, np.float64)
+    pp, k3 = _ptr(pressure, np.float64)
+    fp, k4 = _ptr(flux, np.float64)
+    po, k5 = _ptr(pressure_out, np.float64)
+    fo, k6 = _ptr(flux_out, np.float64)
+    if isinstance(pressure_out, np.ndarray) and k5 is not pressure_out:
+        raise ValueError("pressure_out must be a contiguous float64 array")
+    if isinstance(flux_out, np.ndarray) and k6 is not flux_out:
+        raise ValueError("flux_out must be a contiguous float64 array")
+    _check(lib().rmrcm_downscale(ctx, sp_, bp, pp, fp, po, fo), "rmrcm_downscale")
+
+
+def rmrcm_set_refinement(ctx, ir_tol: float, ir_max_iter: int) -> None:
+    _check(lib().rmrcm_set_refinement(ctx, ir_tol, ir_max_iter), "rmrcm_set_refinement")
 
 
 def rmrcm_setup(params: rmrcm_params, perm, bc_type):
@@ -487,6 +518,14 @@ class Solver:
             flux = np.zeros((4, self.ny, self.nx))
         rmrcm_solve(self.ctx, q, bc_value, pressure, flux)
         return pressure, flux
+
+    def downscale(self, q, bc_value, pressure, flux):
+        """Single-valued, cell-conservative (pressure, flux) from an MRCM
+        solution of this problem (rmrcm_downscale)."""
+        po = np.zeros((self.ny, self.nx))
+        fo = np.zeros((4, self.ny, self.nx))
+        rmrcm_downscale(self.ctx, q, bc_value, pressure, flux, po, fo)
+        return po, fo
 
     def step(self, K, q, bc_value, pressure=None, flux=None):
         """refactor(K) and solve(q, bc_value) as one unit (a replayed graph

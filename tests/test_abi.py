@@ -64,3 +64,66 @@ def test_strerror_table():
     assert rmrcm_strerror(0) == "ok"
     assert "singular" in rmrcm_strerror(-4)
     assert rmrcm_strerror(12345) == "unknown status"
+
+
+def params(nx=64, b=16, seg=4, precision=0, **kw):
+    from paper_2009_07965_amd import rmrcm_default_params
+    p = rmrcm_default_params()
+    p.nx = p.ny = nx
+    p.sub_nx = p.sub_ny = b
+    p.seg = seg
+    p.precision = precision
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_memory_plan_counts_the_large_arrays():
+    """The plan holds at least the basis (nslot columns of b^2 cells per
+    subdomain), the factor store (b inverted b x b blocks per subdomain) and
+    eight cell arrays (permeability, source, pressure, four fluxes, the
+    particular solution), FP64; the traces and merge blocks of every level
+    add less than as much again.  The mixed mode adds exactly its FP32
+    factor store and sweep scratch and its per-subdomain residual, fallback
+    and refinement-history arrays."""
+    from paper_2009_07965_amd import rmrcm_plan_bytes
+    for nx, b, seg in [(64, 16, 4), (1024, 32, 8), (8192, 32, 8), (2048, 16, 4)]:
+        nsub = (nx // b) ** 2
+        R = 4 * b // seg
+        fp64 = rmrcm_plan_bytes(params(nx, b, seg))
+        low = 8 * nsub * (R * b * b + b * b * b) + 8 * 8 * nx * nx
+        assert low < fp64 < 2 * low, (nx, fp64, low)
+        mixed = rmrcm_plan_bytes(params(nx, b, seg, precision=1))
+        extra = 4 * nsub * b * b * b + 4 * nsub * R * b * b + 8 * nsub + 4 * nsub + 4 * 4 + 8 * 2 * 16
+        assert mixed - fp64 == extra
+
+
+def test_memory_plan_rejects_what_setup_rejects():
+    from paper_2009_07965_amd import rmrcm_plan_bytes, RMRCMError
+    with pytest.raises(RMRCMError) as ei:
+        rmrcm_plan_bytes(params(nx=96))
+    assert ei.value.status == -1
+    with pytest.raises(RMRCMError) as ei:
+        rmrcm_plan_bytes(params(nx=96, b=12, seg=4))
+    assert ei.value.status == -7
+
+
+def test_memory_cap_gives_enomem_before_device_work():
+    """A cap one byte below the plan: RMRCM_ENOMEM from the host, with no
+    device (here there is none).  A cap at the plan passes that check, and
+    the setup goes on to the device query (RMRCM_EDEVICE without a GPU)."""
+    import torch
+    from paper_2009_07965_amd import rmrcm_plan_bytes, rmrcm_setup, RMRCMError
+    p = params()
+    need = rmrcm_plan_bytes(p)
+    K, t = np.ones(64 * 64), np.zeros(4 * 64, np.int8)
+    t[:64] = 1
+    p.mem_cap = need - 1
+    with pytest.raises(RMRCMError) as ei:
+        rmrcm_setup(p, K, t)
+    assert ei.value.status == -2
+    if not torch.cuda.is_available():
+        p.mem_cap = need
+        with pytest.raises(RMRCMError) as ei:
+            rmrcm_setup(p, K, t)
+        assert ei.value.status == -3

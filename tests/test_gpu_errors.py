@@ -1,0 +1,87 @@
+"""Error paths on the GPU that the host can force without a faulty kernel:
+the memory plan against what a context really allocates, a memory cap one
+byte short, and a refinement that cannot reach its tolerance."""
+
+import numpy as np
+import pytest
+
+from helpers import make_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2009_07965_amd as lib
+    return lib
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plan_equals_allocation(L, precision):
+    prob = make_problem(128, b=16, seg=4, log_var=2.0)
+    print("[gpu-errors] plan vs allocation, precision %d" % precision, flush=True)
+    S = L.Solver.from_problem(prob, precision=precision)
+    try:
+        got = S.stats()["device_bytes"]
+        plan = L.rmrcm_plan_bytes(S.params)
+    finally:
+        S.close()
+    assert got == plan
+
+
+def test_cap_one_byte_short_is_enomem(L):
+    prob = make_problem(128, b=16, seg=4, log_var=2.0)
+    print("[gpu-errors] memory cap", flush=True)
+    S = L.Solver.from_problem(prob)
+    try:
+        plan = L.rmrcm_plan_bytes(S.params)
+    finally:
+        S.close()
+    with pytest.raises(L.RMRCMError) as ei:
+        L.Solver.from_problem(prob, mem_cap=plan - 1)
+    assert ei.value.status == -2
+    S = L.Solver.from_problem(prob, mem_cap=plan)     # exactly the plan: fits
+    S.close()
+
+
+def test_unreachable_tolerance_at_solve_is_enotconv(L):
+    """Setup with the default refinement (converges), then a tolerance no
+    refinement reaches with one pass: the solve's particular refinement
+    does not converge and the solve reports RMRCM_ENOTCONV; restoring the
+    defaults gives a normal solve again."""
+    prob = make_problem(128, b=16, seg=4, log_var=2.0, source=True)
+    print("[gpu-errors] ENOTCONV at solve", flush=True)
+    S = L.Solver.from_problem(prob, precision=1)
+    try:
+        p0, F0 = S.solve(prob.q, prob.bc_value)
+        L.rmrcm_set_refinement(S.ctx, 1e-300, 1)
+        with pytest.raises(L.RMRCMError) as ei:
+            S.solve(prob.q, prob.bc_value)
+        assert ei.value.status == -5
+        L.rmrcm_set_refinement(S.ctx, 1e-11, 6)
+        p1, F1 = S.solve(prob.q, prob.bc_value)
+        assert np.array_equal(p0, p1) and np.array_equal(F0, F1)
+    finally:
+        S.close()
+
+
+def test_set_refinement_rejects(L):
+    prob = make_problem(64, b=16, seg=4)
+    S = L.Solver.from_problem(prob)
+    try:
+        with pytest.raises(L.RMRCMError) as ei:
+            L.rmrcm_set_refinement(S.ctx, 1e-12, 3)
+        assert ei.value.status == -7           # FP64 context
+    finally:
+        S.close()
+    S = L.Solver.from_problem(prob, precision=1)
+    try:
+        for tol, it in ((0.0, 3), (1e-12, 0)):
+            with pytest.raises(L.RMRCMError) as ei:
+                L.rmrcm_set_refinement(S.ctx, tol, it)
+            assert ei.value.status == -1
+    finally:
+        S.close()
