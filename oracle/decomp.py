@@ -16,6 +16,18 @@
   the two adjacent cell permeabilities (Section 5.1, the Robin-beta and
   effective-permeability equations; N read as the number of fine faces of
   the segment and Hbar as its physical length).
+* General interface spaces (Section 2 leaves U_H and P_H free; Section 4
+  takes them equal): U_H piecewise constant on U-segments of ``seg_u``
+  faces, P_H on P-segments of ``seg_p`` faces, the longer a multiple of the
+  shorter.  The pieces of length ``min(seg_u, seg_p)`` are the segments
+  above (slots, local solves, traces); every piece lies in one U-segment
+  and one P-segment.  beta is that of the piece's U-segment (Hbar = the
+  U-segment's length, Keff over its faces): it multiplies U_H in the Robin
+  condition and weights eq. 14.2, both on U-segments.  With a constant
+  beta on every piece, the datum of a subdomain's face is constant on each
+  piece, so the U-type (eq. 11Hhatbasisa) and P-type (eq. 11Hhatbasisb)
+  bases of a segment are sums of piece bases (the U-type one times
+  ``-beta s``): one local solve per piece and side gives all of them.
 
 Documented global segment order: vertical segments first, by interface
 line x = I*sub_nx*hx (I = 1..mx-1) and then bottom to top; then horizontal
@@ -41,13 +53,20 @@ def _is_pow2(v):
 class Decomposition:
     def __init__(self, prob):
         nx, ny = prob.nx, prob.ny
-        bx, by, sg = prob.sub_nx, prob.sub_ny, prob.seg
+        bx, by = prob.sub_nx, prob.sub_ny
+        su = getattr(prob, "seg_u", 0) or prob.seg
+        sp = getattr(prob, "seg_p", 0) or prob.seg
+        sg = min(su, sp)
         if nx <= 0 or ny <= 0 or bx <= 0 or by <= 0 or sg <= 0:
             raise ValueError("sizes must be positive")
         if nx % bx or ny % by:
             raise ValueError("subdomain size must divide the grid")
-        if bx % sg or by % sg:
+        if bx % su or by % su or bx % sp or by % sp:
             raise ValueError("segment length must divide the subdomain size")
+        if max(su, sp) % sg:
+            raise ValueError("the longer interface segment must be a multiple of the shorter")
+        self.seg_u_cells, self.seg_p_cells = su, sp
+        self.mu, self.mp = su // sg, sp // sg      # pieces per U-segment, per P-segment
         self.mx, self.my = nx // bx, ny // by
         if not (_is_pow2(self.mx) and _is_pow2(self.my)):
             raise ValueError("subdomain counts per direction must be powers of two")
@@ -60,9 +79,17 @@ class Decomposition:
         self.nh = (self.my - 1) * self.lines_h
         self.nseg = self.nv + self.nh
         K = prob.K
-        # per-segment geometry: low/high cells of each fine face
-        lo_cells, hi_cells, length, beta = [], [], np.zeros(self.nseg), np.zeros(self.nseg)
+        # U- and P-segments: the same order as the pieces (vertical lines,
+        # then horizontal ones), n_u / n_p per line
+        self.nUv = (self.mx - 1) * (ny // su)
+        self.nU = self.nUv + (self.my - 1) * (nx // su)
+        self.nPv = (self.mx - 1) * (ny // sp)
+        self.nP = self.nPv + (self.my - 1) * (nx // sp)
+        # per-piece geometry: low/high cells of each fine face
+        lo_cells, hi_cells, length = [], [], np.zeros(self.nseg)
         orient = np.zeros(self.nseg, dtype=int)
+        useg = np.zeros(self.nseg, dtype=int)
+        pseg = np.zeros(self.nseg, dtype=int)
         for e in range(self.nseg):
             if e < self.nv:
                 I = e // self.lines_v + 1
@@ -73,6 +100,8 @@ class Decomposition:
                 hi = [(i_hi, j) for j in js]
                 length[e] = sg * self.hy
                 orient[e] = 0
+                useg[e] = (I - 1) * (ny // su) + k // self.mu
+                pseg[e] = (I - 1) * (ny // sp) + k // self.mp
             else:
                 r = e - self.nv
                 J = r // self.lines_h + 1
@@ -83,17 +112,32 @@ class Decomposition:
                 hi = [(i, j_hi) for i in is_]
                 length[e] = sg * self.hx
                 orient[e] = 1
-            kl = np.array([K[j, i] for (i, j) in lo])
-            kh = np.array([K[j, i] for (i, j) in hi])
-            keff = np.mean(2.0 * kl * kh / (kl + kh))
-            beta[e] = prob.alpha * length[e] / keff
+                useg[e] = self.nUv + (J - 1) * (nx // su) + k // self.mu
+                pseg[e] = self.nPv + (J - 1) * (nx // sp) + k // self.mp
             lo_cells.append(lo)
             hi_cells.append(hi)
+        # beta per U-segment from all of its faces, then per piece
+        hsum = np.zeros(self.nU)
+        nfac = np.zeros(self.nU)
+        ulen = np.zeros(self.nU)
+        for e in range(self.nseg):
+            kl = np.array([K[j, i] for (i, j) in lo_cells[e]])
+            kh = np.array([K[j, i] for (i, j) in hi_cells[e]])
+            hsum[useg[e]] += np.sum(2.0 * kl * kh / (kl + kh))
+            nfac[useg[e]] += len(kl)
+            ulen[useg[e]] += length[e]
+        self.useg_beta = prob.alpha * ulen / (hsum / np.maximum(nfac, 1)) if self.nU else np.zeros(0)
+        self.useg_length = ulen
+        plen = np.zeros(self.nP)
+        np.add.at(plen, pseg, length)
+        self.pseg_length = plen
         self.seg_lo_cells = lo_cells
         self.seg_hi_cells = hi_cells
         self.seg_length = length
-        self.seg_beta = beta
+        self.seg_beta = self.useg_beta[useg] if self.nseg else np.zeros(0)
         self.seg_orient = orient
+        self.seg_useg = useg
+        self.seg_pseg = pseg
 
     # ------------------------------------------------------------------
     def vseg(self, I, k):

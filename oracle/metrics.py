@@ -45,14 +45,17 @@ def cell_backward_error(prob, p, F):
 
 
 def interface_residual(dec, F, U):
-    """Max relative residual of eq. 13.2 and eq. 14.2 (divided by beta)."""
-    r13 = np.zeros(dec.nseg)
-    r14 = np.zeros(dec.nseg)
+    """Max relative residual of eq. 13.2 (tested with the indicator of
+    every P-segment) and eq. 14.2 (divided by beta, with that of every
+    U-segment; U holds one value per U-segment)."""
+    r13 = np.zeros(dec.nP)
+    r14 = np.zeros(dec.nU)
     for e in range(dec.nseg):
         vert = dec.seg_orient[e] == 0
         flo = sum(F[1 if vert else 3, j, i] for (i, j) in dec.seg_lo_cells[e])
         fhi = sum(F[0 if vert else 2, j, i] for (i, j) in dec.seg_hi_cells[e])
-        r13[e] = flo + fhi
-        r14[e] = flo - fhi - 2.0 * dec.seg_length[e] * U[e]
+        r13[dec.seg_pseg[e]] += flo + fhi
+        r14[dec.seg_useg[e]] += flo - fhi
+    r14 -= 2.0 * dec.useg_length * U
     scale = max(np.abs(F).max(), 1e-300)
     return np.abs(r13).max() / scale, np.abs(r14).max() / scale

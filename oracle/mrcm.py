@@ -23,9 +23,17 @@ final solution assembled by eq. final.  With no Dirichlet face anywhere the
 cell pressure is defined up to a constant; the gauge is a zero mean of the
 cell pressures, imposed through a bordered system.
 
+General interface spaces (U_H on U-segments, P_H on P-segments of other
+lengths; the decomposition's pieces are the common refinement): the
+unknowns are one U per U-segment and one P per P-segment, eq. 14.2 is
+tested with the indicator of every U-segment (the sum of the rows above
+over its pieces, with 2 |e| U over its whole length) and eq. 13.2 with that
+of every P-segment; a piece's datum is ``P_q - beta s U_u`` with u, q its
+U- and P-segment.  With equal segments this is the system above.
+
 Pinned by: equality with O-1 when every segment is one fine face (for any
-alpha), exact linear pressure on vertical strips, O-4 brute force and the
-Table 3 local-solve counts.  The values of the paper's 2D accuracy tables
+alpha), exact linear pressure on vertical strips, O-4 brute force (with
+general spaces too) and the Table 3 local-solve counts.  The values of the paper's 2D accuracy tables
 (Section 5.4) are not reproduced (their reference solution is the hybrid
 mixed RT0 scheme with an unstated slice and norm): parity unpinned there;
 only the trend in alpha and Hbar is tested.
@@ -47,8 +55,8 @@ from .tpfa import solve_refined
 class MRCMResult:
     p: np.ndarray        # (ny, nx)
     F: np.ndarray        # (4, ny, nx) one-sided outward fluxes
-    U: np.ndarray        # (nseg,)
-    P: np.ndarray        # (nseg,)
+    U: np.ndarray        # (nU,) one per U-segment (= nseg with MuMM spaces)
+    P: np.ndarray        # (nP,) one per P-segment
     dec: Decomposition
     locals: dict
 
@@ -59,57 +67,61 @@ def all_local_solves(prob, dec):
 
 
 def assemble_interface_system(dec, loc):
-    """Sparse A (2 nseg x 2 nseg) and b of eq. linsys."""
-    ns = dec.nseg
+    """Sparse A ((nU + nP) x (nU + nP)) and b of eq. linsys: rows of eq.
+    14.2 per U-segment, then eq. 13.2 per P-segment; unknowns (U, P)."""
+    nU, nP = dec.nU, dec.nP
+    us, ps = dec.seg_useg, dec.seg_pseg
     rows, cols, vals = [], [], []
-    b = np.zeros(2 * ns)
+    b = np.zeros(nU + nP)
     beta = dec.seg_beta
     for (I, J), r in loc.items():
         act = [(a, e, sg) for a, (e, sg, _sd, _s) in enumerate(r.slots) if e >= 0]
         for (a, e, sa) in act:
-            # F^i_e = tbar[a] + sum_b T[a, b] (P_eb - beta_eb s_b U_eb)
+            # F^i_e = tbar[a] + sum_b T[a, b] (P_q(eb) - beta_eb s_b U_u(eb))
             for (bb, eb, sb) in act:
                 t = r.T[a, bb]
                 if t == 0.0:
                     continue
-                # eq. 14.2 row (index e): beta_e * s_a * F
-                rows += [e, e]
-                cols += [ns + eb, eb]
+                # eq. 14.2 row (U-segment of e): beta_e * s_a * F
+                rows += [us[e], us[e]]
+                cols += [nU + ps[eb], us[eb]]
                 vals += [beta[e] * sa * t, -beta[e] * sa * t * beta[eb] * sb]
-                # eq. 13.2 row (index ns + e): F
-                rows += [ns + e, ns + e]
-                cols += [ns + eb, eb]
+                # eq. 13.2 row (P-segment of e): F
+                rows += [nU + ps[e], nU + ps[e]]
+                cols += [nU + ps[eb], us[eb]]
                 vals += [t, -t * beta[eb] * sb]
-            b[e] -= beta[e] * sa * r.tbar[a]
-            b[ns + e] -= r.tbar[a]
-    for e in range(ns):
-        rows.append(e)
-        cols.append(e)
-        vals.append(-2.0 * beta[e] * dec.seg_length[e])
-    A = sp.coo_matrix((vals, (rows, cols)), shape=(2 * ns, 2 * ns)).tocsr()
+            b[us[e]] -= beta[e] * sa * r.tbar[a]
+            b[nU + ps[e]] -= r.tbar[a]
+    for u in range(nU):
+        rows.append(u)
+        cols.append(u)
+        vals.append(-2.0 * dec.useg_beta[u] * dec.useg_length[u])
+    A = sp.coo_matrix((vals, (rows, cols)), shape=(nU + nP, nU + nP)).tocsr()
     return A, b
 
 
-def robin_data(r, U, P, beta):
+def robin_data(r, U, P, dec):
+    """Robin datum of every slot: P of its P-segment - beta s U of its
+    U-segment (0 on the outer boundary)."""
     g = np.zeros(len(r.slots))
     for a, (e, sgn, _sd, _s) in enumerate(r.slots):
         if e >= 0:
-            g[a] = P[e] - beta[e] * sgn * U[e]
+            g[a] = P[dec.seg_pseg[e]] - dec.seg_beta[e] * sgn * U[dec.seg_useg[e]]
     return g
 
 
 def _gauge_row(prob, dec, loc):
     """Linear functional X -> sum of all cell pressures (and its constant)."""
-    ns = dec.nseg
-    w = np.zeros(2 * ns)
+    nU = dec.nU
+    w = np.zeros(nU + dec.nP)
     c0 = 0.0
     for (I, J), r in loc.items():
         c0 += r.pbar.sum()
         colsum = r.Psi.sum(axis=0)
         for a, (e, sgn, _sd, _s) in enumerate(r.slots):
             if e >= 0:
-                w[ns + e] += colsum[a]
-                w[e] -= colsum[a] * dec.seg_beta[e] * sgn
+                w[nU + dec.seg_pseg[e]] += colsum[a]
+                w[dec.seg_useg[e]] -= colsum[a] * dec.seg_beta[e] * sgn
     return w, c0
 
 
@@ -117,31 +129,31 @@ def mrcm_solve(prob, loc=None) -> MRCMResult:
     dec = Decomposition(prob)
     if loc is None:
         loc = all_local_solves(prob, dec)
-    ns = dec.nseg
-    if ns == 0:
+    nU, nP = dec.nU, dec.nP
+    if dec.nseg == 0:
         U = P = np.zeros(0)
     else:
         A, b = assemble_interface_system(dec, loc)
         if np.any(prob.bc_type == 1):
             X = solve_refined(A, b)
         else:
-            # All outer faces Neumann: shifting every P_e by a constant
+            # All outer faces Neumann: shifting every P by a constant
             # shifts every cell pressure by it (partition of unity) and
             # leaves all fluxes unchanged, so n = (0, 1) spans the null
             # space; the sum of the eq. 13.2 rows, y = (0, 1), spans the
             # left null space.  Since y.n != 0 the bordered system
             # [[A, n], [w^T, 0]] with the zero-mean gauge row w is regular.
             w, c0 = _gauge_row(prob, dec, loc)
-            nullv = np.concatenate([np.zeros(ns), np.ones(ns)])
+            nullv = np.concatenate([np.zeros(nU), np.ones(nP)])
             Ab = sp.bmat([[A, sp.csr_matrix(nullv[:, None])],
                           [sp.csr_matrix(w[None, :]), None]]).tocsr()
             sol = solve_refined(Ab, np.concatenate([b, [-c0]]))
-            X = sol[:2 * ns]
-        U, P = X[:ns], X[ns:]
+            X = sol[:nU + nP]
+        U, P = X[:nU], X[nU:]
     p = np.zeros((prob.ny, prob.nx))
     F = np.zeros((4, prob.ny, prob.nx))
     for (I, J), r in loc.items():
-        g = robin_data(r, U, P, dec.seg_beta)
+        g = robin_data(r, U, P, dec)
         pl = (r.pbar + r.Psi @ g).reshape(dec.by, dec.bx)
         cs = dec.subdomain_cells(I, J)
         p[cs] = pl

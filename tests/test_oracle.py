@@ -362,3 +362,33 @@ def test_alpha_trend_homogeneous():
     for alpha in (1.0, 1e3, 1e6):
         assert errs[alpha, 4] < errs[alpha, 1]
     assert errs[1e6, 4] < 1e-5
+
+
+# ------------------------------------------------- O-4, extended precision
+def test_extended_precision_monolithic_agrees_at_alpha_1():
+    """The extended-precision refinement of O-4 changes nothing where the
+    system is well conditioned; there it equals O-3."""
+    P = make_problem(32, b=8, seg=2, log_var=3.0, source=True, bc="mixed")
+    p0, F0, U0, P0 = monolithic_solve(P)
+    p1, F1, U1, P1 = monolithic_solve(P, ext_iters=3)
+    assert rel_l2(p1, p0) < 1e-13 and rel_l2(F1, F0) < 1e-12
+    r = mrcm_solve(P)
+    assert rel_l2(r.p, p1) < 1e-12 and rel_l2(r.F, F1) < 1e-12
+
+
+def test_alpha_1e6_accuracy_floor():
+    """At alpha = 1e6 the discrete system is ill conditioned: its exact
+    solution (O-4 refined in extended precision) moves by well under 1e-10
+    when every permeability changes by one unit in the last place (the
+    reference is well defined at that level), while the FP64 oracle O-3 is
+    within 2e-9 of it but not within 1e-10 (the floor of FP64 solvers,
+    against which the GPU path at this alpha is tested)."""
+    P = make_problem(64, b=16, seg=4, alpha=1e6, log_var=3.0, lam=0.1, seed=40, source=True)
+    p, F, _U, _P = monolithic_solve(P, ext_iters=4)
+    rng = np.random.default_rng(1)
+    K2 = P.K * (1 + np.finfo(float).eps * rng.choice([-1.0, 1.0], size=P.K.shape))
+    p2, F2, _U2, _P2 = monolithic_solve(P.with_(K=K2), ext_iters=4)
+    assert rel_l2(p2, p) < 1e-10 and rel_l2(F2, F) < 1e-10
+    r = mrcm_solve(P)
+    assert rel_l2(r.p, p) < 2e-9 and rel_l2(r.F, F) < 2e-9
+    assert max(rel_l2(r.p, p), rel_l2(r.F, F)) > 1e-11

@@ -42,6 +42,12 @@ class Problem:
     ly: float = 1.0
     name: str = ""
     meta: dict = field(default_factory=dict)
+    # general MRCM interface spaces (Section 2, with the U and P spaces
+    # chosen apart): piecewise constant U_H on segments of seg_u cells and
+    # P_H on segments of seg_p cells; 0 = seg (the MuMM choice of Section 4,
+    # both spaces on the same segments)
+    seg_u: int = 0
+    seg_p: int = 0
 
     def with_(self, **kw) -> "Problem":
         return replace(self, **kw)
