@@ -267,23 +267,43 @@ def copy_calibration(mib=512, reps=3):
     return {"bytes_read": n * 8, "bytes_written": n * 8, "dispatches": reps}
 
 
-def train_quick_surrogate(prob, path, npairs, seed=4000):
-    """A small surrogate for the workload's subdomain size, trained on the
-    GPU on pairs from the local solver (the learned mode needs one)."""
+def train_surrogate(prob, path, npairs, epochs=4, seed=4000, nval=2000):
+    """The surrogate for the workload's subdomain size, trained on the GPU on
+    pairs from the library's own FP64 local solver (random log-normal
+    fields, log-variance 2-5), then scored on held-out pairs against the
+    best input-independent predictor (the training mean of every basis
+    field)."""
+    import torch
     from paper_2009_07965_amd import Net, learned
     S = prob.sub_nx
     R = 2 * (prob.sub_nx + prob.sub_ny) // prob.seg
     t0 = time.perf_counter()
-    x, t = learned.generate_pairs(npairs, sub=S, seg=prob.seg, m=8, seed=seed)
+    m = max(8, 512 // S)            # subdomains per side of each generating field
+    x, t = learned.generate_pairs(npairs + nval, sub=S, seg=prob.seg, m=m, seed=seed)
+    xv, tv = x[npairs:], t[npairs:]
+    x, t = x[:npairs], t[:npairs]
+    t_gen = time.perf_counter() - t0
+    print("[bench] surrogate: %d pairs of %d^2 patches in %.1f s" % (npairs, S, t_gen), file=sys.stderr,
+          flush=True)
     net = Net(S, 16, 5, R, max_batch=128)
     try:
         net.set_params(learned.init_params(S, 16, 5, R, seed=1))
-        learned.train(net, x, t, epochs=4, batch=128, lr=2e-3, seed=0)
+        t1 = time.perf_counter()
+        learned.train(net, x, t, epochs=epochs, batch=128, lr=2e-3, seed=0,
+                      log=lambda r: print("[bench] surrogate epoch %d: %.1f s" % (r["epoch"], r["seconds"]),
+                                          file=sys.stderr, flush=True))
+        t_train = time.perf_counter() - t1
+        err = learned.rel_error(learned.predict(net, xv), tv)
+        mean = t.mean(dim=0, keepdim=True).expand_as(tv)
+        err_mean = learned.rel_error(mean.contiguous(), tv)
         net.save(path)
     finally:
         net.close()
-    return {"pairs": npairs, "width": 16, "layers": 5, "epochs": 4,
-            "train_s": time.perf_counter() - t0}
+    del x, t, xv, tv
+    torch.cuda.empty_cache()
+    return {"pairs": npairs, "width": 16, "layers": 5, "epochs": epochs, "generate_s": t_gen,
+            "train_s": t_train, "heldout_pairs": nval, "heldout_basis_rel_err": err,
+            "mean_predictor_rel_err": err_mean}
 
 
 WORKLOADS = {
@@ -384,10 +404,17 @@ def run_workload(cfg, modes, args, stream):
     if "mixed+learned" in modes:
         wdir = tempfile.mkdtemp()
         wpath = os.path.join(wdir, "surrogate.bin")
-        learned_info = train_quick_surrogate(prob, wpath, args.learned_pairs)
+        npairs = args.learned_pairs if prob.sub_nx <= 16 else args.learned_pairs_32
+        learned_info = train_surrogate(prob, wpath, npairs)
         runs["mixed+learned"] = measure(prob, RMRCM_MIXED_LEARNED, args.steps, args.warmup, stream,
                                         arrays, ir_tol=args.ir_tol, gate_tol=args.gate_tol,
                                         cnn_weights=wpath.encode())
+        # looser gates: accepted predictions start the refinement, so the
+        # flux error stays that of the mixed mode at every gate
+        for tau in [float(x) for x in args.gate_sweep.split(",") if x]:
+            runs["mixed+learned@gate=%g" % tau] = measure(
+                prob, RMRCM_MIXED_LEARNED, max(3, args.steps // 2), 1, stream, arrays,
+                ir_tol=args.ir_tol, gate_tol=tau, cnn_weights=wpath.encode())
         os.remove(wpath)
         os.rmdir(wdir)
     ref = runs["fp64"]
@@ -480,7 +507,12 @@ def main():
     ap.add_argument("--ir-tol", type=float, default=1e-8,
                     help="refinement tolerance of the mixed modes (chosen for the 1e-6 flux target)")
     ap.add_argument("--gate-tol", type=float, default=1e-8, help="residual gate of the learned mode")
-    ap.add_argument("--learned-pairs", type=int, default=3000)
+    ap.add_argument("--learned-pairs", type=int, default=200000,
+                    help="training pairs of the surrogate for subdomains of at most 16^2 cells")
+    ap.add_argument("--learned-pairs-32", type=int, default=25000,
+                    help="training pairs of the surrogate for 32^2 subdomains")
+    ap.add_argument("--gate-sweep", default="0.01,1,1e30",
+                    help="further gates of the learned mode measured beside --gate-tol")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true", help="FP64 only, no secondary workloads")
     ap.add_argument("--copy-calibration", action="store_true",

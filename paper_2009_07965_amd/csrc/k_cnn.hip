@@ -4,9 +4,13 @@
 // centred log-permeability and the log Robin parameters on the boundary
 // cells) to its R local basis fields (the basis problems of Section 2.1):
 // L 3x3 convolution layers with zero padding, ReLU between them, and a
-// learned mean field added to the output.  Compute and accumulation are
-// FP32; the convolution weights enter rounded to bfloat16 (round to
-// nearest even) from FP32 master weights, which Adam updates.
+// learned mean field added to the output.  The convolution weights enter
+// rounded to bfloat16 (round to nearest even) from FP32 master weights,
+// which Adam updates; activations and accumulation are FP32.  The
+// convolutions run on the matrix cores: forward and backward-data as
+// implicit GEMMs on the bfloat16 units with every FP32 input split exactly
+// in three bfloat16 pieces (so the products are the FP32 products), the
+// weight gradient on the FP32 units.
 //
 // Layout: activations [n][channel][j][i] (row j, column i), weights
 // [co][ci][3][3], parameter vector per layer W then b, then the mean field
@@ -23,155 +27,235 @@ __device__ inline float bf16_rne(float f) {
     return __uint_as_float(u & 0xFFFF0000u);
 }
 
-// y[n][o] = b[o] + sum_c W[o][c] (*) x[n][c] (+ mean field) (ReLU); one
-// workgroup per (sample, group of COB output channels), one thread per
-// pixel; the zero-padded input planes and the group's weights in LDS.
-template <int S, int COB>
-__global__ __launch_bounds__(S * S) void k_conv_fwd(const float* __restrict__ x, int ci,
-                                                    const float* __restrict__ W,
-                                                    const float* __restrict__ b, int co,
-                                                    const float* __restrict__ bmap, int relu,
-                                                    float* __restrict__ y) {
-    constexpr int P = S + 2, NT = S * S;
-    extern __shared__ float sm[];
-    float* xs = sm;
-    float* ws = xs + ci * P * P;
-    const int n = blockIdx.x, cb = blockIdx.y * COB, tid = threadIdx.x;
-    const int nco = min(COB, co - cb);
-    const float* xn = x + (size_t)n * ci * NT;
-    for (int t = tid; t < ci * P * P; t += NT) {
-        const int c = t / (P * P), r = t % (P * P), jj = r / P - 1, ii = r % P - 1;
-        xs[t] = (jj >= 0 && jj < S && ii >= 0 && ii < S) ? xn[(size_t)c * NT + jj * S + ii] : 0.f;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+// bfloat16 bits of f, round to nearest even.
+__device__ inline unsigned bf16_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// Three bfloat16 pieces whose sum is f exactly: the first holds f to 8
+// significant bits, the second the next 8 of the (exact) remainder, the
+// third the last 8; every product of a piece with a bfloat16 weight is
+// exact in FP32, so the matrix cores reproduce the FP32 products.
+__device__ inline void split3(float f, unsigned& h0, unsigned& h1, unsigned& h2) {
+    h0 = bf16_bits(f);
+    float r = f - __uint_as_float(h0 << 16);
+    h1 = bf16_bits(r);
+    r -= __uint_as_float(h1 << 16);
+    h2 = bf16_bits(r);
+}
+
+__device__ inline bf8v pack8(const unsigned (&h)[8]) {
+    u4v w;
+    w.x = h[0] | (h[1] << 16);
+    w.y = h[2] | (h[3] << 16);
+    w.z = h[4] | (h[5] << 16);
+    w.w = h[6] | (h[7] << 16);
+    return __builtin_bit_cast(bf8v, w);
+}
+
+// A 3x3 convolution with zero padding as an implicit GEMM on the bfloat16
+// matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation): rows = output
+// channels (MT tiles of 16), columns = pixels, reduction over (input
+// channel, tap) in steps of 32.  Forward (BWD false):
+//     y[n][o][p] = b[o] + sum_{c,tap} W[o][c][tap] x[n][c][p + tap] (+ mean field) (ReLU);
+// backward data (BWD true), the transposed and flipped weights:
+//     dx[n][c][p] = sum_{o,tap} W[o][c][8 - tap] dy[n][o][p + tap - (1,1)...]
+// i.e. the same access of the zero-padded planes with tap' = 8 - tap, then
+// the ReLU mask of the layer input.  A workgroup (four waves, 64 pixels
+// each) takes 256 consecutive pixels: several whole samples (S = 8), one
+// sample (16) or a band of rows of one (32); its input planes with a
+// one-cell halo are staged in LDS.  Each input value is split in three
+// bfloat16 pieces (exact), the weights are bfloat16 already: three products
+// per step give the FP32 products exactly.
+template <int S, int MT, bool BWD>
+__global__ __launch_bounds__(256) void k_conv_mfma(const float* __restrict__ x, int cin,
+                                                   const float* __restrict__ W, int wci,
+                                                   const float* __restrict__ b, int cout,
+                                                   const float* __restrict__ bmap, int relu,
+                                                   const float* __restrict__ mask, int nb,
+                                                   float* __restrict__ y) {
+    constexpr int NT = S * S, P = S + 2;
+    constexpr int SPW = NT >= 256 ? 1 : 256 / NT;      // samples per workgroup
+    constexpr int RW = NT >= 256 ? 256 / S : S;         // rows per workgroup
+    constexpr int PR = RW + 2;                          // staged padded rows
+    extern __shared__ float xs[];                       // [SPW][cin][PR][P]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    int n0, r0;
+    if (NT >= 256) {
+        constexpr int per = NT / 256;
+        n0 = blockIdx.x / per;
+        r0 = (blockIdx.x % per) * RW;
+    } else {
+        n0 = blockIdx.x * SPW;
+        r0 = 0;
     }
-    for (int t = tid; t < COB * ci * 9; t += NT) {
-        const int o = t / (ci * 9);
-        ws[t] = o < nco ? W[(size_t)(cb + o) * ci * 9 + t % (ci * 9)] : 0.f;
+    for (int t = tid; t < SPW * cin * PR * P; t += 256) {
+        const int pc = t % P, pr = (t / P) % PR, c = (t / (P * PR)) % cin, ls = t / (P * PR * cin);
+        const int n = n0 + ls, jj = r0 + pr - 1, ii = pc - 1;
+        xs[t] = (n < nb && jj >= 0 && jj < S && ii >= 0 && ii < S) ? x[((size_t)n * cin + c) * NT + jj * S + ii]
+                                                                    : 0.f;
     }
     __syncthreads();
-    const int j = tid / S, i = tid % S;
-    float acc[COB];
+    const int K = cin * 9, KS = (K + 31) / 32;
+    f4v acc[MT][4];
 #pragma unroll
-    for (int o = 0; o < COB; ++o) acc[o] = o < nco ? b[cb + o] : 0.f;
-    for (int c = 0; c < ci; ++c) {
-        const float* xc = xs + c * P * P + j * P + i;
-        float xv[9];
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+        // weights of rows 16 mt + l16 at reduction indices 32 ks + 8 lq + j
+        bf8v a[MT];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) xv[a * 3 + d] = xc[a * P + d];
+        for (int mt = 0; mt < MT; ++mt) {
+            unsigned h[8];
+            const int o = 16 * mt + l16;
 #pragma unroll
-        for (int o = 0; o < COB; ++o) {
-            const float* w = ws + (o * ci + c) * 9;
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * ks + 8 * lq + j, c = k / 9, tap = k % 9;
+                float v = 0.f;
+                if (o < cout && k < K)
+                    v = BWD ? W[((size_t)c * wci + o) * 9 + (8 - tap)] : W[((size_t)o * wci + c) * 9 + tap];
+                h[j] = bf16_bits(v);                    // exact: the weights are bfloat16
+            }
+            a[mt] = pack8(h);
+        }
 #pragma unroll
-            for (int k = 0; k < 9; ++k) acc[o] = fmaf(w[k], xv[k], acc[o]);
+        for (int nt = 0; nt < 4; ++nt) {
+            const int q = 64 * w + 16 * nt + l16;       // pixel column of this lane
+            const int ls = q / NT, p = q % NT + r0 * S;
+            const int row = p / S, col = p % S;
+            unsigned h0[8], h1[8], h2[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int k = 32 * ks + 8 * lq + j, c = k / 9, tap = k % 9;
+                const float v = k < K ? xs[((ls * cin + c) * PR + (row - r0 + tap / 3)) * P + col + tap % 3] : 0.f;
+                split3(v, h0[j], h1[j], h2[j]);
+            }
+            const bf8v b0 = pack8(h0), b1 = pack8(h1), b2 = pack8(h2);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b0, acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b1, acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b2, acc[mt][nt], 0, 0, 0);
+            }
         }
     }
+    // lane l holds column l % 16 (a pixel) and rows 4 (l / 16) + v (channels)
 #pragma unroll
-    for (int o = 0; o < COB; ++o) {
-        if (o >= nco) break;
-        float v = acc[o];
-        if (bmap) v += bmap[(size_t)(cb + o) * NT + tid];
-        if (relu) v = fmaxf(v, 0.f);
-        y[((size_t)n * co + cb + o) * NT + tid] = v;
+    for (int nt = 0; nt < 4; ++nt) {
+        const int q = 64 * w + 16 * nt + l16;
+        const int n = n0 + q / NT, p = q % NT + r0 * S;
+        if (n >= nb) continue;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 16 * mt + 4 * lq + v;
+                if (o >= cout) continue;
+                const size_t at = ((size_t)n * cout + o) * NT + p;
+                float r = acc[mt][nt][v];
+                if (BWD) {
+                    if (mask && !(mask[at] > 0.f)) r = 0.f;
+                } else {
+                    r += b[o];
+                    if (bmap) r += bmap[(size_t)o * NT + p];
+                    if (relu) r = fmaxf(r, 0.f);
+                }
+                y[at] = r;
+            }
     }
 }
 
-// dx[n][c] = sum_o W[o][c] (*)^T dy[n][o], times the ReLU mask (x_in > 0)
-// of the layer input when `mask` is given.
-template <int S, int CIB>
-__global__ __launch_bounds__(S * S) void k_conv_bwd_data(const float* __restrict__ dy, int co,
-                                                         const float* __restrict__ W, int ci,
-                                                         const float* __restrict__ mask,
-                                                         float* __restrict__ dx) {
-    constexpr int P = S + 2, NT = S * S;
+// Partial weight and bias gradients of one chunk of samples on the FP32
+// matrix cores (v_mfma_f32_16x16x4f32): part[chunk][o][q] =
+// sum over the chunk's samples and pixels p of dy[n][o][p] x[n][c][p + tap]
+// for q = 9 c + tap, and of dy[n][o][p] for q = 9 cin (the bias column, a
+// column of ones).  Rows = output channels (MT tiles), columns = q (tiles
+// of 16 over the four waves), reduction over pixels in bands of RB rows
+// staged in LDS (the input with a one-cell halo, the output gradient).
+// One workgroup per chunk; samples and bands in a fixed order.
+template <int S, int MT>
+__global__ __launch_bounds__(256) void k_conv_bwd_w_mfma(const float* __restrict__ x, int ci,
+                                                         const float* __restrict__ dy, int co, int nb,
+                                                         int chunk, float* __restrict__ part) {
+    constexpr int NT = S * S, P = S + 2;
+    constexpr int RB = NT >= 256 ? 256 / S : S;         // rows per band (256 pixels or the sample)
+    constexpr int PR = RB + 2;
     extern __shared__ float sm[];
-    float* ds = sm;
-    float* ws = ds + co * P * P;
-    const int n = blockIdx.x, cb = blockIdx.y * CIB, tid = threadIdx.x;
-    const int nci = min(CIB, ci - cb);
-    const float* dn = dy + (size_t)n * co * NT;
-    for (int t = tid; t < co * P * P; t += NT) {
-        const int o = t / (P * P), r = t % (P * P), jj = r / P - 1, ii = r % P - 1;
-        ds[t] = (jj >= 0 && jj < S && ii >= 0 && ii < S) ? dn[(size_t)o * NT + jj * S + ii] : 0.f;
-    }
-    for (int t = tid; t < co * CIB * 9; t += NT) {
-        const int o = t / (CIB * 9), r = t % (CIB * 9), c = r / 9;
-        ws[t] = c < nci ? W[((size_t)o * ci + cb + c) * 9 + r % 9] : 0.f;
-    }
-    __syncthreads();
-    const int j = tid / S, i = tid % S;
-    float acc[CIB];
+    float* xs = sm;                                     // [ci][PR][P]
+    float* ds = xs + ci * PR * P;                       // [co][RB][S]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, lq = lane >> 4;
+    const int ck = blockIdx.x;
+    const int nq = ci * 9 + 1, NQT = (nq + 15) / 16;
+    constexpr int MAXT = 5;                             // column tiles per wave (ci <= 35)
+    f4v acc[MT][MAXT];
 #pragma unroll
-    for (int c = 0; c < CIB; ++c) acc[c] = 0.f;
-    for (int o = 0; o < co; ++o) {
-        // x[j][i] feeds y[j - a + 1][i - d + 1]: padded row j - a + 2
-        const float* dc = ds + o * P * P + (j + 2) * P + (i + 2);
-        float dv[9];
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) dv[a * 3 + d] = dc[-a * P - d];
-#pragma unroll
-        for (int c = 0; c < CIB; ++c) {
-            const float* w = ws + (o * CIB + c) * 9;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) acc[c] = fmaf(w[k], dv[k], acc[c]);
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < CIB; ++c) {
-        if (c >= nci) break;
-        const size_t o = ((size_t)n * ci + cb + c) * NT + tid;
-        float v = acc[c];
-        if (mask && !(mask[o] > 0.f)) v = 0.f;
-        dx[o] = v;
-    }
-}
-
-// Partial weight and bias gradients of one chunk of samples:
-// part[chunk][o][q], q < ci*9: sum_n sum_p dy[n][o][p] x[n][c][p + offset],
-// q = ci*9: sum_n sum_p dy[n][o][p].  One workgroup per (chunk, o).
-template <int S>
-__global__ __launch_bounds__(256) void k_conv_bwd_w(const float* __restrict__ x, int ci,
-                                                    const float* __restrict__ dy, int co, int nb,
-                                                    int chunk, float* __restrict__ part) {
-    constexpr int P = S + 2, NT = S * S;
-    extern __shared__ float sm[];
-    float* ds = sm;            // NT
-    float* xs = ds + NT;       // ci * P * P
-    const int ck = blockIdx.x, o = blockIdx.y, tid = threadIdx.x;
-    const int nq = ci * 9 + 1;
-    float acc[2] = {0.f, 0.f};
+        for (int u = 0; u < MAXT; ++u) acc[mt][u] = f4v{0.f, 0.f, 0.f, 0.f};
     const int n0 = ck * chunk, n1 = min(nb, n0 + chunk);
     for (int n = n0; n < n1; ++n) {
-        const float* xn = x + (size_t)n * ci * NT;
-        for (int t = tid; t < NT; t += 256) ds[t] = dy[((size_t)n * co + o) * NT + t];
-        for (int t = tid; t < ci * P * P; t += 256) {
-            const int c = t / (P * P), r = t % (P * P), jj = r / P - 1, ii = r % P - 1;
-            xs[t] = (jj >= 0 && jj < S && ii >= 0 && ii < S) ? xn[(size_t)c * NT + jj * S + ii] : 0.f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int q = tid + 256 * u;
-            if (q >= nq) continue;
-            float s = 0.f;
-            if (q == nq - 1) {
-                for (int p = 0; p < NT; ++p) s += ds[p];
-            } else {
-                const int c = q / 9, k = q % 9, a = k / 3, d = k % 3;
-                const float* xc = xs + c * P * P + a * P + d;
-                for (int jj = 0; jj < S; ++jj)
-                    for (int ii = 0; ii < S; ++ii) s = fmaf(ds[jj * S + ii], xc[jj * P + ii], s);
+        for (int r0 = 0; r0 < S; r0 += RB) {
+            __syncthreads();
+            for (int t = tid; t < ci * PR * P; t += 256) {
+                const int pc = t % P, pr = (t / P) % PR, c = t / (P * PR);
+                const int jj = r0 + pr - 1, ii = pc - 1;
+                xs[t] = (jj >= 0 && jj < S && ii >= 0 && ii < S) ? x[((size_t)n * ci + c) * NT + jj * S + ii] : 0.f;
             }
-            acc[u] += s;
+            for (int t = tid; t < co * RB * S; t += 256) {
+                const int o = t / (RB * S), p = t % (RB * S);
+                ds[t] = dy[((size_t)n * co + o) * NT + r0 * S + p];
+            }
+            __syncthreads();
+            for (int k0 = 0; k0 < RB * S; k0 += 4) {
+                const int pk = k0 + lq;                 // pixel of this lane's reduction index
+                const int row = pk / S, col = pk % S;
+                float av[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const int o = 16 * mt + l16;
+                    av[mt] = o < co ? ds[(o * RB + row) * S + col] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < MAXT; ++u) {
+                    const int tq = w + 4 * u;
+                    if (tq >= NQT) break;               // uniform per wave
+                    const int q = 16 * tq + l16;
+                    float bv = 0.f;
+                    if (q < nq - 1) {
+                        const int c = q / 9, tap = q % 9;
+                        bv = xs[(c * PR + row + tap / 3) * P + col + tap % 3];
+                    } else if (q == nq - 1) {
+                        bv = 1.f;
+                    }
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mt], bv, acc[mt][u], 0, 0, 0);
+                }
+            }
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int q = tid + 256 * u;
-        if (q < nq) part[((size_t)ck * co + o) * nq + q] = acc[u];
+    for (int u = 0; u < MAXT; ++u) {
+        const int tq = w + 4 * u;
+        if (tq >= NQT) break;
+        const int q = 16 * tq + l16;
+        if (q >= nq) continue;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = 16 * mt + 4 * lq + v;
+                if (o < co) part[((size_t)ck * co + o) * nq + q] = acc[mt][u][v];
+            }
     }
 }
 
@@ -254,18 +338,35 @@ __global__ void k_round_copy(const float* __restrict__ th, const unsigned char* 
 
 // ---------------------------------------------------------------- launchers
 namespace {
-constexpr int kCOB = 8, kCIB = 8;
+template <int S>
+constexpr int conv_workgroups(int nb) {
+    return S * S >= 256 ? nb * (S * S / 256) : (nb + 256 / (S * S) - 1) / (256 / (S * S));
+}
+template <int S>
+constexpr size_t conv_lds(int cin) {
+    return sizeof(float) * (size_t)(S * S >= 256 ? 1 : 256 / (S * S)) * cin *
+           ((S * S >= 256 ? 256 / S : S) + 2) * (S + 2);
+}
+
+template <int S, bool BWD>
+hipError_t conv_mfma_s(hipStream_t st, int nb, const float* x, int cin, const float* W, int wci,
+                       const float* b, int cout, const float* bmap, int relu, const float* mask, float* y) {
+    const size_t lds = conv_lds<S>(cin);
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(conv_workgroups<S>(nb)), dim3(256), lds, st, x, cin, W, wci, b, cout,
+                           bmap, relu, mask, nb, y);
+        return hipGetLastError();
+    };
+    return cout <= 16 ? go(k_conv_mfma<S, 1, BWD>) : go(k_conv_mfma<S, 2, BWD>);
+}
 
 template <int S>
 hipError_t conv_fwd_s(hipStream_t st, int nb, const float* x, int ci, const float* W, const float* b,
                       int co, const float* bmap, int relu, float* y) {
-    const size_t lds = sizeof(float) * ((size_t)ci * (S + 2) * (S + 2) + (size_t)kCOB * ci * 9);
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_fwd<S, kCOB>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_conv_fwd<S, kCOB>), dim3(nb, (co + kCOB - 1) / kCOB), dim3(S * S), lds, st,
-                       x, ci, W, b, co, bmap, relu, y);
-    return hipGetLastError();
+    return conv_mfma_s<S, false>(st, nb, x, ci, W, ci, b, co, bmap, relu, nullptr, y);
 }
 
 template <int S>
@@ -273,22 +374,23 @@ hipError_t conv_bwd_s(hipStream_t st, int nb, const float* x, int ci, const floa
                       const float* dy, float* dx, const float* mask, float* part, int chunk,
                       float* gW, float* gb) {
     const int nchunk = (nb + chunk - 1) / chunk;
-    size_t lds = sizeof(float) * ((size_t)S * S + (size_t)ci * (S + 2) * (S + 2));
-    hipError_t e = hipFuncSetAttribute((const void*)k_conv_bwd_w<S>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    constexpr int RB = S * S >= 256 ? 256 / S : S;
+    const size_t lds = sizeof(float) * ((size_t)ci * (RB + 2) * (S + 2) + (size_t)co * RB * S);
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(nchunk), dim3(256), lds, st, x, ci, dy, co, nb, chunk, part);
+        return hipGetLastError();
+    };
+    hipError_t e = co <= 16 ? go(k_conv_bwd_w_mfma<S, 1>) : go(k_conv_bwd_w_mfma<S, 2>);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_conv_bwd_w<S>, dim3(nchunk, co), dim3(256), lds, st, x, ci, dy, co, nb, chunk,
-                       part);
     const int nq = co * (ci * 9 + 1);
     hipLaunchKernelGGL(k_conv_reduce_w, dim3((nq + 255) / 256), dim3(256), 0, st, part, nchunk, co, ci,
                        gW, gb);
     if (dx) {
-        lds = sizeof(float) * ((size_t)co * (S + 2) * (S + 2) + (size_t)co * kCIB * 9);
-        e = hipFuncSetAttribute((const void*)k_conv_bwd_data<S, kCIB>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        e = conv_mfma_s<S, true>(st, nb, dy, co, W, ci, nullptr, ci, nullptr, 0, mask, dx);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_conv_bwd_data<S, kCIB>), dim3(nb, (ci + kCIB - 1) / kCIB), dim3(S * S),
-                           lds, st, dy, co, W, ci, mask, dx);
     }
     return hipGetLastError();
 }

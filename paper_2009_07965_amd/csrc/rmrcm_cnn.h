@@ -25,7 +25,7 @@ struct rmrcm_cnn {
     double* lpart = nullptr;               // loss partials
     double* loss = nullptr;
     int adam_t = 0;
-    int chunk = 8;                         // samples per weight-gradient partial
+    int chunk = 1;                         // samples per weight-gradient partial
     static constexpr int kLossBlocks = 256;
 };
 
