@@ -58,7 +58,8 @@ enum {
     RMRCM_ENOMEM = -2,     /* device or host allocation failed */
     RMRCM_EDEVICE = -3,    /* a HIP call failed */
     RMRCM_ESINGULAR = -4,  /* a local or interface system is singular */
-    RMRCM_ENOTCONV = -5,   /* iterative refinement did not converge */
+    RMRCM_ENOTCONV = -5,   /* iterative refinement did not converge (not returned by this
+                              version: subdomains that do not converge are redone in FP64) */
     RMRCM_ESTATE = -6,     /* call out of order (e.g. solve before setup) */
     RMRCM_ENOTSUP = -7,    /* configuration not supported by this build */
     RMRCM_ETOOBIG = -8     /* problem exceeds the fixed scratch of rmrcm_step_noalloc */
@@ -96,7 +97,9 @@ typedef struct {
     double ir_tol;           /* mixed: refinement stops when max over subdomains and
                                 columns of |b - A x|_inf / |b|_inf <= ir_tol; default 1e-11 */
     int32_t ir_max_iter;     /* mixed: refinement passes before the subdomains still above
-                                ir_tol are redone in FP64 (setup) or ENOTCONV (solve);
+                                ir_tol are redone in FP64 (setup: factor and basis, kept;
+                                solve: the particular solution, with an FP64 factor for
+                                that solve);
                                 default 6 */
     double gate_tol;         /* learned: residual gate tau >= 0; default 1e-6 */
     const char* cnn_weights; /* learned: weight file (required in that mode) */
@@ -105,6 +108,20 @@ typedef struct {
                                 rmrcm_plan_bytes); 0 = no limit.  A setup whose
                                 plan exceeds it returns RMRCM_ENOMEM before any
                                 device work. */
+    int32_t seg_u, seg_p;    /* general MRCM interface spaces (Section 2 leaves the flux
+                                space U_H and the pressure space P_H free; Section 4's
+                                MuMM takes both piecewise constant on the same
+                                segments): U_H piecewise constant on segments of seg_u
+                                cells, P_H on segments of seg_p cells; 0 = seg.  Each
+                                divides sub_nx and sub_ny and the longer is a multiple
+                                of the shorter.  The segments of the documented order,
+                                of the traces and of rmrcm_get_interface are then the
+                                pieces of min(seg_u, seg_p) cells (U and P constant
+                                over each U- and P-segment); beta is that of the
+                                piece's U-segment (Hbar its length, Keff over its
+                                faces); eq. 14.2 holds on U-segments and eq. 13.2 on
+                                P-segments.  rmrcm_step_noalloc supports only
+                                seg_u = seg_p = seg (ENOTSUP otherwise). */
 } rmrcm_params;
 
 /* Fill *p with defaults (alpha 1, FP64, unit square, device 0); the
@@ -175,9 +192,10 @@ int rmrcm_downscale(rmrcm_ctx* ctx, const double* source, const double* bc_value
 
 /* Mixed modes: the refinement tolerance and pass count of later setups
  * (rmrcm_refactor, rmrcm_step) and solves, in place of those the context
- * was built with (rmrcm_params.ir_tol, ir_max_iter; same meaning).  A solve
- * whose particular refinement does not reach ir_tol within ir_max_iter
- * passes reports RMRCM_ENOTCONV.  RMRCM_ENOTSUP for an FP64 context,
+ * was built with (rmrcm_params.ir_tol, ir_max_iter; same meaning).  The
+ * subdomains whose particular refinement does not reach ir_tol within
+ * ir_max_iter passes are solved again in FP64 (counted in the stats as
+ * fp64_particular_fallback_subdomains).  RMRCM_ENOTSUP for an FP64 context,
  * RMRCM_EINVAL for ir_tol <= 0 or ir_max_iter < 1.  A captured step graph
  * is dropped (captured again by the next step). */
 int rmrcm_set_refinement(rmrcm_ctx* ctx, double ir_tol, int32_t ir_max_iter);
@@ -247,7 +265,15 @@ int rmrcm_step_noalloc(const rmrcm_params* prm, const double* perm, const int8_t
  * and outer boundary data, additive split of Section 2.1), their columns
  * through the merges, the top interface solve, the downward propagation of
  * interface values and the final reconstruction of cell pressures and face
- * fluxes (eq. final).
+ * fluxes (eq. final).  Then up to two steps of iterative refinement of the
+ * interface data, decided on the device: when the residual of eq. 13.2 or
+ * eq. 14.2 of some segment, computed from the reconstructed one-sided
+ * fluxes and the Robin data and divided by the segment's Robin face
+ * conductances, exceeds 1e-13 times the largest |pressure| or |Robin
+ * datum| next to the skeleton, the residual is taken through the merges
+ * and the downward pass once more and the correction added (the explicit
+ * inverses of the merges lose digits when large alpha makes the interface
+ * blocks ill conditioned; at alpha near 1 no step runs).
  *   source:   nx*ny cell-integrated sources, or NULL for zero.
  *   bc_value: 2*nx + 2*ny values matching the setup's bc_type.
  *   pressure: out, nx*ny.     flux: out, 4*nx*ny (layout above).
@@ -274,7 +300,10 @@ int rmrcm_set_stream(rmrcm_ctx* ctx, void* hip_stream);
 
 /* JSON object with per-phase device times of the last setup and solve
  * (milliseconds, from HIP events recorded on the context's stream; waits
- * for those events), workspace bytes and counters.  Writes at most cap
+ * for those events), workspace bytes and counters (among them the
+ * interface residual before the refinement, the steps it ran and the
+ * residual after the first; the subdomains redone in FP64 by setup and
+ * solve in the mixed modes).  Writes at most cap
  * bytes including the terminating NUL; returns the length it needs, or a
  * negative error. */
 int rmrcm_get_stats(const rmrcm_ctx* ctx, char* json, size_t cap);

@@ -112,7 +112,11 @@ int validate(const rmrcm_params* p) {
         return RMRCM_EINVAL;
     if (!(p->alpha > 0) || !std::isfinite(p->alpha)) return RMRCM_EINVAL;
     if (p->nx % p->sub_nx || p->ny % p->sub_ny) return RMRCM_EINVAL;
-    if (p->sub_nx % p->seg || p->sub_ny % p->seg) return RMRCM_EINVAL;
+    if (p->seg_u < 0 || p->seg_p < 0) return RMRCM_EINVAL;
+    const int su = p->seg_u ? p->seg_u : p->seg, sp = p->seg_p ? p->seg_p : p->seg;
+    const int piece = std::min(su, sp);
+    if (p->sub_nx % su || p->sub_ny % su || p->sub_nx % sp || p->sub_ny % sp) return RMRCM_EINVAL;
+    if (std::max(su, sp) % piece) return RMRCM_EINVAL;
     if (!is_pow2(p->nx / p->sub_nx) || !is_pow2(p->ny / p->sub_ny)) return RMRCM_EINVAL;
     if (p->precision < RMRCM_FP64 || p->precision > RMRCM_MIXED_LEARNED) return RMRCM_EINVAL;
     if (p->sub_nx != 4 && p->sub_nx != 8 && p->sub_nx != 16 && p->sub_nx != 32) return RMRCM_ENOTSUP;
@@ -123,7 +127,7 @@ int validate(const rmrcm_params* p) {
         if (p->sub_nx != p->sub_ny || p->sub_nx < 8) return RMRCM_ENOTSUP;
     }
     // the basis block of one subdomain row must fit the local kernel's LDS
-    const int R = 2 * (p->sub_nx + p->sub_ny) / p->seg;
+    const int R = 2 * (p->sub_nx + p->sub_ny) / piece;
     const size_t lds = sizeof(double) * (size_t)(3 * p->sub_nx * p->sub_nx + 2 * p->sub_nx * R + 4 * p->sub_nx);
     if (lds > 160 * 1024) return RMRCM_ENOTSUP;
     return RMRCM_OK;
@@ -136,7 +140,10 @@ void build_geo(rmrcm_ctx* c) {
     g.ny = p.ny;
     g.bx = p.sub_nx;
     g.by = p.sub_ny;
-    g.sg = p.seg;
+    const int su = p.seg_u ? p.seg_u : p.seg, sp = p.seg_p ? p.seg_p : p.seg;
+    g.sg = std::min(su, sp);
+    g.mu = su / g.sg;
+    g.mp = sp / g.sg;
     g.mx = p.nx / p.sub_nx;
     g.my = p.ny / p.sub_ny;
     g.nsx = g.bx / g.sg;
@@ -254,8 +261,8 @@ int alloc_levels(rmrcm_ctx* c) {
             TRY(dalloc(c, &L.gseg, L.h_gseg.size()));
             TRY(dalloc(c, &L.M, (size_t)L.nnodes * L.xi * L.xi));
             TRY(dalloc(c, &L.X, (size_t)L.nnodes * L.xi * L.ld));
-            const size_t wk = rmrcm::merge_work_doubles(L);
-            if (wk) TRY(dalloc(c, &L.work, (size_t)L.nnodes * wk));
+            const size_t wk = rmrcm::merge_work_doubles(c, L);
+            if (wk) TRY(dalloc(c, &L.work, wk));
             // 64-slot tiles of every node that hold an active slot or the
             // particular column (the merge products skip the others)
             const int nt = (L.nslot + 1 + 63) / 64;
@@ -302,10 +309,14 @@ int alloc_arrays(rmrcm_ctx* c) {
     TRY(dalloc(c, &c->flags, rmrcm::kNumFlags));
     TRY(dalloc(c, &c->gauge, 256));
     TRY(dalloc(c, &c->dscal, 1));
+    TRY(dalloc(c, &c->iref_res, 2 * (size_t)g.nseg + 4));
+    TRY(dalloc(c, &c->iref_save, 2 * (size_t)g.nseg));
+    TRY(dalloc(c, &c->iref_flag, 2));
     if (c->prm.precision != RMRCM_FP64) {
         TRY(dalloc(c, &c->P32, nsub * g.by * g.bx * g.bx));
         TRY(dalloc(c, &c->Wsc, nsub * R * n));
         TRY(dalloc(c, &c->resid, nsub));
+        TRY(dalloc(c, &c->pfb, nsub));
         TRY(dalloc(c, &c->fb, nsub));
         TRY(dalloc(c, &c->irst, 4));
         TRY(dalloc(c, &c->irhist, 2 * rmrcm::kIrHist));
@@ -384,9 +395,13 @@ void free_all(rmrcm_ctx* c) {
     f(c->flags);
     f(c->gauge);
     f(c->dscal);
+    f(c->iref_res);
+    f(c->iref_save);
+    f(c->iref_flag);
     f(c->P32);
     f(c->Wsc);
     f(c->resid);
+    f(c->pfb);
     f(c->fb);
     f(c->irst);
     f(c->irhist);
@@ -542,6 +557,52 @@ int run_setup(rmrcm_ctx* c, bool wait) {
     return check_flags(c);
 }
 
+// One step of iterative refinement of the interface data, enqueued after
+// the reconstruction (graph-capturable, no host synchronisation): the
+// residuals of eq. 13.2 and 14.2 of every segment from the reconstructed
+// fluxes and the Robin data; when the largest of them exceeds
+// kIfaceTol times the pressure scale, the device flag runs the particular
+// chain once more with the residual shares as the leaf particular traces,
+// and the correction it yields is added to the Robin data before the
+// reconstruction and the gauge run again.  With the flag clear every
+// kernel of that chain returns at once.
+constexpr double kIfaceTol = 1e-13;
+// one step: at alpha = 1e6 it takes the residual from ~1e-11 to ~1e-15;
+// where it gains little (alpha = 1e-6: the residual is the cancellation in
+// the fluxes of the nearly-Dirichlet Robin faces) a second one gains
+// nothing more.  The flag and maxima arrays hold kIfaceSteps + 1 entries
+// (the last for the residual after the steps).
+constexpr int kIfaceSteps = 1;
+
+int interface_refine(rmrcm_ctx* c) {
+    if (c->D == 0 || c->geo.nseg == 0) return RMRCM_OK;
+    double* mx = c->iref_res + 2 * (size_t)c->geo.nseg;
+    for (int k = 0; k < kIfaceSteps; ++k) {
+        // step k > 0 runs only after step k - 1 ran (its residual kernel
+        // is skipped otherwise, and the cleared maxima then clear its flag)
+        HIP_TRY(rmrcm::launch_fill_i32(c, c->iref_flag + k, 1, 0));
+        HIP_TRY(rmrcm::launch_fill_i32(c, reinterpret_cast<int*>(mx + 2 * k), 4, 0));
+        HIP_TRY(rmrcm::launch_iface_resid(c, kIfaceTol, mx + 2 * k, c->iref_flag + k,
+                                          k ? c->iref_flag + k - 1 : nullptr));
+        c->run_ptr = c->iref_flag + k;
+        hipError_t e = rmrcm::launch_iface_inject(c);
+        for (int d = c->D - 1; d >= 0 && e == hipSuccess; --d) e = rmrcm::launch_merge_particular(c, d);
+        if (e == hipSuccess) e = rmrcm::launch_down_all(c);
+        if (e == hipSuccess) e = rmrcm::launch_iface_apply(c);
+        if (e == hipSuccess) e = rmrcm::launch_reconstruct(c);
+        if (e == hipSuccess && !c->any_dirichlet) e = rmrcm::launch_gauge(c);
+        c->run_ptr = nullptr;
+        HIP_TRY(e);
+    }
+    // the residual after the last step, for the statistics (measured only
+    // when that step ran; its flag slot is not acted on)
+    const int k = kIfaceSteps;
+    HIP_TRY(rmrcm::launch_fill_i32(c, c->iref_flag + k, 1, 0));
+    HIP_TRY(rmrcm::launch_fill_i32(c, reinterpret_cast<int*>(mx + 2 * k), 4, 0));
+    HIP_TRY(rmrcm::launch_iface_resid(c, kIfaceTol, mx + 2 * k, c->iref_flag + k, c->iref_flag + k - 1));
+    return RMRCM_OK;
+}
+
 // Inputs of a solve into the context's staging buffers.
 int solve_inputs(rmrcm_ctx* c, const double* source, const double* bc_value) {
     const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
@@ -597,6 +658,8 @@ int solve_overlapped(rmrcm_ctx* c, const double* source, const double* bc_value)
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
     TRY(mark(c, 9));
+    TRY(interface_refine(c));
+    TRY(mark(c, 16));
     HIP_TRY(hipEventRecord(c->ev_done, c->stream));
     c->done_recorded = true;
     c->solve_overlapped = true;
@@ -611,9 +674,16 @@ int enqueue_solve(rmrcm_ctx* c) {
         HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 0, 0));
         if (learned(c)) HIP_TRY(rmrcm::launch_local_particular(c, true, c->fb, 2, 0));
         HIP_TRY(rmrcm::launch_local_particular(c, false, c->fb, 1, 1));   // FP64-redone subdomains
-        HIP_TRY(rmrcm::launch_fill_i32(c, c->flags + rmrcm::FLAG_NOTCONV, 1, 0));
+        HIP_TRY(rmrcm::launch_fill_i32(c, c->flags + rmrcm::FLAG_PFALLBACK, 1, 0));
+        HIP_TRY(rmrcm::launch_fill_i32(c, c->pfb, (size_t)c->geo.mx * c->geo.my, 0));
         TRY(refine_loop(c, 1));
-        HIP_TRY(rmrcm::launch_ir_notconv(c));
+        // particular solutions still above ir_tol (only if the refinement
+        // did not converge: these kernels return at once otherwise) are
+        // solved again in FP64, with an FP64 factor of their subdomain
+        HIP_TRY(rmrcm::launch_local_refine(c, 1, 0));   // measure only
+        HIP_TRY(rmrcm::launch_mark_part_fallback(c));
+        HIP_TRY(rmrcm::launch_local_setup(c, false, c->pfb, 1, 0, 0));
+        HIP_TRY(rmrcm::launch_local_particular(c, false, c->pfb, 1, 1));
         HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 0));
         if (learned(c)) HIP_TRY(rmrcm::launch_local_traces(c, 1, c->fb, 2));
         HIP_TRY(rmrcm::launch_trace_correct(c, 0, 1));
@@ -630,6 +700,8 @@ int enqueue_solve(rmrcm_ctx* c) {
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
     TRY(mark(c, 9));
+    TRY(interface_refine(c));
+    TRY(mark(c, 16));
     return RMRCM_OK;
 }
 
@@ -669,6 +741,8 @@ int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
     HIP_TRY(rmrcm::launch_reconstruct(c));
     if (!c->any_dirichlet) HIP_TRY(rmrcm::launch_gauge(c));
     TRY(mark(c, 9));
+    TRY(interface_refine(c));
+    TRY(mark(c, 16));
     TRY(mark(c, 10));
     return RMRCM_OK;
 }
@@ -937,7 +1011,8 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         c->t_solve_ms[2] = elapsed(c->ev[6], c->ev[7]);
         c->t_solve_ms[3] = elapsed(c->ev[7], c->ev[8]);
         c->t_solve_ms[4] = elapsed(c->ev[8], c->ev[9]);
-        c->t_solve_ms[5] = elapsed(c->ev[9], c->ev[10]);
+        c->t_solve_ms[7] = elapsed(c->ev[9], c->ev[16]);
+        c->t_solve_ms[5] = elapsed(c->ev[16], c->ev[10]);
         c->t_solve_ms[6] = elapsed(c->ev[4], c->ev[10]);
     }
     if (mixed(c) && hipStreamSynchronize(c->stream) == hipSuccess) {
@@ -951,11 +1026,26 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
             hipMemcpy(hist, c->irhist, sizeof(hist), hipMemcpyDeviceToHost) == hipSuccess) {
             c->n_accepted = h[rmrcm::FLAG_ACCEPTED];
             c->n_fallback = h[rmrcm::FLAG_FALLBACK];
+            c->n_pfallback = h[rmrcm::FLAG_PFALLBACK];
             c->ir_iters_setup = st[1];
             c->ir_iters_solve = st[3];
             const int k0 = std::min(st[1], rmrcm::kIrHist), k1 = std::min(st[3], rmrcm::kIrHist);
             c->ir_resid_setup = k0 > 0 ? hist[k0 - 1] : 0.0;
             c->ir_resid_solve = k1 > 0 ? hist[rmrcm::kIrHist + k1 - 1] : 0.0;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    // the interface residual before the last refinement check, its
+    // pressure scale and whether the refinement ran
+    if (c->iref_flag && c->geo.nseg > 0 && c->D > 0 && hipStreamSynchronize(c->stream) == hipSuccess) {
+        double m[4] = {};
+        int fl[2] = {};
+        if (hipMemcpy(m, c->iref_res + 2 * (size_t)c->geo.nseg, sizeof(m), hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(fl, c->iref_flag, sizeof(fl), hipMemcpyDeviceToHost) == hipSuccess) {
+            c->iface_resid = m[1] > 0.0 ? m[0] / m[1] : m[0];
+            c->iface_resid_after = fl[0] ? (m[3] > 0.0 ? m[2] / m[3] : m[2]) : 0.0;
+            c->iface_refined = fl[0];
         } else {
             (void)hipGetLastError();
         }
@@ -971,13 +1061,16 @@ int rmrcm_get_stats(const rmrcm_ctx* cc, char* json, size_t cap) {
         "\"device_bytes\": %zu, \"precision\": %d, \"ir_iters_setup\": %d, "
         "\"ir_iters_solve\": %d, \"ir_resid_setup\": %.3e, \"ir_resid_solve\": %.3e, "
         "\"fp64_fallback_subdomains\": %d, \"surrogate_accepted_subdomains\": %d, "
-        "\"gate_tol\": %.3e, \"particular_overlapped\": %s}",
+        "\"gate_tol\": %.3e, \"particular_overlapped\": %s, \"interface_residual\": %.3e, "
+        "\"interface_residual_refined\": %.3e, \"interface_refined\": %d, \"refine_ms\": %.6f, "
+        "\"fp64_particular_fallback_subdomains\": %d}",
         c->t_setup_ms[0], c->t_setup_ms[1], c->t_setup_ms[4], c->t_setup_ms[2], c->t_setup_ms[3], c->t_solve_ms[0],
         c->t_solve_ms[1], c->t_solve_ms[2], c->t_solve_ms[3], c->t_solve_ms[4], c->t_solve_ms[5],
         c->t_solve_ms[6], c->D, c->geo.nseg, c->geo.mx * c->geo.my, (long long)c->n_local_solves,
         c->device_bytes, c->prm.precision, c->ir_iters_setup, c->ir_iters_solve, c->ir_resid_setup,
         c->ir_resid_solve, c->n_fallback, c->n_accepted, c->prm.gate_tol,
-        c->solve_overlapped ? "true" : "false");
+        c->solve_overlapped ? "true" : "false", c->iface_resid, c->iface_resid_after, c->iface_refined,
+        c->t_solve_ms[7], c->n_pfallback);
     if (json && cap > 0) {
         std::strncpy(json, buf, cap - 1);
         json[cap - 1] = '\0';
@@ -1732,6 +1825,9 @@ int noalloc_enqueue(rmrcm_ctx* c, const std::vector<int8_t>& ht, const double* p
     TRY(dalloc(c, &c->flags, rmrcm::kNumFlags));
     TRY(dalloc(c, &c->gauge, 256));
     TRY(dalloc(c, &c->dscal, 1));
+    TRY(dalloc(c, &c->iref_res, 2 * (size_t)g.nseg + 4));
+    TRY(dalloc(c, &c->iref_save, 2 * (size_t)g.nseg));
+    TRY(dalloc(c, &c->iref_flag, 2));
     if (!source) TRY(dalloc(c, &c->q, ncell));   // a zero source
     TRY(alloc_levels(c));
     // every array starts at zero, as hipMalloc'ed arrays do after dalloc
@@ -1754,6 +1850,7 @@ extern "C" int rmrcm_step_noalloc(const rmrcm_params* prm, const double* perm, c
     const int v = validate(prm);
     if (v != RMRCM_OK) return v;
     if (prm->precision != RMRCM_FP64) return RMRCM_ENOTSUP;
+    if ((prm->seg_u && prm->seg_u != prm->seg) || (prm->seg_p && prm->seg_p != prm->seg)) return RMRCM_ENOTSUP;
     if (!perm || !bc_type || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {

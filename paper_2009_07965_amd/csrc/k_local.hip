@@ -101,33 +101,37 @@ __device__ inline double bface(const Geo& g, const double* __restrict__ K,
 // ---------------------------------------------------------------- K0
 // Robin parameter per segment: beta_e = alpha * Hbar_e / Keff_e with Keff
 // the mean over the segment's faces of the harmonic mean of the two
-// adjacent permeabilities (Section 5.1).
+// adjacent permeabilities (Section 5.1).  With general interface spaces the
+// segment is the piece's U-segment (its g.mu pieces along the line, the
+// first at a multiple of g.mu); seglen is the piece's own length.
 __device__ inline void beta_of(const Geo& g, const double* __restrict__ K, double* __restrict__ beta,
                                double* __restrict__ seglen, int e) {
-    double hsum = 0.0, len;
+    double hsum = 0.0, len, h;
+    const int nf = g.mu * g.sg;             // faces of the U-segment
     if (e < g.nv) {
         const int I = e / g.lines_v + 1, k = e % g.lines_v;
-        const int ilo = I * g.bx - 1;
-        for (int t = 0; t < g.sg; ++t) {
-            const int j = k * g.sg + t;
+        const int ilo = I * g.bx - 1, k0 = k - k % g.mu;
+        for (int t = 0; t < nf; ++t) {
+            const int j = k0 * g.sg + t;
             const double a = cellK(K, g, ilo, j), b = cellK(K, g, ilo + 1, j);
             hsum += 2.0 * a * b / (a + b);
         }
-        len = g.sg * g.hy;
+        h = g.hy;
     } else {
         const int r = e - g.nv;
         const int J = r / g.lines_h + 1, k = r % g.lines_h;
-        const int jlo = J * g.by - 1;
-        for (int t = 0; t < g.sg; ++t) {
-            const int i = k * g.sg + t;
+        const int jlo = J * g.by - 1, k0 = k - k % g.mu;
+        for (int t = 0; t < nf; ++t) {
+            const int i = k0 * g.sg + t;
             const double a = cellK(K, g, i, jlo), b = cellK(K, g, i, jlo + 1);
             hsum += 2.0 * a * b / (a + b);
         }
-        len = g.sg * g.hx;
+        h = g.hx;
     }
-    const double keff = hsum / g.sg;
+    len = nf * h;
+    const double keff = hsum / nf;
     beta[e] = g.alpha * len / keff;
-    seglen[e] = len;
+    seglen[e] = g.sg * h;
 }
 
 
@@ -338,6 +342,19 @@ __host__ inline size_t carve_bytes(size_t count, size_t elem) { return (count * 
 // w_j = P_j z_j and the trailing update S_{j+1} = A_{j+1} - D_j P_j D_j.
 // Global loads are issued one row ahead of their use.  With a mask, only
 // subdomains whose mask entry equals `want` are processed.
+// A local factorisation that met a non-positive pivot: an error of the FP64
+// factorisation; in FP32 (fbm non-null, the mixed modes) the subdomain is
+// marked for the FP64 redo instead (large Robin parameters make the local
+// systems too ill conditioned for FP32).
+__device__ inline void report_singular(int* flags, int* fbm, int sub) {
+    if (fbm) {
+        fbm[sub] = 1;
+        atomicAdd(&flags[FLAG_FALLBACK], 1);
+    } else {
+        atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+    }
+}
+
 template <int BX, typename S>
 __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restrict__ K,
                                                     const int8_t* __restrict__ bct,
@@ -348,7 +365,7 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
                                                     double* __restrict__ T, int ld,
                                                     int* __restrict__ flags,
                                                     const int* __restrict__ mask, int want,
-                                                    int do_traces, int basis) {
+                                                    int do_traces, int basis, int* __restrict__ fbm) {
     const int sub = blockIdx.x;
     if (mask && mask[sub] != want) return;
     extern __shared__ __align__(16) char smem[];
@@ -477,7 +494,7 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
     // Wl holds x_{j+1}; lane c loads row c of P_j (= column c) and its own
     // row of w_j one step ahead.
     if (!basis) {
-        if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+        if (lane == 0 && sing) report_singular(flags, fbm, sub);
         return;
     }
     S pn[BX];
@@ -543,7 +560,7 @@ __global__ __launch_bounds__(64) void k_local_setup(Geo g, const double* __restr
             Tsub[(size_t)ar * ld + b] = s;
         }
     }
-    if (lane == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+    if (lane == 0 && sing) report_singular(flags, fbm, sub);
 }
 
 // ---------------------------------------------------------------- K1 (MFMA)
@@ -748,7 +765,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
                                                           double* __restrict__ T, int ld,
                                                           int* __restrict__ flags,
                                                           const int* __restrict__ mask, int want,
-                                                          int do_traces, int basis) {
+                                                          int do_traces, int basis, int* __restrict__ fbm) {
     static_assert(BX == 16 || BX == 32, "MFMA tiles of 16");
     typedef Mfma<S> M;
     typedef typename M::v4 v4;
@@ -902,7 +919,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
     }
     __syncthreads();                       // the last forward sweep
     if (!basis) {
-        if (tid == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+        if (tid == 0 && sing) report_singular(flags, fbm, sub);
         return;
     }
     // ---- backward sweep: x_{BY-1} = w_{BY-1}; x_j = w_j + P_j (D_j x_{j+1}).
@@ -988,7 +1005,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_mfma(Geo g, const double
             Tsub[(size_t)ar * ld + b] = s;
         }
     }
-    if (tid == 0 && sing) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+    if (tid == 0 && sing) report_singular(flags, fbm, sub);
 }
 
 // The particular column's product w = P z on the vector units, with P in the
@@ -2290,12 +2307,14 @@ __global__ __launch_bounds__(256) void k_max_resid(int nsub, const double* __res
     __shared__ double s[256];
     if (st[0]) return;
     double m = 0.0;
+    // a NaN residual (a diverged refinement) is kept: it must not pass
+    auto mx = [](double a, double b) { return (b > a || b != b) ? b : a; };
     for (int t = threadIdx.x; t < nsub; t += 256)
-        if (!mask || mask[t] != 1) m = fmax(m, resid[t]);
+        if (!mask || mask[t] != 1) m = mx(m, resid[t]);
     s[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+        if (threadIdx.x < w) s[threadIdx.x] = mx(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -2306,9 +2325,19 @@ __global__ __launch_bounds__(256) void k_max_resid(int nsub, const double* __res
     }
 }
 
-// A refinement of the particular solutions that did not converge.
-__global__ void k_ir_notconv(const int* __restrict__ st, int* __restrict__ flags) {
-    if (!st[0]) flags[FLAG_NOTCONV] = 1;
+// Particular solutions whose refinement did not reach tol (only when the
+// refinement as a whole did not converge): their subdomains are solved
+// again in FP64 by the solve (pfb = 1, counted); subdomains already in FP64
+// are skipped.
+__global__ void k_mark_part_fallback(int nsub, const double* __restrict__ resid, double tol,
+                                     const int* __restrict__ fb, int* __restrict__ pfb,
+                                     int* __restrict__ flags, const int* __restrict__ conv) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (*conv || s >= nsub || fb[s] == 1) return;
+    if (!(resid[s] <= tol)) {
+        pfb[s] = 1;
+        atomicAdd(&flags[FLAG_PFALLBACK], 1);
+    }
 }
 
 // ---------------------------------------------------------------- K1p
@@ -2612,7 +2641,7 @@ static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do
         const int nsub = c->geo.mx * c->geo.my;
         hipLaunchKernelGGL((k_local_setup_mfma<BX, S>), dim3(nsub), dim3(128), lds, c->stream, c->geo,
                            c->K, c->bct, c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask,
-                           want, do_traces, basis);
+                           want, do_traces, basis, std::is_same<S, float>::value ? c->fb : nullptr);
         return hipGetLastError();
     }
     const Level& L = c->levels[c->D];
@@ -2625,7 +2654,7 @@ static hipError_t setup_bx(rmrcm_ctx* c, S* P, const int* mask, int want, int do
     const int nsub = c->geo.mx * c->geo.my;
     hipLaunchKernelGGL((k_local_setup<BX, S>), dim3(nsub), dim3(64), lds, c->stream, c->geo, c->K,
                        c->bct, c->beta, L.slotseg, R, P, c->Psi, L.T, L.ld, c->flags, mask, want,
-                       do_traces, basis);
+                       do_traces, basis, std::is_same<S, float>::value ? c->fb : nullptr);
     return hipGetLastError();
 }
 
@@ -2982,8 +3011,10 @@ hipError_t launch_max_resid(rmrcm_ctx* c, int part) {
     return hipGetLastError();
 }
 
-hipError_t launch_ir_notconv(rmrcm_ctx* c) {
-    hipLaunchKernelGGL(k_ir_notconv, dim3(1), dim3(1), 0, c->stream, (const int*)(c->irst + 2), c->flags);
+hipError_t launch_mark_part_fallback(rmrcm_ctx* c) {
+    const int nsub = c->geo.mx * c->geo.my;
+    hipLaunchKernelGGL(k_mark_part_fallback, dim3((nsub + 255) / 256), dim3(256), 0, c->stream, nsub, c->resid,
+                       c->prm.ir_tol, (const int*)c->fb, c->pfb, c->flags, (const int*)(c->irst + 2));
     return hipGetLastError();
 }
 

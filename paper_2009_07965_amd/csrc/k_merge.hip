@@ -49,7 +49,15 @@ struct MergeArgs {
     double* work;               // scratch of merges with g > 128 (see kBigWork)
     const unsigned char* tflag; // [nnodes][ntiles]: 64-slot tiles holding an active slot
     int ntiles;                 // (the particular column nslot counts as active)
+    const int* run;             // null, or a device flag: the kernel does nothing while it is 0
 };
+
+// The launch does nothing when its run flag is given and 0 (the interface
+// refinement's chain, skipped on the device when it is not needed).
+#define RMRCM_RUN_GUARD(flag)            \
+    do {                                 \
+        if ((flag) && !*(flag)) return;  \
+    } while (0)
 
 // Element-wise copy t -> st(t, ld(t)) for t < n over the workgroup, in
 // batches of B elements per thread whose loads are all issued before any
@@ -330,6 +338,7 @@ __device__ inline void qd_panel_put(double* pn, const double (&r)[4]) {
 // 2: S^{-1} from S in Sg (the products in between by k_qd_es_mfma).
 template <int GT>
 __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_factor_mfma(MergeArgs a, int phase) {
+    RMRCM_RUN_GUARD(a.run);
     typedef QdM<GT> Q;
     constexpr int T = Q::T, CPL = Q::CPL;
     // up to 64 segments the products between the inversions take D^{-1} and
@@ -550,6 +559,7 @@ __device__ __forceinline__ void qd_load_tile(int g, const double* __restrict__ A
 
 template <int GT>
 __global__ __launch_bounds__(QdM<GT>::NT) void k_qd_es_mfma(MergeArgs a) {
+    RMRCM_RUN_GUARD(a.run);
     constexpr int T = QdM<GT>::T;
     __shared__ double Es[GT * 17];
     const int tid = threadIdx.x, lane = tid & 63, r = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -664,6 +674,7 @@ __device__ __forceinline__ void qd_prod_mfma(const double (&av)[GT / 4], const d
 template <int GT, int NCT>
 __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(MergeArgs a, int col0,
                                                                              int ncol) {
+    RMRCM_RUN_GUARD(a.run);
     constexpr int CT = 16 * NCT, AL = CT + 1, NT = 64 * qd_apply_waves<GT>();
     __shared__ double rs[GT * AL], rd[GT * AL], tt[GT * AL];
     const int node = blockIdx.x, g = a.g;
@@ -749,6 +760,7 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
 // products run.
 template <int GT>
 __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int ncol) {
+    RMRCM_RUN_GUARD(a.run);
     constexpr int CT = 16, AL = CT + 1, NT = 512, NW = NT / 64, KS = GT / 4;
     __shared__ double rs[GT * AL], rd[GT * AL], tt[GT * AL];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -928,6 +940,7 @@ __device__ __forceinline__ double qd_vec_dot(const double (&r)[GT / 8], const do
 // datum of each row's side of its segment.
 template <int GT>
 __global__ __launch_bounds__(8 * GT) void k_qd_apply_vec(MergeArgs a, int col, double* glo, double* ghi) {
+    RMRCM_RUN_GUARD(a.run);
     __shared__ double rs[GT], rd[GT], tt[GT], uu[GT];
     const int node = blockIdx.x, g = a.g;
     const int tid = threadIdx.x, i = tid >> 3, c8 = tid & 7;
@@ -990,6 +1003,7 @@ __global__ __launch_bounds__(8 * GT) void k_qd_apply_vec(MergeArgs a, int col, d
 // a workgroup forms the 16 x 16 tile of rows 16 (4 y + w).., columns 16 z..
 template <int GT>
 __global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, int ncol) {
+    RMRCM_RUN_GUARD(a.run);
     constexpr int KS = GT / 4;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
     const int node = blockIdx.x, g = a.g;
@@ -1068,6 +1082,7 @@ __host__ __device__ inline size_t small_lds_bytes(int ncol, int nslot) {
 }
 
 __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
+    RMRCM_RUN_GUARD(a.run);
     extern __shared__ double sm[];
     const int CW = small_cw(ncol), NS16 = small_ns16(a.nslot), CT = (ncol + 15) / 16, NRT = NS16 / 16;
     double* rs = sm;                 // [16][CW]  r1 + r2
@@ -1316,9 +1331,11 @@ struct DownArgs {
     const int* gmap;
     double* glo;
     double* ghi;
+    const int* run;
 };
 
 __global__ __launch_bounds__(256) void k_down(DownArgs a) {
+    RMRCM_RUN_GUARD(a.run);
     extern __shared__ double dvec[];   // nslot + 1
     constexpr int EMAX = 12;           // X row entries per lane held in registers
     const int node = blockIdx.x;
@@ -1388,9 +1405,11 @@ struct GemmArgs {
     double* C;
     long long ldc, sc;
     double alpha, beta;
+    const int* run;
 };
 
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
+    RMRCM_RUN_GUARD(g.run);
     __shared__ double As[64 * 17];
     __shared__ double Bs[16 * 65];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -1466,11 +1485,13 @@ struct GemmNN {
     const unsigned char* cflag;   // [batch][cfs] or null
     int rfs, cfs;
     int skr0, skr1;               // row tiles [skr0, skr1) skipped in every batch entry
+    const int* run;
 };
 
 constexpr int kGemmKT = 32;
 
 __global__ __launch_bounds__(256) void k_gemm_nn_f64(GemmNN g) {
+    RMRCM_RUN_GUARD(g.run);
     __shared__ double As[64 * (kGemmKT + 1)];
     __shared__ double Bs[kGemmKT * 65];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -1552,11 +1573,12 @@ static hipError_t gemm(rmrcm_ctx* c, int batch, int m, int n, int k, int ta, con
                        const unsigned char* cflag = nullptr, int cfs = 0, int skr0 = 0, int skr1 = 0) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (!ta && !tb) {
-        GemmNN g{m, n, k, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta, rflag, cflag, rfs, cfs, skr0, skr1};
+        GemmNN g{m, n, k, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta, rflag, cflag, rfs, cfs, skr0, skr1,
+                 c->run_ptr};
         hipLaunchKernelGGL(k_gemm_nn_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
         return hipGetLastError();
     }
-    GemmArgs g{m, n, k, ta, tb, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta};
+    GemmArgs g{m, n, k, ta, tb, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta, c->run_ptr};
     hipLaunchKernelGGL(k_gemm_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
     return hipGetLastError();
 }
@@ -1599,6 +1621,7 @@ __global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long
 // D, B and N of every merge of the level (one thread per entry; D to the D
 // block, N parked in the S block).
 __global__ __launch_bounds__(256) void k_qd_gather_big(MergeArgs a) {
+    RMRCM_RUN_GUARD(a.run);
     const int node = blockIdx.y, g = a.g;
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= g * g) return;
@@ -1757,10 +1780,89 @@ static hipError_t qd_factor_big(rmrcm_ctx* c, const MergeArgs& a) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// General interface spaces: U_H constant on segments of mu pieces and P_H on
+// segments of mp pieces (one of the two counts is 1; the gamma pieces of a
+// segment are consecutive, the first at a multiple of the count).  The
+// merge system of the pieces in the variables (P, V) (V = beta U, sum and
+// difference of the one-sided data) is
+//     [N B; B D] (P; V) = -(r1 + r2; r2 - r1)
+// and the general spaces restrict it to P = F Ph, V = E Vh (E, F: 0/1
+// expansions from segments to pieces) with the equations summed over the
+// same segments (eq. 13.2 tested on P-segments, eq. 14.2 on U-segments):
+//     [F^T N F  F^T B E; E^T B F  E^T D E] (Ph; Vh) = -(F^T (r1 + r2); E^T (r2 - r1)).
+// Its elimination (Dh = E^T D E, Sh = F^T (N - B E Dh^-1 E^T B) F) gives
+//     P = F Sh^-1 F^T (rs - B t),   t = E Dh^-1 E^T rd,   V = t - (E Dh^-1 E^T B) P,
+// the column formulas of the pieces' merge with D^-1 -> E Dh^-1 E^T and
+// S^-1 -> F Sh^-1 F^T; stored so expanded, the column kernels of every tier
+// apply the general merge unchanged.  Dh is definite (D is) and Sh is the
+// Schur complement of the restricted quasi-definite system.
+__global__ __launch_bounds__(256) void k_gs_restrict(const double* __restrict__ X, long long sx, int g, int m,
+                                                     double* __restrict__ Y, long long sy) {
+    const int n = g / m;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)n * n) return;
+    const int a = (int)(t / n), b = (int)(t % n);
+    const double* Xb = X + (size_t)blockIdx.y * sx;
+    double v = 0.0;
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) v += Xb[(size_t)(a * m + i) * g + b * m + j];
+    Y[(size_t)blockIdx.y * sy + t] = v;
+}
+
+__global__ __launch_bounds__(256) void k_gs_expand(const double* __restrict__ Y, long long sy, int g, int m,
+                                                   double* __restrict__ X, long long sx) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)g * g) return;
+    const int i = (int)(t / g), j = (int)(t % g), n = g / m;
+    X[(size_t)blockIdx.y * sx + t] = Y[(size_t)blockIdx.y * sy + (size_t)(i / m) * n + j / m];
+}
+
+static bool general_spaces(const rmrcm_ctx* c) { return c->geo.mu > 1 || c->geo.mp > 1; }
+
+// Factor of a general-spaces merge: the blocks of the pieces (as for the
+// long interfaces), Dh and Sh restricted, inverted and expanded into the
+// D^-1, E and S^-1 slots.  Scratch: big_work per merge (the inverses' and
+// the apply's), then the restricted block of every merge (g^2 each).
+static hipError_t gs_factor(rmrcm_ctx* c, const MergeArgs& a) {
+    const int g = a.g, nb = a.nnodes, mu = c->geo.mu, mp = c->geo.mp;
+    const int gu = g / mu, gp = g / mp;
+    const long long gg = (long long)g * g, sx = 4 * gg, sw = (long long)big_work(g, a.nslot);
+    double* D = a.M;
+    double* E = a.M + gg;
+    double* S = a.M + 2 * gg;
+    double* B = a.M + 3 * gg;
+    double* H = a.work + (size_t)nb * big_work(g, a.nslot);
+    const long long sh = gg;
+    const dim3 full((unsigned)((gg + 255) / 256), nb);
+    hipLaunchKernelGGL(k_qd_gather_big, full, dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_gs_restrict, dim3((unsigned)(((long long)gu * gu + 255) / 256), nb), dim3(256), 0,
+                       c->stream, (const double*)D, sx, g, mu, H, sh);
+    hipError_t e;
+    if ((e = qd_big_inverse(c, a, H, gu, gu, sh, a.work, sw))) return e;
+    hipLaunchKernelGGL(k_gs_expand, full, dim3(256), 0, c->stream, (const double*)H, sh, g, mu, D, sx);
+    // E = (E Dh^-1 E^T) B;  S = N - B E
+    if ((e = gemm(c, nb, g, g, g, 0, D, g, sx, 0, B, g, sx, E, g, sx, 1.0, 0.0))) return e;
+    if ((e = gemm(c, nb, g, g, g, 0, B, g, sx, 0, E, g, sx, S, g, sx, -1.0, 1.0))) return e;
+    hipLaunchKernelGGL(k_gs_restrict, dim3((unsigned)(((long long)gp * gp + 255) / 256), nb), dim3(256), 0,
+                       c->stream, (const double*)S, sx, g, mp, H, sh);
+    // all-Neumann top: the last P-segment's pressure pinned
+    if (a.pin)
+        hipLaunchKernelGGL(k_qd_big_fix, dim3((gp + 255) / 256, nb), dim3(256), 0, c->stream, H, (long long)gp, sh,
+                           (const double*)nullptr, 0LL, 0, 1, gp);
+    if ((e = qd_big_inverse(c, a, H, gp, gp, sh, a.work, sw))) return e;
+    if (a.pin)
+        hipLaunchKernelGGL(k_qd_big_fix, dim3(1, nb), dim3(256), 0, c->stream, H, (long long)gp, sh,
+                           (const double*)nullptr, 0LL, 0, 2, gp);
+    hipLaunchKernelGGL(k_gs_expand, full, dim3(256), 0, c->stream, (const double*)H, sh, g, mp, S, sx);
+    return hipGetLastError();
+}
+
 // r1 + r2 and r2 - r1 of columns [col0, col0 + ncol) (row stride ncol), and
 // the coefficients X from s and d.
 __global__ __launch_bounds__(256) void k_qd_rhs_big(MergeArgs a, int col0, int ncol, double* RS,
                                                     double* RD, long long sw) {
+    RMRCM_RUN_GUARD(a.run);
     const int node = blockIdx.y, g = a.g;
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= g * ncol) return;
@@ -1784,6 +1886,7 @@ __global__ __launch_bounds__(256) void k_qd_rhs_big(MergeArgs a, int col0, int n
 
 __global__ __launch_bounds__(256) void k_qd_x_big(MergeArgs a, int col0, int ncol, const double* Sv,
                                                   const double* Dv, long long sw) {
+    RMRCM_RUN_GUARD(a.run);
     const int node = blockIdx.y, g = a.g;
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= g * ncol) return;
@@ -1799,6 +1902,7 @@ __global__ __launch_bounds__(256) void k_qd_x_big(MergeArgs a, int col0, int nco
 // for the child k that owns slot o (zero in the other child's half), the
 // terms and their sum being those of k_qd_trace_mfma.
 __global__ __launch_bounds__(256) void k_qd_trace_rows_big(MergeArgs a, double* Ar, long long sw) {
+    RMRCM_RUN_GUARD(a.run);
     const int node = blockIdx.y, g = a.g;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long long)a.nslot * 2 * g) return;
@@ -1815,6 +1919,7 @@ __global__ __launch_bounds__(256) void k_qd_trace_rows_big(MergeArgs a, double* 
 }
 
 __global__ __launch_bounds__(256) void k_qd_trace_direct_big(MergeArgs a, int col0, int ncol) {
+    RMRCM_RUN_GUARD(a.run);
     const int node = blockIdx.y;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= (long long)a.nslot * ncol) return;
@@ -1888,6 +1993,7 @@ struct DownSubArgs {
     const int* tab;     // [subtrees][entries]
     double* glo;
     double* ghi;
+    const int* run;
 };
 
 // The downward pass of n consecutive depths with short interfaces for the
@@ -1908,6 +2014,7 @@ static constexpr int kDownSubThreads = 512;
 static constexpr int kDownSubEntries = 12;   // X row entries per lane and depth held in registers
 
 __global__ __launch_bounds__(kDownSubThreads) void k_down_sub(DownSubArgs A) {
+    RMRCM_RUN_GUARD(A.run);
     extern __shared__ double sm[];
     constexpr int EMAX = kDownSubEntries;
     double* dall = sm;                 // [entries] data vectors of every depth
@@ -2028,6 +2135,7 @@ static MergeArgs make_args(rmrcm_ctx* c, int d) {
     a.work = P.work;
     a.tflag = P.tflag;
     a.ntiles = (P.nslot + 1 + 63) / 64;
+    a.run = c->run_ptr;
     return a;
 }
 
@@ -2122,11 +2230,15 @@ static hipError_t qd_columns_any(rmrcm_ctx* c, const MergeArgs& a, int col0, int
     return hipErrorInvalidValue;
 }
 
-size_t merge_work_doubles(const Level& L) { return L.g >= 128 ? big_work(L.g, L.nslot) : 0; }
+size_t merge_work_doubles(const rmrcm_ctx* c, const Level& L) {
+    if (general_spaces(c)) return (size_t)L.nnodes * (big_work(L.g, L.nslot) + (size_t)L.g * L.g);
+    return L.g >= 128 ? (size_t)L.nnodes * big_work(L.g, L.nslot) : 0;
+}
 
 bool merge_apply_tunable(rmrcm_ctx* c, int d) {
     if (!(d > 0 && d < c->D)) return false;
     const MergeArgs a = make_args(c, d);
+    if (general_spaces(c)) return false;
     if (small_merge_ok(a, d, a.nslot) || small_merge_ok(a, d, a.nslot + 1)) return false;   // fused merge
     if (cols_fused(a, true)) return false;                                                    // fused columns
     return qd_tier(a.g) < 128;
@@ -2148,6 +2260,11 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d, bool part) {
     MergeArgs a = make_args(c, d);
     if (d == 0) a.Tp = nullptr;
     const int ncol = a.nslot + (part ? 1 : 0);
+    if (general_spaces(c)) {
+        hipError_t e = gs_factor(c, a);
+        if (e != hipSuccess || d == 0) return e;
+        return qd_columns_any(c, a, 0, ncol, true, c->ct_tune[d]);
+    }
     if (small_merge_ok(a, d, ncol)) {
         hipLaunchKernelGGL(k_qd_small, dim3(a.nnodes), dim3(64 * small_waves(ncol)), small_lds_bytes(ncol, a.nslot),
                            c->stream, a, ncol);
@@ -2193,6 +2310,7 @@ hipError_t launch_down(rmrcm_ctx* c, int d) {
     a.gmap = P.gmap;
     a.glo = c->glo;
     a.ghi = c->ghi;
+    a.run = c->run_ptr;
     const size_t lds = sizeof(double) * (size_t)(P.nslot + 1);
     hipLaunchKernelGGL(k_down, dim3(P.nnodes, (P.xi + 3) / 4), dim3(256), lds, c->stream, a);
     return hipGetLastError();
@@ -2329,6 +2447,7 @@ hipError_t launch_down_all(rmrcm_ctx* c) {
     A.tab = c->down_tab;
     A.glo = c->glo;
     A.ghi = c->ghi;
+    A.run = c->run_ptr;
     for (int l = 0; l < A.n; ++l) {
         const Level& P = c->levels[ds + l];
         DownLevel& a = A.lv[l];

@@ -28,7 +28,9 @@ __global__ __launch_bounds__(1024) void k_reconstruct(Geo g, const double* __res
                                                      const double* __restrict__ glo,
                                                      const double* __restrict__ ghi,
                                                      double* __restrict__ p_out,
-                                                     double* __restrict__ f_out) {
+                                                     double* __restrict__ f_out,
+                                                     const int* __restrict__ run) {
+    if (run && !*run) return;
     extern __shared__ double sm[];
     double* gs = sm;            // R
     double* ps = gs + R;        // BX * BY
@@ -110,7 +112,9 @@ __global__ void k_interface_values(int nseg, const double* __restrict__ glo,
 constexpr int kGB = 256;      // blocks of the gauge reduction
 
 __global__ __launch_bounds__(256) void k_pressure_partial(const double* __restrict__ p, size_t n,
-                                                          double* __restrict__ part) {
+                                                          double* __restrict__ part,
+                                                          const int* __restrict__ run) {
+    if (run && !*run) return;
     __shared__ double s[256];
     double acc = 0.0;
     const size_t chunk = (n + gridDim.x - 1) / gridDim.x;
@@ -128,7 +132,9 @@ __global__ __launch_bounds__(256) void k_pressure_partial(const double* __restri
 __global__ __launch_bounds__(256) void k_pressure_shift(double* __restrict__ p, size_t n,
                                                         const double* __restrict__ part, int nb,
                                                         double* __restrict__ glo,
-                                                        double* __restrict__ ghi, int nseg) {
+                                                        double* __restrict__ ghi, int nseg,
+                                                        const int* __restrict__ run) {
+    if (run && !*run) return;
     __shared__ double mean;
     if (threadIdx.x == 0) {
         double s = 0.0;
@@ -182,6 +188,192 @@ __global__ __launch_bounds__(1024) void k_compat(const double* __restrict__ q, s
     if (threadIdx.x == 0) flags[FLAG_BAD_DATA] = (fabs(s1[0]) <= 1e-12 * s2[0] + 1e-300) ? 0 : 1;
 }
 
+// ---------------------------------------------------------------- interface refinement
+// The recursive elimination applies explicit inverses of the gamma blocks;
+// when a block is ill conditioned (large Robin parameters: the paper's
+// accuracy runs take alpha = 1e6) the interface data it gives satisfy the
+// interface conditions eq. 13.2 and 14.2 only to a few digits.  One step of
+// iterative refinement of the whole interface system restores them: the
+// residuals of the two conditions at every segment are computed from the
+// cells' one-sided fluxes and the Robin data, split into one flux offset
+// per side of the segment, and taken through the same recursion as the
+// particular column of a solve (leaf particular traces = the offsets,
+// particular solutions zero); its Robin data are the correction.  The
+// residual of segment e between the low side (flux F_lo out of it, datum
+// g_lo) and the high side:
+//     r13 = F_lo + F_hi,   r14 = F_lo - F_hi - |e| (g_hi - g_lo) / beta_e
+// (eq. 14.2 divided by beta_e, with U = (g_hi - g_lo) / (2 beta_e)); the
+// equations of a merge read F_lo + W (g_lo - g_hi) = 0 and
+// F_hi + W (g_hi - g_lo) = 0 with W = |e| / (2 beta_e), whose residuals
+// are (r13 + r14) / 2 on the low side and (r13 - r14) / 2 on the high side.
+// Each residual is measured in pressure units, divided by the sum of its
+// segment's Robin face conductances |f| / (rho_f + beta_e) (the one-sided
+// fluxes are those conductances times pressure differences); the step runs
+// (flag set by k_iface_decide) when the largest of them exceeds tol times
+// the pressure scale, the largest |p| of a cell next to the skeleton or
+// |g| of a Robin datum.  Both maxima are non-negative doubles, whose bit
+// patterns order as unsigned integers: one atomic maximum per wavefront.
+__device__ inline void wave_max_u64(unsigned long long* dst, double v) {
+    unsigned long long b = __double_as_longlong(v);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long t = __shfl_xor(b, o);
+        b = t > b ? t : b;
+    }
+    if ((threadIdx.x & 63) == 0 && b) atomicMax(dst, b);
+}
+
+// One segment's one-sided flux sums, Robin conductance sum and largest
+// |p| of its cells.
+__device__ inline void iface_terms(const Geo& g, const double* __restrict__ K, const double* __restrict__ p,
+                                   const double* __restrict__ f, double be, int e, double* flo, double* fhi,
+                                   double* sc, double* mag) {
+    const size_t plane = (size_t)g.nx * g.ny;
+    for (int t = 0; t < g.sg; ++t) {
+        size_t olo, ohi;
+        double area, rlo, rhi;
+        int slo, shi;
+        if (e < g.nv) {
+            const int I = e / g.lines_v + 1, j = (e % g.lines_v) * g.sg + t;
+            olo = (size_t)j * g.nx + I * g.bx - 1;
+            ohi = olo + 1;
+            area = g.hy;
+            rlo = g.hx / (2.0 * K[olo]);
+            rhi = g.hx / (2.0 * K[ohi]);
+            slo = 1;
+            shi = 0;
+        } else {
+            const int r = e - g.nv, J = r / g.lines_h + 1, i = (r % g.lines_h) * g.sg + t;
+            olo = (size_t)(J * g.by - 1) * g.nx + i;
+            ohi = olo + g.nx;
+            area = g.hx;
+            rlo = g.hy / (2.0 * K[olo]);
+            rhi = g.hy / (2.0 * K[ohi]);
+            slo = 3;
+            shi = 2;
+        }
+        *flo += f[slo * plane + olo];
+        *fhi += f[shi * plane + ohi];
+        *sc += area / (rlo + be) + area / (rhi + be);
+        *mag = fmax(*mag, fmax(fabs(p[olo]), fabs(p[ohi])));
+    }
+}
+
+// Per segment (piece, with general interface spaces): its two residuals
+// for the refinement's leaf traces.  The test uses the residuals of the
+// equations the method imposes: eq. 13.2 summed over each P-segment and
+// eq. 14.2 over each U-segment (one piece each with the MuMM spaces), by
+// the first piece of each.
+__global__ __launch_bounds__(256) void k_iface_resid(Geo g, const double* __restrict__ K,
+                                                     const double* __restrict__ p,
+                                                     const double* __restrict__ f,
+                                                     const double* __restrict__ glo,
+                                                     const double* __restrict__ ghi,
+                                                     const double* __restrict__ beta,
+                                                     const double* __restrict__ seglen,
+                                                     double* __restrict__ res,
+                                                     unsigned long long* __restrict__ mx,
+                                                     const int* __restrict__ run) {
+    if (run && !*run) return;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    double ratio = 0.0, mag = 0.0;
+    if (e < g.nseg) {
+        const int k = e < g.nv ? e % g.lines_v : (e - g.nv) % g.lines_h;
+        double flo = 0.0, fhi = 0.0, sc = 0.0;
+        iface_terms(g, K, p, f, beta[e], e, &flo, &fhi, &sc, &mag);
+        const double gl = glo[e], gh = ghi[e];
+        mag = fmax(mag, fmax(fabs(gl), fabs(gh)));
+        res[e] = flo + fhi;
+        res[g.nseg + e] = flo - fhi - seglen[e] * (gh - gl) / beta[e];
+        if (g.mp == 1) ratio = fabs(res[e]) / sc;
+        if (g.mu == 1) ratio = fmax(ratio, fabs(res[g.nseg + e]) / sc);
+        if (g.mp > 1 && k % g.mp == 0) {        // eq. 13.2 on the P-segment starting here
+            double a = 0.0, b = 0.0, s = 0.0, m = 0.0;
+            for (int q = 0; q < g.mp; ++q) iface_terms(g, K, p, f, beta[e + q], e + q, &a, &b, &s, &m);
+            ratio = fmax(ratio, fabs(a + b) / s);
+        }
+        if (g.mu > 1 && k % g.mu == 0) {        // eq. 14.2 on the U-segment starting here
+            double a = 0.0, b = 0.0, s = 0.0, m = 0.0, u = 0.0;
+            for (int q = 0; q < g.mu; ++q) {
+                iface_terms(g, K, p, f, beta[e + q], e + q, &a, &b, &s, &m);
+                u += seglen[e + q] * (ghi[e + q] - glo[e + q]) / beta[e + q];
+            }
+            ratio = fmax(ratio, fabs(a - b - u) / s);
+        }
+    }
+    wave_max_u64(mx, ratio);
+    wave_max_u64(mx + 1, mag);
+}
+
+__global__ void k_iface_decide(const double* __restrict__ mx, double tol, int* __restrict__ flag) {
+    if (threadIdx.x == 0) *flag = !(mx[0] <= tol * mx[1]);   // NaN residuals refine too
+}
+
+// Leaf particular traces of the refinement: the residual share of each
+// active slot's side of its segment; the Robin data saved (the recursion's
+// downward pass overwrites them with the correction).
+__global__ __launch_bounds__(256) void k_iface_inject(int nsub, int R, const int* __restrict__ slotseg,
+                                                      const double* __restrict__ res, int nseg,
+                                                      double* __restrict__ T, int ld,
+                                                      const double* __restrict__ glo,
+                                                      const double* __restrict__ ghi,
+                                                      double* __restrict__ gsave,
+                                                      const int* __restrict__ flag) {
+    if (!*flag) return;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < (size_t)nseg) {
+        gsave[t] = glo[t];
+        gsave[nseg + t] = ghi[t];
+    }
+    if (t >= (size_t)nsub * R) return;
+    const int code = slotseg[t];
+    double v = 0.0;
+    if (code >= 0) {
+        const int e = code >> 1;
+        v = (code & 1) ? 0.5 * (res[e] + res[nseg + e]) : 0.5 * (res[e] - res[nseg + e]);
+    }
+    T[t * ld + ld - 1] = v;
+}
+
+// Corrected Robin data: saved data + correction.
+__global__ __launch_bounds__(256) void k_iface_apply(int nseg, double* __restrict__ glo,
+                                                     double* __restrict__ ghi,
+                                                     const double* __restrict__ gsave,
+                                                     const int* __restrict__ flag) {
+    if (!*flag) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nseg) return;
+    glo[t] += gsave[t];
+    ghi[t] += gsave[nseg + t];
+}
+
+hipError_t launch_iface_resid(rmrcm_ctx* c, double tol, double* mx, int* flag, const int* run) {
+    const Geo& g = c->geo;
+    if (g.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iface_resid, dim3((g.nseg + 255) / 256), dim3(256), 0, c->stream, g, c->K, c->pout,
+                       c->fout, c->glo, c->ghi, c->beta, c->seglen, c->iref_res,
+                       reinterpret_cast<unsigned long long*>(mx), run);
+    hipLaunchKernelGGL(k_iface_decide, dim3(1), dim3(64), 0, c->stream, (const double*)mx, tol, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_iface_inject(rmrcm_ctx* c) {
+    const Level& L = c->levels[c->D];
+    const size_t nsub = (size_t)c->geo.mx * c->geo.my;
+    const size_t n = nsub * L.nslot > (size_t)c->geo.nseg ? nsub * L.nslot : (size_t)c->geo.nseg;
+    hipLaunchKernelGGL(k_iface_inject, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, (int)nsub,
+                       L.nslot, L.slotseg, c->iref_res, c->geo.nseg, L.T, L.ld, c->glo, c->ghi, c->iref_save,
+                       c->run_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_iface_apply(rmrcm_ctx* c) {
+    if (c->geo.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iface_apply, dim3((c->geo.nseg + 255) / 256), dim3(256), 0, c->stream, c->geo.nseg,
+                       c->glo, c->ghi, c->iref_save, c->run_ptr);
+    return hipGetLastError();
+}
+
 static unsigned fill_blocks(size_t n) {
     const size_t b = (n + 255) / 256;
     return (unsigned)(b < 1 ? 1 : b > 4096 ? 4096 : b);
@@ -206,9 +398,10 @@ hipError_t launch_compat_check(rmrcm_ctx* c) {
 
 hipError_t launch_gauge(rmrcm_ctx* c) {
     const size_t n = (size_t)c->geo.nx * c->geo.ny;
-    hipLaunchKernelGGL(k_pressure_partial, dim3(kGB), dim3(256), 0, c->stream, c->pout, n, c->gauge);
+    hipLaunchKernelGGL(k_pressure_partial, dim3(kGB), dim3(256), 0, c->stream, c->pout, n, c->gauge,
+                       c->run_ptr);
     hipLaunchKernelGGL(k_pressure_shift, dim3(1024), dim3(256), 0, c->stream, c->pout, n, c->gauge, kGB,
-                       c->glo, c->ghi, c->geo.nseg);
+                       c->glo, c->ghi, c->geo.nseg, c->run_ptr);
     return hipGetLastError();
 }
 
@@ -223,7 +416,7 @@ static hipError_t recon_bx(rmrcm_ctx* c) {
     const int nt = BX * c->geo.by < 1024 ? ((BX * c->geo.by + 63) / 64) * 64 : 1024;
     hipLaunchKernelGGL(k_reconstruct<BX>, dim3(nsub), dim3(nt), lds, c->stream, c->geo, c->K,
                        c->bct, c->bcv, c->beta, L.slotseg, L.nslot, c->Psi, c->pbar, c->glo,
-                       c->ghi, c->pout, c->fout);
+                       c->ghi, c->pout, c->fout, c->run_ptr);
     return hipGetLastError();
 }
 

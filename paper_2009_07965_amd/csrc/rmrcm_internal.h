@@ -31,6 +31,9 @@ struct Geo {
     // (0, 0) with no datum, which fixes the constant of its Neumann problem
     int neumann = 0;
     const int* pin = nullptr;
+    // general interface spaces: pieces (segments above) per U-segment and
+    // per P-segment (1 and 1: the MuMM spaces)
+    int mu = 1, mp = 1;
 };
 
 // Slot -> segment code: (segment id << 1) | low_side, or -1 if the slot lies
@@ -59,7 +62,7 @@ struct Level {
     int* gseg = nullptr;       // [nnodes][g] global segment of every gamma segment
     double* M = nullptr;       // [nnodes][4 g^2]: D^{-1}, E, S^{-1}, B of the merge
     double* X = nullptr;       // [nnodes][xi][ld] coefficients of every column
-    double* work = nullptr;    // scratch of merges with g > 128 (merge_work_doubles per node)
+    double* work = nullptr;    // scratch of the merges (merge_work_doubles)
     unsigned char* tflag = nullptr;   // [nnodes][(nslot + 64) / 64] 64-slot tiles with an active
                                       // slot (or the particular column)
     std::vector<int> h_pmap, h_gmap, h_slotseg, h_gseg;
@@ -103,6 +106,8 @@ struct rmrcm_ctx {
     float* Wsc = nullptr;                    // mixed mode: sweep scratch [nsub][nslot][bx*by]
     double* resid = nullptr;                 // mixed mode: relative residual per subdomain
     int* fb = nullptr;                       // mixed mode: 1 = subdomain redone in FP64
+    int* pfb = nullptr;                      // mixed mode: 1 = particular solution of the
+                                             // last solve redone in FP64
     double* dscal = nullptr;                 // device scalar
     int* irst = nullptr;                     // mixed mode: {converged, passes} of setup, solve
     double* irhist = nullptr;                // mixed mode: [2][kIrHist] residual per pass
@@ -129,7 +134,7 @@ struct rmrcm_ctx {
     // allocates nothing (rmrcm_plan_bytes).
     bool counting = false;
     // timing
-    hipEvent_t ev[16] = {};
+    hipEvent_t ev[17] = {};
     // FP64 overlap of the particular chain with the setup merges: an
     // auxiliary stream, one event per merge level of the setup, the end of
     // the local setup, the inputs of a solve and the end of the aux work
@@ -140,6 +145,10 @@ struct rmrcm_ctx {
     bool solve_overlapped = false;  // the last solve ran the particular chain on aux
     double t_setup_ms[8] = {};
     double t_solve_ms[8] = {};
+    double iface_resid = 0.0;                // last interface residual / pressure scale
+    int iface_refined = 0;                   // 1 when the last solve ran the refinement step
+    double iface_resid_after = 0.0;          // residual / scale after the first step (when it ran)
+    int n_pfallback = 0;                     // particular solutions redone in FP64 (last solve)
     int64_t n_local_solves = 0;
     int ir_iters_setup = 0, ir_iters_solve = 0, n_fallback = 0;
     // learned mode: surrogate network, its inputs / outputs, accepted count
@@ -156,6 +165,14 @@ struct rmrcm_ctx {
     double* ds_pb = nullptr;
     int* ds_pin = nullptr;
     double* ds_stage = nullptr;              // [10][ny][nx]: p in, F in, p out, F out
+    // interface refinement: the segment residuals (r13, r14), the saved
+    // Robin data, the device flag that runs the refinement's chain, and
+    // the flag the kernels of a chain check (null outside that chain)
+    double* iref_res = nullptr;              // [2][nseg] + 4: largest residual, pressure scale
+                                             // before the step and after it
+    double* iref_save = nullptr;             // [2][nseg]
+    int* iref_flag = nullptr;
+    const int* run_ptr = nullptr;
     int n_accepted = 0;
     double ir_resid_setup = 0.0, ir_resid_solve = 0.0;
 };
@@ -186,12 +203,13 @@ hipError_t launch_trace_correct(rmrcm_ctx* c, int basis, int part);
 // the fallback marking runs only when the setup refinement did not converge.
 hipError_t launch_mark_fallback(rmrcm_ctx* c, double tol);
 hipError_t launch_max_resid(rmrcm_ctx* c, int part);
-hipError_t launch_ir_notconv(rmrcm_ctx* c);
+hipError_t launch_mark_part_fallback(rmrcm_ctx* c);
 // part: the particular column is eliminated with the basis columns (their
 // traces already hold it), as launch_merge_particular would below the top.
 hipError_t launch_merge_setup(rmrcm_ctx* c, int depth, bool part = false);
-// Scratch doubles per merge of a level (nonzero for 128 < g <= 256).
-size_t merge_work_doubles(const Level& L);
+// Scratch doubles of a level's merges, all nodes (nonzero for g >= 128,
+// and for every level with general interface spaces).
+size_t merge_work_doubles(const rmrcm_ctx* c, const Level& L);
 hipError_t launch_merge_particular(rmrcm_ctx* c, int depth);
 hipError_t launch_down(rmrcm_ctx* c, int depth);
 // The downward pass of every depth (the deep, short-interface depths in one launch).
@@ -200,6 +218,9 @@ hipError_t launch_down_all(rmrcm_ctx* c);
 // host (c->h_down_tab); RMRCM_* code.
 int build_down_sub(rmrcm_ctx* c);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
+hipError_t launch_iface_resid(rmrcm_ctx* c, double tol, double* mx, int* flag, const int* run);
+hipError_t launch_iface_inject(rmrcm_ctx* c);
+hipError_t launch_iface_apply(rmrcm_ctx* c);
 hipError_t launch_ds_source(rmrcm_ctx* c, const double* F, const double* q, double* qo);
 hipError_t launch_ds_compat(rmrcm_ctx* c, const int* pin, double* qo);
 hipError_t launch_ds_finish(rmrcm_ctx* c, const double* pb, const double* p_in, const double* F_in,
@@ -218,7 +239,7 @@ bool merge_apply_tunable(rmrcm_ctx* c, int depth);
 
 // Device error flag slots.
 enum { FLAG_LOCAL_SINGULAR = 0, FLAG_MERGE_SINGULAR = 1, FLAG_BAD_PERM = 2, FLAG_FALLBACK = 3,
-       FLAG_BAD_DATA = 4, FLAG_ACCEPTED = 5, FLAG_NOTCONV = 6, kNumFlags = 8 };
+       FLAG_BAD_DATA = 4, FLAG_ACCEPTED = 5, FLAG_NOTCONV = 6, FLAG_PFALLBACK = 7, kNumFlags = 8 };
 
 // Residual history entries per refinement (setup, solve) kept on the device.
 constexpr int kIrHist = 16;

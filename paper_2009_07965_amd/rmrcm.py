@@ -42,6 +42,7 @@ class rmrcm_params(ctypes.Structure):
         ("cnn_weights", ctypes.c_char_p),
         ("device", ctypes.c_int32),
         ("mem_cap", ctypes.c_uint64),
+        ("seg_u", ctypes.c_int32), ("seg_p", ctypes.c_int32),
     ]
 
 
@@ -496,6 +497,9 @@ class Solver:
 
     @classmethod
     def from_problem(cls, prob, **kw):
+        for k in ("seg_u", "seg_p"):
+            if getattr(prob, k, 0) and k not in kw:
+                kw[k] = getattr(prob, k)
         return cls(prob.nx, prob.ny, prob.K, prob.bc_type, prob.sub_nx, prob.sub_ny,
                    prob.seg, alpha=prob.alpha, lx=prob.lx, ly=prob.ly, **kw)
 

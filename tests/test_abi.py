@@ -85,7 +85,7 @@ def test_memory_plan_counts_the_large_arrays():
     particular solution), FP64; the traces and merge blocks of every level
     add less than as much again.  The mixed mode adds exactly its FP32
     factor store and sweep scratch and its per-subdomain residual, fallback
-    and refinement-history arrays."""
+    (setup and solve) and refinement-history arrays."""
     from paper_2009_07965_amd import rmrcm_plan_bytes
     for nx, b, seg in [(64, 16, 4), (1024, 32, 8), (8192, 32, 8), (2048, 16, 4)]:
         nsub = (nx // b) ** 2
@@ -94,7 +94,7 @@ def test_memory_plan_counts_the_large_arrays():
         low = 8 * nsub * (R * b * b + b * b * b) + 8 * 8 * nx * nx
         assert low < fp64 < 2 * low, (nx, fp64, low)
         mixed = rmrcm_plan_bytes(params(nx, b, seg, precision=1))
-        extra = 4 * nsub * b * b * b + 4 * nsub * R * b * b + 8 * nsub + 4 * nsub + 4 * 4 + 8 * 2 * 16
+        extra = 4 * nsub * b * b * b + 4 * nsub * R * b * b + 8 * nsub + 2 * 4 * nsub + 4 * 4 + 8 * 2 * 16
         assert mixed - fp64 == extra
 
 
@@ -127,3 +127,31 @@ def test_memory_cap_gives_enomem_before_device_work():
         with pytest.raises(RMRCMError) as ei:
             rmrcm_setup(p, K, t)
         assert ei.value.status == -3
+
+
+@pytest.mark.parametrize("bad", [
+    dict(seg_u=3), dict(seg_p=32), dict(seg_u=8, seg_p=12, sub_nx=24, sub_ny=24, nx=96, ny=96),
+    dict(seg_u=-4),
+])
+def test_general_spaces_rejected_by_validation(bad):
+    """General interface spaces: U- and P-segment lengths that do not
+    divide the subdomain, or that are not nested, are EINVAL (host
+    validation, through the memory plan, before any device work)."""
+    from paper_2009_07965_amd import rmrcm_plan_bytes, RMRCMError
+    with pytest.raises(RMRCMError) as ei:
+        rmrcm_plan_bytes(params(**bad))
+    assert ei.value.status in (-1, -7)
+
+
+def test_general_spaces_plan_and_noalloc():
+    """The plan of general spaces holds the merge scratch of every level
+    (more than the MuMM plan on the same pieces); the allocation-free step
+    rejects them with ENOTSUP before looking at its arrays."""
+    import ctypes
+    from paper_2009_07965_amd import rmrcm_plan_bytes, load_library
+    mumm = rmrcm_plan_bytes(params(256, 16, 4))
+    gen = rmrcm_plan_bytes(params(256, 16, 4, seg_u=8))
+    assert gen > mumm
+    lib = load_library()
+    p = params(256, 16, 4, seg_u=8)
+    assert lib.rmrcm_step_noalloc(ctypes.byref(p), None, None, None, None, None, None, None) == -7

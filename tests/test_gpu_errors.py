@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 from helpers import make_problem
+from oracle.metrics import rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -47,25 +48,34 @@ def test_cap_one_byte_short_is_enomem(L):
     S.close()
 
 
-def test_unreachable_tolerance_at_solve_is_enotconv(L):
+def test_unreachable_tolerance_at_solve_falls_back_to_fp64(L):
     """Setup with the default refinement (converges), then a tolerance no
-    refinement reaches with one pass: the solve's particular refinement
-    does not converge and the solve reports RMRCM_ENOTCONV; restoring the
-    defaults gives a normal solve again."""
+    refinement reaches with one pass: the particular solution of every
+    subdomain is solved again in FP64 (its subdomain factored in FP64 for
+    that solve), the solve succeeds and counts them, and its result is that
+    of the FP64 particular solutions; restoring the defaults gives the
+    first solve's result again, bit for bit."""
     prob = make_problem(128, b=16, seg=4, log_var=2.0, source=True)
-    print("[gpu-errors] ENOTCONV at solve", flush=True)
+    print("[gpu-errors] particular fallback at solve", flush=True)
     S = L.Solver.from_problem(prob, precision=1)
     try:
         p0, F0 = S.solve(prob.q, prob.bc_value)
+        assert S.stats()["fp64_particular_fallback_subdomains"] == 0
         L.rmrcm_set_refinement(S.ctx, 1e-300, 1)
-        with pytest.raises(L.RMRCMError) as ei:
-            S.solve(prob.q, prob.bc_value)
-        assert ei.value.status == -5
-        L.rmrcm_set_refinement(S.ctx, 1e-11, 6)
         p1, F1 = S.solve(prob.q, prob.bc_value)
-        assert np.array_equal(p0, p1) and np.array_equal(F0, F1)
+        assert S.stats()["fp64_particular_fallback_subdomains"] == 64
+        assert rel_l2(p1, p0) < 1e-9 and rel_l2(F1, F0) < 1e-9
+        L.rmrcm_set_refinement(S.ctx, 1e-11, 6)
+        p2, F2 = S.solve(prob.q, prob.bc_value)
+        assert np.array_equal(p0, p2) and np.array_equal(F0, F2)
     finally:
         S.close()
+    S = L.Solver.from_problem(prob)
+    try:
+        pr, Fr = S.solve(prob.q, prob.bc_value)
+    finally:
+        S.close()
+    assert rel_l2(p1, pr) < 1e-9 and rel_l2(F1, Fr) < 1e-9
 
 
 def test_set_refinement_rejects(L):
