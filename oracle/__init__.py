@@ -27,6 +27,10 @@ formulation and parallel implementation of multiscale mixed methods"):
                    every interface unknown in one dense system.
 * ``recursive``  — O-5: Algorithm 1 (recursive formulation, Section 3)
                    over the nested binary hierarchy.
+* ``three_d``    — O-6: the three-dimensional method of the paper's
+                   experiments (seven-point scheme, no z-division, Hbar_z =
+                   H_z): fine solve, local problems, non-recursive MRCM and
+                   a face-by-face brute force.
 * ``metrics``    — norms and conservation / interface-equation residuals.
 * ``cnn``        — the local-basis surrogate network (forward, loss,
                    gradients, input features) in FP64, for checking the GPU

@@ -7,9 +7,12 @@ take their inputs from it without sharing any of the computation.
 Everything is deterministic given a seed (NumPy PCG64 ``default_rng``).
 """
 
-from .fields import lognormal_grf, gaussian_field_exp, channelized  # noqa: F401
+from .fields import lognormal_grf, gaussian_field_exp, channelized, lognormal_grf3d  # noqa: F401
 from .problems import (  # noqa: F401
     Problem,
+    Problem3D,
+    bc_faces3d,
+    dirichlet_we3d,
     dirichlet_we,
     five_spot,
     config_problem,

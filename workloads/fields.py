@@ -84,3 +84,22 @@ def channelized(n: int, seed: int, n_channels: int = 24,
     span = np.log(k_channel / k_background)
     lk = lk + rng.standard_normal((n, n)) * (noise_frac * span)
     return np.exp(lk)
+
+
+def lognormal_grf3d(nx: int, ny: int, nz: int, lam: float, log_var: float, seed: int,
+                    lx: float = 1.0, ly: float = 1.0, lz: float = 1.0) -> np.ndarray:
+    """3D log-normal field (the paper's field type, Section 5): K =
+    exp(sqrt(log_var) xi) with xi the exponential-covariance GRF sampled by
+    circulant embedding on the doubled 3D torus (negative eigenvalues
+    clipped).  Shape (nz, ny, nx)."""
+    hx, hy, hz = lx / nx, ly / ny, lz / nz
+    m = (2 * nz, 2 * ny, 2 * nx)
+    d = [np.minimum(np.arange(k), k - np.arange(k)) * h for k, h in zip(m, (hz, hy, hx))]
+    r = np.sqrt(d[0][:, None, None] ** 2 + d[1][None, :, None] ** 2 + d[2][None, None, :] ** 2)
+    lam_eig = np.fft.fftn(np.exp(-r / lam)).real
+    lam_eig = np.where(lam_eig < 0, 0.0, lam_eig)
+    rng = np.random.default_rng(seed)
+    eps = rng.standard_normal(m) + 1j * rng.standard_normal(m)
+    w = np.fft.fftn(np.sqrt(lam_eig / lam_eig.size) * eps)
+    xi = np.ascontiguousarray(w.real[:nz, :ny, :nx])
+    return np.exp(np.sqrt(log_var) * xi)

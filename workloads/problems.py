@@ -133,3 +133,56 @@ def ensemble_member(m: int, n_override: Optional[int] = None) -> Problem:
     return Problem(nx=n, ny=n, K=K, q=q, bc_type=t, bc_value=v,
                    sub_nx=b, sub_ny=b, seg=max(b // 4, 1), alpha=1.0,
                    name="ens%d" % m, meta=dict(lam=lam, log_var=log_var, member=m))
+
+
+@dataclass
+class Problem3D:
+    """The 3D Darcy problem of the paper's experiments (Section 5) on
+    ``[0, lx] x [0, ly] x [0, lz]`` with an ``nx x ny x nz`` grid, split
+    into ``sub_nx x sub_ny`` columns of cells with no division in z
+    (Section 5.1: the finest decomposition has no z-division and
+    Hbar_z = H_z, so a skeleton segment is ``seg`` faces along the interface
+    by the full height).
+
+    Arrays are ``(nz, ny, nx)``.  Boundary data, one entry per boundary
+    face in the order W (ny*nz faces, index k*ny + j), E (same), S (nx*nz,
+    index k*nx + i), N (same), B (z = 0, nx*ny, index j*nx + i), T (z = lz,
+    same).  Types and values as in the 2D problem."""
+    nx: int
+    ny: int
+    nz: int
+    K: np.ndarray
+    q: np.ndarray
+    bc_type: np.ndarray
+    bc_value: np.ndarray
+    sub_nx: int
+    sub_ny: int
+    seg: int
+    alpha: float = 1.0
+    lx: float = 1.0
+    ly: float = 1.0
+    lz: float = 1.0
+    name: str = ""
+
+    def with_(self, **kw) -> "Problem3D":
+        return replace(self, **kw)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def bc_faces3d(nx: int, ny: int, nz: int) -> int:
+    return 2 * ny * nz + 2 * nx * nz + 2 * nx * ny
+
+
+def dirichlet_we3d(nx: int, ny: int, nz: int, p_west: float = 1.0, p_east: float = 0.0):
+    """p = p_west on x = 0, p = p_east on x = lx, no flow elsewhere (the
+    boundary conditions of the paper's runs, Section 5.1)."""
+    n = bc_faces3d(nx, ny, nz)
+    t = np.zeros(n, dtype=np.int8)
+    v = np.zeros(n, dtype=np.float64)
+    t[:2 * ny * nz] = BC_DIRICHLET
+    v[:ny * nz] = p_west
+    v[ny * nz:2 * ny * nz] = p_east
+    return t, v
