@@ -122,6 +122,21 @@ typedef struct {
                                 faces); eq. 14.2 holds on U-segments and eq. 13.2 on
                                 P-segments.  rmrcm_step_noalloc supports only
                                 seg_u = seg_p = seg (ENOTSUP otherwise). */
+    int32_t nz;              /* 0: the 2D problem above.  >= 1: the 3D problem of the
+                                paper's experiments (Section 5) on [0,lx] x [0,ly] x
+                                [0,lz] with nx x ny x nz cells (seven-point scheme),
+                                split into columns of sub_nx x sub_ny x nz cells (no
+                                division in z, Hbar_z = H_z: a segment is seg faces
+                                along its interface line by the full height; beta =
+                                alpha Hbar / Keff with Hbar its length along the line and
+                                Keff over all of its faces).  Cell (i,j,k) at index
+                                (k*ny + j)*nx + i; flux: 6 blocks of nx*ny*nz cells
+                                (W E S N B T, outward); boundary faces in the order
+                                W (ny*nz, index k*ny + j), E, S (nx*nz, index k*nx + i),
+                                N, B (z = 0, nx*ny, index j*nx + i), T.  FP64 only;
+                                sub_nx*nz <= 64; no general spaces, downscaling or
+                                allocation-free step (ENOTSUP). */
+    double lz;               /* z extent when nz >= 1; > 0 */
 } rmrcm_params;
 
 /* Fill *p with defaults (alpha 1, FP64, unit square, device 0); the
@@ -186,7 +201,8 @@ int rmrcm_sync(rmrcm_ctx* ctx);
  * from the new pressure by the two-point law.  Arrays host or device; the
  * call waits for its work.  The first call allocates a second factor store
  * and staging (not part of rmrcm_plan_bytes; the memory cap applies).
- * Errors: EINVAL, ENOMEM, EDEVICE, ESINGULAR. */
+ * 2D contexts with the MuMM spaces only (ENOTSUP otherwise).
+ * Errors: EINVAL, ENOMEM, EDEVICE, ESINGULAR, ENOTSUP. */
 int rmrcm_downscale(rmrcm_ctx* ctx, const double* source, const double* bc_value, const double* pressure,
                     const double* flux, double* pressure_out, double* flux_out);
 
@@ -339,9 +355,10 @@ typedef struct rmrcm_batch rmrcm_batch;
  * device), bc_types[i] as for rmrcm_setup.  autotune != 0 runs
  * rmrcm_autotune on every member and picks the number of pool streams
  * (1, 2, 4, 8 or 16) by timing a full refactor + solve pass of the batch;
- * otherwise 4 streams.  All members must use the same device.
+ * otherwise 4 streams.  All members must use the same device and be 2D
+ * problems (nz = 0; ENOTSUP otherwise).
  * Errors: those of rmrcm_setup for the first failing member, EINVAL,
- * ENOMEM, EDEVICE. */
+ * ENOMEM, EDEVICE, ENOTSUP. */
 int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* const* perms,
                        const int8_t* const* bc_types, int32_t autotune, rmrcm_batch** out);
 

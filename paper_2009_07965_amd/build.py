@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librmrcm.so")
 
-SOURCES = ["api.cpp", "cnn.cpp", "k_local.hip", "k_merge.hip", "k_recon.hip", "k_cnn.hip", "k_downscale.hip"]
+SOURCES = ["api.cpp", "cnn.cpp", "k_local.hip", "k_merge.hip", "k_recon.hip", "k_cnn.hip", "k_downscale.hip", "k_local3d.hip"]
 
 # -packed-fp32-ops: keep hipcc from emitting packed FP32 instructions.
 HIP_FLAGS = [

@@ -119,6 +119,18 @@ int validate(const rmrcm_params* p) {
     if (std::max(su, sp) % piece) return RMRCM_EINVAL;
     if (!is_pow2(p->nx / p->sub_nx) || !is_pow2(p->ny / p->sub_ny)) return RMRCM_EINVAL;
     if (p->precision < RMRCM_FP64 || p->precision > RMRCM_MIXED_LEARNED) return RMRCM_EINVAL;
+    if (p->nz < 0) return RMRCM_EINVAL;
+    if (p->nz > 0) {
+        // the 3D problem: columns of sub_nx x sub_ny x nz cells, FP64, MuMM spaces
+        if (!(p->lz > 0) || !std::isfinite(p->lz)) return RMRCM_EINVAL;
+        if (p->precision != RMRCM_FP64) return RMRCM_ENOTSUP;
+        if ((p->seg_u && p->seg_u != p->seg) || (p->seg_p && p->seg_p != p->seg)) return RMRCM_ENOTSUP;
+        if ((size_t)p->sub_nx * p->nz > 64 || p->sub_ny > 64) return RMRCM_ENOTSUP;
+        // one column's factor block, right-hand sides and products in LDS
+        const size_t nb = (size_t)p->sub_nx * p->nz, ncol = 2 * (size_t)(p->sub_nx + p->sub_ny) / p->seg + 1;
+        if (sizeof(double) * (nb * (nb + 1) + 2 * nb * ncol + 4 * nb + 2) > 160 * 1024) return RMRCM_ENOTSUP;
+        return RMRCM_OK;
+    }
     if (p->sub_nx != 4 && p->sub_nx != 8 && p->sub_nx != 16 && p->sub_nx != 32) return RMRCM_ENOTSUP;
     if (p->sub_ny > 64) return RMRCM_ENOTSUP;
     if (p->precision != RMRCM_FP64 && (!(p->ir_tol > 0) || p->ir_max_iter < 1)) return RMRCM_EINVAL;
@@ -133,9 +145,8 @@ int validate(const rmrcm_params* p) {
     return RMRCM_OK;
 }
 
-void build_geo(rmrcm_ctx* c) {
-    const rmrcm_params& p = c->prm;
-    Geo& g = c->geo;
+Geo geo_of(const rmrcm_params& p) {
+    Geo g{};
     g.nx = p.nx;
     g.ny = p.ny;
     g.bx = p.sub_nx;
@@ -155,7 +166,13 @@ void build_geo(rmrcm_ctx* c) {
     g.hx = p.lx / p.nx;
     g.hy = p.ly / p.ny;
     g.alpha = p.alpha;
+    g.three_d = p.nz > 0 ? 1 : 0;
+    g.nz = p.nz > 0 ? p.nz : 1;
+    g.hz = p.nz > 0 ? p.lz / p.nz : 1.0;
+    return g;
 }
+
+void build_geo(rmrcm_ctx* c) { c->geo = geo_of(c->prm); }
 
 // Host tables of every level: node grid, slots, slot codes, merge maps.
 void build_levels(rmrcm_ctx* c) {
@@ -286,16 +303,17 @@ int alloc_levels(rmrcm_ctx* c) {
 // network of the learned mode allocates its own).
 int alloc_arrays(rmrcm_ctx* c) {
     const Geo& g = c->geo;
-    const size_t ncell = (size_t)g.nx * g.ny;
-    const size_t nbf = 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+    const size_t ncell = geo_ncell(g);
+    const size_t nbf = geo_nbf(g);
     const size_t nsub = (size_t)g.mx * g.my;
-    const size_t n = (size_t)g.bx * g.by;
+    const size_t n = (size_t)g.bx * g.by * g.nz;
+    const size_t nb = (size_t)g.bx * g.nz;     // cells of one row of a column (the factor's block)
     const int R = c->levels[c->D].nslot;
     TRY(dalloc(c, &c->K, ncell));
     TRY(dalloc(c, &c->bct, nbf));
     TRY(dalloc(c, &c->beta, g.nseg));
     TRY(dalloc(c, &c->seglen, g.nseg));
-    TRY(dalloc(c, &c->Pstore, nsub * g.by * g.bx * g.bx));
+    TRY(dalloc(c, &c->Pstore, nsub * g.by * nb * nb));
     TRY(dalloc(c, &c->Psi, nsub * R * n));
     TRY(dalloc(c, &c->pbar, nsub * n));
     TRY(dalloc(c, &c->glo, g.nseg));
@@ -303,7 +321,7 @@ int alloc_arrays(rmrcm_ctx* c) {
     TRY(dalloc(c, &c->q, ncell));
     TRY(dalloc(c, &c->bcv, nbf));
     TRY(dalloc(c, &c->pout, ncell));
-    TRY(dalloc(c, &c->fout, 4 * ncell));
+    TRY(dalloc(c, &c->fout, (size_t)geo_nflux(g) * ncell));
     TRY(dalloc(c, &c->Uout, g.nseg));
     TRY(dalloc(c, &c->Pout, g.nseg));
     TRY(dalloc(c, &c->flags, rmrcm::kNumFlags));
@@ -516,7 +534,7 @@ int mark(rmrcm_ctx* c, int i) {
 // FP64 contexts outside graph capture run the particular chain (local
 // particular solves, merges of the particular column below the top) on the
 // auxiliary stream, each level after its own setup merge.
-bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c); }
+bool overlap(const rmrcm_ctx* c) { return c->aux && !c->capturing && !mixed(c) && !c->geo.three_d; }
 
 // Every permeability-dependent step, enqueued on c->stream (no host
 // synchronisation in FP64 mode, so that it can be captured in a graph).
@@ -605,8 +623,8 @@ int interface_refine(rmrcm_ctx* c) {
 
 // Inputs of a solve into the context's staging buffers.
 int solve_inputs(rmrcm_ctx* c, const double* source, const double* bc_value) {
-    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
-    const size_t nbf = 2 * (size_t)c->geo.nx + 2 * (size_t)c->geo.ny;
+    const size_t ncell = geo_ncell(c->geo);
+    const size_t nbf = geo_nbf(c->geo);
     TRY(mark(c, 4));
     if (source) {
         HIP_TRY(hipMemcpyAsync(c->q, source, ncell * sizeof(double), hipMemcpyDefault, c->stream));
@@ -748,9 +766,10 @@ int enqueue_step_fused(rmrcm_ctx* c, double* kcopy) {
 }
 
 int solve_outputs(rmrcm_ctx* c, double* pressure, double* flux) {
-    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+    const size_t ncell = geo_ncell(c->geo);
     HIP_TRY(hipMemcpyAsync(pressure, c->pout, ncell * sizeof(double), hipMemcpyDefault, c->stream));
-    HIP_TRY(hipMemcpyAsync(flux, c->fout, 4 * ncell * sizeof(double), hipMemcpyDefault, c->stream));
+    HIP_TRY(hipMemcpyAsync(flux, c->fout, geo_nflux(c->geo) * ncell * sizeof(double), hipMemcpyDefault,
+                           c->stream));
     TRY(mark(c, 10));
     return RMRCM_OK;
 }
@@ -771,6 +790,7 @@ void rmrcm_default_params(rmrcm_params* p) {
     p->gate_tol = 1e-6;
     p->cnn_weights = nullptr;
     p->device = 0;
+    p->lz = 1.0;
 }
 
 const char* rmrcm_strerror(int s) {
@@ -826,8 +846,9 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
     if (prm->device < 0 || prm->device >= ndev) return RMRCM_EINVAL;
     if (hipSetDevice(prm->device) != hipSuccess) return RMRCM_EDEVICE;
 
-    const size_t ncell = (size_t)prm->nx * prm->ny;
-    const size_t nbf = 2 * (size_t)prm->nx + 2 * (size_t)prm->ny;
+    const rmrcm::Geo pg = geo_of(*prm);
+    const size_t ncell = geo_ncell(pg);
+    const size_t nbf = geo_nbf(pg);
     const bool kdev = is_device_ptr(perm), tdev = is_device_ptr(bc_type);
     // Validate the host-side copies before any device work.
     std::vector<int8_t> ht(nbf);
@@ -905,7 +926,7 @@ int rmrcm_setup(const rmrcm_params* prm, const double* perm, const int8_t* bc_ty
 int rmrcm_refactor(rmrcm_ctx* c, const double* perm) {
     if (!c || !perm) return RMRCM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
-    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
+    const size_t ncell = geo_ncell(c->geo);
     c->solved = false;
     HIP_TRY(hipMemcpyAsync(c->K, perm, ncell * sizeof(double), hipMemcpyDefault, c->stream));
     return run_setup(c, false);
@@ -916,8 +937,8 @@ int rmrcm_solve(rmrcm_ctx* c, const double* source, const double* bc_value, doub
     if (!c || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
     if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
     const Geo& g = c->geo;
-    const size_t ncell = (size_t)g.nx * g.ny;
-    const size_t nbf = 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+    const size_t ncell = geo_ncell(g);
+    const size_t nbf = geo_nbf(g);
     if (!c->any_dirichlet) {
         // all faces Neumann: the data must be compatible (net source equals
         // the prescribed net outflow)
@@ -1420,8 +1441,10 @@ int rmrcm_batch_create(int32_t count, const rmrcm_params* prms, const double* co
     if (!out) return RMRCM_EINVAL;
     *out = nullptr;
     if (count <= 0 || !prms || !perms || !bc_types) return RMRCM_EINVAL;
-    for (int i = 0; i < count; ++i)
+    for (int i = 0; i < count; ++i) {
         if (prms[i].device != prms[0].device || !perms[i] || !bc_types[i]) return RMRCM_EINVAL;
+        if (prms[i].nz > 0) return RMRCM_ENOTSUP;   // ensembles of 2D problems
+    }
     rmrcm_batch* b = new (std::nothrow) rmrcm_batch();
     if (!b) return RMRCM_ENOMEM;
     b->device = prms[0].device;
@@ -1586,6 +1609,7 @@ int rmrcm_set_step_graph(rmrcm_ctx* c, int enabled) {
 int rmrcm_downscale(rmrcm_ctx* c, const double* source, const double* bc_value, const double* pressure,
                     const double* flux, double* pressure_out, double* flux_out) {
     if (!c || !bc_value || !pressure || !flux || !pressure_out || !flux_out) return RMRCM_EINVAL;
+    if (c->geo.three_d || c->geo.mu > 1 || c->geo.mp > 1) return RMRCM_ENOTSUP;
     if (hipSetDevice(c->device) != hipSuccess) return RMRCM_EDEVICE;
     const Geo& g = c->geo;
     const size_t ncell = (size_t)g.nx * g.ny;
@@ -1707,7 +1731,7 @@ int rmrcm_step(rmrcm_ctx* c, const double* perm, const double* source, const dou
         // the kernels read the caller's permeability, source and boundary
         // data; the library's copy of the permeability (for later calls) is
         // written by the permeability check
-        const size_t ncell = (size_t)cc->geo.nx * cc->geo.ny;
+        const size_t ncell = geo_ncell(cc->geo);
         cc->pout = pressure;
         cc->fout = flux;
         cc->K = const_cast<double*>(perm);
@@ -1851,6 +1875,7 @@ extern "C" int rmrcm_step_noalloc(const rmrcm_params* prm, const double* perm, c
     if (v != RMRCM_OK) return v;
     if (prm->precision != RMRCM_FP64) return RMRCM_ENOTSUP;
     if ((prm->seg_u && prm->seg_u != prm->seg) || (prm->seg_p && prm->seg_p != prm->seg)) return RMRCM_ENOTSUP;
+    if (prm->nz > 0) return RMRCM_ENOTSUP;
     if (!perm || !bc_type || !bc_value || !pressure || !flux) return RMRCM_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {

@@ -104,34 +104,39 @@ __device__ inline double bface(const Geo& g, const double* __restrict__ K,
 // adjacent permeabilities (Section 5.1).  With general interface spaces the
 // segment is the piece's U-segment (its g.mu pieces along the line, the
 // first at a multiple of g.mu); seglen is the piece's own length.
+// In 3D the segment's faces are those of every layer (the mean runs over
+// all of them), Hbar is its length along the line and seglen its area.
 __device__ inline void beta_of(const Geo& g, const double* __restrict__ K, double* __restrict__ beta,
                                double* __restrict__ seglen, int e) {
     double hsum = 0.0, len, h;
-    const int nf = g.mu * g.sg;             // faces of the U-segment
-    if (e < g.nv) {
-        const int I = e / g.lines_v + 1, k = e % g.lines_v;
-        const int ilo = I * g.bx - 1, k0 = k - k % g.mu;
-        for (int t = 0; t < nf; ++t) {
-            const int j = k0 * g.sg + t;
-            const double a = cellK(K, g, ilo, j), b = cellK(K, g, ilo + 1, j);
-            hsum += 2.0 * a * b / (a + b);
+    const int nh = g.mu * g.sg;             // faces of the U-segment along its line
+    const size_t layer = (size_t)g.nx * g.ny;
+    for (int kz = 0; kz < g.nz; ++kz) {
+        const double* Kk = K + kz * layer;
+        if (e < g.nv) {
+            const int I = e / g.lines_v + 1, k = e % g.lines_v;
+            const int ilo = I * g.bx - 1, k0 = k - k % g.mu;
+            for (int t = 0; t < nh; ++t) {
+                const int j = k0 * g.sg + t;
+                const double a = cellK(Kk, g, ilo, j), b = cellK(Kk, g, ilo + 1, j);
+                hsum += 2.0 * a * b / (a + b);
+            }
+        } else {
+            const int r = e - g.nv;
+            const int J = r / g.lines_h + 1, k = r % g.lines_h;
+            const int jlo = J * g.by - 1, k0 = k - k % g.mu;
+            for (int t = 0; t < nh; ++t) {
+                const int i = k0 * g.sg + t;
+                const double a = cellK(Kk, g, i, jlo), b = cellK(Kk, g, i, jlo + 1);
+                hsum += 2.0 * a * b / (a + b);
+            }
         }
-        h = g.hy;
-    } else {
-        const int r = e - g.nv;
-        const int J = r / g.lines_h + 1, k = r % g.lines_h;
-        const int jlo = J * g.by - 1, k0 = k - k % g.mu;
-        for (int t = 0; t < nf; ++t) {
-            const int i = k0 * g.sg + t;
-            const double a = cellK(K, g, i, jlo), b = cellK(K, g, i, jlo + 1);
-            hsum += 2.0 * a * b / (a + b);
-        }
-        h = g.hx;
     }
-    len = nf * h;
-    const double keff = hsum / nf;
+    h = e < g.nv ? g.hy : g.hx;
+    len = nh * h;
+    const double keff = hsum / (nh * g.nz);
     beta[e] = g.alpha * len / keff;
-    seglen[e] = g.sg * h;
+    seglen[e] = g.sg * h * (g.nz * g.hz);
 }
 
 
@@ -2763,7 +2768,7 @@ static hipError_t trace_correct_bx(rmrcm_ctx* c, int basis, int part, const int*
 }
 
 hipError_t launch_check_beta(rmrcm_ctx* c, double* copy) {
-    const size_t n = (size_t)c->geo.nx * c->geo.ny;
+    const size_t n = geo_ncell(c->geo);
     const int nbc = 1024, nbb = (c->geo.nseg + 255) / 256;
     hipLaunchKernelGGL(k_check_beta, dim3(nbc + nbb), dim3(256), 0, c->stream, c->geo, c->K, n, c->flags, copy,
                        nbc, c->beta, c->seglen);
@@ -2781,6 +2786,7 @@ hipError_t launch_check_beta(rmrcm_ctx* c, double* copy) {
 
 hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces,
                               int basis, int part) {
+    if (c->geo.three_d) return fp32 || mask || !basis ? hipErrorInvalidValue : launch_local3d(c, 1, 1, 0);
     if (part && !local_setup_solves_particular(c, fp32)) return hipErrorInvalidValue;
     if (fp32) {
         RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces, basis, 0)),
@@ -2795,11 +2801,12 @@ hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want
 }
 
 bool local_setup_solves_particular(const rmrcm_ctx* c, bool fp32) {
-    return !fp32 && (c->geo.bx == 16 || c->geo.bx == 32);
+    return !fp32 && !c->geo.three_d && (c->geo.bx == 16 || c->geo.bx == 32);
 }
 
 hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,
                                    int do_traces) {
+    if (c->geo.three_d) return fp32 || mask ? hipErrorInvalidValue : launch_local3d(c, 0, 0, 1);
     if (fp32) {
         RMRCM_BX_SWITCH((part_bx<4, float>(c, c->P32, mask, want, do_traces)),
                         (part_bx<8, float>(c, c->P32, mask, want, do_traces)),
@@ -2818,6 +2825,7 @@ hipError_t launch_local_refine(rmrcm_ctx* c, int part, int apply) {
 }
 
 hipError_t launch_trace_correct(rmrcm_ctx* c, int basis, int part) {
+    if (c->geo.three_d) return hipSuccess;   // the 3D traces are formed from the solution directly
     const int nsub = c->geo.mx * c->geo.my;
     RMRCM_BX_SWITCH((trace_correct_bx<4>(c, basis, part, nullptr, nsub)),
                     (trace_correct_bx<8>(c, basis, part, nullptr, nsub)),

@@ -1,0 +1,366 @@
+// The three-dimensional method (Section 5: a box of nx x ny x nz cells,
+// the seven-point two-point-flux scheme, a finest decomposition with no
+// division in z and Hbar_z = H_z).  Every subdomain is a column of
+// bx x by x nz cells; its skeleton faces are on its four sides, a segment
+// covering sg faces along its line by the full height, so the slots, the
+// traces and every merge are those of the 2D method.  Only the local
+// problems and the reconstruction change.
+//
+// Local problem of a column (eq. 11.2-12.2 with the lumped velocity mass):
+// cells ordered by rows j (the y index), row j being the x-z plane of
+// NB = bx * nz cells, element r = k * bx + i.  The matrix is block
+// tridiagonal in j: the plane operator A_j (x and z couplings, the y
+// couplings' diagonal share, Robin and Dirichlet conductances) and the
+// diagonal couplings D_j to row j + 1 (the y transmissibilities).  Block
+// elimination with explicit inverses: S_0 = A_0, P_j = S_j^-1,
+// S_{j+1} = A_{j+1} - D_j P_j D_j; forward y_0 = b_0,
+// y_{j+1} = b_{j+1} + D_j P_j y_j; backward x_last = P_last y_last,
+// x_j = P_j (y_j + D_j x_{j+1}).  One workgroup of 256 threads per column;
+// S_j is inverted in LDS by Gauss-Jordan without pivoting (S_j is SPD);
+// the inverses P_j are the factor store of later particular solves.
+// Traces (the outward flux through each slot's faces per unit datum of
+// each slot, and of the particular solution) are formed from the solution.
+
+#include <algorithm>
+
+#include "rmrcm_internal.h"
+
+namespace rmrcm {
+
+namespace {
+
+struct Face3 {
+    int kind;      // 0 interior, 1 Robin (slot), 2 outer boundary
+    int slot;      // local slot of a Robin face
+    int of;        // boundary-face index of an outer face
+    double cond;   // transmissibility, Robin |f| / (rho + beta), Dirichlet |f| / rho, 0 (Neumann)
+};
+
+__device__ inline double k3(const double* __restrict__ K, const Geo& g, int gi, int gj, int k) {
+    return K[((size_t)k * g.ny + gj) * g.nx + gi];
+}
+
+// Face `side` (0 W, 1 E, 2 S, 3 N, 4 B, 5 T) of local cell (i, j, k) of
+// column (I, J); ss: the column's slot codes.
+__device__ inline Face3 face3(const Geo& g, const double* __restrict__ K, const int8_t* __restrict__ bct,
+                              const double* __restrict__ beta, const int* __restrict__ ss, int I, int J, int i,
+                              int j, int k, int side) {
+    const int gi = I * g.bx + i, gj = J * g.by + j;
+    int ni = gi, nj = gj, nk = k, of = -1;
+    bool skel = false;
+    double area, w;
+    switch (side) {
+        case 0:
+            area = g.hy * g.hz, w = g.hx, ni = gi - 1;
+            if (gi == 0) of = k * g.ny + gj;
+            else skel = i == 0;
+            break;
+        case 1:
+            area = g.hy * g.hz, w = g.hx, ni = gi + 1;
+            if (gi == g.nx - 1) of = g.ny * g.nz + k * g.ny + gj;
+            else skel = i == g.bx - 1;
+            break;
+        case 2:
+            area = g.hx * g.hz, w = g.hy, nj = gj - 1;
+            if (gj == 0) of = 2 * g.ny * g.nz + k * g.nx + gi;
+            else skel = j == 0;
+            break;
+        case 3:
+            area = g.hx * g.hz, w = g.hy, nj = gj + 1;
+            if (gj == g.ny - 1) of = 2 * g.ny * g.nz + g.nx * g.nz + k * g.nx + gi;
+            else skel = j == g.by - 1;
+            break;
+        case 4:
+            area = g.hx * g.hy, w = g.hz, nk = k - 1;
+            if (k == 0) of = 2 * g.ny * g.nz + 2 * g.nx * g.nz + gj * g.nx + gi;
+            break;
+        default:
+            area = g.hx * g.hy, w = g.hz, nk = k + 1;
+            if (k == g.nz - 1) of = 2 * g.ny * g.nz + 2 * g.nx * g.nz + g.nx * g.ny + gj * g.nx + gi;
+            break;
+    }
+    const double rc = w / (2.0 * k3(K, g, gi, gj, k));
+    Face3 f{0, -1, of, 0.0};
+    if (of >= 0) {
+        f.kind = 2;
+        f.cond = bct[of] == RMRCM_BC_DIRICHLET ? area / rc : 0.0;
+    } else if (skel) {
+        const int a = side == 0 ? j / g.sg
+                    : side == 1 ? g.nsy + j / g.sg
+                    : side == 2 ? 2 * g.nsy + i / g.sg
+                                : 2 * g.nsy + g.nsx + i / g.sg;
+        f.kind = 1;
+        f.slot = a;
+        f.cond = area / (rc + beta[ss[a] >> 1]);
+    } else {
+        f.cond = area / (rc + w / (2.0 * k3(K, g, ni, nj, nk)));
+    }
+    return f;
+}
+
+__device__ inline size_t cell3(const Geo& g, int i, int j, int k) { return ((size_t)k * g.by + j) * g.bx + i; }
+
+}  // namespace
+
+__host__ __device__ inline size_t local3d_lds(int nb, int ncol) {
+    return sizeof(double) * ((size_t)nb * (nb + 1) + 2 * (size_t)nb * ncol + 4 * (size_t)nb + 2);
+}
+
+// factor = 1: the factorisation (P_j to the factor store), the basis
+// (basis = 1: one column per slot) and the particular solution (part = 1),
+// with their traces.  factor = 0: the particular solution with the stored
+// P_j, and its traces.
+__global__ __launch_bounds__(256) void k_local3d(Geo g, const double* __restrict__ K,
+                                                 const int8_t* __restrict__ bct,
+                                                 const double* __restrict__ bcv,
+                                                 const double* __restrict__ beta,
+                                                 const int* __restrict__ slotseg, int R,
+                                                 double* __restrict__ Pstore, double* __restrict__ Psi,
+                                                 double* __restrict__ pbar, const double* __restrict__ q,
+                                                 double* __restrict__ T, int ld, int* __restrict__ flags,
+                                                 int factor, int basis, int part) {
+    extern __shared__ double sm3[];
+    const int sub = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int I = sub % g.mx, J = sub / g.mx;
+    const int NB = g.bx * g.nz, BY = g.by, LS = NB + 1;
+    const int nbas = basis ? R : 0, ncol = nbas + (part ? 1 : 0);
+    const size_t n = (size_t)NB * BY;
+    double* S = sm3;                       // NB x LS: S_j, then P_j
+    double* Y = S + (size_t)NB * LS;       // NB x ncol
+    double* Z = Y + (size_t)NB * ncol;     // NB x ncol
+    double* dp = Z + (size_t)NB * ncol;    // couplings D_{j-1}
+    double* dn = dp + NB;                  // couplings D_j
+    double* rowp = dn + NB;                // Gauss-Jordan pivot row
+    double* colp = rowp + NB;              // and column
+    double* piv = colp + NB;               // [0]: 1 / pivot, [1]: singular
+    const int* ss = slotseg + (size_t)sub * R;
+    double* Pst = Pstore + (size_t)sub * BY * NB * NB;
+    // column c's value at local cell (i, j, k)
+    auto col = [&](int c, size_t cell) -> double* {
+        return c < nbas ? Psi + ((size_t)sub * R + c) * n + cell : pbar + (size_t)sub * n + cell;
+    };
+    if (tid == 0) piv[1] = 0.0;
+    // ---- forward: factorisation and y_j
+    for (int j = 0; j < BY; ++j) {
+        if (j > 0) {
+            if (!factor)
+                for (int e = tid; e < NB * NB; e += nt) S[(e / NB) * LS + e % NB] = Pst[(size_t)(j - 1) * NB * NB + e];
+            __syncthreads();
+            for (int e = tid; e < NB * ncol; e += nt) {
+                const int r = e / ncol, c = e % ncol;
+                double s = 0.0;
+                for (int u = 0; u < NB; ++u) s += S[r * LS + u] * Y[u * ncol + c];
+                Z[e] = s;
+            }
+        }
+        __syncthreads();
+        // right-hand sides of row j (+ D_{j-1} P_{j-1} y_{j-1}) and D_j
+        for (int e = tid; e < NB * ncol; e += nt) {
+            const int r = e / ncol, c = e % ncol, k = r / g.bx, i = r % g.bx;
+            double b = 0.0;
+            for (int side = 0; side < 6; ++side) {
+                if (side == 3 && j < BY - 1 && c == 0) {
+                    // coupling to row j + 1 (an interior face inside the column)
+                    const Face3 f = face3(g, K, bct, beta, ss, I, J, i, j, k, 3);
+                    dn[r] = f.cond;
+                }
+                if ((side == 2 && j > 0) || (side == 3 && j < BY - 1)) continue;
+                if ((side == 0 && i > 0) || (side == 1 && i < g.bx - 1)) continue;
+                if ((side == 4 && k > 0) || (side == 5 && k < g.nz - 1)) continue;
+                const Face3 f = face3(g, K, bct, beta, ss, I, J, i, j, k, side);
+                if (c < nbas) {
+                    if (f.kind == 1 && f.slot == c) b += f.cond;
+                } else if (f.kind == 2) {
+                    b += bct[f.of] == RMRCM_BC_DIRICHLET ? f.cond * bcv[f.of] : -bcv[f.of];
+                }
+            }
+            if (c >= nbas && q) b += q[((size_t)k * g.ny + J * BY + j) * g.nx + I * g.bx + i];
+            if (j > 0) b += dp[r] * Z[e];
+            Y[e] = b;
+            *col(c, cell3(g, i, j, k)) = b;     // y_j, overwritten by x_j in the backward pass
+        }
+        if (factor) {
+            __syncthreads();
+            // S_j = A_j - D_{j-1} P_{j-1} D_{j-1} (P_{j-1} in S)
+            for (int e = tid; e < NB * NB; e += nt) {
+                const int r = e / NB, c = e % NB;
+                const int k = r / g.bx, i = r % g.bx, kc = c / g.bx, ic = c % g.bx;
+                double a = 0.0;
+                if (r == c) {
+                    for (int side = 0; side < 6; ++side) a += face3(g, K, bct, beta, ss, I, J, i, j, k, side).cond;
+                } else if (k == kc && (ic == i + 1 || ic == i - 1)) {
+                    a = -face3(g, K, bct, beta, ss, I, J, i, j, k, ic > i ? 1 : 0).cond;
+                } else if (i == ic && (kc == k + 1 || kc == k - 1)) {
+                    a = -face3(g, K, bct, beta, ss, I, J, i, j, k, kc > k ? 5 : 4).cond;
+                }
+                S[r * LS + c] = j > 0 ? a - dp[r] * S[r * LS + c] * dp[c] : a;
+            }
+            __syncthreads();
+            // P_j = S_j^-1, Gauss-Jordan in place
+            for (int p = 0; p < NB; ++p) {
+                if (tid == 0) {
+                    double d = S[p * LS + p];
+                    if (!(d > 0.0)) {
+                        piv[1] = 1.0;
+                        d = 1.0;
+                    }
+                    piv[0] = 1.0 / d;
+                }
+                __syncthreads();
+                const double inv = piv[0];
+                for (int u = tid; u < NB; u += nt) {
+                    rowp[u] = u == p ? inv : S[p * LS + u] * inv;
+                    colp[u] = S[u * LS + p];
+                }
+                __syncthreads();
+                for (int e = tid; e < NB * NB; e += nt) {
+                    const int r = e / NB, c = e % NB;
+                    if (r == p) S[r * LS + c] = rowp[c];
+                    else if (c == p) S[r * LS + c] = -colp[r] * inv;
+                    else S[r * LS + c] -= colp[r] * rowp[c];
+                }
+                __syncthreads();
+            }
+            for (int e = tid; e < NB * NB; e += nt) Pst[(size_t)j * NB * NB + e] = S[(e / NB) * LS + e % NB];
+        }
+        __syncthreads();
+        for (int r = tid; r < NB; r += nt) dp[r] = dn[r];
+        __syncthreads();
+    }
+    // ---- backward: x_last = P_last y_last; x_j = P_j (y_j + D_j x_{j+1})
+    for (int j = BY - 1; j >= 0; --j) {
+        if (!factor || j < BY - 1)
+            for (int e = tid; e < NB * NB; e += nt) S[(e / NB) * LS + e % NB] = Pst[(size_t)j * NB * NB + e];
+        if (j < BY - 1) {
+            for (int e = tid; e < NB * ncol; e += nt) {
+                const int r = e / ncol, c = e % ncol, k = r / g.bx, i = r % g.bx;
+                const double dj = face3(g, K, bct, beta, ss, I, J, i, j, k, 3).cond;
+                Z[e] = *col(c, cell3(g, i, j, k)) + dj * Y[e];
+            }
+        } else {
+            for (int e = tid; e < NB * ncol; e += nt) Z[e] = Y[e];
+        }
+        __syncthreads();
+        for (int e = tid; e < NB * ncol; e += nt) {
+            const int r = e / ncol, c = e % ncol;
+            double s = 0.0;
+            for (int u = 0; u < NB; ++u) s += S[r * LS + u] * Z[u * ncol + c];
+            Y[e] = s;
+            *col(c, cell3(g, r % g.bx, j, r / g.bx)) = s;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && piv[1] != 0.0) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
+    __threadfence_block();
+    __syncthreads();
+    // ---- traces: T[a][b] = sum over the faces f of slot a of c_f (x_b(f) - delta_ab)
+    double* Ts = T + (size_t)sub * R * ld;
+    const int nf = g.sg * g.nz;
+    for (int e = tid; e < R * ncol; e += nt) {
+        const int a = e / ncol, c = e % ncol;
+        const int tc = c < nbas ? c : ld - 1;
+        double s = 0.0;
+        if (ss[a] >= 0 && (c >= nbas || ss[c] >= 0)) {
+            const int side = a < g.nsy ? 0 : a < 2 * g.nsy ? 1 : a < 2 * g.nsy + g.nsx ? 2 : 3;
+            const int s0 = (side == 0 ? a : side == 1 ? a - g.nsy : side == 2 ? a - 2 * g.nsy
+                                                                             : a - 2 * g.nsy - g.nsx) * g.sg;
+            for (int t = 0; t < nf; ++t) {
+                const int k = t / g.sg, u = s0 + t % g.sg;
+                const int i = side == 0 ? 0 : side == 1 ? g.bx - 1 : u;
+                const int j = side == 2 ? 0 : side == 3 ? BY - 1 : u;
+                const double cf = face3(g, K, bct, beta, ss, I, J, i, j, k, side).cond;
+                s += cf * (*col(c, cell3(g, i, j, k)) - (c == a ? 1.0 : 0.0));
+            }
+        }
+        Ts[(size_t)a * ld + tc] = s;
+    }
+}
+
+// Pressures (pbar + sum_a Psi_a g_a) of every cell, then its six outward
+// fluxes: interior faces by the two-point law, Robin faces c (p - g), outer
+// faces from the boundary data.
+__global__ __launch_bounds__(256) void k_recon3d_p(Geo g, int R, const int* __restrict__ slotseg,
+                                                   const double* __restrict__ Psi,
+                                                   const double* __restrict__ pbar,
+                                                   const double* __restrict__ glo,
+                                                   const double* __restrict__ ghi, double* __restrict__ p,
+                                                   const int* __restrict__ run) {
+    if (run && !*run) return;
+    const size_t ncell = geo_ncell(g), n = (size_t)g.bx * g.by * g.nz;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell; t += (size_t)gridDim.x * blockDim.x) {
+        const int gi = (int)(t % g.nx), gj = (int)((t / g.nx) % g.ny), k = (int)(t / ((size_t)g.nx * g.ny));
+        const int I = gi / g.bx, J = gj / g.by, sub = J * g.mx + I;
+        const size_t c = cell3(g, gi - I * g.bx, gj - J * g.by, k);
+        const int* ss = slotseg + (size_t)sub * R;
+        double v = pbar[(size_t)sub * n + c];
+        for (int a = 0; a < R; ++a) {
+            const int code = ss[a];
+            if (code < 0) continue;
+            const double d = (code & 1) ? glo[code >> 1] : ghi[code >> 1];
+            v += Psi[((size_t)sub * R + a) * n + c] * d;
+        }
+        p[t] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_recon3d_f(Geo g, const double* __restrict__ K,
+                                                   const int8_t* __restrict__ bct,
+                                                   const double* __restrict__ bcv,
+                                                   const double* __restrict__ beta, int R,
+                                                   const int* __restrict__ slotseg,
+                                                   const double* __restrict__ glo,
+                                                   const double* __restrict__ ghi,
+                                                   const double* __restrict__ p, double* __restrict__ f,
+                                                   const int* __restrict__ run) {
+    if (run && !*run) return;
+    const size_t ncell = geo_ncell(g);
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < ncell; t += (size_t)gridDim.x * blockDim.x) {
+        const int gi = (int)(t % g.nx), gj = (int)((t / g.nx) % g.ny), k = (int)(t / ((size_t)g.nx * g.ny));
+        const int I = gi / g.bx, J = gj / g.by, sub = J * g.mx + I;
+        const int* ss = slotseg + (size_t)sub * R;
+        const double pc = p[t];
+        for (int side = 0; side < 6; ++side) {
+            const Face3 fc = face3(g, K, bct, beta, ss, I, J, gi - I * g.bx, gj - J * g.by, k, side);
+            double v;
+            if (fc.kind == 0) {
+                const long long d = side == 0 ? -1 : side == 1 ? 1 : side == 2 ? -(long long)g.nx
+                                  : side == 3 ? (long long)g.nx : side == 4 ? -(long long)g.nx * g.ny
+                                                                          : (long long)g.nx * g.ny;
+                v = fc.cond * (pc - p[t + d]);
+            } else if (fc.kind == 1) {
+                const int code = ss[fc.slot];
+                const double gd = (code & 1) ? glo[code >> 1] : ghi[code >> 1];
+                v = fc.cond * (pc - gd);
+            } else {
+                v = bct[fc.of] == RMRCM_BC_DIRICHLET ? fc.cond * (pc - bcv[fc.of]) : bcv[fc.of];
+            }
+            f[side * ncell + t] = v;
+        }
+    }
+}
+
+hipError_t launch_local3d(rmrcm_ctx* c, int factor, int basis, int part) {
+    const Level& L = c->levels[c->D];
+    const int NB = c->geo.bx * c->geo.nz, ncol = (basis ? L.nslot : 0) + (part ? 1 : 0);
+    const size_t lds = local3d_lds(NB, ncol);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void*)k_local3d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_local3d, dim3(c->geo.mx * c->geo.my), dim3(256), lds, c->stream, c->geo, c->K, c->bct,
+                       c->bcv, c->beta, L.slotseg, L.nslot, c->Pstore, c->Psi, c->pbar, c->q, L.T, L.ld, c->flags,
+                       factor, basis, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_reconstruct3d(rmrcm_ctx* c) {
+    const Level& L = c->levels[c->D];
+    const size_t ncell = geo_ncell(c->geo);
+    const unsigned nb = (unsigned)std::min<size_t>((ncell + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_recon3d_p, dim3(nb), dim3(256), 0, c->stream, c->geo, L.nslot, L.slotseg, c->Psi, c->pbar,
+                       c->glo, c->ghi, c->pout, c->run_ptr);
+    hipLaunchKernelGGL(k_recon3d_f, dim3(nb), dim3(256), 0, c->stream, c->geo, c->K, c->bct, c->bcv, c->beta,
+                       L.nslot, L.slotseg, c->glo, c->ghi, c->pout, c->fout, c->run_ptr);
+    return hipGetLastError();
+}
+
+}  // namespace rmrcm

@@ -228,25 +228,26 @@ __device__ inline void wave_max_u64(unsigned long long* dst, double v) {
 __device__ inline void iface_terms(const Geo& g, const double* __restrict__ K, const double* __restrict__ p,
                                    const double* __restrict__ f, double be, int e, double* flo, double* fhi,
                                    double* sc, double* mag) {
-    const size_t plane = (size_t)g.nx * g.ny;
-    for (int t = 0; t < g.sg; ++t) {
+    const size_t plane = geo_ncell(g), layer = (size_t)g.nx * g.ny;
+    for (int t = 0; t < g.sg * g.nz; ++t) {
         size_t olo, ohi;
         double area, rlo, rhi;
         int slo, shi;
+        const int tz = t / g.sg, ta = t % g.sg;   // layer, face along the line
         if (e < g.nv) {
-            const int I = e / g.lines_v + 1, j = (e % g.lines_v) * g.sg + t;
-            olo = (size_t)j * g.nx + I * g.bx - 1;
+            const int I = e / g.lines_v + 1, j = (e % g.lines_v) * g.sg + ta;
+            olo = tz * layer + (size_t)j * g.nx + I * g.bx - 1;
             ohi = olo + 1;
-            area = g.hy;
+            area = g.hy * g.hz;
             rlo = g.hx / (2.0 * K[olo]);
             rhi = g.hx / (2.0 * K[ohi]);
             slo = 1;
             shi = 0;
         } else {
-            const int r = e - g.nv, J = r / g.lines_h + 1, i = (r % g.lines_h) * g.sg + t;
-            olo = (size_t)(J * g.by - 1) * g.nx + i;
+            const int r = e - g.nv, J = r / g.lines_h + 1, i = (r % g.lines_h) * g.sg + ta;
+            olo = tz * layer + (size_t)(J * g.by - 1) * g.nx + i;
             ohi = olo + g.nx;
-            area = g.hx;
+            area = g.hx * g.hz;
             rlo = g.hy / (2.0 * K[olo]);
             rhi = g.hy / (2.0 * K[ohi]);
             slo = 3;
@@ -390,14 +391,14 @@ hipError_t launch_fill_f64(rmrcm_ctx* c, double* p, size_t n, double v) {
 }
 
 hipError_t launch_compat_check(rmrcm_ctx* c) {
-    const size_t ncell = (size_t)c->geo.nx * c->geo.ny;
-    const size_t nbf = 2 * (size_t)c->geo.nx + 2 * (size_t)c->geo.ny;
+    const size_t ncell = geo_ncell(c->geo);
+    const size_t nbf = geo_nbf(c->geo);
     hipLaunchKernelGGL(k_compat, dim3(1), dim3(1024), 0, c->stream, c->q, ncell, c->bcv, nbf, c->flags);
     return hipGetLastError();
 }
 
 hipError_t launch_gauge(rmrcm_ctx* c) {
-    const size_t n = (size_t)c->geo.nx * c->geo.ny;
+    const size_t n = geo_ncell(c->geo);
     hipLaunchKernelGGL(k_pressure_partial, dim3(kGB), dim3(256), 0, c->stream, c->pout, n, c->gauge,
                        c->run_ptr);
     hipLaunchKernelGGL(k_pressure_shift, dim3(1024), dim3(256), 0, c->stream, c->pout, n, c->gauge, kGB,
@@ -421,6 +422,7 @@ static hipError_t recon_bx(rmrcm_ctx* c) {
 }
 
 hipError_t launch_reconstruct(rmrcm_ctx* c) {
+    if (c->geo.three_d) return launch_reconstruct3d(c);
     switch (c->geo.bx) {
         case 4: return recon_bx<4>(c);
         case 8: return recon_bx<8>(c);

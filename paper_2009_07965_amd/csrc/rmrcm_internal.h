@@ -25,6 +25,10 @@ struct Geo {
     int nseg;          // total segments
     double hx, hy;
     double alpha;
+    // 3D (three_d = 1): nz cell layers of height hz; in 2D nz = 1 and
+    // hz = 1 (unit depth: a face area is its 2D length)
+    int nz = 1, three_d = 0;
+    double hz = 1.0;
     // Neumann mode (the downscaling solves): faces on Robin slots carry no
     // conductance, and a subdomain whose pin entry is nonzero (no Dirichlet
     // face) gets the full half-cell conductance on the W face of its cell
@@ -35,6 +39,14 @@ struct Geo {
     // per P-segment (1 and 1: the MuMM spaces)
     int mu = 1, mp = 1;
 };
+
+// Cells, boundary faces and one-sided flux blocks of a problem.
+__host__ __device__ inline size_t geo_ncell(const Geo& g) { return (size_t)g.nx * g.ny * g.nz; }
+__host__ __device__ inline size_t geo_nbf(const Geo& g) {
+    return g.three_d ? 2 * ((size_t)g.ny * g.nz + (size_t)g.nx * g.nz + (size_t)g.nx * g.ny)
+                     : 2 * (size_t)g.nx + 2 * (size_t)g.ny;
+}
+__host__ __device__ inline int geo_nflux(const Geo& g) { return g.three_d ? 6 : 4; }
 
 // Slot -> segment code: (segment id << 1) | low_side, or -1 if the slot lies
 // on the outer boundary.  low_side = 1 when the node is on the low (left or
@@ -219,6 +231,11 @@ hipError_t launch_down_all(rmrcm_ctx* c);
 int build_down_sub(rmrcm_ctx* c);
 hipError_t launch_reconstruct(rmrcm_ctx* c);
 hipError_t launch_iface_resid(rmrcm_ctx* c, double tol, double* mx, int* flag, const int* run);
+// 3D columns: factor store, basis and particular solution (factor = 1), or
+// the particular solution with the stored factor (factor = 0); the
+// reconstruction
+hipError_t launch_local3d(rmrcm_ctx* c, int factor, int basis, int part);
+hipError_t launch_reconstruct3d(rmrcm_ctx* c);
 hipError_t launch_iface_inject(rmrcm_ctx* c);
 hipError_t launch_iface_apply(rmrcm_ctx* c);
 hipError_t launch_ds_source(rmrcm_ctx* c, const double* F, const double* q, double* qo);

@@ -43,6 +43,7 @@ class rmrcm_params(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("mem_cap", ctypes.c_uint64),
         ("seg_u", ctypes.c_int32), ("seg_p", ctypes.c_int32),
+        ("nz", ctypes.c_int32), ("lz", ctypes.c_double),
     ]
 
 
@@ -492,6 +493,10 @@ class Solver:
             setattr(p, k, v)
         self.params = p
         self.nx, self.ny = nx, ny
+        # 3D problems (nz >= 1): arrays (nz, ny, nx), six flux blocks
+        self.nz = p.nz
+        self.shape = (p.nz, ny, nx) if p.nz > 0 else (ny, nx)
+        self.nflux = 6 if p.nz > 0 else 4
         self.ctx = rmrcm_setup(p, K, bc_type)
         self.nseg, self.nlocal = rmrcm_counts(self.ctx)
 
@@ -500,6 +505,8 @@ class Solver:
         for k in ("seg_u", "seg_p"):
             if getattr(prob, k, 0) and k not in kw:
                 kw[k] = getattr(prob, k)
+        if getattr(prob, "nz", 0) and "nz" not in kw:
+            kw["nz"], kw["lz"] = prob.nz, prob.lz
         return cls(prob.nx, prob.ny, prob.K, prob.bc_type, prob.sub_nx, prob.sub_ny,
                    prob.seg, alpha=prob.alpha, lx=prob.lx, ly=prob.ly, **kw)
 
@@ -514,12 +521,12 @@ class Solver:
         rmrcm_sync(self.ctx)
 
     def solve(self, q, bc_value, pressure=None, flux=None):
-        """Returns (pressure (ny, nx), flux (4, ny, nx)); NumPy unless
-        output tensors are given."""
+        """Returns (pressure (ny, nx), flux (4, ny, nx)), in 3D (nz, ny, nx)
+        and (6, nz, ny, nx); NumPy unless output tensors are given."""
         if pressure is None:
-            pressure = np.zeros((self.ny, self.nx))
+            pressure = np.zeros(self.shape)
         if flux is None:
-            flux = np.zeros((4, self.ny, self.nx))
+            flux = np.zeros((self.nflux,) + self.shape)
         rmrcm_solve(self.ctx, q, bc_value, pressure, flux)
         return pressure, flux
 
@@ -535,9 +542,9 @@ class Solver:
         """refactor(K) and solve(q, bc_value) as one unit (a replayed graph
         for FP64 contexts with device arrays); returns (pressure, flux)."""
         if pressure is None:
-            pressure = np.zeros((self.ny, self.nx))
+            pressure = np.zeros(self.shape)
         if flux is None:
-            flux = np.zeros((4, self.ny, self.nx))
+            flux = np.zeros((self.nflux,) + self.shape)
         rmrcm_step(self.ctx, K, q, bc_value, pressure, flux)
         return pressure, flux
 

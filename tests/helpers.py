@@ -34,3 +34,29 @@ def make_problem(nx, ny=None, b=4, by=None, seg=2, alpha=1.0, log_var=1.0,
         q = q + rng.standard_normal((ny, nx)) / (nx * ny)
     return Problem(nx=nx, ny=ny, K=K, q=q, bc_type=t, bc_value=v,
                    sub_nx=b, sub_ny=by, seg=seg, alpha=alpha)
+
+
+def make_problem3d(nx, ny, nz, b=8, seg=2, alpha=1.0, log_var=2.0, lam=0.2, seed=3, bc="we",
+                   source=True, lz=0.5):
+    """A 3D problem (workloads.Problem3D): log-normal field, W/E Dirichlet
+    data (bc="we"), a mixed set (Dirichlet W and T, prescribed fluxes E and
+    S) or all-Neumann five-spot wells (bc="neumann")."""
+    from workloads import Problem3D, dirichlet_we3d, lognormal_grf3d
+    K = lognormal_grf3d(nx, ny, nz, lam, log_var, seed) if log_var > 0 else np.ones((nz, ny, nx))
+    rng = np.random.default_rng(seed + 1)
+    q = rng.standard_normal((nz, ny, nx)) / (nx * ny * nz) if source else np.zeros((nz, ny, nx))
+    t, v = dirichlet_we3d(nx, ny, nz)
+    if bc == "mixed":
+        t[ny * nz:2 * ny * nz] = 0
+        v[ny * nz:2 * ny * nz] = rng.uniform(0.0, 2.0 / (ny * nz), ny * nz)
+        v[2 * ny * nz:2 * ny * nz + nx * nz] = rng.uniform(-0.5, 0.5, nx * nz) / (nx * nz)
+        o = 2 * ny * nz + 2 * nx * nz + nx * ny
+        t[o:] = 1
+        v[o:] = rng.uniform(0.0, 1.0, nx * ny)
+    elif bc == "neumann":
+        t[:] = 0
+        v[:] = 0.0
+        q = np.zeros((nz, ny, nx))
+        q[0, 0, 0], q[-1, -1, -1] = 1.0, -1.0
+    return Problem3D(nx=nx, ny=ny, nz=nz, K=K, q=q, bc_type=t, bc_value=v, sub_nx=b, sub_ny=b, seg=seg,
+                     alpha=alpha, lz=lz)

@@ -155,3 +155,35 @@ def test_general_spaces_plan_and_noalloc():
     lib = load_library()
     p = params(256, 16, 4, seg_u=8)
     assert lib.rmrcm_step_noalloc(ctypes.byref(p), None, None, None, None, None, None, None) == -7
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(nz=-1), -1), (dict(nz=4, lz=0.0), -1), (dict(nz=4, precision=1), -7),
+    (dict(nz=8, sub_nx=16), -7), (dict(nz=4, seg_u=8), -7),
+])
+def test_3d_validation(bad, status):
+    """3D problems (nz >= 1): FP64, MuMM spaces, sub_nx * nz <= 64."""
+    from paper_2009_07965_amd import rmrcm_plan_bytes, RMRCMError
+    p = params(64, 8, 4)
+    p.lz = 1.0
+    for k, v in bad.items():
+        setattr(p, k, v)
+    with pytest.raises(RMRCMError) as ei:
+        rmrcm_plan_bytes(p)
+    assert ei.value.status == status
+
+
+def test_3d_plan_counts_the_columns():
+    """The plan of a 3D problem holds its basis (R columns of the column's
+    cells), factor store (by inverted blocks of (sub_nx nz)^2) and the six
+    flux blocks."""
+    from paper_2009_07965_amd import rmrcm_plan_bytes
+    nx, b, seg, nz = 256, 8, 4, 8
+    p = params(nx, b, seg)
+    p.nz, p.lz = nz, 1.0
+    nsub = (nx // b) ** 2
+    R = 4 * b // seg
+    n = b * b * nz
+    low = 8 * nsub * (R * n + b * (b * nz) ** 2) + 8 * 10 * nx * nx * nz
+    plan = rmrcm_plan_bytes(p)
+    assert low < plan < 2 * low, (plan, low)

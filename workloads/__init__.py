@@ -13,6 +13,7 @@ from .problems import (  # noqa: F401
     Problem3D,
     bc_faces3d,
     dirichlet_we3d,
+    grf3d_problem,
     dirichlet_we,
     five_spot,
     config_problem,

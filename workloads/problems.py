@@ -186,3 +186,20 @@ def dirichlet_we3d(nx: int, ny: int, nz: int, p_west: float = 1.0, p_east: float
     v[:ny * nz] = p_west
     v[ny * nz:2 * ny * nz] = p_east
     return t, v
+
+
+def grf3d_problem(n: int = 512, nz: int = 8, b: int = 8, seg: int = 2, alpha: float = 1e3,
+                  log_var: float = 4.0, lam: float = 0.05, seed: int = 11) -> "Problem3D":
+    """The 3D benchmark workload: an n x n x nz log-normal field (the paper's
+    field type) on [0,1] x [0,1] x [0, nz/n] (cubic cells), columns of
+    b x b x nz cells (no z-division), segments of seg faces (Hbar = H/4 for
+    seg = b/4, one of the paper's two choices), alpha 1e3 (the paper's
+    scaling runs), p = 1 at x = 0 and 0 at x = 1, no flow elsewhere, no
+    source."""
+    from .fields import lognormal_grf3d
+    lz = nz / n
+    K = lognormal_grf3d(n, n, nz, lam, log_var, seed, lz=lz)
+    t, v = dirichlet_we3d(n, n, nz)
+    return Problem3D(nx=n, ny=n, nz=nz, K=K, q=np.zeros((nz, n, n)), bc_type=t, bc_value=v, sub_nx=b,
+                     sub_ny=b, seg=seg, alpha=alpha, lz=lz,
+                     name="grf3d_%dx%dx%d" % (n, n, nz))
