@@ -382,6 +382,74 @@ def measure(prob, precision, steps, warmup, stream, arrays, downscale_reps=0, **
     return out
 
 
+def bench_3d(steps, warmup, stream):
+    """The 3D method (the paper's experiments: seven-point scheme, columns
+    with no z-division, Hbar_z = H_z) on workloads.grf3d_problem: FP64
+    rmrcm_step timed as the 2D line (device arrays, replayed graph), the
+    phases launch by launch, and the local kernel's flop rate.  The local
+    problem of a column is eliminated row block by row block: per row a
+    Gauss-Jordan inverse of the NB x NB block (2 NB^3 flops) and the
+    products with the right-hand sides forward and backward (4 NB^2 ncol)."""
+    import torch
+    from paper_2009_07965_amd import Solver
+    from workloads import grf3d_problem
+    t0 = time.perf_counter()
+    prob = grf3d_problem()
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    K = torch.from_numpy(prob.K).to(dev)
+    bct = torch.from_numpy(prob.bc_type).to(dev)
+    q = torch.from_numpy(prob.q).to(dev)
+    bcv = torch.from_numpy(prob.bc_value).to(dev)
+    p_out = torch.zeros(prob.K.shape, dtype=torch.float64, device=dev)
+    f_out = torch.zeros((6,) + prob.K.shape, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    S = Solver(prob.nx, prob.ny, K, bct, prob.sub_nx, prob.sub_ny, prob.seg, alpha=prob.alpha,
+               nz=prob.nz, lz=prob.lz)
+    try:
+        S.set_stream(stream.cuda_stream)
+        S.autotune()
+        for _ in range(warmup):
+            S.step(K, q, bcv, p_out, f_out)
+        S.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            S.step(K, q, bcv, p_out, f_out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / steps
+        S.sync()
+        S.set_step_graph(False)
+        ph = []
+        for _ in range(3):
+            S.step(K, q, bcv, p_out, f_out)
+            ph.append(S.stats())
+        S.sync()
+    finally:
+        S.close()
+    st = ph[-1]
+    mean = lambda key, sub: float(np.mean([x[key][sub] for x in ph]))   # noqa: E731
+    phases = {"beta": mean("setup_ms", "beta"), "local_setup": mean("setup_ms", "local"),
+              "merges": mean("setup_ms", "merge"), "local_particular": mean("solve_ms", "local"),
+              "top_and_down": mean("solve_ms", "merge") + mean("solve_ms", "down"),
+              "reconstruct": mean("solve_ms", "reconstruct")}
+    nsub = (prob.nx // prob.sub_nx) * (prob.ny // prob.sub_ny)
+    NB = prob.sub_nx * prob.nz
+    R = 2 * (prob.sub_nx + prob.sub_ny) // prob.seg
+    flops = nsub * prob.sub_ny * (2.0 * NB ** 3 + 4.0 * NB * NB * R)
+    achieved = flops / (phases["local_setup"] * 1e-3) / 1e12
+    del K, bct, q, bcv, p_out, f_out
+    torch.cuda.empty_cache()
+    return {"workload": "grf3d: %dx%dx%d log-normal 3D field (corr 0.05, log-var 4), %dx%d columns of "
+                        "%dx%dx%d cells (no z-division), %d-cell segments, alpha %g, %d levels"
+                        % (prob.nx, prob.ny, prob.nz, prob.nx // prob.sub_nx, prob.ny // prob.sub_ny,
+                           prob.sub_nx, prob.sub_ny, prob.nz, prob.seg, prob.alpha, st["levels"]),
+            "cells": prob.ncells, "ms_per_step": ms, "cells_per_s": prob.ncells / (ms * 1e-3),
+            "local_solves": st["local_solves"], "phases_ms": phases, "generate_s": t_gen,
+            "local_kernel": {"kernel": "k_local3d", "bound": "alu", "algorithmic": flops, "unit": "TFLOP/s",
+                             "achieved": achieved, "peak": 78.6, "frac": achieved / 78.6}}
+
+
 def run_workload(cfg, modes, args, stream):
     """Every requested mode on one workload; flux and pressure errors of
     each against the FP64 GPU output."""
@@ -519,6 +587,7 @@ def main():
                     help="run a 512 MiB device copy first (counter calibration)")
     ap.add_argument("--downscale-reps", type=int, default=3,
                     help="timed downscalings of the FP64 solution of the main workload (0: skip)")
+    ap.add_argument("--three-d", type=int, default=1, help="measure the 3D workload beside the main line (0: skip)")
     ap.add_argument("--ensemble", type=int, default=256,
                     help="members of the ensemble batch measured beside the main line (0: skip)")
     args = ap.parse_args()
@@ -585,6 +654,9 @@ def main():
             sec[p2.name]["surrogate"] = li2
     if sec:
         out["secondary"] = sec
+    if args.three_d:
+        print("[bench] 3D workload", file=sys.stderr, flush=True)
+        out["three_d"] = bench_3d(max(3, args.steps // 2), 1, stream)
     if args.ensemble > 0:
         print("[bench] ensemble", file=sys.stderr, flush=True)
         out["ensemble"] = ensemble_bench(args.ensemble, max(3, args.steps // 2), 1)
