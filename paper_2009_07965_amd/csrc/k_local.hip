@@ -2786,7 +2786,7 @@ hipError_t launch_check_beta(rmrcm_ctx* c, double* copy) {
 
 hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want, int do_traces,
                               int basis, int part) {
-    if (c->geo.three_d) return fp32 || mask || !basis ? hipErrorInvalidValue : launch_local3d(c, 1, 1, 0);
+    if (c->geo.three_d) return fp32 || mask || !basis ? hipErrorInvalidValue : launch_local3d(c, 1, 1, part);
     if (part && !local_setup_solves_particular(c, fp32)) return hipErrorInvalidValue;
     if (fp32) {
         RMRCM_BX_SWITCH((setup_bx<4, float>(c, c->P32, mask, want, do_traces, basis, 0)),
@@ -2801,7 +2801,7 @@ hipError_t launch_local_setup(rmrcm_ctx* c, bool fp32, const int* mask, int want
 }
 
 bool local_setup_solves_particular(const rmrcm_ctx* c, bool fp32) {
-    return !fp32 && !c->geo.three_d && (c->geo.bx == 16 || c->geo.bx == 32);
+    return !fp32 && (c->geo.three_d || c->geo.bx == 16 || c->geo.bx == 32);
 }
 
 hipError_t launch_local_particular(rmrcm_ctx* c, bool fp32, const int* mask, int want,

@@ -102,15 +102,28 @@ __device__ inline size_t cell3(const Geo& g, int i, int j, int k) { return ((siz
 
 }  // namespace
 
+// Doubles of the Z buffer: the products' output, and between a row's
+// products the face table of the row (6 NB conductances, 12 NB ints).
+__host__ __device__ inline size_t local3d_zlen(int nb, int ncol) {
+    return (size_t)nb * (ncol > 12 ? ncol : 12);
+}
+
 __host__ __device__ inline size_t local3d_lds(int nb, int ncol) {
-    return sizeof(double) * ((size_t)nb * (nb + 1) + 2 * (size_t)nb * ncol + 4 * (size_t)nb + 2);
+    const size_t nbp = (size_t)(nb + 15) / 16 * 16;
+    return sizeof(double) *
+           ((size_t)nb * (nb + 1) + (size_t)nb * ncol + local3d_zlen(nb, ncol) + 2 * (size_t)nb + 4 * nbp + 2);
 }
 
 // factor = 1: the factorisation (P_j to the factor store), the basis
 // (basis = 1: one column per slot) and the particular solution (part = 1),
 // with their traces.  factor = 0: the particular solution with the stored
-// P_j, and its traces.
-__global__ __launch_bounds__(256) void k_local3d(Geo g, const double* __restrict__ K,
+// P_j, and its traces.  The block, padded with the identity to
+// NBP = 16 TS rows, is held in registers during its factorisation: thread
+// (tr, tc) of the 16 x 16 grid owns the TS x TS tile at rows TS tr.., columns
+// TS tc..; each Gauss-Jordan pivot passes its row and column through LDS
+// (double-buffered: one barrier per pivot).
+template <int TS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_local3d(Geo g, const double* __restrict__ K,
                                                  const int8_t* __restrict__ bct,
                                                  const double* __restrict__ bcv,
                                                  const double* __restrict__ beta,
@@ -128,11 +141,18 @@ __global__ __launch_bounds__(256) void k_local3d(Geo g, const double* __restrict
     double* S = sm3;                       // NB x LS: S_j, then P_j
     double* Y = S + (size_t)NB * LS;       // NB x ncol
     double* Z = Y + (size_t)NB * ncol;     // NB x ncol
-    double* dp = Z + (size_t)NB * ncol;    // couplings D_{j-1}
+    constexpr int NBP = 16 * TS;
+    double* dp = Z + local3d_zlen(NB, ncol);   // couplings D_{j-1}
     double* dn = dp + NB;                  // couplings D_j
-    double* rowp = dn + NB;                // Gauss-Jordan pivot row
-    double* colp = rowp + NB;              // and column
-    double* piv = colp + NB;               // [0]: 1 / pivot, [1]: singular
+    double* rowb = dn + NB;                // Gauss-Jordan pivot rows (two buffers)
+    double* colb = rowb + 2 * NBP;         // and columns
+    double* piv = colb + 2 * NBP;          // [1]: singular
+    double* fc = Z;                        // [6][NB] face conductances of the current row (in Z
+                                           // between the products)
+    int* fk = reinterpret_cast<int*>(fc + 6 * NB);   // [6][NB] kind | slot << 2
+    int* fo = fk + 6 * NB;                 // [6][NB] outer-face index
+    const int tr = tid / 16, tc = tid % 16;
+    double sv[TS][TS];                     // this thread's tile of S_j / P_j
     const int* ss = slotseg + (size_t)sub * R;
     double* Pst = Pstore + (size_t)sub * BY * NB * NB;
     // column c's value at local cell (i, j, k)
@@ -140,88 +160,171 @@ __global__ __launch_bounds__(256) void k_local3d(Geo g, const double* __restrict
         return c < nbas ? Psi + ((size_t)sub * R + c) * n + cell : pbar + (size_t)sub * n + cell;
     };
     if (tid == 0) piv[1] = 0.0;
+    // Block products Out = Sm In (NB x NB times NB x ncol, row strides LS
+    // and ncol): thread (tr, tc) forms rows tr + 16 u (u < TS) of columns
+    // tc + 16 w, each In element read once for its TS rows.
+    auto product = [&](const double* In, auto&& out) {
+        for (int c = tc; c < ncol; c += 16) {
+            double acc[TS];
+#pragma unroll
+            for (int u = 0; u < TS; ++u) acc[u] = 0.0;
+            for (int x = 0; x < NB; ++x) {
+                const double y = In[x * ncol + c];
+#pragma unroll
+                for (int u = 0; u < TS; ++u) {
+                    const int r = tr + 16 * u;
+                    if (r < NB) acc[u] += S[r * LS + x] * y;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TS; ++u) {
+                const int r = tr + 16 * u;
+                if (r < NB) out(r, c, acc[u]);
+            }
+        }
+    };
+    // P_j from the factor store into S
+    auto load_p = [&](int jr) {
+        const double* src = Pst + (size_t)jr * NB * NB;
+#pragma unroll
+        for (int u = 0; u < TS; ++u)
+#pragma unroll
+            for (int v = 0; v < TS; ++v) {
+                const int r = tr + 16 * u, c = tc + 16 * v;
+                if (r < NB && c < NB) S[r * LS + c] = src[r * NB + c];
+            }
+    };
     // ---- forward: factorisation and y_j
     for (int j = 0; j < BY; ++j) {
         if (j > 0) {
-            if (!factor)
-                for (int e = tid; e < NB * NB; e += nt) S[(e / NB) * LS + e % NB] = Pst[(size_t)(j - 1) * NB * NB + e];
+            if (!factor) load_p(j - 1);
             __syncthreads();
-            for (int e = tid; e < NB * ncol; e += nt) {
-                const int r = e / ncol, c = e % ncol;
-                double s = 0.0;
-                for (int u = 0; u < NB; ++u) s += S[r * LS + u] * Y[u * ncol + c];
-                Z[e] = s;
+            // D_{j-1} P_{j-1} y_{j-1}
+            product(Y, [&](int r, int c, double v) { Z[r * ncol + c] = dp[r] * v; });
+        }
+        __syncthreads();
+        // right-hand sides of row j: the coupled term, then each cell's
+        // boundary faces (Robin faces of the basis columns, outer data and
+        // the source of the particular column) by the cell's own thread;
+        // D_j to the next row
+        for (int e = tid; e < NB * ncol; e += nt) Y[e] = j > 0 ? Z[e] : 0.0;
+        __syncthreads();
+        // the faces of row j, one (cell, side) per thread
+        for (int w = tid; w < 6 * NB; w += nt) {
+            const int side = w / NB, r = w - side * NB, k = r / g.bx, i = r - k * g.bx;
+            const Face3 f = face3(g, K, bct, beta, ss, I, J, i, j, k, side);
+            fc[w] = f.cond;
+            fk[w] = f.kind | (f.slot << 2);
+            fo[w] = f.of;
+        }
+        __syncthreads();
+        for (int r = tid; r < NB; r += nt) {
+            double* yr = Y + r * ncol;
+            if (j < BY - 1) dn[r] = fc[3 * NB + r];
+            for (int side = 0; side < 6; ++side) {
+                const int kd = fk[side * NB + r];
+                if ((kd & 3) == 1) {
+                    if ((kd >> 2) < nbas) yr[kd >> 2] += fc[side * NB + r];
+                } else if ((kd & 3) == 2 && ncol > nbas) {
+                    const int of = fo[side * NB + r];
+                    yr[nbas] += bct[of] == RMRCM_BC_DIRICHLET ? fc[side * NB + r] * bcv[of] : -bcv[of];
+                }
+            }
+            if (ncol > nbas && q) {
+                const int k = r / g.bx, i = r - k * g.bx;
+                yr[nbas] += q[((size_t)k * g.ny + J * BY + j) * g.nx + I * g.bx + i];
             }
         }
         __syncthreads();
-        // right-hand sides of row j (+ D_{j-1} P_{j-1} y_{j-1}) and D_j
-        for (int e = tid; e < NB * ncol; e += nt) {
-            const int r = e / ncol, c = e % ncol, k = r / g.bx, i = r % g.bx;
-            double b = 0.0;
-            for (int side = 0; side < 6; ++side) {
-                if (side == 3 && j < BY - 1 && c == 0) {
-                    // coupling to row j + 1 (an interior face inside the column)
-                    const Face3 f = face3(g, K, bct, beta, ss, I, J, i, j, k, 3);
-                    dn[r] = f.cond;
-                }
-                if ((side == 2 && j > 0) || (side == 3 && j < BY - 1)) continue;
-                if ((side == 0 && i > 0) || (side == 1 && i < g.bx - 1)) continue;
-                if ((side == 4 && k > 0) || (side == 5 && k < g.nz - 1)) continue;
-                const Face3 f = face3(g, K, bct, beta, ss, I, J, i, j, k, side);
-                if (c < nbas) {
-                    if (f.kind == 1 && f.slot == c) b += f.cond;
-                } else if (f.kind == 2) {
-                    b += bct[f.of] == RMRCM_BC_DIRICHLET ? f.cond * bcv[f.of] : -bcv[f.of];
-                }
-            }
-            if (c >= nbas && q) b += q[((size_t)k * g.ny + J * BY + j) * g.nx + I * g.bx + i];
-            if (j > 0) b += dp[r] * Z[e];
-            Y[e] = b;
-            *col(c, cell3(g, i, j, k)) = b;     // y_j, overwritten by x_j in the backward pass
+        // y_j to the outputs (overwritten by x_j in the backward pass)
+        for (int r = tr; r < NB; r += 16) {
+            const int k = r / g.bx, i = r - k * g.bx;
+            for (int c = tc; c < ncol; c += 16) *col(c, cell3(g, i, j, k)) = Y[r * ncol + c];
         }
         if (factor) {
+            // A_j into LDS: zero, then each row's diagonal and x and z
+            // couplings by its thread (P_{j-1} in S is no longer needed)
+            for (int e = tid; e < NB * LS; e += nt) S[e] = 0.0;
             __syncthreads();
-            // S_j = A_j - D_{j-1} P_{j-1} D_{j-1} (P_{j-1} in S)
-            for (int e = tid; e < NB * NB; e += nt) {
-                const int r = e / NB, c = e % NB;
-                const int k = r / g.bx, i = r % g.bx, kc = c / g.bx, ic = c % g.bx;
-                double a = 0.0;
-                if (r == c) {
-                    for (int side = 0; side < 6; ++side) a += face3(g, K, bct, beta, ss, I, J, i, j, k, side).cond;
-                } else if (k == kc && (ic == i + 1 || ic == i - 1)) {
-                    a = -face3(g, K, bct, beta, ss, I, J, i, j, k, ic > i ? 1 : 0).cond;
-                } else if (i == ic && (kc == k + 1 || kc == k - 1)) {
-                    a = -face3(g, K, bct, beta, ss, I, J, i, j, k, kc > k ? 5 : 4).cond;
-                }
-                S[r * LS + c] = j > 0 ? a - dp[r] * S[r * LS + c] * dp[c] : a;
-            }
-            __syncthreads();
-            // P_j = S_j^-1, Gauss-Jordan in place
-            for (int p = 0; p < NB; ++p) {
-                if (tid == 0) {
-                    double d = S[p * LS + p];
-                    if (!(d > 0.0)) {
-                        piv[1] = 1.0;
-                        d = 1.0;
+            for (int r = tid; r < NB; r += nt) {
+                double d = 0.0;
+                for (int side = 0; side < 6; ++side) {
+                    const double cv = fc[side * NB + r];
+                    d += cv;
+                    if ((fk[side * NB + r] & 3) == 0 && side != 2 && side != 3) {
+                        const int rc = side == 0 ? r - 1 : side == 1 ? r + 1 : side == 4 ? r - g.bx : r + g.bx;
+                        S[r * LS + rc] = -cv;
                     }
-                    piv[0] = 1.0 / d;
                 }
-                __syncthreads();
-                const double inv = piv[0];
-                for (int u = tid; u < NB; u += nt) {
-                    rowp[u] = u == p ? inv : S[p * LS + u] * inv;
-                    colp[u] = S[u * LS + p];
-                }
-                __syncthreads();
-                for (int e = tid; e < NB * NB; e += nt) {
-                    const int r = e / NB, c = e % NB;
-                    if (r == p) S[r * LS + c] = rowp[c];
-                    else if (c == p) S[r * LS + c] = -colp[r] * inv;
-                    else S[r * LS + c] -= colp[r] * rowp[c];
-                }
-                __syncthreads();
+                S[r * LS + r] = d;
             }
-            for (int e = tid; e < NB * NB; e += nt) Pst[(size_t)j * NB * NB + e] = S[(e / NB) * LS + e % NB];
+            __syncthreads();
+            // S_j = A_j - D_{j-1} P_{j-1} D_{j-1} on the tiles (P_{j-1} in the registers)
+#pragma unroll
+            for (int u = 0; u < TS; ++u)
+#pragma unroll
+                for (int v = 0; v < TS; ++v) {
+                    const int r = TS * tr + u, c = TS * tc + v;
+                    double a = r == c ? 1.0 : 0.0;
+                    if (r < NB && c < NB) {
+                        a = S[r * LS + c];
+                        if (j > 0) a -= dp[r] * sv[u][v] * dp[c];
+                    }
+                    sv[u][v] = a;
+                }
+            // P_j = S_j^-1, Gauss-Jordan without pivoting on the tiles
+            for (int p = 0; p < NBP; ++p) {
+                double* rp = rowb + (p & 1) * NBP;
+                double* cp = colb + (p & 1) * NBP;
+                const int pt = p / TS, pu = p % TS;
+                if (tr == pt) {
+#pragma unroll
+                    for (int v = 0; v < TS; ++v) rp[TS * tc + v] = sv[pu][v];
+                }
+                if (tc == pt) {
+#pragma unroll
+                    for (int u = 0; u < TS; ++u) cp[TS * tr + u] = sv[u][pu];
+                }
+                __syncthreads();
+                double d = rp[p];
+                if (!(d > 0.0)) {
+                    if (tid == 0) piv[1] = 1.0;
+                    d = 1.0;
+                }
+                const double inv = 1.0 / d;
+                // every element: S -= col_p (row_p / d); then the pivot's
+                // row (row_p / d), column (-col_p / d) and entry (1 / d)
+                double rv[TS], cv[TS];
+#pragma unroll
+                for (int v = 0; v < TS; ++v) rv[v] = rp[TS * tc + v] * inv;
+#pragma unroll
+                for (int u = 0; u < TS; ++u) cv[u] = cp[TS * tr + u];
+#pragma unroll
+                for (int u = 0; u < TS; ++u)
+#pragma unroll
+                    for (int v = 0; v < TS; ++v) sv[u][v] = fma(-cv[u], rv[v], sv[u][v]);
+                if (tr == pt) {
+#pragma unroll
+                    for (int v = 0; v < TS; ++v) sv[pu][v] = rv[v];
+                }
+                if (tc == pt) {
+#pragma unroll
+                    for (int u = 0; u < TS; ++u) sv[u][pu] = -cv[u] * inv;
+                }
+                if (tr == pt && tc == pt) sv[pu][pu] = inv;
+            }
+            __syncthreads();
+            // P_j to LDS (the products) and to the factor store
+#pragma unroll
+            for (int u = 0; u < TS; ++u)
+#pragma unroll
+                for (int v = 0; v < TS; ++v) {
+                    const int r = TS * tr + u, c = TS * tc + v;
+                    if (r < NB && c < NB) {
+                        S[r * LS + c] = sv[u][v];
+                        Pst[(size_t)j * NB * NB + r * NB + c] = sv[u][v];
+                    }
+                }
         }
         __syncthreads();
         for (int r = tid; r < NB; r += nt) dp[r] = dn[r];
@@ -229,25 +332,27 @@ __global__ __launch_bounds__(256) void k_local3d(Geo g, const double* __restrict
     }
     // ---- backward: x_last = P_last y_last; x_j = P_j (y_j + D_j x_{j+1})
     for (int j = BY - 1; j >= 0; --j) {
-        if (!factor || j < BY - 1)
-            for (int e = tid; e < NB * NB; e += nt) S[(e / NB) * LS + e % NB] = Pst[(size_t)j * NB * NB + e];
+        if (!factor || j < BY - 1) load_p(j);
         if (j < BY - 1) {
-            for (int e = tid; e < NB * ncol; e += nt) {
-                const int r = e / ncol, c = e % ncol, k = r / g.bx, i = r % g.bx;
-                const double dj = face3(g, K, bct, beta, ss, I, J, i, j, k, 3).cond;
-                Z[e] = *col(c, cell3(g, i, j, k)) + dj * Y[e];
+            for (int r = tid; r < NB; r += nt) {
+                const int k = r / g.bx, i = r - k * g.bx;
+                dn[r] = face3(g, K, bct, beta, ss, I, J, i, j, k, 3).cond;
+            }
+            __syncthreads();
+            for (int r = tr; r < NB; r += 16) {
+                const int k = r / g.bx, i = r - k * g.bx;
+                for (int c = tc; c < ncol; c += 16)
+                    Z[r * ncol + c] = *col(c, cell3(g, i, j, k)) + dn[r] * Y[r * ncol + c];
             }
         } else {
             for (int e = tid; e < NB * ncol; e += nt) Z[e] = Y[e];
         }
         __syncthreads();
-        for (int e = tid; e < NB * ncol; e += nt) {
-            const int r = e / ncol, c = e % ncol;
-            double s = 0.0;
-            for (int u = 0; u < NB; ++u) s += S[r * LS + u] * Z[u * ncol + c];
-            Y[e] = s;
-            *col(c, cell3(g, r % g.bx, j, r / g.bx)) = s;
-        }
+        product(Z, [&](int r, int c, double v) {
+            Y[r * ncol + c] = v;
+            const int k = r / g.bx;
+            *col(c, cell3(g, r - k * g.bx, j, k)) = v;
+        });
         __syncthreads();
     }
     if (tid == 0 && piv[1] != 0.0) atomicOr(&flags[FLAG_LOCAL_SINGULAR], 1);
@@ -339,17 +444,29 @@ __global__ __launch_bounds__(256) void k_recon3d_f(Geo g, const double* __restri
     }
 }
 
-hipError_t launch_local3d(rmrcm_ctx* c, int factor, int basis, int part) {
+template <int TS>
+static hipError_t local3d_ts(rmrcm_ctx* c, int factor, int basis, int part) {
     const Level& L = c->levels[c->D];
     const int NB = c->geo.bx * c->geo.nz, ncol = (basis ? L.nslot : 0) + (part ? 1 : 0);
     const size_t lds = local3d_lds(NB, ncol);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)k_local3d, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e =
+        hipFuncSetAttribute((const void*)k_local3d<TS>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_local3d, dim3(c->geo.mx * c->geo.my), dim3(256), lds, c->stream, c->geo, c->K, c->bct,
-                       c->bcv, c->beta, L.slotseg, L.nslot, c->Pstore, c->Psi, c->pbar, c->q, L.T, L.ld, c->flags,
-                       factor, basis, part);
+    hipLaunchKernelGGL(k_local3d<TS>, dim3(c->geo.mx * c->geo.my), dim3(256), lds, c->stream, c->geo, c->K,
+                       c->bct, c->bcv, c->beta, L.slotseg, L.nslot, c->Pstore, c->Psi, c->pbar, c->q, L.T, L.ld,
+                       c->flags, factor, basis, part);
     return hipGetLastError();
+}
+
+hipError_t launch_local3d(rmrcm_ctx* c, int factor, int basis, int part) {
+    switch ((c->geo.bx * c->geo.nz + 15) / 16) {
+        case 1: return local3d_ts<1>(c, factor, basis, part);
+        case 2: return local3d_ts<2>(c, factor, basis, part);
+        case 3: return local3d_ts<3>(c, factor, basis, part);
+        case 4: return local3d_ts<4>(c, factor, basis, part);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_reconstruct3d(rmrcm_ctx* c) {
