@@ -588,6 +588,8 @@ def main():
     ap.add_argument("--downscale-reps", type=int, default=3,
                     help="timed downscalings of the FP64 solution of the main workload (0: skip)")
     ap.add_argument("--three-d", type=int, default=1, help="measure the 3D workload beside the main line (0: skip)")
+    ap.add_argument("--three-d-only", action="store_true",
+                    help="only the 3D workload's measurement (one JSON object; for profiling its kernels)")
     ap.add_argument("--ensemble", type=int, default=256,
                     help="members of the ensemble batch measured beside the main line (0: skip)")
     args = ap.parse_args()
@@ -596,6 +598,9 @@ def main():
               "design-only); got --gpus %d" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.three_d_only:
+        print(json.dumps(bench_3d(max(3, args.steps // 2), 1, torch.cuda.Stream())), flush=True)
+        return
     if args.fp64_only:
         args.modes, args.secondary = "fp64", ""
     stream = torch.cuda.Stream()     # a caller stream: no host waits between steps
