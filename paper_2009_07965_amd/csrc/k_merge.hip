@@ -175,7 +175,12 @@ __device__ inline double rcp_refined(double d) {
 // M_KK, lanes 16-31 the identity; eliminating below each pivot (multipliers
 // from the pivot row, by symmetry) leaves L^{-1} in lanes 16-31.  kmax: the
 // rows and columns from kmax on are identity ones, whose elimination steps
-// change nothing and are skipped.
+// change nothing and are skipped.  EARLY: row k of the result is stored as
+// soon as pivot k is done (it is final then), so no reciprocal is held to
+// the end: fewer vector registers, but where the caller's own registers are
+// many the compiler then spills scalar ones, so only the fused small merge
+// takes it; both forms store the same numbers.
+template <bool EARLY = false>
 __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double* lt, double* ls,
                                                  int* bad, int kmax = 16) {
     typedef QdM<16> Q;
@@ -190,6 +195,10 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
     for (int k = 0; k < 16; ++k) {
         if (k >= kmax) {
             rd[k] = 1.0;
+            if (EARLY && icol) {
+                lt[li * Q::LTL + k] = a[k];
+                ls[li * Q::LTL + k] = a[k];
+            }
             continue;
         }
         // a zero or non-finite pivot is flagged (the inverse is then not
@@ -200,9 +209,13 @@ __device__ __forceinline__ v4d qd_pivot_inverse(const double* cpk, int K, double
         const double lrow = a[k] * rd[k];          // row k of L^T
 #pragma unroll
         for (int i = k + 1; i < 16; ++i) a[i] = fma(-readlane_d(lrow, i), a[k], a[i]);
+        if (EARLY && icol) {
+            lt[li * Q::LTL + k] = a[k];
+            ls[li * Q::LTL + k] = lrow;
+        }
     }
     if (sing && lane == 0) *bad = 1;
-    if (icol) {
+    if (!EARLY && icol) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             lt[li * Q::LTL + i] = a[i];             // row c = column c of L^{-1}
@@ -886,11 +899,18 @@ __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int
         double av1[KS] = {}, dr1[4] = {};
         int ka1 = -1;
         if (ot + ots < nrt) load_rows(ot + ots, av1, dr1, ka1);
+        // a child's half is skipped when none of the tile's rows is its
+        // (all-zero A rows: the sum is unchanged bit for bit); most tiles
+        // lie on one child's sides
         v4d acc = {0.0, 0.0, 0.0, 0.0};
+        if (__ballot(ka0 == 0) != 0ull) {
 #pragma unroll
-        for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 0 ? av0[q] : 0.0, xb[0][q], acc);
+            for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 0 ? av0[q] : 0.0, xb[0][q], acc);
+        }
+        if (__ballot(ka0 == 1) != 0ull) {
 #pragma unroll
-        for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 1 ? av0[q] : 0.0, xb[1][q], acc);
+            for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 1 ? av0[q] : 0.0, xb[1][q], acc);
+        }
         if (cin) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -1067,12 +1087,14 @@ __global__ __launch_bounds__(256) void k_qd_trace_mfma(MergeArgs a, int col0, in
 // and factors them in registers (the pivot chains stopping at g); the other
 // waves stage in LDS the right-hand sides of every column (r1 + r2 and
 // r2 - r1) and the child trace entries of every parent slot against gamma
-// (the left operand of the trace product); every wave meanwhile loads the
-// direct terms of its columns' parent traces.  After the factorisation each
-// wave applies it to its column tile in registers (a result in the
-// accumulator layout is the next product's B operand), writes X and forms
-// the parent traces of its columns.  Layouts as in the tiers above:
-// accumulator lane l, register v = row l/16 + 4v, column l%16.
+// (the left operand of the trace product).  After the factorisation each
+// wave issues the loads of the direct terms of its columns' parent traces
+// (held for at most 16 MAXRT parent slots; not live during the pivot
+// chains, whose registers bound the occupancy), applies the factorisation
+// to its column tile in registers (a result in the accumulator layout is
+// the next product's B operand), writes X and forms the parent traces of
+// its columns.  Layouts as in the tiers above: accumulator lane l, register
+// v = row l/16 + 4v, column l%16.
 __host__ __device__ inline int small_cw(int ncol) { return 16 * ((ncol + 15) / 16) + 1; }
 __host__ __device__ inline int small_ns16(int nslot) { return 16 * ((nslot + 15) / 16); }
 __host__ __device__ inline int small_waves(int ncol) { return max(4, (ncol + 15) / 16); }
@@ -1081,6 +1103,7 @@ __host__ __device__ inline size_t small_lds_bytes(int ncol, int nslot) {
     return nd * sizeof(double) + (size_t)(48 + small_ns16(nslot) + 1) * sizeof(int);
 }
 
+template <int MAXRT>
 __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
     RMRCM_RUN_GUARD(a.run);
     extern __shared__ double sm[];
@@ -1120,11 +1143,11 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
     // (the particular column: T_k's own)
     const int col = 16 * w + li;
     const bool cin = col < ncol;
-    double dv[8][4];
+    double dv[MAXRT][4];
     auto load_direct = [&]() {
         const int pc = (cin && col < nslot) ? pms[col] : -1;
 #pragma unroll
-        for (int ot = 0; ot < 8; ++ot)
+        for (int ot = 0; ot < MAXRT; ++ot)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int o = 16 * ot + lk + 4 * v;
@@ -1155,7 +1178,6 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
         }
         const int eg = ge[li];
         const double wl = li < g ? a.seglen[eg] / (2.0 * a.beta[eg]) : 0.0;
-        load_direct();
         v4d Dm, Nm, Bm;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -1168,7 +1190,7 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
             bl[i * 17 + li] = Bm[v];
         }
         wave_lds_sync();
-        const v4d Dinv = qd_pivot_inverse(cp, 0, lt, ls, bad, g);
+        const v4d Dinv = qd_pivot_inverse<true>(cp, 0, lt, ls, bad, g);
 #pragma unroll
         for (int v = 0; v < 4; ++v) dl[(lk + 4 * v) * 17 + li] = Dinv[v];
         wave_lds_sync();
@@ -1187,7 +1209,7 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
             cp[i * 17 + li] = in ? S[v] : (i == li ? 1.0 : 0.0);
         }
         wave_lds_sync();
-        const v4d Sinv = qd_pivot_inverse(cp, 0, lt, ls, bad, g);
+        const v4d Sinv = qd_pivot_inverse<true>(cp, 0, lt, ls, bad, g);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = lk + 4 * v;
@@ -1202,7 +1224,6 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
         }
         if (lane == 0 && *bad) atomicOr(&a.flags[FLAG_MERGE_SINGULAR], 1);
     } else {
-        load_direct();
         // right-hand sides of the columns, four loads in flight per thread
         const int t2 = tid - 64, ns = nt - 64, CC = 16 * CT;
         for (int t0 = 0; t0 < 16 * CC; t0 += 4 * ns) {
@@ -1265,6 +1286,7 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
         SA[s] = sl[e];
         EA[s] = el[e];
     }
+    load_direct();
     // t = D^{-1} (r2 - r1), u = r1 + r2 - B t, s = S^{-1} u, d = t - E s
     v4d t = {0.0, 0.0, 0.0, 0.0}, u, sv = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1293,7 +1315,7 @@ __global__ __launch_bounds__(512) void k_qd_small(MergeArgs a, int ncol) {
     // T_p[o, col] = direct + sum_i A_1[o][i] X_1[i][col] + A_2[o][i] X_2[i][col]
     double* Tp = a.Tp + (size_t)node * nslot * a.ld;
 #pragma unroll
-    for (int ot = 0; ot < 8; ++ot) {
+    for (int ot = 0; ot < MAXRT; ++ot) {
         if (ot >= NRT) break;
         const int o = 16 * ot + li;
         const int ko = o < nslot ? (pms[o] >> 24) : -1;
@@ -1471,7 +1493,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 // rows (rflag[z][tile row]) or columns (cflag[z][tile column]) are known to
 // be zero in A or B: the inactive boundary slots of a merge, whose trace
 // rows and columns are zero; such a tile is left as it is, or zeroed when
-// beta = 0.
+// beta = 0.  With kpm, the parent traces' product (A: row o = parent slot o,
+// columns [0, kh) the first child's gamma segments, [kh, 2 kh) the
+// second's, zero outside the half of the child that owns the slot): the
+// workgroup reads its rows' owners from the slot map and runs K only over
+// the halves of the children present (the skipped products are exact
+// zeros, so the sums are those of the full range).
 struct GemmNN {
     int m, n, k;
     const double* A;
@@ -1486,9 +1513,65 @@ struct GemmNN {
     int rfs, cfs;
     int skr0, skr1;               // row tiles [skr0, skr1) skipped in every batch entry
     const int* run;
+    const int* kpm;               // slot map (owner child in bits 24..) or null
+    int kh;                       // gamma segments of one child (K = 2 kh) with kpm
 };
 
 constexpr int kGemmKT = 32;
+
+// One 64 x 64 tile of the product A B into acc (wave w: rows 32 (w / 2)..,
+// columns 32 (w % 2).., 2 x 2 matrix-core tiles): Ab points at the tile's
+// first row of A (row stride lda, mr rows valid), Bb at its first column of B
+// (row stride ldb, nc columns valid), K over [kbeg, kend) in steps of
+// kGemmKT through the LDS tiles As and Bs, the next step's operands loaded
+// into registers while the current step's products run.  Entries outside
+// the valid rows, columns and K range are zero.
+__device__ __forceinline__ void nn_tile(const double* __restrict__ Ab, long long lda, int mr,
+                                        const double* __restrict__ Bb, long long ldb, int nc, int kbeg,
+                                        int kend, double* As, double* Bs, v4d (&acc)[2][2]) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    // loader roles: A rows (tid / 32) + 8 q, column tid % 32; B rows
+    // (tid / 64) + 4 q, column tid % 64
+    const int ar = tid >> 5, ak = tid & 31, br = tid >> 6, bc = tid & 63;
+    double ra[8], rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = ar + 8 * q, kk = k0 + ak;
+            ra[q] = (r < mr && kk < kend) ? Ab[(size_t)r * lda + kk] : 0.0;
+            const int kb = k0 + br + 4 * q;
+            rb[q] = (kb < kend && bc < nc) ? Bb[(size_t)kb * ldb + bc] : 0.0;
+        }
+    };
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += kGemmKT) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            As[(ar + 8 * q) * (kGemmKT + 1) + ak] = ra[q];
+            Bs[(br + 4 * q) * 65 + bc] = rb[q];
+        }
+        __syncthreads();
+        if (k0 + kGemmKT < kend) load(k0 + kGemmKT);
+#pragma unroll
+        for (int s4 = 0; s4 < kGemmKT / 4; ++s4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[(wr + 16 * a + li) * (kGemmKT + 1) + 4 * s4 + lk];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[(4 * s4 + lk) * 65 + wc + 16 * b + li];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+}
 
 __global__ __launch_bounds__(256) void k_gemm_nn_f64(GemmNN g) {
     RMRCM_RUN_GUARD(g.run);
@@ -1511,47 +1594,16 @@ __global__ __launch_bounds__(256) void k_gemm_nn_f64(GemmNN g) {
     const double* A = g.A + (size_t)z * g.sa;
     const double* B = g.B + (size_t)z * g.sb;
     const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
-    // loader roles: A rows (tid / 32) + 8 q, column tid % 32; B rows
-    // (tid / 64) + 4 q, column tid % 64
-    const int ar = tid >> 5, ak = tid & 31, br = tid >> 6, bc = tid & 63;
-    double ra[8], rb[8];
-    auto load = [&](int k0) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int r = bm + ar + 8 * q, kk = k0 + ak;
-            ra[q] = (r < g.m && kk < g.k) ? A[(size_t)r * g.lda + kk] : 0.0;
-            const int kb = k0 + br + 4 * q, cc = bn + bc;
-            rb[q] = (kb < g.k && cc < g.n) ? B[(size_t)kb * g.ldb + cc] : 0.0;
-        }
-    };
-    v4d acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-    load(0);
-    for (int k0 = 0; k0 < g.k; k0 += kGemmKT) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            As[(ar + 8 * q) * (kGemmKT + 1) + ak] = ra[q];
-            Bs[(br + 4 * q) * 65 + bc] = rb[q];
-        }
-        __syncthreads();
-        if (k0 + kGemmKT < g.k) load(k0 + kGemmKT);
-#pragma unroll
-        for (int s4 = 0; s4 < kGemmKT / 4; ++s4) {
-            double av[2], bv[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[(wr + 16 * a + li) * (kGemmKT + 1) + 4 * s4 + lk];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[(4 * s4 + lk) * 65 + wc + 16 * b + li];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = mfma_f64(av[a], bv[b], acc[a][b]);
-        }
-        __syncthreads();
+    int kbeg = 0, kend = g.k;
+    if (g.kpm) {
+        const int r = bm + (tid & 63);
+        const int own = (tid < 64 && r < g.m) ? (g.kpm[r] >> 24) : -1;
+        const int has0 = __syncthreads_or(own == 0), has1 = __syncthreads_or(own == 1);
+        if (!has0) kbeg = g.kh;
+        if (!has1) kend = g.kh;
     }
+    v4d acc[2][2];
+    nn_tile(A + (size_t)bm * g.lda, g.lda, g.m - bm, B + bn, g.ldb, g.n - bn, kbeg, kend, As, Bs, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1570,11 +1622,12 @@ static hipError_t gemm(rmrcm_ctx* c, int batch, int m, int n, int k, int ta, con
                        long long lda, long long sa, int tb, const double* B, long long ldb, long long sb,
                        double* C, long long ldc, long long sc, double alpha, double beta,
                        const unsigned char* rflag = nullptr, int rfs = 0,
-                       const unsigned char* cflag = nullptr, int cfs = 0, int skr0 = 0, int skr1 = 0) {
+                       const unsigned char* cflag = nullptr, int cfs = 0, int skr0 = 0, int skr1 = 0,
+                       const int* kpm = nullptr, int kh = 0) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if (!ta && !tb) {
         GemmNN g{m, n, k, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta, rflag, cflag, rfs, cfs, skr0, skr1,
-                 c->run_ptr};
+                 c->run_ptr, kpm, kh};
         hipLaunchKernelGGL(k_gemm_nn_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
         return hipGetLastError();
     }
@@ -1583,10 +1636,11 @@ static hipError_t gemm(rmrcm_ctx* c, int batch, int m, int n, int k, int ta, con
     return hipGetLastError();
 }
 
-// In-place inverse of the n x n block (n <= 128) at X (row stride ld, batch
-// stride sx), blocked Gauss-Jordan in registers as in k_qd_factor_mfma.
-__global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long long ld, long long sx,
-                                                                  int n, int* flags) {
+// Inverse of the n x n block (n <= 128) at src (row stride lds) into dst
+// (row stride ldd; dst = src: in place) by one workgroup of QdM<128>::NT
+// threads, blocked Gauss-Jordan in registers as in k_qd_factor_mfma.
+__device__ __forceinline__ void invert_block128(const double* src, long long lds, double* dst, long long ldd,
+                                                int n, int* flags) {
     typedef QdM<128> Q;
     constexpr int T = Q::T;
     __shared__ double cp[2 * 128 * Q::CPL];
@@ -1594,7 +1648,6 @@ __global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long
     __shared__ double pt[2 * 16 * 17];
     __shared__ int bad;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
-    double* Xb = X + (size_t)blockIdx.x * sx;
     if (tid == 0) bad = 0;
     const int j = 16 * w + li;
     v4d m[T];
@@ -1603,7 +1656,7 @@ __global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = 16 * I + lk + 4 * v;
-            m[I][v] = (i < n && j < n) ? Xb[(size_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+            m[I][v] = (i < n && j < n) ? src[(size_t)i * lds + j] : (i == j ? 1.0 : 0.0);
         }
     __syncthreads();
     double* lt = lts + 2 * w * 16 * Q::LTL;
@@ -1613,9 +1666,17 @@ __global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = 16 * I + lk + 4 * v;
-            if (i < n && j < n) Xb[(size_t)i * ld + j] = m[I][v];
+            if (i < n && j < n) dst[(size_t)i * ldd + j] = m[I][v];
         }
     if (tid == 0 && bad) atomicOr(&flags[FLAG_MERGE_SINGULAR], 1);
+}
+
+// In-place inverse of the n x n block (n <= 128) at X (row stride ld, batch
+// stride sx).
+__global__ __launch_bounds__(QdM<128>::NT) void k_qd_invert_mfma(double* X, long long ld, long long sx,
+                                                                  int n, int* flags) {
+    double* Xb = X + (size_t)blockIdx.x * sx;
+    invert_block128(Xb, ld, Xb, ld, n, flags);
 }
 
 // D, B and N of every merge of the level (one thread per entry; D to the D
@@ -1677,33 +1738,65 @@ __global__ __launch_bounds__(256) void k_qd_big_fix(double* X, long long ld, lon
 __host__ inline size_t big_inv_work(int n) { return 2 * 128 * (size_t)n + 128 * 128; }
 
 // Gauss-Jordan step at columns k0 .. k0 + kb - 1 of the n x n block X (row
-// stride ld, merge stride sx): the column panel C = X[:, k0:k0+kb] and the
-// pivot block Pw = X[k0:k0+kb, k0:k0+kb] into the merge's scratch.
-__global__ __launch_bounds__(256) void k_gj_prep(const double* X, long long ld, long long sx, int n,
-                                                 int k0, int kb, double* W, long long sw) {
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (long long)n * kb) return;
-    const int i = (int)(t / kb), j = (int)(t % kb);
+// stride ld, merge stride sx), first launch: workgroup 0 of each merge
+// inverts the pivot block X[k0:k0+kb, k0:k0+kb] into Pw (row stride kb),
+// the others copy the column panel C = X[:, k0:k0+kb] into the merge's
+// scratch (row stride kb).
+__global__ __launch_bounds__(QdM<128>::NT) void k_gj_pivot(const double* X, long long ld, long long sx, int n,
+                                                            int k0, int kb, double* W, long long sw, int* flags) {
     const double* Xb = X + (size_t)blockIdx.y * sx;
     double* C = W + (size_t)blockIdx.y * sw;
     double* Pw = C + (size_t)n * 128;
-    const double v = Xb[(size_t)i * ld + k0 + j];
-    C[(size_t)i * kb + j] = v;
-    if (i >= k0 && i < k0 + kb) Pw[(size_t)(i - k0) * kb + j] = v;
+    if (blockIdx.x == 0) {
+        invert_block128(Xb + (size_t)k0 * ld + k0, ld, Pw, kb, kb, flags);
+        return;
+    }
+    const long long t = (long long)(blockIdx.x - 1) * QdM<128>::NT + threadIdx.x;
+    if (t >= (long long)n * kb) return;
+    const int i = (int)(t / kb), j = (int)(t % kb);
+    C[(size_t)i * kb + j] = Xb[(size_t)i * ld + k0 + j];
 }
 
-// End of the step: row panel K of X = R (the pivot rows times the inverted
-// pivot block), its diagonal block = the inverted pivot block.
-__global__ __launch_bounds__(256) void k_gj_finish(double* X, long long ld, long long sx, int n, int k0,
+// Last launch of the step (after R = Pw X[k0:k0+kb, :] into Rw, row stride
+// n), one 64 x 64 tile of X per workgroup: the panel's rows take R and the
+// pivot block Pw; the panel's columns -C Pw; every other tile X - C R.  The
+// products are those of k_gemm_nn_f64 on the same operands.
+__global__ __launch_bounds__(256) void k_gj_update(double* X, long long ld, long long sx, int n, int k0,
                                                    int kb, const double* W, long long sw) {
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= (long long)n * kb) return;
-    const int i = (int)(t / n), j = (int)(t % n);
-    double* Xb = X + (size_t)blockIdx.y * sx;
-    const double* Pw = W + (size_t)blockIdx.y * sw + (size_t)n * 128;
+    __shared__ double As[64 * (kGemmKT + 1)];
+    __shared__ double Bs[kGemmKT * 65];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+    double* Xb = X + (size_t)blockIdx.z * sx;
+    const double* Cw = W + (size_t)blockIdx.z * sw;
+    const double* Pw = Cw + (size_t)n * 128;
     const double* Rw = Pw + 128 * 128;
-    Xb[(size_t)(k0 + i) * ld + j] =
-        (j >= k0 && j < k0 + kb) ? Pw[(size_t)i * kb + (j - k0)] : Rw[(size_t)i * n + j];
+    if (bm >= k0 && bm < k0 + kb) {
+        for (int t = tid; t < 64 * 64; t += 256) {
+            const int r = bm + t / 64, cc = bn + t % 64;
+            if (r < k0 + kb && cc < n)
+                Xb[(size_t)r * ld + cc] = (cc >= k0 && cc < k0 + kb) ? Pw[(size_t)(r - k0) * kb + (cc - k0)]
+                                                                      : Rw[(size_t)(r - k0) * n + cc];
+        }
+        return;
+    }
+    const bool colk = bn >= k0 && bn < k0 + kb;
+    v4d acc[2][2];
+    if (colk) nn_tile(Cw + (size_t)bm * kb, kb, n - bm, Pw + (bn - k0), kb, k0 + kb - bn, 0, kb, As, Bs, acc);
+    else nn_tile(Cw + (size_t)bm * kb, kb, n - bm, Rw + bn, n, n - bn, 0, kb, As, Bs, acc);
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = bm + wr + 16 * a + lk + 4 * v, cc = bn + wc + 16 * b + li;
+                if (r < n && cc < n && (!colk || cc < k0 + kb)) {
+                    double* cp = Xb + (size_t)r * ld + cc;
+                    *cp = colk ? -1.0 * acc[a][b][v] : 1.0 * *cp + -1.0 * acc[a][b][v];
+                }
+            }
 }
 
 // In-place inverse of the n x n block at X (row stride ld, merge stride sx)
@@ -1712,8 +1805,11 @@ __global__ __launch_bounds__(256) void k_gj_finish(double* X, long long ld, long
 // panels of 128: per step K with pivot block P = X_KK^{-1} (registers, one
 // workgroup per merge),
 //     R = P X_K,:      X_I,: -= X_IK R  (I != K)      X_IK = -X_IK P      X_K,: = R, X_KK = P
-// with the old column panel X_:,K kept in scratch.  Every product has K = 128
-// (short chains over many workgroups); scratch per merge from Wb (stride sw).
+// with the old column panel X_:,K kept in scratch, in three launches per
+// step: the pivot block's inverse beside the copy of the column panel
+// (k_gj_pivot), R, and every tile's share of the rest (k_gj_update).  Every
+// product has K = 128 (short chains over many workgroups); scratch per
+// merge from Wb (stride sw).
 static hipError_t qd_big_inverse(rmrcm_ctx* c, const MergeArgs& a, double* X, int n, long long ld,
                                  long long sx, double* Wb, long long sw) {
     const int nb = a.nnodes;
@@ -1721,29 +1817,19 @@ static hipError_t qd_big_inverse(rmrcm_ctx* c, const MergeArgs& a, double* X, in
         hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, X, ld, sx, n, a.flags);
         return hipGetLastError();
     }
-    double* Cw = Wb;                         // n x kb (row stride kb)
-    double* Pw = Wb + (size_t)n * 128;       // kb x kb
+    double* Pw = Wb + (size_t)n * 128;       // kb x kb; the column panel C (n x kb) before it
     double* Rw = Pw + 128 * 128;             // kb x n
     hipError_t e;
+    const unsigned tiles = (unsigned)((n + 63) / 64);
     for (int k0 = 0; k0 < n; k0 += 128) {
         const int kb = n - k0 < 128 ? n - k0 : 128;
-        const unsigned blocks = (unsigned)(((long long)n * kb + 255) / 256);
-        hipLaunchKernelGGL(k_gj_prep, dim3(blocks, nb), dim3(256), 0, c->stream, (const double*)X, ld, sx, n, k0,
-                           kb, Wb, sw);
-        hipLaunchKernelGGL(k_qd_invert_mfma, dim3(nb), dim3(QdM<128>::NT), 0, c->stream, Pw, (long long)kb, sw,
-                           kb, a.flags);
-        // R = P X_K,:  (the pivot block's own columns give P X_KK = I, replaced at the end)
+        const unsigned blocks = 1 + (unsigned)(((long long)n * kb + QdM<128>::NT - 1) / QdM<128>::NT);
+        hipLaunchKernelGGL(k_gj_pivot, dim3(blocks, nb), dim3(QdM<128>::NT), 0, c->stream, (const double*)X, ld,
+                           sx, n, k0, kb, Wb, sw, a.flags);
+        // R = P X_K,:  (the pivot block's own columns give P X_KK = I, replaced by P)
         if ((e = gemm(c, nb, kb, n, kb, 0, Pw, kb, sw, 0, X + (size_t)k0 * ld, ld, sx, Rw, n, sw, 1.0, 0.0)))
             return e;
-        const int s0 = k0 / 64, s1 = (k0 + kb + 63) / 64;     // row tiles of panel K
-        // X_I,: -= X_IK R for the other rows; then their column panel -X_IK P
-        if ((e = gemm(c, nb, n, n, kb, 0, Cw, kb, sw, 0, Rw, n, sw, X, ld, sx, -1.0, 1.0, nullptr, 0, nullptr, 0,
-                      s0, s1)))
-            return e;
-        if ((e = gemm(c, nb, n, kb, kb, 0, Cw, kb, sw, 0, Pw, kb, sw, X + k0, ld, sx, -1.0, 0.0, nullptr, 0,
-                      nullptr, 0, s0, s1)))
-            return e;
-        hipLaunchKernelGGL(k_gj_finish, dim3(blocks, nb), dim3(256), 0, c->stream, X, ld, sx, n, k0, kb,
+        hipLaunchKernelGGL(k_gj_update, dim3(tiles, tiles, nb), dim3(256), 0, c->stream, X, ld, sx, n, k0, kb,
                            (const double*)Wb, sw);
     }
     return hipGetLastError();
@@ -1945,7 +2031,7 @@ static hipError_t qd_trace_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int n
     // zero in X
     return gemm(c, nb, a.nslot, ncol, 2 * g, 0, Ar, 2 * g, sw, 0, a.X + col0, a.ld, (long long)a.xi * a.ld,
                 a.Tp + col0, a.ld, (long long)a.nslot * a.ld, 1.0, 1.0, a.tflag, a.ntiles,
-                col0 == 0 ? a.tflag : nullptr, a.ntiles);
+                col0 == 0 ? a.tflag : nullptr, a.ntiles, 0, 0, a.pmap, g);
 }
 
 static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
@@ -2266,8 +2352,12 @@ hipError_t launch_merge_setup(rmrcm_ctx* c, int d, bool part) {
         return qd_columns_any(c, a, 0, ncol, true, c->ct_tune[d]);
     }
     if (small_merge_ok(a, d, ncol)) {
-        hipLaunchKernelGGL(k_qd_small, dim3(a.nnodes), dim3(64 * small_waves(ncol)), small_lds_bytes(ncol, a.nslot),
-                           c->stream, a, ncol);
+        const int nrt = small_ns16(a.nslot) / 16;
+        const dim3 grid(a.nnodes), block(64 * small_waves(ncol));
+        const size_t lds = small_lds_bytes(ncol, a.nslot);
+        if (nrt <= 2) hipLaunchKernelGGL(k_qd_small<2>, grid, block, lds, c->stream, a, ncol);
+        else if (nrt <= 4) hipLaunchKernelGGL(k_qd_small<4>, grid, block, lds, c->stream, a, ncol);
+        else hipLaunchKernelGGL(k_qd_small<8>, grid, block, lds, c->stream, a, ncol);
         return hipGetLastError();
     }
     hipError_t e = qd_factor_any(c, a);

@@ -1,6 +1,8 @@
 """Error paths on the GPU that the host can force without a faulty kernel:
 the memory plan against what a context really allocates, a memory cap one
-byte short, and a refinement that cannot reach its tolerance."""
+byte short, a refinement that cannot reach its tolerance, and a legal
+permeability whose local system is singular in floating point (the device
+flag of the local factorisation, ESINGULAR at the sync)."""
 
 import numpy as np
 import pytest
@@ -95,3 +97,29 @@ def test_set_refinement_rejects(L):
             assert ei.value.status == -1
     finally:
         S.close()
+
+
+def test_subnormal_permeability_is_esingular(L):
+    """A subdomain whose permeability is the smallest positive subnormal
+    passes the permeability check (finite and positive), but every half-cell
+    resistance h / (2 K) overflows, so every face conductance of its local
+    system is 0 and its first pivot is 0: the FP64 factorisation flags it
+    and setup returns ESINGULAR (-4).  Every kernel after the flagged one is
+    bounded and indexes through the level tables only, so the NaN data it
+    leaves change no access.  A context on the same grid with a regular
+    permeability afterwards solves to the oracle's bar."""
+    from oracle.mrcm import mrcm_solve
+    prob = make_problem(64, b=16, seg=4, log_var=1.0, seed=7)
+    prob.K[16:32, 16:32] = 5e-324
+    assert prob.K[20, 20] > 0.0
+    print("[gpu-errors] subnormal permeability", flush=True)
+    with pytest.raises(L.RMRCMError) as ei:
+        L.Solver.from_problem(prob)
+    assert ei.value.status == -4
+    good = make_problem(64, b=16, seg=4, log_var=1.0, seed=7)
+    S = L.Solver.from_problem(good)
+    try:
+        p, _F = S.solve(good.q, good.bc_value)
+    finally:
+        S.close()
+    assert rel_l2(p, mrcm_solve(good).p) <= 1e-10

@@ -169,3 +169,35 @@ def test_step_incompatible_neumann_data_at_sync(env):
         assert rel_l2(p, ref.p - ref.p.mean()) <= TOL
     finally:
         S.close()
+
+
+def test_step_single_subdomain(env):
+    """One subdomain with Dirichlet faces (no interface, no merge level):
+    the step is the local problem alone; against the eager solve and the
+    oracle, and a second step with new data at the same pointers."""
+    L, torch = env
+    pr = make_problem(32, b=32, seg=8, source=True, seed=61)
+    S = L.Solver.from_problem(pr)
+    stream = torch.cuda.Stream()
+    try:
+        S.set_stream(stream.cuda_stream)
+        K, q, bv, pd, fd = dev_arrays(torch, pr)
+        say("[gpu] step, one subdomain")
+        S.step(K, q, bv, pd, fd)
+        S.sync()
+        p1, F1 = pd.cpu().numpy(), fd.cpu().numpy()
+        pr2 = make_problem(32, b=32, seg=8, source=True, seed=62, log_var=2.0)
+        K.copy_(torch.from_numpy(pr2.K))
+        q.copy_(torch.from_numpy(pr2.q))
+        bv.copy_(torch.from_numpy(pr2.bc_value))
+        torch.cuda.synchronize()
+        S.step(K, q, bv, pd, fd)
+        S.sync()
+        p2, F2 = pd.cpu().numpy(), fd.cpu().numpy()
+    finally:
+        S.close()
+    for prob, p, F in ((pr, p1, F1), (pr2, p2, F2)):
+        pe, Fe = eager(L, prob)
+        assert rel_l2(p, pe) <= STEP_TOL and rel_l2(F, Fe) <= STEP_TOL
+        ref = mrcm_solve(prob)
+        assert rel_l2(p, ref.p) <= TOL and rel_l2(F, ref.F) <= TOL
