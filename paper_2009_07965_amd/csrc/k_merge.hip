@@ -1520,26 +1520,28 @@ struct GemmNN {
 constexpr int kGemmKT = 32;
 
 // One 64 x 64 tile of the product A B into acc (wave w: rows 32 (w / 2)..,
-// columns 32 (w % 2).., 2 x 2 matrix-core tiles): Ab points at the tile's
-// first row of A (row stride lda, mr rows valid), Bb at its first column of B
-// (row stride ldb, nc columns valid), K over [kbeg, kend) in steps of
-// kGemmKT through the LDS tiles As and Bs, the next step's operands loaded
-// into registers while the current step's products run.  Entries outside
-// the valid rows, columns and K range are zero.
-__device__ __forceinline__ void nn_tile(const double* __restrict__ Ab, long long lda, int mr,
-                                        const double* __restrict__ Bb, long long ldb, int nc, int kbeg,
-                                        int kend, double* As, double* Bs, v4d (&acc)[2][2]) {
+// columns 32 (w % 2).., 2 x 2 matrix-core tiles): load_a(q, kk) gives the
+// entry of A at the tile's row (tid / 32) + 8 q and column kk (zero outside
+// the valid rows), Bb points at the tile's first column of B (row stride
+// ldb, nc columns valid), K over [kbeg, kend) in steps of kGemmKT through the
+// LDS tiles As and Bs, the next step's operands loaded into registers while
+// the current step's products run.  Entries outside the valid columns and
+// the K range are zero.
+template <typename LoadA>
+__device__ __forceinline__ void nn_tile(LoadA load_a, const double* __restrict__ Bb, long long ldb, int nc,
+                                        int kbeg, int kend, double* As, double* Bs, v4d (&acc)[2][2]) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
     // loader roles: A rows (tid / 32) + 8 q, column tid % 32; B rows
     // (tid / 64) + 4 q, column tid % 64
     const int ar = tid >> 5, ak = tid & 31, br = tid >> 6, bc = tid & 63;
+    (void)ar;
     double ra[8], rb[8];
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            const int r = ar + 8 * q, kk = k0 + ak;
-            ra[q] = (r < mr && kk < kend) ? Ab[(size_t)r * lda + kk] : 0.0;
+            const int kk = k0 + ak;
+            ra[q] = kk < kend ? load_a(q, kk) : 0.0;
             const int kb = k0 + br + 4 * q;
             rb[q] = (kb < kend && bc < nc) ? Bb[(size_t)kb * ldb + bc] : 0.0;
         }
@@ -1573,6 +1575,18 @@ __device__ __forceinline__ void nn_tile(const double* __restrict__ Ab, long long
     }
 }
 
+// A operand of nn_tile from a dense row-major block: Ab the tile's first
+// row, row stride lda, mr rows valid.
+struct DenseA {
+    const double* __restrict__ Ab;
+    long long lda;
+    int mr;
+    __device__ double operator()(int q, int kk) const {
+        const int r = (int)(threadIdx.x >> 5) + 8 * q;
+        return r < mr ? Ab[(size_t)r * lda + kk] : 0.0;
+    }
+};
+
 __global__ __launch_bounds__(256) void k_gemm_nn_f64(GemmNN g) {
     RMRCM_RUN_GUARD(g.run);
     __shared__ double As[64 * (kGemmKT + 1)];
@@ -1603,7 +1617,7 @@ __global__ __launch_bounds__(256) void k_gemm_nn_f64(GemmNN g) {
         if (!has1) kend = g.kh;
     }
     v4d acc[2][2];
-    nn_tile(A + (size_t)bm * g.lda, g.lda, g.m - bm, B + bn, g.ldb, g.n - bn, kbeg, kend, As, Bs, acc);
+    nn_tile(DenseA{A + (size_t)bm * g.lda, g.lda, g.m - bm}, B + bn, g.ldb, g.n - bn, kbeg, kend, As, Bs, acc);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -1782,8 +1796,9 @@ __global__ __launch_bounds__(256) void k_gj_update(double* X, long long ld, long
     }
     const bool colk = bn >= k0 && bn < k0 + kb;
     v4d acc[2][2];
-    if (colk) nn_tile(Cw + (size_t)bm * kb, kb, n - bm, Pw + (bn - k0), kb, k0 + kb - bn, 0, kb, As, Bs, acc);
-    else nn_tile(Cw + (size_t)bm * kb, kb, n - bm, Rw + bn, n, n - bn, 0, kb, As, Bs, acc);
+    const DenseA ca{Cw + (size_t)bm * kb, kb, n - bm};
+    if (colk) nn_tile(ca, Pw + (bn - k0), kb, k0 + kb - bn, 0, kb, As, Bs, acc);
+    else nn_tile(ca, Rw + bn, n, n - bn, 0, kb, As, Bs, acc);
     const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -2019,8 +2034,116 @@ __global__ __launch_bounds__(256) void k_qd_trace_direct_big(MergeArgs a, int co
     a.Tp[(size_t)node * a.nslot * a.ld + (size_t)o * a.ld + col] = d;
 }
 
+// The same parent traces in one launch, one 64 x 64 tile of Tp per
+// workgroup (columns [col0, col0 + ncol)): the left operand is gathered
+// from the owning child's trace row through the slot map and the gamma map
+// (staged in LDS for the tile's K range), the direct term is added in the
+// epilogue, tiles of inactive slots
+// take the direct terms alone, and K runs over the halves of the children
+// present in the tile's rows, as in k_gemm_nn_f64 with kpm: the operands and
+// sums of k_qd_trace_rows_big, k_qd_trace_direct_big and k_gemm_nn_f64.
+__host__ __device__ inline size_t trace_gemm_lds(int g) {
+    return sizeof(double) * (64 * (kGemmKT + 1) + kGemmKT * 65) + sizeof(int) * 2 * (size_t)g;
+}
+
+__global__ __launch_bounds__(256) void k_qd_trace_gemm(MergeArgs a, int col0, int ncol) {
+    RMRCM_RUN_GUARD(a.run);
+    extern __shared__ double tgs[];
+    double* As = tgs;
+    double* Bs = As + 64 * (kGemmKT + 1);
+    int* gms = reinterpret_cast<int*>(Bs + kGemmKT * 65);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int node = blockIdx.z, g = a.g, nslot = a.nslot;
+    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64;
+    int c1, c2;
+    children(a, node, &c1, &c2);
+    const double* Tk[2] = {a.Tc + (size_t)c1 * a.cnslot * a.cld, a.Tc + (size_t)c2 * a.cnslot * a.cld};
+    double* Tp = a.Tp + (size_t)node * nslot * a.ld + col0;
+    const double* X = a.X + (size_t)node * a.xi * a.ld + col0;
+    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
+    const bool skip = a.tflag && (!a.tflag[(size_t)node * a.ntiles + blockIdx.y] ||
+                                  (col0 == 0 && !a.tflag[(size_t)node * a.ntiles + blockIdx.x]));
+    v4d acc[2][2];
+    if (skip) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    } else {
+        int kbeg = 0, kend = 2 * g;
+        {
+            const int r = bm + (tid & 63);
+            const int own = (tid < 64 && r < nslot) ? (a.pmap[r] >> 24) : -1;
+            const int has0 = __syncthreads_or(own == 0), has1 = __syncthreads_or(own == 1);
+            if (!has0) kbeg = g;
+            if (!has1) kend = g;
+        }
+        for (int t = tid; t < kend - kbeg; t += 256) gms[t] = a.gmap[kbeg + t];
+        // this thread's A rows (tid / 32) + 8 q: owner and trace row
+        int own[8];
+        const double* trow[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int o = bm + (tid >> 5) + 8 * q;
+            const int pm = o < nslot ? a.pmap[o] : -1;
+            own[q] = pm >= 0 ? (pm >> 24) : -1;
+            trow[q] = Tk[own[q] == 1 ? 1 : 0] + (size_t)(pm >= 0 ? (pm & 0xffffff) : 0) * a.cld;
+        }
+        __syncthreads();
+        auto load_a = [&](int q, int kk) -> double {
+            return own[q] == (kk >= g ? 1 : 0) ? trow[q][gms[kk - kbeg]] : 0.0;
+        };
+        nn_tile(load_a, X + bn, a.ld, ncol - bn, kbeg, kend, As, Bs, acc);
+    }
+    // direct terms of this lane's outputs (rows wr + 16 i + lk + 4 v,
+    // columns wc + 16 j + li of the tile), loaded after the products so
+    // that they hold no registers across them
+    double dr[2][2][4];
+    {
+        int pc[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = col0 + bn + wc + 16 * j + li;
+            pc[j] = col < nslot ? a.pmap[col] : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = bm + wr + 16 * i + lk + 4 * v;
+                const int pm = o < nslot ? a.pmap[o] : 0, k = pm >> 24;
+                const double* tr = Tk[k & 1] + (size_t)(pm & 0xffffff) * a.cld;
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int cc = bn + wc + 16 * j + li, col = col0 + cc;
+                    double d = 0.0;
+                    if (o < nslot && cc < ncol)
+                        d = col == nslot ? tr[a.cld - 1] : ((pc[j] >> 24) == k ? tr[pc[j] & 0xffffff] : 0.0);
+                    dr[i][j][v] = d;
+                }
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int o = bm + wr + 16 * i + lk + 4 * v, cc = bn + wc + 16 * j + li;
+                if (o < nslot && cc < ncol) {
+                    const double r = skip ? dr[i][j][v] : 1.0 * dr[i][j][v] + 1.0 * acc[i][j][v];
+                    Tp[(size_t)o * a.ld + cc] = r;
+                }
+            }
+}
+
 static hipError_t qd_trace_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
     const int g = a.g, nb = a.nnodes;
+    if (trace_gemm_lds(g) <= 64 * 1024) {
+        hipLaunchKernelGGL(k_qd_trace_gemm, dim3((ncol + 63) / 64, (a.nslot + 63) / 64, nb), dim3(256),
+                           trace_gemm_lds(g), c->stream, a, col0, ncol);
+        return hipGetLastError();
+    }
     const long long sw = (long long)big_work(g, a.nslot);
     double* Ar = a.work + big_inv_work(g) + 3 * (size_t)g * (a.nslot + 1);
     const long long nr = (long long)a.nslot * 2 * g, nd = (long long)a.nslot * ncol;
