@@ -768,14 +768,15 @@ __global__ __launch_bounds__(64 * qd_apply_waves<GT>()) void k_qd_apply_mfma(Mer
 // k_qd_apply_mfma does; X stays in LDS for the traces, whose row tiles the
 // gridDim.z workgroups of the tile share (each repeats the apply, the first
 // writes X), eight waves each.  The trace operands (the child trace rows
-// against gamma and the direct terms) of a wave's first row tile are loaded
-// before the apply, those of its next row tile while the current one's
-// products run.
+// against gamma and the direct terms) of a row tile are loaded at its start;
+// the gamma maps are staged in LDS and X is read from LDS at each use, so
+// that two workgroups fit a compute unit.
 template <int GT>
 __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int ncol) {
     RMRCM_RUN_GUARD(a.run);
     constexpr int CT = 16, AL = CT + 1, NT = 512, NW = NT / 64, KS = GT / 4;
     __shared__ double rs[GT * AL], rd[GT * AL], tt[GT * AL];
+    __shared__ int gms[2 * GT];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int node = blockIdx.x, g = a.g, nslot = a.nslot;
     const int cb = col0 + blockIdx.y * CT;
@@ -797,22 +798,23 @@ __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int
     const bool cin = li < nc;
     const int pc = (cin && col < nslot) ? a.pmap[col] : -1;
     const int nrt = (nslot + 15) / 16, ot0 = w + NW * blockIdx.z, ots = NW * gridDim.z;
-    int gm[2][KS];
-#pragma unroll
-    for (int q = 0; q < KS; ++q) {
-        const int i = 4 * q + lk;
-        gm[0][q] = i < g ? g1[i] : 0;
-        gm[1][q] = i < g ? g2[i] : 0;
+    // the gamma maps of both children in LDS (read by the trace operand
+    // loads; registers are the occupancy bound here)
+    for (int t = tid; t < 2 * GT; t += NT) {
+        const int k = t / GT, i = t % GT;
+        gms[t] = i < g ? (k ? g2[i] : g1[i]) : 0;
     }
+    __syncthreads();
     auto load_rows = [&](int ot, double (&av)[KS], double (&dr)[4], int& ka) {
         const int oa = 16 * ot + li;
         const int pa = (ot < nrt && oa < nslot) ? a.pmap[oa] : -1;
         ka = pa >= 0 ? (pa >> 24) : -1;
         const double* ta = (ka == 1 ? T2 : T1) + (size_t)(pa >= 0 ? (pa & 0xffffff) : 0) * a.cld;
+        const int* gk = gms + (ka == 1 ? GT : 0);
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
             const int i = 4 * q + lk;
-            av[q] = (ka >= 0 && i < g) ? ta[ka == 1 ? gm[1][q] : gm[0][q]] : 0.0;
+            av[q] = (ka >= 0 && i < g) ? ta[gk[i]] : 0.0;
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -827,9 +829,6 @@ __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int
             dr[v] = d;
         }
     };
-    double av0[KS], dr0[4];
-    int ka0;
-    load_rows(ot0, av0, dr0, ka0);
     // ---- the apply (k_qd_apply_mfma with one column tile)
     double av[GT / 4], an[GT / 4];
     qd_load_tile<GT>(g, Dg, av);
@@ -884,32 +883,33 @@ __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int
             X[(size_t)(g + i) * a.ld + cb + cc] = -(sv + dv);
         }
     }
-    // ---- parent traces of the tile: T_p[o, col] = direct + A_k(o) X_k[:, col]
-    double xb[2][KS];
-#pragma unroll
-    for (int q = 0; q < KS; ++q) {
+    // ---- parent traces of the tile: T_p[o, col] = direct + A_k(o) X_k[:, col],
+    // the B operands X_1 = -(s - d), X_2 = -(s + d) formed from s and d in
+    // LDS at each use; each row tile's operands loaded at its start (another
+    // workgroup on the compute unit covers the latency: registers bound the
+    // occupancy, and holding the next tile's operands would halve it)
+    auto xb = [&](int k, int q) -> double {
         const int i = 4 * q + lk;
         const double sv = rd[i * AL + li], dv = tt[i * AL + li];
         const bool in = i < g && cin;
-        xb[0][q] = in ? -(sv - dv) : 0.0;
-        xb[1][q] = in ? -(sv + dv) : 0.0;
-    }
+        return in ? (k ? -(sv + dv) : -(sv - dv)) : 0.0;
+    };
     double* Tp = a.Tp + (size_t)node * nslot * a.ld;
     for (int ot = ot0; ot < nrt; ot += ots) {
-        double av1[KS] = {}, dr1[4] = {};
-        int ka1 = -1;
-        if (ot + ots < nrt) load_rows(ot + ots, av1, dr1, ka1);
+        double av0[KS], dr0[4];
+        int ka0;
+        load_rows(ot, av0, dr0, ka0);
         // a child's half is skipped when none of the tile's rows is its
         // (all-zero A rows: the sum is unchanged bit for bit); most tiles
         // lie on one child's sides
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         if (__ballot(ka0 == 0) != 0ull) {
 #pragma unroll
-            for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 0 ? av0[q] : 0.0, xb[0][q], acc);
+            for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 0 ? av0[q] : 0.0, xb(0, q), acc);
         }
         if (__ballot(ka0 == 1) != 0ull) {
 #pragma unroll
-            for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 1 ? av0[q] : 0.0, xb[1][q], acc);
+            for (int q = 0; q < KS; ++q) acc = mfma_f64(ka0 == 1 ? av0[q] : 0.0, xb(1, q), acc);
         }
         if (cin) {
 #pragma unroll
@@ -918,11 +918,6 @@ __global__ __launch_bounds__(512) void k_qd_cols_mfma(MergeArgs a, int col0, int
                 if (o < nslot) Tp[(size_t)o * a.ld + col] = dr0[v] + acc[v];
             }
         }
-#pragma unroll
-        for (int q = 0; q < KS; ++q) av0[q] = av1[q];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dr0[v] = dr1[v];
-        ka0 = ka1;
     }
 }
 
