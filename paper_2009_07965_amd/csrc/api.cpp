@@ -128,8 +128,9 @@ int validate(const rmrcm_params* p) {
         if ((size_t)p->sub_nx * p->nz > 64 || p->sub_ny > 64) return RMRCM_ENOTSUP;
         // one column's factor block, right-hand sides and products in LDS
         const size_t nb = (size_t)p->sub_nx * p->nz, ncol = 2 * (size_t)(p->sub_nx + p->sub_ny) / p->seg + 1;
-        const size_t nbp = (nb + 15) / 16 * 16, zlen = nb * (ncol > 12 ? ncol : 12);
-        if (sizeof(double) * (nb * (nb + 1) + nb * ncol + zlen + 2 * nb + 4 * nbp + 2) > 160 * 1024)
+        const size_t ts = (nb + 15) / 16, zl = nb * (ncol > 12 ? ncol : 12);
+        const size_t zlen = zl > 66 * ts * ts ? zl : 66 * ts * ts;
+        if (sizeof(double) * (nb * (nb + 1) + nb * ncol + zlen + 2 * nb + 2) > 160 * 1024)
             return RMRCM_ENOTSUP;
         return RMRCM_OK;
     }

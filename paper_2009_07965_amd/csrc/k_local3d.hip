@@ -102,16 +102,19 @@ __device__ inline size_t cell3(const Geo& g, int i, int j, int k) { return ((siz
 
 }  // namespace
 
-// Doubles of the Z buffer: the products' output, and between a row's
-// products the face table of the row (6 NB conductances, 12 NB ints).
+// Doubles of the Z buffer: the products' output; between a row's products
+// the face table of the row (6 NB conductances, 12 NB ints), then during
+// the row's factorisation the Gauss-Jordan panels (two buffers of TS pivot
+// rows and TS pivot columns of the padded block, NBP = 16 TS, and the
+// inverted pivot block).
 __host__ __device__ inline size_t local3d_zlen(int nb, int ncol) {
-    return (size_t)nb * (ncol > 12 ? ncol : 12);
+    const size_t ts = (size_t)(nb + 15) / 16, zl = (size_t)nb * (ncol > 12 ? ncol : 12);
+    return zl > 66 * ts * ts ? zl : 66 * ts * ts;
 }
 
 __host__ __device__ inline size_t local3d_lds(int nb, int ncol) {
-    const size_t nbp = (size_t)(nb + 15) / 16 * 16;
     return sizeof(double) *
-           ((size_t)nb * (nb + 1) + (size_t)nb * ncol + local3d_zlen(nb, ncol) + 2 * (size_t)nb + 4 * nbp + 2);
+           ((size_t)nb * (nb + 1) + (size_t)nb * ncol + local3d_zlen(nb, ncol) + 2 * (size_t)nb + 2);
 }
 
 // factor = 1: the factorisation (P_j to the factor store), the basis
@@ -144,9 +147,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     constexpr int NBP = 16 * TS;
     double* dp = Z + local3d_zlen(NB, ncol);   // couplings D_{j-1}
     double* dn = dp + NB;                  // couplings D_j
-    double* rowb = dn + NB;                // Gauss-Jordan pivot rows (two buffers)
-    double* colb = rowb + 2 * NBP;         // and columns
-    double* piv = colb + 2 * NBP;          // [1]: singular
+    double* piv = dn + NB;                 // [1]: singular
     double* fc = Z;                        // [6][NB] face conductances of the current row (in Z
                                            // between the products)
     int* fk = reinterpret_cast<int*>(fc + 6 * NB);   // [6][NB] kind | slot << 2
@@ -272,46 +273,106 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                     }
                     sv[u][v] = a;
                 }
-            // P_j = S_j^-1, Gauss-Jordan without pivoting on the tiles
-            for (int p = 0; p < NBP; ++p) {
-                double* rp = rowb + (p & 1) * NBP;
-                double* cp = colb + (p & 1) * NBP;
-                const int pt = p / TS, pu = p % TS;
-                if (tr == pt) {
+            // P_j = S_j^-1, block Gauss-Jordan without pivoting on the tiles:
+            // step K takes the TS pivots of thread row K at once.  The
+            // owners publish the pivot rows (thread row K) and columns
+            // (thread column K) to LDS (the face table's buffer, dead by
+            // now; two buffers: one barrier per step); the owner of the
+            // diagonal tile inverts it in place (Gauss-Jordan, a pivot that
+            // is not positive flagged) and publishes the inverse Q; then,
+            // with R_J = Q S_KJ,
+            //     S_IJ -= S_IK R_J,  S_KJ = R_J,  S_IK = -S_IK Q,  S_KK = Q.
+            for (int K = 0; K < 16; ++K) {
+                double* rp = Z + (size_t)(K & 1) * (2 * TS * NBP + TS * TS);   // TS x NBP: pivot rows
+                double* cp = rp + TS * NBP;                                    // NBP x TS: pivot columns
+                double* qb = cp + TS * NBP;                                    // TS x TS: Q
+                if (tr == K) {
 #pragma unroll
-                    for (int v = 0; v < TS; ++v) rp[TS * tc + v] = sv[pu][v];
+                    for (int u = 0; u < TS; ++u)
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) rp[u * NBP + TS * tc + v] = sv[u][v];
                 }
-                if (tc == pt) {
+                if (tc == K) {
 #pragma unroll
-                    for (int u = 0; u < TS; ++u) cp[TS * tr + u] = sv[u][pu];
+                    for (int u = 0; u < TS; ++u)
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) cp[(TS * tr + u) * TS + v] = sv[u][v];
+                }
+                if (tr == K && tc == K) {
+                    bool bad = false;
+#pragma unroll
+                    for (int k = 0; k < TS; ++k) {
+                        double d = sv[k][k];
+                        if (!(d > 0.0)) {
+                            bad = true;
+                            d = 1.0;
+                        }
+                        const double inv = 1.0 / d;
+                        double rk[TS];
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) rk[v] = sv[k][v] * inv;
+#pragma unroll
+                        for (int u = 0; u < TS; ++u) {
+                            if (u == k) continue;
+                            const double m = sv[u][k];
+#pragma unroll
+                            for (int v = 0; v < TS; ++v) sv[u][v] = fma(-m, rk[v], sv[u][v]);
+                            sv[u][k] = -m * inv;
+                        }
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) sv[k][v] = rk[v];
+                        sv[k][k] = inv;
+                    }
+                    if (bad) piv[1] = 1.0;
+#pragma unroll
+                    for (int u = 0; u < TS; ++u)
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) qb[u * TS + v] = sv[u][v];
                 }
                 __syncthreads();
-                double d = rp[p];
-                if (!(d > 0.0)) {
-                    if (tid == 0) piv[1] = 1.0;
-                    d = 1.0;
+                if (tr == K && tc == K) {
+                    // S_KK = Q, already in place
+                } else if (tc == K) {
+                    // S_IK = -S_IK Q, row by row
+#pragma unroll
+                    for (int u = 0; u < TS; ++u) {
+                        double c[TS];
+#pragma unroll
+                        for (int w2 = 0; w2 < TS; ++w2) c[w2] = sv[u][w2];
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int w2 = 0; w2 < TS; ++w2) acc = fma(c[w2], qb[w2 * TS + v], acc);
+                            sv[u][v] = -acc;
+                        }
+                    }
+                } else {
+                    // R_J = Q S_KJ one row at a time (S_KJ from the panel):
+                    // the pivot rows take it, the others S_IJ -= S_IK R_J
+#pragma unroll
+                    for (int w2 = 0; w2 < TS; ++w2) {
+                        double r[TS];
+#pragma unroll
+                        for (int v = 0; v < TS; ++v) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int x = 0; x < TS; ++x) acc = fma(qb[w2 * TS + x], rp[x * NBP + TS * tc + v], acc);
+                            r[v] = acc;
+                        }
+                        if (tr == K) {
+#pragma unroll
+                            for (int v = 0; v < TS; ++v) sv[w2][v] = r[v];
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < TS; ++u) {
+                                const double ck = cp[(TS * tr + u) * TS + w2];
+#pragma unroll
+                                for (int v = 0; v < TS; ++v) sv[u][v] = fma(-ck, r[v], sv[u][v]);
+                            }
+                        }
+                    }
                 }
-                const double inv = 1.0 / d;
-                // every element: S -= col_p (row_p / d); then the pivot's
-                // row (row_p / d), column (-col_p / d) and entry (1 / d)
-                double rv[TS], cv[TS];
-#pragma unroll
-                for (int v = 0; v < TS; ++v) rv[v] = rp[TS * tc + v] * inv;
-#pragma unroll
-                for (int u = 0; u < TS; ++u) cv[u] = cp[TS * tr + u];
-#pragma unroll
-                for (int u = 0; u < TS; ++u)
-#pragma unroll
-                    for (int v = 0; v < TS; ++v) sv[u][v] = fma(-cv[u], rv[v], sv[u][v]);
-                if (tr == pt) {
-#pragma unroll
-                    for (int v = 0; v < TS; ++v) sv[pu][v] = rv[v];
-                }
-                if (tc == pt) {
-#pragma unroll
-                    for (int u = 0; u < TS; ++u) sv[u][pu] = -cv[u] * inv;
-                }
-                if (tr == pt && tc == pt) sv[pu][pu] = inv;
             }
             __syncthreads();
             // P_j to LDS (the products) and to the factor store
