@@ -163,9 +163,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     if (tid == 0) piv[1] = 0.0;
     // Block products Out = Sm In (NB x NB times NB x ncol, row strides LS
     // and ncol): thread (tr, tc) forms rows tr + 16 u (u < TS) of columns
-    // tc + 16 w, each In element read once for its TS rows.
+    // tc + 16 w below the last whole group of 16 columns, each In element
+    // read once for its TS rows; each column beyond (the particular one of
+    // 16 basis columns and it) is shared by all threads: thread (tr, tc)
+    // sums the terms x = tc + 16 i of rows tr + 16 u, and the 16 lanes of
+    // a thread row (consecutive in their wave) add their sums by shuffles.
+    const int nmain = ncol & ~15;
     auto product = [&](const double* In, auto&& out) {
-        for (int c = tc; c < ncol; c += 16) {
+        for (int c = nmain; c < ncol; ++c) {
+            double acc[TS];
+#pragma unroll
+            for (int u = 0; u < TS; ++u) acc[u] = 0.0;
+            for (int x = tc; x < NB; x += 16) {
+                const double y = In[x * ncol + c];
+#pragma unroll
+                for (int u = 0; u < TS; ++u) {
+                    const int r = tr + 16 * u;
+                    if (r < NB) acc[u] += S[r * LS + x] * y;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TS; ++u) {
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) acc[u] += __shfl_xor(acc[u], o, 16);
+                const int r = tr + 16 * u;
+                if (tc == 0 && r < NB) out(r, c, acc[u]);
+            }
+        }
+        for (int c = tc; c < nmain; c += 16) {
             double acc[TS];
 #pragma unroll
             for (int u = 0; u < TS; ++u) acc[u] = 0.0;
