@@ -2152,6 +2152,30 @@ static hipError_t qd_trace_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int n
                 col0 == 0 ? a.tflag : nullptr, a.ntiles, 0, 0, a.pmap, g);
 }
 
+// y = alpha A x + beta y for the g x g block A of every merge (row-major,
+// merge stride sa) and vectors x, y (merge strides sv): one wave per row,
+// lane l summing the entries l, l + 64, ... (each load instruction reads 64
+// consecutive entries of the row), the lane sums added by shuffles.  The
+// long interfaces' single-column apply (the particular column of the root
+// in a step), where a tiled product would leave most of the chip idle.
+__global__ __launch_bounds__(256) void k_matvec_big(int g, const double* __restrict__ A, long long sa,
+                                                    const double* __restrict__ x, double* y, long long sv,
+                                                    double alpha, double beta, const int* run) {
+    RMRCM_RUN_GUARD(run);
+    const int lane = threadIdx.x & 63, row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= g) return;
+    const double* Ar = A + (size_t)blockIdx.y * sa + (size_t)row * g;
+    const double* xv = x + (size_t)blockIdx.y * sv;
+    double s = 0.0;
+    for (int j = lane; j < g; j += 64) s = fma(Ar[j], xv[j], s);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) {
+        double* yr = y + (size_t)blockIdx.y * sv + row;
+        *yr = beta == 0.0 ? alpha * s : beta * *yr + alpha * s;
+    }
+}
+
 static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int ncol) {
     const int g = a.g, nb = a.nnodes;
     const long long gg = (long long)g * g, sx = 4 * gg;
@@ -2172,6 +2196,19 @@ static hipError_t qd_apply_big(rmrcm_ctx* c, const MergeArgs& a, int col0, int n
     // columns of inactive slots are zero in every right-hand side block
     const unsigned char* cf = col0 == 0 ? a.tflag : nullptr;
     const int cs = a.ntiles;
+    if (ncol == 1) {
+        const dim3 mg((g + 3) / 4, nb);
+        const struct { const double *A, *x; double* y; double alpha, beta; } mv[4] = {
+            {D, RD, TT, 1.0, 0.0}, {B, TT, RS, -1.0, 1.0}, {S, RS, RD, 1.0, 0.0}, {E, RD, TT, -1.0, 1.0}};
+        for (const auto& m : mv) {
+            hipLaunchKernelGGL(k_matvec_big, mg, dim3(256), 0, c->stream, g, m.A, sx, m.x, m.y, sw, m.alpha,
+                               m.beta, c->run_ptr);
+            if ((e = hipGetLastError())) return e;
+        }
+        hipLaunchKernelGGL(k_qd_x_big, grid, dim3(256), 0, c->stream, a, col0, ncol, (const double*)RD,
+                           (const double*)TT, sw);
+        return hipGetLastError();
+    }
     if ((e = gemm(c, nb, g, ncol, g, 0, D, g, sx, 0, RD, ncol, sw, TT, ncol, sw, 1.0, 0.0, nullptr, 0, cf, cs))) return e;   // t
     if ((e = gemm(c, nb, g, ncol, g, 0, B, g, sx, 0, TT, ncol, sw, RS, ncol, sw, -1.0, 1.0, nullptr, 0, cf, cs))) return e;  // u
     if ((e = gemm(c, nb, g, ncol, g, 0, S, g, sx, 0, RS, ncol, sw, RD, ncol, sw, 1.0, 0.0, nullptr, 0, cf, cs))) return e;   // s
