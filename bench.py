@@ -29,6 +29,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -243,15 +244,24 @@ def measured_traffic(workload):
             sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
+    vals = parse_traffic_summary(txt)
+    if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def parse_traffic_summary(txt):
+    """The key lines of a traffic summary ("- source_sha256: `hex` (note)",
+    "- traffic_bytes_per_launch: 7.2e+10"): each value is the first
+    backticked token, else the first word after the colon."""
     vals = {}
     for line in txt.splitlines():
         line = line.strip().lstrip("-").strip()
         if ":" in line and line.startswith(("source_sha256", "traffic_bytes_per_launch")):
             k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256") != sha or "traffic_bytes_per_launch" not in vals:
-        return None
-    return float(vals["traffic_bytes_per_launch"])
+            m = re.search(r"`([^`]*)`", v)
+            vals[k.strip()] = m.group(1) if m else (v.split() or [""])[0]
+    return vals
 
 
 def copy_calibration(mib=512, reps=3):
