@@ -1051,8 +1051,10 @@ __device__ __forceinline__ void part_product(const typename Mfma<double>::v4 (&p
 //     x_j = w_j + P_j D_j x_{j+1}      (j < m),
 //     x_j = w_j + P_j D_{j-1} x_{j-1}  (j > m).
 // The chain of dependent block rows is m + 1 long instead of by.  The factor
-// store holds P_j of this elimination for every row, and the particular
-// solve sweeps it the same way.  Each wave has its own L^{-1} / Schur-term
+// store holds P_j of this elimination for every row, its 16 x 16 tiles on
+// and below the diagonal only (P_j is symmetric; readers take a tile above
+// the diagonal as the transpose of its mirror: a quarter less traffic at
+// 32 cells), and the particular solve sweeps it the same way.  Each wave has its own L^{-1} / Schur-term
 // buffer (also the multiplier buffer of the blocked Cholesky, which is used
 // only while the buffer is free) and right-hand side block in LDS.  The
 // forward sweep takes P_j straight from the accumulators: P_j is symmetric,
@@ -1187,7 +1189,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_twist(
                     for (int v = 0; v < 4; ++v) {
                         const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
                         const S pv = pacc[tr][tc][v];
-                        Ps[(size_t)j * BX * BX + r * BX + cq] = pv;
+                        if (tr >= tc) Ps[(size_t)j * BX * BX + r * BX + cq] = pv;   // lower tiles
                         LTs[r * LT + cq] = -(pv * (tys[jd * BX + r] * tys[jd * BX + cq]));
                     }
             // forward sweep w_j = P_j z_j, then z of the next row = D w_j + f
@@ -1260,7 +1262,7 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_twist(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int r = 16 * tr + M::row(lane, v), cq = 16 * tc + li;
-                    Ps[(size_t)m * BX * BX + r * BX + cq] = pacc[tr][tc][v];
+                    if (tr >= tc) Ps[(size_t)m * BX * BX + r * BX + cq] = pacc[tr][tc][v];
                 }
         if (has_hi) {
             for (int t = lane; t < BX * RP; t += 64) Z0[t] += Z1[t];
@@ -1321,7 +1323,9 @@ __global__ __launch_bounds__(128, 2) void k_local_setup_twist(
         for (int tr = 0; tr < NTL; ++tr) {
 #pragma unroll
             for (int kq4 = 0; kq4 < BX / 4; ++kq4)
-                pn[tr][kq4] = Ps[(size_t)jr * BX * BX + (16 * tr + li) * BX + 4 * kq4 + lk];
+                // tile (tr, k / 16) above the diagonal: its transpose (P_j symmetric)
+                pn[tr][kq4] = (4 * kq4) / 16 > tr ? Ps[(size_t)jr * BX * BX + (4 * kq4 + lk) * BX + 16 * tr + li]
+                                                  : Ps[(size_t)jr * BX * BX + (16 * tr + li) * BX + 4 * kq4 + lk];
 #pragma unroll
             for (int ct = 0; ct < WCT; ++ct)
 #pragma unroll
@@ -2522,7 +2526,8 @@ __global__ __launch_bounds__(64) void k_local_particular_twist(
     double p[BX], pn[BX];
     auto load_p = [&](int jr) {
 #pragma unroll
-        for (int k = 0; k < BX; ++k) pn[k] = Ps[(size_t)jr * BX * BX + k * BX + c];
+        for (int k = 0; k < BX; ++k)   // P[k][c]; above the diagonal tiles, P[c][k] (lower tiles only)
+            pn[k] = k / 16 < c / 16 ? Ps[(size_t)jr * BX * BX + c * BX + k] : Ps[(size_t)jr * BX * BX + k * BX + c];
     };
     if (nrow > 0) load_p(h == 0 ? 0 : BY - 1);
     double wv = 0.0, dprev = 0.0;
