@@ -1968,9 +1968,14 @@ __global__ __launch_bounds__(256) void k_trace_correct_lds(Geo g, const double* 
         const int c = st * CH + tco, i = c % BX, j = c / BX;
         S.ka = S.kb = 1.0;
         if (tid < 2 * CH && c < n) {
+            // the neighbour's permeability by one load at a selected offset
+            // (itself where there is no neighbour; the store then ignores
+            // it): loads of one register on divergent paths made the compiler
+            // wait for every load in flight, the prefetched stages included
             const double* kc = K + (size_t)(J * BY + j) * g.nx + (size_t)I * BX + i;
+            const bool hn = tyd ? j < BY - 1 : i < BX - 1;
             S.ka = kc[0];
-            S.kb = tyd ? (j < BY - 1 ? kc[g.nx] : 1.0) : (i < BX - 1 ? kc[1] : 1.0);
+            S.kb = kc[hn ? (tyd ? (size_t)g.nx : 1) : 0];
         }
     };
     auto store = [&](int st, const Stage& S) {
