@@ -29,6 +29,8 @@ namespace rmrcm {
 
 namespace {
 
+typedef double v4m __attribute__((ext_vector_type(4)));
+
 struct Face3 {
     int kind;      // 0 interior, 1 Robin (slot), 2 outer boundary
     int slot;      // local slot of a Robin face
@@ -169,6 +171,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
     // sums the terms x = tc + 16 i of rows tr + 16 u, and the 16 lanes of
     // a thread row (consecutive in their wave) add their sums by shuffles.
     const int nmain = ncol & ~15;
+    const int wv = tid >> 6, li = tid & 15, lk = (tid >> 4) & 3;   // matrix-core lane roles
+    const int NKS = ((NB + 3) / 4 + 1) & ~1;                         // k-slices, even
     auto product = [&](const double* In, auto&& out) {
         for (int c = nmain; c < ncol; ++c) {
             double acc[TS];
@@ -190,22 +194,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
                 if (tc == 0 && r < NB) out(r, c, acc[u]);
             }
         }
-        for (int c = tc; c < nmain; c += 16) {
-            double acc[TS];
-#pragma unroll
-            for (int u = 0; u < TS; ++u) acc[u] = 0.0;
-            for (int x = 0; x < NB; ++x) {
-                const double y = In[x * ncol + c];
-#pragma unroll
-                for (int u = 0; u < TS; ++u) {
-                    const int r = tr + 16 * u;
-                    if (r < NB) acc[u] += S[r * LS + x] * y;
+        // the groups of 16 columns on the matrix cores (v_mfma_f64_16x16x4):
+        // wave w forms row tile w, lane l = x + 16 k holding Sm[16 w + x][4 s + k]
+        // (A operand) and In[4 s + k][16 t + x] (B operand) for k-slice s;
+        // the result's lane l, register v is row 16 w + l / 16 + 4 v, column
+        // 16 t + l % 16.  Two accumulators (even and odd k-slices) halve the
+        // dependent chain.
+        if (wv < TS) {
+            const int r = 16 * wv + li;
+            for (int ct = 0; ct < nmain / 16; ++ct) {
+                const int cc = 16 * ct + li;
+                v4m acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+                for (int ks = 0; ks < NKS; ks += 2) {
+                    const int k0 = 4 * ks + lk, k1 = k0 + 4;
+                    const double a0 = (r < NB && k0 < NB) ? S[r * LS + k0] : 0.0;
+                    const double b0 = k0 < NB ? In[k0 * ncol + cc] : 0.0;
+                    const double a1 = (r < NB && k1 < NB) ? S[r * LS + k1] : 0.0;
+                    const double b1 = k1 < NB ? In[k1 * ncol + cc] : 0.0;
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
                 }
-            }
 #pragma unroll
-            for (int u = 0; u < TS; ++u) {
-                const int r = tr + 16 * u;
-                if (r < NB) out(r, c, acc[u]);
+                for (int v = 0; v < 4; ++v) {
+                    const int ro = 16 * wv + lk + 4 * v;
+                    if (ro < NB) out(ro, cc, acc0[v] + acc1[v]);
+                }
             }
         }
     };

@@ -1400,83 +1400,12 @@ __global__ __launch_bounds__(256) void k_down(DownArgs a) {
 // ---------------------------------------------------------------- g > 128
 // Merges whose gamma blocks exceed the register-resident inversion (one
 // workgroup holds at most 128 x 128 in registers): the same quasi-definite
-// elimination with the blocks in global memory.  D^{-1} and S^{-1} by a 2 x 2
-// split, [[A, C^T], [C, F]] with A of order 128: A^{-1} in registers (the
-// blocked Gauss-Jordan above), Y = A^{-1} C^T, the Schur block F - C Y and its
-// inverse in the same way (recursively while it exceeds 128), then
-// W = Y F'^{-1} and the four blocks of the inverse (A^{-1} + W Y^T, -W, -W^T,
-// F'^{-1}); E = D^{-1} B and S = N - B E, the four products of the column
-// apply, and beyond 256 the parent traces, as matrix products on the FP64
-// matrix cores (k_gemm_f64), batched over the level's merges.
-
-// C = beta C + alpha op(A) op(B) (row-major; ta / tb: the operand is stored
-// transposed), one 64 x 64 tile of C per workgroup, batch blockIdx.z with
-// the given strides; four waves, each a 32 x 32 sub-tile (2 x 2 matrix-core
-// tiles), K in steps of 16 through LDS.
-struct GemmArgs {
-    int m, n, k, ta, tb;
-    const double* A;
-    long long lda, sa;
-    const double* B;
-    long long ldb, sb;
-    double* C;
-    long long ldc, sc;
-    double alpha, beta;
-    const int* run;
-};
-
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
-    RMRCM_RUN_GUARD(g.run);
-    __shared__ double As[64 * 17];
-    __shared__ double Bs[16 * 65];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, li = lane & 15, lk = lane >> 4;
-    const int bm = blockIdx.y * 64, bn = blockIdx.x * 64, z = blockIdx.z;
-    const double* A = g.A + (size_t)z * g.sa;
-    const double* B = g.B + (size_t)z * g.sb;
-    double* C = g.C + (size_t)z * g.sc;
-    const int wr = 32 * (w >> 1), wc = 32 * (w & 1);
-    v4d acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < g.k; k0 += 16) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = tid + 256 * q;
-            const int r = e >> 4, kk = e & 15, gr = bm + r, gk = k0 + kk;
-            As[r * 17 + kk] = (gr < g.m && gk < g.k)
-                                  ? (g.ta ? A[(size_t)gk * g.lda + gr] : A[(size_t)gr * g.lda + gk])
-                                  : 0.0;
-            const int kb = e >> 6, cb = e & 63, gkb = k0 + kb, gc = bn + cb;
-            Bs[kb * 65 + cb] = (gkb < g.k && gc < g.n)
-                                   ? (g.tb ? B[(size_t)gc * g.ldb + gkb] : B[(size_t)gkb * g.ldb + gc])
-                                   : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = mfma_f64(As[(wr + 16 * a + li) * 17 + 4 * s4 + lk],
-                                         Bs[(4 * s4 + lk) * 65 + wc + 16 * b + li], acc[a][b]);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = bm + wr + 16 * a + lk + 4 * v, cc = bn + wc + 16 * b + li;
-                if (r < g.m && cc < g.n) {
-                    double* cp = C + (size_t)r * g.ldc + cc;
-                    *cp = g.beta == 0.0 ? g.alpha * acc[a][b][v] : g.beta * *cp + g.alpha * acc[a][b][v];
-                }
-            }
-}
+// elimination with the blocks in global memory.  D^{-1} and S^{-1} by
+// blocked Gauss-Jordan over 128-wide panels (qd_big_inverse: the pivot
+// block's inverse in registers on one workgroup per merge, the rest as
+// products over many workgroups); E = D^{-1} B and S = N - B E, the four
+// products of the column apply, and the parent traces, as matrix products
+// on the FP64 matrix cores, batched over the level's merges.
 
 // C = beta C + alpha A B for untransposed row-major operands, one 64 x 64
 // tile of C per workgroup and batch entry blockIdx.z, four waves of 32 x 32
@@ -1640,9 +1569,7 @@ static hipError_t gemm(rmrcm_ctx* c, int batch, int m, int n, int k, int ta, con
         hipLaunchKernelGGL(k_gemm_nn_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
         return hipGetLastError();
     }
-    GemmArgs g{m, n, k, ta, tb, A, lda, sa, B, ldb, sb, C, ldc, sc, alpha, beta, c->run_ptr};
-    hipLaunchKernelGGL(k_gemm_f64, dim3((n + 63) / 64, (m + 63) / 64, batch), dim3(256), 0, c->stream, g);
-    return hipGetLastError();
+    return hipErrorInvalidValue;             // every product here has untransposed operands
 }
 
 // Inverse of the n x n block (n <= 128) at src (row stride lds) into dst
