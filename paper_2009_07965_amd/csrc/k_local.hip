@@ -153,11 +153,23 @@ __global__ void k_check_beta(Geo g, const double* __restrict__ K, size_t n, int*
         if (e < g.nseg) beta_of(g, K, beta, seglen, e);
         return;
     }
+    // four independent loads in flight per thread (a strided sweep of the
+    // grid), then their checks and copies
     bool bad = false;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)nbc * blockDim.x) {
-        const double v = K[t];
-        bad |= !(v > 0.0) || !(v <= 1.7976931348623157e308);
-        if (copy) copy[t] = v;
+    const size_t stride = (size_t)nbc * blockDim.x;
+    for (size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t0 < n; t0 += 4 * stride) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t t = t0 + u * stride;
+            v[u] = t < n ? K[t] : 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const size_t t = t0 + u * stride;
+            bad |= !(v[u] > 0.0) || !(v[u] <= 1.7976931348623157e308);
+            if (copy && t < n) copy[t] = v[u];
+        }
     }
     if (bad) atomicOr(&flags[FLAG_BAD_PERM], 1);
 }
@@ -2779,7 +2791,7 @@ static hipError_t trace_correct_bx(rmrcm_ctx* c, int basis, int part, const int*
 
 hipError_t launch_check_beta(rmrcm_ctx* c, double* copy) {
     const size_t n = geo_ncell(c->geo);
-    const int nbc = 1024, nbb = (c->geo.nseg + 255) / 256;
+    const int nbc = 2048, nbb = (c->geo.nseg + 255) / 256;
     hipLaunchKernelGGL(k_check_beta, dim3(nbc + nbb), dim3(256), 0, c->stream, c->geo, c->K, n, c->flags, copy,
                        nbc, c->beta, c->seglen);
     return hipGetLastError();
