@@ -10,7 +10,7 @@
 // convolutions run on the matrix cores: forward and backward-data as
 // implicit GEMMs on the bfloat16 units with every FP32 input split exactly
 // in three bfloat16 pieces (so the products are the FP32 products), the
-// weight gradient on the FP32 units.
+// weight gradient on the FP32 matrix cores (v_mfma_f32_16x16x4f32).
 //
 // Layout: activations [n][channel][j][i] (row j, column i), weights
 // [co][ci][3][3], parameter vector per layer W then b, then the mean field
